@@ -1,0 +1,204 @@
+"""Pins of the OSLQ / OSA-IOP oracle estimators (CPU only).
+
+Each check fixes the oracle to something other than itself: dense
+log-determinants (LU), closed-form Laplacian eigenvalues, exact Hutch++
+identities when the sketch spans the traced operator, exact scale identities,
+unbiasedness over seeds, and an independent dense evaluation of the
+quadratic forms.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle.philox import rademacher
+
+
+def _full_rank_seed(n, s, start=0):
+    for seed in range(start, start + 200):
+        if np.linalg.matrix_rank(rademacher(seed, n, 0, s)) == min(n, s):
+            return seed
+    raise RuntimeError("no full-rank sketch found")
+
+
+def _dense_logm(q):
+    lam, u = np.linalg.eigh(q)
+    return (u * np.log(lam)) @ u.T
+
+
+def test_laplacian_closed_forms_match_dense():
+    for n2, sh in ((7, 0.1), (5, 1e-3)):
+        a = W.lap2d(n2, sh)
+        assert W.lap2d_exact_logdet(n2, sh) == pytest.approx(O.dense_logdet(a), rel=1e-13)
+    a = W.lap3d(4, 0.2)
+    assert W.lap3d_exact_logdet(4, 0.2) == pytest.approx(O.dense_logdet(a), rel=1e-13)
+
+
+@pytest.mark.parametrize("method", ["oslq", "osa_iop"])
+def test_full_sketch_is_exact(method):
+    # s = n: A spans R^n, the residual vanishes, and with m = n full
+    # re-orthogonalisation every quadratic form is exact, so the estimate is
+    # log det Q itself.
+    n = 8
+    q = W.random_spd_dense(n, seed=4, lo=0.3, hi=4.0)
+    a = W.from_dense(q)
+    seed = _full_rank_seed(n, n)
+    fn = getattr(O, method)
+    res = fn(a, n_probes=n + 1, sketch_rank=n, krylov_steps=n, iop_window=n, seed=seed)
+    assert res.logdet == pytest.approx(O.dense_logdet(a), rel=1e-10, abs=1e-10)
+    assert abs(res.tr_resid) < 1e-10
+
+
+def test_osa_iop_exact_when_traced_operator_has_rank_s():
+    # Hutch++ exactness: if rank(L_c) <= s the sketch Y = L_c S spans
+    # range(L_c); tr(A^T L_c A) = tr(L_c) and every residual form is 0.
+    # Q diagonal: 26 entries at the lower bound 0.2 (so L_c = log Q - log 0.2
+    # vanishes there) and 4 distinct larger values.
+    d = np.concatenate([np.full(26, 0.2), [0.5, 1.3, 2.0, 3.7]])
+    a = W.diag_matrix(d)
+    s = 4
+    seed = None
+    for sd in range(200):
+        if np.linalg.matrix_rank(rademacher(sd, 30, 0, s)[26:, :]) == s:
+            seed = sd
+            break
+    res = O.osa_iop(a, n_probes=7, sketch_rank=s, krylov_steps=10, iop_window=2, seed=seed)
+    assert res.shift_c == pytest.approx(math.log(0.2))
+    assert res.logdet == pytest.approx(float(np.sum(np.log(d))), rel=1e-10)
+    assert abs(res.tr_resid) < 1e-10
+
+
+def test_oslq_scale_identity():
+    # A = orth(J S) does not depend on the scale alpha, and a unit-vector
+    # quadrature of log(Q/alpha) equals that of log Q minus log alpha.  So two
+    # upper hints h1, h2 (c_i = log h_i) give
+    #   est1 - est2 = (c1 - c2) (n - s - (1/r) sum_j ||u_j||^2).
+    a = W.lap2d(12, 0.1)
+    s, npr = 6, 16
+    r = npr - s
+    e1 = O.oslq(a, npr, s, 20, 20, seed=3)
+    e2 = O.oslq(a, npr, s, 20, 20, seed=3, hi_hint=11.0)
+    assert e1.shift_c == pytest.approx(math.log(8.1)) and e2.shift_c == pytest.approx(math.log(11.0))
+    coef = a.n - s - sum(e1.probe_norm2[s:]) / r
+    assert e1.logdet - e2.logdet == pytest.approx((e1.shift_c - e2.shift_c) * coef,
+                                                  abs=1e-9 * abs(e1.logdet))
+    for k1, k2 in zip(e1.probe_K, e2.probe_K):
+        assert k1 - k2 == pytest.approx(e2.shift_c - e1.shift_c, abs=1e-10)
+
+
+def test_osa_iop_gamma_invariance():
+    # K_m(Q/gamma, v) = K_m(Q, v) and H(Q/gamma) = H(Q)/gamma, so the
+    # log(gamma) term of Alg 1 cancels exactly: with c fixed (c = log lo),
+    # changing gamma through the upper hint leaves the estimate unchanged.
+    a = W.lap2d(12, 0.1)
+    e1 = O.osa_iop(a, 15, 5, 12, 2, seed=1)
+    e2 = O.osa_iop(a, 15, 5, 12, 2, seed=1, hi_hint=40.0)
+    assert e1.scale != pytest.approx(e2.scale)
+    assert e1.shift_c == e2.shift_c
+    assert e1.logdet == pytest.approx(e2.logdet, rel=1e-10)
+
+
+@pytest.mark.parametrize("method", ["oslq", "osa_iop"])
+def test_matches_dense_quadratic_forms(method):
+    # With m = n and full re-orthogonalisation every Krylov quadratic form is
+    # exact, so the estimate must equal the Hutch++ split evaluated with the
+    # dense matrix logarithm (eigendecomposition), on the same basis A and
+    # the same residual probes.  (The matrix has a simple spectrum so that
+    # m = n steps do not run past an exhausted Krylov space.)
+    a = W.from_dense(W.random_spd_dense(24, seed=31, lo=0.3, hi=5.0))
+    n = a.n
+    s, npr = 5, 12
+    r = npr - s
+    q = a.to_dense()
+    res = getattr(O, method)(a, npr, s, n, n, seed=2, keep_basis=True)
+    basis = res.sketch_basis
+    lc = _dense_logm(q) - res.shift_c * np.eye(n)
+    g = rademacher(2, n, s, npr)
+    u = g - basis @ (basis.T @ g)
+    tr_s = sum(basis[:, i] @ lc @ basis[:, i] for i in range(s))
+    tr_r = sum(u[:, j] @ lc @ u[:, j] for j in range(r)) / r
+    assert res.tr_sketch == pytest.approx(tr_s, rel=1e-10, abs=1e-10)
+    assert res.tr_resid == pytest.approx(tr_r, rel=1e-10, abs=1e-10)
+    assert res.logdet == pytest.approx(n * res.shift_c + tr_s + tr_r, rel=1e-12)
+    np.testing.assert_allclose(res.probe_norm2[s:], np.sum(u * u, axis=0), rtol=1e-12)
+
+
+def test_osa_iop_sketch_orth_of_log_image():
+    # OSA-IOP's basis spans L_c S (Alg 2), not Q S: check against the dense
+    # image when Alg 1 is exact (m = n, full window).
+    a = W.from_dense(W.random_spd_dense(20, seed=32, lo=0.3, hi=5.0))
+    n, s = a.n, 4
+    res = O.osa_iop(a, 9, s, n, n, seed=5, keep_basis=True)
+    lc = _dense_logm(a.to_dense()) - res.shift_c * np.eye(n)
+    y = lc @ rademacher(5, n, 0, s)
+    qf, rf = np.linalg.qr(y)
+    qf = qf * np.sign(np.diag(rf))[None, :]
+    np.testing.assert_allclose(res.sketch_basis, qf, atol=1e-10)
+
+
+@pytest.mark.parametrize("method", ["oslq", "osa_iop"])
+def test_unbiased_over_seeds(method):
+    # Hutch++ is unbiased given exact quadratic forms (E[g g^T] = I), so the
+    # mean over seeds must approach log det Q; a wrong residual weight or a
+    # dropped term shows up as a bias many standard errors wide.
+    n = 10
+    q = W.random_spd_dense(n, seed=12, lo=0.2, hi=6.0)
+    a = W.from_dense(q)
+    exact = O.dense_logdet(a)
+    fn = getattr(O, method)
+    est = np.array([fn(a, 5, 2, n, n, seed=sd).logdet for sd in range(300)])
+    se = est.std(ddof=1) / math.sqrt(est.size)
+    assert abs(est.mean() - exact) < 4.0 * se + 1e-9
+    assert se > 0
+
+
+def test_slq_is_sketch_rank_zero():
+    a = W.lap2d(8, 0.5)
+    e1 = O.slq(a, 6, 10, 2, seed=4)
+    e2 = O.oslq(a, 6, 0, 10, 2, seed=4)
+    assert e1.logdet == e2.logdet and e1.tr_sketch == 0.0
+    assert e1.probe_norm2 == [float(a.n)] * 6  # ||g||^2 = n for Rademacher g
+
+
+def test_breakdown_reports_steps():
+    d = np.repeat(np.array([0.5, 1.0, 2.0]), 10)
+    a = W.diag_matrix(d)
+    res = O.oslq(a, 4, 1, 10, 10, seed=0)
+    assert res.probe_steps == [3, 3, 3, 3]
+    # with the Krylov space exhausted the quadratic forms are exact
+    lc = np.diag(np.log(d) - res.shift_c)
+    g = rademacher(0, a.n, 1, 4)
+    basis = O.oslq(a, 4, 1, 10, 10, seed=0, keep_basis=True).sketch_basis
+    u = g - basis @ (basis.T @ g)
+    ref = a.n * res.shift_c + basis[:, 0] @ lc @ basis[:, 0] + sum(u[:, j] @ lc @ u[:, j] for j in range(3)) / 3
+    assert res.logdet == pytest.approx(ref, rel=1e-12)
+
+
+def test_laplacian_estimates_near_closed_form():
+    # estimator accuracy (not parity): the 64x64 case is within the error
+    # magnitudes of the paper's Table 3
+    a = W.lap2d(64, 0.1)
+    exact = W.lap2d_exact_logdet(64, 0.1)
+    assert exact == pytest.approx(5018.30909251356, rel=1e-13)
+    e = O.oslq(a, 30, 10, 30, 30, seed=0)
+    assert abs(e.logdet / exact - 1) < 1e-2
+    e = O.osa_iop(a, 30, 10, 30, 2, seed=0)
+    assert abs(e.logdet / exact - 1) < 1e-2
+
+
+def test_not_spd_detected():
+    a = W.diag_matrix([-1.0, 2.0, 3.0, 4.0])
+    with pytest.raises(O.NotSPDError):
+        O.oslq(a, 2, 0, 4, 4, seed=0)
+
+
+def test_parameter_checks():
+    a = W.lap2d(4, 0.1)
+    with pytest.raises(ValueError):
+        O.oslq(a, 5, 5, 4, 2, seed=0)      # r = 0
+    with pytest.raises(ValueError):
+        O.oslq(a, 30, 17, 4, 2, seed=0)    # s > n
+    with pytest.raises(ValueError):
+        O.osa_iop(a, 5, 1, 0, 2, seed=0)   # m = 0

@@ -1,0 +1,106 @@
+"""Pins of the Gauss quadrature and log(H) e1 helpers (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import workloads as W
+from oracle import (NotSPDError, gauss_quadrature_log, log_hessenberg_e1,
+                    tridiag_from_hessenberg, windowed_arnoldi)
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 12])
+def test_legendre_jacobi_matrix_gives_gauss_legendre(m):
+    # The Jacobi matrix of the Legendre weight (alpha = 0,
+    # beta_j = j / sqrt(4 j^2 - 1)) has the Gauss-Legendre nodes as
+    # eigenvalues and weights 2 tau_k^2.  Probe the oracle's rule with
+    # f = log on the shifted matrix T + 3 I: sum tau^2 log(theta + 3) must
+    # equal (1/2) sum w_k log(x_k + 3).
+    j = np.arange(1, m)
+    beta = j / np.sqrt(4.0 * j * j - 1.0)
+    alpha = np.zeros(m)
+    x, w = np.polynomial.legendre.leggauss(m)
+    ref = 0.5 * float(np.sum(w * np.log(x + 3.0)))
+    assert gauss_quadrature_log(alpha + 3.0, beta) == pytest.approx(ref, rel=1e-13, abs=1e-14)
+
+
+def test_quadrature_exact_for_low_degree_polynomials():
+    # with m = n Krylov steps the Gauss rule reproduces the spectral measure
+    # of the unit start vector, so it is exact for every f, log included:
+    # sum tau^2 log(theta) = sum_i (u_i^T v)^2 log(lambda_i).
+    n = 14
+    q = W.random_spd_dense(n, seed=21, lo=0.2, hi=5.0)
+    v = np.random.default_rng(3).standard_normal(n)
+    v /= np.linalg.norm(v)
+    h, _, _, m_eff, _ = windowed_arnoldi(lambda x: q @ x, v, n, n, 1e-13)
+    al, be = tridiag_from_hessenberg(h)
+    lam, u = np.linalg.eigh(q)
+    exact = float(np.sum((u.T @ v) ** 2 * np.log(lam)))
+    assert gauss_quadrature_log(al, be) == pytest.approx(exact, rel=1e-11)
+
+
+def test_quadrature_moments_match_krylov_moments():
+    # moments: e1^T T^p e1 = v^T Q^p v for p <= 2m-1 (full re-orthogonalisation)
+    n, m = 60, 6
+    q = W.random_spd_dense(n, seed=2, lo=0.5, hi=2.0)
+    v = np.random.default_rng(9).standard_normal(n)
+    v /= np.linalg.norm(v)
+    h, _, _, _, _ = windowed_arnoldi(lambda x: q @ x, v, m, m, 1e-13)
+    al, be = tridiag_from_hessenberg(h)
+    t = np.diag(al) + np.diag(be, 1) + np.diag(be, -1)
+    for p in range(2 * m):
+        e1 = np.zeros(m); e1[0] = 1
+        lhs = e1 @ np.linalg.matrix_power(t, p) @ e1
+        rhs = v @ np.linalg.matrix_power(q, p) @ v
+        assert lhs == pytest.approx(rhs, rel=1e-9)
+    # and the log rule uses exactly these moments: first-order check via
+    # the quadrature of log on a tiny diagonal T
+    assert gauss_quadrature_log([2.0], []) == pytest.approx(math.log(2.0))
+
+
+def test_quadrature_rejects_non_spd():
+    with pytest.raises(NotSPDError):
+        gauss_quadrature_log([1.0, -0.5], [0.1])
+
+
+def test_tridiag_from_hessenberg():
+    h = np.arange(16.0).reshape(4, 4)
+    al, be = tridiag_from_hessenberg(h)
+    np.testing.assert_array_equal(al, [0, 5, 10, 15])
+    np.testing.assert_array_equal(be, [4, 9, 14])
+
+
+def test_log_hessenberg_symmetric_case_matches_eigh():
+    rng = np.random.default_rng(5)
+    m = 9
+    al = rng.uniform(0.5, 3.0, m)
+    be = rng.uniform(0.05, 0.3, m - 1)
+    t = np.diag(al) + np.diag(be, 1) + np.diag(be, -1)
+    lam, u = np.linalg.eigh(t)
+    ref = u @ (np.log(lam) * u[0, :])
+    np.testing.assert_allclose(log_hessenberg_e1(t), ref, rtol=1e-12, atol=1e-13)
+    # e1^T log(T) e1 is the Gauss quadrature value
+    assert log_hessenberg_e1(t)[0] == pytest.approx(gauss_quadrature_log(al, be), rel=1e-12)
+
+
+def test_log_hessenberg_nonsymmetric_integral_representation():
+    # Independent route: log(H) = int_0^1 (H - I) (t (H - I) + I)^{-1} dt for a
+    # matrix with spectrum off the closed negative axis; apply it to e1 with a
+    # 80-point Gauss-Legendre rule in t (solves only, no logm).
+    rng = np.random.default_rng(6)
+    m = 10
+    h = np.triu(rng.uniform(-0.2, 0.2, (m, m)), -1)
+    h[np.arange(m), np.arange(m)] = rng.uniform(0.5, 2.0, m)
+    e1 = np.zeros(m); e1[0] = 1.0
+    x, w = np.polynomial.legendre.leggauss(80)
+    tt, ww = 0.5 * (x + 1.0), 0.5 * w
+    b = (h - np.eye(m)) @ e1
+    ref = sum(wk * np.linalg.solve(tk * (h - np.eye(m)) + np.eye(m), b) for tk, wk in zip(tt, ww))
+    np.testing.assert_allclose(log_hessenberg_e1(h), ref, rtol=1e-11, atol=1e-12)
+
+
+def test_log_hessenberg_rejects_negative_spectrum():
+    h = np.array([[-1.0, 0.2], [0.3, 2.0]])
+    with pytest.raises(NotSPDError):
+        log_hessenberg_e1(h)

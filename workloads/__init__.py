@@ -1,0 +1,256 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module builds sparse SPD matrices (CSR, FP64 values, int32 indices) and
+request streams.  It holds none of the estimator's arithmetic: no Krylov
+recurrence, no quadrature, no trace assembly.  The only "answers" here are
+closed-form log-determinants of the Dirichlet Laplacians, computed from their
+known eigenvalues, which the tests and the benchmark report beside estimates.
+
+Matrix families stand in for the application classes of the paper's
+experiments (Section 4, Table 1): stencil/FEM-like operators (2D and 3D
+Laplacians), an unstructured graph (Erdos-Renyi graph Laplacian) and dense
+local coupling (compactly supported Wendland C2 covariance, the kernel of the
+paper's Gaussian-random-field experiment, Section 4, Tables 4-5).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = [
+    "Csr", "lap2d", "lap3d", "er_laplacian", "wendland", "diag_matrix",
+    "random_spd_dense", "from_dense", "lap2d_exact_logdet",
+    "lap3d_exact_logdet", "request_stream", "csr_digest",
+]
+
+
+@dataclasses.dataclass
+class Csr:
+    """Compressed sparse row matrix: int32 row_ptr[n+1], int32 col_idx[nnz],
+    float64 values[nnz]; column indices sorted and unique inside each row."""
+    n: int
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    values: np.ndarray
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def to_scipy(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.values, self.col_idx, self.row_ptr),
+                             shape=(self.n, self.n))
+
+    def to_dense(self) -> np.ndarray:
+        return self.to_scipy().toarray()
+
+
+def _from_scipy(m: sp.spmatrix, name: str) -> Csr:
+    m = sp.csr_matrix(m)
+    m.sum_duplicates()
+    m.sort_indices()
+    return Csr(n=m.shape[0],
+               row_ptr=np.ascontiguousarray(m.indptr, dtype=np.int32),
+               col_idx=np.ascontiguousarray(m.indices, dtype=np.int32),
+               values=np.ascontiguousarray(m.data, dtype=np.float64),
+               name=name)
+
+
+def from_dense(a: np.ndarray, name: str = "dense") -> Csr:
+    """CSR of a dense matrix, keeping every entry that is not exactly zero."""
+    return _from_scipy(sp.csr_matrix(np.asarray(a, dtype=np.float64)), name)
+
+
+def _stencil(dims, shift: float, name: str) -> Csr:
+    """Dirichlet Laplacian on a tensor grid with natural (first axis fastest)
+    ordering: diagonal 2*len(dims) + shift, -1 to each grid neighbour."""
+    dims = tuple(int(d) for d in dims)
+    n = int(np.prod(dims))
+    idx = np.arange(n, dtype=np.int64)
+    rows = [idx]
+    cols = [idx]
+    vals = [np.full(n, 2.0 * len(dims) + shift)]
+    stride = 1
+    for d in dims:
+        coord = (idx // stride) % d
+        for step in (-1, 1):
+            ok = (coord + step >= 0) & (coord + step < d)
+            rows.append(idx[ok])
+            cols.append(idx[ok] + step * stride)
+            vals.append(np.full(int(ok.sum()), -1.0))
+        stride *= d
+    m = sp.coo_matrix((np.concatenate(vals),
+                       (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n))
+    return _from_scipy(m, name)
+
+
+def lap2d(N: int, shift: float) -> Csr:
+    """5-point Dirichlet Laplacian on an N x N grid plus shift*I, row i = x + N*y."""
+    return _stencil((N, N), shift, f"lap2d_{N}_shift{shift:g}")
+
+
+def lap3d(N: int, shift: float) -> Csr:
+    """7-point Dirichlet Laplacian on an N^3 grid plus shift*I."""
+    return _stencil((N, N, N), shift, f"lap3d_{N}_shift{shift:g}")
+
+
+def _dirichlet_eigs_1d(N: int) -> np.ndarray:
+    k = np.arange(1, N + 1, dtype=np.float64)
+    return 2.0 - 2.0 * np.cos(np.pi * k / (N + 1))
+
+
+def lap2d_exact_logdet(N: int, shift: float) -> float:
+    """sum over i,j of log(4 - 2cos(pi i/(N+1)) - 2cos(pi j/(N+1)) + shift)."""
+    e = _dirichlet_eigs_1d(N)
+    lam = e[:, None] + e[None, :] + shift
+    return math.fsum(np.log(lam).ravel())
+
+
+def lap3d_exact_logdet(N: int, shift: float) -> float:
+    """sum over i,j,k of log(6 - 2cos(.) - 2cos(.) - 2cos(.) + shift)."""
+    e = _dirichlet_eigs_1d(N)
+    total = []
+    for a in e:  # one plane at a time keeps memory at N^2
+        lam = a + e[:, None] + e[None, :] + shift
+        total.append(math.fsum(np.log(lam).ravel()))
+    return math.fsum(total)
+
+
+def er_laplacian(n: int, n_edges: int, seed: int = 0, shift: float = 0.05,
+                 wlo: float = 0.5, whi: float = 1.5) -> Csr:
+    """Weighted Erdos-Renyi graph Laplacian plus shift*I.
+
+    n_edges distinct undirected edges without self-loops are drawn uniformly
+    with numpy's PCG64(seed); duplicates and loops are redrawn.  Weights are
+    U(wlo, whi), drawn after the edge set is fixed, in sorted-edge order.
+    Rows keep the natural (random) vertex order.  nnz = n + 2*n_edges.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    keys = np.empty(0, dtype=np.int64)
+    while keys.size < n_edges:
+        need = n_edges - keys.size
+        u = rng.integers(0, n, size=need, dtype=np.int64)
+        v = rng.integers(0, n, size=need, dtype=np.int64)
+        ok = u != v
+        lo = np.minimum(u[ok], v[ok])
+        hi = np.maximum(u[ok], v[ok])
+        keys = np.union1d(keys, lo * n + hi)
+    lo = keys // n
+    hi = keys % n
+    w = rng.uniform(wlo, whi, size=n_edges)
+    deg = np.bincount(lo, weights=w, minlength=n) + np.bincount(hi, weights=w, minlength=n)
+    rows = np.concatenate([lo, hi, np.arange(n)])
+    cols = np.concatenate([hi, lo, np.arange(n)])
+    vals = np.concatenate([-w, -w, deg + shift])
+    m = sp.coo_matrix((vals, (rows, cols)), shape=(n, n))
+    return _from_scipy(m, f"er_{n}_{n_edges}_seed{seed}")
+
+
+def wendland(n: int, nnz_per_row: float = 48.0, nugget: float = 1e-2,
+             seed: int = 0, scale: float = 1.0) -> Csr:
+    """Wendland C2 covariance matrix on n uniform points in [0,1]^2.
+
+    phi(r) = (1 - r/rho)^4_+ (4 r/rho + 1) with support radius
+    rho = sqrt(nnz_per_row / (pi n)), so an interior row holds about
+    nnz_per_row off-diagonal entries; diagonal = scale*phi(0) + nugget.
+    Points (PCG64(seed)) are sorted by rho-cell, row-major over cells, so that
+    neighbouring rows are neighbouring points.
+    """
+    from scipy.spatial import cKDTree
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = rng.random((n, 2))
+    rho = math.sqrt(nnz_per_row / (math.pi * n))
+    ncell = max(1, int(math.floor(1.0 / rho)))
+    cx = np.minimum((pts[:, 0] * ncell).astype(np.int64), ncell - 1)
+    cy = np.minimum((pts[:, 1] * ncell).astype(np.int64), ncell - 1)
+    order = np.argsort(cy * ncell + cx, kind="stable")
+    pts = np.ascontiguousarray(pts[order])
+    tree = cKDTree(pts)
+    pairs = tree.query_pairs(rho, output_type="ndarray").astype(np.int64)
+    d = pts[pairs[:, 0]] - pts[pairs[:, 1]]
+    r = np.sqrt(d[:, 0] ** 2 + d[:, 1] ** 2) / rho
+    keep = r < 1.0
+    pairs, r = pairs[keep], r[keep]
+    phi = scale * (1.0 - r) ** 4 * (4.0 * r + 1.0)
+    rows = np.concatenate([pairs[:, 0], pairs[:, 1], np.arange(n)])
+    cols = np.concatenate([pairs[:, 1], pairs[:, 0], np.arange(n)])
+    vals = np.concatenate([phi, phi, np.full(n, scale + nugget)])
+    m = sp.coo_matrix((vals, (rows, cols)), shape=(n, n))
+    return _from_scipy(m, f"wendland_{n}_nugget{nugget:g}_seed{seed}")
+
+
+def diag_matrix(values) -> Csr:
+    """Diagonal matrix (breakdown cases: d distinct values stop a Krylov run
+    after d steps)."""
+    v = np.asarray(values, dtype=np.float64)
+    n = v.size
+    return Csr(n=n, row_ptr=np.arange(n + 1, dtype=np.int32),
+               col_idx=np.arange(n, dtype=np.int32), values=v.copy(),
+               name=f"diag_{n}")
+
+
+def random_spd_dense(n: int, seed: int, lo: float = 0.1, hi: float = 10.0) -> np.ndarray:
+    """Dense SPD matrix Q = U diag(lam) U^T with log-uniform lam in [lo, hi]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.exp(rng.uniform(math.log(lo), math.log(hi), size=n))
+    q = (u * lam) @ u.T
+    return 0.5 * (q + q.T)
+
+
+def csr_digest(a: Csr) -> str:
+    """Content hash of a CSR matrix (checks that stored expected values were
+    produced from the very same input)."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.int64(a.n).tobytes())
+    h.update(np.ascontiguousarray(a.row_ptr, dtype=np.int32).tobytes())
+    h.update(np.ascontiguousarray(a.col_idx, dtype=np.int32).tobytes())
+    h.update(np.ascontiguousarray(a.values, dtype=np.float64).tobytes())
+    return h.hexdigest()[:16]
+
+
+def request_stream(n_requests: int = 512, seed: int = 1, rate_hz: float = 1.0,
+                   n_min: float = 1e4, n_max: float = 2e6):
+    """Serving workload: request descriptors with Poisson arrival times.
+
+    Each request: kind uniform over {lap2d, lap3d, wendland}; n log-uniform in
+    [n_min, n_max] (2D: N = round(sqrt n), 3D: N = round(cbrt n)); shift or
+    nugget log-uniform in [1e-3, 1]; Krylov steps uniform in 20..60;
+    30 probes (sketch 10 + 20 residual); window 2.  Arrival gaps are
+    exponential with mean 1/rate_hz (seconds).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    kinds = ("lap2d", "lap3d", "wendland")
+    out = []
+    t = 0.0
+    for i in range(n_requests):
+        kind = kinds[int(rng.integers(0, 3))]
+        n = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
+        shift = math.exp(rng.uniform(math.log(1e-3), 0.0))
+        steps = int(rng.integers(20, 61))
+        t += float(rng.exponential(1.0 / rate_hz))
+        if kind == "lap2d":
+            size = max(2, int(round(math.sqrt(n))))
+        elif kind == "lap3d":
+            size = max(2, int(round(n ** (1.0 / 3.0))))
+        else:
+            size = int(round(n))
+        out.append(dict(id=i, kind=kind, size=size, shift=shift,
+                        krylov_steps=steps, n_probes=30, sketch_rank=10,
+                        iop_window=2, arrival_s=t))
+    return out
+
+
+def build_request_matrix(req) -> Csr:
+    """Matrix for one request descriptor from request_stream()."""
+    if req["kind"] == "lap2d":
+        return lap2d(req["size"], req["shift"])
+    if req["kind"] == "lap3d":
+        return lap3d(req["size"], req["shift"])
+    return wendland(req["size"], 48.0, req["shift"], seed=req["id"] + 1000)
