@@ -1,0 +1,184 @@
+/*
+ * liblogdet - log-determinant estimation of large sparse SPD matrices on one
+ * AMD Instinct MI355X (gfx950), by the OSLQ and OSA-IOP estimators of
+ * Mbingui, Tambue and Karambal, "Optimal Stochastic Krylov Based Techniques
+ * for Large-Scale Log-Determinant Estimation".
+ *
+ * Problem statement (Section 2, eqs. Leja1/Leja2): log det Q = tr log Q for a
+ * symmetric positive definite Q that is only touched through products Q x.
+ * Both estimators split tr(log Q - c I) Hutch++-style (Alg 2, Alg 3) into an
+ * exactly evaluated sketch subspace and a Hutchinson residual, and evaluate
+ * every quadratic form with a Krylov recurrence:
+ *   - OSLQ (Section 3, Alg 3): subspace from orth(J S), J = Q / lambda_max
+ *     (when lambda_min < 1), Gauss-Lanczos quadrature of log on T_m.
+ *   - OSA-IOP (Section 2, Alg 2 with Alg 1): subspace from orth(L S), every
+ *     L x from Arnoldi with incomplete orthogonalisation over a window of k
+ *     vectors on Q / gamma, gamma = sqrt(lambda_min lambda_max), and
+ *     log(H_m) e1.
+ *
+ * All pointers in this header are HOST pointers unless stated otherwise.
+ * Every function returns an ld_status; no exception or signal crosses the
+ * ABI; out-parameters are left untouched when an error is returned, and
+ * ld_last_error() then describes the failure (thread-local string).
+ */
+#ifndef LIBLOGDET_H
+#define LIBLOGDET_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ld_status;
+
+enum {
+  LD_OK = 0,
+  LD_PENDING = 1,            /* ld_poll: the request has not finished yet      */
+  LD_E_INVALID_ARG = -1,     /* a parameter is outside its documented range    */
+  LD_E_BAD_CSR = -2,         /* malformed CSR structure                        */
+  LD_E_NOT_SPD = -3,         /* a_ii <= 0, a non-positive Ritz value, or a
+                                Hessenberg log that is not real                */
+  LD_E_NUMERIC = -4,         /* NaN/Inf, or the sketch QR lost rank            */
+  LD_E_NO_MEMORY = -5,       /* the request can never fit the HBM budget       */
+  LD_E_BUSY = -6,            /* object still referenced by in-flight requests  */
+  LD_E_DEVICE = -7,          /* HIP runtime error (message in ld_last_error)   */
+  LD_E_UNKNOWN_TICKET = -8   /* ld_poll/ld_wait on a ticket never issued or
+                                already retired                                */
+};
+
+/* Storage type of the matrix values on the device.  Values are always given
+ * in FP64 and rounded once, round-to-nearest-even. */
+typedef enum { LD_VT_FP64 = 0, LD_VT_FP32 = 1, LD_VT_BF16 = 2 } ld_value_type;
+
+typedef enum { LD_METHOD_OSLQ = 0, LD_METHOD_OSA_IOP = 1 } ld_method;
+
+/* LD_PREC_FP64: every vector, product and reduction in FP64.
+ * LD_PREC_MIXED: Krylov vectors and sparse products in FP32 (matrix values
+ * in the matrix's storage type: FP32, or BF16 widened to FP32); every inner
+ * product and norm accumulated in FP64; sketch QR, projection, the small
+ * tridiagonal/Hessenberg reductions and the trace in FP64. */
+typedef enum { LD_PREC_FP64 = 0, LD_PREC_MIXED = 1 } ld_precision;
+
+typedef struct ld_ctx ld_ctx;
+typedef struct ld_matrix ld_matrix;
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal                              */
+  int32_t max_slots;         /* serving: requests resident at once (0 -> 16)    */
+  uint64_t hbm_budget_bytes; /* serving: device bytes for resident requests
+                                (0 -> 80% of the free memory at creation)       */
+  void* hip_stream;          /* optional hipStream_t to run ld_estimate on
+                                (NULL -> the library creates its own)           */
+  int32_t default_method;    /* ld_method used by ld_estimate                    */
+  int32_t default_precision; /* ld_precision used by ld_estimate                 */
+} ld_ctx_opts;
+
+typedef struct {
+  int32_t method;            /* ld_method                                        */
+  int32_t precision;         /* ld_precision                                     */
+  int32_t n_probes;          /* s + r: sketch columns plus residual probes       */
+  int32_t sketch_rank;       /* s, 0 <= s <= min(n, 256); s = 0 is plain SLQ /
+                                Hutchinson                                       */
+  int32_t krylov_steps;      /* m, 1 <= m <= min(n, 512): mat-vecs per Krylov run */
+  int32_t iop_window;        /* k >= 1: orthogonalise against the k newest basis
+                                vectors (the paper's IOP uses k = 2; k >= m is
+                                full re-orthogonalisation)                      */
+  uint64_t seed;             /* Rademacher probes: Philox4x64-10, key (seed, 0),
+                                counter (row / 256, column, 0, 0)                */
+  double tol;                /* stop a run when h_{t+1,t} < tol (<= 0 -> 1e-10) */
+} ld_params;
+
+typedef struct {
+  double logdet;             /* the estimate of log det Q                        */
+  double tr_sketch;          /* subspace part tr(A^T L_c A)                      */
+  double tr_resid;           /* residual part (1/r) sum_j u_j^T L_c u_j         */
+  double shift_c;            /* c: logdet = n c + tr_sketch + tr_resid           */
+  double lambda_lo;          /* spectral interval used (Gershgorin or hints)     */
+  double lambda_hi;
+  double scale;              /* OSLQ: alpha (runs on Q/alpha); OSA-IOP: gamma    */
+  int64_t probe_steps;       /* sum over Krylov runs of the mat-vecs performed  */
+  int64_t matvecs;           /* all Q x products, sketch included               */
+  int32_t min_steps;         /* smallest effective Krylov dimension of a run    */
+  int32_t n_breakdowns;      /* runs stopped early by h < tol                    */
+  double device_ms;          /* device time of the estimate (HIP events)        */
+  double latency_ms;         /* host wall time from call (or submit) to result  */
+} ld_result;
+
+/* Optional per-run outputs of ld_estimate_detail.  Each pointer may be NULL;
+ * arrays are caller-owned host memory.  Runs are numbered 0..n_probes-1: the
+ * s sketch-basis runs first, then the r residual runs (OSA-IOP's sketch-image
+ * runs are not reported). */
+typedef struct {
+  double* probe_K;           /* [n_probes] quadrature value of the run: the
+                                estimate of x^T (log Q - c I) x / ||x||^2        */
+  double* probe_norm2;       /* [n_probes] ||x||^2 of the run's start vector    */
+  int32_t* probe_steps;      /* [n_probes] effective Krylov dimension            */
+  double* tri_alpha;         /* [n_probes * krylov_steps] h_{t,t}, row-major     */
+  double* tri_beta;          /* [n_probes * krylov_steps] h_{t+1,t}              */
+  double* sketch_basis;      /* [n * sketch_rank] A, row-major (row i, column j
+                                at i*sketch_rank + j)                            */
+} ld_detail;
+
+/* Context: owns a HIP stream (unless one is supplied), a device workspace and
+ * the serving scheduler.  Returns LD_E_DEVICE when the device is absent. */
+ld_status ld_ctx_create(const ld_ctx_opts* opts, ld_ctx** out);
+/* Waits for every submitted request, then releases everything.  Matrices
+ * created in the context must be destroyed first (else LD_E_BUSY). */
+ld_status ld_ctx_destroy(ld_ctx* ctx);
+/* Thread-local description of the last error returned on this thread. */
+const char* ld_last_error(void);
+
+/* Copies a host CSR matrix to the device (the caller keeps ownership of its
+ * arrays and may free them on return).  row_ptr[n+1] is monotone from 0 to
+ * nnz; col_idx[nnz] in [0, n), sorted and unique within each row; every
+ * diagonal entry present and > 0 (else LD_E_NOT_SPD).  values are FP64 and
+ * stored as `vt`; an FP64 copy is kept as well for LD_PREC_FP64 runs.
+ * lambda_lo_hint / lambda_hi_hint > 0 replace the Gershgorin bounds
+ * (Section 2.1); a Gershgorin lower bound <= 0 without a hint is replaced by
+ * 1e-6 * lambda_hi.  n and nnz must fit int32. */
+ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz,
+                        const int32_t* row_ptr, const int32_t* col_idx,
+                        const double* values, int32_t vt,
+                        double lambda_lo_hint, double lambda_hi_hint,
+                        ld_matrix** out);
+/* Releases a matrix; LD_E_BUSY while submitted requests still use it. */
+ld_status ld_destroy(ld_matrix* a);
+/* The spectral interval the estimators will use for this matrix. */
+ld_status ld_matrix_bounds(const ld_matrix* a, double* lambda_lo, double* lambda_hi);
+
+/* Blocking estimate with the context's default method and precision and
+ * tol = 1e-10 (Alg 3 for OSLQ, Alg 2 for OSA-IOP). */
+ld_status ld_estimate(ld_matrix* a, int32_t n_probes, int32_t sketch_rank,
+                      int32_t krylov_steps, int32_t iop_window, uint64_t seed,
+                      ld_result* out);
+/* Blocking estimate with explicit parameters. */
+ld_status ld_estimate_ex(ld_matrix* a, const ld_params* p, ld_result* out);
+/* As ld_estimate_ex, also filling the non-NULL arrays of `detail`. */
+ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
+                             const ld_detail* detail);
+
+/* Serving with continuous batching: queue a request and return at once with
+ * a ticket.  Requests are admitted as resident slots and HBM budget free up;
+ * admitted requests advance together, several Krylov steps per scheduler
+ * tick.  A result depends only on (matrix, params), never on the other
+ * requests in flight.  Returns LD_E_NO_MEMORY if the request could never fit
+ * the budget.  Thread-safe. */
+ld_status ld_submit(ld_matrix* a, const ld_params* p, uint64_t* ticket);
+/* LD_PENDING while the request runs; LD_OK (with *out filled, or the
+ * request's own error) exactly once, after which the ticket is retired. */
+ld_status ld_poll(ld_ctx* ctx, uint64_t ticket, ld_result* out);
+/* Blocks until the request finishes, then behaves as ld_poll. */
+ld_status ld_wait(ld_ctx* ctx, uint64_t ticket, ld_result* out);
+
+/* Test hook: the Rademacher probe columns col_begin..col_end-1 (n rows) as
+ * generated on the device, copied to host memory out[n * (col_end -
+ * col_begin)], row-major. */
+ld_status ld_debug_rademacher(ld_ctx* ctx, uint64_t seed, int64_t n,
+                              int32_t col_begin, int32_t col_end, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBLOGDET_H */

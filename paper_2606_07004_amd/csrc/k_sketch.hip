@@ -1,0 +1,290 @@
+// Dense pieces of the Hutch++ split (FP64): tall-skinny Gram/cross products,
+// the small Cholesky factor and its inverse (CholQR2, the QR of the sketch
+// image with a positive diagonal), the row-wise triangular solve, the
+// residual projection u = g - A (A^T g), and the matrix set-up kernels.
+#include "ld_kernels.h"
+
+namespace ld {
+
+// part[b][i][j] over a 64 x 64 output tile per grid.y; rows staged through LDS
+// 32 at a time, each thread accumulating a 4 x 4 micro-tile in row order.
+__global__ __launch_bounds__(kThreads) void k_gemm_tn(int64_t n, int rpb, const double* __restrict__ Xa,
+                                                     int lda, int ca, const double* __restrict__ Xb,
+                                                     int ldb, int cb, double* __restrict__ part) {
+  __shared__ double sa[32][64 + 1];
+  __shared__ double sb[32][64 + 1];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t r0 = (int64_t)lb * rpb;
+  const int64_t r1 = min(n, r0 + (int64_t)rpb);
+  const int ntj = (cb + 63) / 64;
+  const int ti = blockIdx.y / ntj, tj = blockIdx.y % ntj;
+  const int i0 = ti * 64, j0 = tj * 64;
+  const int ni = min(64, ca - i0), nj = min(64, cb - j0);
+  const int t = threadIdx.x;
+  const int ii0 = (t >> 4) * 4, jj0 = (t & 15) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int64_t row0 = r0; row0 < r1; row0 += 32) {
+    for (int e = t; e < 32 * 64; e += kThreads) {
+      const int rr = e >> 6, c = e & 63;
+      const int64_t row = row0 + rr;
+      sa[rr][c] = (row < r1 && c < ni) ? Xa[(size_t)row * lda + i0 + c] : 0.0;
+      sb[rr][c] = (row < r1 && c < nj) ? Xb[(size_t)row * ldb + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int nr = (int)min((int64_t)32, r1 - row0);
+    for (int rr = 0; rr < nr; ++rr) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { a[q] = sa[rr][ii0 + q]; b[q] = sb[rr][jj0 + q]; }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int i = ii0 + x, j = jj0 + y;
+      if (i < ni && j < nj) part[((size_t)lb * ca + i0 + i) * cb + j0 + j] = acc[x][y];
+    }
+}
+
+// Cholesky G = R^T R (R upper, positive diagonal) and R^{-1}, one block.
+// flag = 1 when a pivot is not positive or falls below 1e-14 of its column's
+// Gram diagonal (the sketch image has numerically lost rank).
+__global__ __launch_bounds__(kThreads) void k_chol_inv(int s, const double* __restrict__ G,
+                                                      double* __restrict__ R,
+                                                      double* __restrict__ Rinv,
+                                                      int* __restrict__ flag) {
+  __shared__ double piv;
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  for (int idx = t; idx < s * s; idx += kThreads) R[idx] = G[idx];
+  if (t == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < s; ++k) {
+    if (t == 0) {
+      const double a = R[k * s + k];
+      if (!(a > 1e-14 * G[k * s + k]) || !isfinite(a)) bad = 1;
+      piv = sqrt(a);
+      R[k * s + k] = piv;
+    }
+    __syncthreads();
+    if (bad) break;
+    for (int j = k + 1 + t; j < s; j += kThreads) R[k * s + j] /= piv;
+    __syncthreads();
+    const int rem = s - k - 1;
+    for (int idx = t; idx < rem * rem; idx += kThreads) {
+      const int i = k + 1 + idx / rem, j = k + 1 + idx % rem;
+      if (j >= i) R[i * s + j] -= R[k * s + i] * R[k * s + j];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (t == 0) *flag = 1;
+    return;
+  }
+  for (int idx = t; idx < s * s; idx += kThreads)
+    if (idx / s > idx % s) R[idx] = 0.0;
+  __syncthreads();
+  // inverse of the upper triangle by back substitution, one column per thread
+  for (int j = t; j < s; j += kThreads) {
+    for (int i = s - 1; i > j; --i) Rinv[i * s + j] = 0.0;
+    Rinv[j * s + j] = 1.0 / R[j * s + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int l = i + 1; l <= j; ++l) acc = fma(R[i * s + l], Rinv[l * s + j], acc);
+      Rinv[i * s + j] = -acc / R[i * s + i];
+    }
+  }
+  if (t == 0) *flag = 0;
+}
+
+// Y[row][:] <- Y[row][:] Rinv (Rinv upper triangular), 16 rows per block,
+// output columns in chunks of 16; the row tile stays in LDS so the update is
+// in place.
+__global__ __launch_bounds__(kThreads) void k_trsm_rows(int64_t n, double* __restrict__ Y, int ld,
+                                                       int s, const double* __restrict__ Rinv) {
+  extern __shared__ double sm[];
+  double* sy = sm;            // [16][s]
+  double* sr = sm + 16 * s;   // [s][16]
+  const int64_t row0 = (int64_t)blockIdx.x * 16;
+  const int t = threadIdx.x;
+  const int nr = (int)min((int64_t)16, n - row0);
+  for (int e = t; e < 16 * s; e += kThreads) {
+    const int rr = e / s, c = e % s;
+    sy[e] = (rr < nr) ? Y[(size_t)(row0 + rr) * ld + c] : 0.0;
+  }
+  for (int j0 = 0; j0 < s; j0 += 16) {
+    const int nc = min(16, s - j0);
+    __syncthreads();
+    for (int e = t; e < s * 16; e += kThreads) {
+      const int i = e / 16, jj = e % 16;
+      sr[e] = (jj < nc) ? Rinv[(size_t)i * s + j0 + jj] : 0.0;
+    }
+    __syncthreads();
+    const int rr = t / 16, jj = t % 16;
+    if (rr < nr && jj < nc) {
+      const int j = j0 + jj;
+      double acc = 0.0;
+      for (int i = 0; i <= j; ++i) acc = fma(sy[rr * s + i], sr[i * 16 + jj], acc);
+      Y[(size_t)(row0 + rr) * ld + j] = acc;
+    }
+  }
+}
+
+// Start block of the Krylov runs: columns [A | G - A P], plus per-block
+// partial squared column norms (FP64 values, before any narrowing).
+template <typename XT>
+__global__ __launch_bounds__(kThreads) void k_project(int64_t n, int rpb, const double* __restrict__ A,
+                                                     int lda, int s, const double* __restrict__ Gm,
+                                                     int ldg, int r, const double* __restrict__ P,
+                                                     int p_in_lds, XT* __restrict__ X0, int ld,
+                                                     int tpr, double* __restrict__ part) {
+  extern __shared__ double sm[];
+  const int rpi = kThreads / tpr;
+  double* sa = sm;                 // [rpi][s]
+  double* sp = sm + rpi * s;       // [s][r] when p_in_lds
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t r0 = (int64_t)lb * rpb;
+  const int64_t r1 = min(n, r0 + (int64_t)rpb);
+  const int t = threadIdx.x;
+  const int c = t % tpr, rg = t / tpr;
+  if (p_in_lds)
+    for (int e = t; e < s * r; e += kThreads) sp[e] = P[e];
+  const double* Pp = p_in_lds ? sp : P;
+  double nacc = 0.0;
+  for (int64_t rowb = r0; rowb < r1; rowb += rpi) {
+    __syncthreads();
+    for (int e = t; e < rpi * s; e += kThreads) {
+      const int rr = e / s, i = e % s;
+      sa[e] = (rowb + rr < r1) ? A[(size_t)(rowb + rr) * lda + i] : 0.0;
+    }
+    __syncthreads();
+    const int64_t row = rowb + rg;
+    if (row < r1 && c < ld) {
+      double val = 0.0;
+      if (c < s) {
+        val = sa[rg * s + c];
+      } else if (c < s + r) {
+        const int j = c - s;
+        double acc = 0.0;
+        for (int i = 0; i < s; ++i) acc = fma(sa[rg * s + i], Pp[(size_t)i * r + j], acc);
+        val = Gm[(size_t)row * ldg + j] - acc;
+      }
+      X0[(size_t)row * ld + c] = XT(val);
+      nacc = fma(val, val, nacc);
+    }
+  }
+  __syncthreads();
+  double* red = sm;  // [rpi][tpr]
+  red[rg * tpr + c] = nacc;
+  __syncthreads();
+  if (rg == 0 && c < ld) {
+    double sum = 0.0;
+    for (int q = 0; q < rpi; ++q) sum += red[q * tpr + c];
+    part[(size_t)lb * ld + c] = sum;
+  }
+}
+
+// Gershgorin: per block min(a_ii - sum|a_ij|) and max(a_ii + sum|a_ij|).
+__global__ __launch_bounds__(kThreads) void k_gershgorin(int64_t n, const int* __restrict__ rp,
+                                                        const int* __restrict__ ci,
+                                                        const double* __restrict__ va,
+                                                        double* __restrict__ part) {
+  __shared__ double smin[kThreads], smax[kThreads];
+  const int64_t row = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double lo = INFINITY, hi = -INFINITY;
+  if (row < n) {
+    double c = 0.0, rad = 0.0;
+    for (int k = rp[row]; k < rp[row + 1]; ++k) {
+      if (ci[k] == row) c += va[k];
+      else rad += fabs(va[k]);
+    }
+    lo = c - rad;
+    hi = c + rad;
+  }
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + off]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = smin[0];
+    part[2 * blockIdx.x + 1] = smax[0];
+  }
+}
+
+hipError_t launch_gemm_tn(hipStream_t st, const Geom& g, const double* Xa, int lda, int ca,
+                          const double* Xb, int ldb, int cb, double* part) {
+  if (g.n < 1 || g.nblk < 1 || !Xa || !Xb || !part || ca < 1 || cb < 1 || ca > lda || cb > ldb ||
+      (int64_t)g.nblk * g.rpb < g.n)
+    return hipErrorInvalidValue;
+  const int nt = ((ca + 63) / 64) * ((cb + 63) / 64);
+  hipLaunchKernelGGL(k_gemm_tn, dim3(g.nblk, nt), dim3(kThreads), 0, st, g.n, g.rpb, Xa, lda, ca,
+                     Xb, ldb, cb, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_inv(hipStream_t st, int s, const double* G, double* work, double* Rinv,
+                           int* flag) {
+  if (s < 1 || s > 256 || !G || !work || !Rinv || !flag) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kThreads), 0, st, s, G, work, Rinv, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_rows(hipStream_t st, int64_t n, double* Y, int ld, int s, const double* Rinv) {
+  if (n < 1 || s < 1 || s > 256 || ld < s || !Y || !Rinv) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(16 * s + 16 * s) * sizeof(double);
+  hipLaunchKernelGGL(k_trsm_rows, dim3((unsigned)((n + 15) / 16)), dim3(kThreads), lds, st, n, Y, ld,
+                     s, Rinv);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int lda, int s,
+                          const double* Gm, int ldg, int r, const double* P, void* X0, double* part) {
+  if (g.n < 1 || g.nblk < 1 || (int64_t)g.nblk * g.rpb < g.n || !Gm || !X0 || !part || r < 1 ||
+      s < 0 || s + r > g.ld || g.ld > 256 || (s > 0 && (!A || !P || lda < s)) || ldg < r)
+    return hipErrorInvalidValue;
+  int tpr = 1;
+  while (tpr < g.ld) tpr <<= 1;
+  const int rpi = kThreads / tpr;
+  size_t lds = (size_t)rpi * (s > 0 ? s : 1) * sizeof(double);
+  if (lds < (size_t)kThreads * sizeof(double)) lds = (size_t)kThreads * sizeof(double);
+  int p_in_lds = 0;
+  if (s > 0 && lds + (size_t)s * r * sizeof(double) <= 48 * 1024) {
+    p_in_lds = 1;
+    lds = (size_t)(rpi * s + s * r) * sizeof(double);
+    if (lds < (size_t)kThreads * sizeof(double)) lds = (size_t)kThreads * sizeof(double);
+  }
+  if (g.xbytes == 8)
+    hipLaunchKernelGGL(k_project<double>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A, lda,
+                       s, Gm, ldg, r, P, p_in_lds, static_cast<double*>(X0), g.ld, tpr, part);
+  else
+    hipLaunchKernelGGL(k_project<float>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A, lda,
+                       s, Gm, ldg, r, P, p_in_lds, static_cast<float*>(X0), g.ld, tpr, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_gershgorin(hipStream_t st, int64_t n, const int* rp, const int* ci,
+                             const double* va, double* part, int* nparts) {
+  if (n < 1 || !rp || !ci || !va || !part || !nparts) return hipErrorInvalidValue;
+  const int nb = (int)((n + kThreads - 1) / kThreads);
+  *nparts = nb;
+  hipLaunchKernelGGL(k_gershgorin, dim3(nb), dim3(kThreads), 0, st, n, rp, ci, va, part);
+  return hipGetLastError();
+}
+
+}  // namespace ld

@@ -1,0 +1,69 @@
+// Device-side helpers shared by the liblogdet kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ld {
+
+constexpr int kThreads = 256;   // every streaming kernel uses 256-thread blocks
+constexpr int kWave = 64;
+constexpr int kMaxNv = 8;       // vectors handled by one dots/update launch
+
+// Blocks are dispatched round-robin over the 8 XCDs of the MI355X (block b on
+// XCD b % 8), each XCD with its own L2.  Remap so that every XCD owns one
+// contiguous range of row blocks: rows that share gathered neighbours (and
+// the partial-sum layout) then stay inside one L2.
+__device__ inline int xcd_remap(int b, int nb) {
+  const int nb8 = nb & ~7;
+  if (b >= nb8) return b;
+  return (b & 7) * (nb8 >> 3) + (b >> 3);
+}
+
+// bf16 storage is the upper half of an IEEE float.
+__device__ inline float bf16_to_float(uint16_t v) { return __uint_as_float(uint32_t(v) << 16); }
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { using type = double; };
+template <> struct Acc<float> { using type = float; };
+
+template <typename VT, typename A> __device__ inline A value_as(VT v) { return A(v); }
+template <> __device__ inline float value_as<uint16_t, float>(uint16_t v) { return bf16_to_float(v); }
+template <> __device__ inline double value_as<uint16_t, double>(uint16_t v) { return double(bf16_to_float(v)); }
+
+// 16-byte vector access: 2 doubles or 4 floats per lane.
+template <typename T> struct V16;
+template <> struct V16<double> {
+  static constexpr int N = 2;
+  double v[2];
+  __device__ inline void load(const double* p) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    v[0] = t.x; v[1] = t.y;
+  }
+  __device__ inline void store(double* p) const {
+    double2 t; t.x = v[0]; t.y = v[1];
+    *reinterpret_cast<double2*>(p) = t;
+  }
+};
+template <> struct V16<float> {
+  static constexpr int N = 4;
+  float v[4];
+  __device__ inline void load(const float* p) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  }
+  __device__ inline void store(float* p) const {
+    float4 t; t.x = v[0]; t.y = v[1]; t.z = v[2]; t.w = v[3];
+    *reinterpret_cast<float4*>(p) = t;
+  }
+};
+
+// Vectors handed to the multi-vector streaming kernels.  x[v] is a block of
+// the same [n][ld] layout as the output; mult[v][col] (may be null -> 1) is
+// the per-column factor that turns the stored block into the basis vector.
+struct VecSet {
+  const void* x[kMaxNv];
+  const double* mult[kMaxNv];
+};
+
+}  // namespace ld

@@ -1,0 +1,746 @@
+// Host runtime of liblogdet: the estimate pipeline as a resumable sequence of
+// device phases, plus the C ABI entry points.
+//
+// Pipeline of one OSLQ estimate (Alg 3), all on one HIP stream:
+//   Rademacher S -> Y = J S (CSR x block) -> CholQR2(Y) = A
+//   -> Rademacher G -> P = A^T G -> X0 = [A | G - A P], column norms
+//   -> m windowed Krylov steps over the whole block of s + r runs
+//   -> Golub-Welsch per run -> per-run K values back to the host, trace sum.
+// OSA-IOP (Alg 2 with Alg 1) adds a first Krylov phase over S whose basis is
+// kept, log(H) e1 per run, Y = L_c S assembled from the stored basis, then
+// the same QR / projection and a second Krylov phase with v1 kept for the
+// quadratic forms.
+#include "runtime.h"
+#include "serve.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace ld {
+
+static thread_local std::string g_last_error;
+
+ld_status set_error(ld_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+double now_seconds() {
+  using clk = std::chrono::steady_clock;
+  return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+#define LD_HIP(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return set_error(LD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+DeviceBuffer::~DeviceBuffer() { release(); }
+
+void DeviceBuffer::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+hipError_t DeviceBuffer::ensure(size_t want) {
+  if (want <= bytes && ptr) return hipSuccess;
+  release();
+  hipError_t e = hipMalloc(&ptr, want);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    return e;
+  }
+  bytes = want;
+  return hipSuccess;
+}
+
+static inline int round4(int x) { return (x + 3) & ~3; }
+static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// Run
+// ---------------------------------------------------------------------------
+enum Stage : int {
+  ST_PROLOGUE = 0,
+  ST_KRYLOV = 1,
+  ST_COMBINE = 2,   // OSA-IOP: between the two Krylov phases
+  ST_EPILOGUE = 3,
+  ST_DONE = 4,
+};
+
+Run::Run(ld_matrix* a, const ld_params& p) : a_(a), p_(p) {}
+
+Run::~Run() {
+  if (ev0_) (void)hipEventDestroy(ev0_);
+  if (ev1_) (void)hipEventDestroy(ev1_);
+}
+
+ld_status Run::validate() {
+  if (!a_) return set_error(LD_E_INVALID_ARG, "null matrix");
+  n_ = a_->n;
+  s_ = p_.sketch_rank;
+  r_ = p_.n_probes - p_.sketch_rank;
+  B_ = p_.n_probes;
+  m_ = p_.krylov_steps;
+  k_ = p_.iop_window;
+  tol_ = p_.tol > 0 ? p_.tol : 1e-10;
+  if (p_.method != LD_METHOD_OSLQ && p_.method != LD_METHOD_OSA_IOP)
+    return set_error(LD_E_INVALID_ARG, "unknown method");
+  if (p_.precision != LD_PREC_FP64 && p_.precision != LD_PREC_MIXED)
+    return set_error(LD_E_INVALID_ARG, "unknown precision");
+  if (s_ < 0 || s_ > 256 || (int64_t)s_ > n_)
+    return set_error(LD_E_INVALID_ARG, "sketch_rank must satisfy 0 <= s <= min(n, 256)");
+  if (r_ < 1) return set_error(LD_E_INVALID_ARG, "n_probes - sketch_rank must be >= 1");
+  if (m_ < 1 || m_ > 512 || (int64_t)m_ > n_)
+    return set_error(LD_E_INVALID_ARG, "krylov_steps must satisfy 1 <= m <= min(n, 512)");
+  if (k_ < 1) return set_error(LD_E_INVALID_ARG, "iop_window must be >= 1");
+  mixed_ = p_.precision == LD_PREC_MIXED;
+  xb_ = mixed_ ? 4 : 8;
+  if (B_ > (mixed_ ? 256 : 128))
+    return set_error(LD_E_INVALID_ARG, mixed_ ? "n_probes must be <= 256 in mixed precision"
+                                              : "n_probes must be <= 128 in FP64");
+  lds_ = round4(std::max(s_, 1));
+  ldr_ = round4(r_);
+  ldB_ = round4(B_);
+  ld1_ = lds_;
+  lo_ = a_->lo;
+  hi_ = a_->hi;
+  if (p_.method == LD_METHOD_OSLQ) {
+    // J = Q / lambda_hi and c = log(lambda_hi) when lambda_lo < 1, else J = Q, c = 0
+    if (lo_ < 1.0) {
+      scale_ = hi_;
+      c_ = std::log(hi_);
+    } else {
+      scale_ = 1.0;
+      c_ = 0.0;
+    }
+  } else {
+    // Krylov on Q / gamma; traced operator log Q - c I
+    scale_ = std::sqrt(lo_ * hi_);
+    c_ = lo_ < 1.0 ? std::log(lo_) : std::log(scale_);
+  }
+  opscale_ = 1.0 / scale_;
+  gB_ = make_geom(n_, ldB_, xb_);
+  gS_ = make_geom(n_, lds_, 8);
+  g1_ = make_geom(n_, ld1_, xb_);
+  return LD_OK;
+}
+
+// One layout for measuring and for carving: with base == nullptr only the
+// size is computed.
+size_t Run::layout(char* base) {
+  size_t off = 0;
+  auto take = [&](size_t sz) -> void* {
+    void* q = base ? base + off : nullptr;
+    off += align_up(sz);
+    return q;
+  };
+  const size_t n = (size_t)n_;
+  const int nvmax = std::min(k_, m_) + 1;
+  size_t slot_bytes;
+  // Krylov storage: OSLQ ring of min(k,m)+1 slots; OSA-IOP max(phase-1 full
+  // basis, phase-2 ring with v1 kept).
+  if (p_.method == LD_METHOD_OSLQ) {
+    nslots_ = std::min(k_, m_) + 1;
+    slot_bytes = (size_t)nslots_ * n * ldB_ * xb_;
+  } else {
+    nslots_ = std::max(m_ + 1, std::min(k_, m_) + 2);
+    slot_bytes = std::max((size_t)(m_ + 1) * n * ld1_ * xb_,
+                          (size_t)(std::min(k_, m_) + 2) * n * ldB_ * xb_);
+  }
+  slots_ = take(slot_bytes);
+  mult_ = static_cast<double*>(take((size_t)nslots_ * std::max(ldB_, ld1_) * 8));
+  S_ = static_cast<double*>(take(n * std::max(lds_, ldr_) * 8));
+  G_ = S_;
+  Y_ = s_ > 0 ? static_cast<double*>(take(n * lds_ * 8)) : nullptr;
+  size_t pe = (size_t)gB_.nblk * std::max(nvmax, 2) * ldB_;
+  pe = std::max(pe, (size_t)g1_.nblk * std::max(nvmax, 2) * ld1_);
+  if (s_ > 0) pe = std::max(pe, (size_t)gS_.nblk * s_ * std::max(s_, r_));
+  part_elems_ = pe;
+  part_ = static_cast<double*>(take(pe * 8));
+  dwin_ = static_cast<double*>(take((size_t)nvmax * ldB_ * 8));
+  nsr_ = static_cast<double*>(take((size_t)2 * ldB_ * 8));
+  norm2_ = static_cast<double*>(take((size_t)ldB_ * 8));
+  K_ = static_cast<double*>(take((size_t)ldB_ * 8));
+  H_ = static_cast<double*>(take((size_t)ldB_ * (m_ + 1) * m_ * 8));
+  gq_ = static_cast<double*>(take((size_t)ldB_ * (m_ + 1) * 8));
+  work_ = static_cast<double*>(take((size_t)ldB_ * (size_t)std::max(3 * m_, 5 * m_ * m_ + 4 * m_) * 8));
+  if (s_ > 0) {
+    gram_ = static_cast<double*>(take((size_t)s_ * s_ * 8));
+    rfac_ = static_cast<double*>(take((size_t)s_ * s_ * 8));
+    rinv_ = static_cast<double*>(take((size_t)s_ * s_ * 8));
+    pmat_ = static_cast<double*>(take((size_t)s_ * r_ * 8));
+  }
+  ell_ = static_cast<double*>(take((size_t)ld1_ * m_ * 8));
+  coefs_ = static_cast<double*>(take((size_t)(m_ + 1) * ld1_ * 8));
+  meff_ = static_cast<int*>(take((size_t)ldB_ * 4));
+  active_ = static_cast<int*>(take((size_t)ldB_ * 4));
+  flags_ = static_cast<int*>(take((size_t)ldB_ * 4));
+  dflag_ = static_cast<int*>(take(16));
+  return off;
+}
+
+size_t Run::device_bytes() const { return const_cast<Run*>(this)->layout(nullptr); }
+
+ld_status Run::bind(void* base, size_t bytes) {
+  const size_t need = layout(nullptr);
+  if (need > bytes) return set_error(LD_E_NO_MEMORY, "workspace smaller than the request needs");
+  layout(static_cast<char*>(base));
+  stage_ = ST_PROLOGUE;
+  t_ = 0;
+  kphase_ = 0;
+  return LD_OK;
+}
+
+// CholQR2: Y <- Y R1^{-1}, then again, so that Y = A R with A orthonormal and
+// R = R2 R1 upper triangular with a positive diagonal (the QR convention of
+// the oracle).  dflag_[0] is set when the Gram matrix is not numerically
+// positive definite.
+ld_status Run::sketch_qr(hipStream_t st, double* Y) {
+  for (int pass = 0; pass < 2; ++pass) {
+    LD_HIP(launch_gemm_tn(st, gS_, Y, lds_, s_, Y, lds_, s_, part_));
+    LD_HIP(launch_reduce(st, part_, gS_.nblk, s_ * s_, gram_));
+    LD_HIP(launch_chol_inv(st, s_, gram_, rfac_, rinv_, dflag_ + pass));
+    LD_HIP(launch_trsm_rows(st, n_, Y, lds_, s_, rinv_));
+  }
+  return LD_OK;
+}
+
+// X0 = [A | G - A (A^T G)] in Krylov precision, its column norms, and the
+// per-run start state.
+ld_status Run::start_block(hipStream_t st, const double* A, int s_cols) {
+  LD_HIP(launch_rademacher(st, p_.seed, n_, s_, ldr_, r_, G_, 8, ldr_, 0));
+  if (s_cols > 0) {
+    LD_HIP(launch_gemm_tn(st, gS_, A, lds_, s_cols, G_, ldr_, r_, part_));
+    LD_HIP(launch_reduce(st, part_, gS_.nblk, s_cols * r_, pmat_));
+  }
+  LD_HIP(launch_project(st, gB_, A, lds_, s_cols, G_, ldr_, r_, pmat_, slots_, part_));
+  LD_HIP(launch_reduce(st, part_, gB_.nblk, ldB_, nsr_));
+  LD_HIP(launch_start_finish(st, B_, ldB_, nsr_, norm2_, mult_, active_, meff_, gq_, m_ + 1));
+  return LD_OK;
+}
+
+ld_status Run::begin_krylov(int phase) {
+  kphase_ = phase;
+  t_ = 0;
+  if (p_.method == LD_METHOD_OSLQ) {
+    kB_ = B_;
+    kld_ = ldB_;
+    kg_ = gB_;
+    kpin_ = false;
+    kfull_ = false;
+    kns_ = std::min(k_, m_) + 1;
+  } else if (phase == 0) {
+    kB_ = s_;
+    kld_ = ld1_;
+    kg_ = g1_;
+    kpin_ = false;
+    kfull_ = true;
+    kns_ = m_ + 1;
+  } else {
+    kB_ = B_;
+    kld_ = ldB_;
+    kg_ = gB_;
+    kpin_ = true;
+    kfull_ = false;
+    kns_ = std::min(k_, m_) + 2;
+  }
+  kslots_ = slots_;
+  kmult_ = mult_;
+  slot_elems_ = (size_t)n_ * kld_;
+  return LD_OK;
+}
+
+ld_status Run::run_prologue(hipStream_t st) {
+  if (!ev0_) LD_HIP(hipEventCreate(&ev0_));
+  if (!ev1_) LD_HIP(hipEventCreate(&ev1_));
+  LD_HIP(hipEventRecord(ev0_, st));
+  LD_HIP(hipMemsetAsync(flags_, 0, (size_t)ldB_ * 4, st));
+  LD_HIP(hipMemsetAsync(dflag_, 0, 16, st));
+  const void* vals_sketch = mixed_ ? a_->vlo : a_->v64;
+  const int vt_sketch = mixed_ ? a_->vt_lo : VT_F64;
+  if (p_.method == LD_METHOD_OSLQ) {
+    if (s_ > 0) {
+      // Y = J S, J = Q / alpha (Alg 3: sketch from J S, not from f(J) S)
+      LD_HIP(launch_rademacher(st, p_.seed, n_, 0, lds_, s_, S_, 8, lds_, 0));
+      LD_HIP(launch_spmm(st, gS_, a_->rp, a_->ci, vals_sketch, vt_sketch, S_, Y_, nullptr,
+                         opscale_));
+      ld_status rc = sketch_qr(st, Y_);
+      if (rc != LD_OK) return rc;
+    }
+    ld_status rc = start_block(st, Y_, s_);
+    if (rc != LD_OK) return rc;
+    begin_krylov(0);
+    return LD_OK;
+  }
+  return set_error(LD_E_INVALID_ARG, "OSA-IOP is not available in this build");
+}
+
+ld_status Run::run_krylov_step(hipStream_t st, int t) {
+  auto slot_of = [&](int j) -> int {
+    if (kfull_) return j;
+    if (kpin_) return j == 0 ? 0 : 1 + (j - 1) % (kns_ - 1);
+    return j % kns_;
+  };
+  const size_t eb = (size_t)xb_;
+  auto slot_ptr = [&](int j) -> void* {
+    return static_cast<char*>(kslots_) + (size_t)slot_of(j) * slot_elems_ * eb;
+  };
+  auto mult_ptr = [&](int j) -> double* { return kmult_ + (size_t)slot_of(j) * kld_; };
+  const void* vals = mixed_ ? a_->vlo : a_->v64;
+  const int vt = mixed_ ? a_->vt_lo : VT_F64;
+  void* W = slot_ptr(t + 1);
+  LD_HIP(launch_spmm(st, kg_, a_->rp, a_->ci, vals, vt, slot_ptr(t), W, mult_ptr(t), opscale_));
+  const int j0 = std::max(0, t - k_ + 1);
+  const int nv = t - j0 + 1;
+  for (int c0 = 0; c0 < nv; c0 += kMaxNv) {
+    VecSet vs{};
+    const int nc = std::min(kMaxNv, nv - c0);
+    for (int v = 0; v < nc; ++v) {
+      vs.x[v] = slot_ptr(j0 + c0 + v);
+      vs.mult[v] = mult_ptr(j0 + c0 + v);
+    }
+    LD_HIP(launch_dots(st, kg_, W, vs, nc, c0, nv, part_));
+  }
+  LD_HIP(launch_reduce(st, part_, kg_.nblk, nv * kld_, dwin_));
+  for (int c0 = 0; c0 < nv; c0 += kMaxNv) {
+    VecSet vs{};
+    const int nc = std::min(kMaxNv, nv - c0);
+    for (int v = 0; v < nc; ++v) {
+      vs.x[v] = slot_ptr(j0 + c0 + v);
+      vs.mult[v] = mult_ptr(j0 + c0 + v);
+    }
+    const bool last = c0 + nc >= nv;
+    LD_HIP(launch_update(st, kg_, W, vs, nc, dwin_, c0, last ? 1 : 0,
+                         (last && kpin_) ? slot_ptr(0) : nullptr,
+                         (last && kpin_) ? mult_ptr(0) : nullptr, part_));
+  }
+  LD_HIP(launch_reduce(st, part_, kg_.nblk, 2 * kld_, nsr_));
+  LD_HIP(launch_step_finish(st, kB_, kld_, t, m_, dwin_, j0, nv, nsr_, tol_, H_, meff_, active_,
+                            mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_));
+  return LD_OK;
+}
+
+ld_status Run::run_epilogue(hipStream_t st) {
+  if (p_.method == LD_METHOD_OSLQ) {
+    LD_HIP(launch_gauss_log(st, B_, m_, H_, meff_, work_, K_, flags_));
+  } else {
+    return set_error(LD_E_INVALID_ARG, "OSA-IOP is not available in this build");
+  }
+  LD_HIP(hipEventRecord(ev1_, st));
+  return LD_OK;
+}
+
+ld_status Run::advance(hipStream_t st, int budget, bool* done) {
+  *done = false;
+  while (budget > 0) {
+    switch (stage_) {
+      case ST_PROLOGUE: {
+        ld_status rc = run_prologue(st);
+        if (rc != LD_OK) return rc;
+        stage_ = ST_KRYLOV;
+        --budget;
+        break;
+      }
+      case ST_KRYLOV: {
+        ld_status rc = run_krylov_step(st, t_);
+        if (rc != LD_OK) return rc;
+        ++t_;
+        --budget;
+        if (t_ >= m_) stage_ = ST_EPILOGUE;
+        break;
+      }
+      case ST_EPILOGUE: {
+        ld_status rc = run_epilogue(st);
+        if (rc != LD_OK) return rc;
+        stage_ = ST_DONE;
+        --budget;
+        break;
+      }
+      default:
+        *done = true;
+        return LD_OK;
+    }
+  }
+  *done = stage_ == ST_DONE;
+  return LD_OK;
+}
+
+ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail) {
+  LD_HIP(hipStreamSynchronize(st));
+  std::vector<double> K(B_), nrm(B_);
+  std::vector<int> meff(B_), flags(B_);
+  int dflag[2] = {0, 0};
+  LD_HIP(hipMemcpy(K.data(), K_, (size_t)B_ * 8, hipMemcpyDeviceToHost));
+  LD_HIP(hipMemcpy(nrm.data(), norm2_, (size_t)B_ * 8, hipMemcpyDeviceToHost));
+  LD_HIP(hipMemcpy(meff.data(), meff_, (size_t)B_ * 4, hipMemcpyDeviceToHost));
+  LD_HIP(hipMemcpy(flags.data(), flags_, (size_t)B_ * 4, hipMemcpyDeviceToHost));
+  LD_HIP(hipMemcpy(dflag, dflag_, 8, hipMemcpyDeviceToHost));
+  float ms = 0.f;
+  LD_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
+  if (dflag[0] || dflag[1])
+    return set_error(LD_E_NUMERIC, "sketch image lost rank (Cholesky of its Gram matrix failed)");
+  int nbreak = 0;
+  for (int p = 0; p < B_; ++p) {
+    if (flags[p] & 1) return set_error(LD_E_NUMERIC, "NaN/Inf in Krylov run " + std::to_string(p));
+    if (flags[p] & 2)
+      return set_error(LD_E_NOT_SPD, "non-positive Ritz value in Krylov run " + std::to_string(p));
+    if (flags[p] & 8)
+      return set_error(LD_E_NUMERIC, "tridiagonal eigenvalues did not converge, run " +
+                                         std::to_string(p));
+    if (flags[p] & 4) ++nbreak;
+  }
+  // trace assembly in a fixed order: sketch runs, then residual runs
+  double tr_sketch = 0.0;
+  for (int i = 0; i < s_; ++i)
+    tr_sketch += (p_.method == LD_METHOD_OSLQ) ? K[i] : nrm[i] * K[i];
+  double acc = 0.0;
+  for (int j = s_; j < B_; ++j) acc += nrm[j] * K[j];
+  const double tr_resid = acc / r_;
+  ld_result res{};
+  res.logdet = (double)n_ * c_ + (tr_sketch + tr_resid);
+  res.tr_sketch = tr_sketch;
+  res.tr_resid = tr_resid;
+  res.shift_c = c_;
+  res.lambda_lo = lo_;
+  res.lambda_hi = hi_;
+  res.scale = scale_;
+  int64_t steps = 0;
+  int minst = m_;
+  for (int p = 0; p < B_; ++p) {
+    steps += meff[p];
+    if (nrm[p] > 0) minst = std::min(minst, meff[p]);
+  }
+  res.probe_steps = steps;
+  const int64_t sketch_mv = (p_.method == LD_METHOD_OSLQ) ? s_ : (int64_t)s_ * m_;
+  res.matvecs = sketch_mv + (int64_t)B_ * m_;
+  res.min_steps = minst;
+  res.n_breakdowns = nbreak;
+  res.device_ms = ms;
+  res.latency_ms = (now_seconds() - t_submit_) * 1e3;
+  if (detail) {
+    if (detail->probe_K) std::memcpy(detail->probe_K, K.data(), (size_t)B_ * 8);
+    if (detail->probe_norm2) std::memcpy(detail->probe_norm2, nrm.data(), (size_t)B_ * 8);
+    if (detail->probe_steps) std::memcpy(detail->probe_steps, meff.data(), (size_t)B_ * 4);
+    if (detail->tri_alpha || detail->tri_beta) {
+      std::vector<double> H((size_t)B_ * (m_ + 1) * m_);
+      LD_HIP(hipMemcpy(H.data(), H_, H.size() * 8, hipMemcpyDeviceToHost));
+      for (int p = 0; p < B_; ++p)
+        for (int t = 0; t < m_; ++t) {
+          const double* Hp = H.data() + (size_t)p * (m_ + 1) * m_;
+          const bool live = t < meff[p];
+          if (detail->tri_alpha)
+            detail->tri_alpha[(size_t)p * m_ + t] = live ? Hp[(size_t)t * m_ + t] : 0.0;
+          if (detail->tri_beta)
+            detail->tri_beta[(size_t)p * m_ + t] = live ? Hp[(size_t)(t + 1) * m_ + t] : 0.0;
+        }
+    }
+    if (detail->sketch_basis && s_ > 0) {
+      std::vector<double> Y((size_t)n_ * lds_);
+      LD_HIP(hipMemcpy(Y.data(), Y_, Y.size() * 8, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < n_; ++i)
+        for (int j = 0; j < s_; ++j) detail->sketch_basis[i * s_ + j] = Y[(size_t)i * lds_ + j];
+    }
+  }
+  *out = res;
+  return LD_OK;
+}
+
+}  // namespace ld
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+using namespace ld;
+
+#define LD_HIP_API(expr)                                                                \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return set_error(LD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" {
+
+const char* ld_last_error(void) { return g_last_error.c_str(); }
+
+ld_status ld_ctx_create(const ld_ctx_opts* opts, ld_ctx** out) {
+  if (!out) return set_error(LD_E_INVALID_ARG, "null out pointer");
+  ld_ctx_opts o{};
+  if (opts) o = *opts;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return set_error(LD_E_DEVICE, "no HIP device available");
+  if (o.device < 0 || o.device >= ndev) return set_error(LD_E_INVALID_ARG, "bad device ordinal");
+  if (o.default_method != LD_METHOD_OSLQ && o.default_method != LD_METHOD_OSA_IOP)
+    return set_error(LD_E_INVALID_ARG, "bad default_method");
+  if (o.default_precision != LD_PREC_FP64 && o.default_precision != LD_PREC_MIXED)
+    return set_error(LD_E_INVALID_ARG, "bad default_precision");
+  LD_HIP_API(hipSetDevice(o.device));
+  std::unique_ptr<ld_ctx> c(new ld_ctx());
+  c->device = o.device;
+  c->opts = o;
+  if (c->opts.max_slots <= 0) c->opts.max_slots = 16;
+  if (o.hip_stream) {
+    c->stream = static_cast<hipStream_t>(o.hip_stream);
+    c->own_stream = false;
+  } else {
+    LD_HIP_API(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  if (c->opts.hbm_budget_bytes == 0) {
+    size_t fr = 0, tot = 0;
+    LD_HIP_API(hipMemGetInfo(&fr, &tot));
+    c->opts.hbm_budget_bytes = (uint64_t)(0.8 * (double)fr);
+  }
+  *out = c.release();
+  return LD_OK;
+}
+
+ld_status ld_ctx_destroy(ld_ctx* ctx) {
+  if (!ctx) return set_error(LD_E_INVALID_ARG, "null context");
+  if (ctx->n_matrices.load() > 0)
+    return set_error(LD_E_BUSY, "destroy every matrix of the context first");
+  (void)hipSetDevice(ctx->device);
+  ctx->server.reset();
+  ctx->workspace.release();
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return LD_OK;
+}
+
+// FP64 -> BF16 with a single round-to-nearest-even: truncate toward zero to
+// FP32 (keeping whether anything was dropped), then round the low 16 bits.
+static uint16_t double_to_bf16_rne(double d) {
+  const double ad = std::fabs(d);
+  float fa = (float)ad;
+  if ((double)fa > ad) fa = std::nextafter(fa, 0.0f);
+  const bool inexact = (double)fa != ad;
+  uint32_t u;
+  std::memcpy(&u, &fa, 4);
+  const uint32_t lower = u & 0xFFFFu;
+  uint32_t upper = u >> 16;
+  if (lower > 0x8000u || (lower == 0x8000u && (inexact || (upper & 1u)))) ++upper;
+  return (uint16_t)(upper | (std::signbit(d) ? 0x8000u : 0u));
+}
+
+ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                        const int32_t* col_idx, const double* values, int32_t vt,
+                        double lambda_lo_hint, double lambda_hi_hint, ld_matrix** out) {
+  if (!ctx || !out || !row_ptr || !col_idx || !values)
+    return set_error(LD_E_INVALID_ARG, "null argument");
+  if (n < 1 || nnz < n || n > INT32_MAX || nnz > INT32_MAX)
+    return set_error(LD_E_INVALID_ARG, "need 1 <= n <= nnz <= 2^31-1");
+  if (vt != LD_VT_FP64 && vt != LD_VT_FP32 && vt != LD_VT_BF16)
+    return set_error(LD_E_INVALID_ARG, "bad value type");
+  if (!(lambda_lo_hint >= 0.0) || !(lambda_hi_hint >= 0.0) ||
+      (lambda_lo_hint > 0 && lambda_hi_hint > 0 && lambda_lo_hint > lambda_hi_hint))
+    return set_error(LD_E_INVALID_ARG, "bad spectral hints");
+  // structure checks on the host copy
+  if (row_ptr[0] != 0 || row_ptr[n] != nnz) return set_error(LD_E_BAD_CSR, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t a = row_ptr[i], b = row_ptr[i + 1];
+    if (b < a) return set_error(LD_E_BAD_CSR, "row_ptr not monotone at row " + std::to_string(i));
+    bool diag = false;
+    for (int32_t k = a; k < b; ++k) {
+      const int32_t c = col_idx[k];
+      if (c < 0 || c >= n) return set_error(LD_E_BAD_CSR, "column index out of range in row " + std::to_string(i));
+      if (k > a && c <= col_idx[k - 1])
+        return set_error(LD_E_BAD_CSR, "columns not sorted/unique in row " + std::to_string(i));
+      if (!std::isfinite(values[k])) return set_error(LD_E_BAD_CSR, "non-finite value in row " + std::to_string(i));
+      if (c == i) {
+        diag = true;
+        if (!(values[k] > 0.0))
+          return set_error(LD_E_NOT_SPD, "non-positive diagonal entry in row " + std::to_string(i));
+      }
+    }
+    if (!diag) return set_error(LD_E_NOT_SPD, "missing diagonal entry in row " + std::to_string(i));
+  }
+  LD_HIP_API(hipSetDevice(ctx->device));
+  std::unique_ptr<ld_matrix> m(new ld_matrix());
+  m->ctx = ctx;
+  m->n = n;
+  m->nnz = nnz;
+  m->vt = vt;
+  m->lo_hint = lambda_lo_hint;
+  m->hi_hint = lambda_hi_hint;
+  auto cleanup = [&]() {
+    if (m->rp) (void)hipFree(m->rp);
+    if (m->ci) (void)hipFree(m->ci);
+    if (m->v64) (void)hipFree(m->v64);
+    if (m->vlo) (void)hipFree(m->vlo);
+  };
+  hipError_t e = hipMalloc(&m->rp, (size_t)(n + 1) * 4);
+  if (e == hipSuccess) e = hipMalloc(&m->ci, (size_t)nnz * 4);
+  if (e == hipSuccess) e = hipMalloc(&m->v64, (size_t)nnz * 8);
+  m->vt_lo = (vt == LD_VT_BF16) ? VT_BF16 : VT_F32;
+  const size_t lo_bytes = (size_t)nnz * (m->vt_lo == VT_BF16 ? 2 : 4);
+  if (e == hipSuccess) e = hipMalloc(&m->vlo, lo_bytes);
+  if (e != hipSuccess) {
+    cleanup();
+    return set_error(e == hipErrorOutOfMemory ? LD_E_NO_MEMORY : LD_E_DEVICE,
+                     std::string("matrix allocation: ") + hipGetErrorString(e));
+  }
+  m->bytes = (size_t)(n + 1) * 4 + (size_t)nnz * 12 + lo_bytes;
+  std::vector<char> lo_host(lo_bytes);
+  if (m->vt_lo == VT_BF16) {
+    uint16_t* h = reinterpret_cast<uint16_t*>(lo_host.data());
+    for (int64_t k = 0; k < nnz; ++k) h[k] = double_to_bf16_rne(values[k]);
+  } else {
+    float* h = reinterpret_cast<float*>(lo_host.data());
+    for (int64_t k = 0; k < nnz; ++k) h[k] = (float)values[k];
+  }
+  e = hipMemcpy(m->rp, row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->ci, col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->v64, values, (size_t)nnz * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->vlo, lo_host.data(), lo_bytes, hipMemcpyHostToDevice);
+  // Gershgorin interval (Section 2.1), on the device
+  double* part = nullptr;
+  const int nb = (int)((n + kThreads - 1) / kThreads);
+  if (e == hipSuccess) e = hipMalloc(&part, (size_t)nb * 2 * 8);
+  int nparts = 0;
+  if (e == hipSuccess) e = launch_gershgorin(ctx->stream, n, m->rp, m->ci, m->v64, part, &nparts);
+  std::vector<double> hp((size_t)nb * 2);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipMemcpy(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost);
+  if (part) (void)hipFree(part);
+  if (e != hipSuccess) {
+    cleanup();
+    return set_error(LD_E_DEVICE, std::string("matrix upload: ") + hipGetErrorString(e));
+  }
+  double glo = INFINITY, ghi = -INFINITY;
+  for (int b = 0; b < nparts; ++b) {
+    glo = std::min(glo, hp[2 * b]);
+    ghi = std::max(ghi, hp[2 * b + 1]);
+  }
+  m->glo = glo;
+  m->ghi = ghi;
+  double hi = lambda_hi_hint > 0 ? lambda_hi_hint : ghi;
+  double lo = lambda_lo_hint > 0 ? lambda_lo_hint : glo;
+  if (lo <= 0.0) lo = 1e-6 * hi;  // Gershgorin lower bound not positive: small positive floor
+  if (!(lo > 0.0) || !(hi >= lo) || !std::isfinite(hi)) {
+    cleanup();
+    return set_error(LD_E_INVALID_ARG, "spectral interval is empty or not finite");
+  }
+  m->lo = lo;
+  m->hi = hi;
+  ctx->n_matrices.fetch_add(1);
+  *out = m.release();
+  return LD_OK;
+}
+
+ld_status ld_destroy(ld_matrix* a) {
+  if (!a) return set_error(LD_E_INVALID_ARG, "null matrix");
+  if (a->inflight.load() > 0) return set_error(LD_E_BUSY, "requests still use the matrix");
+  (void)hipSetDevice(a->ctx->device);
+  (void)hipStreamSynchronize(a->ctx->stream);
+  if (a->rp) (void)hipFree(a->rp);
+  if (a->ci) (void)hipFree(a->ci);
+  if (a->v64) (void)hipFree(a->v64);
+  if (a->vlo) (void)hipFree(a->vlo);
+  a->ctx->n_matrices.fetch_sub(1);
+  delete a;
+  return LD_OK;
+}
+
+ld_status ld_matrix_bounds(const ld_matrix* a, double* lo, double* hi) {
+  if (!a || !lo || !hi) return set_error(LD_E_INVALID_ARG, "null argument");
+  *lo = a->lo;
+  *hi = a->hi;
+  return LD_OK;
+}
+
+ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
+                             const ld_detail* detail) {
+  if (!a || !p || !out) return set_error(LD_E_INVALID_ARG, "null argument");
+  const double t0 = now_seconds();
+  ld_ctx* ctx = a->ctx;
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  LD_HIP_API(hipSetDevice(ctx->device));
+  Run run(a, *p);
+  run.set_submit_time(t0);
+  ld_status rc = run.validate();
+  if (rc != LD_OK) return rc;
+  const size_t need = run.device_bytes();
+  hipError_t e = ctx->workspace.ensure(need);
+  if (e != hipSuccess)
+    return set_error(e == hipErrorOutOfMemory ? LD_E_NO_MEMORY : LD_E_DEVICE,
+                     std::string("workspace allocation: ") + hipGetErrorString(e));
+  rc = run.bind(ctx->workspace.ptr, ctx->workspace.bytes);
+  if (rc != LD_OK) return rc;
+  bool done = false;
+  while (!done) {
+    rc = run.advance(ctx->stream, 1 << 30, &done);
+    if (rc != LD_OK) {
+      (void)hipStreamSynchronize(ctx->stream);
+      return rc;
+    }
+  }
+  return run.collect(ctx->stream, out, detail);
+}
+
+ld_status ld_estimate_ex(ld_matrix* a, const ld_params* p, ld_result* out) {
+  return ld_estimate_detail(a, p, out, nullptr);
+}
+
+ld_status ld_estimate(ld_matrix* a, int32_t n_probes, int32_t sketch_rank, int32_t krylov_steps,
+                      int32_t iop_window, uint64_t seed, ld_result* out) {
+  if (!a) return set_error(LD_E_INVALID_ARG, "null matrix");
+  ld_params p{};
+  p.method = a->ctx->opts.default_method;
+  p.precision = a->ctx->opts.default_precision;
+  p.n_probes = n_probes;
+  p.sketch_rank = sketch_rank;
+  p.krylov_steps = krylov_steps;
+  p.iop_window = iop_window;
+  p.seed = seed;
+  p.tol = 0.0;
+  return ld_estimate_detail(a, &p, out, nullptr);
+}
+
+ld_status ld_debug_rademacher(ld_ctx* ctx, uint64_t seed, int64_t n, int32_t col_begin,
+                              int32_t col_end, double* out) {
+  if (!ctx || !out || n < 1 || col_begin < 0 || col_end <= col_begin || n > INT32_MAX)
+    return set_error(LD_E_INVALID_ARG, "bad argument");
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  LD_HIP_API(hipSetDevice(ctx->device));
+  const int nc = col_end - col_begin;
+  const int ld = (nc + 3) & ~3;
+  DeviceBuffer buf;
+  LD_HIP_API(buf.ensure((size_t)n * ld * 8));
+  LD_HIP_API(launch_rademacher(ctx->stream, seed, n, col_begin, ld, nc, buf.ptr, 8, ld, 0));
+  LD_HIP_API(hipStreamSynchronize(ctx->stream));
+  std::vector<double> h((size_t)n * ld);
+  LD_HIP_API(hipMemcpy(h.data(), buf.ptr, h.size() * 8, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n; ++i)
+    for (int j = 0; j < nc; ++j) out[i * nc + j] = h[(size_t)i * ld + j];
+  return LD_OK;
+}
+
+static ld::Server* server_of(ld_ctx* ctx) {
+  std::lock_guard<std::mutex> lk(ctx->server_mu);
+  if (!ctx->server) ctx->server.reset(new ld::Server(ctx));
+  return ctx->server.get();
+}
+
+ld_status ld_submit(ld_matrix* a, const ld_params* p, uint64_t* ticket) {
+  if (!a || !p || !ticket) return set_error(LD_E_INVALID_ARG, "null argument");
+  return server_of(a->ctx)->submit(a, *p, ticket);
+}
+
+ld_status ld_poll(ld_ctx* ctx, uint64_t ticket, ld_result* out) {
+  if (!ctx || !out) return set_error(LD_E_INVALID_ARG, "null argument");
+  return server_of(ctx)->poll(ticket, out, false);
+}
+
+ld_status ld_wait(ld_ctx* ctx, uint64_t ticket, ld_result* out) {
+  if (!ctx || !out) return set_error(LD_E_INVALID_ARG, "null argument");
+  return server_of(ctx)->poll(ticket, out, true);
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// Host runtime of liblogdet: contexts, the device-resident matrix registry
+// and the estimate pipeline.  Internal header (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/liblogdet.h"
+#include "ld_kernels.h"
+
+namespace ld {
+
+// Thread-local error text behind ld_last_error().
+ld_status set_error(ld_status st, const std::string& msg);
+
+// Device memory with a byte ledger.
+struct DeviceBuffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  ~DeviceBuffer();
+  hipError_t ensure(size_t want);  // grow-only
+  void release();
+};
+
+class Server;
+
+}  // namespace ld
+
+struct ld_ctx {
+  ld_ctx();
+  ~ld_ctx();  // defined where ld::Server is complete
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  ld_ctx_opts opts{};
+  std::mutex est_mu;             // blocking estimates share the stream and workspace
+  ld::DeviceBuffer workspace;
+  std::atomic<int> n_matrices{0};
+  std::unique_ptr<ld::Server> server;
+  std::mutex server_mu;
+};
+
+struct ld_matrix {
+  ld_ctx* ctx = nullptr;
+  int64_t n = 0, nnz = 0;
+  int* rp = nullptr;
+  int* ci = nullptr;
+  double* v64 = nullptr;    // FP64 values (LD_PREC_FP64 runs)
+  void* vlo = nullptr;      // FP32 or BF16 values (LD_PREC_MIXED runs)
+  int vt_lo = 1;            // storage type of vlo (VT_F32 or VT_BF16)
+  int vt = 0;               // requested ld_value_type
+  double glo = 0, ghi = 0;  // Gershgorin bounds
+  double lo_hint = 0, hi_hint = 0;
+  double lo = 0, hi = 0;    // interval used by the estimators
+  size_t bytes = 0;
+  std::atomic<int> inflight{0};
+};
+
+namespace ld {
+
+// One estimate: the device state of one (matrix, params) request and the
+// ordered list of device operations that compute it.  advance() enqueues
+// work on a stream in slices (at most `budget` Krylov steps per call) so that
+// the serving scheduler can interleave many requests; a blocking estimate
+// simply calls it until it reports that everything is enqueued.
+class Run {
+ public:
+  Run(ld_matrix* a, const ld_params& p);
+  ~Run();
+  ld_status validate();                 // parameter checks, derived sizes
+  size_t device_bytes() const;          // bytes needed on the device
+  ld_status bind(void* base, size_t bytes);  // carve the device buffers
+  // Enqueue up to `budget` Krylov steps (non-Krylov phases count as one).
+  // Returns LD_OK when more work remains, LD_PENDING... see .cpp.
+  ld_status advance(hipStream_t st, int budget, bool* done);
+  ld_status collect(hipStream_t st, ld_result* out, const ld_detail* detail);
+  ld_matrix* matrix() const { return a_; }
+  const ld_params& params() const { return p_; }
+
+ private:
+  struct Phase;
+  ld_status run_prologue(hipStream_t st);
+  ld_status run_krylov_step(hipStream_t st, int t);
+  ld_status run_epilogue(hipStream_t st);
+  ld_status sketch_qr(hipStream_t st, double* Y);
+  ld_status osa_sketch_prologue(hipStream_t st);
+  ld_status osa_sketch_combine(hipStream_t st);
+  ld_status start_block(hipStream_t st, const double* A, int s_cols);
+  ld_status begin_krylov(int phase);
+  size_t layout(char* base);
+
+  ld_matrix* a_;
+  ld_params p_;
+  // derived
+  int64_t n_ = 0;
+  int s_ = 0, r_ = 0, B_ = 0, m_ = 0, k_ = 0;
+  double tol_ = 1e-10;
+  double lo_ = 0, hi_ = 0, scale_ = 1, c_ = 0, opscale_ = 1;
+  bool mixed_ = false;
+  int xb_ = 8;                // bytes per Krylov element
+  int lds_ = 0, ldr_ = 0, ldB_ = 0, ld1_ = 0;
+  Geom gB_, gS_, g1_;
+  // state machine
+  int stage_ = 0;             // 0 prologue, 1 krylov, 2 epilogue..., see .cpp
+  int t_ = 0;
+  int kphase_ = 0;            // OSA-IOP: 0 sketch-image runs, 1 estimate runs
+  // Krylov phase parameters (current)
+  int kB_ = 0, kld_ = 0, kns_ = 0;
+  bool kpin_ = false, kfull_ = false;
+  Geom kg_;
+  void* kslots_ = nullptr;
+  double* kmult_ = nullptr;
+  // device buffers
+  double* S_ = nullptr;       // [n][lds] sketch probes (aliases G_)
+  double* Y_ = nullptr;       // [n][lds] sketch image -> basis A
+  double* G_ = nullptr;       // [n][ldr] residual probes
+  void* slots_ = nullptr;     // Krylov storage
+  double* mult_ = nullptr;    // [nslots][ld]
+  double* part_ = nullptr;    // per-block partial sums
+  double* dwin_ = nullptr;    // [nvmax][ld] reduced window dots
+  double* nsr_ = nullptr;     // [2][ld] reduced norm / v1 dots
+  double* norm2_ = nullptr;   // [ld]
+  double* K_ = nullptr;       // [ld]
+  double* H_ = nullptr;       // [ld][(m+1) m]
+  double* gq_ = nullptr;      // [ld][m+1]
+  double* work_ = nullptr;    // quadrature / log work
+  double* gram_ = nullptr;    // [s][s]
+  double* rfac_ = nullptr;    // [s][s]
+  double* rinv_ = nullptr;    // [s][s]
+  double* pmat_ = nullptr;    // [s][r]
+  double* ell_ = nullptr;     // OSA-IOP: [ld][m] log(H) e1 of the sketch runs
+  double* coefs_ = nullptr;   // OSA-IOP: [m][ld1] combination coefficients
+  int* meff_ = nullptr;
+  int* active_ = nullptr;
+  int* flags_ = nullptr;
+  int* dflag_ = nullptr;      // [2] CholQR flags
+  size_t part_elems_ = 0;
+  size_t slot_elems_ = 0;     // elements of one [n][ld] slot
+  int nslots_ = 0;
+  hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+  double t_submit_ = 0;
+ public:
+  double submit_time() const { return t_submit_; }
+  void set_submit_time(double t) { t_submit_ = t; }
+  int64_t n() const { return n_; }
+};
+
+double now_seconds();
+
+}  // namespace ld

@@ -1,0 +1,68 @@
+// Serving scheduler: continuous batching of logdet requests on one GPU.
+//
+// Requests wait in a FIFO until a resident slot and enough of the HBM budget
+// are free; admitted requests own private device state, so a result depends
+// only on its own matrix and parameters.  Each scheduler tick enqueues a few
+// Krylov steps of every resident request on that slot's stream; the streams
+// run concurrently on the device, and a request that finishes frees its slot
+// and memory for the next one at the following tick.
+#pragma once
+
+#include "runtime.h"
+
+namespace ld {
+
+class Server {
+ public:
+  explicit Server(ld_ctx* ctx);
+  ~Server();  // drains every submitted request, then stops the scheduler
+  ld_status submit(ld_matrix* a, const ld_params& p, uint64_t* ticket);
+  ld_status poll(uint64_t ticket, ld_result* out, bool wait);
+
+  // scheduler statistics
+  struct Stats {
+    uint64_t submitted = 0, completed = 0, ticks = 0;
+    size_t peak_bytes = 0;
+    int peak_active = 0;
+  };
+  Stats stats();
+
+ private:
+  struct Request {
+    uint64_t ticket = 0;
+    std::unique_ptr<Run> run;
+    size_t bytes = 0;
+  };
+  struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done_ev = nullptr;
+    std::unique_ptr<Request> req;
+    void* mem = nullptr;
+    size_t mem_bytes = 0;
+    bool enqueued_all = false;
+    bool bound = false;
+  };
+  struct Done {
+    ld_status status = LD_OK;
+    ld_result result{};
+    std::string error;
+  };
+  void loop();
+  void finish(Slot& s, ld_status st, const ld_result* res, const std::string& err);
+
+  ld_ctx* ctx_;
+  std::mutex mu_;
+  std::condition_variable cv_work_, cv_done_;
+  std::deque<std::unique_ptr<Request>> queue_;
+  std::map<uint64_t, Done> done_;
+  std::map<uint64_t, bool> live_;   // submitted and not yet retired
+  std::vector<Slot> slots_;
+  size_t budget_ = 0, used_ = 0;
+  uint64_t next_ticket_ = 1;
+  bool stop_ = false;
+  int steps_per_tick_ = 4;
+  Stats stats_;
+  std::thread thread_;
+};
+
+}  // namespace ld
