@@ -172,6 +172,28 @@ ld_status ld_poll(ld_ctx* ctx, uint64_t ticket, ld_result* out);
 /* Blocks until the request finishes, then behaves as ld_poll. */
 ld_status ld_wait(ld_ctx* ctx, uint64_t ticket, ld_result* out);
 
+/* Instrumentation (off by default).  While enabled, every launch of a kernel
+ * family in `family_mask` is bracketed by two HIP events recorded on the
+ * stream the kernel runs on.  ld_profile_query returns, for the families in
+ * `family` (summed), the number of launches, the summed device time (ms) and
+ * the summed algorithmic bytes: the minimum HBM traffic each launch implies
+ * (matrix, vectors read, vectors written; partial sums excluded).  Enabling
+ * (or disabling) resets the counters.  Times are harvested when a blocking
+ * estimate returns. */
+enum {
+  LD_PROF_SPMM = 1,     /* CSR x probe block                                 */
+  LD_PROF_DOTS = 2,     /* window inner products                             */
+  LD_PROF_UPDATE = 4,   /* orthogonalisation update + norms                  */
+  LD_PROF_REDUCE = 8,   /* fixed-order reductions of partial sums            */
+  LD_PROF_SMALL = 16,   /* per-probe bookkeeping, quadrature, Hessenberg log */
+  LD_PROF_SKETCH = 32,  /* Gram, Cholesky, triangular solve, projection      */
+  LD_PROF_PROBES = 64,  /* Rademacher generation                             */
+  LD_PROF_ALL = 127
+};
+ld_status ld_profile_enable(ld_ctx* ctx, uint32_t family_mask);
+ld_status ld_profile_query(ld_ctx* ctx, uint32_t family, int64_t* launches, double* total_ms,
+                           double* total_bytes);
+
 /* Test hook: the Rademacher probe columns col_begin..col_end-1 (n rows) as
  * generated on the device, copied to host memory out[n * (col_end -
  * col_begin)], row-major. */

@@ -6,53 +6,49 @@
 
 namespace ld {
 
-// part[b][i][j] over a 64 x 64 output tile per grid.y; rows staged through LDS
-// 32 at a time, each thread accumulating a 4 x 4 micro-tile in row order.
+// part[i][j][b] over a 32 x 32 output tile per grid.y; rows staged through
+// LDS 64 at a time, each thread accumulating a 2 x 2 micro-tile in row order.
 __global__ __launch_bounds__(kThreads) void k_gemm_tn(int64_t n, int rpb, const double* __restrict__ Xa,
                                                      int lda, int ca, const double* __restrict__ Xb,
                                                      int ldb, int cb, double* __restrict__ part) {
-  __shared__ double sa[32][64 + 1];
-  __shared__ double sb[32][64 + 1];
+  constexpr int TR = 64, TT = 32;
+  __shared__ double sa[TR][TT + 1];
+  __shared__ double sb[TR][TT + 1];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t r0 = (int64_t)lb * rpb;
   const int64_t r1 = min(n, r0 + (int64_t)rpb);
-  const int ntj = (cb + 63) / 64;
+  const int ntj = (cb + TT - 1) / TT;
   const int ti = blockIdx.y / ntj, tj = blockIdx.y % ntj;
-  const int i0 = ti * 64, j0 = tj * 64;
-  const int ni = min(64, ca - i0), nj = min(64, cb - j0);
+  const int i0 = ti * TT, j0 = tj * TT;
+  const int ni = min(TT, ca - i0), nj = min(TT, cb - j0);
   const int t = threadIdx.x;
-  const int ii0 = (t >> 4) * 4, jj0 = (t & 15) * 4;
-  double acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int64_t row0 = r0; row0 < r1; row0 += 32) {
-    for (int e = t; e < 32 * 64; e += kThreads) {
-      const int rr = e >> 6, c = e & 63;
+  const int ii0 = (t >> 4) * 2, jj0 = (t & 15) * 2;
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int64_t row0 = r0; row0 < r1; row0 += TR) {
+    for (int e = t; e < TR * TT; e += kThreads) {
+      const int rr = e / TT, c = e % TT;
       const int64_t row = row0 + rr;
       sa[rr][c] = (row < r1 && c < ni) ? Xa[(size_t)row * lda + i0 + c] : 0.0;
       sb[rr][c] = (row < r1 && c < nj) ? Xb[(size_t)row * ldb + j0 + c] : 0.0;
     }
     __syncthreads();
-    const int nr = (int)min((int64_t)32, r1 - row0);
+    const int nr = (int)min((int64_t)TR, r1 - row0);
     for (int rr = 0; rr < nr; ++rr) {
-      double a[4], b[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) { a[q] = sa[rr][ii0 + q]; b[q] = sb[rr][jj0 + q]; }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+      const double a0 = sa[rr][ii0], a1 = sa[rr][ii0 + 1];
+      const double b0 = sb[rr][jj0], b1 = sb[rr][jj0 + 1];
+      acc[0][0] = fma(a0, b0, acc[0][0]);
+      acc[0][1] = fma(a0, b1, acc[0][1]);
+      acc[1][0] = fma(a1, b0, acc[1][0]);
+      acc[1][1] = fma(a1, b1, acc[1][1]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
+    for (int y = 0; y < 2; ++y) {
       const int i = ii0 + x, j = jj0 + y;
-      if (i < ni && j < nj) part[((size_t)lb * ca + i0 + i) * cb + j0 + j] = acc[x][y];
+      if (i < ni && j < nj) part[((size_t)(i0 + i) * cb + j0 + j) * gridDim.x + lb] = acc[x][y];
     }
 }
 
@@ -141,56 +137,60 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows(int64_t n, double* __res
 }
 
 // Start block of the Krylov runs: columns [A | G - A P], plus per-block
-// partial squared column norms (FP64 values, before any narrowing).
+// partial squared column norms (FP64 values, before any narrowing).  Rows go
+// through LDS in tiles of 32; thread t owns column t % tpc.
 template <typename XT>
 __global__ __launch_bounds__(kThreads) void k_project(int64_t n, int rpb, const double* __restrict__ A,
                                                      int lda, int s, const double* __restrict__ Gm,
                                                      int ldg, int r, const double* __restrict__ P,
                                                      int p_in_lds, XT* __restrict__ X0, int ld,
-                                                     int tpr, double* __restrict__ part) {
+                                                     int tpc, double* __restrict__ part) {
+  constexpr int TR = 32;
   extern __shared__ double sm[];
-  const int rpi = kThreads / tpr;
-  double* sa = sm;                 // [rpi][s]
-  double* sp = sm + rpi * s;       // [s][r] when p_in_lds
+  double* sa = sm;                 // [TR][s]
+  double* sp = sm + TR * s;        // [s][r] when p_in_lds
+  double* red = sm;                // [kThreads] after the row loop
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t r0 = (int64_t)lb * rpb;
   const int64_t r1 = min(n, r0 + (int64_t)rpb);
   const int t = threadIdx.x;
-  const int c = t % tpr, rg = t / tpr;
+  const int c = t % tpc, rg = t / tpc, ngrp = kThreads / tpc;
   if (p_in_lds)
     for (int e = t; e < s * r; e += kThreads) sp[e] = P[e];
   const double* Pp = p_in_lds ? sp : P;
   double nacc = 0.0;
-  for (int64_t rowb = r0; rowb < r1; rowb += rpi) {
+  for (int64_t rowb = r0; rowb < r1; rowb += TR) {
     __syncthreads();
-    for (int e = t; e < rpi * s; e += kThreads) {
+    for (int e = t; e < TR * s; e += kThreads) {
       const int rr = e / s, i = e % s;
       sa[e] = (rowb + rr < r1) ? A[(size_t)(rowb + rr) * lda + i] : 0.0;
     }
     __syncthreads();
-    const int64_t row = rowb + rg;
-    if (row < r1 && c < ld) {
-      double val = 0.0;
-      if (c < s) {
-        val = sa[rg * s + c];
-      } else if (c < s + r) {
-        const int j = c - s;
-        double acc = 0.0;
-        for (int i = 0; i < s; ++i) acc = fma(sa[rg * s + i], Pp[(size_t)i * r + j], acc);
-        val = Gm[(size_t)row * ldg + j] - acc;
+    if (c < ld) {
+      for (int rr = rg; rr < TR; rr += ngrp) {
+        const int64_t row = rowb + rr;
+        if (row >= r1) break;
+        double val = 0.0;
+        if (c < s) {
+          val = sa[rr * s + c];
+        } else if (c < s + r) {
+          const int j = c - s;
+          double acc = 0.0;
+          for (int i = 0; i < s; ++i) acc = fma(sa[rr * s + i], Pp[(size_t)i * r + j], acc);
+          val = Gm[(size_t)row * ldg + j] - acc;
+        }
+        X0[(size_t)row * ld + c] = XT(val);
+        nacc = fma(val, val, nacc);
       }
-      X0[(size_t)row * ld + c] = XT(val);
-      nacc = fma(val, val, nacc);
     }
   }
   __syncthreads();
-  double* red = sm;  // [rpi][tpr]
-  red[rg * tpr + c] = nacc;
+  red[t] = nacc;
   __syncthreads();
   if (rg == 0 && c < ld) {
     double sum = 0.0;
-    for (int q = 0; q < rpi; ++q) sum += red[q * tpr + c];
-    part[(size_t)lb * ld + c] = sum;
+    for (int q = 0; q < ngrp; ++q) sum += red[q * tpc + c];
+    part[(size_t)c * gridDim.x + lb] = sum;
   }
 }
 
@@ -232,7 +232,7 @@ hipError_t launch_gemm_tn(hipStream_t st, const Geom& g, const double* Xa, int l
   if (g.n < 1 || g.nblk < 1 || !Xa || !Xb || !part || ca < 1 || cb < 1 || ca > lda || cb > ldb ||
       (int64_t)g.nblk * g.rpb < g.n)
     return hipErrorInvalidValue;
-  const int nt = ((ca + 63) / 64) * ((cb + 63) / 64);
+  const int nt = ((ca + 31) / 32) * ((cb + 31) / 32);
   hipLaunchKernelGGL(k_gemm_tn, dim3(g.nblk, nt), dim3(kThreads), 0, st, g.n, g.rpb, Xa, lda, ca,
                      Xb, ldb, cb, part);
   return hipGetLastError();
@@ -258,23 +258,21 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
   if (g.n < 1 || g.nblk < 1 || (int64_t)g.nblk * g.rpb < g.n || !Gm || !X0 || !part || r < 1 ||
       s < 0 || s + r > g.ld || g.ld > 256 || (s > 0 && (!A || !P || lda < s)) || ldg < r)
     return hipErrorInvalidValue;
-  int tpr = 1;
-  while (tpr < g.ld) tpr <<= 1;
-  const int rpi = kThreads / tpr;
-  size_t lds = (size_t)rpi * (s > 0 ? s : 1) * sizeof(double);
-  if (lds < (size_t)kThreads * sizeof(double)) lds = (size_t)kThreads * sizeof(double);
+  int tpc = 1;
+  while (tpc < g.ld) tpc <<= 1;
+  size_t lds = (size_t)32 * s * sizeof(double);
   int p_in_lds = 0;
   if (s > 0 && lds + (size_t)s * r * sizeof(double) <= 48 * 1024) {
     p_in_lds = 1;
-    lds = (size_t)(rpi * s + s * r) * sizeof(double);
-    if (lds < (size_t)kThreads * sizeof(double)) lds = (size_t)kThreads * sizeof(double);
+    lds += (size_t)s * r * sizeof(double);
   }
+  if (lds < (size_t)kThreads * sizeof(double)) lds = (size_t)kThreads * sizeof(double);
   if (g.xbytes == 8)
     hipLaunchKernelGGL(k_project<double>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A, lda,
-                       s, Gm, ldg, r, P, p_in_lds, static_cast<double*>(X0), g.ld, tpr, part);
+                       s, Gm, ldg, r, P, p_in_lds, static_cast<double*>(X0), g.ld, tpc, part);
   else
     hipLaunchKernelGGL(k_project<float>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A, lda,
-                       s, Gm, ldg, r, P, p_in_lds, static_cast<float*>(X0), g.ld, tpr, part);
+                       s, Gm, ldg, r, P, p_in_lds, static_cast<float*>(X0), g.ld, tpc, part);
   return hipGetLastError();
 }
 

@@ -9,6 +9,10 @@
 #include "ld_kernels.h"
 #include "gw_ql.h"
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 namespace ld {
 
 // ---------------------------------------------------------------------------
@@ -60,254 +64,366 @@ __global__ __launch_bounds__(kThreads) void k_rademacher(uint64_t seed, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// CSR x probe block.  G lanes share a row; each lane owns 16 bytes of the
-// row's probe vector.  Column index and value are read once per entry by the
-// row's lanes (same address, one transaction); the gathered X row segments
-// are contiguous.  W = opscale * (Q X) * diag(xmult).
+// Row mapping shared by the streaming kernels.  Rows are swept in chunks of
+// RPI = 256 / L consecutive rows; block b takes chunks b, b + nblk, ... so the
+// whole grid advances through the matrix in order (the rows in flight, and
+// the probe-vector rows their sparse entries gather, stay within a window
+// that the memory-side cache holds).  Inside a chunk L lanes share a row
+// and each lane owns C 16-byte chunks of the row's probe vector (chunk c of
+// lane l is chunk l + L*c), so L*C chunks cover ld columns with few idle
+// lanes (96 FP32 probes: L = 8, C = 3).  Per-block partial sums are stored
+// transposed, part[i][block], so the reduction reads contiguous memory.
 // ---------------------------------------------------------------------------
-template <typename VT, typename XT, int G>
-__global__ __launch_bounds__(kThreads) void k_spmm(int64_t n, int rpb, const int* __restrict__ rp,
+struct RowMap {
+  int lg, L, rpi, rg, gl;
+  __device__ RowMap(int lgL) : lg(lgL), L(1 << lgL), rpi(kThreads >> lgL) {
+    rg = (int)threadIdx.x >> lg;
+    gl = (int)threadIdx.x & (L - 1);
+  }
+};
+
+// Chunk taken by this block in round j.  The grid is at most one resident
+// wave of blocks and, from 8 blocks up, a multiple of 8; blocks are placed
+// round-robin on the 8 XCDs (block b on XCD b % 8), so in every round XCD x
+// gets one contiguous band of the round's chunks: rows a few chunks apart
+// (the +-N neighbours of a stencil) then share that XCD's L2.
+__device__ inline int chunk_of(int j) {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int base = j * nb;
+  return (nb & 7) ? base + b : base + (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// Sum the per-lane accumulators of one vector over the row groups of the
+// block and store the block's partial sums (times mult[col]).
+template <int C, int VEC>
+__device__ inline void block_partials(const double (&acc)[C][VEC], double* red, const RowMap& rm,
+                                      int ld, const double* mult, double* part, size_t row0) {
+  const int WC = rm.L * C * VEC;
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) red[rm.rg * WC + (c * rm.L + rm.gl) * VEC + e] = acc[c][e];
+  __syncthreads();
+  for (int i = threadIdx.x; i < WC; i += kThreads) {
+    double sum = 0.0;
+    for (int q = 0; q < rm.rpi; ++q) sum += red[q * WC + i];
+    if (i < ld) part[(row0 + i) * gridDim.x + blockIdx.x] = sum * (mult ? mult[i] : 1.0);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// CSR x probe block, with the two newest window inner products fused into
+// the epilogue (FUSED).  The newest window vector is the product's own input:
+// its value on the row comes from the gathered diagonal entry (every row
+// stores its diagonal), so only the older one is read again.  W = opscale * (Q X) * diag(xmult); column index and
+// value of an entry are read once by the row's lanes; each lane gathers C
+// contiguous 16-byte segments of the neighbour's probe vector.  For v < nf:
+// part[voff+v][col][block] = mult_v[col] * sum_rows x_v[row][col] w[row][col].
+// ---------------------------------------------------------------------------
+template <typename VT, typename XT, int C, bool FUSED>
+__global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const int* __restrict__ rp,
                                                   const int* __restrict__ ci,
                                                   const VT* __restrict__ va,
                                                   const XT* __restrict__ X, XT* __restrict__ W,
                                                   int ld, int ncolv,
                                                   const double* __restrict__ xmult,
-                                                  double opscale) {
+                                                  double opscale, VecSet vs, int nf, int voff,
+                                                  double* __restrict__ part) {
   using A = typename Acc<XT>::type;
   constexpr int VEC = V16<XT>::N;
-  constexpr int RPI = kThreads / G;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t r0 = (int64_t)lb * rpb;
-  const int64_t r1 = min(n, r0 + (int64_t)rpb);
-  const int rg = threadIdx.x / G, gl = threadIdx.x % G;
-  for (int cv = gl; cv < ncolv; cv += G) {
-    const int col = cv * VEC;
-    double sc[VEC];
+  constexpr int NF = FUSED ? 2 : 1;
+  __shared__ double red[FUSED ? kThreads * VEC * C : 1];
+  const RowMap rm(lgL);
+  bool okc[C];
+  int colc[C];
+  A sc[C][VEC];  // opscale * xmult[col], in the accumulation type
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) sc[e] = opscale * (xmult ? xmult[col + e] : 1.0);
-    for (int64_t row = r0 + rg; row < r1; row += RPI) {
-      A acc[VEC];
+  for (int c = 0; c < C; ++c) {
+    const int cv = rm.gl + rm.L * c;
+    okc[c] = cv < ncolv;
+    colc[c] = cv * VEC;
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) acc[e] = A(0);
-      int k = rp[row];
-      const int kend = rp[row + 1];
-      for (; k + 4 <= kend; k += 4) {
-        int c[4];
-        A a[4];
-        V16<XT> x[4];
+    for (int e = 0; e < VEC; ++e)
+      sc[c][e] = okc[c] ? A(opscale * (xmult ? xmult[colc[c] + e] : 1.0)) : A(0);
+  }
+  double dacc[NF][C][VEC];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          c[u] = ci[k + u];
-          a[u] = value_as<VT, A>(va[k + u]);
+  for (int v = 0; v < NF; ++v)
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) dacc[v][c][e] = 0.0;
+  const int nn = (int)n;  // n < 2^31
+  const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
+  for (int j = 0; j * (int)gridDim.x < nchunk; ++j) {
+    const int ch = chunk_of(j);
+    const int row = ch * rm.rpi + rm.rg;
+    if (ch >= nchunk || row >= nn) continue;
+    A acc[C][VEC];
+    V16<XT> xd[FUSED ? C : 1];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[c][e] = A(0);
+    int k = rp[row];
+    const int kend = rp[row + 1];
+    for (; k + 2 <= kend; k += 2) {
+      const int c0 = ci[k], c1 = ci[k + 1];
+      const A a0 = value_as<VT, A>(va[k]), a1 = value_as<VT, A>(va[k + 1]);
+      V16<XT> x0[C], x1[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        if (okc[c]) {
+          x0[c].load(X + (size_t)c0 * ld + colc[c]);
+          x1[c].load(X + (size_t)c1 * ld + colc[c]);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) x[u].load(X + (size_t)c[u] * ld + col);
+      for (int c = 0; c < C; ++c)
+        if (okc[c]) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) acc[e] = fma(a[u], x[u].v[e], acc[e]);
-      }
-      for (; k < kend; ++k) {
-        const A a = value_as<VT, A>(va[k]);
-        V16<XT> x;
-        x.load(X + (size_t)ci[k] * ld + col);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] = fma(a, x.v[e], acc[e]);
-      }
-      V16<XT> out;
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) out.v[e] = XT(double(acc[e]) * sc[e]);
-      out.store(W + (size_t)row * ld + col);
+          for (int e = 0; e < VEC; ++e) {
+            acc[c][e] = fma(a0, x0[c].v[e], acc[c][e]);
+            acc[c][e] = fma(a1, x1[c].v[e], acc[c][e]);
+          }
+          if (FUSED) {
+            if (c0 == row) xd[c] = x0[c];
+            if (c1 == row) xd[c] = x1[c];
+          }
+        }
     }
+    if (k < kend) {
+      const int c0 = ci[k];
+      const A a0 = value_as<VT, A>(va[k]);
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        if (okc[c]) {
+          V16<XT> x;
+          x.load(X + (size_t)c0 * ld + colc[c]);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[c][e] = fma(a0, x.v[e], acc[c][e]);
+          if (FUSED && c0 == row) xd[c] = x;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (okc[c]) {
+        V16<XT> out;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) out.v[e] = XT(acc[c][e] * sc[c][e]);
+        out.store(W + (size_t)row * ld + colc[c]);
+        if (FUSED) {
+#pragma unroll
+          for (int v = 0; v < NF; ++v)
+            if (v < nf) {
+              V16<XT> x;
+              if (v == nf - 1)
+                x = xd[c];  // the newest window vector is X itself
+              else
+                x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
+#pragma unroll
+              for (int e = 0; e < VEC; ++e)
+                dacc[v][c][e] = fma(double(x.v[e]), double(out.v[e]), dacc[v][c][e]);
+            }
+        }
+      }
+  }
+  if (FUSED) {
+#pragma unroll
+    for (int v = 0; v < NF; ++v)
+      if (v < nf)
+        block_partials<C, VEC>(dacc[v], red, rm, ld, vs.mult[v], part, (size_t)(voff + v) * ld);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Window inner products: per block partials of x_v^T w, FP64 accumulation.
+// Window inner products not fused into the product: up to 4 vectors.
 // ---------------------------------------------------------------------------
-template <typename XT, int G>
-__global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int rpb, const XT* __restrict__ W,
+constexpr int kDotsPerLaunch = 4;
+
+template <typename XT, int C>
+__global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int lgL, const XT* __restrict__ W,
                                                   int ld, int ncolv, VecSet vs, int nv, int voff,
-                                                  int nvtot, double* __restrict__ part) {
+                                                  double* __restrict__ part) {
   constexpr int VEC = V16<XT>::N;
-  constexpr int RPI = kThreads / G;
-  constexpr int CW = G * VEC;
-  __shared__ double red[kThreads * VEC];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t r0 = (int64_t)lb * rpb;
-  const int64_t r1 = min(n, r0 + (int64_t)rpb);
-  const int rg = threadIdx.x / G, gl = threadIdx.x % G;
-  const int npass = (ncolv + G - 1) / G;
-  for (int pass = 0; pass < npass; ++pass) {
-    const int cv = pass * G + gl;
-    const bool ok = cv < ncolv;
-    const int col = cv * VEC;
-    double acc[kMaxNv][VEC];
+  __shared__ double red[kThreads * VEC * C];
+  const RowMap rm(lgL);
+  bool okc[C];
+  int colc[C];
 #pragma unroll
-    for (int v = 0; v < kMaxNv; ++v)
+  for (int c = 0; c < C; ++c) {
+    const int cv = rm.gl + rm.L * c;
+    okc[c] = cv < ncolv;
+    colc[c] = cv * VEC;
+  }
+  double acc[kDotsPerLaunch][C][VEC];
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) acc[v][e] = 0.0;
-    if (ok) {
-      for (int64_t row = r0 + rg; row < r1; row += RPI) {
+  for (int v = 0; v < kDotsPerLaunch; ++v)
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[v][c][e] = 0.0;
+  const int nn = (int)n;  // n < 2^31
+  const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
+  for (int j = 0; j * (int)gridDim.x < nchunk; ++j) {
+    const int ch = chunk_of(j);
+    const int row = ch * rm.rpi + rm.rg;
+    if (ch >= nchunk || row >= nn) continue;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (okc[c]) {
         V16<XT> w;
-        w.load(W + (size_t)row * ld + col);
+        w.load(W + (size_t)row * ld + colc[c]);
 #pragma unroll
-        for (int v = 0; v < kMaxNv; ++v) {
+        for (int v = 0; v < kDotsPerLaunch; ++v)
           if (v < nv) {
             V16<XT> x;
-            x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + col);
+            x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[v][e] = fma(double(x.v[e]), double(w.v[e]), acc[v][e]);
+            for (int e = 0; e < VEC; ++e)
+              acc[v][c][e] = fma(double(x.v[e]), double(w.v[e]), acc[v][c][e]);
           }
-        }
       }
-    }
-#pragma unroll
-    for (int v = 0; v < kMaxNv; ++v) {
-      if (v < nv) {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) red[rg * CW + gl * VEC + e] = acc[v][e];
-        __syncthreads();
-        for (int c = threadIdx.x; c < CW; c += kThreads) {
-          double s = 0.0;
-          for (int q = 0; q < RPI; ++q) s += red[q * CW + c];
-          const int gc = pass * CW + c;
-          if (gc < ld) {
-            const double m = vs.mult[v] ? vs.mult[v][gc] : 1.0;
-            part[((size_t)lb * nvtot + voff + v) * ld + gc] = s * m;
-          }
-        }
-        __syncthreads();
-      }
-    }
   }
+#pragma unroll
+  for (int v = 0; v < kDotsPerLaunch; ++v)
+    if (v < nv) block_partials<C, VEC>(acc[v], red, rm, ld, vs.mult[v], part, (size_t)(voff + v) * ld);
 }
 
 // ---------------------------------------------------------------------------
-// Orthogonalisation update and the new norm: w -= sum_v h_v v_v.
+// Orthogonalisation update and the new norm: w -= sum_v h_v v_v (nv <= NV
+// vectors per launch); with want_norm the block partials of ||w||^2 go to
+// part[0][col][block] and, when v1 is given, those of v1^T w to
+// part[1][col][block].
 // ---------------------------------------------------------------------------
-template <typename XT, int G>
-__global__ __launch_bounds__(kThreads) void k_update(int64_t n, int rpb, XT* __restrict__ W, int ld,
+template <typename XT, int C, int NV, bool V1>
+__global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* __restrict__ W, int ld,
                                                     int ncolv, VecSet vs, int nv,
                                                     const double* __restrict__ d, int voff,
                                                     int want_norm, const XT* __restrict__ v1,
                                                     const double* __restrict__ v1mult,
                                                     double* __restrict__ part) {
   constexpr int VEC = V16<XT>::N;
-  constexpr int RPI = kThreads / G;
-  constexpr int CW = G * VEC;
-  __shared__ double red[2][kThreads * VEC];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t r0 = (int64_t)lb * rpb;
-  const int64_t r1 = min(n, r0 + (int64_t)rpb);
-  const int rg = threadIdx.x / G, gl = threadIdx.x % G;
-  const int npass = (ncolv + G - 1) / G;
-  for (int pass = 0; pass < npass; ++pass) {
-    const int cv = pass * G + gl;
-    const bool ok = cv < ncolv;
-    const int col = cv * VEC;
-    double coef[kMaxNv][VEC];
-    double g1[VEC];
+  __shared__ double red[kThreads * VEC * C];
+  const RowMap rm(lgL);
+  bool okc[C];
+  int colc[C];
+  double coef[NV][C][VEC];
 #pragma unroll
-    for (int v = 0; v < kMaxNv; ++v)
+  for (int c = 0; c < C; ++c) {
+    const int cv = rm.gl + rm.L * c;
+    okc[c] = cv < ncolv;
+    colc[c] = cv * VEC;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int e = 0; e < VEC; ++e)
-        coef[v][e] = (ok && v < nv)
-                         ? d[(size_t)(voff + v) * ld + col + e] * (vs.mult[v] ? vs.mult[v][col + e] : 1.0)
-                         : 0.0;
+        coef[v][c][e] = (okc[c] && v < nv) ? d[(size_t)(voff + v) * ld + colc[c] + e] *
+                                                  (vs.mult[v] ? vs.mult[v][colc[c] + e] : 1.0)
+                                            : 0.0;
+  }
+  double nacc[C][VEC], gacc[V1 ? C : 1][VEC];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) g1[e] = (ok && v1) ? v1mult[col + e] : 0.0;
-    double nacc[VEC], gacc[VEC];
+  for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) { nacc[e] = 0.0; gacc[e] = 0.0; }
-    if (ok) {
-      for (int64_t row = r0 + rg; row < r1; row += RPI) {
+    for (int e = 0; e < VEC; ++e) {
+      nacc[c][e] = 0.0;
+      if constexpr (V1) gacc[c][e] = 0.0;
+    }
+  const int nn = (int)n;  // n < 2^31
+  const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
+  for (int j = 0; j * (int)gridDim.x < nchunk; ++j) {
+    const int ch = chunk_of(j);
+    const int row = ch * rm.rpi + rm.rg;
+    if (ch >= nchunk || row >= nn) continue;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (okc[c]) {
         V16<XT> w;
-        w.load(W + (size_t)row * ld + col);
+        w.load(W + (size_t)row * ld + colc[c]);
         double wd[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) wd[e] = double(w.v[e]);
 #pragma unroll
-        for (int v = 0; v < kMaxNv; ++v) {
+        for (int v = 0; v < NV; ++v)
           if (v < nv) {
             V16<XT> x;
-            x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + col);
+            x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) wd[e] = fma(-coef[v][e], double(x.v[e]), wd[e]);
+            for (int e = 0; e < VEC; ++e) wd[e] = fma(-coef[v][c][e], double(x.v[e]), wd[e]);
           }
-        }
 #pragma unroll
         for (int e = 0; e < VEC; ++e) w.v[e] = XT(wd[e]);
-        w.store(W + (size_t)row * ld + col);
+        w.store(W + (size_t)row * ld + colc[c]);
         if (want_norm) {
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) nacc[e] = fma(double(w.v[e]), double(w.v[e]), nacc[e]);
-          if (v1) {
+          for (int e = 0; e < VEC; ++e) nacc[c][e] = fma(double(w.v[e]), double(w.v[e]), nacc[c][e]);
+          if constexpr (V1) {
             V16<XT> x1;
-            x1.load(v1 + (size_t)row * ld + col);
+            x1.load(v1 + (size_t)row * ld + colc[c]);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) gacc[e] = fma(double(x1.v[e]), double(w.v[e]), gacc[e]);
+            for (int e = 0; e < VEC; ++e)
+              gacc[c][e] = fma(double(x1.v[e]), double(w.v[e]), gacc[c][e]);
           }
         }
       }
-    }
-    if (want_norm) {
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        red[0][rg * CW + gl * VEC + e] = nacc[e];
-        red[1][rg * CW + gl * VEC + e] = gacc[e];
-      }
-      __syncthreads();
-      for (int c = threadIdx.x; c < CW; c += kThreads) {
-        double s0 = 0.0, s1 = 0.0;
-        for (int q = 0; q < RPI; ++q) {
-          s0 += red[0][q * CW + c];
-          s1 += red[1][q * CW + c];
-        }
-        const int gc = pass * CW + c;
-        if (gc < ld) {
-          part[((size_t)lb * 2 + 0) * ld + gc] = s0;
-          part[((size_t)lb * 2 + 1) * ld + gc] = v1 ? s1 * v1mult[gc] : 0.0;
-        }
-      }
-      __syncthreads();
+  }
+  if (want_norm) {
+    block_partials<C, VEC>(nacc, red, rm, ld, nullptr, part, 0);
+    if constexpr (V1) {
+      block_partials<C, VEC>(gacc, red, rm, ld, v1mult, part, (size_t)ld);
+    } else {
+      for (int i = threadIdx.x; i < ld; i += kThreads) part[((size_t)ld + i) * gridDim.x + blockIdx.x] = 0.0;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// out[i] = sum_b part[b][i]: four waves take every fourth block, then the
-// four sums are added in a fixed order.
+// out[i] = sum_b part[i][b]: one wave per output, lanes take every 64th
+// block in order, then a fixed xor-shuffle tree.
 // ---------------------------------------------------------------------------
+__device__ inline double wave_sum_fixed(double s) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
+__device__ inline double row_sum(const double* __restrict__ p, int nblk, int lane) {
+  double s = 0.0;
+  for (int b = lane; b < nblk; b += 64) s += p[b];
+  return wave_sum_fixed(s);
+}
+
 __global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ part, int nblk,
                                                     int width, double* __restrict__ out) {
-  __shared__ double sh[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + lane;
-  double s = 0.0;
-  if (i < width)
-    for (int b = w; b < nblk; b += 4) s += part[(size_t)b * width + i];
-  sh[w][lane] = s;
-  __syncthreads();
-  if (w == 0 && i < width) out[i] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (i >= width) return;
+  const double s = row_sum(part + (size_t)i * nblk, nblk, lane);
+  if (lane == 0) out[i] = s;
 }
 
 // ---------------------------------------------------------------------------
-// Per-probe bookkeeping.
+// Per-probe bookkeeping fused with the reduction of the norm partials.
 // flags: bit 0 numeric (NaN/Inf), bit 1 non-positive Ritz value / log,
 //        bit 2 breakdown (h < tol), bit 3 eigen-iteration did not converge.
 // ---------------------------------------------------------------------------
-__global__ void k_start_finish(int B, int ld, const double* __restrict__ nsum,
-                               double* __restrict__ norm2, double* __restrict__ mult0,
-                               int* __restrict__ active, int* __restrict__ meff,
-                               double* __restrict__ g, int gstride) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kThreads) void k_start_finish(int B, int ld, const double* __restrict__ part,
+                                                          int nblk, double* __restrict__ norm2,
+                                                          double* __restrict__ mult0,
+                                                          int* __restrict__ active,
+                                                          int* __restrict__ meff,
+                                                          double* __restrict__ g, int gstride) {
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (p >= ld) return;
-  const double s = (p < B) ? nsum[p] : 0.0;
-  norm2[p] = s;
+  const double s = row_sum(part + (size_t)p * nblk, nblk, lane);
+  if (lane != 0) return;
+  const double v = (p < B) ? s : 0.0;
+  norm2[p] = v;
   meff[p] = 0;
-  if (p < B && s > 0.0 && isfinite(s)) {
-    mult0[p] = 1.0 / sqrt(s);
+  if (p < B && v > 0.0 && isfinite(v)) {
+    mult0[p] = 1.0 / sqrt(v);
     active[p] = 1;
   } else {
     mult0[p] = 0.0;
@@ -316,13 +432,22 @@ __global__ void k_start_finish(int B, int ld, const double* __restrict__ nsum,
   if (g && p < B) g[(size_t)p * gstride] = 1.0;
 }
 
-__global__ void k_step_finish(int B, int ld, int t, int m, const double* __restrict__ d, int j0,
-                              int nv, const double* __restrict__ ns, double tol,
-                              double* __restrict__ H, int* __restrict__ meff,
-                              int* __restrict__ active, double* __restrict__ mult_next,
-                              double* __restrict__ g, int* __restrict__ flags) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kThreads) void k_step_finish(int B, int ld, int t, int m,
+                                                         const double* __restrict__ d, int j0,
+                                                         int nv, const double* __restrict__ part,
+                                                         int nblk, double tol,
+                                                         double* __restrict__ H,
+                                                         int* __restrict__ meff,
+                                                         int* __restrict__ active,
+                                                         double* __restrict__ mult_next,
+                                                         double* __restrict__ g,
+                                                         int* __restrict__ flags) {
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (p >= ld) return;
+  const double nrm2 = row_sum(part + (size_t)p * nblk, nblk, lane);
+  const double gdot = g ? row_sum(part + (size_t)(ld + p) * nblk, nblk, lane) : 0.0;
+  if (lane != 0) return;
   if (p >= B || !active[p]) {
     mult_next[p] = 0.0;
     return;
@@ -334,7 +459,7 @@ __global__ void k_step_finish(int B, int ld, int t, int m, const double* __restr
     finite = finite && isfinite(h);
     Hp[(size_t)(j0 + v) * m + t] = h;
   }
-  const double beta = sqrt(ns[p]);
+  const double beta = sqrt(nrm2);
   Hp[(size_t)(t + 1) * m + t] = beta;
   meff[p] = t + 1;
   if (!finite || !isfinite(beta)) {
@@ -349,7 +474,7 @@ __global__ void k_step_finish(int B, int ld, int t, int m, const double* __restr
     mult_next[p] = 0.0;
     return;
   }
-  if (g) g[(size_t)p * (m + 1) + t + 1] = ns[ld + p] / beta;
+  if (g) g[(size_t)p * (m + 1) + t + 1] = gdot / beta;
   mult_next[p] = 1.0 / beta;
 }
 
@@ -358,25 +483,28 @@ __global__ void k_step_finish(int B, int ld, int t, int m, const double* __restr
 // One thread per probe; the d/e/z work arrays are [m][B] so that consecutive
 // threads touch consecutive addresses.
 // ---------------------------------------------------------------------------
-__global__ void k_gauss_log(int B, int m, const double* __restrict__ H, const int* __restrict__ meff,
-                            double* __restrict__ work, double* __restrict__ K,
+__global__ void k_gauss_log(int B, int m, int pb, const double* __restrict__ H,
+                            const int* __restrict__ meff, double* __restrict__ K,
                             int* __restrict__ flags) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= B) return;
+  extern __shared__ double sm[];
+  const int pl = threadIdx.x;
+  const int p = blockIdx.x * pb + pl;
+  if (pl >= pb || p >= B) return;
   const int nn = meff[p];
   if (nn <= 0) {
     K[p] = 0.0;
     return;
   }
-  double* dd = work + p;
-  double* ee = work + (size_t)m * B + p;
-  double* zz = work + (size_t)2 * m * B + p;
+  // per-thread arrays in LDS, element i of thread pl at [i * pb + pl]
+  double* dd = sm + pl;
+  double* ee = sm + (size_t)m * pb + pl;
+  double* zz = sm + (size_t)2 * m * pb + pl;
   const double* Hp = H + (size_t)p * (m + 1) * m;
-  for (int i = 0; i < nn; ++i) dd[(size_t)i * B] = Hp[(size_t)i * m + i];
-  for (int i = 0; i + 1 < nn; ++i) ee[(size_t)i * B] = Hp[(size_t)(i + 1) * m + i];
-  const int rc = tridiag_ql_first_row(nn, dd, ee, zz, B);
+  for (int i = 0; i < nn; ++i) dd[(size_t)i * pb] = Hp[(size_t)i * m + i];
+  for (int i = 0; i + 1 < nn; ++i) ee[(size_t)i * pb] = Hp[(size_t)(i + 1) * m + i];
+  const int rc = tridiag_ql_first_row(nn, dd, ee, zz, pb);
   int bad = 0;
-  const double s = gauss_log_sum(nn, dd, zz, B, &bad);
+  const double s = gauss_log_sum(nn, dd, zz, pb, &bad);
   if (rc) flags[p] |= 8;
   if (bad) flags[p] |= 2;
   if (!isfinite(s)) flags[p] |= 1;
@@ -399,31 +527,76 @@ Geom make_geom(int64_t n, int ld, int xbytes) {
   g.xbytes = xbytes;
   g.vec = 16 / xbytes;
   g.ncolv = ld / g.vec;
-  g.G = pow2_at_least(g.ncolv < 1 ? 1 : g.ncolv);
-  if (g.G > 64) g.G = 64;
-  const int rpi = kThreads / g.G;
-  int64_t nb = (n + rpi - 1) / rpi;
+  // lanes per row L (power of two <= 64) and 16-byte chunks per lane C <= 4:
+  // least idle lanes, then C closest to 2
+  int bestL = 64, bestC = 1, bestWaste = 1 << 30, bestPref = 1 << 30;
+  for (int C = 1; C <= kMaxC; ++C) {
+    const int L = pow2_at_least((g.ncolv + C - 1) / C);
+    if (L > 64) continue;
+    const int waste = L * C - g.ncolv;
+    const int pref = C > 2 ? C - 2 : 2 - C;
+    if (waste < bestWaste || (waste == bestWaste && pref < bestPref)) {
+      bestL = L;
+      bestC = C;
+      bestWaste = waste;
+      bestPref = pref;
+    }
+  }
+  g.L = bestL;
+  g.C = bestC;
+  g.lgL = 0;
+  while ((1 << g.lgL) < g.L) ++g.lgL;
+  const int rpi = kThreads / g.L;
+  const int64_t nchunk = (n + rpi - 1) / rpi;
+  int64_t nb = nchunk;
   if (nb > kMaxBlocks) nb = kMaxBlocks;
   if (nb < 1) nb = 1;
   g.nblk = (int)nb;
-  g.rpb = (int)((n + nb - 1) / nb);
+  g.rpb = (int)((n + nb - 1) / nb);  // contiguous partition for the sketch kernels
   return g;
 }
 
 static bool geom_ok(const Geom& g) {
   return g.n > 0 && g.ld > 0 && g.ld % 4 == 0 && (g.xbytes == 8 || g.xbytes == 4) &&
-         g.vec * g.ncolv == g.ld && g.nblk >= 1 && (int64_t)g.nblk * g.rpb >= g.n;
+         g.vec * g.ncolv == g.ld && g.L >= 1 && g.L <= 64 && (1 << g.lgL) == g.L && g.C >= 1 &&
+         g.C <= kMaxC && g.L * g.C >= g.ncolv && g.nblk >= 1 && (int64_t)g.nblk * g.rpb >= g.n;
 }
 
-#define LD_DISPATCH_G(G, ...)                                   \
-  switch (G) {                                                  \
-    case 1: { constexpr int GG = 1; __VA_ARGS__; } break;       \
-    case 2: { constexpr int GG = 2; __VA_ARGS__; } break;       \
-    case 4: { constexpr int GG = 4; __VA_ARGS__; } break;       \
-    case 8: { constexpr int GG = 8; __VA_ARGS__; } break;       \
-    case 16: { constexpr int GG = 16; __VA_ARGS__; } break;     \
-    case 32: { constexpr int GG = 32; __VA_ARGS__; } break;     \
-    default: { constexpr int GG = 64; __VA_ARGS__; } break;     \
+// Resident 256-thread blocks of a kernel on the whole device (cached).
+static int resident_blocks(const void* fn) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(fn);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const int r = std::min(kMaxBlocks, std::max(1, per_cu * cus));
+  cache[fn] = r;
+  return r;
+}
+
+// Grid of a chunk-sweeping kernel: at most one resident wave of blocks, a
+// multiple of 8 from 8 blocks up (see chunk_of).
+static int stream_grid(const Geom& g, const void* fn) {
+  const int rpi = kThreads / g.L;
+  const int64_t nchunk = (g.n + rpi - 1) / rpi;
+  int64_t nb = std::min<int64_t>(nchunk, resident_blocks(fn));
+  if (nb >= 8) nb &= ~int64_t(7);
+  return (int)std::max<int64_t>(1, nb);
+}
+
+#define LD_DISPATCH_C(C, ...)                             \
+  switch (C) {                                            \
+    case 1: { constexpr int CC = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int CC = 2; __VA_ARGS__; } break; \
+    case 3: { constexpr int CC = 3; __VA_ARGS__; } break; \
+    default: { constexpr int CC = 4; __VA_ARGS__; } break; \
   }
 
 hipError_t launch_rademacher(hipStream_t st, uint64_t seed, int64_t n, int pbase, int ncols,
@@ -445,110 +618,259 @@ hipError_t launch_rademacher(hipStream_t st, uint64_t seed, int64_t n, int pbase
 
 template <typename VT, typename XT>
 static hipError_t spmm_typed(hipStream_t st, const Geom& g, const int* rp, const int* ci,
-                             const VT* va, const XT* X, XT* W, const double* xmult, double opscale) {
-  LD_DISPATCH_G(g.G, hipLaunchKernelGGL((k_spmm<VT, XT, GG>), dim3(g.nblk), dim3(kThreads), 0, st,
-                                        g.n, g.rpb, rp, ci, va, X, W, g.ld, g.ncolv, xmult,
-                                        opscale));
+                             const VT* va, const XT* X, XT* W, const double* xmult, double opscale,
+                             const VecSet& vs, int nf, int voff, double* part, int* nblk_out) {
+  if (nf > 0) {
+    LD_DISPATCH_C(g.C, {
+      auto fn = k_spmm<VT, XT, CC, true>;
+      const int nb = stream_grid(g, (const void*)fn);
+      *nblk_out = nb;
+      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, rp, ci, va, X, W, g.ld,
+                         g.ncolv, xmult, opscale, vs, nf, voff, part);
+    });
+  } else {
+    LD_DISPATCH_C(g.C, {
+      auto fn = k_spmm<VT, XT, CC, false>;
+      const int nb = stream_grid(g, (const void*)fn);
+      *nblk_out = nb;
+      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, rp, ci, va, X, W, g.ld,
+                         g.ncolv, xmult, opscale, vs, nf, voff, part);
+    });
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* ci, const void* va,
-                       int vt, const void* X, void* W, const double* xmult, double opscale) {
-  if (!geom_ok(g) || !rp || !ci || !va || !X || !W || X == W) return hipErrorInvalidValue;
+                       int vt, const void* X, void* W, const double* xmult, double opscale,
+                       const VecSet* fused, int nf, int voff, double* part, int* nblk_out) {
+  int dummy = 0;
+  if (!nblk_out) nblk_out = &dummy;
+  if (!geom_ok(g) || !rp || !ci || !va || !X || !W || X == W || nf < 0 || nf > 2 ||
+      (nf > 0 && (!fused || !part || voff < 0)))
+    return hipErrorInvalidValue;
+  VecSet vs{};
+  if (nf > 0) {
+    vs = *fused;
+    for (int v = 0; v < nf; ++v)
+      if (!vs.x[v] || vs.x[v] == W) return hipErrorInvalidValue;
+    if (vs.x[nf - 1] != X) return hipErrorInvalidValue;  // newest vector = the input
+  }
   if (g.xbytes == 8) {
+    const double* x = static_cast<const double*>(X);
+    double* w = static_cast<double*>(W);
     if (vt == VT_F64)
-      return spmm_typed<double, double>(st, g, rp, ci, static_cast<const double*>(va),
-                                        static_cast<const double*>(X), static_cast<double*>(W),
-                                        xmult, opscale);
+      return spmm_typed<double, double>(st, g, rp, ci, static_cast<const double*>(va), x, w, xmult,
+                                        opscale, vs, nf, voff, part, nblk_out);
     if (vt == VT_F32)
-      return spmm_typed<float, double>(st, g, rp, ci, static_cast<const float*>(va),
-                                       static_cast<const double*>(X), static_cast<double*>(W),
-                                       xmult, opscale);
+      return spmm_typed<float, double>(st, g, rp, ci, static_cast<const float*>(va), x, w, xmult,
+                                       opscale, vs, nf, voff, part, nblk_out);
     if (vt == VT_BF16)
-      return spmm_typed<uint16_t, double>(st, g, rp, ci, static_cast<const uint16_t*>(va),
-                                          static_cast<const double*>(X), static_cast<double*>(W),
-                                          xmult, opscale);
+      return spmm_typed<uint16_t, double>(st, g, rp, ci, static_cast<const uint16_t*>(va), x, w,
+                                          xmult, opscale, vs, nf, voff, part, nblk_out);
   } else {
+    const float* x = static_cast<const float*>(X);
+    float* w = static_cast<float*>(W);
     if (vt == VT_F32)
-      return spmm_typed<float, float>(st, g, rp, ci, static_cast<const float*>(va),
-                                      static_cast<const float*>(X), static_cast<float*>(W), xmult,
-                                      opscale);
+      return spmm_typed<float, float>(st, g, rp, ci, static_cast<const float*>(va), x, w, xmult,
+                                      opscale, vs, nf, voff, part, nblk_out);
     if (vt == VT_BF16)
-      return spmm_typed<uint16_t, float>(st, g, rp, ci, static_cast<const uint16_t*>(va),
-                                         static_cast<const float*>(X), static_cast<float*>(W),
-                                         xmult, opscale);
+      return spmm_typed<uint16_t, float>(st, g, rp, ci, static_cast<const uint16_t*>(va), x, w,
+                                         xmult, opscale, vs, nf, voff, part, nblk_out);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSet& vs, int nv,
-                       int voff, int nvtot, double* part) {
-  if (!geom_ok(g) || !W || !part || nv < 1 || nv > kMaxNv || voff < 0 || voff + nv > nvtot)
+                       int voff, double* part, int* nblk_out) {
+  int dummy = 0;
+  if (!nblk_out) nblk_out = &dummy;
+  if (!geom_ok(g) || !W || !part || nv < 1 || nv > kDotsPerLaunch || voff < 0)
     return hipErrorInvalidValue;
   for (int v = 0; v < nv; ++v)
     if (!vs.x[v]) return hipErrorInvalidValue;
   if (g.xbytes == 8) {
-    LD_DISPATCH_G(g.G, hipLaunchKernelGGL((k_dots<double, GG>), dim3(g.nblk), dim3(kThreads), 0, st,
-                                          g.n, g.rpb, static_cast<const double*>(W), g.ld, g.ncolv,
-                                          vs, nv, voff, nvtot, part));
+    LD_DISPATCH_C(g.C, {
+      auto fn = k_dots<double, CC>;
+      const int nb = stream_grid(g, (const void*)fn);
+      *nblk_out = nb;
+      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL,
+                         static_cast<const double*>(W), g.ld, g.ncolv, vs, nv, voff, part);
+    });
   } else {
-    LD_DISPATCH_G(g.G, hipLaunchKernelGGL((k_dots<float, GG>), dim3(g.nblk), dim3(kThreads), 0, st,
-                                          g.n, g.rpb, static_cast<const float*>(W), g.ld, g.ncolv,
-                                          vs, nv, voff, nvtot, part));
+    LD_DISPATCH_C(g.C, {
+      auto fn = k_dots<float, CC>;
+      const int nb = stream_grid(g, (const void*)fn);
+      *nblk_out = nb;
+      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL,
+                         static_cast<const float*>(W), g.ld, g.ncolv, vs, nv, voff, part);
+    });
   }
   return hipGetLastError();
 }
 
 hipError_t launch_update(hipStream_t st, const Geom& g, void* W, const VecSet& vs, int nv,
                          const double* d, int voff, int want_norm, const void* v1,
-                         const double* v1mult, double* part) {
-  if (!geom_ok(g) || !W || !d || nv < 0 || nv > kMaxNv || (want_norm && !part) ||
+                         const double* v1mult, double* part, int* nblk_out) {
+  int dummy = 0;
+  if (!nblk_out) nblk_out = &dummy;
+  if (!geom_ok(g) || !W || !d || nv < 0 || nv > 4 || (want_norm && !part) ||
       (v1 && !v1mult))
     return hipErrorInvalidValue;
   for (int v = 0; v < nv; ++v)
-    if (!vs.x[v]) return hipErrorInvalidValue;
+    if (!vs.x[v] || vs.x[v] == W) return hipErrorInvalidValue;
   if (g.xbytes == 8) {
-    LD_DISPATCH_G(g.G, hipLaunchKernelGGL((k_update<double, GG>), dim3(g.nblk), dim3(kThreads), 0,
-                                          st, g.n, g.rpb, static_cast<double*>(W), g.ld, g.ncolv,
-                                          vs, nv, d, voff, want_norm,
-                                          static_cast<const double*>(v1), v1mult, part));
+    double* w = static_cast<double*>(W);
+    const double* x1 = static_cast<const double*>(v1);
+    if (nv <= 1) {
+      if (v1) {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<double, CC, 1, true>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      } else {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<double, CC, 1, false>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      }
+    } else if (nv == 2) {
+      if (v1) {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<double, CC, 2, true>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      } else {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<double, CC, 2, false>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      }
+    } else {
+      if (v1) {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<double, CC, 4, true>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      } else {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<double, CC, 4, false>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      }
+    }
   } else {
-    LD_DISPATCH_G(g.G, hipLaunchKernelGGL((k_update<float, GG>), dim3(g.nblk), dim3(kThreads), 0,
-                                          st, g.n, g.rpb, static_cast<float*>(W), g.ld, g.ncolv, vs,
-                                          nv, d, voff, want_norm, static_cast<const float*>(v1),
-                                          v1mult, part));
+    float* w = static_cast<float*>(W);
+    const float* x1 = static_cast<const float*>(v1);
+    if (nv <= 1) {
+      if (v1) {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<float, CC, 1, true>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      } else {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<float, CC, 1, false>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      }
+    } else if (nv == 2) {
+      if (v1) {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<float, CC, 2, true>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      } else {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<float, CC, 2, false>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      }
+    } else {
+      if (v1) {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<float, CC, 4, true>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      } else {
+        LD_DISPATCH_C(g.C, {
+          auto fn = k_update<float, CC, 4, false>;
+          const int nb = stream_grid(g, (const void*)fn);
+          *nblk_out = nb;
+          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
+                             nv, d, voff, want_norm, x1, v1mult, part);
+        });
+      }
+    }
   }
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(hipStream_t st, const double* part, int nblk, int width, double* out) {
   if (!part || !out || nblk < 1 || width < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce, dim3((width + 63) / 64), dim3(kThreads), 0, st, part, nblk, width,
-                     out);
+  hipLaunchKernelGGL(k_reduce, dim3((width + 3) / 4), dim3(kThreads), 0, st, part, nblk, width, out);
   return hipGetLastError();
 }
 
-hipError_t launch_start_finish(hipStream_t st, int B, int ld, const double* nsum, double* norm2,
-                               double* mult0, int* active, int* meff, double* g, int gstride) {
-  if (B < 1 || ld < B) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_start_finish, dim3((ld + 255) / 256), dim3(256), 0, st, B, ld, nsum, norm2,
-                     mult0, active, meff, g, gstride);
+hipError_t launch_start_finish(hipStream_t st, int B, int ld, const double* part, int nblk,
+                               double* norm2, double* mult0, int* active, int* meff, double* g,
+                               int gstride) {
+  if (B < 1 || ld < B || !part || nblk < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_start_finish, dim3((ld + 3) / 4), dim3(kThreads), 0, st, B, ld, part, nblk,
+                     norm2, mult0, active, meff, g, gstride);
   return hipGetLastError();
 }
 
 hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, const double* d, int j0,
-                              int nv, const double* ns, double tol, double* H, int* meff,
-                              int* active, double* mult_next, double* g, int* flags) {
-  if (B < 1 || ld < B || t < 0 || t >= m || j0 < 0 || j0 + nv != t + 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_step_finish, dim3((ld + 255) / 256), dim3(256), 0, st, B, ld, t, m, d, j0,
-                     nv, ns, tol, H, meff, active, mult_next, g, flags);
+                              int nv, const double* part, int nblk, double tol, double* H,
+                              int* meff, int* active, double* mult_next, double* g, int* flags) {
+  if (B < 1 || ld < B || t < 0 || t >= m || j0 < 0 || j0 + nv != t + 1 || !part || nblk < 1)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_step_finish, dim3((ld + 3) / 4), dim3(kThreads), 0, st, B, ld, t, m, d, j0,
+                     nv, part, nblk, tol, H, meff, active, mult_next, g, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_gauss_log(hipStream_t st, int B, int m, const double* H, const int* meff,
-                            double* work, double* K, int* flags) {
-  if (B < 1 || m < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gauss_log, dim3((B + 63) / 64), dim3(64), 0, st, B, m, H, meff, work, K,
+                            double* K, int* flags) {
+  if (B < 1 || m < 1 || m > 1024) return hipErrorInvalidValue;
+  // one probe per wave: the implicit QL sweeps of different probes converge
+  // differently, and lanes of one wave would serialise on each other's paths
+  int pb = 1;
+  const size_t lds = (size_t)3 * m * pb * sizeof(double);
+  hipLaunchKernelGGL(k_gauss_log, dim3((B + pb - 1) / pb), dim3(64), lds, st, B, m, pb, H, meff, K,
                      flags);
   return hipGetLastError();
 }

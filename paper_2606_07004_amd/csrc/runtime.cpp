@@ -59,6 +59,109 @@ hipError_t DeviceBuffer::ensure(size_t want) {
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// Profiler
+// ---------------------------------------------------------------------------
+static int fam_index(uint32_t fam) {
+  int i = 0;
+  while (fam > 1u) {
+    fam >>= 1;
+    ++i;
+  }
+  return i;
+}
+
+Profiler::~Profiler() {
+  for (auto& p : pending_) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+}
+
+void Profiler::enable(uint32_t mask) {
+  std::lock_guard<std::mutex> lk(mu_);
+  mask_ = mask;
+  for (int i = 0; i < 8; ++i) {
+    count_[i] = 0;
+    ms_[i] = 0.0;
+    bytes_[i] = 0.0;
+  }
+}
+
+hipEvent_t Profiler::get_event() {
+  if (!pool_.empty()) {
+    hipEvent_t e = pool_.back();
+    pool_.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+hipError_t Profiler::begin(uint32_t fam, hipStream_t st, hipEvent_t* a) {
+  *a = nullptr;
+  std::lock_guard<std::mutex> lk(mu_);
+  if (!(mask_ & fam)) return hipSuccess;
+  *a = get_event();
+  if (!*a) return hipErrorOutOfMemory;
+  return hipEventRecord(*a, st);
+}
+
+hipError_t Profiler::end(uint32_t fam, hipStream_t st, hipEvent_t a, double bytes) {
+  if (!a) return hipSuccess;
+  std::lock_guard<std::mutex> lk(mu_);
+  hipEvent_t b = get_event();
+  if (!b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(b, st);
+  pending_.push_back({fam_index(fam), a, b, bytes});
+  return e;
+}
+
+hipError_t Profiler::harvest() {
+  std::lock_guard<std::mutex> lk(mu_);
+  hipError_t err = hipSuccess;
+  for (auto& p : pending_) {
+    hipError_t e = hipEventSynchronize(p.b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+    if (e == hipSuccess) {
+      count_[p.fam_bit] += 1;
+      ms_[p.fam_bit] += ms;
+      bytes_[p.fam_bit] += p.bytes;
+    } else {
+      err = e;
+    }
+    pool_.push_back(p.a);
+    pool_.push_back(p.b);
+  }
+  pending_.clear();
+  return err;
+}
+
+void Profiler::query(uint32_t fam, int64_t* n, double* ms, double* bytes) {
+  std::lock_guard<std::mutex> lk(mu_);
+  *n = 0;
+  *ms = 0.0;
+  *bytes = 0.0;
+  for (int i = 0; i < 8; ++i)
+    if (fam & (1u << i)) {
+      *n += count_[i];
+      *ms += ms_[i];
+      *bytes += bytes_[i];
+    }
+}
+
+// Launch with optional event bracketing; `bytes` is the algorithmic traffic.
+#define LD_LAUNCH(fam, bytes, expr)                                      \
+  do {                                                                   \
+    hipEvent_t pa_ = nullptr;                                            \
+    if (prof_) LD_HIP(prof_->begin((fam), st, &pa_));                    \
+    LD_HIP(expr);                                                        \
+    if (prof_) LD_HIP(prof_->end((fam), st, pa_, (double)(bytes)));      \
+  } while (0)
+
 static inline int round4(int x) { return (x + 3) & ~3; }
 static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -158,8 +261,9 @@ size_t Run::layout(char* base) {
   S_ = static_cast<double*>(take(n * std::max(lds_, ldr_) * 8));
   G_ = S_;
   Y_ = s_ > 0 ? static_cast<double*>(take(n * lds_ * 8)) : nullptr;
-  size_t pe = (size_t)gB_.nblk * std::max(nvmax, 2) * ldB_;
-  pe = std::max(pe, (size_t)g1_.nblk * std::max(nvmax, 2) * ld1_);
+  // streaming kernels: fused product dots (2 rows of ld) and further dots
+  // launches (up to 4 rows of ld) in separate regions, kMaxBlocks each
+  size_t pe = (size_t)kMaxBlocks * (2 + 4) * std::max(ldB_, ld1_);
   if (s_ > 0) pe = std::max(pe, (size_t)gS_.nblk * s_ * std::max(s_, r_));
   part_elems_ = pe;
   part_ = static_cast<double*>(take(pe * 8));
@@ -197,16 +301,25 @@ ld_status Run::bind(void* base, size_t bytes) {
   return LD_OK;
 }
 
+// Algorithmic bytes of one CSR x block product: the matrix once (values,
+// column indices, row pointers), the input block once, the output block once.
+double Run::spmm_bytes(int ld, int xbytes) const {
+  const int vb = mixed_ ? (a_->vt_lo == VT_BF16 ? 2 : 4) : 8;
+  return (double)a_->nnz * (vb + 4) + 4.0 * (n_ + 1) + 2.0 * (double)n_ * ld * xbytes;
+}
+
 // CholQR2: Y <- Y R1^{-1}, then again, so that Y = A R with A orthonormal and
 // R = R2 R1 upper triangular with a positive diagonal (the QR convention of
 // the oracle).  dflag_[0] is set when the Gram matrix is not numerically
 // positive definite.
 ld_status Run::sketch_qr(hipStream_t st, double* Y) {
   for (int pass = 0; pass < 2; ++pass) {
-    LD_HIP(launch_gemm_tn(st, gS_, Y, lds_, s_, Y, lds_, s_, part_));
-    LD_HIP(launch_reduce(st, part_, gS_.nblk, s_ * s_, gram_));
-    LD_HIP(launch_chol_inv(st, s_, gram_, rfac_, rinv_, dflag_ + pass));
-    LD_HIP(launch_trsm_rows(st, n_, Y, lds_, s_, rinv_));
+    LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * s_ * 8,
+              launch_gemm_tn(st, gS_, Y, lds_, s_, Y, lds_, s_, part_));
+    LD_LAUNCH(LD_PROF_REDUCE, (double)gS_.nblk * s_ * s_ * 8,
+              launch_reduce(st, part_, gS_.nblk, s_ * s_, gram_));
+    LD_LAUNCH(LD_PROF_SKETCH, 0, launch_chol_inv(st, s_, gram_, rfac_, rinv_, dflag_ + pass));
+    LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * s_ * 16, launch_trsm_rows(st, n_, Y, lds_, s_, rinv_));
   }
   return LD_OK;
 }
@@ -214,14 +327,19 @@ ld_status Run::sketch_qr(hipStream_t st, double* Y) {
 // X0 = [A | G - A (A^T G)] in Krylov precision, its column norms, and the
 // per-run start state.
 ld_status Run::start_block(hipStream_t st, const double* A, int s_cols) {
-  LD_HIP(launch_rademacher(st, p_.seed, n_, s_, ldr_, r_, G_, 8, ldr_, 0));
+  LD_LAUNCH(LD_PROF_PROBES, (double)n_ * ldr_ * 8,
+            launch_rademacher(st, p_.seed, n_, s_, ldr_, r_, G_, 8, ldr_, 0));
   if (s_cols > 0) {
-    LD_HIP(launch_gemm_tn(st, gS_, A, lds_, s_cols, G_, ldr_, r_, part_));
-    LD_HIP(launch_reduce(st, part_, gS_.nblk, s_cols * r_, pmat_));
+    LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * (s_cols + r_) * 8,
+              launch_gemm_tn(st, gS_, A, lds_, s_cols, G_, ldr_, r_, part_));
+    LD_LAUNCH(LD_PROF_REDUCE, (double)gS_.nblk * s_cols * r_ * 8,
+              launch_reduce(st, part_, gS_.nblk, s_cols * r_, pmat_));
   }
-  LD_HIP(launch_project(st, gB_, A, lds_, s_cols, G_, ldr_, r_, pmat_, slots_, part_));
-  LD_HIP(launch_reduce(st, part_, gB_.nblk, ldB_, nsr_));
-  LD_HIP(launch_start_finish(st, B_, ldB_, nsr_, norm2_, mult_, active_, meff_, gq_, m_ + 1));
+  LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * (s_cols + r_) * 8 + (double)n_ * ldB_ * xb_,
+            launch_project(st, gB_, A, lds_, s_cols, G_, ldr_, r_, pmat_, slots_, part_));
+  LD_LAUNCH(LD_PROF_SMALL, (double)gB_.nblk * ldB_ * 8,
+            launch_start_finish(st, B_, ldB_, part_, gB_.nblk, norm2_, mult_, active_, meff_, gq_,
+                                m_ + 1));
   return LD_OK;
 }
 
@@ -267,9 +385,11 @@ ld_status Run::run_prologue(hipStream_t st) {
   if (p_.method == LD_METHOD_OSLQ) {
     if (s_ > 0) {
       // Y = J S, J = Q / alpha (Alg 3: sketch from J S, not from f(J) S)
-      LD_HIP(launch_rademacher(st, p_.seed, n_, 0, lds_, s_, S_, 8, lds_, 0));
-      LD_HIP(launch_spmm(st, gS_, a_->rp, a_->ci, vals_sketch, vt_sketch, S_, Y_, nullptr,
-                         opscale_));
+      LD_LAUNCH(LD_PROF_PROBES, (double)n_ * lds_ * 8,
+                launch_rademacher(st, p_.seed, n_, 0, lds_, s_, S_, 8, lds_, 0));
+      LD_LAUNCH(LD_PROF_SPMM, spmm_bytes(lds_, 8),
+                launch_spmm(st, gS_, a_->rp, a_->ci, vals_sketch, vt_sketch, S_, Y_, nullptr,
+                            opscale_, nullptr, 0, 0, nullptr, nullptr));
       ld_status rc = sketch_qr(st, Y_);
       if (rc != LD_OK) return rc;
     }
@@ -294,41 +414,61 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
   auto mult_ptr = [&](int j) -> double* { return kmult_ + (size_t)slot_of(j) * kld_; };
   const void* vals = mixed_ ? a_->vlo : a_->v64;
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
+  const double vec_bytes = (double)n_ * kld_ * xb_;
   void* W = slot_ptr(t + 1);
-  LD_HIP(launch_spmm(st, kg_, a_->rp, a_->ci, vals, vt, slot_ptr(t), W, mult_ptr(t), opscale_));
   const int j0 = std::max(0, t - k_ + 1);
   const int nv = t - j0 + 1;
-  for (int c0 = 0; c0 < nv; c0 += kMaxNv) {
+  // the two newest window vectors (v_t-1, v_t) are dotted in the product's
+  // epilogue; window index v corresponds to Krylov index j0 + v.  Each
+  // launch writes its partial sums to its own region of part_ with its own
+  // grid size, and is reduced into its rows of dwin_.
+  const int nf = std::min(2, nv);
+  VecSet vf{};
+  for (int v = 0; v < nf; ++v) {
+    vf.x[v] = slot_ptr(j0 + nv - nf + v);
+    vf.mult[v] = mult_ptr(j0 + nv - nf + v);
+  }
+  int nb = 0;
+  LD_LAUNCH(LD_PROF_SPMM, spmm_bytes(kld_, xb_) + (nf - 1) * vec_bytes,
+            launch_spmm(st, kg_, a_->rp, a_->ci, vals, vt, slot_ptr(t), W, mult_ptr(t), opscale_,
+                        &vf, nf, 0, part_, &nb));
+  LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nf * kld_ * 8,
+            launch_reduce(st, part_, nb, nf * kld_, dwin_ + (size_t)(nv - nf) * kld_));
+  for (int c0 = 0; c0 < nv - nf; c0 += 4) {
     VecSet vs{};
-    const int nc = std::min(kMaxNv, nv - c0);
+    const int nc = std::min(4, nv - nf - c0);
     for (int v = 0; v < nc; ++v) {
       vs.x[v] = slot_ptr(j0 + c0 + v);
       vs.mult[v] = mult_ptr(j0 + c0 + v);
     }
-    LD_HIP(launch_dots(st, kg_, W, vs, nc, c0, nv, part_));
+    double* pp = part_ + (size_t)2 * kld_ * kMaxBlocks;
+    LD_LAUNCH(LD_PROF_DOTS, (double)(nc + 1) * vec_bytes,
+              launch_dots(st, kg_, W, vs, nc, 0, pp, &nb));
+    LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nc * kld_ * 8,
+              launch_reduce(st, pp, nb, nc * kld_, dwin_ + (size_t)c0 * kld_));
   }
-  LD_HIP(launch_reduce(st, part_, kg_.nblk, nv * kld_, dwin_));
-  for (int c0 = 0; c0 < nv; c0 += kMaxNv) {
+  for (int c0 = 0; c0 < nv; c0 += 4) {
     VecSet vs{};
-    const int nc = std::min(kMaxNv, nv - c0);
+    const int nc = std::min(4, nv - c0);
     for (int v = 0; v < nc; ++v) {
       vs.x[v] = slot_ptr(j0 + c0 + v);
       vs.mult[v] = mult_ptr(j0 + c0 + v);
     }
     const bool last = c0 + nc >= nv;
-    LD_HIP(launch_update(st, kg_, W, vs, nc, dwin_, c0, last ? 1 : 0,
-                         (last && kpin_) ? slot_ptr(0) : nullptr,
-                         (last && kpin_) ? mult_ptr(0) : nullptr, part_));
+    LD_LAUNCH(LD_PROF_UPDATE, (double)(nc + 2 + ((last && kpin_) ? 1 : 0)) * vec_bytes,
+              launch_update(st, kg_, W, vs, nc, dwin_, c0, last ? 1 : 0,
+                            (last && kpin_) ? slot_ptr(0) : nullptr,
+                            (last && kpin_) ? mult_ptr(0) : nullptr, part_, &nb));
   }
-  LD_HIP(launch_reduce(st, part_, kg_.nblk, 2 * kld_, nsr_));
-  LD_HIP(launch_step_finish(st, kB_, kld_, t, m_, dwin_, j0, nv, nsr_, tol_, H_, meff_, active_,
-                            mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_));
+  LD_LAUNCH(LD_PROF_SMALL, (double)nb * 2 * kld_ * 8,
+            launch_step_finish(st, kB_, kld_, t, m_, dwin_, j0, nv, part_, nb, tol_, H_,
+                               meff_, active_, mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_));
   return LD_OK;
 }
 
 ld_status Run::run_epilogue(hipStream_t st) {
   if (p_.method == LD_METHOD_OSLQ) {
-    LD_HIP(launch_gauss_log(st, B_, m_, H_, meff_, work_, K_, flags_));
+    LD_LAUNCH(LD_PROF_SMALL, 0, launch_gauss_log(st, B_, m_, H_, meff_, K_, flags_));
   } else {
     return set_error(LD_E_INVALID_ARG, "OSA-IOP is not available in this build");
   }
@@ -373,6 +513,7 @@ ld_status Run::advance(hipStream_t st, int budget, bool* done) {
 
 ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail) {
   LD_HIP(hipStreamSynchronize(st));
+  if (prof_) LD_HIP(prof_->harvest());
   std::vector<double> K(B_), nrm(B_);
   std::vector<int> meff(B_), flags(B_);
   int dflag[2] = {0, 0};
@@ -664,6 +805,7 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
   LD_HIP_API(hipSetDevice(ctx->device));
   Run run(a, *p);
   run.set_submit_time(t0);
+  run.set_profiler(&ctx->prof);
   ld_status rc = run.validate();
   if (rc != LD_OK) return rc;
   const size_t need = run.device_bytes();
@@ -701,6 +843,23 @@ ld_status ld_estimate(ld_matrix* a, int32_t n_probes, int32_t sketch_rank, int32
   p.seed = seed;
   p.tol = 0.0;
   return ld_estimate_detail(a, &p, out, nullptr);
+}
+
+ld_status ld_profile_enable(ld_ctx* ctx, uint32_t family_mask) {
+  if (!ctx) return set_error(LD_E_INVALID_ARG, "null context");
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  LD_HIP_API(hipSetDevice(ctx->device));
+  LD_HIP_API(ctx->prof.harvest());
+  ctx->prof.enable(family_mask & LD_PROF_ALL);
+  return LD_OK;
+}
+
+ld_status ld_profile_query(ld_ctx* ctx, uint32_t family, int64_t* launches, double* total_ms,
+                           double* total_bytes) {
+  if (!ctx || !launches || !total_ms || !total_bytes)
+    return set_error(LD_E_INVALID_ARG, "null argument");
+  ctx->prof.query(family, launches, total_ms, total_bytes);
+  return LD_OK;
 }
 
 ld_status ld_debug_rademacher(ld_ctx* ctx, uint64_t seed, int64_t n, int32_t col_begin,

@@ -34,6 +34,33 @@ struct DeviceBuffer {
 
 class Server;
 
+// Event-bracketed launch timing per kernel family (see ld_profile_enable).
+class Profiler {
+ public:
+  ~Profiler();
+  void enable(uint32_t mask);
+  bool on(uint32_t fam) const { return (mask_ & fam) != 0; }
+  hipError_t begin(uint32_t fam, hipStream_t st, hipEvent_t* a);
+  hipError_t end(uint32_t fam, hipStream_t st, hipEvent_t a, double bytes);
+  hipError_t harvest();  // waits for pending events and accumulates
+  void query(uint32_t fam, int64_t* n, double* ms, double* bytes);
+
+ private:
+  hipEvent_t get_event();
+  struct Pending {
+    int fam_bit;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::mutex mu_;
+  uint32_t mask_ = 0;
+  std::vector<Pending> pending_;
+  std::vector<hipEvent_t> pool_;
+  int64_t count_[8] = {};
+  double ms_[8] = {};
+  double bytes_[8] = {};
+};
+
 }  // namespace ld
 
 struct ld_ctx {
@@ -48,6 +75,7 @@ struct ld_ctx {
   std::atomic<int> n_matrices{0};
   std::unique_ptr<ld::Server> server;
   std::mutex server_mu;
+  ld::Profiler prof;
 };
 
 struct ld_matrix {
@@ -98,6 +126,7 @@ class Run {
   ld_status start_block(hipStream_t st, const double* A, int s_cols);
   ld_status begin_krylov(int phase);
   size_t layout(char* base);
+  double spmm_bytes(int ld, int xbytes) const;
 
   ld_matrix* a_;
   ld_params p_;
@@ -149,7 +178,9 @@ class Run {
   int nslots_ = 0;
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
   double t_submit_ = 0;
+  Profiler* prof_ = nullptr;
  public:
+  void set_profiler(Profiler* p) { prof_ = p; }
   double submit_time() const { return t_submit_; }
   void set_submit_time(double t) { t_submit_ = t; }
   int64_t n() const { return n_; }

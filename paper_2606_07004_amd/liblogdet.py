@@ -94,6 +94,9 @@ _SIGNATURES = [
     ("ld_submit", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(C.c_uint64)]),
     ("ld_poll", C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(ld_result)]),
     ("ld_wait", C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(ld_result)]),
+    ("ld_profile_enable", C.c_int32, [C.c_void_p, C.c_uint32]),
+    ("ld_profile_query", C.c_int32, [C.c_void_p, C.c_uint32, C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("ld_debug_rademacher", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, C.c_int32,
                                         _DP]),
 ]
@@ -231,6 +234,23 @@ def ld_wait(ctx, ticket: int) -> ld_result:
     res = ld_result()
     _check(lib().ld_wait(ctx, ticket, C.byref(res)))
     return res
+
+
+LD_PROF_SPMM, LD_PROF_DOTS, LD_PROF_UPDATE, LD_PROF_REDUCE = 1, 2, 4, 8
+LD_PROF_SMALL, LD_PROF_SKETCH, LD_PROF_PROBES, LD_PROF_ALL = 16, 32, 64, 127
+PROF_FAMILIES = {"spmm": 1, "dots": 2, "update": 4, "reduce": 8, "small": 16, "sketch": 32,
+                 "probes": 64}
+
+
+def ld_profile_enable(ctx, family_mask: int) -> None:
+    _check(lib().ld_profile_enable(ctx, family_mask))
+
+
+def ld_profile_query(ctx, family: int):
+    """(launches, total_ms, total_algorithmic_bytes) summed over `family`."""
+    n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+    _check(lib().ld_profile_query(ctx, family, C.byref(n), C.byref(ms), C.byref(by)))
+    return n.value, ms.value, by.value
 
 
 def ld_debug_rademacher(ctx, seed: int, n: int, col_begin: int, col_end: int) -> np.ndarray:
