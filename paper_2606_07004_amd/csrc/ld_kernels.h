@@ -81,6 +81,23 @@ hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, const
 hipError_t launch_gauss_log(hipStream_t st, int B, int m, const double* H, const int* meff,
                             double* K, int* flags);
 
+// OSA-IOP: Gauss-Legendre rule of the Pade step of log(H) e1 (nodes on [0, 1]).
+struct LogRule {
+  double x[10];
+  double w[10];
+};
+// mode 0: ell[p][t] = (log H_p e1)_t; mode 1: K[p] = sum_t g[p][t] (log H_p e1)_t + shift.
+// work: wstride doubles per run (>= 6 m^2 + 4 m).
+hipError_t launch_hess_log(hipStream_t st, int B, int m, const double* H, const int* meff,
+                           double* work, int wstride, int mode, double* ell, const double* g,
+                           double shift, double* K, int* flags);
+hipError_t launch_osa_coef(hipStream_t st, int B, int ld, int m, const double* ell,
+                           const double* mult, const double* norm2, const int* meff, double shift,
+                           double* coef);
+// Y[row][col] = sum_{t < nt} coef[t][col] X_t[row][col], X_t = slots + t * slot_elems.
+hipError_t launch_combine(hipStream_t st, int64_t n, int ld, int nt, const void* slots, int xbytes,
+                          size_t slot_elems, const double* coef, double* Y, int ldy);
+
 // Dense pieces of the Hutch++ sketch (FP64).
 // part[i][j][b] = sum_{rows of b} Xa[row][i] * Xb[row][j], i < ca, j < cb
 hipError_t launch_gemm_tn(hipStream_t st, const Geom& g, const double* Xa, int lda, int ca,

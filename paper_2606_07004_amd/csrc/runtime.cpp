@@ -273,7 +273,10 @@ size_t Run::layout(char* base) {
   K_ = static_cast<double*>(take((size_t)ldB_ * 8));
   H_ = static_cast<double*>(take((size_t)ldB_ * (m_ + 1) * m_ * 8));
   gq_ = static_cast<double*>(take((size_t)ldB_ * (m_ + 1) * 8));
-  work_ = static_cast<double*>(take((size_t)ldB_ * (size_t)std::max(3 * m_, 5 * m_ * m_ + 4 * m_) * 8));
+  wstride_ = 6 * m_ * m_ + 4 * m_;
+  work_ = (p_.method == LD_METHOD_OSA_IOP)
+              ? static_cast<double*>(take((size_t)ldB_ * (size_t)wstride_ * 8))
+              : nullptr;
   if (s_ > 0) {
     gram_ = static_cast<double*>(take((size_t)s_ * s_ * 8));
     rfac_ = static_cast<double*>(take((size_t)s_ * s_ * 8));
@@ -398,7 +401,49 @@ ld_status Run::run_prologue(hipStream_t st) {
     begin_krylov(0);
     return LD_OK;
   }
-  return set_error(LD_E_INVALID_ARG, "OSA-IOP is not available in this build");
+  // OSA-IOP: the sketch-image runs start from S itself (phase 0, basis kept)
+  if (s_ > 0) {
+    LD_LAUNCH(LD_PROF_PROBES, (double)n_ * ld1_ * xb_,
+              launch_rademacher(st, p_.seed, n_, 0, ld1_, s_, slots_, xb_, ld1_, 0));
+    VecSet vs{};
+    vs.x[0] = slots_;
+    int nb = 0;
+    LD_LAUNCH(LD_PROF_DOTS, (double)n_ * ld1_ * xb_,
+              launch_dots(st, g1_, slots_, vs, 1, 0, part_, &nb));
+    LD_LAUNCH(LD_PROF_SMALL, (double)nb * ld1_ * 8,
+              launch_start_finish(st, s_, ld1_, part_, nb, norm2_, mult_, active_, meff_, nullptr,
+                                  0));
+    LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldB_ * (m_ + 1) * m_ * 8, st));
+    begin_krylov(0);
+    return LD_OK;
+  }
+  ld_status rc = start_block(st, nullptr, 0);
+  if (rc != LD_OK) return rc;
+  LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldB_ * (m_ + 1) * m_ * 8, st));
+  begin_krylov(1);
+  return LD_OK;
+}
+
+// OSA-IOP between the two Krylov phases: y_i = ||s_i|| V log(H) e1 +
+// (log gamma - c) s_i for every sketch column (Alg 1 on each column of S),
+// then A = orth(Y) and the start block [A | (I - A A^T) G] of the estimate
+// runs (Alg 2).
+ld_status Run::osa_sketch_combine(hipStream_t st) {
+  const double shift = std::log(scale_) - c_;
+  LD_LAUNCH(LD_PROF_SMALL, 0,
+            launch_hess_log(st, s_, m_, H_, meff_, work_, wstride_, 0, ell_, nullptr, 0.0,
+                            nullptr, flags_));
+  LD_LAUNCH(LD_PROF_SMALL, 0,
+            launch_osa_coef(st, s_, ld1_, m_, ell_, mult_, norm2_, meff_, shift, coefs_));
+  LD_LAUNCH(LD_PROF_SKETCH, (double)m_ * n_ * ld1_ * xb_ + (double)n_ * lds_ * 8,
+            launch_combine(st, n_, ld1_, m_, slots_, xb_, (size_t)n_ * ld1_, coefs_, Y_, lds_));
+  ld_status rc = sketch_qr(st, Y_);
+  if (rc != LD_OK) return rc;
+  rc = start_block(st, Y_, s_);
+  if (rc != LD_OK) return rc;
+  LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldB_ * (m_ + 1) * m_ * 8, st));
+  begin_krylov(1);
+  return LD_OK;
 }
 
 ld_status Run::run_krylov_step(hipStream_t st, int t) {
@@ -470,7 +515,10 @@ ld_status Run::run_epilogue(hipStream_t st) {
   if (p_.method == LD_METHOD_OSLQ) {
     LD_LAUNCH(LD_PROF_SMALL, 0, launch_gauss_log(st, B_, m_, H_, meff_, K_, flags_));
   } else {
-    return set_error(LD_E_INVALID_ARG, "OSA-IOP is not available in this build");
+    // x^T L_c x / ||x||^2 = sum_t g_t (log H e1)_t + log(gamma) - c
+    LD_LAUNCH(LD_PROF_SMALL, 0,
+              launch_hess_log(st, B_, m_, H_, meff_, work_, wstride_, 1, nullptr, gq_,
+                              std::log(scale_) - c_, K_, flags_));
   }
   LD_HIP(hipEventRecord(ev1_, st));
   return LD_OK;
@@ -492,7 +540,15 @@ ld_status Run::advance(hipStream_t st, int budget, bool* done) {
         if (rc != LD_OK) return rc;
         ++t_;
         --budget;
-        if (t_ >= m_) stage_ = ST_EPILOGUE;
+        if (t_ >= m_)
+          stage_ = (p_.method == LD_METHOD_OSA_IOP && kphase_ == 0) ? ST_COMBINE : ST_EPILOGUE;
+        break;
+      }
+      case ST_COMBINE: {
+        ld_status rc = osa_sketch_combine(st);
+        if (rc != LD_OK) return rc;
+        stage_ = ST_KRYLOV;
+        --budget;
         break;
       }
       case ST_EPILOGUE: {

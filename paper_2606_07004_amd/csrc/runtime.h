@@ -176,6 +176,7 @@ class Run {
   size_t part_elems_ = 0;
   size_t slot_elems_ = 0;     // elements of one [n][ld] slot
   int nslots_ = 0;
+  int wstride_ = 0;           // OSA-IOP: per-run workspace of the Hessenberg log
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
   double t_submit_ = 0;
   Profiler* prof_ = nullptr;

@@ -1,0 +1,101 @@
+"""Full-size GPU parity against stored oracle results.
+
+The stored values (tests/golden/*.json) were written by
+tests/golden/make_golden.py, which runs only the CPU FP64 oracle on the seeded
+inputs; each file records the input's content digest, checked here before
+comparing.  At these sizes the oracle takes minutes, so the comparison is
+against the stored per-run values: every run's quadrature value, start norm
+and Krylov dimension, then the assembled log-determinant (FP64 <= 1e-6,
+mixed precision <= 1e-4).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+BUILDERS = {
+    "lap3d128_s1e-2_oslq_k2": lambda: W.lap3d(128, 1e-2),
+    "lap3d128_s1e-3_oslq_k2": lambda: W.lap3d(128, 1e-3),
+    "lap3d128_s1e-2_oslq_k8": lambda: W.lap3d(128, 1e-2),
+    "lap3d128_s1e-2_osaiop_k2": lambda: W.lap3d(128, 1e-2),
+    "er1e6_oslq_k4": lambda: W.er_laplacian(1_000_000, 8_000_000, seed=0, shift=0.05),
+    "wendland5e5_oslq_k2": lambda: W.wendland(500_000, 48.0, 1e-2, seed=0),
+}
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2606_07004_amd import liblogdet
+    liblogdet.lib()
+    return liblogdet
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    c = L.Context(0)
+    yield c
+    c.close()
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        return json.load(f)
+
+
+def _run(L, ctx, name, precision, vt):
+    gold = _load(name)
+    print(f"\n[case] fullsize {name} precision={precision} vt={vt}", flush=True)
+    a = BUILDERS[name]()
+    assert W.csr_digest(a) == gold["digest"], "input differs from the one the oracle saw"
+    method = L.LD_METHOD_OSLQ if gold["method"] == "oslq" else L.LD_METHOD_OSA_IOP
+    h = ctx.matrix(a, vt=vt, lo_hint=gold["lo_hint"], hi_hint=gold["hi_hint"])
+    try:
+        p = L.make_params(gold["n_probes"], gold["sketch_rank"], gold["krylov_steps"],
+                          gold["iop_window"], gold["seed"], method=method, precision=precision)
+        res, det = L.ld_estimate_detail(h, p)
+    finally:
+        ctx.release(h)
+    rel = abs(res.logdet - gold["logdet"]) / abs(gold["logdet"])
+    print(f"  gpu {res.logdet!r} oracle {gold['logdet']!r} rel {rel:.3e} "
+          f"device {res.device_ms:.1f} ms", flush=True)
+    return gold, res, det, rel
+
+
+OSLQ_CASES = [n for n in BUILDERS if "oslq" in n]
+ALL_CASES = list(BUILDERS)
+
+
+@pytest.mark.parametrize("name", ALL_CASES)
+def test_fullsize_fp64_elementwise(L, ctx, name):
+    gold, res, det, rel = _run(L, ctx, name, L.LD_PREC_FP64, L.LD_VT_FP64)
+    assert rel <= 1e-6
+    np.testing.assert_array_equal(det["probe_steps"], np.array(gold["probe_steps"]))
+    np.testing.assert_allclose(det["probe_norm2"], gold["probe_norm2"], rtol=1e-10)
+    np.testing.assert_allclose(det["probe_K"], gold["probe_K"], rtol=1e-7, atol=1e-9)
+    assert res.shift_c == pytest.approx(gold["shift_c"], rel=1e-13)
+    assert res.tr_sketch == pytest.approx(gold["tr_sketch"], rel=1e-9, abs=1e-6)
+    assert res.tr_resid == pytest.approx(gold["tr_resid"], rel=1e-8)
+
+
+@pytest.mark.parametrize("name", ALL_CASES)
+def test_fullsize_mixed_within_1e4(L, ctx, name):
+    gold, res, det, rel = _run(L, ctx, name, L.LD_PREC_MIXED, L.LD_VT_FP32)
+    assert rel <= 1e-4
+
+
+def test_fullsize_bf16_values_reported(L, ctx):
+    # BF16 storage rounds the matrix itself (relative 2^-9 per value, about
+    # 2e-3 absolute on entries near 1, against a smallest eigenvalue of 1e-2
+    # from the nugget): the log-determinant of the rounded matrix differs by
+    # a few percent.  This is reported, not gated; the run must stay finite
+    # and SPD.
+    gold, res, det, rel = _run(L, ctx, "wendland5e5_oslq_k2", L.LD_PREC_MIXED, L.LD_VT_BF16)
+    print(f"  bf16-value error vs FP64 oracle: {rel:.3e}")
+    assert np.isfinite(res.logdet) and rel < 0.2
