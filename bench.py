@@ -52,12 +52,19 @@ def parse():
     return ap.parse_args()
 
 
-def golden_for(name):
-    path = os.path.join(ROOT, "tests", "golden", name + ".json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        return json.load(f)
+def golden_for(matrix_name, args):
+    """The stored oracle result (tests/golden/*.json) for this exact matrix,
+    method and parameters, if one was recorded."""
+    import glob
+    for path in glob.glob(os.path.join(ROOT, "tests", "golden", "*.json")):
+        with open(path) as f:
+            g = json.load(f)
+        if (g.get("matrix") == matrix_name and g.get("method") == args.method
+                and g.get("n_probes") == args.probes and g.get("sketch_rank") == args.sketch
+                and g.get("krylov_steps") == args.krylov_steps
+                and g.get("iop_window") == args.window and g.get("seed") == args.seed):
+            return g
+    return None
 
 
 def cpu_baseline(a, args):
@@ -123,10 +130,8 @@ def main():
             exact = W.lap3d_exact_logdet(args.grid, args.shift)
             accuracy["closed_form"] = exact
             accuracy["estimator_rel_err_vs_closed_form"] = abs(rt.logdet - exact) / abs(exact)
-        gname = f"lap3d{args.grid}_s{args.shift:g}_{args.method.replace('_', '')}_k{args.window}"
-        gold = golden_for(gname)
-        if gold and gold["n_probes"] == args.probes and gold["sketch_rank"] == args.sketch \
-                and gold["krylov_steps"] == args.krylov_steps and gold["seed"] == args.seed:
+        gold = golden_for(a.name, args)
+        if gold:
             accuracy["oracle_fp64"] = gold["logdet"]
             accuracy["rel_err_fp64_gpu_vs_oracle"] = abs(r64.logdet - gold["logdet"]) / abs(gold["logdet"])
             accuracy["rel_err_vs_oracle"] = abs(rt.logdet - gold["logdet"]) / abs(gold["logdet"])

@@ -98,7 +98,8 @@ typedef struct {
   double lambda_lo;          /* spectral interval used (Gershgorin or hints)     */
   double lambda_hi;
   double scale;              /* OSLQ: alpha (runs on Q/alpha); OSA-IOP: gamma    */
-  int64_t probe_steps;       /* sum over Krylov runs of the mat-vecs performed  */
+  int64_t probe_steps;       /* sum over Krylov runs of the mat-vecs performed
+                                (OSA-IOP: sketch-image runs included)            */
   int64_t matvecs;           /* all Q x products, sketch included               */
   int32_t min_steps;         /* smallest effective Krylov dimension of a run    */
   int32_t n_breakdowns;      /* runs stopped early by h < tol                    */

@@ -31,8 +31,16 @@ namespace ld {
 // d[i*stride] (i < n): diagonal, overwritten by the eigenvalues.
 // e[i*stride] (i < n-1): subdiagonal; e[(n-1)*stride] is scratch.
 // z[i*stride]: on entry anything, on exit the first eigenvector components.
+// Optional rotation log (rot_c, rot_s, rot_i non-null, capacity rot_cap):
+// every plane rotation applied to the eigenvector columns (i, i+1) is
+// appended in order, so that U y = G_1 (G_2 (... G_N y)) can be replayed;
+// *rot_n receives the count (-1 when the capacity was exceeded).
 // Returns 0 on success, 1 when an eigenvalue needed more than 64 sweeps.
-LD_HD inline int tridiag_ql_first_row(int n, double* d, double* e, double* z, int stride) {
+LD_HD inline int tridiag_ql_first_row(int n, double* d, double* e, double* z, int stride,
+                                      double* rot_c = nullptr, double* rot_s = nullptr,
+                                      int* rot_i = nullptr, int rot_cap = 0,
+                                      int* rot_n = nullptr) {
+  int nrot = 0;
 #define LD_D(i) d[(i) * stride]
 #define LD_E(i) e[(i) * stride]
 #define LD_Z(i) z[(i) * stride]
@@ -46,7 +54,10 @@ LD_HD inline int tridiag_ql_first_row(int n, double* d, double* e, double* z, in
         if (fabs(LD_E(mm)) <= DBL_EPSILON * dd) break;
       }
       if (mm == l) break;  // d_l has converged
-      if (sweep == 64) return 1;
+      if (sweep == 64) {
+        if (rot_n) *rot_n = -1;
+        return 1;
+      }
       // shift: eigenvalue of [[d_l, e_l], [e_l, d_l+1]] nearest d_l, expressed
       // relative to d_mm so that the chase starts from the bottom of the block
       double g = (LD_D(l + 1) - LD_D(l)) / (2.0 * LD_E(l));
@@ -75,6 +86,14 @@ LD_HD inline int tridiag_ql_first_row(int n, double* d, double* e, double* z, in
         const double zi1 = LD_Z(i + 1);
         LD_Z(i + 1) = s * LD_Z(i) + c * zi1;
         LD_Z(i) = c * LD_Z(i) - s * zi1;
+        if (rot_c) {
+          if (nrot < rot_cap) {
+            rot_c[nrot] = c;
+            rot_s[nrot] = s;
+            rot_i[nrot] = i;
+          }
+          ++nrot;
+        }
       }
       if (split) continue;
       LD_D(l) -= p;
@@ -82,6 +101,7 @@ LD_HD inline int tridiag_ql_first_row(int n, double* d, double* e, double* z, in
       LD_E(mm) = 0.0;
     }
   }
+  if (rot_n) *rot_n = (nrot <= rot_cap) ? nrot : -1;
   return 0;
 #undef LD_D
 #undef LD_E
@@ -102,6 +122,20 @@ LD_HD inline double gauss_log_sum(int n, const double* d, const double* z, int s
     acc += w * log(th);
   }
   return acc;
+}
+
+// y <- U y for U = G_1 G_2 ... G_N, the rotations logged by
+// tridiag_ql_first_row (G_q acts on entries (i, i+1): y_i' = c y_i + s y_i+1,
+// y_i+1' = c y_i+1 - s y_i), applied last one first.
+LD_HD inline void apply_logged_rotations(int nrot, const double* rot_c, const double* rot_s,
+                                         const int* rot_i, double* y, int stride) {
+  for (int q = nrot - 1; q >= 0; --q) {
+    const int i = rot_i[q];
+    const double c = rot_c[q], s = rot_s[q];
+    const double a = y[i * stride], b = y[(i + 1) * stride];
+    y[i * stride] = c * a + s * b;
+    y[(i + 1) * stride] = c * b - s * a;
+  }
 }
 
 }  // namespace ld

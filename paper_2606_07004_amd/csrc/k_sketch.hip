@@ -138,60 +138,71 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows(int64_t n, double* __res
 
 // Start block of the Krylov runs: columns [A | G - A P], plus per-block
 // partial squared column norms (FP64 values, before any narrowing).  Rows go
-// through LDS in tiles of 32; thread t owns column t % tpc.
+// through LDS in tiles of tr: the A tile and P (when it fits) are staged,
+// each thread forms 4 adjacent columns of one row of G - A P in registers,
+// the finished tile [tr][ld] is assembled in LDS and written row-major, and
+// thread c accumulates column c's norm in row order.
 template <typename XT>
 __global__ __launch_bounds__(kThreads) void k_project(int64_t n, int rpb, const double* __restrict__ A,
                                                      int lda, int s, const double* __restrict__ Gm,
                                                      int ldg, int r, const double* __restrict__ P,
                                                      int p_in_lds, XT* __restrict__ X0, int ld,
-                                                     int tpc, double* __restrict__ part) {
-  constexpr int TR = 32;
+                                                     int tr, double* __restrict__ part) {
   extern __shared__ double sm[];
-  double* sa = sm;                 // [TR][s]
-  double* sp = sm + TR * s;        // [s][r] when p_in_lds
-  double* red = sm;                // [kThreads] after the row loop
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  double* sa = sm;                      // [tr][s]
+  double* so = sa + (size_t)tr * s;     // [tr][ld]
+  double* sp = so + (size_t)tr * ld;    // [s][r] when p_in_lds
+  const int lb = blockIdx.x;
   const int64_t r0 = (int64_t)lb * rpb;
   const int64_t r1 = min(n, r0 + (int64_t)rpb);
   const int t = threadIdx.x;
-  const int c = t % tpc, rg = t / tpc, ngrp = kThreads / tpc;
   if (p_in_lds)
     for (int e = t; e < s * r; e += kThreads) sp[e] = P[e];
   const double* Pp = p_in_lds ? sp : P;
+  const int nq = (r + 3) / 4;
   double nacc = 0.0;
-  for (int64_t rowb = r0; rowb < r1; rowb += TR) {
+  for (int64_t rowb = r0; rowb < r1; rowb += tr) {
+    const int nr = (int)min((int64_t)tr, r1 - rowb);
     __syncthreads();
-    for (int e = t; e < TR * s; e += kThreads) {
+    for (int e = t; e < tr * s; e += kThreads) {
       const int rr = e / s, i = e % s;
-      sa[e] = (rowb + rr < r1) ? A[(size_t)(rowb + rr) * lda + i] : 0.0;
+      sa[e] = (rr < nr) ? A[(size_t)(rowb + rr) * lda + i] : 0.0;
     }
     __syncthreads();
-    if (c < ld) {
-      for (int rr = rg; rr < TR; rr += ngrp) {
-        const int64_t row = rowb + rr;
-        if (row >= r1) break;
-        double val = 0.0;
-        if (c < s) {
-          val = sa[rr * s + c];
-        } else if (c < s + r) {
-          const int j = c - s;
-          double acc = 0.0;
-          for (int i = 0; i < s; ++i) acc = fma(sa[rr * s + i], Pp[(size_t)i * r + j], acc);
-          val = Gm[(size_t)row * ldg + j] - acc;
-        }
-        X0[(size_t)row * ld + c] = XT(val);
-        nacc = fma(val, val, nacc);
+    // sketch columns and padding of the output tile
+    for (int e = t; e < tr * ld; e += kThreads) {
+      const int rr = e / ld, c = e % ld;
+      if (c < s) so[e] = sa[rr * s + c];
+      else if (c >= s + r) so[e] = 0.0;
+    }
+    // residual columns: 4 at a time per thread
+    for (int it = t; it < tr * nq; it += kThreads) {
+      const int rr = it / nq, q = it % nq;
+      if (rr >= nr) continue;
+      const int j0 = 4 * q;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < s; ++i) {
+        const double a = sa[rr * s + i];
+        const double* pr = Pp + (size_t)i * r + j0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (j0 + u < r) acc[u] = fma(a, pr[u], acc[u]);
+      }
+      const double* gr = Gm + (size_t)(rowb + rr) * ldg + j0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j0 + u < r) so[rr * ld + s + j0 + u] = gr[u] - acc[u];
+    }
+    __syncthreads();
+    if (t < ld) {
+      for (int rr = 0; rr < nr; ++rr) {
+        const double v = so[rr * ld + t];
+        X0[(size_t)(rowb + rr) * ld + t] = XT(v);
+        nacc = fma(v, v, nacc);
       }
     }
   }
-  __syncthreads();
-  red[t] = nacc;
-  __syncthreads();
-  if (rg == 0 && c < ld) {
-    double sum = 0.0;
-    for (int q = 0; q < ngrp; ++q) sum += red[q * tpc + c];
-    part[(size_t)c * gridDim.x + lb] = sum;
-  }
+  if (t < ld) part[(size_t)t * gridDim.x + lb] = nacc;
 }
 
 // Gershgorin: per block min(a_ii - sum|a_ij|) and max(a_ii + sum|a_ij|).
@@ -256,23 +267,25 @@ hipError_t launch_trsm_rows(hipStream_t st, int64_t n, double* Y, int ld, int s,
 hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int lda, int s,
                           const double* Gm, int ldg, int r, const double* P, void* X0, double* part) {
   if (g.n < 1 || g.nblk < 1 || (int64_t)g.nblk * g.rpb < g.n || !Gm || !X0 || !part || r < 1 ||
-      s < 0 || s + r > g.ld || g.ld > 256 || (s > 0 && (!A || !P || lda < s)) || ldg < r)
+      s < 0 || s + r > g.ld || g.ld > kThreads || (s > 0 && (!A || !P || lda < s)) || ldg < r)
     return hipErrorInvalidValue;
-  int tpc = 1;
-  while (tpc < g.ld) tpc <<= 1;
-  size_t lds = (size_t)32 * s * sizeof(double);
+  // largest row tile (32, 16 or 8) whose staging fits 64 KB, P staged too when it fits
+  const size_t budget = 64 * 1024;
+  int tr = 32;
+  while (tr > 8 && (size_t)tr * (s + g.ld) * sizeof(double) > budget) tr /= 2;
+  size_t lds = (size_t)tr * (s + g.ld) * sizeof(double);
+  if (lds > budget) return hipErrorInvalidValue;
   int p_in_lds = 0;
-  if (s > 0 && lds + (size_t)s * r * sizeof(double) <= 48 * 1024) {
+  if (s > 0 && lds + (size_t)s * r * sizeof(double) <= budget) {
     p_in_lds = 1;
     lds += (size_t)s * r * sizeof(double);
   }
-  if (lds < (size_t)kThreads * sizeof(double)) lds = (size_t)kThreads * sizeof(double);
   if (g.xbytes == 8)
     hipLaunchKernelGGL(k_project<double>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A, lda,
-                       s, Gm, ldg, r, P, p_in_lds, static_cast<double*>(X0), g.ld, tpc, part);
+                       s, Gm, ldg, r, P, p_in_lds, static_cast<double*>(X0), g.ld, tr, part);
   else
     hipLaunchKernelGGL(k_project<float>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A, lda,
-                       s, Gm, ldg, r, P, p_in_lds, static_cast<float*>(X0), g.ld, tpc, part);
+                       s, Gm, ldg, r, P, p_in_lds, static_cast<float*>(X0), g.ld, tr, part);
   return hipGetLastError();
 }
 

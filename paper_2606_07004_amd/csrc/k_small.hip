@@ -18,11 +18,12 @@ __global__ __launch_bounds__(kThreads) void k_hess_log(int B, int m, const doubl
                                                       double* __restrict__ ell,
                                                       const double* __restrict__ g, double shift,
                                                       double* __restrict__ K,
-                                                      int* __restrict__ flags) {
+                                                      int* __restrict__ flags,
+                                                      const int* __restrict__ need) {
   __shared__ double shd[kThreads + 4];
   __shared__ int shi[kThreads + 4];
   const int p = blockIdx.x;
-  if (p >= B) return;
+  if (p >= B || (need && !need[p])) return;
   const int nn = meff[p];
   double* ws = work + (size_t)p * wstride;
   double* lv = ws + hess_log_workspace(m);  // [m] result
@@ -55,6 +56,82 @@ __global__ __launch_bounds__(kThreads) void k_hess_log(int B, int m, const doubl
     K[p] = acc;
   }
   if (!finite) flags[p] |= 1;
+}
+
+// Fast path for log(H) e1.  For an SPD operator the windowed recurrence
+// gives an H that is symmetric tridiagonal up to rounding (h_{t-1,t} equals
+// h_{t,t-1} and the entries above the first superdiagonal vanish in exact
+// arithmetic).  When the measured asymmetry is below symtol * max|h|, H is
+// replaced by its symmetric tridiagonal part T and log(T) e1 = U log(Theta)
+// U^T e1 is formed from the implicit QL iteration: U^T e1 is its first-row
+// output and U y is replayed from the logged rotations - O(m^2) work on one
+// lane.  Otherwise need_iss[p] = 1 and the general routine (k_hess_log)
+// takes the run.  One wave per run; lane 0 works (the QL sweep counts of
+// different runs diverge).
+__global__ void k_hess_log_sym(int B, int m, const double* __restrict__ H,
+                               const int* __restrict__ meff, double* __restrict__ work,
+                               int wstride, double symtol, int mode, double* __restrict__ ell,
+                               const double* __restrict__ g, double shift,
+                               double* __restrict__ K, int* __restrict__ flags,
+                               int* __restrict__ need_iss) {
+  const int p = blockIdx.x;
+  if (p >= B || threadIdx.x != 0) return;
+  const int nn = meff[p];
+  need_iss[p] = 0;
+  if (nn <= 0) {
+    if (mode == 0)
+      for (int t = 0; t < m; ++t) ell[(size_t)p * m + t] = 0.0;
+    else
+      K[p] = 0.0;
+    return;
+  }
+  const double* Hp = H + (size_t)p * (m + 1) * m;
+  double hmax = 0.0, asym = 0.0;
+  for (int i = 0; i < nn; ++i)
+    for (int j = (i > 0 ? i - 1 : 0); j < nn; ++j) {
+      const double h = Hp[(size_t)i * m + j];
+      hmax = fmax(hmax, fabs(h));
+      if (j == i + 1) asym = fmax(asym, fabs(h - Hp[(size_t)j * m + i]));
+      else if (j > i + 1) asym = fmax(asym, fabs(h));
+    }
+  if (!(asym <= symtol * hmax)) {
+    need_iss[p] = 1;
+    return;
+  }
+  const int cap = 4 * nn * nn;
+  double* ws = work + (size_t)p * wstride;
+  double* rc = ws;
+  double* rs = ws + cap;
+  int* ri = reinterpret_cast<int*>(ws + 2 * cap);
+  double* d = ws + 2 * cap + (cap + 1) / 2;
+  double* e = d + nn;
+  double* z = e + nn;
+  for (int i = 0; i < nn; ++i) {
+    d[i] = Hp[(size_t)i * m + i];
+    e[i] = (i + 1 < nn) ? 0.5 * (Hp[(size_t)i * m + i + 1] + Hp[(size_t)(i + 1) * m + i]) : 0.0;
+  }
+  int nrot = 0;
+  const int st = tridiag_ql_first_row(nn, d, e, z, 1, rc, rs, ri, cap, &nrot);
+  if (st != 0 || nrot < 0) {
+    need_iss[p] = 1;
+    return;
+  }
+  bool ok = true;
+  for (int k = 0; k < nn; ++k) {
+    if (!(d[k] > 0.0)) ok = false;
+    z[k] = (d[k] > 0.0) ? z[k] * log(d[k]) : 0.0;  // y = log(Theta) U^T e1
+  }
+  if (!ok) flags[p] |= 2;
+  apply_logged_rotations(nrot, rc, rs, ri, z, 1);   // U y = log(T) e1
+  if (mode == 0) {
+    for (int t = 0; t < m; ++t) ell[(size_t)p * m + t] = (t < nn) ? z[t] : 0.0;
+  } else {
+    double acc = 0.0;
+    for (int t = 0; t < nn; ++t) acc = fma(g[(size_t)p * (m + 1) + t], z[t], acc);
+    acc += shift;
+    if (!isfinite(acc)) flags[p] |= 1;
+    K[p] = acc;
+  }
 }
 
 // coef[t][p] = ||s_p|| ell[p][t] mult_t[p] (t < meff_p) plus (log gamma - c)
@@ -108,15 +185,21 @@ LogRule make_log_rule() {
   return r;
 }
 
+int hess_log_wstride(int m) { return 10 * m * m + 8 * m; }
+
 hipError_t launch_hess_log(hipStream_t st, int B, int m, const double* H, const int* meff,
                            double* work, int wstride, int mode, double* ell, const double* g,
-                           double shift, double* K, int* flags) {
-  if (B < 1 || m < 1 || !H || !meff || !work || wstride < hess_log_workspace(m) + m || !flags ||
-      (mode == 0 && !ell) || (mode == 1 && (!g || !K)))
+                           double shift, double* K, int* flags, double symtol, int* need) {
+  if (B < 1 || m < 1 || !H || !meff || !work || wstride < hess_log_wstride(m) || !flags ||
+      !need || (mode == 0 && !ell) || (mode == 1 && (!g || !K)))
     return hipErrorInvalidValue;
   static const LogRule rule = make_log_rule();
+  hipLaunchKernelGGL(k_hess_log_sym, dim3(B), dim3(64), 0, st, B, m, H, meff, work, wstride, symtol,
+                     mode, ell, g, shift, K, flags, need);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_hess_log, dim3(B), dim3(kThreads), 0, st, B, m, H, meff, work, wstride, rule,
-                     mode, ell, g, shift, K, flags);
+                     mode, ell, g, shift, K, flags, (const int*)need);
   return hipGetLastError();
 }
 

@@ -273,7 +273,7 @@ size_t Run::layout(char* base) {
   K_ = static_cast<double*>(take((size_t)ldB_ * 8));
   H_ = static_cast<double*>(take((size_t)ldB_ * (m_ + 1) * m_ * 8));
   gq_ = static_cast<double*>(take((size_t)ldB_ * (m_ + 1) * 8));
-  wstride_ = 6 * m_ * m_ + 4 * m_;
+  wstride_ = hess_log_wstride(m_);
   work_ = (p_.method == LD_METHOD_OSA_IOP)
               ? static_cast<double*>(take((size_t)ldB_ * (size_t)wstride_ * 8))
               : nullptr;
@@ -289,6 +289,8 @@ size_t Run::layout(char* base) {
   active_ = static_cast<int*>(take((size_t)ldB_ * 4));
   flags_ = static_cast<int*>(take((size_t)ldB_ * 4));
   dflag_ = static_cast<int*>(take(16));
+  need_ = static_cast<int*>(take((size_t)ldB_ * 4));
+  meff0_ = static_cast<int*>(take((size_t)ldB_ * 4));
   return off;
 }
 
@@ -430,9 +432,11 @@ ld_status Run::run_prologue(hipStream_t st) {
 // runs (Alg 2).
 ld_status Run::osa_sketch_combine(hipStream_t st) {
   const double shift = std::log(scale_) - c_;
+  // keep the sketch-image runs' Krylov dimensions for the step count
+  LD_HIP(hipMemcpyAsync(meff0_, meff_, (size_t)std::max(s_, 1) * 4, hipMemcpyDeviceToDevice, st));
   LD_LAUNCH(LD_PROF_SMALL, 0,
             launch_hess_log(st, s_, m_, H_, meff_, work_, wstride_, 0, ell_, nullptr, 0.0,
-                            nullptr, flags_));
+                            nullptr, flags_, symtol(), need_));
   LD_LAUNCH(LD_PROF_SMALL, 0,
             launch_osa_coef(st, s_, ld1_, m_, ell_, mult_, norm2_, meff_, shift, coefs_));
   LD_LAUNCH(LD_PROF_SKETCH, (double)m_ * n_ * ld1_ * xb_ + (double)n_ * lds_ * 8,
@@ -518,7 +522,7 @@ ld_status Run::run_epilogue(hipStream_t st) {
     // x^T L_c x / ||x||^2 = sum_t g_t (log H e1)_t + log(gamma) - c
     LD_LAUNCH(LD_PROF_SMALL, 0,
               launch_hess_log(st, B_, m_, H_, meff_, work_, wstride_, 1, nullptr, gq_,
-                              std::log(scale_) - c_, K_, flags_));
+                              std::log(scale_) - c_, K_, flags_, symtol(), need_));
   }
   LD_HIP(hipEventRecord(ev1_, st));
   return LD_OK;
@@ -612,6 +616,12 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail) 
   for (int p = 0; p < B_; ++p) {
     steps += meff[p];
     if (nrm[p] > 0) minst = std::min(minst, meff[p]);
+  }
+  if (p_.method == LD_METHOD_OSA_IOP && s_ > 0) {
+    // OSA-IOP also ran s Krylov runs for the sketch image Y = L_c S
+    std::vector<int> m0(s_);
+    LD_HIP(hipMemcpy(m0.data(), meff0_, (size_t)s_ * 4, hipMemcpyDeviceToHost));
+    for (int p = 0; p < s_; ++p) steps += m0[p];
   }
   res.probe_steps = steps;
   const int64_t sketch_mv = (p_.method == LD_METHOD_OSLQ) ? s_ : (int64_t)s_ * m_;

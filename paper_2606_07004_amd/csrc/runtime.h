@@ -173,6 +173,11 @@ class Run {
   int* active_ = nullptr;
   int* flags_ = nullptr;
   int* dflag_ = nullptr;      // [2] CholQR flags
+  int* need_ = nullptr;       // OSA-IOP: runs needing the general Hessenberg log
+  int* meff0_ = nullptr;      // OSA-IOP: Krylov dimensions of the sketch-image runs
+  // asymmetry of H accepted by the symmetric fast path of log(H) e1: rounding
+  // level of the vectors' precision
+  double symtol() const { return mixed_ ? 1e-5 : 1e-12; }
   size_t part_elems_ = 0;
   size_t slot_elems_ = 0;     // elements of one [n][ld] slot
   int nslots_ = 0;
