@@ -49,7 +49,45 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-probes", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-nmax", type=float, default=2e5)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--copy-bytes", type=float, default=805306368,
+                    help="bytes of the copy-kernel calibration (0 to skip)")
     return ap.parse_args()
+
+
+def pmc_traffic(args, family):
+    """HBM bytes per launch of `family`'s kernel from the committed PMC summary.
+
+    FETCH_SIZE and WRITE_SIZE were taken with rocprofv3 on this workload and
+    scaled by what they read for a plain copy of known size.  Returns None when
+    the workload differs or the kernel source changed since the counters were
+    taken (the figures would then describe another kernel).
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    key = (f"{args.method} {args.precision} values={args.values} lap3d {args.grid} "
+           f"shift={args.shift:g} probes={args.probes} sketch={args.sketch} "
+           f"m={args.krylov_steps} k={args.window} seed={args.seed}")
+    if rec.get("workload") != key:
+        return None
+    for src, digest in rec.get("sources", {}).items():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    kname = rec.get("family_kernel", {}).get(family)
+    k = rec.get("kernels", {}).get(kname)
+    if k is None:
+        return None
+    return {"bytes_per_launch": k["scaled_bytes"], "kernel": kname,
+            "fetch_scale": rec["fetch_scale"], "write_scale": rec["write_scale"],
+            "summary": "profiles/oslq_mixed_lap3d128_pmc_traffic.md"}
 
 
 def golden_for(matrix_name, args):
@@ -89,6 +127,82 @@ def cpu_baseline(a, args):
             "sample": f"{args.method} oracle, same {a.name} matrix, {npr} probes "
                       f"(sketch {s}), {args.krylov_steps} steps, window {args.window}: "
                       f"{steps} probe-steps in {dt:.1f} s"}
+
+
+def serving_bench(L, W, args):
+    """Served log-determinants (SURVEY C5 shape): requests of uneven n,
+    kind and Krylov depth.  Baseline: plain FP64 estimates one at a time.
+    Served: mixed precision through ld_submit with continuous batching,
+    (i) all requests at t = 0 (throughput), (ii) Poisson arrivals at 0.7x the
+    FP64 sequential rate (latency).  Every served result is checked against
+    its own FP64 result."""
+    import numpy as np
+    reqs = W.request_stream(args.serve_requests, seed=1, rate_hz=1.0, n_min=1e4,
+                            n_max=args.serve_nmax)
+    t0 = time.perf_counter()
+    mats = [W.build_request_matrix(r) for r in reqs]
+    t_build = time.perf_counter() - t0
+    print(f"[bench] serving: built {len(mats)} matrices in {t_build:.1f} s", file=sys.stderr,
+          flush=True)
+    ctx = L.Context(0, max_slots=args.serve_slots)
+    try:
+        hs = [ctx.matrix(a, vt=L.LD_VT_FP32, lo_hint=(r["shift"] if r["kind"] == "wendland" else 0.0))
+              for a, r in zip(mats, reqs)]
+
+        def params(r, prec):
+            return L.make_params(r["n_probes"], r["sketch_rank"], r["krylov_steps"],
+                                 r["iop_window"], 1000 + r["id"], precision=prec)
+        # warm the kernels once
+        L.ld_estimate_ex(hs[0], params(reqs[0], L.LD_PREC_FP64))
+        t0 = time.perf_counter()
+        ref = [L.ld_estimate_ex(h, params(r, L.LD_PREC_FP64)).logdet for h, r in zip(hs, reqs)]
+        t_seq = time.perf_counter() - t0
+        seq_rate = len(reqs) / t_seq
+        print(f"[bench] serving: FP64 sequential {seq_rate:.1f} logdets/s", file=sys.stderr,
+              flush=True)
+        # (i) saturation: everything submitted at once
+        t0 = time.perf_counter()
+        tickets = [L.ld_submit(h, params(r, L.LD_PREC_MIXED)) for h, r in zip(hs, reqs)]
+        served = [L.ld_wait(ctx.handle, t) for t in tickets]
+        t_sat = time.perf_counter() - t0
+        sat_rate = len(reqs) / t_sat
+        errs = [abs(sv.logdet - rf) / abs(rf) for sv, rf in zip(served, ref)]
+        print(f"[bench] serving: mixed served {sat_rate:.1f} logdets/s, max rel err "
+              f"{max(errs):.2e}", file=sys.stderr, flush=True)
+        # (ii) Poisson arrivals at 0.7x the FP64 sequential rate
+        rate = 0.7 * seq_rate
+        rng = np.random.Generator(np.random.PCG64(7))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
+        pending = {}
+        lat = []
+        start = time.perf_counter()
+        i = 0
+        while i < len(reqs) or pending:
+            now = time.perf_counter() - start
+            while i < len(reqs) and arrivals[i] <= now:
+                pending[L.ld_submit(hs[i], params(reqs[i], L.LD_PREC_MIXED))] = i
+                i += 1
+            for t in list(pending):
+                res = L.ld_poll(ctx.handle, t)
+                if res is not None:
+                    lat.append(res.latency_ms)
+                    del pending[t]
+            time.sleep(0.0002)
+        lat = np.array(lat)
+        out = {"requests": len(reqs), "n_range": [1e4, args.serve_nmax],
+               "fp64_sequential_logdets_per_s": seq_rate,
+               "mixed_served_logdets_per_s": sat_rate,
+               "speedup_vs_fp64_sequential": sat_rate / seq_rate,
+               "max_rel_err_vs_fp64": max(errs),
+               "poisson_rate_hz": rate,
+               "p50_latency_ms": float(np.percentile(lat, 50)),
+               "p99_latency_ms": float(np.percentile(lat, 99)),
+               "slots": args.serve_slots}
+        for h in hs:
+            ctx.release(h)
+        return out
+    finally:
+        ctx.close()
 
 
 def main():
@@ -164,10 +278,26 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": achieved * 1e9 / HBM_PEAK, "traffic": None,
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch}
+    tr = pmc_traffic(args, dom)
+    if tr is not None:
+        roofline["traffic"] = tr["bytes_per_launch"]
+        roofline["traffic_detail"] = tr
     device_ms_total = sum(v["ms"] for v in fam.values())
     families = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                     "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
                 for k, v in fam.items()}
+
+    copy = None
+    if args.copy_bytes > 0:
+        nb = int(args.copy_bytes) // 16 * 16
+        ms = L.ld_debug_copy(ctx.handle, nb, 10)
+        copy = {"bytes": nb, "ms": ms, "GB/s": 2 * nb / (ms * 1e-3) / 1e9}
+        print(f"[bench] copy calibration {copy}", file=sys.stderr, flush=True)
+
+    serving = None
+    if not args.no_serving:
+        serving = serving_bench(L, W, args)
+        print(f"[bench] serving {serving}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -199,6 +329,8 @@ def main():
         "cpu_baseline": cpu,
         "accuracy": accuracy,
         "kernel_families": families,
+        "serving": serving,
+        "copy_kernel": copy,
         "device_ms_per_step": device_ms_total / args.steps,
     }
     ctx.close()

@@ -201,6 +201,13 @@ ld_status ld_profile_query(ld_ctx* ctx, uint32_t family, int64_t* launches, doub
 ld_status ld_debug_rademacher(ld_ctx* ctx, uint64_t seed, int64_t n,
                               int32_t col_begin, int32_t col_end, double* out);
 
+/* Calibration hook: copies `bytes` (rounded down to 16) between two device
+ * buffers with a plain 16-byte-per-lane copy kernel, `reps` times, and
+ * returns the mean device time per copy in *ms.  Used to scale hardware
+ * byte counters (FETCH_SIZE / WRITE_SIZE) against a transfer of known size
+ * and to measure attainable HBM bandwidth. */
+ld_status ld_debug_copy(ld_ctx* ctx, uint64_t bytes, int32_t reps, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

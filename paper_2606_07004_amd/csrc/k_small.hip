@@ -170,6 +170,21 @@ __global__ __launch_bounds__(kThreads) void k_combine(int64_t n, int ld, int nt,
   }
 }
 
+// Plain copy, 16 bytes per lane, grid-stride (calibration of byte counters).
+__global__ __launch_bounds__(kThreads) void k_copy16(const float4* __restrict__ a,
+                                                    float4* __restrict__ b, size_t n16) {
+  const size_t stride = (size_t)gridDim.x * kThreads;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n16; i += stride) b[i] = a[i];
+}
+
+hipError_t launch_copy16(hipStream_t st, const void* src, void* dst, size_t bytes) {
+  const size_t n16 = bytes / 16;
+  if (!src || !dst || n16 == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_copy16, dim3(4 * kMaxBlocks), dim3(kThreads), 0, st,
+                     static_cast<const float4*>(src), static_cast<float4*>(dst), n16);
+  return hipGetLastError();
+}
+
 LogRule make_log_rule() {
   LogRule r{};
   double d[kLogNodes], e[kLogNodes], z[kLogNodes];

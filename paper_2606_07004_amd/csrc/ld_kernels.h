@@ -114,6 +114,9 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
                           const double* Gm, int ldg, int r, const double* P, void* X0,
                           double* part);
 
+// Plain device copy of `bytes` (multiple of 16 used), calibration only.
+hipError_t launch_copy16(hipStream_t st, const void* src, void* dst, size_t bytes);
+
 // Matrix set-up.
 hipError_t launch_gershgorin(hipStream_t st, int64_t n, const int* rp, const int* ci,
                              const double* va, double* part, int* nparts);

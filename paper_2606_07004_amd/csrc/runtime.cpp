@@ -928,6 +928,30 @@ ld_status ld_profile_query(ld_ctx* ctx, uint32_t family, int64_t* launches, doub
   return LD_OK;
 }
 
+ld_status ld_debug_copy(ld_ctx* ctx, uint64_t bytes, int32_t reps, double* ms) {
+  if (!ctx || !ms || bytes < 16 || reps < 1) return set_error(LD_E_INVALID_ARG, "bad argument");
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  LD_HIP_API(hipSetDevice(ctx->device));
+  DeviceBuffer a, b;
+  LD_HIP_API(a.ensure(bytes));
+  LD_HIP_API(b.ensure(bytes));
+  LD_HIP_API(hipMemsetAsync(a.ptr, 0, bytes, ctx->stream));
+  hipEvent_t e0, e1;
+  LD_HIP_API(hipEventCreate(&e0));
+  LD_HIP_API(hipEventCreate(&e1));
+  LD_HIP_API(launch_copy16(ctx->stream, a.ptr, b.ptr, bytes));  // warm-up
+  LD_HIP_API(hipEventRecord(e0, ctx->stream));
+  for (int i = 0; i < reps; ++i) LD_HIP_API(launch_copy16(ctx->stream, a.ptr, b.ptr, bytes));
+  LD_HIP_API(hipEventRecord(e1, ctx->stream));
+  LD_HIP_API(hipEventSynchronize(e1));
+  float t = 0.f;
+  LD_HIP_API(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = t / reps;
+  return LD_OK;
+}
+
 ld_status ld_debug_rademacher(ld_ctx* ctx, uint64_t seed, int64_t n, int32_t col_begin,
                               int32_t col_end, double* out) {
   if (!ctx || !out || n < 1 || col_begin < 0 || col_end <= col_begin || n > INT32_MAX)

@@ -99,6 +99,7 @@ _SIGNATURES = [
                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("ld_debug_rademacher", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, C.c_int32,
                                         _DP]),
+    ("ld_debug_copy", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int32, _DP]),
 ]
 
 
@@ -257,6 +258,13 @@ def ld_debug_rademacher(ctx, seed: int, n: int, col_begin: int, col_end: int) ->
     out = np.zeros((n, col_end - col_begin))
     _check(lib().ld_debug_rademacher(ctx, seed, n, col_begin, col_end, out.ctypes.data_as(_DP)))
     return out
+
+
+def ld_debug_copy(ctx, nbytes: int, reps: int = 10) -> float:
+    """Mean device ms of a plain copy of nbytes (calibration hook)."""
+    ms = C.c_double()
+    _check(lib().ld_debug_copy(ctx, nbytes, reps, C.byref(ms)))
+    return ms.value
 
 
 class Context:
