@@ -113,26 +113,28 @@ __device__ inline void block_partials(const double (&acc)[C][VEC], double* red, 
 }
 
 // ---------------------------------------------------------------------------
-// CSR x probe block, with the two newest window inner products fused into
-// the epilogue (FUSED).  The newest window vector is the product's own input:
-// its value on the row comes from the gathered diagonal entry (every row
-// stores its diagonal), so only the older one is read again.  W = opscale * (Q X) * diag(xmult); column index and
-// value of an entry are read once by the row's lanes; each lane gathers C
-// contiguous 16-byte segments of the neighbour's probe vector.  For v < nf:
+// CSR x probe block, with up to two window inner products fused into the
+// epilogue (NF of them).  The newest window vector is the product's own
+// input: its value on the row comes from the gathered diagonal entry (every
+// row stores its diagonal), so only an older one (NF = 2) is read again.
+// W = opscale * (Q X) * diag(xmult); column index and value of an entry are
+// read once by the row's lanes; each lane gathers C contiguous 16-byte
+// segments of the neighbour's probe vector.  For v < NF:
 // part[voff+v][col][block] = mult_v[col] * sum_rows x_v[row][col] w[row][col].
 // ---------------------------------------------------------------------------
-template <typename VT, typename XT, int C, bool FUSED>
+template <typename VT, typename XT, int C, int NF>
 __global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const int* __restrict__ rp,
                                                   const int* __restrict__ ci,
                                                   const VT* __restrict__ va,
                                                   const XT* __restrict__ X, XT* __restrict__ W,
                                                   int ld, int ncolv,
                                                   const double* __restrict__ xmult,
-                                                  double opscale, VecSet vs, int nf, int voff,
+                                                  double opscale, VecSet vs, int voff,
                                                   double* __restrict__ part) {
   using A = typename Acc<XT>::type;
   constexpr int VEC = V16<XT>::N;
-  constexpr int NF = FUSED ? 2 : 1;
+  constexpr bool FUSED = NF > 0;
+  constexpr int ND = FUSED ? NF : 1;
   __shared__ double red[FUSED ? kThreads * VEC * C : 1];
   const RowMap rm(lgL);
   bool okc[C];
@@ -147,9 +149,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const 
     for (int e = 0; e < VEC; ++e)
       sc[c][e] = okc[c] ? A(opscale * (xmult ? xmult[colc[c] + e] : 1.0)) : A(0);
   }
-  double dacc[NF][C][VEC];
+  double dacc[ND][C][VEC];
 #pragma unroll
-  for (int v = 0; v < NF; ++v)
+  for (int v = 0; v < ND; ++v)
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
@@ -212,12 +214,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const 
 #pragma unroll
         for (int e = 0; e < VEC; ++e) out.v[e] = XT(acc[c][e] * sc[c][e]);
         out.store(W + (size_t)row * ld + colc[c]);
-        if (FUSED) {
+        if constexpr (FUSED) {
 #pragma unroll
-          for (int v = 0; v < NF; ++v)
-            if (v < nf) {
+          for (int v = 0; v < NF; ++v) {
               V16<XT> x;
-              if (v == nf - 1)
+              if (v == NF - 1)
                 x = xd[c];  // the newest window vector is X itself
               else
                 x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
@@ -228,11 +229,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const 
         }
       }
   }
-  if (FUSED) {
+  if constexpr (FUSED) {
 #pragma unroll
     for (int v = 0; v < NF; ++v)
-      if (v < nf)
-        block_partials<C, VEC>(dacc[v], red, rm, ld, vs.mult[v], part, (size_t)(voff + v) * ld);
+      block_partials<C, VEC>(dacc[v], red, rm, ld, vs.mult[v], part, (size_t)(voff + v) * ld);
   }
 }
 
@@ -292,11 +292,15 @@ __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int lgL, const XT*
 
 // ---------------------------------------------------------------------------
 // Orthogonalisation update and the new norm: w -= sum_v h_v v_v (nv <= NV
-// vectors per launch); with want_norm the block partials of ||w||^2 go to
-// part[0][col][block] and, when v1 is given, those of v1^T w to
-// part[1][col][block].
+// vectors per launch).  With want_norm the block partials of ||w||^2 go to
+// part[0][col][block]; when v1 is given, those of v1^T w to
+// part[1][col][block]; with SYM, those of w_in^T w (w_in = W as it was read,
+// before the update) to part[2][col][block].  For a symmetric operator J and
+// W = J v_t, w_in^T w / ||w|| = (J v_t)^T v_t+1 = v_t^T (J v_t+1): the window
+// inner product of v_t with the next product, which the next step then does
+// not have to read v_t for.  The coefficients h_v * mult_v live in LDS.
 // ---------------------------------------------------------------------------
-template <typename XT, int C, int NV, bool V1>
+template <typename XT, int C, int NV, bool V1, bool SYM>
 __global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* __restrict__ W, int ld,
                                                     int ncolv, VecSet vs, int nv,
                                                     const double* __restrict__ d, int voff,
@@ -305,30 +309,29 @@ __global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* 
                                                     double* __restrict__ part) {
   constexpr int VEC = V16<XT>::N;
   __shared__ double red[kThreads * VEC * C];
+  __shared__ double cf[NV * kMaxLd];
   const RowMap rm(lgL);
+  for (int i = threadIdx.x; i < NV * ld; i += kThreads) {
+    const int v = i / ld, col = i - v * ld;
+    cf[i] = v < nv ? d[(size_t)(voff + v) * ld + col] * (vs.mult[v] ? vs.mult[v][col] : 1.0) : 0.0;
+  }
+  __syncthreads();
   bool okc[C];
   int colc[C];
-  double coef[NV][C][VEC];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int cv = rm.gl + rm.L * c;
     okc[c] = cv < ncolv;
     colc[c] = cv * VEC;
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-      for (int e = 0; e < VEC; ++e)
-        coef[v][c][e] = (okc[c] && v < nv) ? d[(size_t)(voff + v) * ld + colc[c] + e] *
-                                                  (vs.mult[v] ? vs.mult[v][colc[c] + e] : 1.0)
-                                            : 0.0;
   }
-  double nacc[C][VEC], gacc[V1 ? C : 1][VEC];
+  double nacc[C][VEC], gacc[V1 ? C : 1][VEC], sacc[SYM ? C : 1][VEC];
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
       nacc[c][e] = 0.0;
       if constexpr (V1) gacc[c][e] = 0.0;
+      if constexpr (SYM) sacc[c][e] = 0.0;
     }
   const int nn = (int)n;  // n < 2^31
   const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
@@ -349,21 +352,28 @@ __global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* 
           if (v < nv) {
             V16<XT> x;
             x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
+            const double* cfv = cf + v * ld + colc[c];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) wd[e] = fma(-coef[v][c][e], double(x.v[e]), wd[e]);
+            for (int e = 0; e < VEC; ++e) wd[e] = fma(-cfv[e], double(x.v[e]), wd[e]);
           }
+        V16<XT> o;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) w.v[e] = XT(wd[e]);
-        w.store(W + (size_t)row * ld + colc[c]);
+        for (int e = 0; e < VEC; ++e) o.v[e] = XT(wd[e]);
+        o.store(W + (size_t)row * ld + colc[c]);
         if (want_norm) {
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) nacc[c][e] = fma(double(w.v[e]), double(w.v[e]), nacc[c][e]);
+          for (int e = 0; e < VEC; ++e) nacc[c][e] = fma(double(o.v[e]), double(o.v[e]), nacc[c][e]);
+          if constexpr (SYM) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+              sacc[c][e] = fma(double(w.v[e]), double(o.v[e]), sacc[c][e]);
+          }
           if constexpr (V1) {
             V16<XT> x1;
             x1.load(v1 + (size_t)row * ld + colc[c]);
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
-              gacc[c][e] = fma(double(x1.v[e]), double(w.v[e]), gacc[c][e]);
+              gacc[c][e] = fma(double(x1.v[e]), double(o.v[e]), gacc[c][e]);
           }
         }
       }
@@ -375,6 +385,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* 
     } else {
       for (int i = threadIdx.x; i < ld; i += kThreads) part[((size_t)ld + i) * gridDim.x + blockIdx.x] = 0.0;
     }
+    if constexpr (SYM) block_partials<C, VEC>(sacc, red, rm, ld, nullptr, part, (size_t)2 * ld);
   }
 }
 
@@ -433,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void k_start_finish(int B, int ld, const 
 }
 
 __global__ __launch_bounds__(kThreads) void k_step_finish(int B, int ld, int t, int m,
-                                                         const double* __restrict__ d, int j0,
+                                                         double* __restrict__ d, int j0,
                                                          int nv, const double* __restrict__ part,
                                                          int nblk, double tol,
                                                          double* __restrict__ H,
@@ -441,15 +452,20 @@ __global__ __launch_bounds__(kThreads) void k_step_finish(int B, int ld, int t, 
                                                          int* __restrict__ active,
                                                          double* __restrict__ mult_next,
                                                          double* __restrict__ g,
-                                                         int* __restrict__ flags) {
+                                                         int* __restrict__ flags, int sym_row) {
   const int lane = threadIdx.x & 63;
   const int p = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (p >= ld) return;
   const double nrm2 = row_sum(part + (size_t)p * nblk, nblk, lane);
   const double gdot = g ? row_sum(part + (size_t)(ld + p) * nblk, nblk, lane) : 0.0;
+  const double sdot = sym_row >= 0 ? row_sum(part + (size_t)(2 * ld + p) * nblk, nblk, lane) : 0.0;
   if (lane != 0) return;
+  // the window inner products of this step are read below before d[sym_row]
+  // (a row of the same array, for the next step) is written
+  double* dsym = sym_row >= 0 ? d + (size_t)sym_row * ld + p : nullptr;
   if (p >= B || !active[p]) {
     mult_next[p] = 0.0;
+    if (dsym) *dsym = 0.0;
     return;
   }
   double* Hp = H + (size_t)p * (m + 1) * m;
@@ -466,15 +482,18 @@ __global__ __launch_bounds__(kThreads) void k_step_finish(int B, int ld, int t, 
     flags[p] |= 1;
     active[p] = 0;
     mult_next[p] = 0.0;
+    if (dsym) *dsym = 0.0;
     return;
   }
   if (!(beta >= tol)) {
     flags[p] |= 4;
     active[p] = 0;
     mult_next[p] = 0.0;
+    if (dsym) *dsym = 0.0;
     return;
   }
   if (g) g[(size_t)p * (m + 1) + t + 1] = gdot / beta;
+  if (dsym) *dsym = sdot / beta;
   mult_next[p] = 1.0 / beta;
 }
 
@@ -616,27 +635,29 @@ hipError_t launch_rademacher(hipStream_t st, uint64_t seed, int64_t n, int pbase
   return hipGetLastError();
 }
 
+template <typename VT, typename XT, int NF>
+static void spmm_launch_nf(hipStream_t st, const Geom& g, const int* rp, const int* ci,
+                           const VT* va, const XT* X, XT* W, const double* xmult, double opscale,
+                           const VecSet& vs, int voff, double* part, int* nblk_out) {
+  LD_DISPATCH_C(g.C, {
+    auto fn = k_spmm<VT, XT, CC, NF>;
+    const int nb = stream_grid(g, (const void*)fn);
+    *nblk_out = nb;
+    hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, rp, ci, va, X, W, g.ld,
+                       g.ncolv, xmult, opscale, vs, voff, part);
+  });
+}
+
 template <typename VT, typename XT>
 static hipError_t spmm_typed(hipStream_t st, const Geom& g, const int* rp, const int* ci,
                              const VT* va, const XT* X, XT* W, const double* xmult, double opscale,
                              const VecSet& vs, int nf, int voff, double* part, int* nblk_out) {
-  if (nf > 0) {
-    LD_DISPATCH_C(g.C, {
-      auto fn = k_spmm<VT, XT, CC, true>;
-      const int nb = stream_grid(g, (const void*)fn);
-      *nblk_out = nb;
-      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, rp, ci, va, X, W, g.ld,
-                         g.ncolv, xmult, opscale, vs, nf, voff, part);
-    });
-  } else {
-    LD_DISPATCH_C(g.C, {
-      auto fn = k_spmm<VT, XT, CC, false>;
-      const int nb = stream_grid(g, (const void*)fn);
-      *nblk_out = nb;
-      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, rp, ci, va, X, W, g.ld,
-                         g.ncolv, xmult, opscale, vs, nf, voff, part);
-    });
-  }
+  if (nf == 2)
+    spmm_launch_nf<VT, XT, 2>(st, g, rp, ci, va, X, W, xmult, opscale, vs, voff, part, nblk_out);
+  else if (nf == 1)
+    spmm_launch_nf<VT, XT, 1>(st, g, rp, ci, va, X, W, xmult, opscale, vs, voff, part, nblk_out);
+  else
+    spmm_launch_nf<VT, XT, 0>(st, g, rp, ci, va, X, W, xmult, opscale, vs, voff, part, nblk_out);
   return hipGetLastError();
 }
 
@@ -708,133 +729,64 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
   return hipGetLastError();
 }
 
+template <typename XT, int NV, bool V1, bool SYM>
+static void update_launch(hipStream_t st, const Geom& g, XT* W, const VecSet& vs, int nv,
+                          const double* d, int voff, int want_norm, const XT* v1,
+                          const double* v1mult, double* part, int* nblk_out) {
+  LD_DISPATCH_C(g.C, {
+    auto fn = k_update<XT, CC, NV, V1, SYM>;
+    const int nb = stream_grid(g, (const void*)fn);
+    *nblk_out = nb;
+    hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, W, g.ld, g.ncolv, vs, nv, d,
+                       voff, want_norm, v1, v1mult, part);
+  });
+}
+
+template <typename XT, int NV>
+static void update_nv(hipStream_t st, const Geom& g, XT* W, const VecSet& vs, int nv,
+                      const double* d, int voff, int want_norm, const XT* v1,
+                      const double* v1mult, bool sym, double* part, int* nblk_out) {
+  if (v1) {
+    if (sym)
+      update_launch<XT, NV, true, true>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, part, nblk_out);
+    else
+      update_launch<XT, NV, true, false>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, part, nblk_out);
+  } else {
+    if (sym)
+      update_launch<XT, NV, false, true>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, part, nblk_out);
+    else
+      update_launch<XT, NV, false, false>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, part, nblk_out);
+  }
+}
+
+template <typename XT>
+static void update_typed(hipStream_t st, const Geom& g, XT* W, const VecSet& vs, int nv,
+                         const double* d, int voff, int want_norm, const XT* v1,
+                         const double* v1mult, bool sym, double* part, int* nblk_out) {
+  if (nv <= 1)
+    update_nv<XT, 1>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, sym, part, nblk_out);
+  else if (nv == 2)
+    update_nv<XT, 2>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, sym, part, nblk_out);
+  else
+    update_nv<XT, 4>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, sym, part, nblk_out);
+}
+
 hipError_t launch_update(hipStream_t st, const Geom& g, void* W, const VecSet& vs, int nv,
                          const double* d, int voff, int want_norm, const void* v1,
-                         const double* v1mult, double* part, int* nblk_out) {
+                         const double* v1mult, bool sym, double* part, int* nblk_out) {
   int dummy = 0;
   if (!nblk_out) nblk_out = &dummy;
-  if (!geom_ok(g) || !W || !d || nv < 0 || nv > 4 || (want_norm && !part) ||
-      (v1 && !v1mult))
+  if (!geom_ok(g) || g.ld > kMaxLd || !W || !d || nv < 0 || nv > 4 || (want_norm && !part) ||
+      (v1 && !v1mult) || (sym && !want_norm))
     return hipErrorInvalidValue;
   for (int v = 0; v < nv; ++v)
     if (!vs.x[v] || vs.x[v] == W) return hipErrorInvalidValue;
-  if (g.xbytes == 8) {
-    double* w = static_cast<double*>(W);
-    const double* x1 = static_cast<const double*>(v1);
-    if (nv <= 1) {
-      if (v1) {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<double, CC, 1, true>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      } else {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<double, CC, 1, false>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      }
-    } else if (nv == 2) {
-      if (v1) {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<double, CC, 2, true>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      } else {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<double, CC, 2, false>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      }
-    } else {
-      if (v1) {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<double, CC, 4, true>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      } else {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<double, CC, 4, false>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      }
-    }
-  } else {
-    float* w = static_cast<float*>(W);
-    const float* x1 = static_cast<const float*>(v1);
-    if (nv <= 1) {
-      if (v1) {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<float, CC, 1, true>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      } else {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<float, CC, 1, false>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      }
-    } else if (nv == 2) {
-      if (v1) {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<float, CC, 2, true>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      } else {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<float, CC, 2, false>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      }
-    } else {
-      if (v1) {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<float, CC, 4, true>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      } else {
-        LD_DISPATCH_C(g.C, {
-          auto fn = k_update<float, CC, 4, false>;
-          const int nb = stream_grid(g, (const void*)fn);
-          *nblk_out = nb;
-          hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, w, g.ld, g.ncolv, vs,
-                             nv, d, voff, want_norm, x1, v1mult, part);
-        });
-      }
-    }
-  }
+  if (g.xbytes == 8)
+    update_typed<double>(st, g, static_cast<double*>(W), vs, nv, d, voff, want_norm,
+                         static_cast<const double*>(v1), v1mult, sym, part, nblk_out);
+  else
+    update_typed<float>(st, g, static_cast<float*>(W), vs, nv, d, voff, want_norm,
+                        static_cast<const float*>(v1), v1mult, sym, part, nblk_out);
   return hipGetLastError();
 }
 
@@ -853,13 +805,17 @@ hipError_t launch_start_finish(hipStream_t st, int B, int ld, const double* part
   return hipGetLastError();
 }
 
-hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, const double* d, int j0,
+hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, double* d, int j0,
                               int nv, const double* part, int nblk, double tol, double* H,
-                              int* meff, int* active, double* mult_next, double* g, int* flags) {
-  if (B < 1 || ld < B || t < 0 || t >= m || j0 < 0 || j0 + nv != t + 1 || !part || nblk < 1)
+                              int* meff, int* active, double* mult_next, double* g, int* flags,
+                              int sym_row) {
+  // the next step has at most nv + 1 window vectors: its second newest sits
+  // at row <= nv - 1 of d
+  if (B < 1 || ld < B || t < 0 || t >= m || j0 < 0 || j0 + nv != t + 1 || !part || nblk < 1 ||
+      sym_row >= nv || (sym_row >= 0 && t + 1 >= m))
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_step_finish, dim3((ld + 3) / 4), dim3(kThreads), 0, st, B, ld, t, m, d, j0,
-                     nv, part, nblk, tol, H, meff, active, mult_next, g, flags);
+                     nv, part, nblk, tol, H, meff, active, mult_next, g, flags, sym_row < 0 ? -1 : sym_row);
   return hipGetLastError();
 }
 

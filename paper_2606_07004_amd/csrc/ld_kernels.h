@@ -15,6 +15,7 @@ enum ValueType : int { VT_F64 = 0, VT_F32 = 1, VT_BF16 = 2 };
 
 constexpr int kMaxBlocks = 2048;  // 256 CUs x 8 resident 256-thread blocks
 constexpr int kMaxC = 4;          // 16-byte chunks per lane
+constexpr int kMaxLd = 256;       // probe-block row length (columns) of the Krylov kernels
 
 // Row partition of an [n][ld] probe block.  The streaming kernels sweep
 // chunks of 256/L consecutive rows, block b taking chunks b, b+nblk, ...; the
@@ -60,10 +61,11 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
 
 // w[row][col] -= sum_v d[voff+v][col] * mult_v[col] * x_v[row][col] (nv <= 4); when
 // want_norm: part[0][col][block] = sum w^2, part[1][col][block] = v1mult[col] *
-// sum v1[row][col] w[row][col] (zero when v1 is null).
+// sum v1[row][col] w[row][col] (zero when v1 is null) and, with sym,
+// part[2][col][block] = sum w_in[row][col] w[row][col] (w_in: W before the update).
 hipError_t launch_update(hipStream_t st, const Geom& g, void* W, const VecSet& vs, int nv,
                          const double* d, int voff, int want_norm, const void* v1,
-                         const double* v1mult, double* part, int* nblk_out);
+                         const double* v1mult, bool sym, double* part, int* nblk_out);
 
 // out[i] = sum_{b < nblk} part[i*nblk + b], fixed order.
 hipError_t launch_reduce(hipStream_t st, const double* part, int nblk, int width, double* out);
@@ -73,9 +75,13 @@ hipError_t launch_reduce(hipStream_t st, const double* part, int nblk, int width
 hipError_t launch_start_finish(hipStream_t st, int B, int ld, const double* part, int nblk,
                                double* norm2, double* mult0, int* active, int* meff, double* g,
                                int gstride);
-hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, const double* d, int j0,
+// With sym_row >= 0 it also reduces part[2] and stores, per probe, the inner
+// product of the new vector with the product it came from (sum / ||w||) in
+// d[sym_row][p], where the next step's window inner products are read.
+hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, double* d, int j0,
                               int nv, const double* part, int nblk, double tol, double* H,
-                              int* meff, int* active, double* mult_next, double* g, int* flags);
+                              int* meff, int* active, double* mult_next, double* g, int* flags,
+                              int sym_row);
 
 // Gauss quadrature of log on each probe's T (diag h_tt, subdiag h_t+1,t).
 hipError_t launch_gauss_log(hipStream_t st, int B, int m, const double* H, const int* meff,

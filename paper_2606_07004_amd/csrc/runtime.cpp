@@ -351,6 +351,7 @@ ld_status Run::start_block(hipStream_t st, const double* A, int s_cols) {
 ld_status Run::begin_krylov(int phase) {
   kphase_ = phase;
   t_ = 0;
+  sym_ready_ = false;
   if (p_.method == LD_METHOD_OSLQ) {
     kB_ = B_;
     kld_ = ldB_;
@@ -467,11 +468,16 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
   void* W = slot_ptr(t + 1);
   const int j0 = std::max(0, t - k_ + 1);
   const int nv = t - j0 + 1;
-  // the two newest window vectors (v_t-1, v_t) are dotted in the product's
-  // epilogue; window index v corresponds to Krylov index j0 + v.  Each
-  // launch writes its partial sums to its own region of part_ with its own
-  // grid size, and is reduced into its rows of dwin_.
-  const int nf = std::min(2, nv);
+  // Window inner products h_jt = v_j^T (J v_t), row v = j - j0 of dwin_.
+  // The newest (j = t) is fused into the product's epilogue.  The second
+  // newest, v_t-1^T J v_t = v_t^T (J v_t-1) since J is symmetric, was formed
+  // by the previous step's update pass when that pass was a single launch
+  // (sym_in); otherwise the product's epilogue reads v_t-1 for it.  Older
+  // ones take separate passes.  Each launch writes its partial sums to its own
+  // region of part_ with its own grid size and is reduced into its rows.
+  const bool sym_in = sym_ready_ && nv >= 2;
+  const int nf = sym_in ? 1 : std::min(2, nv);
+  const int nold = nv - nf - (sym_in ? 1 : 0);  // rows [0, nold) need a dots pass
   VecSet vf{};
   for (int v = 0; v < nf; ++v) {
     vf.x[v] = slot_ptr(j0 + nv - nf + v);
@@ -483,9 +489,9 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
                         &vf, nf, 0, part_, &nb));
   LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nf * kld_ * 8,
             launch_reduce(st, part_, nb, nf * kld_, dwin_ + (size_t)(nv - nf) * kld_));
-  for (int c0 = 0; c0 < nv - nf; c0 += 4) {
+  for (int c0 = 0; c0 < nold; c0 += 4) {
     VecSet vs{};
-    const int nc = std::min(4, nv - nf - c0);
+    const int nc = std::min(4, nold - c0);
     for (int v = 0; v < nc; ++v) {
       vs.x[v] = slot_ptr(j0 + c0 + v);
       vs.mult[v] = mult_ptr(j0 + c0 + v);
@@ -496,6 +502,10 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
     LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nc * kld_ * 8,
               launch_reduce(st, pp, nb, nc * kld_, dwin_ + (size_t)c0 * kld_));
   }
+  // the update pass hands the next step its second-newest inner product when
+  // it runs as one launch and the window holds two vectors or more
+  const bool sym_out = k_ >= 2 && nv <= 4 && t + 1 < m_;
+  const int nv_next = (t + 1) - std::max(0, t + 2 - k_) + 1;
   for (int c0 = 0; c0 < nv; c0 += 4) {
     VecSet vs{};
     const int nc = std::min(4, nv - c0);
@@ -507,11 +517,13 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
     LD_LAUNCH(LD_PROF_UPDATE, (double)(nc + 2 + ((last && kpin_) ? 1 : 0)) * vec_bytes,
               launch_update(st, kg_, W, vs, nc, dwin_, c0, last ? 1 : 0,
                             (last && kpin_) ? slot_ptr(0) : nullptr,
-                            (last && kpin_) ? mult_ptr(0) : nullptr, part_, &nb));
+                            (last && kpin_) ? mult_ptr(0) : nullptr, last && sym_out, part_, &nb));
   }
+  sym_ready_ = sym_out;
   LD_LAUNCH(LD_PROF_SMALL, (double)nb * 2 * kld_ * 8,
             launch_step_finish(st, kB_, kld_, t, m_, dwin_, j0, nv, part_, nb, tol_, H_,
-                               meff_, active_, mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_));
+                               meff_, active_, mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_,
+                               sym_out ? nv_next - 2 : -1));
   return LD_OK;
 }
 

@@ -146,6 +146,7 @@ class Run {
   // Krylov phase parameters (current)
   int kB_ = 0, kld_ = 0, kns_ = 0;
   bool kpin_ = false, kfull_ = false;
+  bool sym_ready_ = false;    // the next step's second-newest window product is in dwin_
   Geom kg_;
   void* kslots_ = nullptr;
   double* kmult_ = nullptr;
