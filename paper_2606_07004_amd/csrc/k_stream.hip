@@ -93,23 +93,37 @@ __device__ inline int chunk_of(int j) {
   return (nb & 7) ? base + b : base + (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-// Sum the per-lane accumulators of one vector over the row groups of the
-// block and store the block's partial sums (times mult[col]).
+// Column sums of the per-thread slots red[rg][c][gl][e] over the row groups
+// of the block, stored as the block's partial sums (times mult[col]).
 template <int C, int VEC>
-__device__ inline void block_partials(const double (&acc)[C][VEC], double* red, const RowMap& rm,
-                                      int ld, const double* mult, double* part, size_t row0) {
+__device__ inline void red_partials(const double* red, const RowMap& rm, int ld, const double* mult,
+                                    double* part, size_t row0) {
   const int WC = rm.L * C * VEC;
-#pragma unroll
-  for (int c = 0; c < C; ++c)
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) red[rm.rg * WC + (c * rm.L + rm.gl) * VEC + e] = acc[c][e];
-  __syncthreads();
   for (int i = threadIdx.x; i < WC; i += kThreads) {
     double sum = 0.0;
     for (int q = 0; q < rm.rpi; ++q) sum += red[q * WC + i];
     if (i < ld) part[(row0 + i) * gridDim.x + blockIdx.x] = sum * (mult ? mult[i] : 1.0);
   }
   __syncthreads();
+}
+
+// Slot of thread (rg, gl) for chunk c, element e in a [rpi][C*L*VEC] array.
+template <int C, int VEC>
+__device__ inline int red_slot(const RowMap& rm, int c, int e) {
+  return rm.rg * (rm.L * C * VEC) + (c * rm.L + rm.gl) * VEC + e;
+}
+
+// Sum the per-lane accumulators of one vector over the row groups of the
+// block and store the block's partial sums (times mult[col]).
+template <int C, int VEC>
+__device__ inline void block_partials(const double (&acc)[C][VEC], double* red, const RowMap& rm,
+                                      int ld, const double* mult, double* part, size_t row0) {
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) red[red_slot<C, VEC>(rm, c, e)] = acc[c][e];
+  __syncthreads();
+  red_partials<C, VEC>(red, rm, ld, mult, part, row0);
 }
 
 // ---------------------------------------------------------------------------
@@ -134,21 +148,29 @@ __global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const 
   using A = typename Acc<XT>::type;
   constexpr int VEC = V16<XT>::N;
   constexpr bool FUSED = NF > 0;
-  constexpr int ND = FUSED ? NF : 1;
+  // one fused product: its per-thread FP64 sums live in the thread's own LDS
+  // slots (fewer registers, more waves in flight for the gather); two: in
+  // registers, with the LDS array used for the final column sums
+  constexpr bool LDSACC = NF == 1;
+  constexpr int ND = (FUSED && !LDSACC) ? NF : 1;
   __shared__ double red[FUSED ? kThreads * VEC * C : 1];
+  __shared__ A scs[kMaxLd];  // opscale * xmult[col], in the accumulation type
   const RowMap rm(lgL);
+  for (int i = threadIdx.x; i < ld; i += kThreads)
+    scs[i] = A(opscale * (xmult ? xmult[i] : 1.0));
   bool okc[C];
   int colc[C];
-  A sc[C][VEC];  // opscale * xmult[col], in the accumulation type
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int cv = rm.gl + rm.L * c;
     okc[c] = cv < ncolv;
     colc[c] = cv * VEC;
+    if constexpr (LDSACC) {
 #pragma unroll
-    for (int e = 0; e < VEC; ++e)
-      sc[c][e] = okc[c] ? A(opscale * (xmult ? xmult[colc[c] + e] : 1.0)) : A(0);
+      for (int e = 0; e < VEC; ++e) red[red_slot<C, VEC>(rm, c, e)] = 0.0;
+    }
   }
+  __syncthreads();
   double dacc[ND][C][VEC];
 #pragma unroll
   for (int v = 0; v < ND; ++v)
@@ -211,10 +233,18 @@ __global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const 
     for (int c = 0; c < C; ++c)
       if (okc[c]) {
         V16<XT> out;
+        const A* sce = scs + colc[c];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) out.v[e] = XT(acc[c][e] * sc[c][e]);
+        for (int e = 0; e < VEC; ++e) out.v[e] = XT(acc[c][e] * sce[e]);
         out.store(W + (size_t)row * ld + colc[c]);
-        if constexpr (FUSED) {
+        if constexpr (LDSACC) {
+          // the newest window vector is X itself
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            double& slot = red[red_slot<C, VEC>(rm, c, e)];
+            slot = fma(double(xd[c].v[e]), double(out.v[e]), slot);
+          }
+        } else if constexpr (FUSED) {
 #pragma unroll
           for (int v = 0; v < NF; ++v) {
               V16<XT> x;
@@ -229,7 +259,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const 
         }
       }
   }
-  if constexpr (FUSED) {
+  if constexpr (LDSACC) {
+    __syncthreads();
+    red_partials<C, VEC>(red, rm, ld, vs.mult[0], part, (size_t)voff * ld);
+  } else if constexpr (FUSED) {
 #pragma unroll
     for (int v = 0; v < NF; ++v)
       block_partials<C, VEC>(dacc[v], red, rm, ld, vs.mult[v], part, (size_t)(voff + v) * ld);
@@ -666,7 +699,7 @@ hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* 
                        const VecSet* fused, int nf, int voff, double* part, int* nblk_out) {
   int dummy = 0;
   if (!nblk_out) nblk_out = &dummy;
-  if (!geom_ok(g) || !rp || !ci || !va || !X || !W || X == W || nf < 0 || nf > 2 ||
+  if (!geom_ok(g) || g.ld > kMaxLd || !rp || !ci || !va || !X || !W || X == W || nf < 0 || nf > 2 ||
       (nf > 0 && (!fused || !part || voff < 0)))
     return hipErrorInvalidValue;
   VecSet vs{};
