@@ -13,6 +13,8 @@ Techniques for Large-Scale Log-Determinant Estimation"):
                     generator (Salmon et al., SC'11); the paper draws +-1 with
                     probability 1/2 (Section 2, eq. (TE); Algs 2 and 3) and
                     names no generator, so both sides implement this one.
+                    Gaussian probes (the alternative Section 2 allows) by the
+                    Box-Muller transform of the same generator's words.
 * ``spectral``    - Gershgorin spectral interval (Section 2.1), the scale
                     gamma = sqrt(lmin lmax) (Proposition 2.1) and the shifts
                     that make the traced operator PSD (eqs. for L in Section
@@ -23,25 +25,29 @@ Techniques for Large-Scale Log-Determinant Estimation"):
 * ``quadrature``  - Gauss quadrature from the tridiagonal T_m (Section 3.1,
                     eq. gauss_quadrature) and log(H_m) e1 (Alg 1, via the
                     principal matrix logarithm).
-* ``estimators``  - OSLQ (Alg 3), OSA-IOP (Alg 2), and plain Hutchinson/SLQ
-                    as the sketch-rank-0 setting.
+* ``estimators``  - OSLQ (Alg 3), OSA-IOP (Alg 2), plain Hutchinson/SLQ
+                    as the sketch-rank-0 setting, and the So-SLQ comparator of
+                    Section 4 (subspace from the dominant left singular
+                    vectors of a sketch of log J).
 
 Parity status: every function here is pinned by the CPU tests in
 ``tests/test_oracle_*.py`` (known-answer RNG vectors, closed forms, quadrature
 and polynomial exactness, Hutch++ exactness, brute force on tiny inputs, scale
 identities).  No function is "parity unpinned".
 """
-from .philox import philox4x64_10, philox4x64_10_np, rademacher
+from .philox import (philox4x64_10, philox4x64_10_np, rademacher, gaussian, probes,
+                     PROBE_RADEMACHER, PROBE_GAUSSIAN)
 from .spectral import (GERSH_FLOOR_REL, gershgorin_bounds, spectral_interval,
                        oslq_scaling, osa_iop_shift)
 from .krylov import windowed_arnoldi
 from .quadrature import gauss_quadrature_log, tridiag_from_hessenberg, log_hessenberg_e1
-from .estimators import oslq, osa_iop, slq, OracleResult, dense_logdet, NotSPDError
+from .estimators import oslq, osa_iop, slq, so_slq, OracleResult, dense_logdet, NotSPDError
 
 __all__ = [
-    "philox4x64_10", "philox4x64_10_np", "rademacher", "GERSH_FLOOR_REL",
+    "philox4x64_10", "philox4x64_10_np", "rademacher", "gaussian", "probes",
+    "PROBE_RADEMACHER", "PROBE_GAUSSIAN", "GERSH_FLOOR_REL",
     "gershgorin_bounds", "spectral_interval", "oslq_scaling", "osa_iop_shift",
     "windowed_arnoldi", "gauss_quadrature_log", "tridiag_from_hessenberg",
-    "log_hessenberg_e1", "oslq", "osa_iop", "slq", "OracleResult",
+    "log_hessenberg_e1", "oslq", "osa_iop", "slq", "so_slq", "OracleResult",
     "dense_logdet", "NotSPDError",
 ]

@@ -32,7 +32,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .krylov import windowed_arnoldi
-from .philox import rademacher
+from .philox import PROBE_RADEMACHER, probes
 from .quadrature import (NotSPDError, gauss_quadrature_log, log_hessenberg_e1,
                          tridiag_from_hessenberg)
 from .spectral import osa_iop_shift, oslq_scaling, spectral_interval
@@ -84,7 +84,8 @@ def _split(n_probes: int, sketch_rank: int, n: int, m: int, window: int):
 
 def oslq(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: int,
          seed: int, tol: float = DEFAULT_TOL, lo_hint: float = 0.0,
-         hi_hint: float = 0.0, keep_basis: bool = False) -> OracleResult:
+         hi_hint: float = 0.0, keep_basis: bool = False,
+         dist: int = PROBE_RADEMACHER) -> OracleResult:
     """Alg 3: Hutch++ with the subspace from orth(J S) and Gauss-Lanczos
     quadrature for every quadratic form of log J."""
     n = a.n
@@ -101,7 +102,7 @@ def oslq(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: int,
         al, be = tridiag_from_hessenberg(h)
         return gauss_quadrature_log(al, be), m_eff, al, be
 
-    sk = rademacher(seed, n, 0, s)
+    sk = probes(seed, n, 0, s, dist)
     y = (q @ sk) / alpha if s > 0 else np.zeros((n, 0))
     basis = _orth(y)
 
@@ -114,7 +115,7 @@ def oslq(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: int,
         ks.append(kval); norms.append(float(qi @ qi)); steps.append(m_eff)
         alphas.append(al); betas.append(be)
 
-    g = rademacher(seed, n, s, s + r)
+    g = probes(seed, n, s, s + r, dist)
     acc = 0.0
     for j in range(r):
         u = g[:, j] - basis @ (basis.T @ g[:, j]) if s > 0 else g[:, j].copy()
@@ -134,9 +135,11 @@ def oslq(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: int,
 
 
 def slq(a, n_probes: int, krylov_steps: int, iop_window: int, seed: int,
-        tol: float = DEFAULT_TOL, lo_hint: float = 0.0, hi_hint: float = 0.0):
+        tol: float = DEFAULT_TOL, lo_hint: float = 0.0, hi_hint: float = 0.0,
+        dist: int = PROBE_RADEMACHER):
     """Stochastic Lanczos quadrature: the sketch-rank-0 setting of OSLQ."""
-    return oslq(a, n_probes, 0, krylov_steps, iop_window, seed, tol, lo_hint, hi_hint)
+    return oslq(a, n_probes, 0, krylov_steps, iop_window, seed, tol, lo_hint, hi_hint,
+                dist=dist)
 
 
 def _iop_log_action(q, x, gamma: float, c: float, m: int, window: int, tol: float):
@@ -153,7 +156,8 @@ def _iop_log_action(q, x, gamma: float, c: float, m: int, window: int, tol: floa
 
 def osa_iop(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: int,
             seed: int, tol: float = DEFAULT_TOL, lo_hint: float = 0.0,
-            hi_hint: float = 0.0, keep_basis: bool = False) -> OracleResult:
+            hi_hint: float = 0.0, keep_basis: bool = False,
+            dist: int = PROBE_RADEMACHER) -> OracleResult:
     """Alg 2: Hutch++ on L_c with every L_c x from Alg 1 (Arnoldi-IOP-LOG)."""
     n = a.n
     s, r = _split(n_probes, sketch_rank, n, krylov_steps, iop_window)
@@ -161,7 +165,7 @@ def osa_iop(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: i
     lo, hi = spectral_interval(a, lo_hint, hi_hint)
     gamma, c = osa_iop_shift(lo, hi)
 
-    sk = rademacher(seed, n, 0, s)
+    sk = probes(seed, n, 0, s, dist)
     y = np.zeros((n, s))
     for i in range(s):
         y[:, i], _, _, _ = _iop_log_action(q, sk[:, i], gamma, c, krylov_steps, iop_window, tol)
@@ -179,7 +183,7 @@ def osa_iop(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: i
         al, be = tridiag_from_hessenberg(h)
         alphas.append(al); betas.append(be)
 
-    g = rademacher(seed, n, s, s + r)
+    g = probes(seed, n, s, s + r, dist)
     acc = 0.0
     for j in range(r):
         u = g[:, j] - basis @ (basis.T @ g[:, j]) if s > 0 else g[:, j].copy()
@@ -207,3 +211,77 @@ def dense_logdet(a) -> float:
     if sign <= 0:
         raise NotSPDError("matrix is not positive definite")
     return float(val)
+
+
+def so_slq(a, n_probes: int, sketch_rank: int, subspace_rank: int, krylov_steps: int,
+           iop_window: int, seed: int, tol: float = DEFAULT_TOL, lo_hint: float = 0.0,
+           hi_hint: float = 0.0, keep_basis: bool = False,
+           dist: int = PROBE_RADEMACHER) -> OracleResult:
+    """So-SLQ, the comparator of Section 4 (Han et al.'s subspace construction,
+    with the settings the paper gives: a sketch of q = sketch_rank columns and a
+    kept rank k = subspace_rank).
+
+    Reading used (the paper describes the method in words only): the sketch is
+    Y = log(J) S with J the OSLQ operator (Y = L_c S with OSLQ's shift c, each
+    column from Alg 1 on J); the subspace is spanned by the k dominant left
+    singular vectors of Y (QR of Y, then the SVD of its R factor); tr(L_c) is
+    split as in Hutch++ into the k Gauss-Lanczos quadratic forms on the basis
+    vectors and the Hutchinson average over the r = n_probes - q residual
+    probes projected off the basis, each also by Gauss-Lanczos quadrature.
+    """
+    n = a.n
+    q_cols = int(sketch_rank)
+    k_rank = int(subspace_rank)
+    r = int(n_probes) - q_cols
+    if q_cols < 1 or k_rank < 1 or k_rank > q_cols or q_cols > n or r < 1 \
+            or krylov_steps < 1 or iop_window < 1:
+        raise ValueError(f"bad So-SLQ parameters n_probes={n_probes} sketch_rank={q_cols} "
+                         f"subspace_rank={k_rank}")
+    q = _as_scipy(a)
+    lo, hi = spectral_interval(a, lo_hint, hi_hint)
+    alpha, c = oslq_scaling(lo, hi)
+
+    def apply_j(x):
+        return (q @ x) / alpha
+
+    def quad(x):
+        h, beta0, _, m_eff, _ = windowed_arnoldi(apply_j, x, krylov_steps, iop_window, tol)
+        al, be = tridiag_from_hessenberg(h)
+        return gauss_quadrature_log(al, be), m_eff, al, be
+
+    # sketch of the traced operator log(J) = L_c, one Alg 1 run per column
+    sk = probes(seed, n, 0, q_cols, dist)
+    y = np.zeros((n, q_cols))
+    for i in range(q_cols):
+        y[:, i], _, _, _ = _iop_log_action(q, sk[:, i], alpha, c, krylov_steps, iop_window, tol)
+    qy = _orth(y)
+    rfac = qy.T @ y
+    u_r, sig, _ = np.linalg.svd(rfac)
+    basis = qy @ u_r[:, :k_rank]
+
+    ks, norms, steps, alphas, betas = [], [], [], [], []
+    tr_sketch = 0.0
+    for i in range(k_rank):
+        bi = basis[:, i]
+        kval, m_eff, al, be = quad(bi / math.sqrt(float(bi @ bi)))
+        tr_sketch += kval
+        ks.append(kval); norms.append(float(bi @ bi)); steps.append(m_eff)
+        alphas.append(al); betas.append(be)
+
+    g = probes(seed, n, q_cols, q_cols + r, dist)
+    acc = 0.0
+    for j in range(r):
+        u = g[:, j] - basis @ (basis.T @ g[:, j])
+        nu2 = float(u @ u)
+        if nu2 == 0.0:
+            ks.append(0.0); norms.append(0.0); steps.append(0)
+            alphas.append(np.zeros(0)); betas.append(np.zeros(0))
+            continue
+        kval, m_eff, al, be = quad(u / math.sqrt(nu2))
+        acc += nu2 * kval
+        ks.append(kval); norms.append(nu2); steps.append(m_eff)
+        alphas.append(al); betas.append(be)
+    tr_resid = acc / r
+    logdet = n * c + (tr_sketch + tr_resid)
+    return OracleResult(logdet, tr_sketch, tr_resid, c, lo, hi, alpha, ks, norms,
+                        steps, alphas, betas, basis if keep_basis else None)

@@ -107,3 +107,53 @@ def rademacher(seed: int, n: int, col_begin: int, col_end: int) -> np.ndarray:
         bits = (words[blk, word] >> bit) & np.uint64(1)
         out[:, j] = np.where(bits == 1, -1.0, 1.0)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Gaussian probes (the normal alternative the paper allows for the sketch and
+# probe vectors, Section 2).  Box-Muller transform (Box & Muller, Ann. Math.
+# Stat. 1958) of Philox4x64-10 words: rows 4b..4b+3 of probe column p take the
+# block at counter (b, p, 1, 0) under key (seed, 0) - the third counter word
+# 1 keeps this stream apart from the Rademacher one.  Words (w0, w1) feed rows
+# 4b, 4b+1 and (w2, w3) rows 4b+2, 4b+3; for a pair (wa, wb):
+#   u1 = ((wa >> 11) + 1) / 2^53 in (0, 1],  u2 = (wb >> 11) / 2^53 in [0, 1),
+#   rho = sqrt(-2 log u1),  even row rho cos(2 pi u2),  odd row rho sin(2 pi u2).
+# ---------------------------------------------------------------------------
+def gaussian(seed: int, n: int, col_begin: int, col_end: int) -> np.ndarray:
+    """Probe columns col_begin..col_end-1 as an (n, ncols) float64 array of N(0, 1) draws."""
+    ncols = col_end - col_begin
+    out = np.empty((n, ncols), dtype=np.float64)
+    if n == 0 or ncols == 0:
+        return out
+    nblk = (n + 3) // 4
+    b = np.arange(nblk, dtype=np.uint64)
+    two_pi = 2.0 * np.pi
+    scale = 2.0 ** -53
+    for j in range(ncols):
+        p = col_begin + j
+        w = philox4x64_10_np(b, np.full(nblk, p, dtype=np.uint64),
+                             np.ones(nblk, dtype=np.uint64),
+                             np.zeros(nblk, dtype=np.uint64), seed, 0)
+        col = np.empty(4 * nblk)
+        for pair in range(2):
+            wa, wb = w[2 * pair], w[2 * pair + 1]
+            u1 = ((wa >> np.uint64(11)).astype(np.float64) + 1.0) * scale
+            u2 = (wb >> np.uint64(11)).astype(np.float64) * scale
+            rho = np.sqrt(-2.0 * np.log(u1))
+            col[2 * pair::4] = rho * np.cos(two_pi * u2)
+            col[2 * pair + 1::4] = rho * np.sin(two_pi * u2)
+        out[:, j] = col[:n]
+    return out
+
+
+PROBE_RADEMACHER = 0
+PROBE_GAUSSIAN = 1
+
+
+def probes(seed: int, n: int, col_begin: int, col_end: int, dist: int = PROBE_RADEMACHER) -> np.ndarray:
+    """Probe columns of the given distribution (Rademacher or Gaussian)."""
+    if dist == PROBE_RADEMACHER:
+        return rademacher(seed, n, col_begin, col_end)
+    if dist == PROBE_GAUSSIAN:
+        return gaussian(seed, n, col_begin, col_end)
+    raise ValueError(f"unknown probe distribution {dist}")

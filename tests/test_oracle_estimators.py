@@ -202,3 +202,57 @@ def test_parameter_checks():
         O.oslq(a, 30, 17, 4, 2, seed=0)    # s > n
     with pytest.raises(ValueError):
         O.osa_iop(a, 5, 1, 0, 2, seed=0)   # m = 0
+
+
+# ---------------------------------------------------------------------------
+# So-SLQ (the Section 4 comparator) and Gaussian probes
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dist", [O.PROBE_RADEMACHER, O.PROBE_GAUSSIAN])
+def test_so_slq_captures_a_rank_k_traced_operator(dist):
+    # Q = diag(d) with four eigenvalues below 1 and the rest equal to 1:
+    # lambda_hi = 1, so J = Q, c = 0 and log J has rank 4.  The dominant rank-4
+    # subspace of Y = log(J) S is span(e_1..e_4); the basis runs see exact
+    # Krylov spaces (5 distinct eigenvalues <= m), every residual probe is
+    # projected onto the kernel of log J, and the estimate is exact.  Keeping
+    # the weakest singular directions instead, or a wrong shift, fails.  The
+    # basis vectors carry rounding-level components on the eigenvalue-1
+    # coordinates; tol 1e-8 ends their runs at the exhausted Krylov space.
+    # (The first four rows of the 12 sketch columns have full rank for seed 3.)
+    d = np.concatenate([[0.01, 0.02, 0.05, 0.1], np.ones(36)])
+    a = W.diag_matrix(d)
+    assert np.linalg.matrix_rank(O.probes(3, 40, 0, 12, dist)[:4]) == 4
+    res = O.so_slq(a, 18, 12, 4, 10, 10, 3, tol=1e-8, dist=dist, keep_basis=True)
+    exact = float(np.sum(np.log(d)))
+    assert res.logdet == pytest.approx(exact, rel=1e-10, abs=1e-10)
+    assert abs(res.tr_resid) < 1e-10
+    proj = res.sketch_basis @ res.sketch_basis.T
+    np.testing.assert_allclose(proj[:4, :4], np.eye(4), atol=1e-10)
+    assert np.abs(proj[4:, :]).max() < 1e-10
+
+
+def test_so_slq_full_basis_is_exact():
+    # k = q = n with m = n and full orthogonalisation: the basis spans R^n, the
+    # residual vanishes and every quadratic form is exact
+    a = W.from_dense(W.random_spd_dense(6, seed=4, lo=0.2, hi=6.0))
+    res = O.so_slq(a, 7, 6, 6, 6, 6, 2, dist=O.PROBE_GAUSSIAN)
+    assert res.logdet == pytest.approx(O.dense_logdet(a), rel=1e-10)
+    assert abs(res.tr_resid) < 1e-10
+
+
+def test_so_slq_parameter_checks():
+    a = W.lap2d(8, 0.1)
+    with pytest.raises(ValueError):
+        O.so_slq(a, 10, 4, 5, 8, 2, 0)      # k > q
+    with pytest.raises(ValueError):
+        O.so_slq(a, 4, 4, 2, 8, 2, 0)       # no residual probe
+    with pytest.raises(ValueError):
+        O.so_slq(a, 10, 0, 0, 8, 2, 0)      # no sketch
+
+
+@pytest.mark.parametrize("method", ["oslq", "osa_iop"])
+def test_gaussian_probes_full_sketch_is_exact(method):
+    # Hutch++ exactness does not depend on the probe distribution
+    a = W.from_dense(W.random_spd_dense(8, seed=9, lo=0.3, hi=6.0))
+    fn = getattr(O, method)
+    res = fn(a, 9, 8, 8, 8, 1, dist=O.PROBE_GAUSSIAN)
+    assert res.logdet == pytest.approx(O.dense_logdet(a), rel=1e-9)

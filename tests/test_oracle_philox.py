@@ -70,3 +70,59 @@ def test_rademacher_columns_are_independent_of_range():
     assert np.mean(a != c) > 0.4
     big = rademacher(3, 20000, 0, 4)
     assert abs(big.mean()) < 0.02
+
+
+# ---------------------------------------------------------------------------
+# Gaussian probes: Box-Muller on the Philox stream with counter word 2 = 1.
+# ---------------------------------------------------------------------------
+from oracle.philox import gaussian, probes, PROBE_GAUSSIAN, PROBE_RADEMACHER  # noqa: E402
+
+
+def _numpy_block(seed, b, p, c2):
+    # independent Philox implementation: numpy's generator at counter c - 1
+    c = b | (p << 64) | (c2 << 128)
+    return [int(x) for x in np.random.Philox(counter=c - 1, key=[seed, 0]).random_raw(4)]
+
+
+def test_gaussian_pairs_follow_numpy_philox_words():
+    # every pair of rows (4b + 2j, 4b + 2j + 1) carries radius^2 = -2 log u1 and
+    # angle 2 pi u2 of words (2j, 2j + 1) of the block at counter (b, p, 1, 0):
+    # a wrong counter word, word pairing or sin/cos assignment fails here
+    seed = 0x1234_5678_9ABC
+    g = gaussian(seed, 4 * 7 + 2, 3, 6)  # ragged tail: 30 rows
+    for col in range(3):
+        p = 3 + col
+        for b in range(8):
+            w = _numpy_block(seed, b, p, 1)
+            for pair in range(2):
+                r0 = 4 * b + 2 * pair
+                if r0 + 1 >= g.shape[0]:
+                    continue
+                u1 = ((w[2 * pair] >> 11) + 1) * 2.0**-53
+                u2 = (w[2 * pair + 1] >> 11) * 2.0**-53
+                ze, zo = g[r0, col], g[r0 + 1, col]
+                assert ze * ze + zo * zo == pytest.approx(-2.0 * np.log(u1), rel=1e-13)
+                ang = np.arctan2(zo, ze) % (2 * np.pi)
+                assert ang == pytest.approx(2 * np.pi * u2, abs=1e-12) or \
+                    abs(ang - 2 * np.pi * u2) > 2 * np.pi - 1e-12
+
+
+def test_gaussian_distribution():
+    # N(0, 1): Kolmogorov-Smirnov, moments, no correlation between columns
+    import scipy.stats as st
+    g = gaussian(11, 400_000, 0, 3)
+    for j in range(3):
+        assert st.kstest(g[:, j], "norm").pvalue > 1e-3
+    assert np.all(np.abs(g.mean(axis=0)) < 0.01)
+    assert np.all(np.abs(g.var(axis=0) - 1.0) < 0.01)
+    assert np.all(np.abs(st.kurtosis(g, axis=0, fisher=False) - 3.0) < 0.05)
+    c = np.corrcoef(g.T)
+    assert np.all(np.abs(c - np.eye(3)) < 0.01)
+
+
+def test_gaussian_columns_are_independent_of_range():
+    a = gaussian(5, 1001, 0, 6)
+    b = gaussian(5, 1001, 2, 5)
+    np.testing.assert_array_equal(a[:, 2:5], b)
+    np.testing.assert_array_equal(probes(5, 1001, 2, 5, PROBE_GAUSSIAN), b)
+    np.testing.assert_array_equal(probes(5, 1001, 2, 5, PROBE_RADEMACHER), rademacher(5, 1001, 2, 5))
