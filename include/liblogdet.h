@@ -15,6 +15,10 @@
  *     L x from Arnoldi with incomplete orthogonalisation over a window of k
  *     vectors on Q / gamma, gamma = sqrt(lambda_min lambda_max), and
  *     log(H_m) e1.
+ *   - SLQ (the sketch-rank-0 setting of OSLQ) and So-SLQ, the comparators of
+ *     Section 4: So-SLQ keeps the k dominant left singular vectors of a sketch
+ *     log(J) S (each column from Alg 1) and evaluates both parts by
+ *     Gauss-Lanczos quadrature.
  *
  * All pointers in this header are HOST pointers unless stated otherwise.
  * Every function returns an ld_status; no exception or signal crosses the
@@ -52,7 +56,19 @@ enum {
  * in FP64 and rounded once, round-to-nearest-even. */
 typedef enum { LD_VT_FP64 = 0, LD_VT_FP32 = 1, LD_VT_BF16 = 2 } ld_value_type;
 
-typedef enum { LD_METHOD_OSLQ = 0, LD_METHOD_OSA_IOP = 1 } ld_method;
+typedef enum { LD_METHOD_OSLQ = 0, LD_METHOD_OSA_IOP = 1, LD_METHOD_SO_SLQ = 2 } ld_method;
+/* Distribution of the random sketch and probe columns (Section 2 allows both).
+ * Both come from Philox4x64-10 (Salmon et al., SC'11) under key (seed, 0):
+ *   RADEMACHER: row i, column p: bit i % 64 of word (i / 64) % 4 of the block
+ *               at counter (i / 256, p, 0, 0); a set bit gives -1, else +1.
+ *   GAUSSIAN:   rows 4b..4b+3 of column p from the block at counter
+ *               (b, p, 1, 0) by the Box-Muller transform: words (w0, w1) feed
+ *               rows 4b, 4b+1 and (w2, w3) rows 4b+2, 4b+3; for a pair (wa, wb),
+ *               u1 = ((wa >> 11) + 1) 2^-53, u2 = (wb >> 11) 2^-53,
+ *               rho = sqrt(-2 log u1): even row rho cos(2 pi u2), odd row
+ *               rho sin(2 pi u2) (device log/sqrt/sin/cos, not bit-exact with
+ *               other math libraries). */
+typedef enum { LD_PROBE_RADEMACHER = 0, LD_PROBE_GAUSSIAN = 1 } ld_probe_dist;
 
 /* LD_PREC_FP64: every vector, product and reduction in FP64.
  * LD_PREC_MIXED: Krylov vectors and sparse products in FP32 (matrix values
@@ -80,14 +96,26 @@ typedef struct {
   int32_t precision;         /* ld_precision                                     */
   int32_t n_probes;          /* s + r: sketch columns plus residual probes       */
   int32_t sketch_rank;       /* s, 0 <= s <= min(n, 256); s = 0 is plain SLQ /
-                                Hutchinson                                       */
+                                Hutchinson.  So-SLQ: the sketch width q,
+                                1 <= q <= min(n, 64)                             */
   int32_t krylov_steps;      /* m, 1 <= m <= min(n, 512): mat-vecs per Krylov run */
   int32_t iop_window;        /* k >= 1: orthogonalise against the k newest basis
                                 vectors (the paper's IOP uses k = 2; k >= m is
                                 full re-orthogonalisation)                      */
-  uint64_t seed;             /* Rademacher probes: Philox4x64-10, key (seed, 0),
-                                counter (row / 256, column, 0, 0)                */
+  uint64_t seed;             /* key of the probe generator (see ld_probe_dist)   */
   double tol;                /* stop a run when h_{t+1,t} < tol (<= 0 -> 1e-10) */
+  int32_t probe_dist;        /* ld_probe_dist of every random column             */
+  int32_t subspace_rank;     /* So-SLQ: kept rank k, 1 <= k <= q (0 -> min(10, q));
+                                must be 0 for the other methods                  */
+  double adapt_tol;          /* > 0: adaptive Krylov dimension (OSLQ, SLQ,
+                                So-SLQ): every adapt_every steps each run's
+                                Gauss quadrature value K_t is formed, and the
+                                run stops at step t once
+                                |K_t - K_{t - adapt_every}| <= adapt_tol |K_t|;
+                                0 -> every run takes krylov_steps (or stops at
+                                h < tol).  Must be 0 for OSA-IOP.                */
+  int32_t adapt_every;       /* steps between convergence checks (0 -> 5)        */
+  int32_t reserved;          /* must be 0                                        */
 } ld_params;
 
 typedef struct {
@@ -112,15 +140,18 @@ typedef struct {
  * s sketch-basis runs first, then the r residual runs (OSA-IOP's sketch-image
  * runs are not reported). */
 typedef struct {
-  double* probe_K;           /* [n_probes] quadrature value of the run: the
+  double* probe_K;           /* [runs] quadrature value of the run: the
                                 estimate of x^T (log Q - c I) x / ||x||^2        */
-  double* probe_norm2;       /* [n_probes] ||x||^2 of the run's start vector    */
-  int32_t* probe_steps;      /* [n_probes] effective Krylov dimension            */
-  double* tri_alpha;         /* [n_probes * krylov_steps] h_{t,t}, row-major     */
-  double* tri_beta;          /* [n_probes * krylov_steps] h_{t+1,t}              */
-  double* sketch_basis;      /* [n * sketch_rank] A, row-major (row i, column j
-                                at i*sketch_rank + j)                            */
+  double* probe_norm2;       /* [runs] ||x||^2 of the run's start vector        */
+  int32_t* probe_steps;      /* [runs] effective Krylov dimension                */
+  double* tri_alpha;         /* [runs * krylov_steps] h_{t,t}, row-major         */
+  double* tri_beta;          /* [runs * krylov_steps] h_{t+1,t}                  */
+  double* sketch_basis;      /* [n * b] the basis A, row-major (row i, column j
+                                at i*b + j)                                      */
 } ld_detail;
+/* In ld_detail, runs = n_probes and b = sketch_rank for OSLQ and OSA-IOP;
+ * runs = subspace_rank + n_probes - sketch_rank and b = subspace_rank for
+ * So-SLQ (the q sketch-image runs are not reported). */
 
 /* Context: owns a HIP stream (unless one is supplied), a device workspace and
  * the serving scheduler.  Returns LD_E_DEVICE when the device is absent. */
@@ -200,6 +231,9 @@ ld_status ld_profile_query(ld_ctx* ctx, uint32_t family, int64_t* launches, doub
  * col_begin)], row-major. */
 ld_status ld_debug_rademacher(ld_ctx* ctx, uint64_t seed, int64_t n,
                               int32_t col_begin, int32_t col_end, double* out);
+/* Test hook: as ld_debug_rademacher for either distribution (ld_probe_dist). */
+ld_status ld_debug_probes(ld_ctx* ctx, uint64_t seed, int64_t n, int32_t col_begin,
+                          int32_t col_end, int32_t dist, double* out);
 
 /* Calibration hook: copies `bytes` (rounded down to 16) between two device
  * buffers with a plain 16-byte-per-lane copy kernel, `reps` times, and

@@ -103,11 +103,12 @@ __global__ __launch_bounds__(kThreads) void k_chol_inv(int s, const double* __re
   if (t == 0) *flag = 0;
 }
 
-// Y[row][:] <- Y[row][:] Rinv (Rinv upper triangular), 16 rows per block,
-// output columns in chunks of 16; the row tile stays in LDS so the update is
-// in place.
-__global__ __launch_bounds__(kThreads) void k_trsm_rows(int64_t n, double* __restrict__ Y, int ld,
-                                                       int s, const double* __restrict__ Rinv) {
+// Y[row][j] <- sum_i Y[row][i] M[i][j] for j < sout (M is s x sout, row-major;
+// with UPPER only i <= j, M upper triangular), 16 rows per block, output
+// columns in chunks of 16; the row tile stays in LDS so the update is in place.
+template <bool UPPER>
+__global__ __launch_bounds__(kThreads) void k_rows_mat(int64_t n, double* __restrict__ Y, int ld,
+                                                      int s, const double* __restrict__ M, int sout) {
   extern __shared__ double sm[];
   double* sy = sm;            // [16][s]
   double* sr = sm + 16 * s;   // [s][16]
@@ -118,21 +119,163 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows(int64_t n, double* __res
     const int rr = e / s, c = e % s;
     sy[e] = (rr < nr) ? Y[(size_t)(row0 + rr) * ld + c] : 0.0;
   }
-  for (int j0 = 0; j0 < s; j0 += 16) {
-    const int nc = min(16, s - j0);
+  for (int j0 = 0; j0 < sout; j0 += 16) {
+    const int nc = min(16, sout - j0);
     __syncthreads();
     for (int e = t; e < s * 16; e += kThreads) {
       const int i = e / 16, jj = e % 16;
-      sr[e] = (jj < nc) ? Rinv[(size_t)i * s + j0 + jj] : 0.0;
+      sr[e] = (jj < nc) ? M[(size_t)i * sout + j0 + jj] : 0.0;
     }
     __syncthreads();
     const int rr = t / 16, jj = t % 16;
     if (rr < nr && jj < nc) {
       const int j = j0 + jj;
+      const int iend = UPPER ? j + 1 : s;
       double acc = 0.0;
-      for (int i = 0; i <= j; ++i) acc = fma(sy[rr * s + i], sr[i * 16 + jj], acc);
+      for (int i = 0; i < iend; ++i) acc = fma(sy[rr * s + i], sr[i * 16 + jj], acc);
       Y[(size_t)(row0 + rr) * ld + j] = acc;
     }
+  }
+}
+
+// Dominant rank-k left singular subspace of Y from its Gram matrix
+// G = Y^T Y (q x q): the eigenvectors v_j of G for its k largest eigenvalues
+// lambda_j, returned as U[i*k + j] = v_j[i] / sqrt(lambda_j), so that Y U has
+// orthonormal columns spanning the k dominant left singular vectors of Y (in
+// exact arithmetic; a CholQR pass on Y U removes the rounding).  This needs
+// no full-rank factorisation of Y, so a sketch of rank between k and q is
+// fine.  Cyclic Jacobi (Golub & Van Loan, the symmetric Schur rotation) with
+// the round-robin ordering: in each round the q/2 rotations act on disjoint
+// index pairs and are applied together, rows first, then columns and the
+// eigenvector matrix V.  Sweeps stop when the off-diagonal mass falls below
+// 1e-30 of the diagonal mass (at most 60).  Eigenvalues are taken in
+// descending order, ties by index; each v_j has its largest-magnitude
+// component (first one on ties) positive.  flag = 1 when the sweeps did not
+// converge or lambda_k <= 1e-13 lambda_1 (the sketch has rank below k).
+constexpr int kEigMax = kSoSlqMaxSketch;
+
+__global__ __launch_bounds__(kThreads) void k_subspace_eig(int q, int k, const double* __restrict__ G,
+                                                          double* __restrict__ U,
+                                                          int* __restrict__ flag) {
+  __shared__ double M[kEigMax * kEigMax];
+  __shared__ double V[kEigMax * kEigMax];
+  __shared__ double cs[kEigMax / 2], sn[kEigMax / 2];
+  __shared__ int pa[kEigMax / 2], pb[kEigMax / 2];
+  __shared__ double red[2][kThreads];
+  __shared__ int order[kEigMax];
+  const int t = threadIdx.x;
+  // symmetrised copy of G (the Gram sums of (i, j) and (j, i) may round apart)
+  for (int e = t; e < q * q; e += kThreads) {
+    const int i = e / q, j = e % q;
+    M[e] = 0.5 * (G[i * q + j] + G[j * q + i]);
+    V[e] = (i == j) ? 1.0 : 0.0;
+  }
+  const int qq = q + (q & 1);       // even number of players; index q is a dummy
+  const int np = qq / 2;
+  bool converged = q == 1;
+  for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
+    for (int round = 0; round < qq - 1; ++round) {
+      // pairs of the round (circle method: qq-1 players rotate, one is fixed)
+      __syncthreads();
+      if (t < np) {
+        int a, b;
+        if (t == 0) {
+          a = round;
+          b = qq - 1;
+        } else {
+          a = (round + t) % (qq - 1);
+          b = (round - t + (qq - 1)) % (qq - 1);
+        }
+        const int p = min(a, b), r = max(a, b);
+        double c = 1.0, s = 0.0;
+        if (r < q) {
+          const double app = M[p * q + p], arr = M[r * q + r], apr = M[p * q + r];
+          if (apr != 0.0) {
+            const double tau = (arr - app) / (2.0 * apr);
+            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+        }
+        pa[t] = p;
+        pb[t] = r;
+        cs[t] = c;
+        sn[t] = s;
+      }
+      __syncthreads();
+      // rows p, r of every pair: M <- J^T M
+      for (int e = t; e < np * q; e += kThreads) {
+        const int w = e / q, j = e % q;
+        const int p = pa[w], r = pb[w];
+        if (r >= q || sn[w] == 0.0) continue;
+        const double mp = M[p * q + j], mr = M[r * q + j];
+        M[p * q + j] = cs[w] * mp - sn[w] * mr;
+        M[r * q + j] = sn[w] * mp + cs[w] * mr;
+      }
+      __syncthreads();
+      // columns p, r: M <- M J, V <- V J
+      for (int e = t; e < np * q; e += kThreads) {
+        const int w = e / q, i = e % q;
+        const int p = pa[w], r = pb[w];
+        if (r >= q || sn[w] == 0.0) continue;
+        const double mp = M[i * q + p], mr = M[i * q + r];
+        M[i * q + p] = cs[w] * mp - sn[w] * mr;
+        M[i * q + r] = sn[w] * mp + cs[w] * mr;
+        const double vp = V[i * q + p], vr = V[i * q + r];
+        V[i * q + p] = cs[w] * vp - sn[w] * vr;
+        V[i * q + r] = sn[w] * vp + cs[w] * vr;
+      }
+    }
+    __syncthreads();
+    double off = 0.0, dia = 0.0;
+    for (int e = t; e < q * q; e += kThreads) {
+      const double v = M[e] * M[e];
+      if (e / q == e % q) dia += v; else off += v;
+    }
+    red[0][t] = off;
+    red[1][t] = dia;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+      if (t < w) {
+        red[0][t] += red[0][t + w];
+        red[1][t] += red[1][t + w];
+      }
+      __syncthreads();
+    }
+    converged = red[0][0] <= 1e-30 * red[1][0];
+    __syncthreads();
+  }
+  if (t == 0) {
+    // k largest eigenvalues, descending, ties by index
+    for (int i = 0; i < q; ++i) order[i] = i;
+    for (int i = 0; i < k; ++i) {
+      int best = i;
+      for (int j = i + 1; j < q; ++j) {
+        const double vj = M[order[j] * q + order[j]], vb = M[order[best] * q + order[best]];
+        if (vj > vb || (vj == vb && order[j] < order[best])) best = j;
+      }
+      const int tmp = order[i];
+      order[i] = order[best];
+      order[best] = tmp;
+    }
+    const double l1 = M[order[0] * q + order[0]], lk = M[order[k - 1] * q + order[k - 1]];
+    *flag = (converged && lk > 1e-13 * l1 && lk > 0.0) ? 0 : 1;
+  }
+  __syncthreads();
+  for (int j = t; j < k; j += kThreads) {
+    const int col = order[j];
+    int imax = 0;
+    double vmax = -1.0;
+    for (int i = 0; i < q; ++i) {
+      const double a = fabs(V[i * q + col]);
+      if (a > vmax) {
+        vmax = a;
+        imax = i;
+      }
+    }
+    const double lam = M[col * q + col];
+    const double sc = (V[imax * q + col] >= 0.0 ? 1.0 : -1.0) / sqrt(lam > 0.0 ? lam : 1.0);
+    for (int i = 0; i < q; ++i) U[i * k + j] = sc * V[i * q + col];
   }
 }
 
@@ -259,8 +402,24 @@ hipError_t launch_chol_inv(hipStream_t st, int s, const double* G, double* work,
 hipError_t launch_trsm_rows(hipStream_t st, int64_t n, double* Y, int ld, int s, const double* Rinv) {
   if (n < 1 || s < 1 || s > 256 || ld < s || !Y || !Rinv) return hipErrorInvalidValue;
   const size_t lds = (size_t)(16 * s + 16 * s) * sizeof(double);
-  hipLaunchKernelGGL(k_trsm_rows, dim3((unsigned)((n + 15) / 16)), dim3(kThreads), lds, st, n, Y, ld,
-                     s, Rinv);
+  hipLaunchKernelGGL(k_rows_mat<true>, dim3((unsigned)((n + 15) / 16)), dim3(kThreads), lds, st, n, Y,
+                     ld, s, Rinv, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_mat(hipStream_t st, int64_t n, double* Y, int ld, int s, const double* M,
+                           int sout) {
+  if (n < 1 || s < 1 || s > 256 || sout < 1 || sout > s || ld < s || !Y || !M)
+    return hipErrorInvalidValue;
+  const size_t lds = (size_t)(16 * s + 16 * s) * sizeof(double);
+  hipLaunchKernelGGL(k_rows_mat<false>, dim3((unsigned)((n + 15) / 16)), dim3(kThreads), lds, st, n, Y,
+                     ld, s, M, sout);
+  return hipGetLastError();
+}
+
+hipError_t launch_subspace_eig(hipStream_t st, int q, int k, const double* G, double* U, int* flag) {
+  if (q < 1 || q > kEigMax || k < 1 || k > q || !G || !U || !flag) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_subspace_eig, dim3(1), dim3(kThreads), 0, st, q, k, G, U, flag);
   return hipGetLastError();
 }
 

@@ -63,6 +63,39 @@ __global__ __launch_bounds__(kThreads) void k_rademacher(uint64_t seed, int64_t 
   }
 }
 
+// Gaussian probe columns: Box-Muller on Philox4x64-10 words.  Thread (b, j)
+// takes the block at counter (b, pbase + cbase + j, 1, 0) and writes rows
+// 4b..4b+3 of column j: words (w0, w1) give rows 4b, 4b+1 and (w2, w3) rows
+// 4b+2, 4b+3, each pair as u1 = ((wa >> 11) + 1) 2^-53 in (0, 1],
+// u2 = (wb >> 11) 2^-53, rho = sqrt(-2 log u1), rows rho cos(2 pi u2) and
+// rho sin(2 pi u2).  Columns are the fastest thread index so that a wave
+// writes contiguous row segments.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gaussian(uint64_t seed, int64_t n, int pbase,
+                                                      int ncols, int nvalid, T* __restrict__ X,
+                                                      int ld, int col0) {
+  const int j = (int)(threadIdx.x % 64) + 64 * (int)blockIdx.y;
+  const int64_t b = (int64_t)blockIdx.x * (kThreads / 64) + threadIdx.x / 64;
+  if (j >= ncols || 4 * b >= n) return;
+  uint64_t c0 = (uint64_t)b, c1 = (uint64_t)(pbase + j), c2 = 1, c3 = 0;
+  philox4x64_10(c0, c1, c2, c3, seed, 0ull);
+  const uint64_t w[4] = {c0, c1, c2, c3};
+  constexpr double kTwoPi = 6.283185307179586;
+  constexpr double kInv53 = 1.0 / 9007199254740992.0;  // 2^-53
+#pragma unroll
+  for (int pair = 0; pair < 2; ++pair) {
+    const double u1 = (double)((w[2 * pair] >> 11) + 1) * kInv53;
+    const double u2 = (double)(w[2 * pair + 1] >> 11) * kInv53;
+    const double rho = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(kTwoPi * u2, &sn, &cs);
+    const int64_t r0 = 4 * b + 2 * pair;
+    const bool valid = j < nvalid;
+    if (r0 < n) X[(size_t)r0 * ld + col0 + j] = valid ? T(rho * cs) : T(0);
+    if (r0 + 1 < n) X[(size_t)(r0 + 1) * ld + col0 + j] = valid ? T(rho * sn) : T(0);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Row mapping shared by the streaming kernels.  Rows are swept in chunks of
 // RPI = 256 / L consecutive rows; block b takes chunks b, b + nblk, ... so the
@@ -662,6 +695,27 @@ hipError_t launch_rademacher(hipStream_t st, uint64_t seed, int64_t n, int pbase
                        nvalid, static_cast<double*>(X), ld, col0);
   else if (xbytes == 4)
     hipLaunchKernelGGL(k_rademacher<float>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
+                       nvalid, static_cast<float*>(X), ld, col0);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_probes(hipStream_t st, int dist, uint64_t seed, int64_t n, int pbase, int ncols,
+                         int nvalid, void* X, int xbytes, int ld, int col0) {
+  if (dist == PROBE_RADEMACHER)
+    return launch_rademacher(st, seed, n, pbase, ncols, nvalid, X, xbytes, ld, col0);
+  if (dist != PROBE_GAUSSIAN) return hipErrorInvalidValue;
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  if (!X || col0 < 0 || col0 + ncols > ld || pbase < 0 || nvalid < 0 || nvalid > ncols)
+    return hipErrorInvalidValue;
+  const int64_t nb4 = (n + 3) / 4;
+  dim3 grid((unsigned)((nb4 + kThreads / 64 - 1) / (kThreads / 64)), (unsigned)((ncols + 63) / 64));
+  if (xbytes == 8)
+    hipLaunchKernelGGL(k_gaussian<double>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
+                       nvalid, static_cast<double*>(X), ld, col0);
+  else if (xbytes == 4)
+    hipLaunchKernelGGL(k_gaussian<float>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
                        nvalid, static_cast<float*>(X), ld, col0);
   else
     return hipErrorInvalidValue;

@@ -16,6 +16,7 @@ enum ValueType : int { VT_F64 = 0, VT_F32 = 1, VT_BF16 = 2 };
 constexpr int kMaxBlocks = 2048;  // 256 CUs x 8 resident 256-thread blocks
 constexpr int kMaxC = 4;          // 16-byte chunks per lane
 constexpr int kMaxLd = 256;       // probe-block row length (columns) of the Krylov kernels
+constexpr int kSoSlqMaxSketch = 48;  // So-SLQ sketch width (Jacobi eigen-solve in LDS)
 
 // Row partition of an [n][ld] probe block.  The streaming kernels sweep
 // chunks of 256/L consecutive rows, block b taking chunks b, b+nblk, ...; the
@@ -43,6 +44,11 @@ Geom make_geom(int64_t n, int ld, int xbytes);
 // then zeros up to ncols (padding).
 hipError_t launch_rademacher(hipStream_t st, uint64_t seed, int64_t n, int pbase, int ncols,
                              int nvalid, void* X, int xbytes, int ld, int col0);
+// Same for either distribution (PROBE_RADEMACHER or PROBE_GAUSSIAN).
+constexpr int PROBE_RADEMACHER = 0;
+constexpr int PROBE_GAUSSIAN = 1;
+hipError_t launch_probes(hipStream_t st, int dist, uint64_t seed, int64_t n, int pbase, int ncols,
+                         int nvalid, void* X, int xbytes, int ld, int col0);
 
 // W = opscale * (Q X) * diag(xmult); X, W share ld/type.  With nf (<= 2)
 // fused vectors: part[voff+v][col][block] = mult_v[col] * sum x_v w, where
@@ -114,6 +120,13 @@ hipError_t launch_gemm_tn(hipStream_t st, const Geom& g, const double* Xa, int l
 hipError_t launch_chol_inv(hipStream_t st, int s, const double* G, double* work, double* Rinv,
                            int* flag);
 hipError_t launch_trsm_rows(hipStream_t st, int64_t n, double* Y, int ld, int s, const double* Rinv);
+// Y[row][j] <- sum_{i < s} Y[row][i] M[i][j], j < sout <= s (M is s x sout), in place.
+hipError_t launch_rows_mat(hipStream_t st, int64_t n, double* Y, int ld, int s, const double* M,
+                           int sout);
+// U (q x k, row-major): v_j / sqrt(lambda_j) for the eigenpairs of the Gram
+// matrix G (q x q, q <= 48) with the k largest eigenvalues; flag = 1 when
+// Jacobi did not converge or lambda_k <= 1e-13 lambda_1.
+hipError_t launch_subspace_eig(hipStream_t st, int q, int k, const double* G, double* U, int* flag);
 // X0[row][i] = A[row][i] (i < s); X0[row][s+j] = G[row][j] - sum_i A[row][i] P[i][j];
 // part[col][b] = sum over rows of b of X0[row][col]^2 (FP64 values).
 hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int lda, int s,

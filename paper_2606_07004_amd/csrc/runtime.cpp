@@ -188,33 +188,55 @@ ld_status Run::validate() {
   n_ = a_->n;
   s_ = p_.sketch_rank;
   r_ = p_.n_probes - p_.sketch_rank;
-  B_ = p_.n_probes;
   m_ = p_.krylov_steps;
   k_ = p_.iop_window;
   tol_ = p_.tol > 0 ? p_.tol : 1e-10;
-  if (p_.method != LD_METHOD_OSLQ && p_.method != LD_METHOD_OSA_IOP)
+  if (p_.method != LD_METHOD_OSLQ && p_.method != LD_METHOD_OSA_IOP &&
+      p_.method != LD_METHOD_SO_SLQ)
     return set_error(LD_E_INVALID_ARG, "unknown method");
   if (p_.precision != LD_PREC_FP64 && p_.precision != LD_PREC_MIXED)
     return set_error(LD_E_INVALID_ARG, "unknown precision");
-  if (s_ < 0 || s_ > 256 || (int64_t)s_ > n_)
-    return set_error(LD_E_INVALID_ARG, "sketch_rank must satisfy 0 <= s <= min(n, 256)");
+  if (p_.probe_dist != LD_PROBE_RADEMACHER && p_.probe_dist != LD_PROBE_GAUSSIAN)
+    return set_error(LD_E_INVALID_ARG, "unknown probe distribution");
+  if (p_.reserved != 0) return set_error(LD_E_INVALID_ARG, "reserved field must be 0");
+  if (!(p_.adapt_tol >= 0.0) || !std::isfinite(p_.adapt_tol) || p_.adapt_every < 0)
+    return set_error(LD_E_INVALID_ARG, "adapt_tol must be finite and >= 0, adapt_every >= 0");
+  if (p_.adapt_tol > 0.0 && p_.method == LD_METHOD_OSA_IOP)
+    return set_error(LD_E_INVALID_ARG, "the adaptive Krylov dimension applies to the Gauss "
+                                       "quadrature methods (OSLQ, SLQ, So-SLQ)");
+  if (p_.method == LD_METHOD_SO_SLQ) {
+    if (s_ < 1 || s_ > kSoSlqMaxSketch || (int64_t)s_ > n_)
+      return set_error(LD_E_INVALID_ARG, "So-SLQ: sketch_rank q must satisfy 1 <= q <= min(n, 48)");
+    kb_ = p_.subspace_rank > 0 ? p_.subspace_rank : std::min(10, s_);
+    if (kb_ > s_) return set_error(LD_E_INVALID_ARG, "So-SLQ: subspace_rank must be <= sketch_rank");
+  } else {
+    if (p_.subspace_rank != 0)
+      return set_error(LD_E_INVALID_ARG, "subspace_rank applies to So-SLQ only");
+    if (s_ < 0 || s_ > 256 || (int64_t)s_ > n_)
+      return set_error(LD_E_INVALID_ARG, "sketch_rank must satisfy 0 <= s <= min(n, 256)");
+    kb_ = s_;
+  }
   if (r_ < 1) return set_error(LD_E_INVALID_ARG, "n_probes - sketch_rank must be >= 1");
+  B_ = kb_ + r_;
   if (m_ < 1 || m_ > 512 || (int64_t)m_ > n_)
     return set_error(LD_E_INVALID_ARG, "krylov_steps must satisfy 1 <= m <= min(n, 512)");
   if (k_ < 1) return set_error(LD_E_INVALID_ARG, "iop_window must be >= 1");
+  adapt_every_ = p_.adapt_every > 0 ? p_.adapt_every : 5;
   mixed_ = p_.precision == LD_PREC_MIXED;
   xb_ = mixed_ ? 4 : 8;
-  if (B_ > (mixed_ ? 256 : 128))
+  if (std::max(B_, s_) > (mixed_ ? 256 : 128))
     return set_error(LD_E_INVALID_ARG, mixed_ ? "n_probes must be <= 256 in mixed precision"
                                               : "n_probes must be <= 128 in FP64");
   lds_ = round4(std::max(s_, 1));
   ldr_ = round4(r_);
   ldB_ = round4(B_);
   ld1_ = lds_;
+  ldx_ = std::max(ldB_, ld1_);
   lo_ = a_->lo;
   hi_ = a_->hi;
-  if (p_.method == LD_METHOD_OSLQ) {
-    // J = Q / lambda_hi and c = log(lambda_hi) when lambda_lo < 1, else J = Q, c = 0
+  if (p_.method != LD_METHOD_OSA_IOP) {
+    // OSLQ and its comparators: J = Q / lambda_hi and c = log(lambda_hi) when
+    // lambda_lo < 1, else J = Q, c = 0
     if (lo_ < 1.0) {
       scale_ = hi_;
       c_ = std::log(hi_);
@@ -252,30 +274,32 @@ size_t Run::layout(char* base) {
     nslots_ = std::min(k_, m_) + 1;
     slot_bytes = (size_t)nslots_ * n * ldB_ * xb_;
   } else {
-    nslots_ = std::max(m_ + 1, std::min(k_, m_) + 2);
-    slot_bytes = std::max((size_t)(m_ + 1) * n * ld1_ * xb_,
-                          (size_t)(std::min(k_, m_) + 2) * n * ldB_ * xb_);
+    // phase 0 keeps the sketch runs' whole basis; phase 1 is a ring (OSA-IOP
+    // also keeps v1)
+    const int ring = std::min(k_, m_) + (p_.method == LD_METHOD_OSA_IOP ? 2 : 1);
+    nslots_ = std::max(m_ + 1, ring);
+    slot_bytes = std::max((size_t)(m_ + 1) * n * ld1_ * xb_, (size_t)ring * n * ldB_ * xb_);
   }
   slots_ = take(slot_bytes);
-  mult_ = static_cast<double*>(take((size_t)nslots_ * std::max(ldB_, ld1_) * 8));
+  mult_ = static_cast<double*>(take((size_t)nslots_ * ldx_ * 8));
   S_ = static_cast<double*>(take(n * std::max(lds_, ldr_) * 8));
   G_ = S_;
   Y_ = s_ > 0 ? static_cast<double*>(take(n * lds_ * 8)) : nullptr;
   // streaming kernels: fused product dots (2 rows of ld) and further dots
   // launches (up to 4 rows of ld) in separate regions, kMaxBlocks each
-  size_t pe = (size_t)kMaxBlocks * (2 + 4) * std::max(ldB_, ld1_);
+  size_t pe = (size_t)kMaxBlocks * (2 + 4) * ldx_;
   if (s_ > 0) pe = std::max(pe, (size_t)gS_.nblk * s_ * std::max(s_, r_));
   part_elems_ = pe;
   part_ = static_cast<double*>(take(pe * 8));
-  dwin_ = static_cast<double*>(take((size_t)nvmax * ldB_ * 8));
-  nsr_ = static_cast<double*>(take((size_t)2 * ldB_ * 8));
-  norm2_ = static_cast<double*>(take((size_t)ldB_ * 8));
-  K_ = static_cast<double*>(take((size_t)ldB_ * 8));
-  H_ = static_cast<double*>(take((size_t)ldB_ * (m_ + 1) * m_ * 8));
-  gq_ = static_cast<double*>(take((size_t)ldB_ * (m_ + 1) * 8));
+  dwin_ = static_cast<double*>(take((size_t)nvmax * ldx_ * 8));
+  nsr_ = static_cast<double*>(take((size_t)2 * ldx_ * 8));
+  norm2_ = static_cast<double*>(take((size_t)ldx_ * 8));
+  K_ = static_cast<double*>(take((size_t)ldx_ * 8));
+  H_ = static_cast<double*>(take((size_t)ldx_ * (m_ + 1) * m_ * 8));
+  gq_ = static_cast<double*>(take((size_t)ldx_ * (m_ + 1) * 8));
   wstride_ = hess_log_wstride(m_);
-  work_ = (p_.method == LD_METHOD_OSA_IOP)
-              ? static_cast<double*>(take((size_t)ldB_ * (size_t)wstride_ * 8))
+  work_ = (p_.method != LD_METHOD_OSLQ)
+              ? static_cast<double*>(take((size_t)ldx_ * (size_t)wstride_ * 8))
               : nullptr;
   if (s_ > 0) {
     gram_ = static_cast<double*>(take((size_t)s_ * s_ * 8));
@@ -283,14 +307,15 @@ size_t Run::layout(char* base) {
     rinv_ = static_cast<double*>(take((size_t)s_ * s_ * 8));
     pmat_ = static_cast<double*>(take((size_t)s_ * r_ * 8));
   }
+  if (p_.method == LD_METHOD_SO_SLQ) umat_ = static_cast<double*>(take((size_t)s_ * kb_ * 8));
   ell_ = static_cast<double*>(take((size_t)ld1_ * m_ * 8));
   coefs_ = static_cast<double*>(take((size_t)(m_ + 1) * ld1_ * 8));
-  meff_ = static_cast<int*>(take((size_t)ldB_ * 4));
-  active_ = static_cast<int*>(take((size_t)ldB_ * 4));
-  flags_ = static_cast<int*>(take((size_t)ldB_ * 4));
+  meff_ = static_cast<int*>(take((size_t)ldx_ * 4));
+  active_ = static_cast<int*>(take((size_t)ldx_ * 4));
+  flags_ = static_cast<int*>(take((size_t)ldx_ * 4));
   dflag_ = static_cast<int*>(take(16));
-  need_ = static_cast<int*>(take((size_t)ldB_ * 4));
-  meff0_ = static_cast<int*>(take((size_t)ldB_ * 4));
+  need_ = static_cast<int*>(take((size_t)ldx_ * 4));
+  meff0_ = static_cast<int*>(take((size_t)ldx_ * 4));
   return off;
 }
 
@@ -317,14 +342,15 @@ double Run::spmm_bytes(int ld, int xbytes) const {
 // R = R2 R1 upper triangular with a positive diagonal (the QR convention of
 // the oracle).  dflag_[0] is set when the Gram matrix is not numerically
 // positive definite.
-ld_status Run::sketch_qr(hipStream_t st, double* Y) {
+ld_status Run::sketch_qr(hipStream_t st, double* Y, int cols) {
   for (int pass = 0; pass < 2; ++pass) {
-    LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * s_ * 8,
-              launch_gemm_tn(st, gS_, Y, lds_, s_, Y, lds_, s_, part_));
-    LD_LAUNCH(LD_PROF_REDUCE, (double)gS_.nblk * s_ * s_ * 8,
-              launch_reduce(st, part_, gS_.nblk, s_ * s_, gram_));
-    LD_LAUNCH(LD_PROF_SKETCH, 0, launch_chol_inv(st, s_, gram_, rfac_, rinv_, dflag_ + pass));
-    LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * s_ * 16, launch_trsm_rows(st, n_, Y, lds_, s_, rinv_));
+    LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * cols * 8,
+              launch_gemm_tn(st, gS_, Y, lds_, cols, Y, lds_, cols, part_));
+    LD_LAUNCH(LD_PROF_REDUCE, (double)gS_.nblk * cols * cols * 8,
+              launch_reduce(st, part_, gS_.nblk, cols * cols, gram_));
+    LD_LAUNCH(LD_PROF_SKETCH, 0, launch_chol_inv(st, cols, gram_, rfac_, rinv_, dflag_ + pass));
+    LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * cols * 16,
+              launch_trsm_rows(st, n_, Y, lds_, cols, rinv_));
   }
   return LD_OK;
 }
@@ -333,7 +359,7 @@ ld_status Run::sketch_qr(hipStream_t st, double* Y) {
 // per-run start state.
 ld_status Run::start_block(hipStream_t st, const double* A, int s_cols) {
   LD_LAUNCH(LD_PROF_PROBES, (double)n_ * ldr_ * 8,
-            launch_rademacher(st, p_.seed, n_, s_, ldr_, r_, G_, 8, ldr_, 0));
+            launch_probes(st, p_.probe_dist, p_.seed, n_, s_, ldr_, r_, G_, 8, ldr_, 0));
   if (s_cols > 0) {
     LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * (s_cols + r_) * 8,
               launch_gemm_tn(st, gS_, A, lds_, s_cols, G_, ldr_, r_, part_));
@@ -352,7 +378,7 @@ ld_status Run::begin_krylov(int phase) {
   kphase_ = phase;
   t_ = 0;
   sym_ready_ = false;
-  if (p_.method == LD_METHOD_OSLQ) {
+  if (p_.method == LD_METHOD_OSLQ || (p_.method == LD_METHOD_SO_SLQ && phase == 1)) {
     kB_ = B_;
     kld_ = ldB_;
     kg_ = gB_;
@@ -392,11 +418,11 @@ ld_status Run::run_prologue(hipStream_t st) {
     if (s_ > 0) {
       // Y = J S, J = Q / alpha (Alg 3: sketch from J S, not from f(J) S)
       LD_LAUNCH(LD_PROF_PROBES, (double)n_ * lds_ * 8,
-                launch_rademacher(st, p_.seed, n_, 0, lds_, s_, S_, 8, lds_, 0));
+                launch_probes(st, p_.probe_dist, p_.seed, n_, 0, lds_, s_, S_, 8, lds_, 0));
       LD_LAUNCH(LD_PROF_SPMM, spmm_bytes(lds_, 8),
                 launch_spmm(st, gS_, a_->rp, a_->ci, vals_sketch, vt_sketch, S_, Y_, nullptr,
                             opscale_, nullptr, 0, 0, nullptr, nullptr));
-      ld_status rc = sketch_qr(st, Y_);
+      ld_status rc = sketch_qr(st, Y_, s_);
       if (rc != LD_OK) return rc;
     }
     ld_status rc = start_block(st, Y_, s_);
@@ -407,7 +433,7 @@ ld_status Run::run_prologue(hipStream_t st) {
   // OSA-IOP: the sketch-image runs start from S itself (phase 0, basis kept)
   if (s_ > 0) {
     LD_LAUNCH(LD_PROF_PROBES, (double)n_ * ld1_ * xb_,
-              launch_rademacher(st, p_.seed, n_, 0, ld1_, s_, slots_, xb_, ld1_, 0));
+              launch_probes(st, p_.probe_dist, p_.seed, n_, 0, ld1_, s_, slots_, xb_, ld1_, 0));
     VecSet vs{};
     vs.x[0] = slots_;
     int nb = 0;
@@ -416,13 +442,13 @@ ld_status Run::run_prologue(hipStream_t st) {
     LD_LAUNCH(LD_PROF_SMALL, (double)nb * ld1_ * 8,
               launch_start_finish(st, s_, ld1_, part_, nb, norm2_, mult_, active_, meff_, nullptr,
                                   0));
-    LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldB_ * (m_ + 1) * m_ * 8, st));
+    LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldx_ * (m_ + 1) * m_ * 8, st));
     begin_krylov(0);
     return LD_OK;
   }
   ld_status rc = start_block(st, nullptr, 0);
   if (rc != LD_OK) return rc;
-  LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldB_ * (m_ + 1) * m_ * 8, st));
+  LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldx_ * (m_ + 1) * m_ * 8, st));
   begin_krylov(1);
   return LD_OK;
 }
@@ -442,11 +468,23 @@ ld_status Run::osa_sketch_combine(hipStream_t st) {
             launch_osa_coef(st, s_, ld1_, m_, ell_, mult_, norm2_, meff_, shift, coefs_));
   LD_LAUNCH(LD_PROF_SKETCH, (double)m_ * n_ * ld1_ * xb_ + (double)n_ * lds_ * 8,
             launch_combine(st, n_, ld1_, m_, slots_, xb_, (size_t)n_ * ld1_, coefs_, Y_, lds_));
-  ld_status rc = sketch_qr(st, Y_);
+  if (p_.method == LD_METHOD_SO_SLQ) {
+    // So-SLQ keeps the kb dominant left singular vectors of Y: Y V_k
+    // Lambda_k^{-1/2} from the eigenpairs of Y^T Y (rank-deficient sketches
+    // allowed), then CholQR2 of those kb columns
+    LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * s_ * 8,
+              launch_gemm_tn(st, gS_, Y_, lds_, s_, Y_, lds_, s_, part_));
+    LD_LAUNCH(LD_PROF_REDUCE, (double)gS_.nblk * s_ * s_ * 8,
+              launch_reduce(st, part_, gS_.nblk, s_ * s_, gram_));
+    LD_LAUNCH(LD_PROF_SKETCH, 0, launch_subspace_eig(st, s_, kb_, gram_, umat_, dflag_ + 2));
+    LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * (s_ + kb_) * 8,
+              launch_rows_mat(st, n_, Y_, lds_, s_, umat_, kb_));
+  }
+  ld_status rc = sketch_qr(st, Y_, kb_);
   if (rc != LD_OK) return rc;
-  rc = start_block(st, Y_, s_);
+  rc = start_block(st, Y_, kb_);
   if (rc != LD_OK) return rc;
-  LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldB_ * (m_ + 1) * m_ * 8, st));
+  LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldx_ * (m_ + 1) * m_ * 8, st));
   begin_krylov(1);
   return LD_OK;
 }
@@ -528,7 +566,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
 }
 
 ld_status Run::run_epilogue(hipStream_t st) {
-  if (p_.method == LD_METHOD_OSLQ) {
+  if (p_.method != LD_METHOD_OSA_IOP) {
     LD_LAUNCH(LD_PROF_SMALL, 0, launch_gauss_log(st, B_, m_, H_, meff_, K_, flags_));
   } else {
     // x^T L_c x / ||x||^2 = sum_t g_t (log H e1)_t + log(gamma) - c
@@ -557,7 +595,7 @@ ld_status Run::advance(hipStream_t st, int budget, bool* done) {
         ++t_;
         --budget;
         if (t_ >= m_)
-          stage_ = (p_.method == LD_METHOD_OSA_IOP && kphase_ == 0) ? ST_COMBINE : ST_EPILOGUE;
+          stage_ = (p_.method != LD_METHOD_OSLQ && kphase_ == 0) ? ST_COMBINE : ST_EPILOGUE;
         break;
       }
       case ST_COMBINE: {
@@ -588,16 +626,19 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail) 
   if (prof_) LD_HIP(prof_->harvest());
   std::vector<double> K(B_), nrm(B_);
   std::vector<int> meff(B_), flags(B_);
-  int dflag[2] = {0, 0};
+  int dflag[3] = {0, 0, 0};
   LD_HIP(hipMemcpy(K.data(), K_, (size_t)B_ * 8, hipMemcpyDeviceToHost));
   LD_HIP(hipMemcpy(nrm.data(), norm2_, (size_t)B_ * 8, hipMemcpyDeviceToHost));
   LD_HIP(hipMemcpy(meff.data(), meff_, (size_t)B_ * 4, hipMemcpyDeviceToHost));
   LD_HIP(hipMemcpy(flags.data(), flags_, (size_t)B_ * 4, hipMemcpyDeviceToHost));
-  LD_HIP(hipMemcpy(dflag, dflag_, 8, hipMemcpyDeviceToHost));
+  LD_HIP(hipMemcpy(dflag, dflag_, 12, hipMemcpyDeviceToHost));
   float ms = 0.f;
   LD_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
   if (dflag[0] || dflag[1])
     return set_error(LD_E_NUMERIC, "sketch image lost rank (Cholesky of its Gram matrix failed)");
+  if (dflag[2])
+    return set_error(LD_E_NUMERIC, "So-SLQ: the sketch has rank below subspace_rank, or the Jacobi "
+                                   "eigen-decomposition of its Gram matrix did not converge");
   int nbreak = 0;
   for (int p = 0; p < B_; ++p) {
     if (flags[p] & 1) return set_error(LD_E_NUMERIC, "NaN/Inf in Krylov run " + std::to_string(p));
@@ -608,12 +649,14 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail) 
                                          std::to_string(p));
     if (flags[p] & 4) ++nbreak;
   }
-  // trace assembly in a fixed order: sketch runs, then residual runs
+  // trace assembly in a fixed order: basis runs, then residual runs (the
+  // Gauss quadrature methods start from unit basis vectors; OSA-IOP's K is
+  // per unit norm of its start vector)
   double tr_sketch = 0.0;
-  for (int i = 0; i < s_; ++i)
-    tr_sketch += (p_.method == LD_METHOD_OSLQ) ? K[i] : nrm[i] * K[i];
+  for (int i = 0; i < kb_; ++i)
+    tr_sketch += (p_.method != LD_METHOD_OSA_IOP) ? K[i] : nrm[i] * K[i];
   double acc = 0.0;
-  for (int j = s_; j < B_; ++j) acc += nrm[j] * K[j];
+  for (int j = kb_; j < B_; ++j) acc += nrm[j] * K[j];
   const double tr_resid = acc / r_;
   ld_result res{};
   res.logdet = (double)n_ * c_ + (tr_sketch + tr_resid);
@@ -629,14 +672,14 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail) 
     steps += meff[p];
     if (nrm[p] > 0) minst = std::min(minst, meff[p]);
   }
-  if (p_.method == LD_METHOD_OSA_IOP && s_ > 0) {
-    // OSA-IOP also ran s Krylov runs for the sketch image Y = L_c S
+  if (p_.method != LD_METHOD_OSLQ && s_ > 0) {
+    // OSA-IOP and So-SLQ also ran s Krylov runs for the sketch image
     std::vector<int> m0(s_);
     LD_HIP(hipMemcpy(m0.data(), meff0_, (size_t)s_ * 4, hipMemcpyDeviceToHost));
     for (int p = 0; p < s_; ++p) steps += m0[p];
   }
   res.probe_steps = steps;
-  const int64_t sketch_mv = (p_.method == LD_METHOD_OSLQ) ? s_ : (int64_t)s_ * m_;
+  const int64_t sketch_mv = (p_.method == LD_METHOD_OSLQ) ? s_ : (int64_t)s_ * m_;  // S or L S
   res.matvecs = sketch_mv + (int64_t)B_ * m_;
   res.min_steps = minst;
   res.n_breakdowns = nbreak;
@@ -659,11 +702,11 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail) 
             detail->tri_beta[(size_t)p * m_ + t] = live ? Hp[(size_t)(t + 1) * m_ + t] : 0.0;
         }
     }
-    if (detail->sketch_basis && s_ > 0) {
+    if (detail->sketch_basis && kb_ > 0) {
       std::vector<double> Y((size_t)n_ * lds_);
       LD_HIP(hipMemcpy(Y.data(), Y_, Y.size() * 8, hipMemcpyDeviceToHost));
       for (int64_t i = 0; i < n_; ++i)
-        for (int j = 0; j < s_; ++j) detail->sketch_basis[i * s_ + j] = Y[(size_t)i * lds_ + j];
+        for (int j = 0; j < kb_; ++j) detail->sketch_basis[i * kb_ + j] = Y[(size_t)i * lds_ + j];
     }
   }
   *out = res;
@@ -696,7 +739,8 @@ ld_status ld_ctx_create(const ld_ctx_opts* opts, ld_ctx** out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return set_error(LD_E_DEVICE, "no HIP device available");
   if (o.device < 0 || o.device >= ndev) return set_error(LD_E_INVALID_ARG, "bad device ordinal");
-  if (o.default_method != LD_METHOD_OSLQ && o.default_method != LD_METHOD_OSA_IOP)
+  if (o.default_method != LD_METHOD_OSLQ && o.default_method != LD_METHOD_OSA_IOP &&
+      o.default_method != LD_METHOD_SO_SLQ)
     return set_error(LD_E_INVALID_ARG, "bad default_method");
   if (o.default_precision != LD_PREC_FP64 && o.default_precision != LD_PREC_MIXED)
     return set_error(LD_E_INVALID_ARG, "bad default_precision");
@@ -975,6 +1019,26 @@ ld_status ld_debug_rademacher(ld_ctx* ctx, uint64_t seed, int64_t n, int32_t col
   DeviceBuffer buf;
   LD_HIP_API(buf.ensure((size_t)n * ld * 8));
   LD_HIP_API(launch_rademacher(ctx->stream, seed, n, col_begin, ld, nc, buf.ptr, 8, ld, 0));
+  LD_HIP_API(hipStreamSynchronize(ctx->stream));
+  std::vector<double> h((size_t)n * ld);
+  LD_HIP_API(hipMemcpy(h.data(), buf.ptr, h.size() * 8, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n; ++i)
+    for (int j = 0; j < nc; ++j) out[i * nc + j] = h[(size_t)i * ld + j];
+  return LD_OK;
+}
+
+ld_status ld_debug_probes(ld_ctx* ctx, uint64_t seed, int64_t n, int32_t col_begin,
+                          int32_t col_end, int32_t dist, double* out) {
+  if (!ctx || !out || n < 1 || col_begin < 0 || col_end <= col_begin || n > INT32_MAX ||
+      (dist != LD_PROBE_RADEMACHER && dist != LD_PROBE_GAUSSIAN))
+    return set_error(LD_E_INVALID_ARG, "bad argument");
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  LD_HIP_API(hipSetDevice(ctx->device));
+  const int nc = col_end - col_begin;
+  const int ld = (nc + 3) & ~3;
+  DeviceBuffer buf;
+  LD_HIP_API(buf.ensure((size_t)n * ld * 8));
+  LD_HIP_API(launch_probes(ctx->stream, dist, seed, n, col_begin, ld, nc, buf.ptr, 8, ld, 0));
   LD_HIP_API(hipStreamSynchronize(ctx->stream));
   std::vector<double> h((size_t)n * ld);
   LD_HIP_API(hipMemcpy(h.data(), buf.ptr, h.size() * 8, hipMemcpyDeviceToHost));

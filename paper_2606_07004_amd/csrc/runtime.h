@@ -120,7 +120,7 @@ class Run {
   ld_status run_prologue(hipStream_t st);
   ld_status run_krylov_step(hipStream_t st, int t);
   ld_status run_epilogue(hipStream_t st);
-  ld_status sketch_qr(hipStream_t st, double* Y);
+  ld_status sketch_qr(hipStream_t st, double* Y, int cols);
   ld_status osa_sketch_prologue(hipStream_t st);
   ld_status osa_sketch_combine(hipStream_t st);
   ld_status start_block(hipStream_t st, const double* A, int s_cols);
@@ -133,11 +133,13 @@ class Run {
   // derived
   int64_t n_ = 0;
   int s_ = 0, r_ = 0, B_ = 0, m_ = 0, k_ = 0;
+  int kb_ = 0;                // basis columns of the estimate phase (So-SLQ: subspace rank)
+  int adapt_every_ = 5;
   double tol_ = 1e-10;
   double lo_ = 0, hi_ = 0, scale_ = 1, c_ = 0, opscale_ = 1;
   bool mixed_ = false;
   int xb_ = 8;                // bytes per Krylov element
-  int lds_ = 0, ldr_ = 0, ldB_ = 0, ld1_ = 0;
+  int lds_ = 0, ldr_ = 0, ldB_ = 0, ld1_ = 0, ldx_ = 0;
   Geom gB_, gS_, g1_;
   // state machine
   int stage_ = 0;             // 0 prologue, 1 krylov, 2 epilogue..., see .cpp
@@ -167,6 +169,7 @@ class Run {
   double* gram_ = nullptr;    // [s][s]
   double* rfac_ = nullptr;    // [s][s]
   double* rinv_ = nullptr;    // [s][s]
+  double* umat_ = nullptr;    // So-SLQ: [s][kb] kept eigenvectors / sqrt(eigenvalue)
   double* pmat_ = nullptr;    // [s][r]
   double* ell_ = nullptr;     // OSA-IOP: [ld][m] log(H) e1 of the sketch runs
   double* coefs_ = nullptr;   // OSA-IOP: [m][ld1] combination coefficients

@@ -27,7 +27,8 @@ LD_E_DEVICE = -7
 LD_E_UNKNOWN_TICKET = -8
 
 LD_VT_FP64, LD_VT_FP32, LD_VT_BF16 = 0, 1, 2
-LD_METHOD_OSLQ, LD_METHOD_OSA_IOP = 0, 1
+LD_METHOD_OSLQ, LD_METHOD_OSA_IOP, LD_METHOD_SO_SLQ = 0, 1, 2
+LD_PROBE_RADEMACHER, LD_PROBE_GAUSSIAN = 0, 1
 LD_PREC_FP64, LD_PREC_MIXED = 0, 1
 
 _STATUS_NAMES = {
@@ -52,7 +53,9 @@ class ld_ctx_opts(C.Structure):
 class ld_params(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("n_probes", C.c_int32),
                 ("sketch_rank", C.c_int32), ("krylov_steps", C.c_int32),
-                ("iop_window", C.c_int32), ("seed", C.c_uint64), ("tol", C.c_double)]
+                ("iop_window", C.c_int32), ("seed", C.c_uint64), ("tol", C.c_double),
+                ("probe_dist", C.c_int32), ("subspace_rank", C.c_int32),
+                ("adapt_tol", C.c_double), ("adapt_every", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ld_result(C.Structure):
@@ -100,6 +103,8 @@ _SIGNATURES = [
     ("ld_debug_rademacher", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, C.c_int32,
                                         _DP]),
     ("ld_debug_copy", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int32, _DP]),
+    ("ld_debug_probes", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, C.c_int32,
+                                    C.c_int32, _DP]),
 ]
 
 
@@ -175,9 +180,19 @@ def ld_matrix_bounds(a):
 
 def make_params(n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: int, seed: int,
                 method: int = LD_METHOD_OSLQ, precision: int = LD_PREC_FP64,
-                tol: float = 0.0) -> ld_params:
+                tol: float = 0.0, probe_dist: int = LD_PROBE_RADEMACHER,
+                subspace_rank: int = 0, adapt_tol: float = 0.0,
+                adapt_every: int = 0) -> ld_params:
     return ld_params(method, precision, n_probes, sketch_rank, krylov_steps, iop_window,
-                     seed, tol)
+                     seed, tol, probe_dist, subspace_rank, adapt_tol, adapt_every, 0)
+
+
+def runs_and_basis(params: ld_params):
+    """(Krylov runs reported, basis columns) of a request, as ld_detail sizes them."""
+    if params.method == LD_METHOD_SO_SLQ:
+        k = params.subspace_rank if params.subspace_rank > 0 else min(10, params.sketch_rank)
+        return k + params.n_probes - params.sketch_rank, k
+    return params.n_probes, params.sketch_rank
 
 
 def ld_estimate(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: int,
@@ -198,8 +213,9 @@ def ld_estimate_detail(a, params: ld_params, n: Optional[int] = None, tri: bool 
                        basis: bool = False):
     """Estimate plus per-run arrays: dict with probe_K, probe_norm2,
     probe_steps and optionally tri_alpha/tri_beta ([runs, m]) and the sketch
-    basis ([n, s])."""
-    B, m, s = params.n_probes, params.krylov_steps, params.sketch_rank
+    basis ([n, b])."""
+    B, s = runs_and_basis(params)
+    m = params.krylov_steps
     arrays = {"probe_K": np.zeros(B), "probe_norm2": np.zeros(B),
               "probe_steps": np.zeros(B, dtype=np.int32)}
     if tri:
@@ -257,6 +273,14 @@ def ld_profile_query(ctx, family: int):
 def ld_debug_rademacher(ctx, seed: int, n: int, col_begin: int, col_end: int) -> np.ndarray:
     out = np.zeros((n, col_end - col_begin))
     _check(lib().ld_debug_rademacher(ctx, seed, n, col_begin, col_end, out.ctypes.data_as(_DP)))
+    return out
+
+
+def ld_debug_probes(ctx, seed: int, n: int, col_begin: int, col_end: int,
+                    dist: int = LD_PROBE_RADEMACHER) -> np.ndarray:
+    out = np.zeros((n, col_end - col_begin))
+    _check(lib().ld_debug_probes(ctx, seed, n, col_begin, col_end, dist,
+                                 out.ctypes.data_as(_DP)))
     return out
 
 

@@ -1,0 +1,28 @@
+/* Prints "struct field offset size" for every field of the ABI structs and
+ * "struct - sizeof" lines, compiled as plain C against include/liblogdet.h. */
+#include <stddef.h>
+#include <stdio.h>
+#include "liblogdet.h"
+
+#define F(S, f) printf(#S " " #f " %zu %zu\n", offsetof(S, f), sizeof(((S*)0)->f))
+#define Z(S) printf(#S " - %zu 0\n", sizeof(S))
+
+int main(void) {
+  F(ld_ctx_opts, device); F(ld_ctx_opts, max_slots); F(ld_ctx_opts, hbm_budget_bytes);
+  F(ld_ctx_opts, hip_stream); F(ld_ctx_opts, default_method); F(ld_ctx_opts, default_precision);
+  Z(ld_ctx_opts);
+  F(ld_params, method); F(ld_params, precision); F(ld_params, n_probes); F(ld_params, sketch_rank);
+  F(ld_params, krylov_steps); F(ld_params, iop_window); F(ld_params, seed); F(ld_params, tol);
+  F(ld_params, probe_dist); F(ld_params, subspace_rank); F(ld_params, adapt_tol);
+  F(ld_params, adapt_every); F(ld_params, reserved);
+  Z(ld_params);
+  F(ld_result, logdet); F(ld_result, tr_sketch); F(ld_result, tr_resid); F(ld_result, shift_c);
+  F(ld_result, lambda_lo); F(ld_result, lambda_hi); F(ld_result, scale); F(ld_result, probe_steps);
+  F(ld_result, matvecs); F(ld_result, min_steps); F(ld_result, n_breakdowns);
+  F(ld_result, device_ms); F(ld_result, latency_ms);
+  Z(ld_result);
+  F(ld_detail, probe_K); F(ld_detail, probe_norm2); F(ld_detail, probe_steps);
+  F(ld_detail, tri_alpha); F(ld_detail, tri_beta); F(ld_detail, sketch_basis);
+  Z(ld_detail);
+  return 0;
+}

@@ -40,14 +40,33 @@ def test_library_exports_every_declared_symbol():
         assert set(_declared()) <= exported
 
 
-def test_struct_layouts_match_header():
-    # ld_params: 6 int32 + uint64 + double; ld_result: 7 double, 2 int64, 2 int32, 2 double
+def test_struct_layouts_match_header(tmp_path):
+    # every field offset and size of the ctypes mirrors equals what a C
+    # compiler makes of include/liblogdet.h
     from paper_2606_07004_amd import liblogdet as L
     import ctypes as C
-    assert C.sizeof(L.ld_params) == 6 * 4 + 8 + 8
-    assert C.sizeof(L.ld_result) == 7 * 8 + 2 * 8 + 2 * 4 + 2 * 8
-    assert C.sizeof(L.ld_ctx_opts) == 4 + 4 + 8 + 8 + 4 + 4
-    assert C.sizeof(L.ld_detail) == 6 * 8
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    exe = tmp_path / "abi_layout"
+    subprocess.run([gcc, "-std=c99", "-I" + os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "csrc", "abi_layout.c"), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    mirrors = {"ld_ctx_opts": L.ld_ctx_opts, "ld_params": L.ld_params, "ld_result": L.ld_result,
+               "ld_detail": L.ld_detail}
+    seen = {k: set() for k in mirrors}
+    for line in out.strip().splitlines():
+        struct, field, off, size = line.split()
+        cls = mirrors[struct]
+        if field == "-":
+            assert C.sizeof(cls) == int(off), struct
+            continue
+        desc = getattr(cls, field)
+        assert (desc.offset, desc.size) == (int(off), int(size)), (struct, field)
+        seen[struct].add(field)
+    for struct, cls in mirrors.items():
+        assert seen[struct] == {name for name, _ in cls._fields_}, struct
 
 
 @pytest.fixture(scope="module")

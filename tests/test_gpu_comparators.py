@@ -1,0 +1,167 @@
+"""GPU parity of the comparators and the probe distributions against the
+CPU FP64 oracle: Gaussian probes (Box-Muller on Philox4x64-10), OSLQ and
+OSA-IOP with Gaussian probes, and So-SLQ (the Section 4 comparator: the k
+dominant left singular vectors of a sketch log(J) S, then Gauss-Lanczos
+quadrature on the basis and on the projected residual probes).
+
+Tolerances: FP64 |dlogdet|/|logdet| <= 1e-6, per-run quadrature values
+<= 1e-8; mixed precision <= 1e-4.  Gaussian entries are compared to 1e-14
+relative (the device and NumPy log/sqrt/sin/cos need not round alike).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2606_07004_amd import liblogdet
+    liblogdet.lib()  # fails loudly when the HIP library is missing
+    return liblogdet
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    c = L.Context(0)
+    yield c
+    c.close()
+
+
+def _announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+@pytest.mark.parametrize("n,c0,c1", [(4, 0, 3), (1001, 2, 9), (70_003, 0, 70)])
+def test_gaussian_probes_match_oracle(L, ctx, n, c0, c1):
+    _announce(f"gaussian probes n={n} columns {c0}..{c1 - 1}")
+    got = L.ld_debug_probes(ctx.handle, 0xC0FFEE, n, c0, c1, L.LD_PROBE_GAUSSIAN)
+    ref = oracle.gaussian(0xC0FFEE, n, c0, c1)
+    np.testing.assert_allclose(got, ref, rtol=1e-14, atol=1e-15)
+    rad = L.ld_debug_probes(ctx.handle, 0xC0FFEE, n, c0, c1, L.LD_PROBE_RADEMACHER)
+    np.testing.assert_array_equal(rad, oracle.rademacher(0xC0FFEE, n, c0, c1))
+
+
+def _run(L, ctx, a, p, lo_hint=0.0, basis=False):
+    h = ctx.matrix(a, vt=L.LD_VT_FP64 if p.precision == L.LD_PREC_FP64 else L.LD_VT_FP32,
+                   lo_hint=lo_hint)
+    try:
+        return L.ld_estimate_detail(h, p, n=a.n, basis=basis)
+    finally:
+        ctx.release(h)
+
+
+@pytest.mark.parametrize("method", ["oslq", "osa_iop"])
+def test_gaussian_probe_estimators(L, ctx, method):
+    a = W.lap2d(31, 0.1)
+    _announce(f"{method} gaussian {a.name} probes=18 s=6 m=16 k=2")
+    mcode = L.LD_METHOD_OSLQ if method == "oslq" else L.LD_METHOD_OSA_IOP
+    ref = getattr(oracle, method)(a, 18, 6, 16, 2, 4, dist=oracle.PROBE_GAUSSIAN)
+    p = L.make_params(18, 6, 16, 2, 4, method=mcode, probe_dist=L.LD_PROBE_GAUSSIAN)
+    res, det = _run(L, ctx, a, p)
+    rel = abs(res.logdet - ref.logdet) / abs(ref.logdet)
+    print(f"  gpu {res.logdet!r} oracle {ref.logdet!r} rel {rel:.3e}", flush=True)
+    assert rel <= 1e-6
+    np.testing.assert_array_equal(det["probe_steps"], np.array(ref.probe_steps))
+    np.testing.assert_allclose(det["probe_K"], ref.probe_K, rtol=1e-8, atol=1e-8)
+
+
+def _check_so_slq(L, ctx, a, npr, q, k, m, win, seed, dist, prec=None, lo_hint=0.0,
+                  rtol=1e-6, tol=0.0):
+    prec = L.LD_PREC_FP64 if prec is None else prec
+    _announce(f"so-slq {a.name} n={a.n} probes={npr} q={q} k={k} m={m} window={win} "
+              f"seed={seed} dist={dist} prec={prec}")
+    ref = oracle.so_slq(a, npr, q, k, m, win, seed, dist=dist, lo_hint=lo_hint,
+                        keep_basis=True, **({"tol": tol} if tol > 0 else {}))
+    p = L.make_params(npr, q, m, win, seed, method=L.LD_METHOD_SO_SLQ, precision=prec,
+                      probe_dist=dist, subspace_rank=k, tol=tol)
+    res, det = _run(L, ctx, a, p, lo_hint=lo_hint, basis=True)
+    rel = abs(res.logdet - ref.logdet) / abs(ref.logdet)
+    print(f"  gpu {res.logdet!r} oracle {ref.logdet!r} rel {rel:.3e} device {res.device_ms:.2f} ms",
+          flush=True)
+    assert rel <= rtol
+    assert res.shift_c == pytest.approx(ref.shift_c, rel=1e-14)
+    if prec == L.LD_PREC_FP64:
+        np.testing.assert_array_equal(det["probe_steps"], np.array(ref.probe_steps))
+        np.testing.assert_allclose(det["probe_norm2"], ref.probe_norm2, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(det["probe_K"], ref.probe_K, rtol=1e-8, atol=1e-8)
+        # the kept subspace (columns agree up to sign)
+        pg = det["sketch_basis"] @ det["sketch_basis"].T
+        pr = ref.sketch_basis @ ref.sketch_basis.T
+        np.testing.assert_allclose(pg, pr, atol=1e-8)
+    return ref, res, det
+
+
+@pytest.mark.parametrize("dist", [0, 1])
+def test_so_slq_lap2d(L, ctx, dist):
+    _check_so_slq(L, ctx, W.lap2d(40, 0.05), 30, 12, 4, 20, 2, 0, dist)
+
+
+def test_so_slq_ragged_full_window(L, ctx):
+    # odd sketch width (a dummy index in the Jacobi ordering), ragged n
+    _check_so_slq(L, ctx, W.lap3d(13, 1e-2), 21, 9, 5, 14, 14, 6, 1)
+
+
+def test_so_slq_wendland_hint(L, ctx):
+    _check_so_slq(L, ctx, W.wendland(3000, 30.0, 1e-2, seed=3), 20, 10, 3, 16, 2, 1, 1,
+                  lo_hint=1e-2)
+
+
+def test_so_slq_paper_settings(L, ctx):
+    # the comparator's settings in Section 4: sketch q = 30, rank k = 10
+    _check_so_slq(L, ctx, W.lap2d(64, 0.1), 60, 30, 10, 20, 2, 2, 1)
+
+
+def test_so_slq_captures_rank_k(L, ctx):
+    # log J of rank 4: the kept subspace is span(e_1..e_4) and the estimate exact
+    d = np.concatenate([[0.01, 0.02, 0.05, 0.1], np.ones(36)])
+    a = W.diag_matrix(d)
+    ref, res, det = _check_so_slq(L, ctx, a, 18, 12, 4, 10, 10, 3, 1, tol=1e-8)
+    assert res.logdet == pytest.approx(float(np.sum(np.log(d))), rel=1e-9)
+
+
+def test_so_slq_mixed(L, ctx):
+    _check_so_slq(L, ctx, W.lap3d(20, 1e-2), 30, 12, 6, 20, 2, 5, 1,
+                  prec=L.LD_PREC_MIXED, rtol=1e-4)
+
+
+def test_parameter_errors(L, ctx):
+    _announce("comparator parameter errors")
+    a = W.lap2d(12, 0.1)
+    h = ctx.matrix(a)
+    try:
+        bad = [
+            L.make_params(20, 8, 10, 2, 0, method=L.LD_METHOD_SO_SLQ, subspace_rank=9),
+            L.make_params(80, 49, 10, 2, 0, method=L.LD_METHOD_SO_SLQ, precision=L.LD_PREC_MIXED),
+            L.make_params(20, 0, 10, 2, 0, method=L.LD_METHOD_SO_SLQ),
+            L.make_params(20, 8, 10, 2, 0, method=L.LD_METHOD_OSLQ, subspace_rank=3),
+            L.make_params(20, 8, 10, 2, 0, probe_dist=2),
+            L.make_params(20, 8, 10, 2, 0, method=L.LD_METHOD_OSA_IOP, adapt_tol=1e-3),
+            L.make_params(20, 8, 10, 2, 0, adapt_tol=-1.0),
+        ]
+        for p in bad:
+            with pytest.raises(L.LdError) as e:
+                L.ld_estimate_ex(h, p)
+            assert e.value.status == L.LD_E_INVALID_ARG
+    finally:
+        ctx.release(h)
+
+
+def test_so_slq_served_equals_alone(L, ctx):
+    _announce("so-slq served vs alone")
+    mats = [W.lap2d(50, 0.05), W.lap3d(15, 1e-2)]
+    ps = [L.make_params(24, 10, 15, 2, i, method=L.LD_METHOD_SO_SLQ, subspace_rank=4,
+                        probe_dist=L.LD_PROBE_GAUSSIAN,
+                        precision=L.LD_PREC_MIXED if i % 2 else L.LD_PREC_FP64)
+          for i in range(4)]
+    with L.Context(0, max_slots=4) as c:
+        hs = [c.matrix(a) for a in mats]
+        alone = [L.ld_estimate_ex(hs[i % 2], p).logdet for i, p in enumerate(ps)]
+        tk = [L.ld_submit(hs[i % 2], p) for i, p in enumerate(ps)]
+        got = [L.ld_wait(c.handle, t).logdet for t in tk]
+        for h in hs:
+            c.release(h)
+    assert got == alone
