@@ -33,8 +33,8 @@ import scipy.sparse as sp
 
 from .krylov import windowed_arnoldi
 from .philox import PROBE_RADEMACHER, probes
-from .quadrature import (NotSPDError, gauss_quadrature_log, log_hessenberg_e1,
-                         tridiag_from_hessenberg)
+from .quadrature import (NotSPDError, adaptive_dimension, gauss_quadrature_log,
+                         log_hessenberg_e1, tridiag_from_hessenberg)
 from .spectral import osa_iop_shift, oslq_scaling, spectral_interval
 
 DEFAULT_TOL = 1e-10
@@ -85,9 +85,11 @@ def _split(n_probes: int, sketch_rank: int, n: int, m: int, window: int):
 def oslq(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: int,
          seed: int, tol: float = DEFAULT_TOL, lo_hint: float = 0.0,
          hi_hint: float = 0.0, keep_basis: bool = False,
-         dist: int = PROBE_RADEMACHER) -> OracleResult:
+         dist: int = PROBE_RADEMACHER, adapt_tol: float = 0.0,
+         adapt_every: int = 5) -> OracleResult:
     """Alg 3: Hutch++ with the subspace from orth(J S) and Gauss-Lanczos
-    quadrature for every quadratic form of log J."""
+    quadrature for every quadratic form of log J (optionally with the adaptive
+    Krylov dimension of quadrature.adaptive_dimension)."""
     n = a.n
     s, r = _split(n_probes, sketch_rank, n, krylov_steps, iop_window)
     q = _as_scipy(a)
@@ -98,9 +100,11 @@ def oslq(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: int,
         return (q @ x) / alpha
 
     def quad(x):
-        h, beta0, _, m_eff, _ = windowed_arnoldi(apply_j, x, krylov_steps, iop_window, tol)
+        h, beta0, _, m_eff, broke = windowed_arnoldi(apply_j, x, krylov_steps, iop_window, tol)
         al, be = tridiag_from_hessenberg(h)
-        return gauss_quadrature_log(al, be), m_eff, al, be
+        m_stop = adaptive_dimension(al, be, m_eff, broke, krylov_steps, adapt_every, adapt_tol)
+        al, be = al[:m_stop], be[:max(m_stop - 1, 0)]
+        return gauss_quadrature_log(al, be), m_stop, al, be
 
     sk = probes(seed, n, 0, s, dist)
     y = (q @ sk) / alpha if s > 0 else np.zeros((n, 0))
@@ -136,10 +140,10 @@ def oslq(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: int,
 
 def slq(a, n_probes: int, krylov_steps: int, iop_window: int, seed: int,
         tol: float = DEFAULT_TOL, lo_hint: float = 0.0, hi_hint: float = 0.0,
-        dist: int = PROBE_RADEMACHER):
+        dist: int = PROBE_RADEMACHER, adapt_tol: float = 0.0, adapt_every: int = 5):
     """Stochastic Lanczos quadrature: the sketch-rank-0 setting of OSLQ."""
     return oslq(a, n_probes, 0, krylov_steps, iop_window, seed, tol, lo_hint, hi_hint,
-                dist=dist)
+                dist=dist, adapt_tol=adapt_tol, adapt_every=adapt_every)
 
 
 def _iop_log_action(q, x, gamma: float, c: float, m: int, window: int, tol: float):
@@ -216,7 +220,8 @@ def dense_logdet(a) -> float:
 def so_slq(a, n_probes: int, sketch_rank: int, subspace_rank: int, krylov_steps: int,
            iop_window: int, seed: int, tol: float = DEFAULT_TOL, lo_hint: float = 0.0,
            hi_hint: float = 0.0, keep_basis: bool = False,
-           dist: int = PROBE_RADEMACHER) -> OracleResult:
+           dist: int = PROBE_RADEMACHER, adapt_tol: float = 0.0,
+           adapt_every: int = 5) -> OracleResult:
     """So-SLQ, the comparator of Section 4 (Han et al.'s subspace construction,
     with the settings the paper gives: a sketch of q = sketch_rank columns and a
     kept rank k = subspace_rank).
@@ -245,9 +250,11 @@ def so_slq(a, n_probes: int, sketch_rank: int, subspace_rank: int, krylov_steps:
         return (q @ x) / alpha
 
     def quad(x):
-        h, beta0, _, m_eff, _ = windowed_arnoldi(apply_j, x, krylov_steps, iop_window, tol)
+        h, beta0, _, m_eff, broke = windowed_arnoldi(apply_j, x, krylov_steps, iop_window, tol)
         al, be = tridiag_from_hessenberg(h)
-        return gauss_quadrature_log(al, be), m_eff, al, be
+        m_stop = adaptive_dimension(al, be, m_eff, broke, krylov_steps, adapt_every, adapt_tol)
+        al, be = al[:m_stop], be[:max(m_stop - 1, 0)]
+        return gauss_quadrature_log(al, be), m_stop, al, be
 
     # sketch of the traced operator log(J) = L_c, one Alg 1 run per column
     sk = probes(seed, n, 0, q_cols, dist)

@@ -57,3 +57,30 @@ def log_hessenberg_e1(h: np.ndarray) -> np.ndarray:
             raise NotSPDError("log(H) is not real: H has eigenvalues off the positive axis")
         lh = lh.real
     return np.ascontiguousarray(lh[:, 0], dtype=np.float64)
+
+
+def adaptive_dimension(alpha, beta, m_eff: int, broke: bool, m_max: int, every: int,
+                       rtol: float) -> int:
+    """Krylov dimension at which a run stops under the adaptive rule.
+
+    The paper only names adaptive control of the Krylov dimension (Sections 1
+    and 5, with the stop on h < tol of Alg 1); the reading used here: at
+    every multiple t of `every` with t < m_max, a run that has not stopped
+    forms its Gauss quadrature value K_t on its leading t x t tridiagonal and
+    stops at dimension t once |K_t - K_{t - every}| <= rtol |K_t| (the first
+    check only records K).  A run that broke down at dimension t is not
+    checked there.  rtol <= 0 disables the rule.
+    """
+    if rtol <= 0.0:
+        return m_eff
+    prev = None
+    t = every
+    while t < m_max and t <= m_eff:
+        if broke and t == m_eff:
+            break
+        k_t = gauss_quadrature_log(alpha[:t], beta[:t - 1])
+        if prev is not None and abs(k_t - prev) <= rtol * abs(k_t):
+            return t
+        prev = k_t
+        t += every
+    return m_eff

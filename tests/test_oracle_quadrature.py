@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 import scipy.linalg
 
+import oracle as O
 import workloads as W
 from oracle import (NotSPDError, gauss_quadrature_log, log_hessenberg_e1,
                     tridiag_from_hessenberg, windowed_arnoldi)
@@ -104,3 +105,47 @@ def test_log_hessenberg_rejects_negative_spectrum():
     h = np.array([[-1.0, 0.2], [0.3, 2.0]])
     with pytest.raises(NotSPDError):
         log_hessenberg_e1(h)
+
+
+# ---------------------------------------------------------------------------
+# Adaptive Krylov dimension (stop once the quadrature value settles)
+# ---------------------------------------------------------------------------
+from oracle.quadrature import adaptive_dimension  # noqa: E402
+
+
+def test_adaptive_dimension_on_decoupled_tridiagonal():
+    # beta_5 = 0 decouples T after row 5: e1 sees only the leading 5 x 5 block,
+    # so K_t = K_5 for t >= 5.  Checks every 3: t = 3 records, t = 6 differs
+    # from K_3, t = 9 equals K_6 -> stop at 9.  A run that broke down at its
+    # last dimension is not checked there; rtol 0 never stops.
+    rng = np.random.default_rng(3)
+    al = rng.uniform(0.2, 0.9, 20)
+    be = rng.uniform(0.05, 0.1, 19)
+    be[4] = 0.0
+    assert adaptive_dimension(al, be, 20, False, 20, 3, 1e-12) == 9
+    assert adaptive_dimension(al, be, 9, True, 20, 3, 1e-12) == 9   # not checked at 9
+    assert adaptive_dimension(al, be, 20, False, 20, 3, 0.0) == 20
+    assert adaptive_dimension(al, be, 20, False, 9, 3, 1e-12) == 20  # t < m_max only
+
+
+def test_adaptive_rtol_zero_is_the_plain_estimator():
+    a = W.lap2d(20, 0.1)
+    r0 = O.oslq(a, 12, 4, 30, 2, 1)
+    r1 = O.oslq(a, 12, 4, 30, 2, 1, adapt_tol=0.0, adapt_every=4)
+    assert r0.logdet == r1.logdet and r0.probe_steps == r1.probe_steps
+
+
+def test_adaptive_estimate_close_to_converged_one():
+    # geometric convergence of Gauss quadrature on a well-conditioned operator:
+    # the adaptive estimate is within a few rtol of the full-depth estimate and
+    # uses fewer steps; a tighter rtol never uses fewer steps
+    a = W.lap2d(30, 0.5)
+    full = O.oslq(a, 12, 4, 60, 60, 2)
+    steps = []
+    for rtol in (1e-3, 1e-6, 1e-9):
+        r = O.oslq(a, 12, 4, 60, 60, 2, adapt_tol=rtol, adapt_every=4)
+        rel = abs(r.logdet - full.logdet) / abs(full.logdet)
+        assert rel <= 10 * rtol
+        assert max(r.probe_steps) < 60
+        steps.append(sum(r.probe_steps))
+    assert steps[0] <= steps[1] <= steps[2]
