@@ -570,11 +570,12 @@ __global__ __launch_bounds__(kThreads) void k_step_finish(int B, int ld, int t, 
 // ---------------------------------------------------------------------------
 __global__ void k_gauss_log(int B, int m, int pb, const double* __restrict__ H,
                             const int* __restrict__ meff, double* __restrict__ K,
-                            int* __restrict__ flags) {
+                            int* __restrict__ flags, const int* __restrict__ need) {
   extern __shared__ double sm[];
   const int pl = threadIdx.x;
   const int p = blockIdx.x * pb + pl;
   if (pl >= pb || p >= B) return;
+  if (need && !need[p]) return;
   const int nn = meff[p];
   if (nn <= 0) {
     K[p] = 0.0;
@@ -594,6 +595,117 @@ __global__ void k_gauss_log(int B, int m, int pb, const double* __restrict__ H,
   if (bad) flags[p] |= 2;
   if (!isfinite(s)) flags[p] |= 1;
   K[p] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Gauss quadrature value K = e1^T log(T) e1 = sum_k tau_k^2 log(theta_k) of
+// each run's tridiagonal T (diagonal h_tt, subdiagonal h_t+1,t, its first
+// meff rows), from the Stieltjes form of the logarithm,
+//   log x = integral over s > 0 of 1/(1+s) - 1/(x+s) ds,
+// which for the matrix reads K = integral of 1/(1+s) - e1^T (T + sI)^{-1} e1.
+// With s = e^u the integrand is analytic in the strip |Im u| < pi and decays
+// exponentially at both ends, so the trapezoidal rule with step 1/2 on
+// [log(a) - 40, log(max(b, 1)) + 40] is accurate to rounding when the
+// spectrum of T lies in [a, b] (the exponentially convergent trapezoidal
+// rule, Trefethen & Weideman, SIAM Review 2014).  e1^T (T + sI)^{-1} e1 is
+// 1/d_1 for the pivots of T + sI eliminated from the bottom
+// (d_t = alpha_t + s, d_i = alpha_i + s - beta_i^2 / d_{i+1}); the integrand
+// is formed as s n / ((1+s) d_1) with n = d_1 - (1+s) computed directly, so
+// nothing cancels.  One wave per run, the nodes spread over the lanes, a
+// fixed-order reduction.
+//
+// A run whose T has an eigenvalue outside [a/1000, 1000 b] (Sturm counts) is
+// left to the Golub-Welsch kernel (need[p] = 1).  In check mode (the adaptive
+// Krylov dimension) only runs that are active and advanced to dimension dim
+// are evaluated: K is compared with the previous check's value kprev[p] and
+// the run stops (active = 0, mult_next = 0, flag bit 4) once
+// |K - kprev| <= rtol |K|; nactive counts the runs still active.
+// ---------------------------------------------------------------------------
+constexpr int kQuadWaves = 4;      // runs per 256-thread block
+constexpr double kQuadStep = 0.5;  // trapezoidal step in u = log s
+constexpr double kQuadTail = 40.0; // e^-40: both tails below rounding
+
+__device__ inline int sturm_below(int nn, const double* al, const double* b2, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (int i = 0; i < nn; ++i) {
+    q = al[i] - x - (i > 0 ? b2[i - 1] / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(kThreads) void k_quad_log(int B, int m, const double* __restrict__ H,
+                                                      const int* __restrict__ meff, double a, double b,
+                                                      double* __restrict__ K, int* __restrict__ need,
+                                                      int check_dim, int* __restrict__ active,
+                                                      double* __restrict__ kprev, double rtol,
+                                                      double* __restrict__ mult_next,
+                                                      int* __restrict__ flags,
+                                                      int* __restrict__ nactive) {
+  extern __shared__ double qsm[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = blockIdx.x * kQuadWaves + w;
+  double* al = qsm + (size_t)w * 2 * m;
+  double* b2 = al + m;
+  if (p >= B) return;
+  const bool check = check_dim > 0;
+  const int nn = meff[p];
+  if (check && (!active[p] || nn != check_dim)) return;
+  if (nn <= 0) {
+    if (!check && lane == 0) {
+      K[p] = 0.0;
+      need[p] = 0;
+    }
+    return;
+  }
+  const double* Hp = H + (size_t)p * (m + 1) * m;
+  for (int i = lane; i < nn; i += 64) {
+    al[i] = Hp[(size_t)i * m + i];
+    const double be = (i + 1 < nn) ? Hp[(size_t)(i + 1) * m + i] : 0.0;
+    b2[i] = be * be;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // spectrum inside the trusted interval?
+  int outside = 0;
+  if (lane == 0) outside = sturm_below(nn, al, b2, a * 1e-3) > 0;
+  if (lane == 1) outside = sturm_below(nn, al, b2, b * 1e3) < nn;
+  outside = __shfl(outside, 0, 64) | __shfl(outside, 1, 64);
+  if (outside) {
+    if (!check && lane == 0) need[p] = 1;
+    return;  // check mode: this run keeps going
+  }
+  const double umin = log(a) - kQuadTail;
+  const double umax = log(b > 1.0 ? b : 1.0) + kQuadTail;
+  const int nodes = (int)ceil((umax - umin) / kQuadStep) + 1;
+  double acc = 0.0;
+  for (int j = lane; j < nodes; j += 64) {
+    const double sv = exp(umin + j * kQuadStep);
+    double d = al[nn - 1] + sv;
+    for (int i = nn - 2; i >= 1; --i) d = al[i] + sv - b2[i] / d;
+    const double num = (al[0] - 1.0) - (nn >= 2 ? b2[0] / d : 0.0);
+    const double d1 = (1.0 + sv) + num;
+    acc += sv * num / ((1.0 + sv) * d1);
+  }
+  const double kval = wave_sum_fixed(acc) * kQuadStep;
+  if (lane != 0) return;
+  if (!check) {
+    K[p] = kval;
+    need[p] = 0;
+    if (!isfinite(kval)) flags[p] |= 1;
+    return;
+  }
+  const double prev = kprev[p];
+  kprev[p] = kval;
+  if (fabs(kval - prev) <= rtol * fabs(kval)) {  // false for the first check (prev NaN)
+    active[p] = 0;
+    mult_next[p] = 0.0;
+    flags[p] |= 16;
+  } else {
+    atomicAdd(nactive, 1);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -907,14 +1019,38 @@ hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, doubl
 }
 
 hipError_t launch_gauss_log(hipStream_t st, int B, int m, const double* H, const int* meff,
-                            double* K, int* flags) {
+                            double* K, int* flags, const int* need) {
   if (B < 1 || m < 1 || m > 1024) return hipErrorInvalidValue;
   // one probe per wave: the implicit QL sweeps of different probes converge
   // differently, and lanes of one wave would serialise on each other's paths
   int pb = 1;
   const size_t lds = (size_t)3 * m * pb * sizeof(double);
   hipLaunchKernelGGL(k_gauss_log, dim3((B + pb - 1) / pb), dim3(64), lds, st, B, m, pb, H, meff, K,
-                     flags);
+                     flags, need);
+  return hipGetLastError();
+}
+
+hipError_t launch_quad_log(hipStream_t st, int B, int m, const double* H, const int* meff, double a,
+                           double b, double* K, int* need, int* flags) {
+  if (B < 1 || m < 1 || m > 1024 || !(a > 0.0) || !(b >= a) || !H || !meff || !K || !need ||
+      !flags)
+    return hipErrorInvalidValue;
+  const size_t lds = (size_t)kQuadWaves * 2 * m * sizeof(double);
+  hipLaunchKernelGGL(k_quad_log, dim3((B + kQuadWaves - 1) / kQuadWaves), dim3(kThreads), lds, st, B,
+                     m, H, meff, a, b, K, need, 0, nullptr, nullptr, 0.0, nullptr, flags, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_quad_check(hipStream_t st, int B, int m, const double* H, const int* meff,
+                             double a, double b, int dim, int* active, double* kprev, double rtol,
+                             double* mult_next, int* flags, int* nactive) {
+  if (B < 1 || m < 1 || m > 1024 || dim < 1 || dim > m || !(a > 0.0) || !(b >= a) || !H ||
+      !meff || !active || !kprev || !mult_next || !flags || !nactive)
+    return hipErrorInvalidValue;
+  const size_t lds = (size_t)kQuadWaves * 2 * m * sizeof(double);
+  hipLaunchKernelGGL(k_quad_log, dim3((B + kQuadWaves - 1) / kQuadWaves), dim3(kThreads), lds, st, B,
+                     m, H, meff, a, b, nullptr, nullptr, dim, active, kprev, rtol, mult_next, flags,
+                     nactive);
   return hipGetLastError();
 }
 

@@ -90,8 +90,22 @@ hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, doubl
                               int sym_row);
 
 // Gauss quadrature of log on each probe's T (diag h_tt, subdiag h_t+1,t).
+// (need: when non-null, only runs with need[p] != 0 are evaluated.)
 hipError_t launch_gauss_log(hipStream_t st, int B, int m, const double* H, const int* meff,
-                            double* K, int* flags);
+                            double* K, int* flags, const int* need);
+// The same value K = e1^T log(T) e1 from the trapezoidal rule on the Stieltjes
+// integral of log, valid when T's spectrum lies in [a, b]; runs whose T has
+// an eigenvalue outside [a/1000, 1000 b] get need[p] = 1 (left to the
+// Golub-Welsch kernel), the others need[p] = 0.
+hipError_t launch_quad_log(hipStream_t st, int B, int m, const double* H, const int* meff, double a,
+                           double b, double* K, int* need, int* flags);
+// Adaptive Krylov dimension: for the active runs at dimension dim, K from the
+// same rule is compared with kprev (then replaced); a run whose K moved by at
+// most rtol |K| stops (active = 0, mult_next = 0, flag bit 4); nactive is
+// incremented once per run still active.
+hipError_t launch_quad_check(hipStream_t st, int B, int m, const double* H, const int* meff,
+                             double a, double b, int dim, int* active, double* kprev, double rtol,
+                             double* mult_next, int* flags, int* nactive);
 
 // OSA-IOP: Gauss-Legendre rule of the Pade step of log(H) e1 (nodes on [0, 1]).
 struct LogRule {

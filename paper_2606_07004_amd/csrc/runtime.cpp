@@ -181,6 +181,11 @@ Run::Run(ld_matrix* a, const ld_params& p) : a_(a), p_(p) {}
 Run::~Run() {
   if (ev0_) (void)hipEventDestroy(ev0_);
   if (ev1_) (void)hipEventDestroy(ev1_);
+  if (check_ev_) {
+    (void)hipEventSynchronize(check_ev_);
+    (void)hipEventDestroy(check_ev_);
+  }
+  if (nact_host_) (void)hipHostFree(nact_host_);
 }
 
 ld_status Run::validate() {
@@ -314,6 +319,8 @@ size_t Run::layout(char* base) {
   active_ = static_cast<int*>(take((size_t)ldx_ * 4));
   flags_ = static_cast<int*>(take((size_t)ldx_ * 4));
   dflag_ = static_cast<int*>(take(16));
+  nact_ = static_cast<int*>(take(16));
+  kprev_ = static_cast<double*>(take((size_t)ldx_ * 8));
   need_ = static_cast<int*>(take((size_t)ldx_ * 4));
   meff0_ = static_cast<int*>(take((size_t)ldx_ * 4));
   return off;
@@ -358,6 +365,8 @@ ld_status Run::sketch_qr(hipStream_t st, double* Y, int cols) {
 // X0 = [A | G - A (A^T G)] in Krylov precision, its column norms, and the
 // per-run start state.
 ld_status Run::start_block(hipStream_t st, const double* A, int s_cols) {
+  // no previous quadrature value yet (all-ones bytes: NaN) for the adaptive test
+  LD_HIP(hipMemsetAsync(kprev_, 0xFF, (size_t)ldx_ * 8, st));
   LD_LAUNCH(LD_PROF_PROBES, (double)n_ * ldr_ * 8,
             launch_probes(st, p_.probe_dist, p_.seed, n_, s_, ldr_, r_, G_, 8, ldr_, 0));
   if (s_cols > 0) {
@@ -403,6 +412,7 @@ ld_status Run::begin_krylov(int phase) {
   kslots_ = slots_;
   kmult_ = mult_;
   slot_elems_ = (size_t)n_ * kld_;
+  pending_check_ = false;
   return LD_OK;
 }
 
@@ -562,12 +572,29 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
             launch_step_finish(st, kB_, kld_, t, m_, dwin_, j0, nv, part_, nb, tol_, H_,
                                meff_, active_, mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_,
                                sym_out ? nv_next - 2 : -1));
+  if (adaptive() && (t + 1) % adapt_every_ == 0 && t + 1 < m_) {
+    // adaptive Krylov dimension: runs whose quadrature value settled stop;
+    // the count of runs still going comes back to the host for the early exit
+    if (!nact_host_) LD_HIP(hipHostMalloc((void**)&nact_host_, sizeof(int), hipHostMallocDefault));
+    if (!check_ev_) LD_HIP(hipEventCreateWithFlags(&check_ev_, hipEventDisableTiming));
+    LD_HIP(hipMemsetAsync(nact_, 0, sizeof(int), st));
+    LD_LAUNCH(LD_PROF_SMALL, 0,
+              launch_quad_check(st, kB_, m_, H_, meff_, quad_a(), quad_b(), t + 1, active_, kprev_,
+                                p_.adapt_tol, mult_ptr(t + 1), flags_, nact_));
+    LD_HIP(hipMemcpyAsync(nact_host_, nact_, sizeof(int), hipMemcpyDeviceToHost, st));
+    LD_HIP(hipEventRecord(check_ev_, st));
+    pending_check_ = true;
+  }
   return LD_OK;
 }
 
 ld_status Run::run_epilogue(hipStream_t st) {
   if (p_.method != LD_METHOD_OSA_IOP) {
-    LD_LAUNCH(LD_PROF_SMALL, 0, launch_gauss_log(st, B_, m_, H_, meff_, K_, flags_));
+    // K = e1^T log(T) e1 per run by the trapezoidal Stieltjes rule; runs whose
+    // Ritz values leave the operator's spectral interval go to Golub-Welsch
+    LD_LAUNCH(LD_PROF_SMALL, 0,
+              launch_quad_log(st, B_, m_, H_, meff_, quad_a(), quad_b(), K_, need_, flags_));
+    LD_LAUNCH(LD_PROF_SMALL, 0, launch_gauss_log(st, B_, m_, H_, meff_, K_, flags_, need_));
   } else {
     // x^T L_c x / ||x||^2 = sum_t g_t (log H e1)_t + log(gamma) - c
     LD_LAUNCH(LD_PROF_SMALL, 0,
@@ -590,6 +617,21 @@ ld_status Run::advance(hipStream_t st, int budget, bool* done) {
         break;
       }
       case ST_KRYLOV: {
+        if (pending_check_) {
+          // all runs stopped by the adaptive test: skip the remaining steps
+          if (blocking_) LD_HIP(hipEventSynchronize(check_ev_));
+          const hipError_t q = hipEventQuery(check_ev_);
+          if (q == hipSuccess) {
+            pending_check_ = false;
+            if (*nact_host_ == 0) {
+              t_ = m_;
+              stage_ = ST_EPILOGUE;
+              break;
+            }
+          } else if (q != hipErrorNotReady) {
+            LD_HIP(q);
+          }
+        }
         ld_status rc = run_krylov_step(st, t_);
         if (rc != LD_OK) return rc;
         ++t_;
@@ -928,6 +970,7 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
   Run run(a, *p);
   run.set_submit_time(t0);
   run.set_profiler(&ctx->prof);
+  run.set_blocking(true);
   ld_status rc = run.validate();
   if (rc != LD_OK) return rc;
   const size_t need = run.device_bytes();

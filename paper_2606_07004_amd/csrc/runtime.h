@@ -182,6 +182,18 @@ class Run {
   // asymmetry of H accepted by the symmetric fast path of log(H) e1: rounding
   // level of the vectors' precision
   double symtol() const { return mixed_ ? 1e-5 : 1e-12; }
+  // spectral interval of the Gauss-quadrature runs' operator (Q / scale)
+  double quad_a() const { return lo_ / scale_; }
+  double quad_b() const { return hi_ / scale_; }
+  bool adaptive() const { return p_.adapt_tol > 0.0 && p_.method != LD_METHOD_OSA_IOP &&
+                                 (p_.method == LD_METHOD_OSLQ || kphase_ == 1); }
+  // adaptive Krylov dimension
+  int* nact_ = nullptr;        // device: runs still active after a check
+  int* nact_host_ = nullptr;   // pinned copy
+  double* kprev_ = nullptr;    // [ld] quadrature value at the previous check
+  hipEvent_t check_ev_ = nullptr;
+  bool pending_check_ = false;
+  bool blocking_ = false;
   size_t part_elems_ = 0;
   size_t slot_elems_ = 0;     // elements of one [n][ld] slot
   int nslots_ = 0;
@@ -191,6 +203,7 @@ class Run {
   Profiler* prof_ = nullptr;
  public:
   void set_profiler(Profiler* p) { prof_ = p; }
+  void set_blocking(bool b) { blocking_ = b; }
   double submit_time() const { return t_submit_; }
   void set_submit_time(double t) { t_submit_ = t; }
   int64_t n() const { return n_; }
