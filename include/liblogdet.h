@@ -179,6 +179,10 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz,
 ld_status ld_destroy(ld_matrix* a);
 /* The spectral interval the estimators will use for this matrix. */
 ld_status ld_matrix_bounds(const ld_matrix* a, double* lambda_lo, double* lambda_hi);
+/* x^T Q x for a host vector x[n] (caller-owned), on the device in FP64: the
+ * data term of the Gaussian log-likelihood of Section 4,
+ * L(theta) = log det Q / 2 - x^T Q x / 2 - n log(2 pi) / 2.  Blocking. */
+ld_status ld_quad_form(ld_matrix* a, const double* x, double* out);
 
 /* Blocking estimate with the context's default method and precision and
  * tol = 1e-10 (Alg 3 for OSLQ, Alg 2 for OSA-IOP). */

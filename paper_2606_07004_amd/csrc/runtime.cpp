@@ -960,6 +960,41 @@ ld_status ld_matrix_bounds(const ld_matrix* a, double* lo, double* hi) {
   return LD_OK;
 }
 
+ld_status ld_quad_form(ld_matrix* a, const double* x, double* out) {
+  if (!a || !x || !out) return set_error(LD_E_INVALID_ARG, "null argument");
+  ld_ctx* ctx = a->ctx;
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  LD_HIP_API(hipSetDevice(ctx->device));
+  const int64_t n = a->n;
+  // x as column 0 of an [n][4] FP64 block (the product kernels' minimum
+  // width); W = Q X with the inner product x^T (Q x) fused in the epilogue
+  const int ld = 4;
+  const Geom g = make_geom(n, ld, 8);
+  std::vector<double> hx((size_t)n * ld, 0.0);
+  for (int64_t i = 0; i < n; ++i) hx[(size_t)i * ld] = x[i];
+  DeviceBuffer buf;
+  const size_t vec = (size_t)n * ld * 8;
+  const size_t part = (size_t)kMaxBlocks * ld * 8;
+  LD_HIP_API(buf.ensure(2 * vec + part + 64));
+  char* base = static_cast<char*>(buf.ptr);
+  double* X = reinterpret_cast<double*>(base);
+  double* W = reinterpret_cast<double*>(base + vec);
+  double* pt = reinterpret_cast<double*>(base + 2 * vec);
+  double* res = reinterpret_cast<double*>(base + 2 * vec + part);
+  LD_HIP_API(hipMemcpyAsync(X, hx.data(), vec, hipMemcpyHostToDevice, ctx->stream));
+  VecSet vs{};
+  vs.x[0] = X;
+  int nb = 0;
+  LD_HIP_API(launch_spmm(ctx->stream, g, a->rp, a->ci, a->v64, VT_F64, X, W, nullptr, 1.0, &vs, 1,
+                         0, pt, &nb));
+  LD_HIP_API(launch_reduce(ctx->stream, pt, nb, ld, res));
+  double r[4];
+  LD_HIP_API(hipMemcpyAsync(r, res, sizeof(r), hipMemcpyDeviceToHost, ctx->stream));
+  LD_HIP_API(hipStreamSynchronize(ctx->stream));
+  *out = r[0];
+  return LD_OK;
+}
+
 ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
                              const ld_detail* detail) {
   if (!a || !p || !out) return set_error(LD_E_INVALID_ARG, "null argument");

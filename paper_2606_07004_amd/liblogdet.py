@@ -89,6 +89,7 @@ _SIGNATURES = [
                                   C.c_double, C.c_double, C.POINTER(C.c_void_p)]),
     ("ld_destroy", C.c_int32, [C.c_void_p]),
     ("ld_matrix_bounds", C.c_int32, [C.c_void_p, _DP, _DP]),
+    ("ld_quad_form", C.c_int32, [C.c_void_p, _DP, _DP]),
     ("ld_estimate", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                 C.c_uint64, C.POINTER(ld_result)]),
     ("ld_estimate_ex", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(ld_result)]),
@@ -232,6 +233,14 @@ def ld_estimate_detail(a, params: ld_params, n: Optional[int] = None, tri: bool 
     res = ld_result()
     _check(lib().ld_estimate_detail(a, C.byref(params), C.byref(res), C.byref(det)))
     return res, arrays
+
+
+def ld_quad_form(a, x) -> float:
+    """x^T Q x on the device (FP64)."""
+    xv = np.ascontiguousarray(x, dtype=np.float64)
+    out = C.c_double()
+    _check(lib().ld_quad_form(a, xv.ctypes.data_as(_DP), C.byref(out)))
+    return out.value
 
 
 def ld_submit(a, params: ld_params) -> int:

@@ -184,6 +184,71 @@ def wendland(n: int, nnz_per_row: float = 48.0, nugget: float = 1e-2,
     return _from_scipy(m, f"wendland_{n}_nugget{nugget:g}_seed{seed}")
 
 
+def wendland_grid(ny: int, nx: int, rho: float, nugget: float = 1e-2, scale: float = 1.0) -> Csr:
+    """Wendland C2 covariance matrix on the ny x nx unit-spaced grid.
+
+    Grid point (iy, ix) is row iy * nx + ix; the entry between points at
+    distance r < rho is scale * phi(r) with phi(r) = (1 - r/rho)^4 (4 r/rho + 1),
+    the diagonal scale + nugget.  On a grid every interior row holds the same
+    stencil of about pi rho^2 entries; columns are sorted within a row.
+    """
+    n = ny * nx
+    R = int(math.ceil(rho))
+    offs = [(dy, dx) for dy in range(-R, R + 1) for dx in range(-R, R + 1)
+            if dy * dy + dx * dx < rho * rho]
+    iy = np.repeat(np.arange(ny, dtype=np.int64), nx)
+    ix = np.tile(np.arange(nx, dtype=np.int64), ny)
+    noff = len(offs)
+    cols = np.empty((n, noff), dtype=np.int64)
+    vals = np.empty(noff, dtype=np.float64)
+    for j, (dy, dx) in enumerate(offs):  # (dy, dx) ascending: columns ascending
+        ok = (iy + dy >= 0) & (iy + dy < ny) & (ix + dx >= 0) & (ix + dx < nx)
+        c = (iy + dy) * nx + (ix + dx)
+        c[~ok] = -1
+        cols[:, j] = c
+        r = math.sqrt(dy * dy + dx * dx) / rho
+        vals[j] = scale * (1.0 - r) ** 4 * (4.0 * r + 1.0) + (nugget if (dy, dx) == (0, 0) else 0.0)
+    valid = cols >= 0
+    counts = valid.sum(axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] >= 2**31:
+        raise ValueError("wendland_grid: nnz does not fit int32")
+    col_idx = cols[valid].astype(np.int32)
+    values = np.broadcast_to(vals, (n, noff))[valid].copy()
+    del cols, valid
+    return Csr(n=n, row_ptr=row_ptr.astype(np.int32), col_idx=col_idx, values=values,
+               name=f"wendland_grid_{ny}x{nx}_rho{rho:g}_nugget{nugget:g}")
+
+
+def grf_field(ny: int, nx: int, seed: int = 0, waves: int = 16) -> np.ndarray:
+    """Seeded smooth synthetic field on the grid (row-major, unit variance):
+    a sum of plane waves with wavelengths between 10 and 200 grid cells and
+    random phases, plus white noise of standard deviation 0.1 (PCG64(seed))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    iy = np.repeat(np.arange(ny, dtype=np.float64), nx)
+    ix = np.tile(np.arange(nx, dtype=np.float64), ny)
+    x = np.zeros(ny * nx)
+    for _ in range(waves):
+        lam = math.exp(rng.uniform(math.log(10.0), math.log(200.0)))
+        ang = rng.uniform(0.0, math.pi)
+        ph = rng.uniform(0.0, 2 * math.pi)
+        k = 2 * math.pi / lam
+        x += rng.standard_normal() * np.cos(k * (math.cos(ang) * ix + math.sin(ang) * iy) + ph)
+    x /= max(float(np.std(x)), 1e-300)
+    return x + 0.1 * rng.standard_normal(ny * nx)
+
+
+# GRF likelihood sweep (Section 4): candidate parameters and the support
+# radius of each on the unit-spaced grid.  The paper does not state the
+# units of theta; here rho = theta / 10 grid spacings.
+GRF_THETAS = (20, 30, 40, 50, 60, 70, 80)
+
+
+def grf_rho(theta: float) -> float:
+    return theta / 10.0
+
+
 def diag_matrix(values) -> Csr:
     """Diagonal matrix (breakdown cases: d distinct values stop a Krylov run
     after d steps)."""
