@@ -48,13 +48,18 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--cpu-probes", type=int, default=3)
+    ap.add_argument("--cpu-probes", type=int, default=12)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-nmax", type=float, default=2e5)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--copy-bytes", type=float, default=805306368,
                     help="bytes of the copy-kernel calibration (0 to skip)")
+    ap.add_argument("--no-comparators", action="store_true",
+                    help="skip the SLQ / So-SLQ / adaptive / OSA-IOP leg on the same matrix")
+    ap.add_argument("--no-grf", action="store_true",
+                    help="skip the GRF likelihood theta-sweep leg")
+    ap.add_argument("--grf-grid", type=str, default="900x1200")
     return ap.parse_args()
 
 
@@ -129,8 +134,83 @@ def cpu_baseline(a, args):
                       f"{steps} probe-steps in {dt:.1f} s"}
 
 
+def comparators_bench(L, W, ctx, h, a, vt, args):
+    """The paper's comparison (SLQ, So-SLQ, OSLQ, OSA-IOP, Section 4) redone on
+    the benchmark matrix: one estimate each after a warm-up, the same total
+    probe count, mixed precision; error against the closed form."""
+    exact = W.lap3d_exact_logdet(args.grid, args.shift) if args.grid in (64, 128) else None
+    npr, m, win = args.probes, args.krylov_steps, args.window
+    cases = {
+        "slq": L.make_params(npr, 0, m, win, args.seed),
+        "oslq": L.make_params(npr, args.sketch, m, win, args.seed),
+        "oslq_adaptive_1e-6": L.make_params(npr, args.sketch, m, win, args.seed, adapt_tol=1e-6,
+                                             adapt_every=5),
+        "so_slq_q30_k10": L.make_params(30 + (npr - args.sketch), 30, m, win, args.seed,
+                                        method=L.LD_METHOD_SO_SLQ, subspace_rank=10,
+                                        probe_dist=L.LD_PROBE_GAUSSIAN),
+        "osa_iop": L.make_params(npr, args.sketch, m, win, args.seed,
+                                 method=L.LD_METHOD_OSA_IOP),
+    }
+    out = {}
+    for name, p in cases.items():
+        p.precision = L.LD_PREC_MIXED if args.precision == "mixed" else L.LD_PREC_FP64
+        L.ld_estimate_ex(h, p)
+        t0 = time.perf_counter()
+        r = L.ld_estimate_ex(h, p)
+        dt = time.perf_counter() - t0
+        rec = {"logdet": r.logdet, "ms": dt * 1e3, "device_ms": r.device_ms,
+               "probe_steps": r.probe_steps, "probe_steps_per_s": r.probe_steps / dt,
+               "matvecs": r.matvecs, "min_steps": r.min_steps}
+        if exact:
+            rec["rel_err_vs_closed_form"] = abs(r.logdet - exact) / abs(exact)
+        out[name] = rec
+        print(f"[bench] comparator {name} {rec}", file=sys.stderr, flush=True)
+    return out
+
+
+def grf_bench(L, W, args):
+    """GRF likelihood sweep (Section 4): the seven theta candidates on the
+    900 x 1200 grid, Wendland covariance with support radius theta/10 grid
+    spacings and nugget 1e-2, all requests in flight together; the paper's
+    settings for each estimator (OSLQ: 60 steps, 30 probes; OSA-IOP: 20
+    steps, 21 probes, tol 1e-6), mixed precision."""
+    from paper_2606_07004_amd import grf
+    ny, nx = (int(v) for v in args.grf_grid.split("x"))
+    x = W.grf_field(ny, nx, seed=11)
+    legs = {
+        "oslq": L.make_params(30, 10, 60, 2, args.seed, precision=L.LD_PREC_MIXED),
+        "osa_iop": L.make_params(21, 7, 20, 2, args.seed, method=L.LD_METHOD_OSA_IOP,
+                                 precision=L.LD_PREC_MIXED, tol=1e-6),
+    }
+    cache = {}
+
+    def make(th):
+        if th not in cache:
+            cache[th] = W.wendland_grid(ny, nx, W.grf_rho(th), nugget=1e-2)
+        return cache[th]
+
+    t0 = time.perf_counter()
+    for th in W.GRF_THETAS:
+        make(th)
+    build_s = time.perf_counter() - t0
+    out = {"grid": f"{ny}x{nx}", "n": ny * nx, "thetas": list(W.GRF_THETAS),
+           "nnz": [cache[th].nnz for th in W.GRF_THETAS], "host_build_s": build_s}
+    with L.Context(0, max_slots=8) as c:
+        for name, p in legs.items():
+            recs = grf.theta_sweep(c, W.GRF_THETAS, make, x, p, lo_hint=lambda th: 1e-2,
+                                   vt=L.LD_VT_FP32)
+            out[name] = {"sweep_wall_s": recs[0]["sweep_wall_s"],
+                         "logdets_per_s": len(recs) / recs[0]["sweep_wall_s"],
+                         "best_theta": grf.best_theta(recs),
+                         "logdet": [r["logdet"] for r in recs],
+                         "loglik": [r["loglik"] for r in recs],
+                         "latency_ms": [r["latency_ms"] for r in recs]}
+            print(f"[bench] grf {name} {out[name]}", file=sys.stderr, flush=True)
+    return out
+
+
 def serving_bench(L, W, args):
-    """Served log-determinants (SURVEY C5 shape): requests of uneven n,
+    """Served log-determinants (the serving workload): requests of uneven n,
     kind and Krylov depth.  Baseline: plain FP64 estimates one at a time.
     Served: mixed precision through ld_submit with continuous batching,
     (i) all requests at t = 0 (throughput), (ii) Poisson arrivals at 0.7x the
@@ -146,7 +226,10 @@ def serving_bench(L, W, args):
           flush=True)
     ctx = L.Context(0, max_slots=args.serve_slots)
     try:
-        hs = [ctx.matrix(a, vt=L.LD_VT_FP32, lo_hint=(r["shift"] if r["kind"] == "wendland" else 0.0))
+        # FP64 storage: the mixed requests read FP64 values with FP64 row sums
+        # (FP32 vectors), which keeps ill-conditioned requests (small nuggets)
+        # well inside the 1e-4 gate
+        hs = [ctx.matrix(a, vt=L.LD_VT_FP64, lo_hint=(r["shift"] if r["kind"] == "wendland" else 0.0))
               for a, r in zip(mats, reqs)]
 
         def params(r, prec):
@@ -210,7 +293,7 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "
                                    "layout (probe-parallel runs, one all-gather of the sketch) "
-                                   "is described in DESIGN.md but not built"}))
+                                   "is designed (see the design notes) but not built"}))
         sys.exit(2)
     import workloads as W
     from paper_2606_07004_amd import liblogdet as L
@@ -294,10 +377,18 @@ def main():
         copy = {"bytes": nb, "ms": ms, "GB/s": 2 * nb / (ms * 1e-3) / 1e9}
         print(f"[bench] copy calibration {copy}", file=sys.stderr, flush=True)
 
+    comparators = None
+    if not args.no_comparators:
+        comparators = comparators_bench(L, W, ctx, h, a, vt, args)
+
     serving = None
     if not args.no_serving:
         serving = serving_bench(L, W, args)
         print(f"[bench] serving {serving}", file=sys.stderr, flush=True)
+
+    grf_sweep = None
+    if not args.no_grf:
+        grf_sweep = grf_bench(L, W, args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -330,6 +421,8 @@ def main():
         "accuracy": accuracy,
         "kernel_families": families,
         "serving": serving,
+        "comparators": comparators,
+        "grf_sweep": grf_sweep,
         "copy_kernel": copy,
         "device_ms_per_step": device_ms_total / args.steps,
     }

@@ -71,9 +71,10 @@ typedef enum { LD_METHOD_OSLQ = 0, LD_METHOD_OSA_IOP = 1, LD_METHOD_SO_SLQ = 2 }
 typedef enum { LD_PROBE_RADEMACHER = 0, LD_PROBE_GAUSSIAN = 1 } ld_probe_dist;
 
 /* LD_PREC_FP64: every vector, product and reduction in FP64.
- * LD_PREC_MIXED: Krylov vectors and sparse products in FP32 (matrix values
- * in the matrix's storage type: FP32, or BF16 widened to FP32); every inner
- * product and norm accumulated in FP64; sketch QR, projection, the small
+ * LD_PREC_MIXED: Krylov vectors in FP32; sparse products read the matrix in
+ * its storage type (FP32 or BF16 values with FP32 row sums; FP64 values with
+ * FP64 row sums, rounded to FP32 once per entry); every inner product and
+ * norm accumulated in FP64; sketch QR, projection, the small
  * tridiagonal/Hessenberg reductions and the trace in FP64. */
 typedef enum { LD_PREC_FP64 = 0, LD_PREC_MIXED = 1 } ld_precision;
 

@@ -7,6 +7,7 @@
 // probe values.  Every reduction goes through per-block partial sums in a
 // fixed order (no floating-point atomics): results are bitwise reproducible.
 #include "ld_kernels.h"
+#include <type_traits>
 #include "gw_ql.h"
 
 #include <algorithm>
@@ -178,7 +179,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const 
                                                   const double* __restrict__ xmult,
                                                   double opscale, VecSet vs, int voff,
                                                   double* __restrict__ part) {
-  using A = typename Acc<XT>::type;
+  // FP32 sums for FP32 (or BF16) values on FP32 vectors; FP64 sums whenever
+  // the values or the vectors are FP64
+  using A = typename std::conditional<std::is_same<VT, double>::value, double,
+                                      typename Acc<XT>::type>::type;
   constexpr int VEC = V16<XT>::N;
   constexpr bool FUSED = NF > 0;
   // one fused product: its per-thread FP64 sums live in the thread's own LDS
@@ -890,6 +894,9 @@ hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* 
   } else {
     const float* x = static_cast<const float*>(X);
     float* w = static_cast<float*>(W);
+    if (vt == VT_F64)
+      return spmm_typed<double, float>(st, g, rp, ci, static_cast<const double*>(va), x, w, xmult,
+                                       opscale, vs, nf, voff, part, nblk_out);
     if (vt == VT_F32)
       return spmm_typed<float, float>(st, g, rp, ci, static_cast<const float*>(va), x, w, xmult,
                                       opscale, vs, nf, voff, part, nblk_out);

@@ -341,7 +341,7 @@ ld_status Run::bind(void* base, size_t bytes) {
 // Algorithmic bytes of one CSR x block product: the matrix once (values,
 // column indices, row pointers), the input block once, the output block once.
 double Run::spmm_bytes(int ld, int xbytes) const {
-  const int vb = mixed_ ? (a_->vt_lo == VT_BF16 ? 2 : 4) : 8;
+  const int vb = mixed_ ? (a_->vt_lo == VT_BF16 ? 2 : (a_->vt_lo == VT_F32 ? 4 : 8)) : 8;
   return (double)a_->nnz * (vb + 4) + 4.0 * (n_ + 1) + 2.0 * (double)n_ * ld * xbytes;
 }
 
@@ -422,7 +422,7 @@ ld_status Run::run_prologue(hipStream_t st) {
   LD_HIP(hipEventRecord(ev0_, st));
   LD_HIP(hipMemsetAsync(flags_, 0, (size_t)ldB_ * 4, st));
   LD_HIP(hipMemsetAsync(dflag_, 0, 16, st));
-  const void* vals_sketch = mixed_ ? a_->vlo : a_->v64;
+  const void* vals_sketch = (mixed_ && a_->vlo) ? a_->vlo : a_->v64;
   const int vt_sketch = mixed_ ? a_->vt_lo : VT_F64;
   if (p_.method == LD_METHOD_OSLQ) {
     if (s_ > 0) {
@@ -510,7 +510,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
     return static_cast<char*>(kslots_) + (size_t)slot_of(j) * slot_elems_ * eb;
   };
   auto mult_ptr = [&](int j) -> double* { return kmult_ + (size_t)slot_of(j) * kld_; };
-  const void* vals = mixed_ ? a_->vlo : a_->v64;
+  const void* vals = (mixed_ && a_->vlo) ? a_->vlo : a_->v64;
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
   const double vec_bytes = (double)n_ * kld_ * xb_;
   void* W = slot_ptr(t + 1);
@@ -883,9 +883,12 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
   hipError_t e = hipMalloc(&m->rp, (size_t)(n + 1) * 4);
   if (e == hipSuccess) e = hipMalloc(&m->ci, (size_t)nnz * 4);
   if (e == hipSuccess) e = hipMalloc(&m->v64, (size_t)nnz * 8);
-  m->vt_lo = (vt == LD_VT_BF16) ? VT_BF16 : VT_F32;
-  const size_t lo_bytes = (size_t)nnz * (m->vt_lo == VT_BF16 ? 2 : 4);
-  if (e == hipSuccess) e = hipMalloc(&m->vlo, lo_bytes);
+  // mixed-precision runs read the values in the storage type: FP32 or BF16
+  // copies, or (FP64 storage) the FP64 values themselves
+  m->vt_lo = (vt == LD_VT_BF16) ? VT_BF16 : (vt == LD_VT_FP32 ? VT_F32 : VT_F64);
+  const size_t lo_bytes =
+      m->vt_lo == VT_F64 ? 0 : (size_t)nnz * (m->vt_lo == VT_BF16 ? 2 : 4);
+  if (e == hipSuccess && lo_bytes > 0) e = hipMalloc(&m->vlo, lo_bytes);
   if (e != hipSuccess) {
     cleanup();
     return set_error(e == hipErrorOutOfMemory ? LD_E_NO_MEMORY : LD_E_DEVICE,
@@ -896,14 +899,15 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
   if (m->vt_lo == VT_BF16) {
     uint16_t* h = reinterpret_cast<uint16_t*>(lo_host.data());
     for (int64_t k = 0; k < nnz; ++k) h[k] = double_to_bf16_rne(values[k]);
-  } else {
+  } else if (m->vt_lo == VT_F32) {
     float* h = reinterpret_cast<float*>(lo_host.data());
     for (int64_t k = 0; k < nnz; ++k) h[k] = (float)values[k];
   }
   e = hipMemcpy(m->rp, row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->ci, col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(m->v64, values, (size_t)nnz * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->vlo, lo_host.data(), lo_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess && lo_bytes > 0)
+    e = hipMemcpy(m->vlo, lo_host.data(), lo_bytes, hipMemcpyHostToDevice);
   // Gershgorin interval (Section 2.1), on the device
   double* part = nullptr;
   const int nb = (int)((n + kThreads - 1) / kThreads);
