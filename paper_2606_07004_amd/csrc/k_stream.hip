@@ -171,7 +171,7 @@ __device__ inline void block_partials(const double (&acc)[C][VEC], double* red, 
 // part[voff+v][col][block] = mult_v[col] * sum_rows x_v[row][col] w[row][col].
 // ---------------------------------------------------------------------------
 template <typename VT, typename XT, int C, int NF>
-__global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const int* __restrict__ rp,
+__global__ __launch_bounds__(kThreads, (NF == 2 || sizeof(VT) > sizeof(XT)) ? 4 : 6) void k_spmm(int64_t n, int lgL, const int* __restrict__ rp,
                                                   const int* __restrict__ ci,
                                                   const VT* __restrict__ va,
                                                   const XT* __restrict__ X, XT* __restrict__ W,
@@ -227,11 +227,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const 
     for (int c = 0; c < C; ++c)
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[c][e] = A(0);
-    int k = rp[row];
-    const int kend = rp[row + 1];
-    for (; k + 2 <= kend; k += 2) {
-      const int c0 = ci[k], c1 = ci[k + 1];
-      const A a0 = value_as<VT, A>(va[k]), a1 = value_as<VT, A>(va[k + 1]);
+    // accumulate a_k x_k in entry order; two entries' gathers in flight
+    auto step2 = [&](int c0, A a0, int c1, A a1) {
       V16<XT> x0[C], x1[C];
 #pragma unroll
       for (int c = 0; c < C; ++c)
@@ -252,10 +249,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const 
             if (c1 == row) xd[c] = x1[c];
           }
         }
-    }
-    if (k < kend) {
-      const int c0 = ci[k];
-      const A a0 = value_as<VT, A>(va[k]);
+    };
+    auto step1 = [&](int c0, A a0) {
 #pragma unroll
       for (int c = 0; c < C; ++c)
         if (okc[c]) {
@@ -265,6 +260,25 @@ __global__ __launch_bounds__(kThreads, 4) void k_spmm(int64_t n, int lgL, const 
           for (int e = 0; e < VEC; ++e) acc[c][e] = fma(a0, x.v[e], acc[c][e]);
           if (FUSED && c0 == row) xd[c] = x;
         }
+    };
+    const int kbeg = rp[row];
+    const int kend = rp[row + 1];
+    // the row's L lanes load L consecutive entries (column, value) once and
+    // pass them around the group by lane shuffles
+    for (int base = kbeg; base < kend; base += rm.L) {
+      const int kk = base + rm.gl;
+      int myc = row;
+      A mya = A(0);
+      if (kk < kend) {
+        myc = ci[kk];
+        mya = value_as<VT, A>(va[kk]);
+      }
+      const int cnt = min(rm.L, kend - base);
+      int j = 0;
+      for (; j + 2 <= cnt; j += 2)
+        step2(__shfl(myc, j, rm.L), __shfl(mya, j, rm.L), __shfl(myc, j + 1, rm.L),
+              __shfl(mya, j + 1, rm.L));
+      if (j < cnt) step1(__shfl(myc, j, rm.L), __shfl(mya, j, rm.L));
     }
 #pragma unroll
     for (int c = 0; c < C; ++c)
