@@ -279,6 +279,216 @@ __global__ __launch_bounds__(kThreads) void k_subspace_eig(int q, int k, const d
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 matrix-core (MFMA) versions of the tall-skinny contractions of the
+// sketch: Gram blocks X_a^T X_b, rows times a small matrix, and the
+// projection of the residual probes.  v_mfma_f64_16x16x4f64 multiplies a
+// 16 x 4 block by a 4 x 16 block into a 16 x 16 accumulator; its lanes
+// (measured on gfx950): lane l carries A[l % 16][l / 16] and B[l / 16][l % 16],
+// and element e of lane l's accumulator is D[4 e + l / 16][l % 16].
+// ---------------------------------------------------------------------------
+typedef double dmf4 __attribute__((ext_vector_type(4)));
+
+__device__ inline dmf4 mfma_f64(double a, double b, dmf4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// part[i][j][block] = sum over the block's rows of Xa[row][i] Xb[row][j]:
+// one wave per (row block, group of TI x TJ output tiles of 16 x 16); the k
+// dimension of the product is the row index, 4 rows per instruction.
+template <int TI, int TJ>
+__global__ __launch_bounds__(64) void k_gemm_tn_mfma(int64_t n, int rpb, const double* __restrict__ Xa,
+                                                    int lda, int ca, const double* __restrict__ Xb,
+                                                    int ldb, int cb, int ngj,
+                                                    double* __restrict__ part) {
+  const int l = threadIdx.x;
+  const int gi = blockIdx.y / ngj, gj = blockIdx.y % ngj;
+  const int b = blockIdx.x;
+  const int64_t r0 = (int64_t)b * rpb;
+  const int64_t r1 = min(n, r0 + (int64_t)rpb);
+  const int kr = l >> 4, cl = l & 15;
+  int ia[TI], jb[TJ];
+  bool oka[TI], okb[TJ];
+#pragma unroll
+  for (int t = 0; t < TI; ++t) {
+    ia[t] = (gi * TI + t) * 16 + cl;
+    oka[t] = ia[t] < ca;
+  }
+#pragma unroll
+  for (int t = 0; t < TJ; ++t) {
+    jb[t] = (gj * TJ + t) * 16 + cl;
+    okb[t] = jb[t] < cb;
+  }
+  dmf4 acc[TI][TJ];
+#pragma unroll
+  for (int x = 0; x < TI; ++x)
+#pragma unroll
+    for (int y = 0; y < TJ; ++y) acc[x][y] = dmf4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int64_t base = r0; base < r1; base += 4) {
+    const int64_t row = base + kr;
+    const bool okr = row < r1;
+    double a[TI], bb[TJ];
+#pragma unroll
+    for (int t = 0; t < TI; ++t) a[t] = (okr && oka[t]) ? Xa[(size_t)row * lda + ia[t]] : 0.0;
+#pragma unroll
+    for (int t = 0; t < TJ; ++t) bb[t] = (okr && okb[t]) ? Xb[(size_t)row * ldb + jb[t]] : 0.0;
+#pragma unroll
+    for (int x = 0; x < TI; ++x)
+#pragma unroll
+      for (int y = 0; y < TJ; ++y) acc[x][y] = mfma_f64(a[x], bb[y], acc[x][y]);
+  }
+#pragma unroll
+  for (int x = 0; x < TI; ++x)
+#pragma unroll
+    for (int y = 0; y < TJ; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = (gi * TI + x) * 16 + 4 * e + kr, j = (gj * TJ + y) * 16 + cl;
+        if (i < ca && j < cb) part[((size_t)i * cb + j) * gridDim.x + b] = acc[x][y][e];
+      }
+}
+
+// Y[row][j] <- sum_{i < s} Y[row][i] M[i][j] for j < sout (s, sout <= 64):
+// one wave per 16-row tile, M (zero-padded to 64 x 64) in LDS; all of a
+// tile's reads precede its writes (the accumulators need every k step), so
+// the update is in place.
+constexpr int kMfmaMaxCols = 64;
+
+__global__ __launch_bounds__(kThreads) void k_rows_mat_mfma(int64_t n, double* __restrict__ Y, int ld,
+                                                           int s, const double* __restrict__ M,
+                                                           int sout) {
+  __shared__ double sM[kMfmaMaxCols * kMfmaMaxCols];
+  for (int e = threadIdx.x; e < kMfmaMaxCols * kMfmaMaxCols; e += kThreads) {
+    const int i = e / kMfmaMaxCols, j = e % kMfmaMaxCols;
+    sM[e] = (i < s && j < sout) ? M[(size_t)i * sout + j] : 0.0;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int kr = l >> 4, cl = l & 15;
+  const int64_t row0 = ((int64_t)blockIdx.x * (kThreads / 64) + w) * 16;
+  if (row0 >= n) return;
+  const int s4 = (s + 3) & ~3, ntile = (sout + 15) / 16;
+  dmf4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = dmf4{0.0, 0.0, 0.0, 0.0};
+  const int64_t arow = row0 + cl;
+  for (int k0 = 0; k0 < s4; k0 += 4) {
+    const int kk = k0 + kr;
+    const double a = (arow < n && kk < s) ? Y[(size_t)arow * ld + kk] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < ntile) acc[t] = mfma_f64(a, sM[kk * kMfmaMaxCols + t * 16 + cl], acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    if (t < ntile)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = row0 + 4 * e + kr;
+        const int j = t * 16 + cl;
+        if (row < n && j < sout) Y[(size_t)row * ld + j] = acc[t][e];
+      }
+}
+
+// Start block [A | G - A P] (s <= 64, r <= 256, P in LDS) and the per-block
+// partial squared column norms (FP64 values before narrowing): one wave per
+// 16-row tile of the block's rows, the product A P on the matrix cores in
+// chunks of 4 column tiles.  Column norms: each lane sums its column over
+// its rows, the four lanes of a column are combined by a fixed shuffle tree,
+// the block's waves in wave order.
+template <typename XT>
+__global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, const double* __restrict__ A,
+                                                          int lda, int s, const double* __restrict__ Gm,
+                                                          int ldg, int r, const double* __restrict__ P,
+                                                          XT* __restrict__ X0, int ld,
+                                                          double* __restrict__ part) {
+  extern __shared__ double sm[];
+  const int r16 = (r + 15) & ~15, s4 = (s + 3) & ~3;
+  double* sP = sm;                                  // [s4][r16]
+  double* sN = sm + (size_t)s4 * r16;               // [4 waves][kMaxLd] norm partials
+  for (int e = threadIdx.x; e < s4 * r16; e += kThreads) {
+    const int i = e / r16, j = e % r16;
+    sP[e] = (i < s && j < r) ? P[(size_t)i * r + j] : 0.0;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int kr = l >> 4, cl = l & 15;
+  const int64_t rb0 = (int64_t)blockIdx.x * rpb;
+  const int64_t rb1 = min(n, rb0 + (int64_t)rpb);
+  const int ntile = r16 / 16;
+  double nrm_res[16];   // this lane's column (16 t + cl) of the residual part
+#pragma unroll
+  for (int t = 0; t < 16; ++t) nrm_res[t] = 0.0;
+  double nrm_a = 0.0;   // column l of the sketch part (l < s)
+  for (int64_t row0 = rb0 + 16 * w; row0 < rb1; row0 += 16 * (kThreads / 64)) {
+    // sketch columns (lane l: column l) and padding columns (lane l: s + r + l)
+    if (l < s) {
+      for (int q = 0; q < 16; ++q) {
+        const int64_t row = row0 + q;
+        if (row >= rb1) break;
+        const double v = A[(size_t)row * lda + l];
+        X0[(size_t)row * ld + l] = XT(v);
+        nrm_a = fma(v, v, nrm_a);
+      }
+    }
+    if (l < ld - s - r) {
+      for (int q = 0; q < 16; ++q) {
+        const int64_t row = row0 + q;
+        if (row >= rb1) break;
+        X0[(size_t)row * ld + s + r + l] = XT(0.0);
+      }
+    }
+    const int64_t arow = row0 + cl;
+    for (int t0 = 0; t0 < ntile; t0 += 4) {
+      dmf4 acc[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = dmf4{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < s4; k0 += 4) {
+        const int kk = k0 + kr;
+        const double a = (arow < rb1 && kk < s) ? A[(size_t)arow * lda + kk] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t0 + t < ntile) acc[t] = mfma_f64(a, sP[kk * r16 + (t0 + t) * 16 + cl], acc[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t0 + t >= ntile) break;
+        const int j = (t0 + t) * 16 + cl;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = row0 + 4 * e + kr;
+          if (row < rb1 && j < r) {
+            const double v = Gm[(size_t)row * ldg + j] - acc[t][e];
+            X0[(size_t)row * ld + s + j] = XT(v);
+            nrm_res[t0 + t] = fma(v, v, nrm_res[t0 + t]);
+          }
+        }
+      }
+    }
+  }
+  // column sums: residual columns over the 4 lanes of a column, then waves
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    double v = nrm_res[t];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    nrm_res[t] = v;
+  }
+  for (int c = threadIdx.x; c < 4 * kMaxLd; c += kThreads) sN[c] = 0.0;
+  __syncthreads();
+  if (l < s) sN[w * kMaxLd + l] = nrm_a;
+  if (kr == 0)
+    for (int t = 0; t < ntile; ++t)
+      if (t * 16 + cl < r) sN[w * kMaxLd + s + t * 16 + cl] = nrm_res[t];
+  __syncthreads();
+  for (int c = threadIdx.x; c < ld; c += kThreads) {
+    double v = 0.0;
+    for (int q = 0; q < kThreads / 64; ++q) v += sN[q * kMaxLd + c];
+    part[(size_t)c * gridDim.x + blockIdx.x] = v;
+  }
+}
+
 // Start block of the Krylov runs: columns [A | G - A P], plus per-block
 // partial squared column norms (FP64 values, before any narrowing).  Rows go
 // through LDS in tiles of tr: the A tile and P (when it fits) are staged,
@@ -386,9 +596,10 @@ hipError_t launch_gemm_tn(hipStream_t st, const Geom& g, const double* Xa, int l
   if (g.n < 1 || g.nblk < 1 || !Xa || !Xb || !part || ca < 1 || cb < 1 || ca > lda || cb > ldb ||
       (int64_t)g.nblk * g.rpb < g.n)
     return hipErrorInvalidValue;
-  const int nt = ((ca + 31) / 32) * ((cb + 31) / 32);
-  hipLaunchKernelGGL(k_gemm_tn, dim3(g.nblk, nt), dim3(kThreads), 0, st, g.n, g.rpb, Xa, lda, ca,
-                     Xb, ldb, cb, part);
+  // 2 x 2 tiles of 16 x 16 per wave on the matrix cores
+  const int ngi = (ca + 31) / 32, ngj = (cb + 31) / 32;
+  hipLaunchKernelGGL((k_gemm_tn_mfma<2, 2>), dim3(g.nblk, ngi * ngj), dim3(64), 0, st, g.n, g.rpb,
+                     Xa, lda, ca, Xb, ldb, cb, ngj, part);
   return hipGetLastError();
 }
 
@@ -401,6 +612,12 @@ hipError_t launch_chol_inv(hipStream_t st, int s, const double* G, double* work,
 
 hipError_t launch_trsm_rows(hipStream_t st, int64_t n, double* Y, int ld, int s, const double* Rinv) {
   if (n < 1 || s < 1 || s > 256 || ld < s || !Y || !Rinv) return hipErrorInvalidValue;
+  if (s <= kMfmaMaxCols) {
+    const int tiles = (int)((n + 15) / 16);
+    hipLaunchKernelGGL(k_rows_mat_mfma, dim3((tiles + 3) / 4), dim3(kThreads), 0, st, n, Y, ld, s,
+                       Rinv, s);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)(16 * s + 16 * s) * sizeof(double);
   hipLaunchKernelGGL(k_rows_mat<true>, dim3((unsigned)((n + 15) / 16)), dim3(kThreads), lds, st, n, Y,
                      ld, s, Rinv, s);
@@ -411,6 +628,12 @@ hipError_t launch_rows_mat(hipStream_t st, int64_t n, double* Y, int ld, int s, 
                            int sout) {
   if (n < 1 || s < 1 || s > 256 || sout < 1 || sout > s || ld < s || !Y || !M)
     return hipErrorInvalidValue;
+  if (s <= kMfmaMaxCols) {
+    const int tiles = (int)((n + 15) / 16);
+    hipLaunchKernelGGL(k_rows_mat_mfma, dim3((tiles + 3) / 4), dim3(kThreads), 0, st, n, Y, ld, s, M,
+                       sout);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)(16 * s + 16 * s) * sizeof(double);
   hipLaunchKernelGGL(k_rows_mat<false>, dim3((unsigned)((n + 15) / 16)), dim3(kThreads), lds, st, n, Y,
                      ld, s, M, sout);
@@ -428,6 +651,20 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
   if (g.n < 1 || g.nblk < 1 || (int64_t)g.nblk * g.rpb < g.n || !Gm || !X0 || !part || r < 1 ||
       s < 0 || s + r > g.ld || g.ld > kThreads || (s > 0 && (!A || !P || lda < s)) || ldg < r)
     return hipErrorInvalidValue;
+  {
+    // matrix cores when P (and the norm partials) fit the block's LDS
+    const size_t r16 = (size_t)((r + 15) & ~15), s4 = (size_t)((s + 3) & ~3);
+    const size_t lds_m = (s4 * r16 + 4 * kMaxLd) * sizeof(double);
+    if (s <= kMfmaMaxCols && r <= 256 && lds_m <= 64 * 1024) {
+      if (g.xbytes == 8)
+        hipLaunchKernelGGL(k_project_mfma<double>, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n, g.rpb,
+                           A, lda, s, Gm, ldg, r, P, static_cast<double*>(X0), g.ld, part);
+      else
+        hipLaunchKernelGGL(k_project_mfma<float>, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n, g.rpb,
+                           A, lda, s, Gm, ldg, r, P, static_cast<float*>(X0), g.ld, part);
+      return hipGetLastError();
+    }
+  }
   // largest row tile (32, 16 or 8) whose staging fits 64 KB, P staged too when it fits
   const size_t budget = 64 * 1024;
   int tr = 32;

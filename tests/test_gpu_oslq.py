@@ -179,3 +179,12 @@ def test_error_paths(L, ctx):
     with pytest.raises(L.LdError) as e:
         L.ld_create_csr(ctx.handle, 2, 3, [0, 2, 3], [1, 0, 1], [1.0, 1.0, 1.0])
     assert e.value.status == L.LD_E_BAD_CSR
+
+
+@pytest.mark.parametrize("s", [1, 63, 64, 65, 80])
+def test_oslq_sketch_widths(L, ctx, s):
+    # sketch widths around the matrix-core limit of the sketch kernels (64
+    # columns): both the MFMA and the scalar Gram / triangular / projection paths
+    a = W.lap2d(45, 0.3)
+    ref, res, det = _check_oslq(L, ctx, a, s + 20, s, 12, 2, 5)
+    _elementwise(ref, det, s, 1e-8)
