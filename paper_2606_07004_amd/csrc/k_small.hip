@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kThreads) void k_hess_log(int B, int m, const doubl
   __shared__ double shd[kThreads + 4];
   __shared__ int shi[kThreads + 4];
   const int p = blockIdx.x;
-  if (p >= B || (need && !need[p])) return;
+  if (p >= B || (need && need[p] != 1)) return;
   const int nn = meff[p];
   double* ws = work + (size_t)p * wstride;
   double* lv = ws + hess_log_workspace(m);  // [m] result
@@ -75,7 +75,7 @@ __global__ void k_hess_log_sym(int B, int m, const double* __restrict__ H,
                                double* __restrict__ K, int* __restrict__ flags,
                                int* __restrict__ need_iss) {
   const int p = blockIdx.x;
-  if (p >= B || threadIdx.x != 0) return;
+  if (p >= B || threadIdx.x != 0 || need_iss[p] != 2) return;
   const int nn = meff[p];
   need_iss[p] = 0;
   if (nn <= 0) {
@@ -131,6 +131,151 @@ __global__ void k_hess_log_sym(int B, int m, const double* __restrict__ H,
     acc += shift;
     if (!isfinite(acc)) flags[p] |= 1;
     K[p] = acc;
+  }
+}
+
+// log(H) e1 for a symmetric H, one wave per run: the same symmetry test and
+// symmetric tridiagonal part T as k_hess_log_sym, then
+//   log(T) e1 = integral over s > 0 of e1/(1+s) - (T + sI)^{-1} e1 ds
+// (the Stieltjes form of the logarithm) by the trapezoidal rule in u = log s
+// with step 1/2 on [log(a) - 40, log(max(b, 1)) + 40], exact to rounding when
+// T's spectrum lies in [a, b].  Each node solves (T + sI) y = e1 by pivots
+// eliminated from the bottom (d_t = alpha_t + s, d_i = alpha_i + s -
+// e_i^2 / d_{i+1}) and the forward recursion y_1 = 1/d_1,
+// y_{i+1} = -e_i y_i / d_{i+1}; component 1 is formed as
+// s (d_1 - 1 - s) / ((1+s) d_1) so nothing cancels.  Nodes run on the lanes;
+// every component is summed over the lanes by a fixed shuffle tree.
+// need[p]: 0 done here, 1 not symmetric (inverse scaling and squaring),
+// 2 symmetric but with an eigenvalue outside [a/1000, 1000 b] or longer than
+// kTrapMaxDim (QL with logged rotations).
+constexpr int kTrapMaxDim = 96;
+constexpr double kTrapStep = 0.5;
+constexpr double kTrapTail = 40.0;
+
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline double wave_max64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ inline int sturm_count_below(int nn, const double* al, const double* e, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (int i = 0; i < nn; ++i) {
+    q = al[i] - x - (i > 0 ? e[i - 1] * e[i - 1] / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(64) void k_hess_log_trap(int B, int m, const double* __restrict__ H,
+                                                     const int* __restrict__ meff, double a,
+                                                     double b, double symtol, int mode,
+                                                     double* __restrict__ ell,
+                                                     const double* __restrict__ g, double shift,
+                                                     double* __restrict__ K,
+                                                     int* __restrict__ flags,
+                                                     int* __restrict__ need) {
+  __shared__ double al[kTrapMaxDim], ee[kTrapMaxDim], lv[kTrapMaxDim];
+  __shared__ double piv[64 * kTrapMaxDim];
+  const int p = blockIdx.x, l = threadIdx.x;
+  if (p >= B) return;
+  const int nn = meff[p];
+  if (nn <= 0) {
+    if (l == 0) {
+      need[p] = 0;
+      if (mode == 1) K[p] = 0.0;
+    }
+    if (mode == 0)
+      for (int t = l; t < m; t += 64) ell[(size_t)p * m + t] = 0.0;
+    return;
+  }
+  const double* Hp = H + (size_t)p * (m + 1) * m;
+  double hmax = 0.0, asym = 0.0;
+  for (int i = l; i < nn; i += 64)
+    for (int j = (i > 0 ? i - 1 : 0); j < nn; ++j) {
+      const double h = Hp[(size_t)i * m + j];
+      hmax = fmax(hmax, fabs(h));
+      if (j == i + 1) asym = fmax(asym, fabs(h - Hp[(size_t)j * m + i]));
+      else if (j > i + 1) asym = fmax(asym, fabs(h));
+    }
+  hmax = wave_max64(hmax);
+  asym = wave_max64(asym);
+  if (!(asym <= symtol * hmax)) {
+    if (l == 0) need[p] = 1;
+    return;
+  }
+  if (nn > kTrapMaxDim) {
+    if (l == 0) need[p] = 2;
+    return;
+  }
+  for (int i = l; i < nn; i += 64) {
+    al[i] = Hp[(size_t)i * m + i];
+    ee[i] = (i + 1 < nn) ? 0.5 * (Hp[(size_t)i * m + i + 1] + Hp[(size_t)(i + 1) * m + i]) : 0.0;
+    lv[i] = 0.0;
+  }
+  __syncthreads();
+  int outside = 0;
+  if (l == 0) outside = sturm_count_below(nn, al, ee, a * 1e-3) > 0;
+  if (l == 1) outside = sturm_count_below(nn, al, ee, b * 1e3) < nn;
+  outside = __shfl(outside, 0, 64) | __shfl(outside, 1, 64);
+  if (outside) {
+    if (l == 0) need[p] = 2;
+    return;
+  }
+  const double umin = log(a) - kTrapTail;
+  const double umax = log(b > 1.0 ? b : 1.0) + kTrapTail;
+  const int nodes = (int)ceil((umax - umin) / kTrapStep) + 1;
+  double* dv = piv + (size_t)l * kTrapMaxDim;
+  for (int j0 = 0; j0 < nodes; j0 += 64) {
+    const int j = j0 + l;
+    const bool act = j < nodes;
+    const double sv = act ? exp(umin + j * kTrapStep) : 1.0;
+    // pivots from the bottom
+    double d = al[nn - 1] + sv;
+    dv[nn - 1] = d;
+    for (int i = nn - 2; i >= 0; --i) {
+      d = al[i] + sv - ee[i] * ee[i] / d;
+      dv[i] = d;
+    }
+    // component 1: s (1/(1+s) - 1/d_1) without cancellation
+    const double num = (al[0] - 1.0) - (nn >= 2 ? ee[0] * ee[0] / dv[1] : 0.0);
+    double c1 = act ? sv * num / ((1.0 + sv) * dv[0]) : 0.0;
+    c1 = wave_sum64(c1);
+    if (l == 0) lv[0] += c1;
+    double y = 1.0 / dv[0];
+    for (int i = 1; i < nn; ++i) {
+      y = -ee[i - 1] * y / dv[i];
+      double ci = act ? -sv * y : 0.0;
+      ci = wave_sum64(ci);
+      if (l == 0) lv[i] += ci;
+    }
+  }
+  __syncthreads();
+  if (l == 0) need[p] = 0;
+  if (mode == 0) {
+    bool finite = true;
+    for (int t = l; t < m; t += 64) {
+      const double v = (t < nn) ? lv[t] * kTrapStep : 0.0;
+      finite = finite && isfinite(v);
+      ell[(size_t)p * m + t] = v;
+    }
+    if (!finite) flags[p] |= 1;
+  } else {
+    double acc = 0.0;
+    for (int t = l; t < nn; t += 64) acc = fma(g[(size_t)p * (m + 1) + t], lv[t] * kTrapStep, acc);
+    acc = wave_sum64(acc) + shift;
+    if (l == 0) {
+      if (!isfinite(acc)) flags[p] |= 1;
+      K[p] = acc;
+    }
   }
 }
 
@@ -203,12 +348,18 @@ LogRule make_log_rule() {
 int hess_log_wstride(int m) { return 10 * m * m + 8 * m; }
 
 hipError_t launch_hess_log(hipStream_t st, int B, int m, const double* H, const int* meff,
-                           double* work, int wstride, int mode, double* ell, const double* g,
-                           double shift, double* K, int* flags, double symtol, int* need) {
+                           double a, double b, double* work, int wstride, int mode, double* ell,
+                           const double* g, double shift, double* K, int* flags, double symtol,
+                           int* need) {
   if (B < 1 || m < 1 || !H || !meff || !work || wstride < hess_log_wstride(m) || !flags ||
-      !need || (mode == 0 && !ell) || (mode == 1 && (!g || !K)))
+      !need || (mode == 0 && !ell) || (mode == 1 && (!g || !K)) || !(a > 0.0) || !(b >= a))
     return hipErrorInvalidValue;
   static const LogRule rule = make_log_rule();
+  // symmetric runs: trapezoidal Stieltjes rule; those it leaves (need = 2):
+  // QL with logged rotations; non-symmetric ones (need = 1): inverse scaling
+  // and squaring
+  hipLaunchKernelGGL(k_hess_log_trap, dim3(B), dim3(64), 0, st, B, m, H, meff, a, b, symtol, mode,
+                     ell, g, shift, K, flags, need);
   hipLaunchKernelGGL(k_hess_log_sym, dim3(B), dim3(64), 0, st, B, m, H, meff, work, wstride, symtol,
                      mode, ell, g, shift, K, flags, need);
   hipError_t e = hipGetLastError();

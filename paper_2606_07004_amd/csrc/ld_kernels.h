@@ -115,11 +115,14 @@ struct LogRule {
 // mode 0: ell[p][t] = (log H_p e1)_t; mode 1: K[p] = sum_t g[p][t] (log H_p e1)_t + shift.
 // work: wstride >= hess_log_wstride(m) doubles per run; need: B ints of scratch.
 // Runs whose H is symmetric tridiagonal to within symtol * max|h| take the
-// O(m^2) eigen-path, the others inverse scaling and squaring.
+// trapezoidal Stieltjes rule (spectrum inside [a, b], the operator's
+// interval) or else the O(m^2) eigen-path; the others inverse scaling and
+// squaring.
 int hess_log_wstride(int m);
 hipError_t launch_hess_log(hipStream_t st, int B, int m, const double* H, const int* meff,
-                           double* work, int wstride, int mode, double* ell, const double* g,
-                           double shift, double* K, int* flags, double symtol, int* need);
+                           double a, double b, double* work, int wstride, int mode, double* ell,
+                           const double* g, double shift, double* K, int* flags, double symtol,
+                           int* need);
 hipError_t launch_osa_coef(hipStream_t st, int B, int ld, int m, const double* ell,
                            const double* mult, const double* norm2, const int* meff, double shift,
                            double* coef);

@@ -472,8 +472,8 @@ ld_status Run::osa_sketch_combine(hipStream_t st) {
   // keep the sketch-image runs' Krylov dimensions for the step count
   LD_HIP(hipMemcpyAsync(meff0_, meff_, (size_t)std::max(s_, 1) * 4, hipMemcpyDeviceToDevice, st));
   LD_LAUNCH(LD_PROF_SMALL, 0,
-            launch_hess_log(st, s_, m_, H_, meff_, work_, wstride_, 0, ell_, nullptr, 0.0,
-                            nullptr, flags_, symtol(), need_));
+            launch_hess_log(st, s_, m_, H_, meff_, quad_a(), quad_b(), work_, wstride_, 0, ell_,
+                            nullptr, 0.0, nullptr, flags_, symtol(), need_));
   LD_LAUNCH(LD_PROF_SMALL, 0,
             launch_osa_coef(st, s_, ld1_, m_, ell_, mult_, norm2_, meff_, shift, coefs_));
   LD_LAUNCH(LD_PROF_SKETCH, (double)m_ * n_ * ld1_ * xb_ + (double)n_ * lds_ * 8,
@@ -598,8 +598,8 @@ ld_status Run::run_epilogue(hipStream_t st) {
   } else {
     // x^T L_c x / ||x||^2 = sum_t g_t (log H e1)_t + log(gamma) - c
     LD_LAUNCH(LD_PROF_SMALL, 0,
-              launch_hess_log(st, B_, m_, H_, meff_, work_, wstride_, 1, nullptr, gq_,
-                              std::log(scale_) - c_, K_, flags_, symtol(), need_));
+              launch_hess_log(st, B_, m_, H_, meff_, quad_a(), quad_b(), work_, wstride_, 1,
+                              nullptr, gq_, std::log(scale_) - c_, K_, flags_, symtol(), need_));
   }
   LD_HIP(hipEventRecord(ev1_, st));
   return LD_OK;
