@@ -190,7 +190,9 @@ ld_status ld_quad_form(ld_matrix* a, const double* x, double* out);
 ld_status ld_estimate(ld_matrix* a, int32_t n_probes, int32_t sketch_rank,
                       int32_t krylov_steps, int32_t iop_window, uint64_t seed,
                       ld_result* out);
-/* Blocking estimate with explicit parameters. */
+/* Blocking estimate with explicit parameters.  A matrix whose spectral
+ * interval has zero width (lambda_lo == lambda_hi: Q = q I) gets the exact
+ * n log q without any Krylov run (probe_steps = 0; detail arrays zero). */
 ld_status ld_estimate_ex(ld_matrix* a, const ld_params* p, ld_result* out);
 /* As ld_estimate_ex, also filling the non-NULL arrays of `detail`. */
 ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,

@@ -610,6 +610,18 @@ ld_status Run::advance(hipStream_t st, int budget, bool* done) {
   while (budget > 0) {
     switch (stage_) {
       case ST_PROLOGUE: {
+        if (lo_ == hi_) {
+          // a zero-width Gershgorin interval means Q = q I exactly: every
+          // traced operator L_c is a multiple of I and the estimate is
+          // exactly n log q (collect forms it); no kernel runs
+          if (!ev0_) LD_HIP(hipEventCreate(&ev0_));
+          if (!ev1_) LD_HIP(hipEventCreate(&ev1_));
+          LD_HIP(hipEventRecord(ev0_, st));
+          LD_HIP(hipEventRecord(ev1_, st));
+          stage_ = ST_DONE;
+          --budget;
+          break;
+        }
         ld_status rc = run_prologue(st);
         if (rc != LD_OK) return rc;
         stage_ = ST_KRYLOV;
@@ -666,6 +678,33 @@ ld_status Run::advance(hipStream_t st, int budget, bool* done) {
 ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail) {
   LD_HIP(hipStreamSynchronize(st));
   if (prof_) LD_HIP(prof_->harvest());
+  if (lo_ == hi_) {
+    // Q = q I (see advance): x^T L_c x / ||x||^2 = log q - c for every run
+    float ms = 0.f;
+    LD_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
+    ld_result res{};
+    res.logdet = (double)n_ * std::log(lo_);
+    res.shift_c = c_;
+    res.tr_sketch = 0.0;
+    res.tr_resid = res.logdet - (double)n_ * c_;
+    res.lambda_lo = lo_;
+    res.lambda_hi = hi_;
+    res.scale = scale_;
+    res.device_ms = ms;
+    res.latency_ms = (now_seconds() - t_submit_) * 1e3;
+    if (detail) {
+      for (int p = 0; p < B_; ++p) {
+        if (detail->probe_K) detail->probe_K[p] = std::log(lo_) - c_;
+        if (detail->probe_norm2) detail->probe_norm2[p] = 0.0;
+        if (detail->probe_steps) detail->probe_steps[p] = 0;
+      }
+      if (detail->tri_alpha) std::memset(detail->tri_alpha, 0, (size_t)B_ * m_ * 8);
+      if (detail->tri_beta) std::memset(detail->tri_beta, 0, (size_t)B_ * m_ * 8);
+      if (detail->sketch_basis) std::memset(detail->sketch_basis, 0, (size_t)n_ * kb_ * 8);
+    }
+    *out = res;
+    return LD_OK;
+  }
   std::vector<double> K(B_), nrm(B_);
   std::vector<int> meff(B_), flags(B_);
   int dflag[3] = {0, 0, 0};
