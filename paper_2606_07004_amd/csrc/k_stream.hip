@@ -287,7 +287,7 @@ __global__ __launch_bounds__(kThreads, (NF == 2 || sizeof(VT) > sizeof(XT)) ? 4 
         const A* sce = scs + colc[c];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) out.v[e] = XT(acc[c][e] * sce[e]);
-        out.store(W + (size_t)row * ld + colc[c]);
+        out.store_nt(W + (size_t)row * ld + colc[c]);
         if constexpr (LDSACC) {
           // the newest window vector is X itself
 #pragma unroll
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* 
     for (int c = 0; c < C; ++c)
       if (okc[c]) {
         V16<XT> w;
-        w.load(W + (size_t)row * ld + colc[c]);
+        w.load_nt(W + (size_t)row * ld + colc[c]);  // the product is read once
         double wd[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) wd[e] = double(w.v[e]);
@@ -435,7 +435,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* 
         for (int v = 0; v < NV; ++v)
           if (v < nv) {
             V16<XT> x;
-            x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
+            // the oldest window vector leaves the window with this step
+            if (v == 0 && nv >= 2)
+              x.load_nt(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
+            else
+              x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
             const double* cfv = cf + v * ld + colc[c];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) wd[e] = fma(-cfv[e], double(x.v[e]), wd[e]);
@@ -443,7 +447,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* 
         V16<XT> o;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) o.v[e] = XT(wd[e]);
-        o.store(W + (size_t)row * ld + colc[c]);
+        o.store_nt(W + (size_t)row * ld + colc[c]);
         if (want_norm) {
 #pragma unroll
           for (int e = 0; e < VEC; ++e) nacc[c][e] = fma(double(o.v[e]), double(o.v[e]), nacc[c][e]);

@@ -44,6 +44,18 @@ template <> struct V16<double> {
     double2 t; t.x = v[0]; t.y = v[1];
     *reinterpret_cast<double2*>(p) = t;
   }
+  // streaming load: last use of the line
+  __device__ inline void load_nt(const double* p) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 t = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+    v[0] = t.x; v[1] = t.y;
+  }
+  // streaming store: the line is not kept in the caches for reuse
+  __device__ inline void store_nt(double* p) const {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 t = {v[0], v[1]};
+    __builtin_nontemporal_store(t, reinterpret_cast<d2*>(p));
+  }
 };
 template <> struct V16<float> {
   static constexpr int N = 4;
@@ -55,6 +67,18 @@ template <> struct V16<float> {
   __device__ inline void store(float* p) const {
     float4 t; t.x = v[0]; t.y = v[1]; t.z = v[2]; t.w = v[3];
     *reinterpret_cast<float4*>(p) = t;
+  }
+  // streaming load: last use of the line
+  __device__ inline void load_nt(const float* p) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  }
+  // streaming store: the line is not kept in the caches for reuse
+  __device__ inline void store_nt(float* p) const {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 t = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(t, reinterpret_cast<f4*>(p));
   }
 };
 
