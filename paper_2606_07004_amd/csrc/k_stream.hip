@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <map>
+#include <vector>
 #include <mutex>
 
 namespace ld {
@@ -121,8 +122,7 @@ struct RowMap {
 // round-robin on the 8 XCDs (block b on XCD b % 8), so in every round XCD x
 // gets one contiguous band of the round's chunks: rows a few chunks apart
 // (the +-N neighbours of a stencil) then share that XCD's L2.
-__device__ inline int chunk_of(int j) {
-  const int nb = gridDim.x, b = blockIdx.x;
+__device__ inline int chunk_of(int j, int b, int nb) {
   const int base = j * nb;
   return (nb & 7) ? base + b : base + (b & 7) * (nb >> 3) + (b >> 3);
 }
@@ -131,12 +131,12 @@ __device__ inline int chunk_of(int j) {
 // of the block, stored as the block's partial sums (times mult[col]).
 template <int C, int VEC>
 __device__ inline void red_partials(const double* red, const RowMap& rm, int ld, const double* mult,
-                                    double* part, size_t row0) {
+                                    double* part, size_t row0, int bk, int nbk) {
   const int WC = rm.L * C * VEC;
   for (int i = threadIdx.x; i < WC; i += kThreads) {
     double sum = 0.0;
     for (int q = 0; q < rm.rpi; ++q) sum += red[q * WC + i];
-    if (i < ld) part[(row0 + i) * gridDim.x + blockIdx.x] = sum * (mult ? mult[i] : 1.0);
+    if (i < ld) part[(row0 + i) * nbk + bk] = sum * (mult ? mult[i] : 1.0);
   }
   __syncthreads();
 }
@@ -151,13 +151,14 @@ __device__ inline int red_slot(const RowMap& rm, int c, int e) {
 // block and store the block's partial sums (times mult[col]).
 template <int C, int VEC>
 __device__ inline void block_partials(const double (&acc)[C][VEC], double* red, const RowMap& rm,
-                                      int ld, const double* mult, double* part, size_t row0) {
+                                      int ld, const double* mult, double* part, size_t row0, int bk,
+                                      int nbk) {
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
     for (int e = 0; e < VEC; ++e) red[red_slot<C, VEC>(rm, c, e)] = acc[c][e];
   __syncthreads();
-  red_partials<C, VEC>(red, rm, ld, mult, part, row0);
+  red_partials<C, VEC>(red, rm, ld, mult, part, row0, bk, nbk);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,14 +172,12 @@ __device__ inline void block_partials(const double (&acc)[C][VEC], double* red, 
 // part[voff+v][col][block] = mult_v[col] * sum_rows x_v[row][col] w[row][col].
 // ---------------------------------------------------------------------------
 template <typename VT, typename XT, int C, int NF>
-__global__ __launch_bounds__(kThreads, (NF == 2 || sizeof(VT) > sizeof(XT)) ? 4 : 6) void k_spmm(int64_t n, int lgL, const int* __restrict__ rp,
-                                                  const int* __restrict__ ci,
-                                                  const VT* __restrict__ va,
-                                                  const XT* __restrict__ X, XT* __restrict__ W,
-                                                  int ld, int ncolv,
-                                                  const double* __restrict__ xmult,
-                                                  double opscale, VecSet vs, int voff,
-                                                  double* __restrict__ part) {
+__device__ inline void spmm_body(int64_t n, int lgL, const int* __restrict__ rp,
+                                 const int* __restrict__ ci, const VT* __restrict__ va,
+                                 const XT* __restrict__ X, XT* __restrict__ W, int ld, int ncolv,
+                                 const double* __restrict__ xmult, double opscale, const void* const* fx,
+                                 const double* const* fmult, int voff, double* __restrict__ part,
+                                 int bk, int nbk) {
   // FP32 sums for FP32 (or BF16) values on FP32 vectors; FP64 sums whenever
   // the values or the vectors are FP64
   using A = typename std::conditional<std::is_same<VT, double>::value, double,
@@ -217,8 +216,8 @@ __global__ __launch_bounds__(kThreads, (NF == 2 || sizeof(VT) > sizeof(XT)) ? 4 
       for (int e = 0; e < VEC; ++e) dacc[v][c][e] = 0.0;
   const int nn = (int)n;  // n < 2^31
   const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
-  for (int j = 0; j * (int)gridDim.x < nchunk; ++j) {
-    const int ch = chunk_of(j);
+  for (int j = 0; j * nbk < nchunk; ++j) {
+    const int ch = chunk_of(j, bk, nbk);
     const int row = ch * rm.rpi + rm.rg;
     if (ch >= nchunk || row >= nn) continue;
     A acc[C][VEC];
@@ -302,7 +301,7 @@ __global__ __launch_bounds__(kThreads, (NF == 2 || sizeof(VT) > sizeof(XT)) ? 4 
               if (v == NF - 1)
                 x = xd[c];  // the newest window vector is X itself
               else
-                x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
+                x.load(static_cast<const XT*>(fx[v]) + (size_t)row * ld + colc[c]);
 #pragma unroll
               for (int e = 0; e < VEC; ++e)
                 dacc[v][c][e] = fma(double(x.v[e]), double(out.v[e]), dacc[v][c][e]);
@@ -312,12 +311,26 @@ __global__ __launch_bounds__(kThreads, (NF == 2 || sizeof(VT) > sizeof(XT)) ? 4 
   }
   if constexpr (LDSACC) {
     __syncthreads();
-    red_partials<C, VEC>(red, rm, ld, vs.mult[0], part, (size_t)voff * ld);
+    red_partials<C, VEC>(red, rm, ld, fmult[0], part, (size_t)voff * ld, bk, nbk);
   } else if constexpr (FUSED) {
 #pragma unroll
     for (int v = 0; v < NF; ++v)
-      block_partials<C, VEC>(dacc[v], red, rm, ld, vs.mult[v], part, (size_t)(voff + v) * ld);
+      block_partials<C, VEC>(dacc[v], red, rm, ld, fmult[v], part, (size_t)(voff + v) * ld, bk, nbk);
   }
+}
+
+// One CSR x block product per batch entry: blocks off[r] .. off[r+1]-1 of
+// the grid belong to request r (a single product is a batch of one).
+template <typename VT, typename XT, int C, int NF>
+__global__ __launch_bounds__(kThreads, (NF == 2 || sizeof(VT) > sizeof(XT)) ? 4 : 6) void k_spmm(
+    BatchArgs<SpmmDesc> bt) {
+  int r = 0;
+  while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
+  const SpmmDesc& q = bt.d[r];
+  spmm_body<VT, XT, C, NF>(q.n, q.lgL, q.rp, q.ci, static_cast<const VT*>(q.va),
+                           static_cast<const XT*>(q.X), static_cast<XT*>(q.W), q.ld, q.ncolv, q.xmult,
+                           q.opscale, q.fx, q.fmult, q.voff, q.part, (int)blockIdx.x - bt.off[r],
+                           bt.off[r + 1] - bt.off[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,7 +363,7 @@ __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int lgL, const XT*
   const int nn = (int)n;  // n < 2^31
   const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
   for (int j = 0; j * (int)gridDim.x < nchunk; ++j) {
-    const int ch = chunk_of(j);
+    const int ch = chunk_of(j, (int)blockIdx.x, (int)gridDim.x);
     const int row = ch * rm.rpi + rm.rg;
     if (ch >= nchunk || row >= nn) continue;
 #pragma unroll
@@ -371,7 +384,9 @@ __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int lgL, const XT*
   }
 #pragma unroll
   for (int v = 0; v < kDotsPerLaunch; ++v)
-    if (v < nv) block_partials<C, VEC>(acc[v], red, rm, ld, vs.mult[v], part, (size_t)(voff + v) * ld);
+    if (v < nv)
+      block_partials<C, VEC>(acc[v], red, rm, ld, vs.mult[v], part, (size_t)(voff + v) * ld,
+                             (int)blockIdx.x, (int)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -385,19 +400,18 @@ __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int lgL, const XT*
 // not have to read v_t for.  The coefficients h_v * mult_v live in LDS.
 // ---------------------------------------------------------------------------
 template <typename XT, int C, int NV, bool V1, bool SYM>
-__global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* __restrict__ W, int ld,
-                                                    int ncolv, VecSet vs, int nv,
-                                                    const double* __restrict__ d, int voff,
-                                                    int want_norm, const XT* __restrict__ v1,
-                                                    const double* __restrict__ v1mult,
-                                                    double* __restrict__ part) {
+__device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int ld, int ncolv,
+                                   const void* const* vx, const double* const* vmult, int nv,
+                                   const double* __restrict__ d, int voff, int want_norm,
+                                   const XT* __restrict__ v1, const double* __restrict__ v1mult,
+                                   double* __restrict__ part, int bk, int nbk) {
   constexpr int VEC = V16<XT>::N;
   __shared__ double red[kThreads * VEC * C];
   __shared__ double cf[NV * kMaxLd];
   const RowMap rm(lgL);
   for (int i = threadIdx.x; i < NV * ld; i += kThreads) {
     const int v = i / ld, col = i - v * ld;
-    cf[i] = v < nv ? d[(size_t)(voff + v) * ld + col] * (vs.mult[v] ? vs.mult[v][col] : 1.0) : 0.0;
+    cf[i] = v < nv ? d[(size_t)(voff + v) * ld + col] * (vmult[v] ? vmult[v][col] : 1.0) : 0.0;
   }
   __syncthreads();
   bool okc[C];
@@ -419,8 +433,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* 
     }
   const int nn = (int)n;  // n < 2^31
   const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
-  for (int j = 0; j * (int)gridDim.x < nchunk; ++j) {
-    const int ch = chunk_of(j);
+  for (int j = 0; j * nbk < nchunk; ++j) {
+    const int ch = chunk_of(j, bk, nbk);
     const int row = ch * rm.rpi + rm.rg;
     if (ch >= nchunk || row >= nn) continue;
 #pragma unroll
@@ -437,9 +451,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* 
             V16<XT> x;
             // the oldest window vector leaves the window with this step
             if (v == 0 && nv >= 2)
-              x.load_nt(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
+              x.load_nt(static_cast<const XT*>(vx[v]) + (size_t)row * ld + colc[c]);
             else
-              x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
+              x.load(static_cast<const XT*>(vx[v]) + (size_t)row * ld + colc[c]);
             const double* cfv = cf + v * ld + colc[c];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) wd[e] = fma(-cfv[e], double(x.v[e]), wd[e]);
@@ -467,14 +481,26 @@ __global__ __launch_bounds__(kThreads, 4) void k_update(int64_t n, int lgL, XT* 
       }
   }
   if (want_norm) {
-    block_partials<C, VEC>(nacc, red, rm, ld, nullptr, part, 0);
+    block_partials<C, VEC>(nacc, red, rm, ld, nullptr, part, 0, bk, nbk);
     if constexpr (V1) {
-      block_partials<C, VEC>(gacc, red, rm, ld, v1mult, part, (size_t)ld);
+      block_partials<C, VEC>(gacc, red, rm, ld, v1mult, part, (size_t)ld, bk, nbk);
     } else {
-      for (int i = threadIdx.x; i < ld; i += kThreads) part[((size_t)ld + i) * gridDim.x + blockIdx.x] = 0.0;
+      for (int i = threadIdx.x; i < ld; i += kThreads) part[((size_t)ld + i) * nbk + bk] = 0.0;
     }
-    if constexpr (SYM) block_partials<C, VEC>(sacc, red, rm, ld, nullptr, part, (size_t)2 * ld);
+    if constexpr (SYM) block_partials<C, VEC>(sacc, red, rm, ld, nullptr, part, (size_t)2 * ld, bk, nbk);
   }
+}
+
+// One update per batch entry (see k_spmm for the block ranges).
+template <typename XT, int C, int NV, bool V1, bool SYM>
+__global__ __launch_bounds__(kThreads, 4) void k_update(BatchArgs<UpdDesc> bt) {
+  int r = 0;
+  while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
+  const UpdDesc& q = bt.d[r];
+  update_body<XT, C, NV, V1, SYM>(q.n, q.lgL, static_cast<XT*>(q.W), q.ld, q.ncolv, q.vx, q.vmult,
+                                  q.nv, q.d, q.voff, q.want_norm, static_cast<const XT*>(q.v1),
+                                  q.v1mult, q.part, (int)blockIdx.x - bt.off[r],
+                                  bt.off[r + 1] - bt.off[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -493,13 +519,17 @@ __device__ inline double row_sum(const double* __restrict__ p, int nblk, int lan
   return wave_sum_fixed(s);
 }
 
-__global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ part, int nblk,
-                                                    int width, double* __restrict__ out) {
+// One wave per output; outputs off[r] .. off[r+1]-1 belong to batch entry r.
+__global__ __launch_bounds__(kThreads) void k_reduce(BatchArgs<RedDesc> bt) {
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-  if (i >= width) return;
-  const double s = row_sum(part + (size_t)i * nblk, nblk, lane);
-  if (lane == 0) out[i] = s;
+  const int o = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (o >= bt.off[bt.count]) return;
+  int r = 0;
+  while (r + 1 < bt.count && o >= bt.off[r + 1]) ++r;
+  const RedDesc& q = bt.d[r];
+  const int i = o - bt.off[r];
+  const double s = row_sum(q.part + (size_t)i * q.nblk, q.nblk, lane);
+  if (lane == 0) q.out[i] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -531,19 +561,27 @@ __global__ __launch_bounds__(kThreads) void k_start_finish(int B, int ld, const 
   if (g && p < B) g[(size_t)p * gstride] = 1.0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_step_finish(int B, int ld, int t, int m,
-                                                         double* __restrict__ d, int j0,
-                                                         int nv, const double* __restrict__ part,
-                                                         int nblk, double tol,
-                                                         double* __restrict__ H,
-                                                         int* __restrict__ meff,
-                                                         int* __restrict__ active,
-                                                         double* __restrict__ mult_next,
-                                                         double* __restrict__ g,
-                                                         int* __restrict__ flags, int sym_row) {
+// One wave per probe column; columns off[r] .. off[r+1]-1 belong to batch
+// entry r.
+__global__ __launch_bounds__(kThreads) void k_step_finish(BatchArgs<FinDesc> bt) {
   const int lane = threadIdx.x & 63;
-  const int p = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-  if (p >= ld) return;
+  const int o = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (o >= bt.off[bt.count]) return;
+  int r = 0;
+  while (r + 1 < bt.count && o >= bt.off[r + 1]) ++r;
+  const FinDesc& q = bt.d[r];
+  const int p = o - bt.off[r];
+  const int B = q.B, ld = q.ld, t = q.t, m = q.m, j0 = q.j0, nv = q.nv, nblk = q.nblk;
+  const int sym_row = q.sym_row;
+  const double tol = q.tol;
+  double* __restrict__ d = q.d;
+  const double* __restrict__ part = q.part;
+  double* __restrict__ H = q.H;
+  int* __restrict__ meff = q.meff;
+  int* __restrict__ active = q.active;
+  double* __restrict__ mult_next = q.mult_next;
+  double* __restrict__ g = q.g;
+  int* __restrict__ flags = q.flags;
   const double nrm2 = row_sum(part + (size_t)p * nblk, nblk, lane);
   const double gdot = g ? row_sum(part + (size_t)(ld + p) * nblk, nblk, lane) : 0.0;
   const double sdot = sym_row >= 0 ? row_sum(part + (size_t)(2 * ld + p) * nblk, nblk, lane) : 0.0;
@@ -856,73 +894,140 @@ hipError_t launch_probes(hipStream_t st, int dist, uint64_t seed, int64_t n, int
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Batched launches.  Every per-step launcher takes a list of items (a single
+// request is a list of one); items that need the same kernel instantiation
+// share one launch of at most kMaxBatch entries, each entry keeping the grid
+// it would get alone (so a request's partial sums, and therefore its result,
+// do not depend on what it is batched with).
+// ---------------------------------------------------------------------------
+template <typename Item, typename KeyFn, typename LaunchFn>
+static hipError_t launch_grouped(Item* items, int count, KeyFn key, LaunchFn launch) {
+  std::vector<char> used((size_t)count, 0);
+  for (int a = 0; a < count; ++a) {
+    if (used[a]) continue;
+    const uint64_t k = key(items[a]);
+    int idx[kMaxBatch];
+    int cnt = 0;
+    for (int b = a; b < count && cnt < kMaxBatch; ++b)
+      if (!used[b] && key(items[b]) == k) {
+        idx[cnt++] = b;
+        used[b] = 1;
+      }
+    const hipError_t e = launch(idx, cnt);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static bool spmm_item_ok(const SpmmItem& it) {
+  const Geom& g = it.g;
+  if (!geom_ok(g) || g.ld > kMaxLd || !it.rp || !it.ci || !it.va || !it.X || !it.W ||
+      it.X == it.W || it.nf < 0 || it.nf > 2 || (it.nf > 0 && (!it.part || it.voff < 0)))
+    return false;
+  if (!(it.vt == VT_F64 || it.vt == VT_F32 || it.vt == VT_BF16)) return false;
+  if (g.xbytes == 8 && it.vt != VT_F64 && it.vt != VT_F32 && it.vt != VT_BF16) return false;
+  for (int v = 0; v < it.nf; ++v)
+    if (!it.fused.x[v] || it.fused.x[v] == it.W) return false;
+  if (it.nf > 0 && it.fused.x[it.nf - 1] != it.X) return false;  // newest vector = the input
+  return true;
+}
+
+template <typename VT, typename XT, int C, int NF>
+static hipError_t spmm_launch(hipStream_t st, SpmmItem* items, const int* idx, int cnt) {
+  auto fn = k_spmm<VT, XT, C, NF>;
+  BatchArgs<SpmmDesc> bt{};
+  bt.count = cnt;
+  int off = 0;
+  for (int q = 0; q < cnt; ++q) {
+    SpmmItem& it = items[idx[q]];
+    const int nb = stream_grid(it.g, (const void*)fn);
+    it.nblk = nb;
+    SpmmDesc& d = bt.d[q];
+    d.n = it.g.n;
+    d.rp = it.rp;
+    d.ci = it.ci;
+    d.va = it.va;
+    d.X = it.X;
+    d.W = it.W;
+    d.xmult = it.xmult;
+    d.opscale = it.opscale;
+    for (int v = 0; v < 2; ++v) {
+      d.fx[v] = v < it.nf ? it.fused.x[v] : nullptr;
+      d.fmult[v] = v < it.nf ? it.fused.mult[v] : nullptr;
+    }
+    d.part = it.part;
+    d.lgL = it.g.lgL;
+    d.ld = it.g.ld;
+    d.ncolv = it.g.ncolv;
+    d.voff = it.voff;
+    bt.off[q] = off;
+    off += nb;
+  }
+  bt.off[cnt] = off;
+  hipLaunchKernelGGL(fn, dim3(off), dim3(kThreads), 0, st, bt);
+  return hipGetLastError();
+}
+
 template <typename VT, typename XT, int NF>
-static void spmm_launch_nf(hipStream_t st, const Geom& g, const int* rp, const int* ci,
-                           const VT* va, const XT* X, XT* W, const double* xmult, double opscale,
-                           const VecSet& vs, int voff, double* part, int* nblk_out) {
-  LD_DISPATCH_C(g.C, {
-    auto fn = k_spmm<VT, XT, CC, NF>;
-    const int nb = stream_grid(g, (const void*)fn);
-    *nblk_out = nb;
-    hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, rp, ci, va, X, W, g.ld,
-                       g.ncolv, xmult, opscale, vs, voff, part);
-  });
+static hipError_t spmm_launch_c(hipStream_t st, int C, SpmmItem* items, const int* idx, int cnt) {
+  hipError_t e = hipErrorInvalidValue;
+  LD_DISPATCH_C(C, { e = spmm_launch<VT, XT, CC, NF>(st, items, idx, cnt); });
+  return e;
 }
 
 template <typename VT, typename XT>
-static hipError_t spmm_typed(hipStream_t st, const Geom& g, const int* rp, const int* ci,
-                             const VT* va, const XT* X, XT* W, const double* xmult, double opscale,
-                             const VecSet& vs, int nf, int voff, double* part, int* nblk_out) {
-  if (nf == 2)
-    spmm_launch_nf<VT, XT, 2>(st, g, rp, ci, va, X, W, xmult, opscale, vs, voff, part, nblk_out);
-  else if (nf == 1)
-    spmm_launch_nf<VT, XT, 1>(st, g, rp, ci, va, X, W, xmult, opscale, vs, voff, part, nblk_out);
-  else
-    spmm_launch_nf<VT, XT, 0>(st, g, rp, ci, va, X, W, xmult, opscale, vs, voff, part, nblk_out);
-  return hipGetLastError();
+static hipError_t spmm_launch_typed(hipStream_t st, int C, int nf, SpmmItem* items, const int* idx,
+                                    int cnt) {
+  if (nf == 2) return spmm_launch_c<VT, XT, 2>(st, C, items, idx, cnt);
+  if (nf == 1) return spmm_launch_c<VT, XT, 1>(st, C, items, idx, cnt);
+  return spmm_launch_c<VT, XT, 0>(st, C, items, idx, cnt);
+}
+
+hipError_t launch_spmm_batch(hipStream_t st, SpmmItem* items, int count) {
+  if (count < 0 || (count > 0 && !items)) return hipErrorInvalidValue;
+  for (int a = 0; a < count; ++a)
+    if (!spmm_item_ok(items[a])) return hipErrorInvalidValue;
+  auto key = [](const SpmmItem& it) -> uint64_t {
+    return (uint64_t)it.g.xbytes | ((uint64_t)it.vt << 8) | ((uint64_t)it.g.C << 16) |
+           ((uint64_t)it.nf << 24);
+  };
+  return launch_grouped(items, count, key, [&](const int* idx, int cnt) -> hipError_t {
+    const SpmmItem& it = items[idx[0]];
+    if (it.g.xbytes == 8) {
+      if (it.vt == VT_F64) return spmm_launch_typed<double, double>(st, it.g.C, it.nf, items, idx, cnt);
+      if (it.vt == VT_F32) return spmm_launch_typed<float, double>(st, it.g.C, it.nf, items, idx, cnt);
+      return spmm_launch_typed<uint16_t, double>(st, it.g.C, it.nf, items, idx, cnt);
+    }
+    if (it.vt == VT_F64) return spmm_launch_typed<double, float>(st, it.g.C, it.nf, items, idx, cnt);
+    if (it.vt == VT_F32) return spmm_launch_typed<float, float>(st, it.g.C, it.nf, items, idx, cnt);
+    return spmm_launch_typed<uint16_t, float>(st, it.g.C, it.nf, items, idx, cnt);
+  });
 }
 
 hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* ci, const void* va,
                        int vt, const void* X, void* W, const double* xmult, double opscale,
                        const VecSet* fused, int nf, int voff, double* part, int* nblk_out) {
-  int dummy = 0;
-  if (!nblk_out) nblk_out = &dummy;
-  if (!geom_ok(g) || g.ld > kMaxLd || !rp || !ci || !va || !X || !W || X == W || nf < 0 || nf > 2 ||
-      (nf > 0 && (!fused || !part || voff < 0)))
-    return hipErrorInvalidValue;
-  VecSet vs{};
+  SpmmItem it{};
+  it.g = g;
+  it.rp = rp;
+  it.ci = ci;
+  it.va = va;
+  it.vt = vt;
+  it.X = X;
+  it.W = W;
+  it.xmult = xmult;
+  it.opscale = opscale;
   if (nf > 0) {
-    vs = *fused;
-    for (int v = 0; v < nf; ++v)
-      if (!vs.x[v] || vs.x[v] == W) return hipErrorInvalidValue;
-    if (vs.x[nf - 1] != X) return hipErrorInvalidValue;  // newest vector = the input
+    if (!fused) return hipErrorInvalidValue;
+    it.fused = *fused;
   }
-  if (g.xbytes == 8) {
-    const double* x = static_cast<const double*>(X);
-    double* w = static_cast<double*>(W);
-    if (vt == VT_F64)
-      return spmm_typed<double, double>(st, g, rp, ci, static_cast<const double*>(va), x, w, xmult,
-                                        opscale, vs, nf, voff, part, nblk_out);
-    if (vt == VT_F32)
-      return spmm_typed<float, double>(st, g, rp, ci, static_cast<const float*>(va), x, w, xmult,
-                                       opscale, vs, nf, voff, part, nblk_out);
-    if (vt == VT_BF16)
-      return spmm_typed<uint16_t, double>(st, g, rp, ci, static_cast<const uint16_t*>(va), x, w,
-                                          xmult, opscale, vs, nf, voff, part, nblk_out);
-  } else {
-    const float* x = static_cast<const float*>(X);
-    float* w = static_cast<float*>(W);
-    if (vt == VT_F64)
-      return spmm_typed<double, float>(st, g, rp, ci, static_cast<const double*>(va), x, w, xmult,
-                                       opscale, vs, nf, voff, part, nblk_out);
-    if (vt == VT_F32)
-      return spmm_typed<float, float>(st, g, rp, ci, static_cast<const float*>(va), x, w, xmult,
-                                      opscale, vs, nf, voff, part, nblk_out);
-    if (vt == VT_BF16)
-      return spmm_typed<uint16_t, float>(st, g, rp, ci, static_cast<const uint16_t*>(va), x, w,
-                                         xmult, opscale, vs, nf, voff, part, nblk_out);
-  }
-  return hipErrorInvalidValue;
+  it.nf = nf;
+  it.voff = voff;
+  it.part = part;
+  const hipError_t e = launch_spmm_batch(st, &it, 1);
+  if (nblk_out) *nblk_out = it.nblk;
+  return e;
 }
 
 hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSet& vs, int nv,
@@ -953,71 +1058,145 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
   return hipGetLastError();
 }
 
+static bool update_item_ok(const UpdateItem& it) {
+  const Geom& g = it.g;
+  if (!geom_ok(g) || g.ld > kMaxLd || !it.W || !it.d || it.nv < 0 || it.nv > 4 ||
+      (it.want_norm && !it.part) || (it.v1 && !it.v1mult) || (it.sym && !it.want_norm))
+    return false;
+  for (int v = 0; v < it.nv; ++v)
+    if (!it.vs.x[v] || it.vs.x[v] == it.W) return false;
+  return true;
+}
+
+static int update_nv_class(int nv) { return nv <= 1 ? 1 : (nv == 2 ? 2 : 4); }
+
+template <typename XT, int C, int NV, bool V1, bool SYM>
+static hipError_t update_launch(hipStream_t st, UpdateItem* items, const int* idx, int cnt) {
+  auto fn = k_update<XT, C, NV, V1, SYM>;
+  BatchArgs<UpdDesc> bt{};
+  bt.count = cnt;
+  int off = 0;
+  for (int q = 0; q < cnt; ++q) {
+    UpdateItem& it = items[idx[q]];
+    const int nb = stream_grid(it.g, (const void*)fn);
+    it.nblk = nb;
+    UpdDesc& d = bt.d[q];
+    d.n = it.g.n;
+    d.W = it.W;
+    for (int v = 0; v < 4; ++v) {
+      d.vx[v] = v < it.nv ? it.vs.x[v] : nullptr;
+      d.vmult[v] = v < it.nv ? it.vs.mult[v] : nullptr;
+    }
+    d.d = it.d;
+    d.v1 = it.v1;
+    d.v1mult = it.v1mult;
+    d.part = it.part;
+    d.lgL = it.g.lgL;
+    d.ld = it.g.ld;
+    d.ncolv = it.g.ncolv;
+    d.nv = it.nv;
+    d.voff = it.voff;
+    d.want_norm = it.want_norm;
+    bt.off[q] = off;
+    off += nb;
+  }
+  bt.off[cnt] = off;
+  hipLaunchKernelGGL(fn, dim3(off), dim3(kThreads), 0, st, bt);
+  return hipGetLastError();
+}
+
 template <typename XT, int NV, bool V1, bool SYM>
-static void update_launch(hipStream_t st, const Geom& g, XT* W, const VecSet& vs, int nv,
-                          const double* d, int voff, int want_norm, const XT* v1,
-                          const double* v1mult, double* part, int* nblk_out) {
-  LD_DISPATCH_C(g.C, {
-    auto fn = k_update<XT, CC, NV, V1, SYM>;
-    const int nb = stream_grid(g, (const void*)fn);
-    *nblk_out = nb;
-    hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL, W, g.ld, g.ncolv, vs, nv, d,
-                       voff, want_norm, v1, v1mult, part);
-  });
+static hipError_t update_launch_c(hipStream_t st, int C, UpdateItem* items, const int* idx,
+                                  int cnt) {
+  hipError_t e = hipErrorInvalidValue;
+  LD_DISPATCH_C(C, { e = update_launch<XT, CC, NV, V1, SYM>(st, items, idx, cnt); });
+  return e;
 }
 
 template <typename XT, int NV>
-static void update_nv(hipStream_t st, const Geom& g, XT* W, const VecSet& vs, int nv,
-                      const double* d, int voff, int want_norm, const XT* v1,
-                      const double* v1mult, bool sym, double* part, int* nblk_out) {
-  if (v1) {
-    if (sym)
-      update_launch<XT, NV, true, true>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, part, nblk_out);
-    else
-      update_launch<XT, NV, true, false>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, part, nblk_out);
-  } else {
-    if (sym)
-      update_launch<XT, NV, false, true>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, part, nblk_out);
-    else
-      update_launch<XT, NV, false, false>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, part, nblk_out);
-  }
+static hipError_t update_launch_flags(hipStream_t st, int C, bool v1, bool sym, UpdateItem* items,
+                                      const int* idx, int cnt) {
+  if (v1)
+    return sym ? update_launch_c<XT, NV, true, true>(st, C, items, idx, cnt)
+               : update_launch_c<XT, NV, true, false>(st, C, items, idx, cnt);
+  return sym ? update_launch_c<XT, NV, false, true>(st, C, items, idx, cnt)
+             : update_launch_c<XT, NV, false, false>(st, C, items, idx, cnt);
 }
 
 template <typename XT>
-static void update_typed(hipStream_t st, const Geom& g, XT* W, const VecSet& vs, int nv,
-                         const double* d, int voff, int want_norm, const XT* v1,
-                         const double* v1mult, bool sym, double* part, int* nblk_out) {
-  if (nv <= 1)
-    update_nv<XT, 1>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, sym, part, nblk_out);
-  else if (nv == 2)
-    update_nv<XT, 2>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, sym, part, nblk_out);
-  else
-    update_nv<XT, 4>(st, g, W, vs, nv, d, voff, want_norm, v1, v1mult, sym, part, nblk_out);
+static hipError_t update_launch_typed(hipStream_t st, const UpdateItem& it, UpdateItem* items,
+                                      const int* idx, int cnt) {
+  const bool v1 = it.v1 != nullptr;
+  switch (update_nv_class(it.nv)) {
+    case 1: return update_launch_flags<XT, 1>(st, it.g.C, v1, it.sym, items, idx, cnt);
+    case 2: return update_launch_flags<XT, 2>(st, it.g.C, v1, it.sym, items, idx, cnt);
+    default: return update_launch_flags<XT, 4>(st, it.g.C, v1, it.sym, items, idx, cnt);
+  }
+}
+
+hipError_t launch_update_batch(hipStream_t st, UpdateItem* items, int count) {
+  if (count < 0 || (count > 0 && !items)) return hipErrorInvalidValue;
+  for (int a = 0; a < count; ++a)
+    if (!update_item_ok(items[a])) return hipErrorInvalidValue;
+  auto key = [](const UpdateItem& it) -> uint64_t {
+    return (uint64_t)it.g.xbytes | ((uint64_t)it.g.C << 8) |
+           ((uint64_t)update_nv_class(it.nv) << 16) | ((uint64_t)(it.v1 != nullptr) << 24) |
+           ((uint64_t)it.sym << 25);
+  };
+  return launch_grouped(items, count, key, [&](const int* idx, int cnt) -> hipError_t {
+    const UpdateItem& it = items[idx[0]];
+    return it.g.xbytes == 8 ? update_launch_typed<double>(st, it, items, idx, cnt)
+                            : update_launch_typed<float>(st, it, items, idx, cnt);
+  });
 }
 
 hipError_t launch_update(hipStream_t st, const Geom& g, void* W, const VecSet& vs, int nv,
                          const double* d, int voff, int want_norm, const void* v1,
                          const double* v1mult, bool sym, double* part, int* nblk_out) {
-  int dummy = 0;
-  if (!nblk_out) nblk_out = &dummy;
-  if (!geom_ok(g) || g.ld > kMaxLd || !W || !d || nv < 0 || nv > 4 || (want_norm && !part) ||
-      (v1 && !v1mult) || (sym && !want_norm))
-    return hipErrorInvalidValue;
-  for (int v = 0; v < nv; ++v)
-    if (!vs.x[v] || vs.x[v] == W) return hipErrorInvalidValue;
-  if (g.xbytes == 8)
-    update_typed<double>(st, g, static_cast<double*>(W), vs, nv, d, voff, want_norm,
-                         static_cast<const double*>(v1), v1mult, sym, part, nblk_out);
-  else
-    update_typed<float>(st, g, static_cast<float*>(W), vs, nv, d, voff, want_norm,
-                        static_cast<const float*>(v1), v1mult, sym, part, nblk_out);
-  return hipGetLastError();
+  UpdateItem it{};
+  it.g = g;
+  it.W = W;
+  it.vs = vs;
+  it.nv = nv;
+  it.d = d;
+  it.voff = voff;
+  it.want_norm = want_norm;
+  it.v1 = v1;
+  it.v1mult = v1mult;
+  it.sym = sym;
+  it.part = part;
+  const hipError_t e = launch_update_batch(st, &it, 1);
+  if (nblk_out) *nblk_out = it.nblk;
+  return e;
+}
+
+hipError_t launch_reduce_batch(hipStream_t st, const ReduceItem* items, int count) {
+  if (count < 0 || (count > 0 && !items)) return hipErrorInvalidValue;
+  for (int a = 0; a < count; ++a)
+    if (!items[a].part || !items[a].out || items[a].nblk < 1 || items[a].width < 1)
+      return hipErrorInvalidValue;
+  for (int a0 = 0; a0 < count; a0 += kMaxBatch) {
+    const int cnt = std::min(kMaxBatch, count - a0);
+    BatchArgs<RedDesc> bt{};
+    bt.count = cnt;
+    int off = 0;
+    for (int q = 0; q < cnt; ++q) {
+      const ReduceItem& it = items[a0 + q];
+      bt.d[q] = RedDesc{it.part, it.out, it.nblk, it.width};
+      bt.off[q] = off;
+      off += it.width;
+    }
+    bt.off[cnt] = off;
+    hipLaunchKernelGGL(k_reduce, dim3((off + 3) / 4), dim3(kThreads), 0, st, bt);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_reduce(hipStream_t st, const double* part, int nblk, int width, double* out) {
-  if (!part || !out || nblk < 1 || width < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce, dim3((width + 3) / 4), dim3(kThreads), 0, st, part, nblk, width, out);
-  return hipGetLastError();
+  const ReduceItem it{part, nblk, width, out};
+  return launch_reduce_batch(st, &it, 1);
 }
 
 hipError_t launch_start_finish(hipStream_t st, int B, int ld, const double* part, int nblk,
@@ -1029,18 +1208,60 @@ hipError_t launch_start_finish(hipStream_t st, int B, int ld, const double* part
   return hipGetLastError();
 }
 
+hipError_t launch_step_finish_batch(hipStream_t st, const FinishItem* items, int count) {
+  if (count < 0 || (count > 0 && !items)) return hipErrorInvalidValue;
+  for (int a = 0; a < count; ++a) {
+    const FinishItem& it = items[a];
+    // the next step has at most nv + 1 window vectors: its second newest sits
+    // at row <= nv - 1 of d
+    if (it.B < 1 || it.ld < it.B || it.t < 0 || it.t >= it.m || it.j0 < 0 ||
+        it.j0 + it.nv != it.t + 1 || !it.part || it.nblk < 1 || it.sym_row >= it.nv ||
+        (it.sym_row >= 0 && it.t + 1 >= it.m))
+      return hipErrorInvalidValue;
+  }
+  for (int a0 = 0; a0 < count; a0 += kMaxBatch) {
+    const int cnt = std::min(kMaxBatch, count - a0);
+    BatchArgs<FinDesc> bt{};
+    bt.count = cnt;
+    int off = 0;
+    for (int q = 0; q < cnt; ++q) {
+      const FinishItem& it = items[a0 + q];
+      FinDesc& d = bt.d[q];
+      d.d = it.d;
+      d.part = it.part;
+      d.H = it.H;
+      d.meff = it.meff;
+      d.active = it.active;
+      d.mult_next = it.mult_next;
+      d.g = it.g;
+      d.flags = it.flags;
+      d.tol = it.tol;
+      d.B = it.B;
+      d.ld = it.ld;
+      d.t = it.t;
+      d.m = it.m;
+      d.j0 = it.j0;
+      d.nv = it.nv;
+      d.nblk = it.nblk;
+      d.sym_row = it.sym_row < 0 ? -1 : it.sym_row;
+      bt.off[q] = off;
+      off += it.ld;
+    }
+    bt.off[cnt] = off;
+    hipLaunchKernelGGL(k_step_finish, dim3((off + 3) / 4), dim3(kThreads), 0, st, bt);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, double* d, int j0,
                               int nv, const double* part, int nblk, double tol, double* H,
                               int* meff, int* active, double* mult_next, double* g, int* flags,
                               int sym_row) {
-  // the next step has at most nv + 1 window vectors: its second newest sits
-  // at row <= nv - 1 of d
-  if (B < 1 || ld < B || t < 0 || t >= m || j0 < 0 || j0 + nv != t + 1 || !part || nblk < 1 ||
-      sym_row >= nv || (sym_row >= 0 && t + 1 >= m))
-    return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_step_finish, dim3((ld + 3) / 4), dim3(kThreads), 0, st, B, ld, t, m, d, j0,
-                     nv, part, nblk, tol, H, meff, active, mult_next, g, flags, sym_row < 0 ? -1 : sym_row);
-  return hipGetLastError();
+  const FinishItem it{B, ld, t, m, d, j0, nv, part, nblk, tol, H, meff, active, mult_next, g, flags,
+                      sym_row};
+  return launch_step_finish_batch(st, &it, 1);
 }
 
 hipError_t launch_gauss_log(hipStream_t st, int B, int m, const double* H, const int* meff,

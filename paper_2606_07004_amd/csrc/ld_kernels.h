@@ -40,6 +40,67 @@ struct Geom {
 };
 Geom make_geom(int64_t n, int ld, int xbytes);
 
+// ---------------------------------------------------------------------------
+// Batched per-step launches: one launch advances the same kernel for up to
+// kMaxBatch requests (the scheduler's continuous batching); a single request
+// is a batch of one.  Device-side descriptors travel by value in the kernel
+// arguments; entry r owns grid blocks (or outputs) off[r] .. off[r+1]-1.
+// ---------------------------------------------------------------------------
+constexpr int kMaxBatch = 16;
+
+template <typename D>
+struct BatchArgs {
+  int count;
+  int off[kMaxBatch + 1];
+  D d[kMaxBatch];
+};
+
+struct SpmmDesc {
+  int64_t n;
+  const int* rp;
+  const int* ci;
+  const void* va;
+  const void* X;
+  void* W;
+  const double* xmult;
+  double opscale;
+  const void* fx[2];
+  const double* fmult[2];
+  double* part;
+  int lgL, ld, ncolv, voff;
+};
+
+struct UpdDesc {
+  int64_t n;
+  void* W;
+  const void* vx[4];
+  const double* vmult[4];
+  const double* d;
+  const void* v1;
+  const double* v1mult;
+  double* part;
+  int lgL, ld, ncolv, nv, voff, want_norm;
+};
+
+struct RedDesc {
+  const double* part;
+  double* out;
+  int nblk, width;
+};
+
+struct FinDesc {
+  double* d;
+  const double* part;
+  double* H;
+  int* meff;
+  int* active;
+  double* mult_next;
+  double* g;
+  int* flags;
+  double tol;
+  int B, ld, t, m, j0, nv, nblk, sym_row;
+};
+
 // Columns col0 .. col0+ncols-1 of X: probe columns pbase .. pbase+nvalid-1,
 // then zeros up to ncols (padding).
 hipError_t launch_rademacher(hipStream_t st, uint64_t seed, int64_t n, int pbase, int ncols,
@@ -72,6 +133,65 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
 hipError_t launch_update(hipStream_t st, const Geom& g, void* W, const VecSet& vs, int nv,
                          const double* d, int voff, int want_norm, const void* v1,
                          const double* v1mult, bool sym, double* part, int* nblk_out);
+
+// Host-side items of the batched launchers (same meaning as the arguments of
+// launch_spmm / launch_update / launch_reduce / launch_step_finish); nblk is
+// an output (the partial-sum blocks the item's product or update used).
+struct SpmmItem {
+  Geom g;
+  const int* rp;
+  const int* ci;
+  const void* va;
+  int vt;
+  const void* X;
+  void* W;
+  const double* xmult;
+  double opscale;
+  VecSet fused;
+  int nf;
+  int voff;
+  double* part;
+  int nblk;
+};
+struct UpdateItem {
+  Geom g;
+  void* W;
+  VecSet vs;
+  int nv;
+  const double* d;
+  int voff;
+  int want_norm;
+  const void* v1;
+  const double* v1mult;
+  bool sym;
+  double* part;
+  int nblk;
+};
+struct ReduceItem {
+  const double* part;
+  int nblk;
+  int width;
+  double* out;
+};
+struct FinishItem {
+  int B, ld, t, m;
+  double* d;
+  int j0, nv;
+  const double* part;
+  int nblk;
+  double tol;
+  double* H;
+  int* meff;
+  int* active;
+  double* mult_next;
+  double* g;
+  int* flags;
+  int sym_row;
+};
+hipError_t launch_spmm_batch(hipStream_t st, SpmmItem* items, int count);
+hipError_t launch_update_batch(hipStream_t st, UpdateItem* items, int count);
+hipError_t launch_reduce_batch(hipStream_t st, const ReduceItem* items, int count);
+hipError_t launch_step_finish_batch(hipStream_t st, const FinishItem* items, int count);
 
 // out[i] = sum_{b < nblk} part[i*nblk + b], fixed order.
 hipError_t launch_reduce(hipStream_t st, const double* part, int nblk, int width, double* out);
