@@ -499,7 +499,7 @@ ld_status Run::osa_sketch_combine(hipStream_t st) {
   return LD_OK;
 }
 
-ld_status Run::run_krylov_step(hipStream_t st, int t) {
+ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
   auto slot_of = [&](int j) -> int {
     if (kfull_) return j;
     if (kpin_) return j == 0 ? 0 : 1 + (j - 1) % (kns_ - 1);
@@ -531,6 +531,55 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
     vf.x[v] = slot_ptr(j0 + nv - nf + v);
     vf.mult[v] = mult_ptr(j0 + nv - nf + v);
   }
+  // the update pass hands the next step its second-newest inner product when
+  // it runs as one launch and the window holds two vectors or more
+  const bool sym_out = k_ >= 2 && nv <= 4 && t + 1 < m_;
+  const int nv_next = (t + 1) - std::max(0, t + 2 - k_) + 1;
+  const bool check = adaptive() && (t + 1) % adapt_every_ == 0 && t + 1 < m_;
+  if (plan) {
+    // a step of four launches (product, reduction, one update, bookkeeping)
+    // can join a batch of other requests' steps; the caller launches it
+    plan->valid = nold == 0 && nv <= 4 && !check && !prof_;
+    if (plan->valid) {
+      SpmmItem& sp = plan->spmm;
+      sp = SpmmItem{};
+      sp.g = kg_;
+      sp.rp = a_->rp;
+      sp.ci = a_->ci;
+      sp.va = vals;
+      sp.vt = vt;
+      sp.X = slot_ptr(t);
+      sp.W = W;
+      sp.xmult = mult_ptr(t);
+      sp.opscale = opscale_;
+      sp.fused = vf;
+      sp.nf = nf;
+      sp.voff = 0;
+      sp.part = part_;
+      plan->red = ReduceItem{part_, 0, nf * kld_, dwin_ + (size_t)(nv - nf) * kld_};
+      UpdateItem& up = plan->upd;
+      up = UpdateItem{};
+      up.g = kg_;
+      up.W = W;
+      for (int v = 0; v < nv; ++v) {
+        up.vs.x[v] = slot_ptr(j0 + v);
+        up.vs.mult[v] = mult_ptr(j0 + v);
+      }
+      up.nv = nv;
+      up.d = dwin_;
+      up.voff = 0;
+      up.want_norm = 1;
+      up.v1 = kpin_ ? slot_ptr(0) : nullptr;
+      up.v1mult = kpin_ ? mult_ptr(0) : nullptr;
+      up.sym = sym_out;
+      up.part = part_;
+      plan->fin = FinishItem{kB_, kld_, t, m_, dwin_, j0, nv, part_, 0, tol_, H_, meff_, active_,
+                             mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_,
+                             sym_out ? nv_next - 2 : -1};
+      sym_ready_ = sym_out;
+      return LD_OK;
+    }
+  }
   int nb = 0;
   LD_LAUNCH(LD_PROF_SPMM, spmm_bytes(kld_, xb_) + (nf - 1) * vec_bytes,
             launch_spmm(st, kg_, a_->rp, a_->ci, vals, vt, slot_ptr(t), W, mult_ptr(t), opscale_,
@@ -550,10 +599,6 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
     LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nc * kld_ * 8,
               launch_reduce(st, pp, nb, nc * kld_, dwin_ + (size_t)c0 * kld_));
   }
-  // the update pass hands the next step its second-newest inner product when
-  // it runs as one launch and the window holds two vectors or more
-  const bool sym_out = k_ >= 2 && nv <= 4 && t + 1 < m_;
-  const int nv_next = (t + 1) - std::max(0, t + 2 - k_) + 1;
   for (int c0 = 0; c0 < nv; c0 += 4) {
     VecSet vs{};
     const int nc = std::min(4, nv - c0);
@@ -572,7 +617,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
             launch_step_finish(st, kB_, kld_, t, m_, dwin_, j0, nv, part_, nb, tol_, H_,
                                meff_, active_, mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_,
                                sym_out ? nv_next - 2 : -1));
-  if (adaptive() && (t + 1) % adapt_every_ == 0 && t + 1 < m_) {
+  if (check) {
     // adaptive Krylov dimension: runs whose quadrature value settled stop;
     // the count of runs still going comes back to the host for the early exit
     if (!nact_host_) LD_HIP(hipHostMalloc((void**)&nact_host_, sizeof(int), hipHostMallocDefault));
@@ -586,6 +631,34 @@ ld_status Run::run_krylov_step(hipStream_t st, int t) {
     pending_check_ = true;
   }
   return LD_OK;
+}
+
+// Launch the planned steps of several requests: one launch per kernel for
+// all of them (grouped by kernel instantiation), in the order of a step.
+hipError_t launch_step_plans(hipStream_t st, std::vector<StepPlan>& plans) {
+  const int n = (int)plans.size();
+  if (n == 0) return hipSuccess;
+  std::vector<SpmmItem> sp(n);
+  std::vector<ReduceItem> rd(n);
+  std::vector<UpdateItem> up(n);
+  std::vector<FinishItem> fi(n);
+  for (int i = 0; i < n; ++i) sp[i] = plans[i].spmm;
+  hipError_t e = launch_spmm_batch(st, sp.data(), n);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < n; ++i) {
+    rd[i] = plans[i].red;
+    rd[i].nblk = sp[i].nblk;
+    up[i] = plans[i].upd;
+  }
+  e = launch_reduce_batch(st, rd.data(), n);
+  if (e != hipSuccess) return e;
+  e = launch_update_batch(st, up.data(), n);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < n; ++i) {
+    fi[i] = plans[i].fin;
+    fi[i].nblk = up[i].nblk;
+  }
+  return launch_step_finish_batch(st, fi.data(), n);
 }
 
 ld_status Run::run_epilogue(hipStream_t st) {
@@ -605,8 +678,9 @@ ld_status Run::run_epilogue(hipStream_t st) {
   return LD_OK;
 }
 
-ld_status Run::advance(hipStream_t st, int budget, bool* done) {
+ld_status Run::advance(hipStream_t st, int budget, bool* done, StepPlan* plan, bool* planned) {
   *done = false;
+  if (planned) *planned = false;
   while (budget > 0) {
     switch (stage_) {
       case ST_PROLOGUE: {
@@ -644,12 +718,17 @@ ld_status Run::advance(hipStream_t st, int budget, bool* done) {
             LD_HIP(q);
           }
         }
-        ld_status rc = run_krylov_step(st, t_);
+        ld_status rc = run_krylov_step(st, t_, plan);
         if (rc != LD_OK) return rc;
         ++t_;
         --budget;
         if (t_ >= m_)
           stage_ = (p_.method != LD_METHOD_OSLQ && kphase_ == 0) ? ST_COMBINE : ST_EPILOGUE;
+        if (plan && plan->valid) {
+          // the caller launches this step (with other requests' steps) first
+          *planned = true;
+          return LD_OK;
+        }
         break;
       }
       case ST_COMBINE: {
@@ -675,8 +754,11 @@ ld_status Run::advance(hipStream_t st, int budget, bool* done) {
   return LD_OK;
 }
 
-ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail) {
-  LD_HIP(hipStreamSynchronize(st));
+ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail, hipEvent_t done) {
+  if (done)
+    LD_HIP(hipEventSynchronize(done));  // a shared stream may hold later work of other requests
+  else
+    LD_HIP(hipStreamSynchronize(st));
   if (prof_) LD_HIP(prof_->harvest());
   if (lo_ == hi_) {
     // Q = q I (see advance): x^T L_c x / ||x||^2 = log q - c for every run

@@ -101,6 +101,16 @@ namespace ld {
 // work on a stream in slices (at most `budget` Krylov steps per call) so that
 // the serving scheduler can interleave many requests; a blocking estimate
 // simply calls it until it reports that everything is enqueued.
+// One Krylov step of one request as four batchable launches.
+struct StepPlan {
+  bool valid = false;
+  SpmmItem spmm{};
+  ReduceItem red{};
+  UpdateItem upd{};
+  FinishItem fin{};
+};
+hipError_t launch_step_plans(hipStream_t st, std::vector<StepPlan>& plans);
+
 class Run {
  public:
   Run(ld_matrix* a, const ld_params& p);
@@ -110,15 +120,22 @@ class Run {
   ld_status bind(void* base, size_t bytes);  // carve the device buffers
   // Enqueue up to `budget` Krylov steps (non-Krylov phases count as one).
   // Returns LD_OK when more work remains, LD_PENDING... see .cpp.
-  ld_status advance(hipStream_t st, int budget, bool* done);
-  ld_status collect(hipStream_t st, ld_result* out, const ld_detail* detail);
+  // With `plan`, a Krylov step that can join a batch is returned in *plan
+  // (and *planned set) instead of being launched; the caller must launch it
+  // (launch_step_plans) before advancing this request again.
+  ld_status advance(hipStream_t st, int budget, bool* done, StepPlan* plan = nullptr,
+                    bool* planned = nullptr);
+  // Waits for `done` when given (a stream shared with other requests), else
+  // for the whole stream.
+  ld_status collect(hipStream_t st, ld_result* out, const ld_detail* detail,
+                    hipEvent_t done = nullptr);
   ld_matrix* matrix() const { return a_; }
   const ld_params& params() const { return p_; }
 
  private:
   struct Phase;
   ld_status run_prologue(hipStream_t st);
-  ld_status run_krylov_step(hipStream_t st, int t);
+  ld_status run_krylov_step(hipStream_t st, int t, StepPlan* plan = nullptr);
   ld_status run_epilogue(hipStream_t st);
   ld_status sketch_qr(hipStream_t st, double* Y, int cols);
   ld_status osa_sketch_prologue(hipStream_t st);

@@ -22,11 +22,11 @@ Server::~Server() {
   cv_work_.notify_all();
   if (thread_.joinable()) thread_.join();
   (void)hipSetDevice(ctx_->device);
+  if (stream_) {
+    (void)hipStreamSynchronize(stream_);
+    (void)hipStreamDestroy(stream_);
+  }
   for (Slot& s : slots_) {
-    if (s.stream) {
-      (void)hipStreamSynchronize(s.stream);
-      (void)hipStreamDestroy(s.stream);
-    }
     if (s.done_ev) (void)hipEventDestroy(s.done_ev);
     if (s.mem) (void)hipFree(s.mem);
   }
@@ -127,48 +127,77 @@ void Server::loop() {
       if (used_ > stats_.peak_bytes) stats_.peak_bytes = used_;
       ++stats_.ticks;
     }
-    // bind newly admitted requests and enqueue a slice of every resident one
+    // bind newly admitted requests
+    if (!stream_ && hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking) != hipSuccess) {
+      stream_ = nullptr;
+      for (Slot& s : slots_)
+        if (s.req) finish(s, LD_E_DEVICE, nullptr, "stream creation failed");
+      continue;
+    }
     for (Slot& s : slots_) {
-      if (!s.req || s.enqueued_all) continue;
-      if (!s.stream) {
-        if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming) != hipSuccess) {
-          finish(s, LD_E_DEVICE, nullptr, "stream creation failed");
-          continue;
-        }
-      }
-      if (!s.bound) {
-        if (s.mem_bytes < s.req->bytes) {
-          if (s.mem) {
-            (void)hipStreamSynchronize(s.stream);
-            (void)hipFree(s.mem);
-            s.mem = nullptr;
-            s.mem_bytes = 0;
-          }
-          if (hipMalloc(&s.mem, s.req->bytes) != hipSuccess) {
-            s.mem = nullptr;
-            finish(s, LD_E_NO_MEMORY, nullptr, "device allocation for a request failed");
-            continue;
-          }
-          s.mem_bytes = s.req->bytes;
-        }
-        ld_status brc = s.req->run->bind(s.mem, s.mem_bytes);
-        if (brc != LD_OK) {
-          finish(s, brc, nullptr, ld_last_error());
-          continue;
-        }
-        s.bound = true;
-      }
-      bool done = false;
-      ld_status rc = s.req->run->advance(s.stream, steps_per_tick_, &done);
-      if (rc != LD_OK) {
-        (void)hipStreamSynchronize(s.stream);
-        finish(s, rc, nullptr, ld_last_error());
+      if (!s.req || s.enqueued_all || s.bound) continue;
+      if (!s.done_ev && hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming) != hipSuccess) {
+        s.done_ev = nullptr;
+        finish(s, LD_E_DEVICE, nullptr, "event creation failed");
         continue;
       }
-      if (done) {
-        s.enqueued_all = true;
-        (void)hipEventRecord(s.done_ev, s.stream);
+      if (s.mem_bytes < s.req->bytes) {
+        if (s.mem) {
+          (void)hipStreamSynchronize(stream_);
+          (void)hipFree(s.mem);
+          s.mem = nullptr;
+          s.mem_bytes = 0;
+        }
+        if (hipMalloc(&s.mem, s.req->bytes) != hipSuccess) {
+          s.mem = nullptr;
+          finish(s, LD_E_NO_MEMORY, nullptr, "device allocation for a request failed");
+          continue;
+        }
+        s.mem_bytes = s.req->bytes;
+      }
+      // a slot's memory is reused only after its previous request's work:
+      // every request runs on the one scheduler stream, in order
+      ld_status brc = s.req->run->bind(s.mem, s.mem_bytes);
+      if (brc != LD_OK) {
+        finish(s, brc, nullptr, ld_last_error());
+        continue;
+      }
+      s.bound = true;
+    }
+    // steps_per_tick rounds: in each, every resident request advances by one
+    // stage (its own launches) or by one Krylov step; the Krylov steps of a
+    // round go to the device together, one launch per kernel for all of them
+    for (int rep = 0; rep < steps_per_tick_; ++rep) {
+      std::vector<StepPlan> plans;
+      std::vector<Slot*> owners;
+      for (Slot& s : slots_) {
+        if (!s.req || s.enqueued_all || !s.bound) continue;
+        bool done = false, planned = false;
+        StepPlan pl;
+        const ld_status rc = s.req->run->advance(stream_, 1, &done, &pl, &planned);
+        if (rc != LD_OK) {
+          (void)hipStreamSynchronize(stream_);
+          finish(s, rc, nullptr, ld_last_error());
+          continue;
+        }
+        if (planned) {
+          plans.push_back(pl);
+          owners.push_back(&s);
+        }
+        if (done) {
+          s.enqueued_all = true;
+          (void)hipEventRecord(s.done_ev, stream_);
+        }
+      }
+      if (!plans.empty()) {
+        const hipError_t e = launch_step_plans(stream_, plans);
+        if (e != hipSuccess) {
+          (void)hipStreamSynchronize(stream_);
+          for (Slot* o : owners)
+            if (o->req) finish(*o, LD_E_DEVICE, nullptr, hipGetErrorString(e));
+        }
+        stats_.batched_steps += plans.size();
+        ++stats_.batched_launches;
       }
     }
     // retire finished requests
@@ -181,7 +210,7 @@ void Server::loop() {
         continue;
       }
       ld_result res{};
-      ld_status rc = (q == hipSuccess) ? s.req->run->collect(s.stream, &res, nullptr)
+      ld_status rc = (q == hipSuccess) ? s.req->run->collect(stream_, &res, nullptr, s.done_ev)
                                        : set_error(LD_E_DEVICE, hipGetErrorString(q));
       finish(s, rc, rc == LD_OK ? &res : nullptr, rc == LD_OK ? std::string() : ld_last_error());
     }

@@ -2,9 +2,12 @@
 //
 // Requests wait in a FIFO until a resident slot and enough of the HBM budget
 // are free; admitted requests own private device state, so a result depends
-// only on its own matrix and parameters.  Each scheduler tick enqueues a few
-// Krylov steps of every resident request on that slot's stream; the streams
-// run concurrently on the device, and a request that finishes frees its slot
+// only on its own matrix and parameters.  Each scheduler tick runs a few
+// rounds; in a round every resident request advances by one stage or one
+// Krylov step, and the Krylov steps of all resident requests go to the device
+// as one launch per kernel (batched kernels: each request keeps the grid it
+// would have alone, so its result is the same alone and in the mix).  All
+// work runs on one scheduler stream; a request that finishes frees its slot
 // and memory for the next one at the following tick.
 #pragma once
 
@@ -22,6 +25,7 @@ class Server {
   // scheduler statistics
   struct Stats {
     uint64_t submitted = 0, completed = 0, ticks = 0;
+    uint64_t batched_steps = 0, batched_launches = 0;  // Krylov steps, batches
     size_t peak_bytes = 0;
     int peak_active = 0;
   };
@@ -34,7 +38,6 @@ class Server {
     size_t bytes = 0;
   };
   struct Slot {
-    hipStream_t stream = nullptr;
     hipEvent_t done_ev = nullptr;
     std::unique_ptr<Request> req;
     void* mem = nullptr;
@@ -57,6 +60,7 @@ class Server {
   std::map<uint64_t, Done> done_;
   std::map<uint64_t, bool> live_;   // submitted and not yet retired
   std::vector<Slot> slots_;
+  hipStream_t stream_ = nullptr;    // the scheduler's stream
   size_t budget_ = 0, used_ = 0;
   uint64_t next_ticket_ = 1;
   bool stop_ = false;
