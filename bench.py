@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--no-grf", action="store_true",
                     help="skip the GRF likelihood theta-sweep leg")
     ap.add_argument("--grf-grid", type=str, default="900x1200")
+    ap.add_argument("--tune-reps", type=int, default=10,
+                    help="launches per candidate of the product/update geometry autotuner "
+                         "(0 keeps the default geometry)")
     return ap.parse_args()
 
 
@@ -313,6 +316,13 @@ def main():
     p = L.make_params(args.probes, args.sketch, args.krylov_steps, args.window, args.seed,
                       method=method, precision=prec)
 
+    tune = None
+    if args.tune_reps > 0:
+        t_tune = time.perf_counter()
+        tune = L.ld_autotune(h, p, args.tune_reps).as_dict()
+        tune["wall_s"] = time.perf_counter() - t_tune
+        print(f"[bench] autotune {tune}", file=sys.stderr, flush=True)
+
     accuracy = {}
     if not args.no_accuracy:
         p64 = L.make_params(args.probes, args.sketch, args.krylov_steps, args.window, args.seed,
@@ -415,7 +425,11 @@ def main():
                                f"(sketch {args.sketch} + {args.probes - args.sketch}), "
                                f"{args.krylov_steps} Krylov steps, window {args.window}, "
                                f"seed {args.seed}",
-                   "precision": args.precision, "values": vt, "parallelism": "single GPU"},
+                   "precision": args.precision, "values": vt, "parallelism": "single GPU",
+                   "geometry": ({"product": [tune["spmm_lanes"], tune["spmm_chunks"]],
+                                 "update": [tune["update_lanes"], tune["update_chunks"]]}
+                                if tune else "default")},
+        "autotune": tune,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": accuracy,

@@ -198,6 +198,41 @@ ld_status ld_estimate_ex(ld_matrix* a, const ld_params* p, ld_result* out);
 ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
                              const ld_detail* detail);
 
+/* Autotuner of the Krylov-step kernels (the product Q V of a probe block,
+ * and the orthogonalisation update with its fused norms).  Both sweep the
+ * probe block row by row with L lanes per row (a power of two <= 64), each
+ * lane holding C 16-byte chunks of the row (1 <= C <= 4, L * C chunks
+ * covering the block).  ld_autotune times every such (L, C) with at most half
+ * a row of idle chunks on this matrix, for the probe-block shapes and
+ * precision that `p` implies (the estimate block and, for OSA-IOP and So-SLQ,
+ * the sketch-run block), each kernel `reps` times per round over three
+ * rounds, keeping the fastest per kernel.  The choice is stored in the
+ * matrix and used by every later estimate and served request whose shapes
+ * match; results then differ from the untuned ones only by the summation
+ * order of the partial sums (FP64 rounding), and stay bitwise reproducible
+ * for a fixed choice.  Blocking; call it before submitting requests on this
+ * matrix (a request takes its geometry when it is admitted).  reps = 0 drops
+ * the stored choice for these shapes (back to the default).  `out` may be
+ * NULL; the lanes and chunks fields give the choice for the estimate block,
+ * the *_ms fields the mean time per launch of the choice and of the default
+ * geometry. */
+typedef struct {
+  int32_t spmm_lanes, spmm_chunks;
+  int32_t update_lanes, update_chunks;
+  double spmm_ms, spmm_default_ms;
+  double update_ms, update_default_ms;
+  int32_t candidates;        /* (L, C) pairs timed per kernel                  */
+  int32_t reserved;
+} ld_tune_result;
+ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_result* out);
+/* Stores a given geometry for the estimate block of `p` on this matrix (a
+ * choice found earlier, or one to test): the product with spmm_lanes lanes
+ * per row and spmm_chunks chunks per lane, the update likewise.  Any (L, C)
+ * with L a power of two <= 64, 1 <= C <= 4 and L * C chunks covering the
+ * block is accepted; anything else is LD_E_INVALID_ARG and stores nothing. */
+ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
+                      int32_t update_lanes, int32_t update_chunks);
+
 /* Serving with continuous batching: queue a request and return at once with
  * a ticket.  Requests are admitted as resident slots and HBM budget free up;
  * admitted requests advance together, several Krylov steps per scheduler

@@ -779,9 +779,6 @@ static int pow2_at_least(int x) {
 
 Geom make_geom(int64_t n, int ld, int xbytes) {
   Geom g;
-  g.n = n;
-  g.ld = ld;
-  g.xbytes = xbytes;
   g.vec = 16 / xbytes;
   g.ncolv = ld / g.vec;
   // lanes per row L (power of two <= 64) and 16-byte chunks per lane C <= 4:
@@ -799,11 +796,21 @@ Geom make_geom(int64_t n, int ld, int xbytes) {
       bestPref = pref;
     }
   }
-  g.L = bestL;
-  g.C = bestC;
+  return make_geom_lc(n, ld, xbytes, bestL, bestC);
+}
+
+Geom make_geom_lc(int64_t n, int ld, int xbytes, int L, int C) {
+  Geom g;
+  g.n = n;
+  g.ld = ld;
+  g.xbytes = xbytes;
+  g.vec = 16 / xbytes;
+  g.ncolv = ld / g.vec;
+  g.L = L;
+  g.C = C;
   g.lgL = 0;
-  while ((1 << g.lgL) < g.L) ++g.lgL;
-  const int rpi = kThreads / g.L;
+  while (g.lgL < 7 && (1 << g.lgL) < g.L) ++g.lgL;
+  const int rpi = kThreads / (L >= 1 && L <= kThreads ? L : 1);
   const int64_t nchunk = (n + rpi - 1) / rpi;
   int64_t nb = nchunk;
   if (nb > kMaxBlocks) nb = kMaxBlocks;
@@ -812,6 +819,9 @@ Geom make_geom(int64_t n, int ld, int xbytes) {
   g.rpb = (int)((n + nb - 1) / nb);  // contiguous partition for the sketch kernels
   return g;
 }
+
+static bool geom_ok(const Geom& g);
+bool geom_usable(const Geom& g) { return geom_ok(g); }
 
 static bool geom_ok(const Geom& g) {
   return g.n > 0 && g.ld > 0 && g.ld % 4 == 0 && (g.xbytes == 8 || g.xbytes == 4) &&

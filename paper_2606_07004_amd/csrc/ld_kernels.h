@@ -39,6 +39,10 @@ struct Geom {
   int rpb = 0;     // rows per block
 };
 Geom make_geom(int64_t n, int ld, int xbytes);
+// The same with an explicit lanes-per-row L (power of two) and chunks per
+// lane C (an autotuned choice); geom_usable tells whether it covers ld.
+Geom make_geom_lc(int64_t n, int ld, int xbytes, int L, int C);
+bool geom_usable(const Geom& g);
 
 // ---------------------------------------------------------------------------
 // Batched per-step launches: one launch advances the same kernel for up to

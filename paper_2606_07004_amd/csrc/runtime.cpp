@@ -258,7 +258,30 @@ ld_status Run::validate() {
   gB_ = make_geom(n_, ldB_, xb_);
   gS_ = make_geom(n_, lds_, 8);
   g1_ = make_geom(n_, ld1_, xb_);
+  gBp_ = krylov_geom(ldB_, 0);
+  gBu_ = krylov_geom(ldB_, 1);
+  g1p_ = krylov_geom(ld1_, 0);
+  g1u_ = krylov_geom(ld1_, 1);
   return LD_OK;
+}
+
+// Key of a tuned geometry: block width, element bytes, matrix value type of
+// the product, kernel (0 product, 1 update).
+static uint64_t tune_key(int ld, int xbytes, int vt, int which) {
+  return (uint64_t)ld | ((uint64_t)xbytes << 16) | ((uint64_t)vt << 24) | ((uint64_t)which << 32);
+}
+
+Geom Run::krylov_geom(int ld, int which) const {
+  const int vt = mixed_ ? a_->vt_lo : VT_F64;
+  {
+    std::lock_guard<std::mutex> lk(a_->tune_mu);
+    auto it = a_->tune.find(tune_key(ld, xb_, vt, which));
+    if (it != a_->tune.end()) {
+      const Geom g = make_geom_lc(n_, ld, xb_, it->second.first, it->second.second);
+      if (geom_usable(g)) return g;
+    }
+  }
+  return make_geom(n_, ld, xb_);
 }
 
 // One layout for measuring and for carving: with base == nullptr only the
@@ -390,21 +413,24 @@ ld_status Run::begin_krylov(int phase) {
   if (p_.method == LD_METHOD_OSLQ || (p_.method == LD_METHOD_SO_SLQ && phase == 1)) {
     kB_ = B_;
     kld_ = ldB_;
-    kg_ = gB_;
+    kg_ = gBp_;
+    kgu_ = gBu_;
     kpin_ = false;
     kfull_ = false;
     kns_ = std::min(k_, m_) + 1;
   } else if (phase == 0) {
     kB_ = s_;
     kld_ = ld1_;
-    kg_ = g1_;
+    kg_ = g1p_;
+    kgu_ = g1u_;
     kpin_ = false;
     kfull_ = true;
     kns_ = m_ + 1;
   } else {
     kB_ = B_;
     kld_ = ldB_;
-    kg_ = gB_;
+    kg_ = gBp_;
+    kgu_ = gBu_;
     kpin_ = true;
     kfull_ = false;
     kns_ = std::min(k_, m_) + 2;
@@ -559,7 +585,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
       plan->red = ReduceItem{part_, 0, nf * kld_, dwin_ + (size_t)(nv - nf) * kld_};
       UpdateItem& up = plan->upd;
       up = UpdateItem{};
-      up.g = kg_;
+      up.g = kgu_;
       up.W = W;
       for (int v = 0; v < nv; ++v) {
         up.vs.x[v] = slot_ptr(j0 + v);
@@ -595,7 +621,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
     }
     double* pp = part_ + (size_t)2 * kld_ * kMaxBlocks;
     LD_LAUNCH(LD_PROF_DOTS, (double)(nc + 1) * vec_bytes,
-              launch_dots(st, kg_, W, vs, nc, 0, pp, &nb));
+              launch_dots(st, kgu_, W, vs, nc, 0, pp, &nb));
     LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nc * kld_ * 8,
               launch_reduce(st, pp, nb, nc * kld_, dwin_ + (size_t)c0 * kld_));
   }
@@ -608,7 +634,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
     }
     const bool last = c0 + nc >= nv;
     LD_LAUNCH(LD_PROF_UPDATE, (double)(nc + 2 + ((last && kpin_) ? 1 : 0)) * vec_bytes,
-              launch_update(st, kg_, W, vs, nc, dwin_, c0, last ? 1 : 0,
+              launch_update(st, kgu_, W, vs, nc, dwin_, c0, last ? 1 : 0,
                             (last && kpin_) ? slot_ptr(0) : nullptr,
                             (last && kpin_) ? mult_ptr(0) : nullptr, last && sym_out, part_, &nb));
   }
@@ -876,6 +902,155 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail, 
   return LD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner of the Krylov-step geometry (lanes per row L, chunks per lane C).
+// ---------------------------------------------------------------------------
+
+// (L, C) pairs for a block of ld columns: L a power of two <= 64, C <= kMaxC,
+// L * C chunks covering the row with at most half a row idle; the default
+// geometry first.
+static std::vector<std::pair<int, int>> tune_candidates(int64_t n, int ld, int xbytes) {
+  const Geom d = make_geom(n, ld, xbytes);
+  std::vector<std::pair<int, int>> out{{d.L, d.C}};
+  for (int L = 1; L <= 64; L <<= 1)
+    for (int C = 1; C <= kMaxC; ++C) {
+      const int idle = L * C - d.ncolv;
+      if (idle < 0 || 2 * idle > d.ncolv || (L == d.L && C == d.C)) continue;
+      if (geom_usable(make_geom_lc(n, ld, xbytes, L, C))) out.push_back({L, C});
+    }
+  return out;
+}
+
+namespace {
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+}  // namespace
+
+ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
+  const int vt = mixed_ ? a_->vt_lo : VT_F64;
+  std::vector<int> widths{ldB_};
+  if (p_.method != LD_METHOD_OSLQ && s_ > 0 && ld1_ != ldB_) widths.push_back(ld1_);
+  if (reps == 0) {
+    std::lock_guard<std::mutex> lk(a_->tune_mu);
+    for (int ld : widths)
+      for (int which = 0; which < 2; ++which) a_->tune.erase(tune_key(ld, xb_, vt, which));
+    if (out) *out = ld_tune_result{};
+    return LD_OK;
+  }
+  const int ldmax = std::max(ldB_, ld1_);
+  const size_t n = (size_t)n_;
+  const size_t vec = align_up(n * ldmax * xb_);
+  // X (the product's input and newest window vector), V (an older window
+  // vector), W (product / update in place), column multipliers, zero
+  // coefficients and the partial sums
+  const size_t small = align_up((size_t)ldmax * 8) + align_up((size_t)4 * ldmax * 8);
+  const size_t partb = align_up((size_t)kMaxBlocks * 4 * ldmax * 8);
+  DeviceBuffer buf;
+  LD_HIP(buf.ensure(3 * vec + small + partb));
+  char* base = static_cast<char*>(buf.ptr);
+  void* X = base;
+  void* V = base + vec;
+  void* W = base + 2 * vec;
+  double* mult = reinterpret_cast<double*>(base + 3 * vec);
+  double* dcoef = reinterpret_cast<double*>(base + 3 * vec + align_up((size_t)ldmax * 8));
+  double* part = reinterpret_cast<double*>(base + 3 * vec + small);
+  const std::vector<double> ones((size_t)ldmax, 1.0);
+  LD_HIP(hipMemcpyAsync(mult, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, st));
+  LD_HIP(hipMemsetAsync(dcoef, 0, (size_t)4 * ldmax * 8, st));
+  const void* vals = (mixed_ && a_->vlo) ? a_->vlo : a_->v64;
+  // the window of a steady-state step: min(k, 4) vectors in one update pass,
+  // the second-newest inner product formed there when k >= 2
+  const int nv = std::max(1, std::min(k_, 4));
+  const bool sym = k_ >= 2;
+  EventPair ev;
+  LD_HIP(hipEventCreate(&ev.a));
+  LD_HIP(hipEventCreate(&ev.b));
+  for (size_t wi = 0; wi < widths.size(); ++wi) {
+    const int ld = widths[wi];
+    LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7475u, n_, 0, ld, ld, X, xb_, ld, 0));
+    LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7476u, n_, 0, ld, ld, V, xb_, ld, 0));
+    const auto cand = tune_candidates(n_, ld, xb_);
+    const int nc = (int)cand.size();
+    std::vector<double> tp(nc, 1e300), tu(nc, 1e300);
+    VecSet vf{};
+    vf.x[0] = X;
+    vf.mult[0] = mult;
+    VecSet vu{};
+    for (int v = 0; v < nv; ++v) {
+      vu.x[v] = v + 1 == nv ? X : V;
+      vu.mult[v] = mult;
+    }
+    for (int round = 0; round < 3; ++round)
+      for (int c = 0; c < nc; ++c) {
+        const Geom g = make_geom_lc(n_, ld, xb_, cand[c].first, cand[c].second);
+        int nb = 0;
+        float ms = 0.f;
+        auto product = [&]() {
+          return launch_spmm(st, g, a_->rp, a_->ci, vals, vt, X, W, mult, opscale_, &vf, 1, 0,
+                             part, &nb);
+        };
+        auto update = [&]() {
+          return launch_update(st, g, W, vu, nv, dcoef, 0, 1, nullptr, nullptr, sym, part, &nb);
+        };
+        LD_HIP(product());  // warm-up
+        LD_HIP(hipEventRecord(ev.a, st));
+        for (int i = 0; i < reps; ++i) LD_HIP(product());
+        LD_HIP(hipEventRecord(ev.b, st));
+        LD_HIP(hipEventSynchronize(ev.b));
+        LD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+        tp[c] = std::min(tp[c], (double)ms / reps);
+        LD_HIP(update());
+        LD_HIP(hipEventRecord(ev.a, st));
+        for (int i = 0; i < reps; ++i) LD_HIP(update());
+        LD_HIP(hipEventRecord(ev.b, st));
+        LD_HIP(hipEventSynchronize(ev.b));
+        LD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+        tu[c] = std::min(tu[c], (double)ms / reps);
+      }
+    int bp = 0, bu = 0;
+    for (int c = 1; c < nc; ++c) {
+      if (tp[c] < tp[bp]) bp = c;
+      if (tu[c] < tu[bu]) bu = c;
+    }
+    {
+      std::lock_guard<std::mutex> lk(a_->tune_mu);
+      a_->tune[tune_key(ld, xb_, vt, 0)] = cand[bp];
+      a_->tune[tune_key(ld, xb_, vt, 1)] = cand[bu];
+    }
+    if (wi == 0 && out) {
+      *out = ld_tune_result{};
+      out->spmm_lanes = cand[bp].first;
+      out->spmm_chunks = cand[bp].second;
+      out->update_lanes = cand[bu].first;
+      out->update_chunks = cand[bu].second;
+      out->spmm_ms = tp[bp];
+      out->spmm_default_ms = tp[0];
+      out->update_ms = tu[bu];
+      out->update_default_ms = tu[0];
+      out->candidates = nc;
+    }
+  }
+  return LD_OK;
+}
+
+ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int update_lanes, int update_chunks) {
+  if (!geom_usable(make_geom_lc(n_, ldB_, xb_, spmm_lanes, spmm_chunks)) ||
+      !geom_usable(make_geom_lc(n_, ldB_, xb_, update_lanes, update_chunks)))
+    return set_error(LD_E_INVALID_ARG,
+                     "lanes must be a power of two <= 64 and chunks in [1, 4], together "
+                     "covering the probe block");
+  const int vt = mixed_ ? a_->vt_lo : VT_F64;
+  std::lock_guard<std::mutex> lk(a_->tune_mu);
+  a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes, spmm_chunks};
+  a_->tune[tune_key(ldB_, xb_, vt, 1)] = {update_lanes, update_chunks};
+  return LD_OK;
+}
+
 }  // namespace ld
 
 // ---------------------------------------------------------------------------
@@ -1083,6 +1258,27 @@ ld_status ld_matrix_bounds(const ld_matrix* a, double* lo, double* hi) {
   *lo = a->lo;
   *hi = a->hi;
   return LD_OK;
+}
+
+ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_result* out) {
+  if (!a || !p) return set_error(LD_E_INVALID_ARG, "null argument");
+  if (reps < 0 || reps > 10000) return set_error(LD_E_INVALID_ARG, "reps must be in [0, 10000]");
+  ld_ctx* ctx = a->ctx;
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  LD_HIP_API(hipSetDevice(ctx->device));
+  Run run(a, *p);
+  ld_status rc = run.validate();
+  if (rc != LD_OK) return rc;
+  return run.tune(ctx->stream, reps, out);
+}
+
+ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
+                      int32_t update_lanes, int32_t update_chunks) {
+  if (!a || !p) return set_error(LD_E_INVALID_ARG, "null argument");
+  Run run(a, *p);
+  ld_status rc = run.validate();
+  if (rc != LD_OK) return rc;
+  return run.tune_set(spmm_lanes, spmm_chunks, update_lanes, update_chunks);
 }
 
 ld_status ld_quad_form(ld_matrix* a, const double* x, double* out) {

@@ -92,15 +92,14 @@ struct ld_matrix {
   double lo = 0, hi = 0;    // interval used by the estimators
   size_t bytes = 0;
   std::atomic<int> inflight{0};
+  // autotuned product/update geometry per Krylov block shape:
+  // key (ld, bytes per element, value type) -> (lanes per row, chunks per lane)
+  mutable std::mutex tune_mu;
+  std::map<uint64_t, std::pair<int, int>> tune;
 };
 
 namespace ld {
 
-// One estimate: the device state of one (matrix, params) request and the
-// ordered list of device operations that compute it.  advance() enqueues
-// work on a stream in slices (at most `budget` Krylov steps per call) so that
-// the serving scheduler can interleave many requests; a blocking estimate
-// simply calls it until it reports that everything is enqueued.
 // One Krylov step of one request as four batchable launches.
 struct StepPlan {
   bool valid = false;
@@ -111,6 +110,11 @@ struct StepPlan {
 };
 hipError_t launch_step_plans(hipStream_t st, std::vector<StepPlan>& plans);
 
+// One estimate: the device state of one (matrix, params) request and the
+// ordered list of device operations that compute it.  advance() enqueues
+// work on a stream in slices (at most `budget` Krylov steps per call) so that
+// the serving scheduler can interleave many requests; a blocking estimate
+// simply calls it until it reports that everything is enqueued.
 class Run {
  public:
   Run(ld_matrix* a, const ld_params& p);
@@ -143,6 +147,9 @@ class Run {
   ld_status start_block(hipStream_t st, const double* A, int s_cols);
   ld_status begin_krylov(int phase);
   size_t layout(char* base);
+  // product (which = 0) or update (which = 1) geometry of a Krylov block of
+  // width ld: the matrix's tuned choice when it holds one, else the default
+  Geom krylov_geom(int ld, int which) const;
   double spmm_bytes(int ld, int xbytes) const;
 
   ld_matrix* a_;
@@ -158,6 +165,7 @@ class Run {
   int xb_ = 8;                // bytes per Krylov element
   int lds_ = 0, ldr_ = 0, ldB_ = 0, ld1_ = 0, ldx_ = 0;
   Geom gB_, gS_, g1_;
+  Geom gBp_, gBu_, g1p_, g1u_;  // Krylov product / update geometries
   // state machine
   int stage_ = 0;             // 0 prologue, 1 krylov, 2 epilogue..., see .cpp
   int t_ = 0;
@@ -166,7 +174,7 @@ class Run {
   int kB_ = 0, kld_ = 0, kns_ = 0;
   bool kpin_ = false, kfull_ = false;
   bool sym_ready_ = false;    // the next step's second-newest window product is in dwin_
-  Geom kg_;
+  Geom kg_, kgu_;             // product / dots-and-update geometry of the phase
   void* kslots_ = nullptr;
   double* kmult_ = nullptr;
   // device buffers
@@ -221,6 +229,10 @@ class Run {
  public:
   void set_profiler(Profiler* p) { prof_ = p; }
   void set_blocking(bool b) { blocking_ = b; }
+  // Time the candidate geometries of the Krylov-block product and update on
+  // this request's matrix and block shape; store the fastest in the matrix.
+  ld_status tune(hipStream_t st, int reps, ld_tune_result* out);
+  ld_status tune_set(int spmm_lanes, int spmm_chunks, int update_lanes, int update_chunks);
   double submit_time() const { return t_submit_; }
   void set_submit_time(double t) { t_submit_ = t; }
   int64_t n() const { return n_; }

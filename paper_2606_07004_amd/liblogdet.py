@@ -78,6 +78,17 @@ class ld_detail(C.Structure):
                 ("tri_alpha", _DP), ("tri_beta", _DP), ("sketch_basis", _DP)]
 
 
+class ld_tune_result(C.Structure):
+    _fields_ = [("spmm_lanes", C.c_int32), ("spmm_chunks", C.c_int32),
+                ("update_lanes", C.c_int32), ("update_chunks", C.c_int32),
+                ("spmm_ms", C.c_double), ("spmm_default_ms", C.c_double),
+                ("update_ms", C.c_double), ("update_default_ms", C.c_double),
+                ("candidates", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
 _lib: Optional[C.CDLL] = None
 
 # (name, restype, argtypes) of every function declared in include/liblogdet.h
@@ -90,6 +101,10 @@ _SIGNATURES = [
     ("ld_destroy", C.c_int32, [C.c_void_p]),
     ("ld_matrix_bounds", C.c_int32, [C.c_void_p, _DP, _DP]),
     ("ld_quad_form", C.c_int32, [C.c_void_p, _DP, _DP]),
+    ("ld_autotune", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.c_int32,
+                                C.POINTER(ld_tune_result)]),
+    ("ld_tune_set", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.c_int32, C.c_int32,
+                                C.c_int32, C.c_int32]),
     ("ld_estimate", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                 C.c_uint64, C.POINTER(ld_result)]),
     ("ld_estimate_ex", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(ld_result)]),
@@ -241,6 +256,21 @@ def ld_quad_form(a, x) -> float:
     out = C.c_double()
     _check(lib().ld_quad_form(a, xv.ctypes.data_as(_DP), C.byref(out)))
     return out.value
+
+
+def ld_autotune(a, params: ld_params, reps: int = 20) -> ld_tune_result:
+    """Time the Krylov-step kernel geometries on matrix `a` for the shapes of
+    `params` and store the fastest in the matrix (reps = 0: drop it)."""
+    out = ld_tune_result()
+    _check(lib().ld_autotune(a, C.byref(params), int(reps), C.byref(out)))
+    return out
+
+
+def ld_tune_set(a, params: ld_params, spmm_lanes: int, spmm_chunks: int, update_lanes: int,
+                update_chunks: int) -> None:
+    """Store a given product / update geometry for the estimate block of `params`."""
+    _check(lib().ld_tune_set(a, C.byref(params), int(spmm_lanes), int(spmm_chunks),
+                             int(update_lanes), int(update_chunks)))
 
 
 def ld_submit(a, params: ld_params) -> int:

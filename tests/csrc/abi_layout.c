@@ -24,5 +24,10 @@ int main(void) {
   F(ld_detail, probe_K); F(ld_detail, probe_norm2); F(ld_detail, probe_steps);
   F(ld_detail, tri_alpha); F(ld_detail, tri_beta); F(ld_detail, sketch_basis);
   Z(ld_detail);
+  F(ld_tune_result, spmm_lanes); F(ld_tune_result, spmm_chunks); F(ld_tune_result, update_lanes);
+  F(ld_tune_result, update_chunks); F(ld_tune_result, spmm_ms); F(ld_tune_result, spmm_default_ms);
+  F(ld_tune_result, update_ms); F(ld_tune_result, update_default_ms);
+  F(ld_tune_result, candidates); F(ld_tune_result, reserved);
+  Z(ld_tune_result);
   return 0;
 }

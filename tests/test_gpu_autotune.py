@@ -1,0 +1,171 @@
+"""GPU tests of the Krylov-step geometry autotuner (ld_autotune, ld_tune_set).
+
+The product and update kernels sweep a probe block with L lanes per row and
+C 16-byte chunks per lane.  Any usable (L, C) must give the same estimate up
+to the summation order of the FP64 partial sums: every geometry is forced in
+turn and compared with the CPU FP64 oracle (1e-6 FP64, 1e-4 mixed) and with
+the default geometry (much tighter).  A tuned matrix must keep results
+bitwise reproducible, served requests equal to the same request alone, and
+a reset must restore the untuned results bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2606_07004_amd import liblogdet
+    liblogdet.lib()  # fails loudly when the HIP library is missing
+    return liblogdet
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    c = L.Context(0)
+    yield c
+    c.close()
+
+
+def _announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _usable(ncolv):
+    return [(lanes, ch) for lanes in (1, 2, 4, 8, 16, 32, 64) for ch in (1, 2, 3, 4)
+            if lanes * ch >= ncolv]
+
+
+def _sweep(L, ctx, a, npr, prec, vt, rtol_oracle, rtol_default, vec, k):
+    s, m, seed = 6, 14, 31
+    ref = oracle.oslq(a, npr, s, m, k, seed)
+    h = ctx.matrix(a, vt=vt)
+    try:
+        p = L.make_params(npr, s, m, k, seed, method=L.LD_METHOD_OSLQ, precision=prec)
+        base = L.ld_estimate_ex(h, p).logdet
+        assert abs(base - ref.logdet) <= rtol_oracle * abs(ref.logdet)
+        ncolv = ((npr + 3) // 4 * 4) // vec
+        geoms = _usable(ncolv)
+        for i, (lanes, ch) in enumerate(geoms):
+            # the update takes the geometries in the other order, so product
+            # and update differ in most cases
+            ul, uc = geoms[len(geoms) - 1 - i]
+            _announce(f"forced geometry n={a.n} probes={npr} prec={prec} "
+                      f"product L={lanes} C={ch} update L={ul} C={uc}")
+            L.ld_tune_set(h, p, lanes, ch, ul, uc)
+            res, det = L.ld_estimate_detail(h, p, n=a.n, tri=True)
+            rel = abs(res.logdet - ref.logdet) / abs(ref.logdet)
+            assert rel <= rtol_oracle, (lanes, ch, ul, uc, rel)
+            assert abs(res.logdet - base) <= rtol_default * abs(base), (lanes, ch, ul, uc)
+            np.testing.assert_array_equal(det["probe_steps"], np.array(ref.probe_steps))
+            np.testing.assert_allclose(det["probe_K"], ref.probe_K,
+                                       rtol=rtol_oracle * 100, atol=rtol_oracle * 100)
+    finally:
+        ctx.release(h)
+
+
+def test_every_geometry_fp64(L, ctx):
+    # 24 probes in FP64: 12 chunks per row; ragged n over the row chunks;
+    # window 5, so the separate inner-product pass and a two-launch update
+    # run with the forced update geometry as well
+    _sweep(L, ctx, W.lap3d(17, 0.05), 24, L.LD_PREC_FP64, L.LD_VT_FP64, 1e-6, 1e-11, 2, 5)
+
+
+def test_every_geometry_mixed(L, ctx):
+    # 96 probes in FP32: 24 chunks per row (the default is L = 8, C = 3)
+    _sweep(L, ctx, W.er_laplacian(6007, 40000, seed=4), 96, L.LD_PREC_MIXED, L.LD_VT_FP32,
+           1e-4, 1e-5, 4, 2)
+
+
+def test_invalid_geometry_rejected(L, ctx):
+    a = W.lap2d(40, 0.1)
+    h = ctx.matrix(a)
+    try:
+        p = L.make_params(24, 6, 10, 2, 1)
+        base = L.ld_estimate_ex(h, p).logdet
+        for bad in ((3, 4), (0, 1), (128, 1), (4, 0), (4, 5), (1, 4), (2, 4)):
+            _announce(f"ld_tune_set rejects L={bad[0]} C={bad[1]} for 12 chunks per row")
+            with pytest.raises(L.LdError) as ei:
+                L.ld_tune_set(h, p, bad[0], bad[1], 4, 3)
+            assert ei.value.status == L.LD_E_INVALID_ARG
+        # nothing was stored: still the default geometry
+        assert L.ld_estimate_ex(h, p).logdet == base
+    finally:
+        ctx.release(h)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotune_parity_and_reset(L, ctx, prec):
+    a = W.lap3d(24, 0.02)
+    mixed = prec == "mixed"
+    npr = 64 if mixed else 32
+    P = L.LD_PREC_MIXED if mixed else L.LD_PREC_FP64
+    vt = L.LD_VT_FP32 if mixed else L.LD_VT_FP64
+    s, m, k, seed = 8, 16, 2, 9
+    ref = oracle.oslq(a, npr, s, m, k, seed)
+    h = ctx.matrix(a, vt=vt)
+    try:
+        p = L.make_params(npr, s, m, k, seed, precision=P)
+        untuned = L.ld_estimate_ex(h, p).logdet
+        _announce(f"autotune n={a.n} probes={npr} prec={prec}")
+        tr = L.ld_autotune(h, p, 5)
+        print("  ", tr.as_dict(), flush=True)
+        ncolv = npr // (4 if mixed else 2)
+        assert tr.candidates >= 1
+        for lanes, ch in ((tr.spmm_lanes, tr.spmm_chunks), (tr.update_lanes, tr.update_chunks)):
+            assert (lanes, ch) in _usable(ncolv)
+            assert 2 * (lanes * ch - ncolv) <= ncolv or tr.candidates == 1
+        assert 0 < tr.spmm_ms <= tr.spmm_default_ms
+        assert 0 < tr.update_ms <= tr.update_default_ms
+        r1 = L.ld_estimate_ex(h, p).logdet
+        r2 = L.ld_estimate_ex(h, p).logdet
+        assert r1 == r2  # a fixed geometry stays bitwise reproducible
+        tol = 1e-4 if mixed else 1e-6
+        assert abs(r1 - ref.logdet) <= tol * abs(ref.logdet)
+        assert abs(r1 - untuned) <= (1e-5 if mixed else 1e-11) * abs(untuned)
+        _announce("autotune reset (reps = 0)")
+        L.ld_autotune(h, p, 0)
+        assert L.ld_estimate_ex(h, p).logdet == untuned
+    finally:
+        ctx.release(h)
+
+
+def test_autotune_osa_iop(L, ctx):
+    # OSA-IOP also tunes the sketch-run block (s columns)
+    a = W.lap2d(70, 0.05)
+    npr, s, m, k, seed = 40, 12, 14, 2, 5
+    ref = oracle.osa_iop(a, npr, s, m, k, seed)
+    h = ctx.matrix(a)
+    try:
+        p = L.make_params(npr, s, m, k, seed, method=L.LD_METHOD_OSA_IOP)
+        _announce(f"autotune osa-iop n={a.n} probes={npr} s={s}")
+        L.ld_autotune(h, p, 3)
+        res = L.ld_estimate_ex(h, p)
+        assert abs(res.logdet - ref.logdet) <= 1e-6 * abs(ref.logdet)
+    finally:
+        ctx.release(h)
+
+
+def test_served_equals_alone_when_tuned(L):
+    mats = [W.lap3d(20, 0.03), W.wendland(5000, 30.0, 0.02, seed=3)]
+    reqs = []
+    for i in range(len(mats)):
+        for j, prec in enumerate((L.LD_PREC_FP64, L.LD_PREC_MIXED)):
+            reqs.append((i, L.make_params(24 + 8 * j, 6, 12, 2, 70 + 3 * i + j, precision=prec)))
+    c = L.Context(0)
+    try:
+        hs = [c.matrix(a) for a in mats]
+        for i, p in reqs:
+            L.ld_tune_set(hs[i], p, *((16, 1, 8, 2) if p.precision == L.LD_PREC_FP64
+                                      else (16, 2, 32, 1)))
+        _announce("served vs alone on tuned matrices")
+        alone = [L.ld_estimate_ex(hs[i], p).logdet for i, p in reqs]
+        tickets = [L.ld_submit(hs[i], p) for i, p in reqs]
+        served = [L.ld_wait(c.handle, t).logdet for t in tickets]
+        assert served == alone
+    finally:
+        c.close()
