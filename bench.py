@@ -66,13 +66,15 @@ def parse():
     return ap.parse_args()
 
 
-def pmc_traffic(args, family):
+def pmc_traffic(args, family, tune):
     """HBM bytes per launch of `family`'s kernel from the committed PMC summary.
 
     FETCH_SIZE and WRITE_SIZE were taken with rocprofv3 on this workload and
-    scaled by what they read for a plain copy of known size.  Returns None when
-    the workload differs or the kernel source changed since the counters were
-    taken (the figures would then describe another kernel).
+    scaled by what they read for a plain copy of known size.  The kernel
+    instance is the one of the geometry this run used (its chunks-per-lane
+    template argument).  Returns None when the workload differs, the kernel
+    source changed since the counters were taken, or that instance was not
+    profiled (the figures would then describe another kernel).
     """
     import hashlib
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
@@ -89,7 +91,14 @@ def pmc_traffic(args, family):
         with open(os.path.join(ROOT, src), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
-    kname = rec.get("family_kernel", {}).get(family)
+    pattern = rec.get("family_kernel", {}).get(family)
+    if pattern is None:
+        return None
+    if tune:
+        chunks = tune["spmm_chunks"] if family == "spmm" else tune["update_chunks"]
+    else:
+        chunks = rec.get("default_chunks", {}).get(family)
+    kname = pattern.replace("{C}", str(chunks))
     k = rec.get("kernels", {}).get(kname)
     if k is None:
         return None
@@ -371,7 +380,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": achieved * 1e9 / HBM_PEAK, "traffic": None,
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch}
-    tr = pmc_traffic(args, dom)
+    tr = pmc_traffic(args, dom, tune)
     if tr is not None:
         roofline["traffic"] = tr["bytes_per_launch"]
         roofline["traffic_detail"] = tr
