@@ -31,13 +31,18 @@ HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
 FAMILIES = ("spmm", "dots", "update", "reduce", "small", "sketch", "probes")
 
 
+PRECISIONS = {"mixed": lambda L: L.LD_PREC_MIXED, "half": lambda L: L.LD_PREC_HALF,
+              "fp64": lambda L: L.LD_PREC_FP64}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--method", choices=("oslq", "osa_iop"), default="oslq")
-    ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
+    ap.add_argument("--precision", choices=("mixed", "half", "fp64"), default="mixed",
+                    help="Krylov vectors in FP32 (mixed), FP16 (half) or FP64")
     ap.add_argument("--values", choices=("fp32", "bf16"), default="fp32")
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--shift", type=float, default=1e-2)
@@ -165,7 +170,7 @@ def comparators_bench(L, W, ctx, h, a, vt, args):
     }
     out = {}
     for name, p in cases.items():
-        p.precision = L.LD_PREC_MIXED if args.precision == "mixed" else L.LD_PREC_FP64
+        p.precision = PRECISIONS[args.precision](L)
         L.ld_estimate_ex(h, p)
         t0 = time.perf_counter()
         r = L.ld_estimate_ex(h, p)
@@ -314,7 +319,7 @@ def main():
     a = W.lap3d(args.grid, args.shift)
     t_build = time.perf_counter() - t_build
     method = L.LD_METHOD_OSLQ if args.method == "oslq" else L.LD_METHOD_OSA_IOP
-    prec = L.LD_PREC_MIXED if args.precision == "mixed" else L.LD_PREC_FP64
+    prec = PRECISIONS[args.precision](L)
     vt = L.LD_VT_FP64 if args.precision == "fp64" else (
         L.LD_VT_FP32 if args.values == "fp32" else L.LD_VT_BF16)
     print(f"[bench] {a.name} n={a.n} nnz={a.nnz} built in {t_build:.1f} s", file=sys.stderr,
@@ -427,7 +432,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "mixed" else "f64",
+        "dtype": {"mixed": "f32", "half": "f16", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.method} 3D 7-point Laplacian {args.grid}^3 + {args.shift:g} I "
                                f"(n={a.n}, nnz={a.nnz}), {args.probes} Rademacher probes "

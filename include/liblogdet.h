@@ -75,8 +75,15 @@ typedef enum { LD_PROBE_RADEMACHER = 0, LD_PROBE_GAUSSIAN = 1 } ld_probe_dist;
  * its storage type (FP32 or BF16 values with FP32 row sums; FP64 values with
  * FP64 row sums, rounded to FP32 once per entry); every inner product and
  * norm accumulated in FP64; sketch QR, projection, the small
- * tridiagonal/Hessenberg reductions and the trace in FP64. */
-typedef enum { LD_PREC_FP64 = 0, LD_PREC_MIXED = 1 } ld_precision;
+ * tridiagonal/Hessenberg reductions and the trace in FP64.
+ * LD_PREC_HALF: as LD_PREC_MIXED with the Krylov vectors stored in IEEE
+ * FP16 (row sums of the product in FP32, or FP64 for FP64 values).  Each
+ * stored block carries a power-of-two scale that keeps the entries of unit
+ * vectors near 1 and below the FP16 range limit; the scale is removed
+ * exactly from every inner product and norm.  Half the vector traffic of
+ * LD_PREC_MIXED; the extra rounding (2^-11 per stored entry) enters the
+ * estimate through averages over n entries and many probes. */
+typedef enum { LD_PREC_FP64 = 0, LD_PREC_MIXED = 1, LD_PREC_HALF = 2 } ld_precision;
 
 typedef struct ld_ctx ld_ctx;
 typedef struct ld_matrix ld_matrix;

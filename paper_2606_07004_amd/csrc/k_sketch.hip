@@ -402,7 +402,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
                                                           int lda, int s, const double* __restrict__ Gm,
                                                           int ldg, int r, const double* __restrict__ P,
                                                           XT* __restrict__ X0, int ld,
-                                                          double* __restrict__ part) {
+                                                          double* __restrict__ part, double oscale) {
   extern __shared__ double sm[];
   const int r16 = (r + 15) & ~15, s4 = (s + 3) & ~3;
   double* sP = sm;                                  // [s4][r16]
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
         const int64_t row = row0 + q;
         if (row >= rb1) break;
         const double v = A[(size_t)row * lda + l];
-        X0[(size_t)row * ld + l] = XT(v);
+        X0[(size_t)row * ld + l] = XT(v * oscale);
         nrm_a = fma(v, v, nrm_a);
       }
     }
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
           const int64_t row = row0 + 4 * e + kr;
           if (row < rb1 && j < r) {
             const double v = Gm[(size_t)row * ldg + j] - acc[t][e];
-            X0[(size_t)row * ld + s + j] = XT(v);
+            X0[(size_t)row * ld + s + j] = XT(v * oscale);
             nrm_res[t0 + t] = fma(v, v, nrm_res[t0 + t]);
           }
         }
@@ -500,7 +500,8 @@ __global__ __launch_bounds__(kThreads) void k_project(int64_t n, int rpb, const 
                                                      int lda, int s, const double* __restrict__ Gm,
                                                      int ldg, int r, const double* __restrict__ P,
                                                      int p_in_lds, XT* __restrict__ X0, int ld,
-                                                     int tr, double* __restrict__ part) {
+                                                     int tr, double* __restrict__ part,
+                                                     double oscale) {
   extern __shared__ double sm[];
   double* sa = sm;                      // [tr][s]
   double* so = sa + (size_t)tr * s;     // [tr][ld]
@@ -550,7 +551,7 @@ __global__ __launch_bounds__(kThreads) void k_project(int64_t n, int rpb, const 
     if (t < ld) {
       for (int rr = 0; rr < nr; ++rr) {
         const double v = so[rr * ld + t];
-        X0[(size_t)(rowb + rr) * ld + t] = XT(v);
+        X0[(size_t)(rowb + rr) * ld + t] = XT(v * oscale);
         nacc = fma(v, v, nacc);
       }
     }
@@ -647,9 +648,11 @@ hipError_t launch_subspace_eig(hipStream_t st, int q, int k, const double* G, do
 }
 
 hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int lda, int s,
-                          const double* Gm, int ldg, int r, const double* P, void* X0, double* part) {
+                          const double* Gm, int ldg, int r, const double* P, void* X0, double* part,
+                          double oscale) {
   if (g.n < 1 || g.nblk < 1 || (int64_t)g.nblk * g.rpb < g.n || !Gm || !X0 || !part || r < 1 ||
-      s < 0 || s + r > g.ld || g.ld > kThreads || (s > 0 && (!A || !P || lda < s)) || ldg < r)
+      s < 0 || s + r > g.ld || g.ld > kThreads || (s > 0 && (!A || !P || lda < s)) || ldg < r ||
+      !(oscale > 0.0))
     return hipErrorInvalidValue;
   {
     // matrix cores when P (and the norm partials) fit the block's LDS
@@ -658,10 +661,14 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
     if (s <= kMfmaMaxCols && r <= 256 && lds_m <= 64 * 1024) {
       if (g.xbytes == 8)
         hipLaunchKernelGGL(k_project_mfma<double>, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n, g.rpb,
-                           A, lda, s, Gm, ldg, r, P, static_cast<double*>(X0), g.ld, part);
-      else
+                           A, lda, s, Gm, ldg, r, P, static_cast<double*>(X0), g.ld, part, oscale);
+      else if (g.xbytes == 4)
         hipLaunchKernelGGL(k_project_mfma<float>, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n, g.rpb,
-                           A, lda, s, Gm, ldg, r, P, static_cast<float*>(X0), g.ld, part);
+                           A, lda, s, Gm, ldg, r, P, static_cast<float*>(X0), g.ld, part, oscale);
+      else
+        hipLaunchKernelGGL(k_project_mfma<_Float16>, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n,
+                           g.rpb, A, lda, s, Gm, ldg, r, P, static_cast<_Float16*>(X0), g.ld, part,
+                           oscale);
       return hipGetLastError();
     }
   }
@@ -678,10 +685,14 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
   }
   if (g.xbytes == 8)
     hipLaunchKernelGGL(k_project<double>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A, lda,
-                       s, Gm, ldg, r, P, p_in_lds, static_cast<double*>(X0), g.ld, tr, part);
-  else
+                       s, Gm, ldg, r, P, p_in_lds, static_cast<double*>(X0), g.ld, tr, part, oscale);
+  else if (g.xbytes == 4)
     hipLaunchKernelGGL(k_project<float>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A, lda,
-                       s, Gm, ldg, r, P, p_in_lds, static_cast<float*>(X0), g.ld, tr, part);
+                       s, Gm, ldg, r, P, p_in_lds, static_cast<float*>(X0), g.ld, tr, part, oscale);
+  else
+    hipLaunchKernelGGL(k_project<_Float16>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A,
+                       lda, s, Gm, ldg, r, P, p_in_lds, static_cast<_Float16*>(X0), g.ld, tr, part,
+                       oscale);
   return hipGetLastError();
 }
 

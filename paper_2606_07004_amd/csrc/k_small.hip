@@ -390,9 +390,14 @@ hipError_t launch_combine(hipStream_t st, int64_t n, int ld, int nt, const void*
   if (xbytes == 8)
     hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)nb), dim3(kThreads), 0, st, n, ld, nt,
                        static_cast<const double*>(slots), slot_elems, coef, Y, ldy);
-  else
+  else if (xbytes == 4)
     hipLaunchKernelGGL(k_combine<float>, dim3((unsigned)nb), dim3(kThreads), 0, st, n, ld, nt,
                        static_cast<const float*>(slots), slot_elems, coef, Y, ldy);
+  else if (xbytes == 2)
+    hipLaunchKernelGGL(k_combine<_Float16>, dim3((unsigned)nb), dim3(kThreads), 0, st, n, ld, nt,
+                       static_cast<const _Float16*>(slots), slot_elems, coef, Y, ldy);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -240,8 +240,8 @@ __device__ inline void spmm_body(int64_t n, int lgL, const int* __restrict__ rp,
         if (okc[c]) {
 #pragma unroll
           for (int e = 0; e < VEC; ++e) {
-            acc[c][e] = fma(a0, x0[c].v[e], acc[c][e]);
-            acc[c][e] = fma(a1, x1[c].v[e], acc[c][e]);
+            acc[c][e] = fma(a0, A(x0[c].v[e]), acc[c][e]);
+            acc[c][e] = fma(a1, A(x1[c].v[e]), acc[c][e]);
           }
           if (FUSED) {
             if (c0 == row) xd[c] = x0[c];
@@ -256,7 +256,7 @@ __device__ inline void spmm_body(int64_t n, int lgL, const int* __restrict__ rp,
           V16<XT> x;
           x.load(X + (size_t)c0 * ld + colc[c]);
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) acc[c][e] = fma(a0, x.v[e], acc[c][e]);
+          for (int e = 0; e < VEC; ++e) acc[c][e] = fma(a0, A(x.v[e]), acc[c][e]);
           if (FUSED && c0 == row) xd[c] = x;
         }
     };
@@ -322,7 +322,7 @@ __device__ inline void spmm_body(int64_t n, int lgL, const int* __restrict__ rp,
 // One CSR x block product per batch entry: blocks off[r] .. off[r+1]-1 of
 // the grid belong to request r (a single product is a batch of one).
 template <typename VT, typename XT, int C, int NF>
-__global__ __launch_bounds__(kThreads, (NF == 2 || sizeof(VT) > sizeof(XT)) ? 4 : 6) void k_spmm(
+__global__ __launch_bounds__(kThreads, (NF == 2 || (sizeof(VT) == 8 && sizeof(XT) < 8)) ? 4 : 6) void k_spmm(
     BatchArgs<SpmmDesc> bt) {
   int r = 0;
   while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
@@ -406,12 +406,15 @@ __device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int l
                                    const XT* __restrict__ v1, const double* __restrict__ v1mult,
                                    double* __restrict__ part, int bk, int nbk) {
   constexpr int VEC = V16<XT>::N;
+  // the vector arithmetic: FP64 for FP64 and FP32 storage; FP32 for FP16
+  // storage (its 11-bit results leave FP32 rounding far below their own)
+  using U = typename std::conditional<std::is_same<XT, _Float16>::value, float, double>::type;
   __shared__ double red[kThreads * VEC * C];
-  __shared__ double cf[NV * kMaxLd];
+  __shared__ U cf[NV * kMaxLd];
   const RowMap rm(lgL);
   for (int i = threadIdx.x; i < NV * ld; i += kThreads) {
     const int v = i / ld, col = i - v * ld;
-    cf[i] = v < nv ? d[(size_t)(voff + v) * ld + col] * (vmult[v] ? vmult[v][col] : 1.0) : 0.0;
+    cf[i] = U(v < nv ? d[(size_t)(voff + v) * ld + col] * (vmult[v] ? vmult[v][col] : 1.0) : 0.0);
   }
   __syncthreads();
   bool okc[C];
@@ -442,9 +445,9 @@ __device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int l
       if (okc[c]) {
         V16<XT> w;
         w.load_nt(W + (size_t)row * ld + colc[c]);  // the product is read once
-        double wd[VEC];
+        U wd[VEC];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) wd[e] = double(w.v[e]);
+        for (int e = 0; e < VEC; ++e) wd[e] = U(w.v[e]);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
           if (v < nv) {
@@ -454,28 +457,31 @@ __device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int l
               x.load_nt(static_cast<const XT*>(vx[v]) + (size_t)row * ld + colc[c]);
             else
               x.load(static_cast<const XT*>(vx[v]) + (size_t)row * ld + colc[c]);
-            const double* cfv = cf + v * ld + colc[c];
+            const U* cfv = cf + v * ld + colc[c];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) wd[e] = fma(-cfv[e], double(x.v[e]), wd[e]);
+            for (int e = 0; e < VEC; ++e) wd[e] = fma(-cfv[e], U(x.v[e]), wd[e]);
           }
         V16<XT> o;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) o.v[e] = XT(wd[e]);
         o.store_nt(W + (size_t)row * ld + colc[c]);
         if (want_norm) {
+          double od[VEC];
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) nacc[c][e] = fma(double(o.v[e]), double(o.v[e]), nacc[c][e]);
+          for (int e = 0; e < VEC; ++e) od[e] = double(U(o.v[e]));
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) nacc[c][e] = fma(od[e], od[e], nacc[c][e]);
           if constexpr (SYM) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
-              sacc[c][e] = fma(double(w.v[e]), double(o.v[e]), sacc[c][e]);
+              sacc[c][e] = fma(double(U(w.v[e])), od[e], sacc[c][e]);
           }
           if constexpr (V1) {
             V16<XT> x1;
             x1.load(v1 + (size_t)row * ld + colc[c]);
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
-              gacc[c][e] = fma(double(x1.v[e]), double(o.v[e]), gacc[c][e]);
+              gacc[c][e] = fma(double(U(x1.v[e])), od[e], gacc[c][e]);
           }
         }
       }
@@ -542,7 +548,8 @@ __global__ __launch_bounds__(kThreads) void k_start_finish(int B, int ld, const 
                                                           double* __restrict__ mult0,
                                                           int* __restrict__ active,
                                                           int* __restrict__ meff,
-                                                          double* __restrict__ g, int gstride) {
+                                                          double* __restrict__ g, int gstride,
+                                                          double inv_oscale) {
   const int lane = threadIdx.x & 63;
   const int p = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (p >= ld) return;
@@ -552,7 +559,7 @@ __global__ __launch_bounds__(kThreads) void k_start_finish(int B, int ld, const 
   norm2[p] = v;
   meff[p] = 0;
   if (p < B && v > 0.0 && isfinite(v)) {
-    mult0[p] = 1.0 / sqrt(v);
+    mult0[p] = inv_oscale / sqrt(v);  // the block is stored at scale 1 / inv_oscale
     active[p] = 1;
   } else {
     mult0[p] = 0.0;
@@ -596,12 +603,15 @@ __global__ __launch_bounds__(kThreads) void k_step_finish(BatchArgs<FinDesc> bt)
   }
   double* Hp = H + (size_t)p * (m + 1) * m;
   bool finite = true;
+  // the product output, and with it every window inner product and the new
+  // vector, is stored at the scale 1 / inv_s (a power of two)
   for (int v = 0; v < nv; ++v) {
-    const double h = d[(size_t)v * ld + p];
+    const double h = d[(size_t)v * ld + p] * q.inv_s;
     finite = finite && isfinite(h);
     Hp[(size_t)(j0 + v) * m + t] = h;
   }
-  const double beta = sqrt(nrm2);
+  const double nrm = sqrt(nrm2);  // norm of the stored new vector
+  const double beta = nrm * q.inv_s;
   Hp[(size_t)(t + 1) * m + t] = beta;
   meff[p] = t + 1;
   if (!finite || !isfinite(beta)) {
@@ -618,9 +628,9 @@ __global__ __launch_bounds__(kThreads) void k_step_finish(BatchArgs<FinDesc> bt)
     if (dsym) *dsym = 0.0;
     return;
   }
-  if (g) g[(size_t)p * (m + 1) + t + 1] = gdot / beta;
-  if (dsym) *dsym = sdot / beta;
-  mult_next[p] = 1.0 / beta;
+  if (g) g[(size_t)p * (m + 1) + t + 1] = gdot / nrm;
+  if (dsym) *dsym = sdot / nrm;
+  mult_next[p] = 1.0 / nrm;
 }
 
 // ---------------------------------------------------------------------------
@@ -781,6 +791,11 @@ Geom make_geom(int64_t n, int ld, int xbytes) {
   Geom g;
   g.vec = 16 / xbytes;
   g.ncolv = ld / g.vec;
+  // FP16 blocks: one chunk per lane (the per-thread column sums of the
+  // fused inner products, 8 per chunk, then fit the registers and the
+  // block's LDS at full occupancy)
+  if (xbytes == 2 && pow2_at_least(g.ncolv) <= 64)
+    return make_geom_lc(n, ld, xbytes, pow2_at_least(g.ncolv), 1);
   // lanes per row L (power of two <= 64) and 16-byte chunks per lane C <= 4:
   // least idle lanes, then C closest to 2
   int bestL = 64, bestC = 1, bestWaste = 1 << 30, bestPref = 1 << 30;
@@ -824,7 +839,7 @@ static bool geom_ok(const Geom& g);
 bool geom_usable(const Geom& g) { return geom_ok(g); }
 
 static bool geom_ok(const Geom& g) {
-  return g.n > 0 && g.ld > 0 && g.ld % 4 == 0 && (g.xbytes == 8 || g.xbytes == 4) &&
+  return g.n > 0 && g.ld > 0 && g.ld % 4 == 0 && (g.xbytes == 8 || g.xbytes == 4 || g.xbytes == 2) &&
          g.vec * g.ncolv == g.ld && g.L >= 1 && g.L <= 64 && (1 << g.lgL) == g.L && g.C >= 1 &&
          g.C <= kMaxC && g.L * g.C >= g.ncolv && g.nblk >= 1 && (int64_t)g.nblk * g.rpb >= g.n;
 }
@@ -878,6 +893,9 @@ hipError_t launch_rademacher(hipStream_t st, uint64_t seed, int64_t n, int pbase
   else if (xbytes == 4)
     hipLaunchKernelGGL(k_rademacher<float>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
                        nvalid, static_cast<float*>(X), ld, col0);
+  else if (xbytes == 2)
+    hipLaunchKernelGGL(k_rademacher<_Float16>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
+                       nvalid, static_cast<_Float16*>(X), ld, col0);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -899,6 +917,9 @@ hipError_t launch_probes(hipStream_t st, int dist, uint64_t seed, int64_t n, int
   else if (xbytes == 4)
     hipLaunchKernelGGL(k_gaussian<float>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
                        nvalid, static_cast<float*>(X), ld, col0);
+  else if (xbytes == 2)
+    hipLaunchKernelGGL(k_gaussian<_Float16>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
+                       nvalid, static_cast<_Float16*>(X), ld, col0);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1009,6 +1030,13 @@ hipError_t launch_spmm_batch(hipStream_t st, SpmmItem* items, int count) {
       if (it.vt == VT_F32) return spmm_launch_typed<float, double>(st, it.g.C, it.nf, items, idx, cnt);
       return spmm_launch_typed<uint16_t, double>(st, it.g.C, it.nf, items, idx, cnt);
     }
+    if (it.g.xbytes == 2) {
+      if (it.vt == VT_F64)
+        return spmm_launch_typed<double, _Float16>(st, it.g.C, it.nf, items, idx, cnt);
+      if (it.vt == VT_F32)
+        return spmm_launch_typed<float, _Float16>(st, it.g.C, it.nf, items, idx, cnt);
+      return spmm_launch_typed<uint16_t, _Float16>(st, it.g.C, it.nf, items, idx, cnt);
+    }
     if (it.vt == VT_F64) return spmm_launch_typed<double, float>(st, it.g.C, it.nf, items, idx, cnt);
     if (it.vt == VT_F32) return spmm_launch_typed<float, float>(st, it.g.C, it.nf, items, idx, cnt);
     return spmm_launch_typed<uint16_t, float>(st, it.g.C, it.nf, items, idx, cnt);
@@ -1056,13 +1084,21 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
       hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL,
                          static_cast<const double*>(W), g.ld, g.ncolv, vs, nv, voff, part);
     });
-  } else {
+  } else if (g.xbytes == 4) {
     LD_DISPATCH_C(g.C, {
       auto fn = k_dots<float, CC>;
       const int nb = stream_grid(g, (const void*)fn);
       *nblk_out = nb;
       hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL,
                          static_cast<const float*>(W), g.ld, g.ncolv, vs, nv, voff, part);
+    });
+  } else {
+    LD_DISPATCH_C(g.C, {
+      auto fn = k_dots<_Float16, CC>;
+      const int nb = stream_grid(g, (const void*)fn);
+      *nblk_out = nb;
+      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL,
+                         static_cast<const _Float16*>(W), g.ld, g.ncolv, vs, nv, voff, part);
     });
   }
   return hipGetLastError();
@@ -1155,8 +1191,9 @@ hipError_t launch_update_batch(hipStream_t st, UpdateItem* items, int count) {
   };
   return launch_grouped(items, count, key, [&](const int* idx, int cnt) -> hipError_t {
     const UpdateItem& it = items[idx[0]];
-    return it.g.xbytes == 8 ? update_launch_typed<double>(st, it, items, idx, cnt)
-                            : update_launch_typed<float>(st, it, items, idx, cnt);
+    if (it.g.xbytes == 8) return update_launch_typed<double>(st, it, items, idx, cnt);
+    if (it.g.xbytes == 4) return update_launch_typed<float>(st, it, items, idx, cnt);
+    return update_launch_typed<_Float16>(st, it, items, idx, cnt);
   });
 }
 
@@ -1211,10 +1248,10 @@ hipError_t launch_reduce(hipStream_t st, const double* part, int nblk, int width
 
 hipError_t launch_start_finish(hipStream_t st, int B, int ld, const double* part, int nblk,
                                double* norm2, double* mult0, int* active, int* meff, double* g,
-                               int gstride) {
-  if (B < 1 || ld < B || !part || nblk < 1) return hipErrorInvalidValue;
+                               int gstride, double inv_oscale) {
+  if (B < 1 || ld < B || !part || nblk < 1 || !(inv_oscale > 0.0)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_start_finish, dim3((ld + 3) / 4), dim3(kThreads), 0, st, B, ld, part, nblk,
-                     norm2, mult0, active, meff, g, gstride);
+                     norm2, mult0, active, meff, g, gstride, inv_oscale);
   return hipGetLastError();
 }
 
@@ -1254,6 +1291,7 @@ hipError_t launch_step_finish_batch(hipStream_t st, const FinishItem* items, int
       d.nv = it.nv;
       d.nblk = it.nblk;
       d.sym_row = it.sym_row < 0 ? -1 : it.sym_row;
+      d.inv_s = it.inv_s;
       bt.off[q] = off;
       off += it.ld;
     }
@@ -1268,9 +1306,9 @@ hipError_t launch_step_finish_batch(hipStream_t st, const FinishItem* items, int
 hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, double* d, int j0,
                               int nv, const double* part, int nblk, double tol, double* H,
                               int* meff, int* active, double* mult_next, double* g, int* flags,
-                              int sym_row) {
-  const FinishItem it{B, ld, t, m, d, j0, nv, part, nblk, tol, H, meff, active, mult_next, g, flags,
-                      sym_row};
+                              int sym_row, double inv_s) {
+  const FinishItem it{B,     ld,   t,    m,      d,         j0, nv,    part,    nblk,
+                      tol,   H,    meff, active, mult_next, g,  flags, sym_row, inv_s};
   return launch_step_finish_batch(st, &it, 1);
 }
 

@@ -26,12 +26,13 @@ __device__ inline float bf16_to_float(uint16_t v) { return __uint_as_float(uint3
 template <typename T> struct Acc;
 template <> struct Acc<double> { using type = double; };
 template <> struct Acc<float> { using type = float; };
+template <> struct Acc<_Float16> { using type = float; };  // FP16 storage, FP32 sums
 
 template <typename VT, typename A> __device__ inline A value_as(VT v) { return A(v); }
 template <> __device__ inline float value_as<uint16_t, float>(uint16_t v) { return bf16_to_float(v); }
 template <> __device__ inline double value_as<uint16_t, double>(uint16_t v) { return double(bf16_to_float(v)); }
 
-// 16-byte vector access: 2 doubles or 4 floats per lane.
+// 16-byte vector access: 2 doubles, 4 floats or 8 FP16 values per lane.
 template <typename T> struct V16;
 template <> struct V16<double> {
   static constexpr int N = 2;
@@ -79,6 +80,36 @@ template <> struct V16<float> {
     typedef float f4 __attribute__((ext_vector_type(4)));
     const f4 t = {v[0], v[1], v[2], v[3]};
     __builtin_nontemporal_store(t, reinterpret_cast<f4*>(p));
+  }
+};
+
+template <> struct V16<_Float16> {
+  static constexpr int N = 8;
+  typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+  _Float16 v[8];
+  __device__ inline void load(const _Float16* p) {
+    const h8 t = *reinterpret_cast<const h8*>(p);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = t[e];
+  }
+  __device__ inline void store(_Float16* p) const {
+    h8 t;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = v[e];
+    *reinterpret_cast<h8*>(p) = t;
+  }
+  // streaming load: last use of the line
+  __device__ inline void load_nt(const _Float16* p) {
+    const h8 t = __builtin_nontemporal_load(reinterpret_cast<const h8*>(p));
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = t[e];
+  }
+  // streaming store: the line is not kept in the caches for reuse
+  __device__ inline void store_nt(_Float16* p) const {
+    h8 t;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = v[e];
+    __builtin_nontemporal_store(t, reinterpret_cast<h8*>(p));
   }
 };
 

@@ -102,6 +102,7 @@ struct FinDesc {
   double* g;
   int* flags;
   double tol;
+  double inv_s;  // 1 / the power-of-two scale the product output is stored at
   int B, ld, t, m, j0, nv, nblk, sym_row;
 };
 
@@ -191,6 +192,7 @@ struct FinishItem {
   double* g;
   int* flags;
   int sym_row;
+  double inv_s;
 };
 hipError_t launch_spmm_batch(hipStream_t st, SpmmItem* items, int count);
 hipError_t launch_update_batch(hipStream_t st, UpdateItem* items, int count);
@@ -202,16 +204,18 @@ hipError_t launch_reduce(hipStream_t st, const double* part, int nblk, int width
 
 // Per-probe bookkeeping (B real probes, ld columns), each fused with the
 // reduction of the partial sums it consumes (part in the transposed layout).
+// The start block is stored at the scale 1 / inv_oscale (its squared norms
+// are those of the unscaled vectors); the product output at 1 / inv_s.
 hipError_t launch_start_finish(hipStream_t st, int B, int ld, const double* part, int nblk,
                                double* norm2, double* mult0, int* active, int* meff, double* g,
-                               int gstride);
+                               int gstride, double inv_oscale);
 // With sym_row >= 0 it also reduces part[2] and stores, per probe, the inner
 // product of the new vector with the product it came from (sum / ||w||) in
 // d[sym_row][p], where the next step's window inner products are read.
 hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, double* d, int j0,
                               int nv, const double* part, int nblk, double tol, double* H,
                               int* meff, int* active, double* mult_next, double* g, int* flags,
-                              int sym_row);
+                              int sym_row, double inv_s);
 
 // Gauss quadrature of log on each probe's T (diag h_tt, subdiag h_t+1,t).
 // (need: when non-null, only runs with need[p] != 0 are evaluated.)
@@ -270,9 +274,11 @@ hipError_t launch_rows_mat(hipStream_t st, int64_t n, double* Y, int ld, int s, 
 hipError_t launch_subspace_eig(hipStream_t st, int q, int k, const double* G, double* U, int* flag);
 // X0[row][i] = A[row][i] (i < s); X0[row][s+j] = G[row][j] - sum_i A[row][i] P[i][j];
 // part[col][b] = sum over rows of b of X0[row][col]^2 (FP64 values).
+// X0 is stored at the scale oscale (a power of two); the norm partials are
+// those of the unscaled FP64 vectors.
 hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int lda, int s,
                           const double* Gm, int ldg, int r, const double* P, void* X0,
-                          double* part);
+                          double* part, double oscale);
 
 // Plain device copy of `bytes` (multiple of 16 used), calibration only.
 hipError_t launch_copy16(hipStream_t st, const void* src, void* dst, size_t bytes);

@@ -199,7 +199,8 @@ ld_status Run::validate() {
   if (p_.method != LD_METHOD_OSLQ && p_.method != LD_METHOD_OSA_IOP &&
       p_.method != LD_METHOD_SO_SLQ)
     return set_error(LD_E_INVALID_ARG, "unknown method");
-  if (p_.precision != LD_PREC_FP64 && p_.precision != LD_PREC_MIXED)
+  if (p_.precision != LD_PREC_FP64 && p_.precision != LD_PREC_MIXED &&
+      p_.precision != LD_PREC_HALF)
     return set_error(LD_E_INVALID_ARG, "unknown precision");
   if (p_.probe_dist != LD_PROBE_RADEMACHER && p_.probe_dist != LD_PROBE_GAUSSIAN)
     return set_error(LD_E_INVALID_ARG, "unknown probe distribution");
@@ -227,14 +228,17 @@ ld_status Run::validate() {
     return set_error(LD_E_INVALID_ARG, "krylov_steps must satisfy 1 <= m <= min(n, 512)");
   if (k_ < 1) return set_error(LD_E_INVALID_ARG, "iop_window must be >= 1");
   adapt_every_ = p_.adapt_every > 0 ? p_.adapt_every : 5;
-  mixed_ = p_.precision == LD_PREC_MIXED;
-  xb_ = mixed_ ? 4 : 8;
+  mixed_ = p_.precision != LD_PREC_FP64;
+  half_ = p_.precision == LD_PREC_HALF;
+  xb_ = half_ ? 2 : (mixed_ ? 4 : 8);
   if (std::max(B_, s_) > (mixed_ ? 256 : 128))
     return set_error(LD_E_INVALID_ARG, mixed_ ? "n_probes must be <= 256 in mixed precision"
                                               : "n_probes must be <= 128 in FP64");
-  lds_ = round4(std::max(s_, 1));
+  // Krylov blocks hold whole 16-byte chunks per row (8 FP16 values)
+  auto roundv = [&](int x) { return half_ ? (x + 7) / 8 * 8 : round4(x); };
+  lds_ = roundv(std::max(s_, 1));
   ldr_ = round4(r_);
-  ldB_ = round4(B_);
+  ldB_ = roundv(B_);
   ld1_ = lds_;
   ldx_ = std::max(ldB_, ld1_);
   lo_ = a_->lo;
@@ -255,6 +259,19 @@ ld_status Run::validate() {
     c_ = lo_ < 1.0 ? std::log(lo_) : std::log(scale_);
   }
   opscale_ = 1.0 / scale_;
+  vscale_ = 1.0;
+  oscale_ = 1.0;
+  if (half_) {
+    // FP16 Krylov vectors: the product output (and every vector derived from
+    // it) is stored at a power-of-two scale that puts the entries of a unit
+    // vector near 1 while |entries| <= vscale * ||operator|| stays far below
+    // the FP16 maximum; the start block likewise (its entries are at most a
+    // few units before scaling)
+    const double opnorm = hi_ * opscale_;
+    const double target = std::min(std::sqrt((double)n_), 4096.0 / opnorm);
+    vscale_ = std::ldexp(1.0, std::max(-20, std::min(14, (int)std::floor(std::log2(target)))));
+    oscale_ = std::ldexp(1.0, std::max(0, std::min(10, (int)std::floor(std::log2(std::sqrt((double)n_))))));
+  }
   gB_ = make_geom(n_, ldB_, xb_);
   gS_ = make_geom(n_, lds_, 8);
   g1_ = make_geom(n_, ld1_, xb_);
@@ -399,10 +416,10 @@ ld_status Run::start_block(hipStream_t st, const double* A, int s_cols) {
               launch_reduce(st, part_, gS_.nblk, s_cols * r_, pmat_));
   }
   LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * (s_cols + r_) * 8 + (double)n_ * ldB_ * xb_,
-            launch_project(st, gB_, A, lds_, s_cols, G_, ldr_, r_, pmat_, slots_, part_));
+            launch_project(st, gB_, A, lds_, s_cols, G_, ldr_, r_, pmat_, slots_, part_, oscale_));
   LD_LAUNCH(LD_PROF_SMALL, (double)gB_.nblk * ldB_ * 8,
             launch_start_finish(st, B_, ldB_, part_, gB_.nblk, norm2_, mult_, active_, meff_, gq_,
-                                m_ + 1));
+                                m_ + 1, 1.0 / oscale_));
   return LD_OK;
 }
 
@@ -477,7 +494,7 @@ ld_status Run::run_prologue(hipStream_t st) {
               launch_dots(st, g1_, slots_, vs, 1, 0, part_, &nb));
     LD_LAUNCH(LD_PROF_SMALL, (double)nb * ld1_ * 8,
               launch_start_finish(st, s_, ld1_, part_, nb, norm2_, mult_, active_, meff_, nullptr,
-                                  0));
+                                  0, 1.0));
     LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldx_ * (m_ + 1) * m_ * 8, st));
     begin_krylov(0);
     return LD_OK;
@@ -577,7 +594,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
       sp.X = slot_ptr(t);
       sp.W = W;
       sp.xmult = mult_ptr(t);
-      sp.opscale = opscale_;
+      sp.opscale = opscale_ * vscale_;
       sp.fused = vf;
       sp.nf = nf;
       sp.voff = 0;
@@ -601,15 +618,15 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
       up.part = part_;
       plan->fin = FinishItem{kB_, kld_, t, m_, dwin_, j0, nv, part_, 0, tol_, H_, meff_, active_,
                              mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_,
-                             sym_out ? nv_next - 2 : -1};
+                             sym_out ? nv_next - 2 : -1, 1.0 / vscale_};
       sym_ready_ = sym_out;
       return LD_OK;
     }
   }
   int nb = 0;
   LD_LAUNCH(LD_PROF_SPMM, spmm_bytes(kld_, xb_) + (nf - 1) * vec_bytes,
-            launch_spmm(st, kg_, a_->rp, a_->ci, vals, vt, slot_ptr(t), W, mult_ptr(t), opscale_,
-                        &vf, nf, 0, part_, &nb));
+            launch_spmm(st, kg_, a_->rp, a_->ci, vals, vt, slot_ptr(t), W, mult_ptr(t),
+                        opscale_ * vscale_, &vf, nf, 0, part_, &nb));
   LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nf * kld_ * 8,
             launch_reduce(st, part_, nb, nf * kld_, dwin_ + (size_t)(nv - nf) * kld_));
   for (int c0 = 0; c0 < nold; c0 += 4) {
@@ -642,7 +659,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
   LD_LAUNCH(LD_PROF_SMALL, (double)nb * 2 * kld_ * 8,
             launch_step_finish(st, kB_, kld_, t, m_, dwin_, j0, nv, part_, nb, tol_, H_,
                                meff_, active_, mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_,
-                               sym_out ? nv_next - 2 : -1));
+                               sym_out ? nv_next - 2 : -1, 1.0 / vscale_));
   if (check) {
     // adaptive Krylov dimension: runs whose quadrature value settled stop;
     // the count of runs still going comes back to the host for the early exit
@@ -991,7 +1008,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
         int nb = 0;
         float ms = 0.f;
         auto product = [&]() {
-          return launch_spmm(st, g, a_->rp, a_->ci, vals, vt, X, W, mult, opscale_, &vf, 1, 0,
+          return launch_spmm(st, g, a_->rp, a_->ci, vals, vt, X, W, mult, opscale_ * vscale_, &vf, 1, 0,
                              part, &nb);
         };
         auto update = [&]() {
@@ -1080,7 +1097,8 @@ ld_status ld_ctx_create(const ld_ctx_opts* opts, ld_ctx** out) {
   if (o.default_method != LD_METHOD_OSLQ && o.default_method != LD_METHOD_OSA_IOP &&
       o.default_method != LD_METHOD_SO_SLQ)
     return set_error(LD_E_INVALID_ARG, "bad default_method");
-  if (o.default_precision != LD_PREC_FP64 && o.default_precision != LD_PREC_MIXED)
+  if (o.default_precision != LD_PREC_FP64 && o.default_precision != LD_PREC_MIXED &&
+      o.default_precision != LD_PREC_HALF)
     return set_error(LD_E_INVALID_ARG, "bad default_precision");
   LD_HIP_API(hipSetDevice(o.device));
   std::unique_ptr<ld_ctx> c(new ld_ctx());

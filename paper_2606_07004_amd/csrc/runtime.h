@@ -161,7 +161,10 @@ class Run {
   int adapt_every_ = 5;
   double tol_ = 1e-10;
   double lo_ = 0, hi_ = 0, scale_ = 1, c_ = 0, opscale_ = 1;
-  bool mixed_ = false;
+  bool mixed_ = false;        // Krylov vectors narrower than FP64 (FP32 or FP16)
+  bool half_ = false;         // FP16 Krylov vectors
+  double vscale_ = 1.0;       // power-of-two scale of the stored product output
+  double oscale_ = 1.0;       // power-of-two scale of the stored start block
   int xb_ = 8;                // bytes per Krylov element
   int lds_ = 0, ldr_ = 0, ldB_ = 0, ld1_ = 0, ldx_ = 0;
   Geom gB_, gS_, g1_;

@@ -6,7 +6,7 @@ inputs; each file records the input's content digest, checked here before
 comparing.  At these sizes the oracle takes minutes, so the comparison is
 against the stored per-run values: every run's quadrature value, start norm
 and Krylov dimension, then the assembled log-determinant (FP64 <= 1e-6,
-mixed precision <= 1e-4).
+FP32 or FP16 Krylov vectors <= 1e-4).
 """
 import json
 import os
@@ -88,6 +88,14 @@ def test_fullsize_fp64_elementwise(L, ctx, name):
 def test_fullsize_mixed_within_1e4(L, ctx, name):
     gold, res, det, rel = _run(L, ctx, name, L.LD_PREC_MIXED, L.LD_VT_FP32)
     assert rel <= 1e-4
+
+
+@pytest.mark.parametrize("name", ALL_CASES)
+def test_fullsize_half_within_1e4(L, ctx, name):
+    # FP16 Krylov vectors, FP32 values
+    gold, res, det, rel = _run(L, ctx, name, L.LD_PREC_HALF, L.LD_VT_FP32)
+    assert rel <= 1e-4
+    np.testing.assert_allclose(det["probe_norm2"], gold["probe_norm2"], rtol=1e-10)
 
 
 def test_fullsize_bf16_values_reported(L, ctx):
