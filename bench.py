@@ -41,8 +41,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--method", choices=("oslq", "osa_iop"), default="oslq")
-    ap.add_argument("--precision", choices=("mixed", "half", "fp64"), default="mixed",
-                    help="Krylov vectors in FP32 (mixed), FP16 (half) or FP64")
+    ap.add_argument("--precision", choices=("mixed", "half", "fp64"), default="half",
+                    help="Krylov vectors in FP16 (half), FP32 (mixed) or FP64")
+    ap.add_argument("--serve-precision", choices=("mixed", "half"), default="mixed",
+                    help="Krylov vectors of the served requests")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip timing the other precisions on the headline workload")
     ap.add_argument("--values", choices=("fp32", "bf16"), default="fp32")
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--shift", type=float, default=1e-2)
@@ -109,7 +113,7 @@ def pmc_traffic(args, family, tune):
         return None
     return {"bytes_per_launch": k["scaled_bytes"], "kernel": kname,
             "fetch_scale": rec["fetch_scale"], "write_scale": rec["write_scale"],
-            "summary": "profiles/oslq_mixed_lap3d128_pmc_traffic.md"}
+            "summary": "profiles/oslq_half_lap3d128_pmc_traffic.md"}
 
 
 def golden_for(matrix_name, args):
@@ -226,10 +230,37 @@ def grf_bench(L, W, args):
     return out
 
 
+def precision_variants(L, ctx, h, args, ref):
+    """The headline workload with the Krylov vectors in the other precisions
+    (FP32 and FP64 beside FP16): probe-steps/s over a few blocking estimates
+    after a tuning pass, and the distance of each from the FP64 result."""
+    out = {}
+    for name in ("half", "mixed", "fp64"):
+        if name == args.precision:
+            continue
+        p = L.make_params(args.probes, args.sketch, args.krylov_steps, args.window, args.seed,
+                          method=L.LD_METHOD_OSLQ if args.method == "oslq" else L.LD_METHOD_OSA_IOP,
+                          precision=PRECISIONS[name](L))
+        if args.tune_reps > 0:
+            L.ld_autotune(h, p, args.tune_reps)
+        r = L.ld_estimate_ex(h, p)
+        reps = max(1, min(args.steps, 5))
+        steps = 0
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            steps += L.ld_estimate_ex(h, p).probe_steps
+        dt = time.perf_counter() - t0
+        out[name] = {"probe_steps_per_s": steps / dt, "ms_per_estimate": dt * 1e3 / reps,
+                     "logdet": r.logdet,
+                     "rel_err_vs_fp64_gpu": abs(r.logdet - ref) / abs(ref) if ref else None}
+        print(f"[bench] variant {name} {out[name]}", file=sys.stderr, flush=True)
+    return out
+
+
 def serving_bench(L, W, args):
     """Served log-determinants (the serving workload): requests of uneven n,
     kind and Krylov depth.  Baseline: plain FP64 estimates one at a time.
-    Served: mixed precision through ld_submit with continuous batching,
+    Served: FP32 or FP16 Krylov vectors through ld_submit with continuous batching,
     (i) all requests at t = 0 (throughput), (ii) Poisson arrivals at 0.7x the
     FP64 sequential rate (latency).  Every served result is checked against
     its own FP64 result."""
@@ -262,12 +293,13 @@ def serving_bench(L, W, args):
               flush=True)
         # (i) saturation: everything submitted at once
         t0 = time.perf_counter()
-        tickets = [L.ld_submit(h, params(r, L.LD_PREC_MIXED)) for h, r in zip(hs, reqs)]
+        sprec = PRECISIONS[args.serve_precision](L)
+        tickets = [L.ld_submit(h, params(r, sprec)) for h, r in zip(hs, reqs)]
         served = [L.ld_wait(ctx.handle, t) for t in tickets]
         t_sat = time.perf_counter() - t0
         sat_rate = len(reqs) / t_sat
         errs = [abs(sv.logdet - rf) / abs(rf) for sv, rf in zip(served, ref)]
-        print(f"[bench] serving: mixed served {sat_rate:.1f} logdets/s, max rel err "
+        print(f"[bench] serving: {args.serve_precision} served {sat_rate:.1f} logdets/s, max rel err "
               f"{max(errs):.2e}", file=sys.stderr, flush=True)
         # (ii) Poisson arrivals at 0.7x the FP64 sequential rate
         rate = 0.7 * seq_rate
@@ -280,7 +312,7 @@ def serving_bench(L, W, args):
         while i < len(reqs) or pending:
             now = time.perf_counter() - start
             while i < len(reqs) and arrivals[i] <= now:
-                pending[L.ld_submit(hs[i], params(reqs[i], L.LD_PREC_MIXED))] = i
+                pending[L.ld_submit(hs[i], params(reqs[i], sprec))] = i
                 i += 1
             for t in list(pending):
                 res = L.ld_poll(ctx.handle, t)
@@ -291,7 +323,8 @@ def serving_bench(L, W, args):
         lat = np.array(lat)
         out = {"requests": len(reqs), "n_range": [1e4, args.serve_nmax],
                "fp64_sequential_logdets_per_s": seq_rate,
-               "mixed_served_logdets_per_s": sat_rate,
+               "served_precision": args.serve_precision,
+               "served_logdets_per_s": sat_rate,
                "speedup_vs_fp64_sequential": sat_rate / seq_rate,
                "max_rel_err_vs_fp64": max(errs),
                "poisson_rate_hz": rate,
@@ -394,6 +427,10 @@ def main():
                     "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
                 for k, v in fam.items()}
 
+    variants = None
+    if not args.no_variants:
+        variants = precision_variants(L, ctx, h, args, accuracy.get("logdet_fp64_gpu"))
+
     copy = None
     if args.copy_bytes > 0:
         nb = int(args.copy_bytes) // 16 * 16
@@ -439,7 +476,12 @@ def main():
                                f"(sketch {args.sketch} + {args.probes - args.sketch}), "
                                f"{args.krylov_steps} Krylov steps, window {args.window}, "
                                f"seed {args.seed}",
-                   "precision": args.precision, "values": vt, "parallelism": "single GPU",
+                   "precision": {"half": "FP16 Krylov vectors, FP32 product sums, FP64 inner "
+                                         "products, norms and small matrices",
+                                 "mixed": "FP32 Krylov vectors, FP64 inner products, norms and "
+                                          "small matrices",
+                                 "fp64": "FP64 throughout"}[args.precision],
+                   "values": {0: "fp64", 1: "fp32", 2: "bf16"}[vt], "parallelism": "single GPU",
                    "geometry": ({"product": [tune["spmm_lanes"], tune["spmm_chunks"]],
                                  "update": [tune["update_lanes"], tune["update_chunks"]]}
                                 if tune else "default")},
@@ -450,6 +492,7 @@ def main():
         "kernel_families": families,
         "serving": serving,
         "comparators": comparators,
+        "precision_variants": variants,
         "grf_sweep": grf_sweep,
         "copy_kernel": copy,
         "device_ms_per_step": device_ms_total / args.steps,
