@@ -209,7 +209,11 @@ class Run {
   int* meff0_ = nullptr;      // OSA-IOP: Krylov dimensions of the sketch-image runs
   // asymmetry of H accepted by the symmetric fast path of log(H) e1: rounding
   // level of the vectors' precision
-  double symtol() const { return mixed_ ? 1e-5 : 1e-12; }
+  // relative asymmetry of H below which log(H) e1 takes the symmetric
+  // tridiagonal path: rounding level of the Krylov vectors' storage (FP16
+  // entries carry 2^-11 relative rounding, which reaches the two estimates of
+  // each off-diagonal entry differently)
+  double symtol() const { return half_ ? 1e-3 : (mixed_ ? 1e-5 : 1e-12); }
   // spectral interval of the Gauss-quadrature runs' operator (Q / scale)
   double quad_a() const { return lo_ / scale_; }
   double quad_b() const { return hi_ / scale_; }
