@@ -82,7 +82,10 @@ typedef enum { LD_PROBE_RADEMACHER = 0, LD_PROBE_GAUSSIAN = 1 } ld_probe_dist;
  * vectors near 1 and below the FP16 range limit; the scale is removed
  * exactly from every inner product and norm.  Half the vector traffic of
  * LD_PREC_MIXED; the extra rounding (2^-11 per stored entry) enters the
- * estimate through averages over n entries and many probes. */
+ * estimate through averages over n entries and many probes.  Windows up to
+ * iop_window = 4 (LD_E_INVALID_ARG beyond: classical Gram-Schmidt over a
+ * longer window of FP16-rounded vectors can lose stability and make the
+ * tridiagonal T indefinite). */
 typedef enum { LD_PREC_FP64 = 0, LD_PREC_MIXED = 1, LD_PREC_HALF = 2 } ld_precision;
 
 typedef struct ld_ctx ld_ctx;

@@ -234,6 +234,10 @@ ld_status Run::validate() {
   if (std::max(B_, s_) > (mixed_ ? 256 : 128))
     return set_error(LD_E_INVALID_ARG, mixed_ ? "n_probes must be <= 256 in mixed precision"
                                               : "n_probes must be <= 128 in FP64");
+  if (half_ && k_ > 4)
+    return set_error(LD_E_INVALID_ARG,
+                     "FP16 Krylov vectors take iop_window <= 4: with more window vectors the "
+                     "classical Gram-Schmidt step on FP16-rounded vectors loses stability");
   // Krylov blocks hold whole 16-byte chunks per row (8 FP16 values)
   auto roundv = [&](int x) { return half_ ? (x + 7) / 8 * 8 : round4(x); };
   lds_ = roundv(std::max(s_, 1));

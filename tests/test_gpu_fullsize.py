@@ -90,9 +90,12 @@ def test_fullsize_mixed_within_1e4(L, ctx, name):
     assert rel <= 1e-4
 
 
-@pytest.mark.parametrize("name", ALL_CASES)
+HALF_CASES = [n for n in BUILDERS if _load(n)["iop_window"] <= 4]
+
+
+@pytest.mark.parametrize("name", HALF_CASES)
 def test_fullsize_half_within_1e4(L, ctx, name):
-    # FP16 Krylov vectors, FP32 values
+    # FP16 Krylov vectors, FP32 values (windows up to 4 vectors)
     gold, res, det, rel = _run(L, ctx, name, L.LD_PREC_HALF, L.LD_VT_FP32)
     assert rel <= 1e-4
     np.testing.assert_allclose(det["probe_norm2"], gold["probe_norm2"], rtol=1e-10)
