@@ -521,6 +521,8 @@ __device__ inline double wave_sum_fixed(double s) {
 
 __device__ inline double row_sum(const double* __restrict__ p, int nblk, int lane) {
   double s = 0.0;
+  // unrolled so that the loads are in flight together; the sum keeps its order
+#pragma unroll 8
   for (int b = lane; b < nblk; b += 64) s += p[b];
   return wave_sum_fixed(s);
 }
