@@ -189,6 +189,8 @@ __device__ inline void spmm_body(int64_t n, int lgL, const int* __restrict__ rp,
   // registers, with the LDS array used for the final column sums
   constexpr bool LDSACC = NF == 1;
   constexpr int ND = (FUSED && !LDSACC) ? NF : 1;
+  // sparse entries whose (column, value) a lane loads per round
+  constexpr int KE = C >= 3 ? 2 : 4;
   __shared__ double red[FUSED ? kThreads * VEC * C : 1];
   __shared__ A scs[kMaxLd];  // opscale * xmult[col], in the accumulation type
   const RowMap rm(lgL);
@@ -262,22 +264,32 @@ __device__ inline void spmm_body(int64_t n, int lgL, const int* __restrict__ rp,
     };
     const int kbeg = rp[row];
     const int kend = rp[row + 1];
-    // the row's L lanes load L consecutive entries (column, value) once and
-    // pass them around the group by lane shuffles
-    for (int base = kbeg; base < kend; base += rm.L) {
-      const int kk = base + rm.gl;
-      int myc = row;
-      A mya = A(0);
-      if (kk < kend) {
-        myc = ci[kk];
-        mya = value_as<VT, A>(va[kk]);
+    // the row's L lanes load KE * L consecutive entries (column, value) per
+    // round, lane l holding entries l, l + L, ..., and pass them around the
+    // group by lane shuffles; entries are accumulated in order
+    for (int base = kbeg; base < kend; base += rm.L * KE) {
+      int myc[KE];
+      A mya[KE];
+#pragma unroll
+      for (int u = 0; u < KE; ++u) {
+        const int kk = base + rm.gl + rm.L * u;
+        myc[u] = row;
+        mya[u] = A(0);
+        if (kk < kend) {
+          myc[u] = ci[kk];
+          mya[u] = value_as<VT, A>(va[kk]);
+        }
       }
-      const int cnt = min(rm.L, kend - base);
-      int j = 0;
-      for (; j + 2 <= cnt; j += 2)
-        step2(__shfl(myc, j, rm.L), __shfl(mya, j, rm.L), __shfl(myc, j + 1, rm.L),
-              __shfl(mya, j + 1, rm.L));
-      if (j < cnt) step1(__shfl(myc, j, rm.L), __shfl(mya, j, rm.L));
+#pragma unroll
+      for (int u = 0; u < KE; ++u) {
+        const int cnt = min(rm.L, kend - base - rm.L * u);
+        if (cnt <= 0) break;
+        int j = 0;
+        for (; j + 2 <= cnt; j += 2)
+          step2(__shfl(myc[u], j, rm.L), __shfl(mya[u], j, rm.L), __shfl(myc[u], j + 1, rm.L),
+                __shfl(mya[u], j + 1, rm.L));
+        if (j < cnt) step1(__shfl(myc[u], j, rm.L), __shfl(mya[u], j, rm.L));
+      }
     }
 #pragma unroll
     for (int c = 0; c < C; ++c)
