@@ -212,8 +212,11 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
  * and the orthogonalisation update with its fused norms).  Both sweep the
  * probe block row by row with L lanes per row (a power of two <= 64), each
  * lane holding C 16-byte chunks of the row (1 <= C <= 4, L * C chunks
- * covering the block).  ld_autotune times every such (L, C) with at most half
- * a row of idle chunks on this matrix, for the probe-block shapes and
+ * covering the block).  The product may also split a row's sparse entries
+ * over E = 1, 2, 4 or 8 lane groups (L / E column lanes each, their sums
+ * added at the row's end), which shortens the per-lane chain of dependent
+ * gathers on long rows.  ld_autotune times every such (L, C, E) with at most
+ * half a row of idle chunks on this matrix, for the probe-block shapes and
  * precision that `p` implies (the estimate block and, for OSA-IOP and So-SLQ,
  * the sketch-run block), each kernel `reps` times per round over three
  * rounds, keeping the fastest per kernel.  The choice is stored in the
@@ -231,17 +234,19 @@ typedef struct {
   int32_t update_lanes, update_chunks;
   double spmm_ms, spmm_default_ms;
   double update_ms, update_default_ms;
-  int32_t candidates;        /* (L, C) pairs timed per kernel                  */
-  int32_t reserved;
+  int32_t candidates;        /* geometries timed for the product               */
+  int32_t spmm_entry_split;  /* sparse-entry groups per row of the product     */
 } ld_tune_result;
 ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_result* out);
 /* Stores a given geometry for the estimate block of `p` on this matrix (a
  * choice found earlier, or one to test): the product with spmm_lanes lanes
- * per row and spmm_chunks chunks per lane, the update likewise.  Any (L, C)
- * with L a power of two <= 64, 1 <= C <= 4 and L * C chunks covering the
- * block is accepted; anything else is LD_E_INVALID_ARG and stores nothing. */
+ * per row, spmm_chunks chunks per lane and its entries split over
+ * spmm_entry_split lane groups, the update likewise (no split).  Any
+ * (L, C, E) with L a power of two <= 64, 1 <= C <= 4, E in {1, 2, 4, 8},
+ * E <= L, C <= 2 when E > 1, and (L / E) * C chunks covering the block is
+ * accepted; anything else is LD_E_INVALID_ARG and stores nothing. */
 ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
-                      int32_t update_lanes, int32_t update_chunks);
+                      int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks);
 
 /* Serving with continuous batching: queue a request and return at once with
  * a ticket.  Requests are admitted as resident slots and HBM budget free up;

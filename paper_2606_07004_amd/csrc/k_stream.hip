@@ -109,11 +109,17 @@ __global__ __launch_bounds__(kThreads) void k_gaussian(uint64_t seed, int64_t n,
 // lanes (96 FP32 probes: L = 8, C = 3).  Per-block partial sums are stored
 // transposed, part[i][block], so the reduction reads contiguous memory.
 // ---------------------------------------------------------------------------
+// With an entry split ES = 2^lgES (the product only) the L lanes of a row
+// form ES groups of Lc = L / ES column lanes; group eg takes every ES-th
+// sparse entry of the row and the groups' sums are added at the row's end.
 struct RowMap {
-  int lg, L, rpi, rg, gl;
-  __device__ RowMap(int lgL) : lg(lgL), L(1 << lgL), rpi(kThreads >> lgL) {
+  int lg, L, rpi, rg, gl, Lc, cl, eg;
+  __device__ RowMap(int lgL, int lgES = 0) : lg(lgL), L(1 << lgL), rpi(kThreads >> lgL) {
     rg = (int)threadIdx.x >> lg;
     gl = (int)threadIdx.x & (L - 1);
+    Lc = L >> lgES;
+    cl = gl & (Lc - 1);
+    eg = lgES ? gl >> (lgL - lgES) : 0;
   }
 };
 
@@ -132,7 +138,7 @@ __device__ inline int chunk_of(int j, int b, int nb) {
 template <int C, int VEC>
 __device__ inline void red_partials(const double* red, const RowMap& rm, int ld, const double* mult,
                                     double* part, size_t row0, int bk, int nbk) {
-  const int WC = rm.L * C * VEC;
+  const int WC = rm.Lc * C * VEC;
   for (int i = threadIdx.x; i < WC; i += kThreads) {
     double sum = 0.0;
     for (int q = 0; q < rm.rpi; ++q) sum += red[q * WC + i];
@@ -141,10 +147,11 @@ __device__ inline void red_partials(const double* red, const RowMap& rm, int ld,
   __syncthreads();
 }
 
-// Slot of thread (rg, gl) for chunk c, element e in a [rpi][C*L*VEC] array.
+// Slot of thread (rg, cl) for chunk c, element e in a [rpi][C*Lc*VEC] array
+// (the slot index within a row group is the column).
 template <int C, int VEC>
 __device__ inline int red_slot(const RowMap& rm, int c, int e) {
-  return rm.rg * (rm.L * C * VEC) + (c * rm.L + rm.gl) * VEC + e;
+  return rm.rg * (rm.Lc * C * VEC) + (c * rm.Lc + rm.cl) * VEC + e;
 }
 
 // Sum the per-lane accumulators of one vector over the row groups of the
@@ -153,10 +160,12 @@ template <int C, int VEC>
 __device__ inline void block_partials(const double (&acc)[C][VEC], double* red, const RowMap& rm,
                                       int ld, const double* mult, double* part, size_t row0, int bk,
                                       int nbk) {
+  if (rm.eg == 0) {
 #pragma unroll
-  for (int c = 0; c < C; ++c)
+    for (int c = 0; c < C; ++c)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) red[red_slot<C, VEC>(rm, c, e)] = acc[c][e];
+      for (int e = 0; e < VEC; ++e) red[red_slot<C, VEC>(rm, c, e)] = acc[c][e];
+  }
   __syncthreads();
   red_partials<C, VEC>(red, rm, ld, mult, part, row0, bk, nbk);
 }
@@ -171,8 +180,8 @@ __device__ inline void block_partials(const double (&acc)[C][VEC], double* red, 
 // segments of the neighbour's probe vector.  For v < NF:
 // part[voff+v][col][block] = mult_v[col] * sum_rows x_v[row][col] w[row][col].
 // ---------------------------------------------------------------------------
-template <typename VT, typename XT, int C, int NF>
-__device__ inline void spmm_body(int64_t n, int lgL, const int* __restrict__ rp,
+template <typename VT, typename XT, int C, int NF, bool SPLIT>
+__device__ inline void spmm_body(int64_t n, int lgL, int lgES_arg, const int* __restrict__ rp,
                                  const int* __restrict__ ci, const VT* __restrict__ va,
                                  const XT* __restrict__ X, XT* __restrict__ W, int ld, int ncolv,
                                  const double* __restrict__ xmult, double opscale, const void* const* fx,
@@ -193,14 +202,18 @@ __device__ inline void spmm_body(int64_t n, int lgL, const int* __restrict__ rp,
   constexpr int KE = C >= 3 ? 2 : 4;
   __shared__ double red[FUSED ? kThreads * VEC * C : 1];
   __shared__ A scs[kMaxLd];  // opscale * xmult[col], in the accumulation type
-  const RowMap rm(lgL);
+  // entry split only in the SPLIT instantiations (the plain path keeps its
+  // registers and code)
+  const int lgES = SPLIT ? lgES_arg : 0;
+  const RowMap rm(lgL, lgES);
+  const int ES = 1 << lgES;
   for (int i = threadIdx.x; i < ld; i += kThreads)
     scs[i] = A(opscale * (xmult ? xmult[i] : 1.0));
   bool okc[C];
   int colc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const int cv = rm.gl + rm.L * c;
+    const int cv = rm.cl + rm.Lc * c;
     okc[c] = cv < ncolv;
     colc[c] = cv * VEC;
     if constexpr (LDSACC) {
@@ -284,16 +297,50 @@ __device__ inline void spmm_body(int64_t n, int lgL, const int* __restrict__ rp,
       for (int u = 0; u < KE; ++u) {
         const int cnt = min(rm.L, kend - base - rm.L * u);
         if (cnt <= 0) break;
-        int j = 0;
-        for (; j + 2 <= cnt; j += 2)
-          step2(__shfl(myc[u], j, rm.L), __shfl(mya[u], j, rm.L), __shfl(myc[u], j + 1, rm.L),
-                __shfl(mya[u], j + 1, rm.L));
-        if (j < cnt) step1(__shfl(myc[u], j, rm.L), __shfl(mya[u], j, rm.L));
+        if (ES == 1) {
+          int j = 0;
+          for (; j + 2 <= cnt; j += 2)
+            step2(__shfl(myc[u], j, rm.L), __shfl(mya[u], j, rm.L), __shfl(myc[u], j + 1, rm.L),
+                  __shfl(mya[u], j + 1, rm.L));
+          if (j < cnt) step1(__shfl(myc[u], j, rm.L), __shfl(mya[u], j, rm.L));
+        } else {
+          // entry group eg: entries eg, eg + ES, ... of the round (absent
+          // ones gather the row itself with a zero coefficient)
+          const int ni = (cnt + ES - 1) >> lgES;
+          for (int i = 0; i < ni; i += 2) {
+            const int e0 = rm.eg + (i << lgES), e1 = e0 + ES;
+            int c0 = __shfl(myc[u], e0, rm.L), c1 = __shfl(myc[u], e1, rm.L);
+            A a0 = __shfl(mya[u], e0, rm.L), a1 = __shfl(mya[u], e1, rm.L);
+            if (e0 >= cnt) {
+              c0 = row;
+              a0 = A(0);
+            }
+            if (i + 1 >= ni || e1 >= cnt) {
+              c1 = row;
+              a1 = A(0);
+            }
+            step2(c0, a0, c1, a1);
+          }
+        }
+      }
+    }
+    if (ES > 1) {
+      // add the entry groups' sums (a fixed butterfly: every lane of the row
+      // ends with the same total); the diagonal block row is read again
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          for (int d = rm.Lc; d < rm.L; d <<= 1) acc[c][e] += __shfl_xor(acc[c][e], d, 64);
+      if (FUSED) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          if (okc[c]) xd[c].load(X + (size_t)row * ld + colc[c]);
       }
     }
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      if (okc[c]) {
+      if (okc[c] && rm.eg == 0) {
         V16<XT> out;
         const A* sce = scs + colc[c];
 #pragma unroll
@@ -333,13 +380,13 @@ __device__ inline void spmm_body(int64_t n, int lgL, const int* __restrict__ rp,
 
 // One CSR x block product per batch entry: blocks off[r] .. off[r+1]-1 of
 // the grid belong to request r (a single product is a batch of one).
-template <typename VT, typename XT, int C, int NF>
+template <typename VT, typename XT, int C, int NF, bool SPLIT>
 __global__ __launch_bounds__(kThreads, (NF == 2 || (sizeof(VT) == 8 && sizeof(XT) < 8)) ? 4 : 6) void k_spmm(
     BatchArgs<SpmmDesc> bt) {
   int r = 0;
   while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
   const SpmmDesc& q = bt.d[r];
-  spmm_body<VT, XT, C, NF>(q.n, q.lgL, q.rp, q.ci, static_cast<const VT*>(q.va),
+  spmm_body<VT, XT, C, NF, SPLIT>(q.n, q.lgL, q.lgES, q.rp, q.ci, static_cast<const VT*>(q.va),
                            static_cast<const XT*>(q.X), static_cast<XT*>(q.W), q.ld, q.ncolv, q.xmult,
                            q.opscale, q.fx, q.fmult, q.voff, q.part, (int)blockIdx.x - bt.off[r],
                            bt.off[r + 1] - bt.off[r]);
@@ -811,13 +858,14 @@ Geom make_geom(int64_t n, int ld, int xbytes) {
   if (xbytes == 2 && pow2_at_least(g.ncolv) <= 64)
     return make_geom_lc(n, ld, xbytes, pow2_at_least(g.ncolv), 1);
   // lanes per row L (power of two <= 64) and 16-byte chunks per lane C <= 4:
-  // least idle lanes, then C closest to 2
+  // least idle lanes, then the fewest chunks per lane (more rows of lanes in
+  // flight, fewer registers)
   int bestL = 64, bestC = 1, bestWaste = 1 << 30, bestPref = 1 << 30;
   for (int C = 1; C <= kMaxC; ++C) {
     const int L = pow2_at_least((g.ncolv + C - 1) / C);
     if (L > 64) continue;
     const int waste = L * C - g.ncolv;
-    const int pref = C > 2 ? C - 2 : 2 - C;
+    const int pref = C;
     if (waste < bestWaste || (waste == bestWaste && pref < bestPref)) {
       bestL = L;
       bestC = C;
@@ -855,7 +903,9 @@ bool geom_usable(const Geom& g) { return geom_ok(g); }
 static bool geom_ok(const Geom& g) {
   return g.n > 0 && g.ld > 0 && g.ld % 4 == 0 && (g.xbytes == 8 || g.xbytes == 4 || g.xbytes == 2) &&
          g.vec * g.ncolv == g.ld && g.L >= 1 && g.L <= 64 && (1 << g.lgL) == g.L && g.C >= 1 &&
-         g.C <= kMaxC && g.L * g.C >= g.ncolv && g.nblk >= 1 && (int64_t)g.nblk * g.rpb >= g.n;
+         g.C <= kMaxC && g.lges >= 0 && g.lges <= g.lgL && g.lges <= 3 &&
+         (g.lges == 0 || g.C <= 2) &&
+         (g.L >> g.lges) * g.C >= g.ncolv && g.nblk >= 1 && (int64_t)g.nblk * g.rpb >= g.n;
 }
 
 // Resident 256-thread blocks of a kernel on the whole device (cached).
@@ -978,9 +1028,9 @@ static bool spmm_item_ok(const SpmmItem& it) {
   return true;
 }
 
-template <typename VT, typename XT, int C, int NF>
+template <typename VT, typename XT, int C, int NF, bool SPLIT>
 static hipError_t spmm_launch(hipStream_t st, SpmmItem* items, const int* idx, int cnt) {
-  auto fn = k_spmm<VT, XT, C, NF>;
+  auto fn = k_spmm<VT, XT, C, NF, SPLIT>;
   BatchArgs<SpmmDesc> bt{};
   bt.count = cnt;
   int off = 0;
@@ -1003,6 +1053,7 @@ static hipError_t spmm_launch(hipStream_t st, SpmmItem* items, const int* idx, i
     }
     d.part = it.part;
     d.lgL = it.g.lgL;
+    d.lgES = it.g.lges;
     d.ld = it.g.ld;
     d.ncolv = it.g.ncolv;
     d.voff = it.voff;
@@ -1017,7 +1068,13 @@ static hipError_t spmm_launch(hipStream_t st, SpmmItem* items, const int* idx, i
 template <typename VT, typename XT, int NF>
 static hipError_t spmm_launch_c(hipStream_t st, int C, SpmmItem* items, const int* idx, int cnt) {
   hipError_t e = hipErrorInvalidValue;
-  LD_DISPATCH_C(C, { e = spmm_launch<VT, XT, CC, NF>(st, items, idx, cnt); });
+  if (items[idx[0]].g.lges > 0) {
+    // entry-split instantiations: one or two chunks per lane
+    if (C == 1) return spmm_launch<VT, XT, 1, NF, true>(st, items, idx, cnt);
+    if (C == 2) return spmm_launch<VT, XT, 2, NF, true>(st, items, idx, cnt);
+    return hipErrorInvalidValue;
+  }
+  LD_DISPATCH_C(C, { e = spmm_launch<VT, XT, CC, NF, false>(st, items, idx, cnt); });
   return e;
 }
 
@@ -1035,7 +1092,7 @@ hipError_t launch_spmm_batch(hipStream_t st, SpmmItem* items, int count) {
     if (!spmm_item_ok(items[a])) return hipErrorInvalidValue;
   auto key = [](const SpmmItem& it) -> uint64_t {
     return (uint64_t)it.g.xbytes | ((uint64_t)it.vt << 8) | ((uint64_t)it.g.C << 16) |
-           ((uint64_t)it.nf << 24);
+           ((uint64_t)it.nf << 24) | ((uint64_t)(it.g.lges > 0) << 32);
   };
   return launch_grouped(items, count, key, [&](const int* idx, int cnt) -> hipError_t {
     const SpmmItem& it = items[idx[0]];
@@ -1086,7 +1143,7 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
                        int voff, double* part, int* nblk_out) {
   int dummy = 0;
   if (!nblk_out) nblk_out = &dummy;
-  if (!geom_ok(g) || !W || !part || nv < 1 || nv > kDotsPerLaunch || voff < 0)
+  if (!geom_ok(g) || g.lges != 0 || !W || !part || nv < 1 || nv > kDotsPerLaunch || voff < 0)
     return hipErrorInvalidValue;
   for (int v = 0; v < nv; ++v)
     if (!vs.x[v]) return hipErrorInvalidValue;
@@ -1120,7 +1177,7 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
 
 static bool update_item_ok(const UpdateItem& it) {
   const Geom& g = it.g;
-  if (!geom_ok(g) || g.ld > kMaxLd || !it.W || !it.d || it.nv < 0 || it.nv > 4 ||
+  if (!geom_ok(g) || g.lges != 0 || g.ld > kMaxLd || !it.W || !it.d || it.nv < 0 || it.nv > 4 ||
       (it.want_norm && !it.part) || (it.v1 && !it.v1mult) || (it.sym && !it.want_norm))
     return false;
   for (int v = 0; v < it.nv; ++v)

@@ -37,6 +37,7 @@ struct Geom {
   int C = 1;       // 16-byte chunks per lane (<= 4), L * C >= ncolv
   int nblk = 0;
   int rpb = 0;     // rows per block
+  int lges = 0;    // product only: log2 of the entry split (L / 2^lges column lanes)
 };
 Geom make_geom(int64_t n, int ld, int xbytes);
 // The same with an explicit lanes-per-row L (power of two) and chunks per
@@ -71,7 +72,7 @@ struct SpmmDesc {
   const void* fx[2];
   const double* fmult[2];
   double* part;
-  int lgL, ld, ncolv, voff;
+  int lgL, lgES, ld, ncolv, voff;
 };
 
 struct UpdDesc {

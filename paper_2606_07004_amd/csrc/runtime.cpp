@@ -298,7 +298,20 @@ Geom Run::krylov_geom(int ld, int which) const {
     std::lock_guard<std::mutex> lk(a_->tune_mu);
     auto it = a_->tune.find(tune_key(ld, xb_, vt, which));
     if (it != a_->tune.end()) {
-      const Geom g = make_geom_lc(n_, ld, xb_, it->second.first, it->second.second);
+      Geom g = make_geom_lc(n_, ld, xb_, it->second.first & 0xff, it->second.second);
+      g.lges = it->second.first >> 8;  // entry split of the product
+      if (geom_usable(g)) return g;
+    }
+  }
+  if (which == 0 && a_->nnz >= 64 * a_->n) {
+    // long rows: one chunk per lane and the row's entries over two lane
+    // groups, which halves each lane's chain of dependent gathers
+    const int ncolv = ld / (16 / xb_);
+    int Lc = 1;
+    while (Lc < ncolv) Lc <<= 1;
+    if (Lc <= 32) {
+      Geom g = make_geom_lc(n_, ld, xb_, 2 * Lc, 1);
+      g.lges = 1;
       if (geom_usable(g)) return g;
     }
   }
@@ -929,17 +942,31 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail, 
 
 // (L, C) pairs for a block of ld columns: L a power of two <= 64, C <= kMaxC,
 // L * C chunks covering the row with at most half a row idle; the default
-// geometry first.
-static std::vector<std::pair<int, int>> tune_candidates(int64_t n, int ld, int xbytes) {
+// geometry first.  With split > 0 (the product) also every entry split
+// 2^e <= 8 of each pair with L 2^e <= 64 lanes per row, encoded as
+// (L 2^e) | (e << 8).
+static std::vector<std::pair<int, int>> tune_candidates(int64_t n, int ld, int xbytes,
+                                                        bool split) {
   const Geom d = make_geom(n, ld, xbytes);
   std::vector<std::pair<int, int>> out{{d.L, d.C}};
   for (int L = 1; L <= 64; L <<= 1)
     for (int C = 1; C <= kMaxC; ++C) {
       const int idle = L * C - d.ncolv;
-      if (idle < 0 || 2 * idle > d.ncolv || (L == d.L && C == d.C)) continue;
-      if (geom_usable(make_geom_lc(n, ld, xbytes, L, C))) out.push_back({L, C});
+      if (idle < 0 || 2 * idle > d.ncolv) continue;
+      for (int e = 0; e <= (split ? 3 : 0); ++e) {
+        if ((L << e) > 64 || (L == d.L && C == d.C && e == 0)) continue;
+        Geom g = make_geom_lc(n, ld, xbytes, L << e, C);
+        g.lges = e;
+        if (geom_usable(g)) out.push_back({(L << e) | (e << 8), C});
+      }
     }
   return out;
+}
+
+static Geom candidate_geom(int64_t n, int ld, int xbytes, const std::pair<int, int>& c) {
+  Geom g = make_geom_lc(n, ld, xbytes, c.first & 0xff, c.second);
+  g.lges = c.first >> 8;
+  return g;
 }
 
 namespace {
@@ -995,7 +1022,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     const int ld = widths[wi];
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7475u, n_, 0, ld, ld, X, xb_, ld, 0));
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7476u, n_, 0, ld, ld, V, xb_, ld, 0));
-    const auto cand = tune_candidates(n_, ld, xb_);
+    const auto cand = tune_candidates(n_, ld, xb_, true);
     const int nc = (int)cand.size();
     std::vector<double> tp(nc, 1e300), tu(nc, 1e300);
     VecSet vf{};
@@ -1008,7 +1035,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     }
     for (int round = 0; round < 3; ++round)
       for (int c = 0; c < nc; ++c) {
-        const Geom g = make_geom_lc(n_, ld, xb_, cand[c].first, cand[c].second);
+        const Geom g = candidate_geom(n_, ld, xb_, cand[c]);
         int nb = 0;
         float ms = 0.f;
         auto product = [&]() {
@@ -1025,6 +1052,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
         LD_HIP(hipEventSynchronize(ev.b));
         LD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
         tp[c] = std::min(tp[c], (double)ms / reps);
+        if (g.lges != 0) continue;  // the update has no sparse entries to split
         LD_HIP(update());
         LD_HIP(hipEventRecord(ev.a, st));
         for (int i = 0; i < reps; ++i) LD_HIP(update());
@@ -1045,8 +1073,9 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     }
     if (wi == 0 && out) {
       *out = ld_tune_result{};
-      out->spmm_lanes = cand[bp].first;
+      out->spmm_lanes = cand[bp].first & 0xff;
       out->spmm_chunks = cand[bp].second;
+      out->spmm_entry_split = 1 << (cand[bp].first >> 8);
       out->update_lanes = cand[bu].first;
       out->update_chunks = cand[bu].second;
       out->spmm_ms = tp[bp];
@@ -1059,15 +1088,21 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
   return LD_OK;
 }
 
-ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int update_lanes, int update_chunks) {
-  if (!geom_usable(make_geom_lc(n_, ldB_, xb_, spmm_lanes, spmm_chunks)) ||
+ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int update_lanes,
+                         int update_chunks) {
+  int e = 0;
+  while (e < 4 && (1 << e) < spmm_split) ++e;
+  Geom gp = make_geom_lc(n_, ldB_, xb_, spmm_lanes, spmm_chunks);
+  gp.lges = e;
+  if ((1 << e) != spmm_split || !geom_usable(gp) ||
       !geom_usable(make_geom_lc(n_, ldB_, xb_, update_lanes, update_chunks)))
     return set_error(LD_E_INVALID_ARG,
-                     "lanes must be a power of two <= 64 and chunks in [1, 4], together "
-                     "covering the probe block");
+                     "lanes must be a power of two <= 64, chunks in [1, 4] and the entry split "
+                     "1, 2, 4 or 8 (at most the lanes), the lanes per split group and the "
+                     "chunks covering the probe block");
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
   std::lock_guard<std::mutex> lk(a_->tune_mu);
-  a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes, spmm_chunks};
+  a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes | (e << 8), spmm_chunks};
   a_->tune[tune_key(ldB_, xb_, vt, 1)] = {update_lanes, update_chunks};
   return LD_OK;
 }
@@ -1295,12 +1330,12 @@ ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_re
 }
 
 ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
-                      int32_t update_lanes, int32_t update_chunks) {
+                      int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks) {
   if (!a || !p) return set_error(LD_E_INVALID_ARG, "null argument");
   Run run(a, *p);
   ld_status rc = run.validate();
   if (rc != LD_OK) return rc;
-  return run.tune_set(spmm_lanes, spmm_chunks, update_lanes, update_chunks);
+  return run.tune_set(spmm_lanes, spmm_chunks, spmm_entry_split, update_lanes, update_chunks);
 }
 
 ld_status ld_quad_form(ld_matrix* a, const double* x, double* out) {

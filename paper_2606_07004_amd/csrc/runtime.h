@@ -93,7 +93,8 @@ struct ld_matrix {
   size_t bytes = 0;
   std::atomic<int> inflight{0};
   // autotuned product/update geometry per Krylov block shape:
-  // key (ld, bytes per element, value type) -> (lanes per row, chunks per lane)
+  // key (ld, bytes per element, value type, kernel) -> (lanes per row |
+  // log2(entry split) << 8, chunks per lane)
   mutable std::mutex tune_mu;
   std::map<uint64_t, std::pair<int, int>> tune;
 };
@@ -239,7 +240,8 @@ class Run {
   // Time the candidate geometries of the Krylov-block product and update on
   // this request's matrix and block shape; store the fastest in the matrix.
   ld_status tune(hipStream_t st, int reps, ld_tune_result* out);
-  ld_status tune_set(int spmm_lanes, int spmm_chunks, int update_lanes, int update_chunks);
+  ld_status tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int update_lanes,
+                     int update_chunks);
   double submit_time() const { return t_submit_; }
   void set_submit_time(double t) { t_submit_ = t; }
   int64_t n() const { return n_; }

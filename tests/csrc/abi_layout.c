@@ -27,7 +27,7 @@ int main(void) {
   F(ld_tune_result, spmm_lanes); F(ld_tune_result, spmm_chunks); F(ld_tune_result, update_lanes);
   F(ld_tune_result, update_chunks); F(ld_tune_result, spmm_ms); F(ld_tune_result, spmm_default_ms);
   F(ld_tune_result, update_ms); F(ld_tune_result, update_default_ms);
-  F(ld_tune_result, candidates); F(ld_tune_result, reserved);
+  F(ld_tune_result, candidates); F(ld_tune_result, spmm_entry_split);
   Z(ld_tune_result);
   return 0;
 }

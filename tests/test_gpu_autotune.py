@@ -40,6 +40,12 @@ def _usable(ncolv):
             if lanes * ch >= ncolv]
 
 
+def _splits(lanes, chunks=1):
+    """Entry splits of the product that fit `lanes` column lanes in 64 (one or
+    two chunks per lane)."""
+    return [e for e in (1, 2, 4, 8) if lanes * e <= 64 and (e == 1 or chunks <= 2)]
+
+
 def _sweep(L, ctx, a, npr, prec, vt, rtol_oracle, rtol_default, vec, k):
     s, m, seed = 6, 14, 31
     ref = oracle.oslq(a, npr, s, m, k, seed)
@@ -50,17 +56,18 @@ def _sweep(L, ctx, a, npr, prec, vt, rtol_oracle, rtol_default, vec, k):
         assert abs(base - ref.logdet) <= rtol_oracle * abs(ref.logdet)
         ncolv = ((npr + 3) // 4 * 4) // vec
         geoms = _usable(ncolv)
-        for i, (lanes, ch) in enumerate(geoms):
+        cases = [(lanes, ch, e) for lanes, ch in geoms for e in _splits(lanes, ch)]
+        for i, (lanes, ch, e) in enumerate(cases):
             # the update takes the geometries in the other order, so product
             # and update differ in most cases
-            ul, uc = geoms[len(geoms) - 1 - i]
+            ul, uc = geoms[(len(geoms) - 1 - i) % len(geoms)]
             _announce(f"forced geometry n={a.n} probes={npr} prec={prec} "
-                      f"product L={lanes} C={ch} update L={ul} C={uc}")
-            L.ld_tune_set(h, p, lanes, ch, ul, uc)
+                      f"product L={lanes * e} C={ch} split={e} update L={ul} C={uc}")
+            L.ld_tune_set(h, p, lanes * e, ch, ul, uc, e)
             res, det = L.ld_estimate_detail(h, p, n=a.n, tri=True)
             rel = abs(res.logdet - ref.logdet) / abs(ref.logdet)
             assert rel <= rtol_oracle, (lanes, ch, ul, uc, rel)
-            assert abs(res.logdet - base) <= rtol_default * abs(base), (lanes, ch, ul, uc)
+            assert abs(res.logdet - base) <= rtol_default * abs(base), (lanes, ch, e, ul, uc)
             np.testing.assert_array_equal(det["probe_steps"], np.array(ref.probe_steps))
             np.testing.assert_allclose(det["probe_K"], ref.probe_K,
                                        rtol=rtol_oracle * 100, atol=rtol_oracle * 100)
@@ -81,16 +88,55 @@ def test_every_geometry_mixed(L, ctx):
            1e-4, 1e-5, 4, 2)
 
 
+def test_entry_split_long_rows(L, ctx):
+    # Wendland rows (~60 entries): every entry split of the product, FP64 and
+    # FP16 vectors, against the oracle; fused inner product from the re-read
+    # diagonal block row
+    a = W.wendland(6000, 60.0, 1e-2, seed=9)
+    npr, s, m, k, seed = 32, 8, 20, 2, 4
+    ref = oracle.oslq(a, npr, s, m, k, seed, lo_hint=1e-2)
+    # FP16 vectors on a Wendland matrix sit near 1e-4 from FP64 (its many
+    # eigenvalues near the nugget): checked against the unsplit FP16 run
+    for prec, vec, tol in ((L.LD_PREC_FP64, 2, 1e-6), (L.LD_PREC_HALF, 8, 1e-3)):
+        h = ctx.matrix(a, vt=L.LD_VT_FP32 if prec == L.LD_PREC_HALF else L.LD_VT_FP64,
+                       lo_hint=1e-2)
+        try:
+            p = L.make_params(npr, s, m, k, seed, precision=prec)
+            ncolv = npr // vec
+            lanes = 1
+            while lanes < ncolv:
+                lanes *= 2
+            base = None
+            for e in _splits(lanes):
+                _announce(f"entry split {e} n={a.n} nnz={a.nnz} prec={prec} L={lanes * e}")
+                L.ld_tune_set(h, p, lanes * e, 1, lanes, 1, e)
+                res = L.ld_estimate_ex(h, p)
+                rel = abs(res.logdet - ref.logdet) / abs(ref.logdet)
+                print(f"  rel {rel:.3e}", flush=True)
+                assert rel <= tol, (e, rel)
+                assert L.ld_estimate_ex(h, p).logdet == res.logdet
+                if base is None:
+                    base = res.logdet
+                # a split changes the order of the FP32 row sums; with FP16
+                # storage that moves the estimate within its rounding noise
+                btol = 1e-12 if prec == L.LD_PREC_FP64 else 1e-4
+                assert abs(res.logdet - base) <= btol * abs(base), e
+        finally:
+            ctx.release(h)
+
+
 def test_invalid_geometry_rejected(L, ctx):
     a = W.lap2d(40, 0.1)
     h = ctx.matrix(a)
     try:
         p = L.make_params(24, 6, 10, 2, 1)
         base = L.ld_estimate_ex(h, p).logdet
-        for bad in ((3, 4), (0, 1), (128, 1), (4, 0), (4, 5), (1, 4), (2, 4)):
-            _announce(f"ld_tune_set rejects L={bad[0]} C={bad[1]} for 12 chunks per row")
+        for bad in ((3, 4, 1), (0, 1, 1), (128, 1, 1), (4, 0, 1), (4, 5, 1), (1, 4, 1),
+                    (2, 4, 1), (16, 1, 3), (16, 1, 16), (8, 2, 2), (64, 1, 8)):
+            _announce(f"ld_tune_set rejects L={bad[0]} C={bad[1]} split={bad[2]} "
+                      "for 12 chunks per row")
             with pytest.raises(L.LdError) as ei:
-                L.ld_tune_set(h, p, bad[0], bad[1], 4, 3)
+                L.ld_tune_set(h, p, bad[0], bad[1], 4, 3, bad[2])
             assert ei.value.status == L.LD_E_INVALID_ARG
         # nothing was stored: still the default geometry
         assert L.ld_estimate_ex(h, p).logdet == base
@@ -116,7 +162,9 @@ def test_autotune_parity_and_reset(L, ctx, prec):
         print("  ", tr.as_dict(), flush=True)
         ncolv = npr // (4 if mixed else 2)
         assert tr.candidates >= 1
-        for lanes, ch in ((tr.spmm_lanes, tr.spmm_chunks), (tr.update_lanes, tr.update_chunks)):
+        assert tr.spmm_entry_split in (1, 2, 4, 8)
+        for lanes, ch in ((tr.spmm_lanes // tr.spmm_entry_split, tr.spmm_chunks),
+                          (tr.update_lanes, tr.update_chunks)):
             assert (lanes, ch) in _usable(ncolv)
             assert 2 * (lanes * ch - ncolv) <= ncolv or tr.candidates == 1
         assert 0 < tr.spmm_ms <= tr.spmm_default_ms
