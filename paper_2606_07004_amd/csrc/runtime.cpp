@@ -1107,6 +1107,68 @@ ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int upd
   return LD_OK;
 }
 
+// Host threads for a pass over `work` items: one per ~4M items, at most 16.
+static int host_threads(int64_t work) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int64_t want = std::max<int64_t>(1, work / (int64_t(1) << 22));
+  return (int)std::min<int64_t>(std::min(hw, 16), want);
+}
+
+// f(t, begin, end) on nt contiguous ranges of [0, count), in threads.
+template <typename F>
+static void parallel_ranges(int64_t count, int nt, F f) {
+  if (nt <= 1) {
+    f(0, 0, count);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) {
+    const int64_t b = count * t / nt, e = count * (t + 1) / nt;
+    th.emplace_back([=, &f]() { f(t, b, e); });
+  }
+  for (auto& x : th) x.join();
+}
+
+Stager::~Stager() {
+  if (st) (void)hipStreamSynchronize(st);
+  for (int i = 0; i < 2; ++i) {
+    if (buf[i]) (void)hipHostFree(buf[i]);
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  }
+  if (st) (void)hipStreamDestroy(st);
+}
+
+hipError_t Stager::init() {
+  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    e = hipHostMalloc((void**)&buf[i], kChunk, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+  }
+  return e;
+}
+
+hipError_t Stager::upload(void* dst, const void* src, size_t bytes) {
+  const char* s = static_cast<const char*>(src);
+  char* d = static_cast<char*>(dst);
+  size_t i = 0;
+  for (size_t off = 0; off < bytes; off += kChunk, ++i) {
+    const size_t len = std::min(kChunk, bytes - off);
+    char* b = buf[i & 1];
+    if (i >= 2) {
+      // the buffer's previous copy must have left it
+      const hipError_t e = hipEventSynchronize(ev[i & 1]);
+      if (e != hipSuccess) return e;
+    }
+    parallel_ranges((int64_t)len, host_threads((int64_t)len / 4), [&](int, int64_t b0, int64_t b1) {
+      std::memcpy(b + b0, s + off + b0, (size_t)(b1 - b0));
+    });
+    hipError_t e = hipMemcpyAsync(d + off, b, len, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[i & 1], st);
+    if (e != hipSuccess) return e;
+  }
+  return hipStreamSynchronize(st);
+}
+
 }  // namespace ld
 
 // ---------------------------------------------------------------------------
@@ -1199,25 +1261,46 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
   if (!(lambda_lo_hint >= 0.0) || !(lambda_hi_hint >= 0.0) ||
       (lambda_lo_hint > 0 && lambda_hi_hint > 0 && lambda_lo_hint > lambda_hi_hint))
     return set_error(LD_E_INVALID_ARG, "bad spectral hints");
-  // structure checks on the host copy
+  // structure checks on the host copy, rows split over host threads; the
+  // error reported is the one the first failing row (in row order) gives
   if (row_ptr[0] != 0 || row_ptr[n] != nnz) return set_error(LD_E_BAD_CSR, "row_ptr[0] != 0 or row_ptr[n] != nnz");
-  for (int64_t i = 0; i < n; ++i) {
-    const int32_t a = row_ptr[i], b = row_ptr[i + 1];
-    if (b < a) return set_error(LD_E_BAD_CSR, "row_ptr not monotone at row " + std::to_string(i));
-    bool diag = false;
-    for (int32_t k = a; k < b; ++k) {
-      const int32_t c = col_idx[k];
-      if (c < 0 || c >= n) return set_error(LD_E_BAD_CSR, "column index out of range in row " + std::to_string(i));
-      if (k > a && c <= col_idx[k - 1])
-        return set_error(LD_E_BAD_CSR, "columns not sorted/unique in row " + std::to_string(i));
-      if (!std::isfinite(values[k])) return set_error(LD_E_BAD_CSR, "non-finite value in row " + std::to_string(i));
-      if (c == i) {
-        diag = true;
-        if (!(values[k] > 0.0))
-          return set_error(LD_E_NOT_SPD, "non-positive diagonal entry in row " + std::to_string(i));
+  {
+    struct Fail {
+      int64_t row = INT64_MAX;
+      ld_status st = LD_OK;
+      const char* what = nullptr;
+    };
+    auto check_rows = [&](int64_t r0, int64_t r1, Fail* f) {
+      for (int64_t i = r0; i < r1; ++i) {
+        const int32_t a = row_ptr[i], b = row_ptr[i + 1];
+        auto fail = [&](ld_status st, const char* what) {
+          f->row = i;
+          f->st = st;
+          f->what = what;
+        };
+        if (b < a) return fail(LD_E_BAD_CSR, "row_ptr not monotone at row ");
+        bool diag = false;
+        for (int32_t k = a; k < b; ++k) {
+          const int32_t c = col_idx[k];
+          if (c < 0 || c >= n) return fail(LD_E_BAD_CSR, "column index out of range in row ");
+          if (k > a && c <= col_idx[k - 1])
+            return fail(LD_E_BAD_CSR, "columns not sorted/unique in row ");
+          if (!std::isfinite(values[k])) return fail(LD_E_BAD_CSR, "non-finite value in row ");
+          if (c == i) {
+            diag = true;
+            if (!(values[k] > 0.0)) return fail(LD_E_NOT_SPD, "non-positive diagonal entry in row ");
+          }
+        }
+        if (!diag) return fail(LD_E_NOT_SPD, "missing diagonal entry in row ");
       }
-    }
-    if (!diag) return set_error(LD_E_NOT_SPD, "missing diagonal entry in row " + std::to_string(i));
+    };
+    const int nt = host_threads(nnz);
+    std::vector<Fail> fails((size_t)nt);
+    parallel_ranges(n, nt, [&](int t, int64_t r0, int64_t r1) { check_rows(r0, r1, &fails[t]); });
+    const Fail* first = nullptr;
+    for (const Fail& f : fails)
+      if (f.st != LD_OK && (!first || f.row < first->row)) first = &f;
+    if (first) return set_error(first->st, std::string(first->what) + std::to_string(first->row));
   }
   LD_HIP_API(hipSetDevice(ctx->device));
   std::unique_ptr<ld_matrix> m(new ld_matrix());
@@ -1249,18 +1332,37 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
   }
   m->bytes = (size_t)(n + 1) * 4 + (size_t)nnz * 12 + lo_bytes;
   std::vector<char> lo_host(lo_bytes);
-  if (m->vt_lo == VT_BF16) {
-    uint16_t* h = reinterpret_cast<uint16_t*>(lo_host.data());
-    for (int64_t k = 0; k < nnz; ++k) h[k] = double_to_bf16_rne(values[k]);
-  } else if (m->vt_lo == VT_F32) {
-    float* h = reinterpret_cast<float*>(lo_host.data());
-    for (int64_t k = 0; k < nnz; ++k) h[k] = (float)values[k];
+  {
+    const int nt = host_threads(nnz);
+    if (m->vt_lo == VT_BF16) {
+      uint16_t* h = reinterpret_cast<uint16_t*>(lo_host.data());
+      parallel_ranges(nnz, nt, [&](int, int64_t k0, int64_t k1) {
+        for (int64_t k = k0; k < k1; ++k) h[k] = double_to_bf16_rne(values[k]);
+      });
+    } else if (m->vt_lo == VT_F32) {
+      float* h = reinterpret_cast<float*>(lo_host.data());
+      parallel_ranges(nnz, nt, [&](int, int64_t k0, int64_t k1) {
+        for (int64_t k = k0; k < k1; ++k) h[k] = (float)values[k];
+      });
+    }
   }
-  e = hipMemcpy(m->rp, row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->ci, col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->v64, values, (size_t)nnz * 8, hipMemcpyHostToDevice);
+  // large arrays go through the context's pinned staging buffers
+  auto upload = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (bytes < ((size_t)32 << 20)) return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    std::lock_guard<std::mutex> lk(ctx->stage_mu);
+    if (!ctx->stager) {
+      std::unique_ptr<Stager> sg(new Stager());
+      const hipError_t ei = sg->init();
+      if (ei != hipSuccess) return ei;
+      ctx->stager = std::move(sg);
+    }
+    return ctx->stager->upload(dst, src, bytes);
+  };
+  e = upload(m->rp, row_ptr, (size_t)(n + 1) * 4);
+  if (e == hipSuccess) e = upload(m->ci, col_idx, (size_t)nnz * 4);
+  if (e == hipSuccess) e = upload(m->v64, values, (size_t)nnz * 8);
   if (e == hipSuccess && lo_bytes > 0)
-    e = hipMemcpy(m->vlo, lo_host.data(), lo_bytes, hipMemcpyHostToDevice);
+    e = upload(m->vlo, lo_host.data(), lo_bytes);
   // Gershgorin interval (Section 2.1), on the device
   double* part = nullptr;
   const int nb = (int)((n + kThreads - 1) / kThreads);

@@ -34,6 +34,19 @@ struct DeviceBuffer {
 
 class Server;
 
+// Host -> device uploads through two pinned staging buffers: host threads
+// fill one while the other is in flight (pageable sources reach only a part
+// of the link rate).  Created on the first large upload of a context.
+struct Stager {
+  static constexpr size_t kChunk = (size_t)64 << 20;
+  char* buf[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t st = nullptr;
+  ~Stager();
+  hipError_t init();
+  hipError_t upload(void* dst, const void* src, size_t bytes);
+};
+
 // Event-bracketed launch timing per kernel family (see ld_profile_enable).
 class Profiler {
  public:
@@ -76,6 +89,8 @@ struct ld_ctx {
   std::unique_ptr<ld::Server> server;
   std::mutex server_mu;
   ld::Profiler prof;
+  std::mutex stage_mu;
+  std::unique_ptr<ld::Stager> stager;
 };
 
 struct ld_matrix {
