@@ -105,9 +105,11 @@ def pmc_traffic(args, family, tune):
         return None
     if tune:
         chunks = tune["spmm_chunks"] if family == "spmm" else tune["update_chunks"]
+        split = tune.get("spmm_entry_split", 1) > 1
     else:
         chunks = rec.get("default_chunks", {}).get(family)
-    kname = pattern.replace("{C}", str(chunks))
+        split = False
+    kname = pattern.replace("{C}", str(chunks)).replace("{S}", "true" if split else "false")
     k = rec.get("kernels", {}).get(kname)
     if k is None:
         return None

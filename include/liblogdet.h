@@ -215,7 +215,8 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
  * covering the block).  The product may also split a row's sparse entries
  * over E = 1, 2, 4 or 8 lane groups (L / E column lanes each, their sums
  * added at the row's end), which shortens the per-lane chain of dependent
- * gathers on long rows.  ld_autotune times every such (L, C, E) with at most
+ * gathers on long rows (tried when rows hold 16 entries or more on average).
+ * ld_autotune times every such (L, C, E) with at most
  * half a row of idle chunks on this matrix, for the probe-block shapes and
  * precision that `p` implies (the estimate block and, for OSA-IOP and So-SLQ,
  * the sketch-run block), each kernel `reps` times per round over three

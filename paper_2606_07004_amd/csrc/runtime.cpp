@@ -1022,7 +1022,8 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     const int ld = widths[wi];
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7475u, n_, 0, ld, ld, X, xb_, ld, 0));
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7476u, n_, 0, ld, ld, V, xb_, ld, 0));
-    const auto cand = tune_candidates(n_, ld, xb_, true);
+    // entry splits only pay on rows of many entries
+    const auto cand = tune_candidates(n_, ld, xb_, a_->nnz >= 16 * a_->n);
     const int nc = (int)cand.size();
     std::vector<double> tp(nc, 1e300), tu(nc, 1e300);
     VecSet vf{};
