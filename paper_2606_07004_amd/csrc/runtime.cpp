@@ -165,6 +165,12 @@ void Profiler::query(uint32_t fam, int64_t* n, double* ms, double* bytes) {
 static inline int round4(int x) { return (x + 3) & ~3; }
 static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// LD_PREC_AUTO: FP16 Krylov vectors when lambda_hi / lambda_lo is at most
+// this, FP32 otherwise (measured on the serving mix of Laplacians and
+// Wendland covariances: FP16 stays within 1e-4 of FP64 up to a ratio of ~500
+// on every kind, and on the Laplacians far beyond)
+constexpr double kAutoHalfRatio = 512.0;
+
 // ---------------------------------------------------------------------------
 // Run
 // ---------------------------------------------------------------------------
@@ -200,7 +206,7 @@ ld_status Run::validate() {
       p_.method != LD_METHOD_SO_SLQ)
     return set_error(LD_E_INVALID_ARG, "unknown method");
   if (p_.precision != LD_PREC_FP64 && p_.precision != LD_PREC_MIXED &&
-      p_.precision != LD_PREC_HALF)
+      p_.precision != LD_PREC_HALF && p_.precision != LD_PREC_AUTO)
     return set_error(LD_E_INVALID_ARG, "unknown precision");
   if (p_.probe_dist != LD_PROBE_RADEMACHER && p_.probe_dist != LD_PROBE_GAUSSIAN)
     return set_error(LD_E_INVALID_ARG, "unknown probe distribution");
@@ -230,6 +236,8 @@ ld_status Run::validate() {
   adapt_every_ = p_.adapt_every > 0 ? p_.adapt_every : 5;
   mixed_ = p_.precision != LD_PREC_FP64;
   half_ = p_.precision == LD_PREC_HALF;
+  if (p_.precision == LD_PREC_AUTO)
+    half_ = a_->hi <= kAutoHalfRatio * a_->lo && k_ <= 4;
   xb_ = half_ ? 2 : (mixed_ ? 4 : 8);
   if (std::max(B_, s_) > (mixed_ ? 256 : 128))
     return set_error(LD_E_INVALID_ARG, mixed_ ? "n_probes must be <= 256 in mixed precision"
@@ -1200,7 +1208,7 @@ ld_status ld_ctx_create(const ld_ctx_opts* opts, ld_ctx** out) {
       o.default_method != LD_METHOD_SO_SLQ)
     return set_error(LD_E_INVALID_ARG, "bad default_method");
   if (o.default_precision != LD_PREC_FP64 && o.default_precision != LD_PREC_MIXED &&
-      o.default_precision != LD_PREC_HALF)
+      o.default_precision != LD_PREC_HALF && o.default_precision != LD_PREC_AUTO)
     return set_error(LD_E_INVALID_ARG, "bad default_precision");
   LD_HIP_API(hipSetDevice(o.device));
   std::unique_ptr<ld_ctx> c(new ld_ctx());

@@ -29,7 +29,7 @@ LD_E_UNKNOWN_TICKET = -8
 LD_VT_FP64, LD_VT_FP32, LD_VT_BF16 = 0, 1, 2
 LD_METHOD_OSLQ, LD_METHOD_OSA_IOP, LD_METHOD_SO_SLQ = 0, 1, 2
 LD_PROBE_RADEMACHER, LD_PROBE_GAUSSIAN = 0, 1
-LD_PREC_FP64, LD_PREC_MIXED, LD_PREC_HALF = 0, 1, 2
+LD_PREC_FP64, LD_PREC_MIXED, LD_PREC_HALF, LD_PREC_AUTO = 0, 1, 2, 3
 
 _STATUS_NAMES = {
     0: "LD_OK", 1: "LD_PENDING", -1: "LD_E_INVALID_ARG", -2: "LD_E_BAD_CSR",

@@ -166,3 +166,26 @@ def test_half_rejects_long_windows(L, ctx):
                                                              precision=L.LD_PREC_HALF)).logdet)
     finally:
         ctx.release(h)
+
+
+def test_auto_precision_choice(L, ctx):
+    # LD_PREC_AUTO: FP16 vectors when lambda_hi <= 512 lambda_lo (and window
+    # <= 4), FP32 otherwise; the result is bitwise the chosen precision's
+    for shift, expect in ((0.5, L.LD_PREC_HALF), (1e-3, L.LD_PREC_MIXED)):
+        a = W.lap2d(60, shift)
+        h = ctx.matrix(a, vt=L.LD_VT_FP32)
+        try:
+            lo, hi = L.ld_matrix_bounds(h)
+            _announce(f"auto precision {a.name} ratio {hi / lo:.1f}")
+            auto = L.ld_estimate_ex(h, L.make_params(20, 6, 20, 2, 8,
+                                                     precision=L.LD_PREC_AUTO)).logdet
+            ref = L.ld_estimate_ex(h, L.make_params(20, 6, 20, 2, 8, precision=expect)).logdet
+            assert auto == ref
+            # window 5 never takes FP16
+            auto5 = L.ld_estimate_ex(h, L.make_params(20, 6, 20, 5, 8,
+                                                      precision=L.LD_PREC_AUTO)).logdet
+            mixed5 = L.ld_estimate_ex(h, L.make_params(20, 6, 20, 5, 8,
+                                                       precision=L.LD_PREC_MIXED)).logdet
+            assert auto5 == mixed5
+        finally:
+            ctx.release(h)
