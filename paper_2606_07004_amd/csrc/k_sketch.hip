@@ -294,18 +294,24 @@ __device__ inline dmf4 mfma_f64(double a, double b, dmf4 c) {
 }
 
 // part[i][j][block] = sum over the block's rows of Xa[row][i] Xb[row][j]:
-// one wave per (row block, group of TI x TJ output tiles of 16 x 16); the k
-// dimension of the product is the row index, 4 rows per instruction.
+// one block of 4 waves per (row block, group of TI x TJ output tiles of
+// 16 x 16); each wave takes a quarter of the block's rows (the k dimension of
+// the product is the row index, 4 rows per instruction) and the four waves'
+// sums are added in wave order.
 template <int TI, int TJ>
-__global__ __launch_bounds__(64) void k_gemm_tn_mfma(int64_t n, int rpb, const double* __restrict__ Xa,
-                                                    int lda, int ca, const double* __restrict__ Xb,
-                                                    int ldb, int cb, int ngj,
-                                                    double* __restrict__ part) {
-  const int l = threadIdx.x;
+__global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, const double* __restrict__ Xa,
+                                                          int lda, int ca, const double* __restrict__ Xb,
+                                                          int ldb, int cb, int ngj,
+                                                          double* __restrict__ part) {
+  __shared__ double red[3][TI * TJ * 4][64];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int gi = blockIdx.y / ngj, gj = blockIdx.y % ngj;
   const int b = blockIdx.x;
-  const int64_t r0 = (int64_t)b * rpb;
-  const int64_t r1 = min(n, r0 + (int64_t)rpb);
+  const int64_t b0 = (int64_t)b * rpb;
+  const int64_t b1 = min(n, b0 + (int64_t)rpb);
+  const int64_t q = (((b1 - b0) + 15) / 16) * 4;  // rows per wave, a multiple of 4
+  const int64_t r0 = min(b1, b0 + w * q);
+  const int64_t r1 = min(b1, r0 + q);
   const int kr = l >> 4, cl = l & 15;
   int ia[TI], jb[TJ];
   bool oka[TI], okb[TJ];
@@ -338,14 +344,26 @@ __global__ __launch_bounds__(64) void k_gemm_tn_mfma(int64_t n, int rpb, const d
 #pragma unroll
       for (int y = 0; y < TJ; ++y) acc[x][y] = mfma_f64(a[x], bb[y], acc[x][y]);
   }
+  if (w > 0) {
+#pragma unroll
+    for (int x = 0; x < TI; ++x)
+#pragma unroll
+      for (int y = 0; y < TJ; ++y)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[w - 1][(x * TJ + y) * 4 + e][l] = acc[x][y][e];
+  }
+  __syncthreads();
+  if (w != 0) return;
 #pragma unroll
   for (int x = 0; x < TI; ++x)
 #pragma unroll
     for (int y = 0; y < TJ; ++y)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
+        double v = acc[x][y][e];
+        for (int ww = 0; ww < 3; ++ww) v += red[ww][(x * TJ + y) * 4 + e][l];
         const int i = (gi * TI + x) * 16 + 4 * e + kr, j = (gj * TJ + y) * 16 + cl;
-        if (i < ca && j < cb) part[((size_t)i * cb + j) * gridDim.x + b] = acc[x][y][e];
+        if (i < ca && j < cb) part[((size_t)i * cb + j) * gridDim.x + b] = v;
       }
 }
 
@@ -397,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_mat_mfma(int64_t n, double* _
 // chunks of 4 column tiles.  Column norms: each lane sums its column over
 // its rows, the four lanes of a column are combined by a fixed shuffle tree,
 // the block's waves in wave order.
-template <typename XT>
+template <typename XT, int NT>
 __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, const double* __restrict__ A,
                                                           int lda, int s, const double* __restrict__ Gm,
                                                           int ldg, int r, const double* __restrict__ P,
@@ -417,9 +435,9 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
   const int64_t rb0 = (int64_t)blockIdx.x * rpb;
   const int64_t rb1 = min(n, rb0 + (int64_t)rpb);
   const int ntile = r16 / 16;
-  double nrm_res[16];   // this lane's column (16 t + cl) of the residual part
+  double nrm_res[NT];   // this lane's column (16 t + cl) of the residual part (ntile <= NT)
 #pragma unroll
-  for (int t = 0; t < 16; ++t) nrm_res[t] = 0.0;
+  for (int t = 0; t < NT; ++t) nrm_res[t] = 0.0;
   double nrm_a = 0.0;   // column l of the sketch part (l < s)
   for (int64_t row0 = rb0 + 16 * w; row0 < rb1; row0 += 16 * (kThreads / 64)) {
     // sketch columns (lane l: column l) and padding columns (lane l: s + r + l)
@@ -469,7 +487,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
   }
   // column sums: residual columns over the 4 lanes of a column, then waves
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
+  for (int t = 0; t < NT; ++t) {
     double v = nrm_res[t];
     v += __shfl_xor(v, 16, 64);
     v += __shfl_xor(v, 32, 64);
@@ -599,8 +617,8 @@ hipError_t launch_gemm_tn(hipStream_t st, const Geom& g, const double* Xa, int l
     return hipErrorInvalidValue;
   // 2 x 2 tiles of 16 x 16 per wave on the matrix cores
   const int ngi = (ca + 31) / 32, ngj = (cb + 31) / 32;
-  hipLaunchKernelGGL((k_gemm_tn_mfma<2, 2>), dim3(g.nblk, ngi * ngj), dim3(64), 0, st, g.n, g.rpb,
-                     Xa, lda, ca, Xb, ldb, cb, ngj, part);
+  hipLaunchKernelGGL((k_gemm_tn_mfma<2, 2>), dim3(g.nblk, ngi * ngj), dim3(kThreads), 0, st, g.n,
+                     g.rpb, Xa, lda, ca, Xb, ldb, cb, ngj, part);
   return hipGetLastError();
 }
 
@@ -659,16 +677,29 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
     const size_t r16 = (size_t)((r + 15) & ~15), s4 = (size_t)((s + 3) & ~3);
     const size_t lds_m = (s4 * r16 + 4 * kMaxLd) * sizeof(double);
     if (s <= kMfmaMaxCols && r <= 256 && lds_m <= 64 * 1024) {
+      // residual column tiles held per lane: 4, 8 or 16
+      const int nt = (int)(r16 / 16);
+      auto go = [&](auto xt_tag, auto nt_tag) {
+        using XTT = decltype(xt_tag);
+        constexpr int NT = decltype(nt_tag)::value;
+        auto fn = k_project_mfma<XTT, NT>;
+        hipLaunchKernelGGL(fn, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n, g.rpb, A, lda, s, Gm,
+                           ldg, r, P, static_cast<XTT*>(X0), g.ld, part, oscale);
+      };
+      auto by_nt = [&](auto xt_tag) {
+        if (nt <= 4)
+          go(xt_tag, std::integral_constant<int, 4>{});
+        else if (nt <= 8)
+          go(xt_tag, std::integral_constant<int, 8>{});
+        else
+          go(xt_tag, std::integral_constant<int, 16>{});
+      };
       if (g.xbytes == 8)
-        hipLaunchKernelGGL(k_project_mfma<double>, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n, g.rpb,
-                           A, lda, s, Gm, ldg, r, P, static_cast<double*>(X0), g.ld, part, oscale);
+        by_nt(double{});
       else if (g.xbytes == 4)
-        hipLaunchKernelGGL(k_project_mfma<float>, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n, g.rpb,
-                           A, lda, s, Gm, ldg, r, P, static_cast<float*>(X0), g.ld, part, oscale);
+        by_nt(float{});
       else
-        hipLaunchKernelGGL(k_project_mfma<_Float16>, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n,
-                           g.rpb, A, lda, s, Gm, ldg, r, P, static_cast<_Float16*>(X0), g.ld, part,
-                           oscale);
+        by_nt(_Float16{});
       return hipGetLastError();
     }
   }
