@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--serve-precision", choices=("mixed", "half", "auto"), default="auto",
                     help="Krylov vectors of the served requests (auto: FP16 when the "
                          "spectral bound ratio allows, else FP32)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other full-size configurations (graph, Wendland)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip timing the other precisions on the headline workload")
     ap.add_argument("--values", choices=("fp32", "bf16"), default="fp32")
@@ -132,6 +134,15 @@ def golden_for(matrix_name, args):
                 and g.get("iop_window") == args.window and g.get("seed") == args.seed):
             return g
     return None
+
+
+def golden_file(name):
+    """The stored oracle result tests/golden/<name>.json, if present."""
+    path = os.path.join(ROOT, "tests", "golden", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
 
 
 def cpu_baseline(a, args):
@@ -230,6 +241,51 @@ def grf_bench(L, W, args):
                          "loglik": [r["loglik"] for r in recs],
                          "latency_ms": [r["latency_ms"] for r in recs]}
             print(f"[bench] grf {name} {out[name]}", file=sys.stderr, flush=True)
+    return out
+
+
+def configs_bench(L, W, args):
+    """The other full-size configurations of the workload table: the
+    Erdos-Renyi graph Laplacian (n = 1e6, 17e6 entries, 128 probes = 42 + 86,
+    60 steps, window 4) and the Wendland covariance (n = 5e5, 24.4e6 entries,
+    64 probes = 21 + 43, 40 steps, window 2, lower hint 1e-2), FP32 values.
+    Per precision: probe-steps/s over a few blocking estimates after a tuning
+    pass, and the distance from the stored FP64 oracle result of the same
+    seeded inputs."""
+    out = {}
+    cases = {
+        "er1e6_oslq_k4": (lambda: W.er_laplacian(1_000_000, 8_000_000, seed=0, shift=0.05),
+                          128, 42, 60, 4, 0.0),
+        "wendland5e5_oslq_k2": (lambda: W.wendland(500_000, 48.0, 1e-2, seed=0), 64, 21, 40, 2,
+                                1e-2),
+    }
+    with L.Context(0) as ctx:
+        for name, (build, npr, s, m, k, lo) in cases.items():
+            a = build()
+            gold = golden_file(name)
+            h = ctx.matrix(a, vt=L.LD_VT_FP32, lo_hint=lo)
+            rec = {"n": a.n, "nnz": a.nnz, "probes": npr, "sketch": s, "steps": m, "window": k}
+            del a
+            for prec in ("half", "mixed", "auto"):
+                if prec == "half" and k > 4:
+                    continue
+                p = L.make_params(npr, s, m, k, 0, precision=PRECISIONS[prec](L))
+                if args.tune_reps > 0 and prec != "auto":
+                    L.ld_autotune(h, p, args.tune_reps)
+                r = L.ld_estimate_ex(h, p)
+                reps = 3
+                steps = 0
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    steps += L.ld_estimate_ex(h, p).probe_steps
+                dt = time.perf_counter() - t0
+                rec[prec] = {"probe_steps_per_s": steps / dt, "ms_per_estimate": dt * 1e3 / reps,
+                             "logdet": r.logdet,
+                             "rel_err_vs_oracle": (abs(r.logdet - gold["logdet"]) / abs(gold["logdet"])
+                                                   if gold else None)}
+            ctx.release(h)
+            out[name] = rec
+            print(f"[bench] config {name} {rec}", file=sys.stderr, flush=True)
     return out
 
 
@@ -430,6 +486,10 @@ def main():
                     "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
                 for k, v in fam.items()}
 
+    configs = None
+    if not args.no_configs:
+        configs = configs_bench(L, W, args)
+
     variants = None
     if not args.no_variants:
         variants = precision_variants(L, ctx, h, args, accuracy.get("logdet_fp64_gpu"))
@@ -496,6 +556,7 @@ def main():
         "serving": serving,
         "comparators": comparators,
         "precision_variants": variants,
+        "configs": configs,
         "grf_sweep": grf_sweep,
         "copy_kernel": copy,
         "device_ms_per_step": device_ms_total / args.steps,
