@@ -3,6 +3,8 @@
 // quadratic forms x^T L_c x / ||x||^2 = sum_t g_t l_t + log(gamma) - c with
 // g_t = v_1^T v_t and l = log(H_m) e1.
 #include "ld_kernels.h"
+#include <algorithm>
+#include <cstdint>
 #include "gw_ql.h"
 #include "hess_log.h"
 
@@ -315,6 +317,60 @@ __global__ __launch_bounds__(kThreads) void k_combine(int64_t n, int ld, int nt,
   }
 }
 
+// The same sums, 16 bytes of a row per thread (one coalesced stream per basis
+// block, four blocks' loads in flight) with the coefficients in LDS; each
+// element keeps the FMA chain over t in ascending order, so the result is
+// bitwise that of k_combine.
+template <typename XT>
+__global__ __launch_bounds__(kThreads) void k_combine16(int64_t n, int ld, int nt,
+                                                       const XT* __restrict__ slots,
+                                                       size_t slot_elems,
+                                                       const double* __restrict__ coef,
+                                                       double* __restrict__ Y) {
+  constexpr int VEC = 16 / sizeof(XT);
+  typedef XT xv __attribute__((ext_vector_type(VEC)));
+  extern __shared__ double cs[];  // [nt][ld]
+  for (int i = threadIdx.x; i < nt * ld; i += kThreads) cs[i] = coef[i];
+  __syncthreads();
+  const int nch = ld / VEC;
+  const int64_t total = n * nch;
+  for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * kThreads) {
+    const int64_t row = q / nch;
+    const int col = (int)(q - row * nch) * VEC;
+    const size_t off = (size_t)row * ld + col;
+    double acc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = 0.0;
+    int t = 0;
+    for (; t + 4 <= nt; t += 4) {
+      xv x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        x[u] = __builtin_nontemporal_load(
+            reinterpret_cast<const xv*>(slots + (size_t)(t + u) * slot_elems + off));
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          acc[e] = fma(cs[(t + u) * ld + col + e], double(x[u][e]), acc[e]);
+    }
+    for (; t < nt; ++t) {
+      const xv x = __builtin_nontemporal_load(
+          reinterpret_cast<const xv*>(slots + (size_t)t * slot_elems + off));
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] = fma(cs[t * ld + col + e], double(x[e]), acc[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; e += 2) {
+      double2 o;
+      o.x = acc[e];
+      o.y = acc[e + 1];
+      *reinterpret_cast<double2*>(Y + off + e) = o;
+    }
+  }
+}
+
 // Plain copy, 16 bytes per lane, grid-stride (calibration of byte counters).
 __global__ __launch_bounds__(kThreads) void k_copy16(const float4* __restrict__ a,
                                                     float4* __restrict__ b, size_t n16) {
@@ -384,6 +440,27 @@ hipError_t launch_combine(hipStream_t st, int64_t n, int ld, int nt, const void*
   if (n < 1 || ld < 1 || nt < 1 || !slots || !coef || !Y || ldy != ld ||
       slot_elems < (size_t)n * ld)
     return hipErrorInvalidValue;
+  // vectorised form: whole 16-byte chunks per row, coefficients within 48 KB
+  // of LDS, 16-byte aligned blocks
+  const int vec = xbytes > 0 ? 16 / xbytes : 0;
+  const size_t lds = (size_t)nt * ld * 8;
+  if (vec > 0 && ld % vec == 0 && lds <= 48 * 1024 && slot_elems % vec == 0 &&
+      reinterpret_cast<uintptr_t>(slots) % 16 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0) {
+    const int64_t chunks = n * (ld / vec);
+    const int64_t nb = std::min<int64_t>((chunks + kThreads - 1) / kThreads, kMaxBlocks);
+    if (xbytes == 8)
+      hipLaunchKernelGGL(k_combine16<double>, dim3((unsigned)nb), dim3(kThreads), lds, st, n, ld,
+                         nt, static_cast<const double*>(slots), slot_elems, coef, Y);
+    else if (xbytes == 4)
+      hipLaunchKernelGGL(k_combine16<float>, dim3((unsigned)nb), dim3(kThreads), lds, st, n, ld,
+                         nt, static_cast<const float*>(slots), slot_elems, coef, Y);
+    else if (xbytes == 2)
+      hipLaunchKernelGGL(k_combine16<_Float16>, dim3((unsigned)nb), dim3(kThreads), lds, st, n, ld,
+                         nt, static_cast<const _Float16*>(slots), slot_elems, coef, Y);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   const int64_t total = n * ld;
   int64_t nb = (total + kThreads - 1) / kThreads;
   if (nb > 4 * kMaxBlocks) nb = 4 * kMaxBlocks;
