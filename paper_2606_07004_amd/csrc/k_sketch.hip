@@ -55,12 +55,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn(int64_t n, int rpb, const 
 // Cholesky G = R^T R (R upper, positive diagonal) and R^{-1}, one block.
 // flag = 1 when a pivot is not positive or falls below 1e-14 of its column's
 // Gram diagonal (the sketch image has numerically lost rank).
-__global__ __launch_bounds__(kThreads) void k_chol_inv(int s, const double* __restrict__ G,
-                                                      double* __restrict__ R,
-                                                      double* __restrict__ Rinv,
-                                                      int* __restrict__ flag) {
-  __shared__ double piv;
-  __shared__ int bad;
+// R and Rinv may live in global memory or in LDS (small s): the same
+// operations in the same order either way.
+__device__ inline void chol_inv_body(int s, const double* __restrict__ G, double* __restrict__ R,
+                                     double* __restrict__ Rinv, int* __restrict__ flag,
+                                     double& piv, int& bad) {
   const int t = threadIdx.x;
   for (int idx = t; idx < s * s; idx += kThreads) R[idx] = G[idx];
   if (t == 0) bad = 0;
@@ -101,6 +100,36 @@ __global__ __launch_bounds__(kThreads) void k_chol_inv(int s, const double* __re
     }
   }
   if (t == 0) *flag = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_chol_inv(int s, const double* __restrict__ G,
+                                                      double* __restrict__ R,
+                                                      double* __restrict__ Rinv,
+                                                      int* __restrict__ flag) {
+  __shared__ double piv;
+  __shared__ int bad;
+  chol_inv_body(s, G, R, Rinv, flag, piv, bad);
+}
+
+// s <= kCholLdsMax: the factor and its inverse in LDS, copied out at the end
+// (each step's barriers then wait on LDS, not on L2 round trips).
+constexpr int kCholLdsMax = 64;
+__global__ __launch_bounds__(kThreads) void k_chol_inv_lds(int s, const double* __restrict__ G,
+                                                          double* __restrict__ R,
+                                                          double* __restrict__ Rinv,
+                                                          int* __restrict__ flag) {
+  extern __shared__ double sm[];
+  __shared__ double piv;
+  __shared__ int bad;
+  double* sR = sm;
+  double* sI = sm + (size_t)s * s;
+  chol_inv_body(s, G, sR, sI, flag, piv, bad);
+  __syncthreads();
+  if (bad) return;
+  for (int idx = threadIdx.x; idx < s * s; idx += kThreads) {
+    R[idx] = sR[idx];
+    Rinv[idx] = sI[idx];
+  }
 }
 
 // Y[row][j] <- sum_i Y[row][i] M[i][j] for j < sout (M is s x sout, row-major;
@@ -330,6 +359,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, c
   for (int x = 0; x < TI; ++x)
 #pragma unroll
     for (int y = 0; y < TJ; ++y) acc[x][y] = dmf4{0.0, 0.0, 0.0, 0.0};
+  // a Gram product (the same block on both sides, diagonal tile group):
+  // the B operand is the A operand already loaded
+  const bool same = Xa == Xb && lda == ldb && gi == gj && ca == cb;
 #pragma unroll 4
   for (int64_t base = r0; base < r1; base += 4) {
     const int64_t row = base + kr;
@@ -338,7 +370,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, c
 #pragma unroll
     for (int t = 0; t < TI; ++t) a[t] = (okr && oka[t]) ? Xa[(size_t)row * lda + ia[t]] : 0.0;
 #pragma unroll
-    for (int t = 0; t < TJ; ++t) bb[t] = (okr && okb[t]) ? Xb[(size_t)row * ldb + jb[t]] : 0.0;
+    for (int t = 0; t < TJ; ++t)
+      bb[t] = (same && t < TI) ? a[t] : ((okr && okb[t]) ? Xb[(size_t)row * ldb + jb[t]] : 0.0);
 #pragma unroll
     for (int x = 0; x < TI; ++x)
 #pragma unroll
@@ -625,7 +658,11 @@ hipError_t launch_gemm_tn(hipStream_t st, const Geom& g, const double* Xa, int l
 hipError_t launch_chol_inv(hipStream_t st, int s, const double* G, double* work, double* Rinv,
                            int* flag) {
   if (s < 1 || s > 256 || !G || !work || !Rinv || !flag) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kThreads), 0, st, s, G, work, Rinv, flag);
+  if (s <= kCholLdsMax)
+    hipLaunchKernelGGL(k_chol_inv_lds, dim3(1), dim3(kThreads), (size_t)2 * s * s * sizeof(double),
+                       st, s, G, work, Rinv, flag);
+  else
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kThreads), 0, st, s, G, work, Rinv, flag);
   return hipGetLastError();
 }
 
