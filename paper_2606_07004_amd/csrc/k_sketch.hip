@@ -329,9 +329,8 @@ __device__ inline dmf4 mfma_f64(double a, double b, dmf4 c) {
 // sums are added in wave order.
 template <int TI, int TJ>
 __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, const double* __restrict__ Xa,
-                                                          int lda, int ca, const double* __restrict__ Xb,
-                                                          int ldb, int cb, int ngj,
-                                                          double* __restrict__ part) {
+                                                          int lda, int ca, const GSrc Xb, int cb,
+                                                          int ngj, double* __restrict__ part) {
   __shared__ double red[3][TI * TJ * 4][64];
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int gi = blockIdx.y / ngj, gj = blockIdx.y % ngj;
@@ -361,7 +360,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, c
     for (int y = 0; y < TJ; ++y) acc[x][y] = dmf4{0.0, 0.0, 0.0, 0.0};
   // a Gram product (the same block on both sides, diagonal tile group):
   // the B operand is the A operand already loaded
-  const bool same = Xa == Xb && lda == ldb && gi == gj && ca == cb;
+  const bool same = Xa == Xb.dense && lda == Xb.ld && gi == gj && ca == cb;
 #pragma unroll 4
   for (int64_t base = r0; base < r1; base += 4) {
     const int64_t row = base + kr;
@@ -371,7 +370,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, c
     for (int t = 0; t < TI; ++t) a[t] = (okr && oka[t]) ? Xa[(size_t)row * lda + ia[t]] : 0.0;
 #pragma unroll
     for (int t = 0; t < TJ; ++t)
-      bb[t] = (same && t < TI) ? a[t] : ((okr && okb[t]) ? Xb[(size_t)row * ldb + jb[t]] : 0.0);
+      bb[t] = (same && t < TI) ? a[t] : ((okr && okb[t]) ? gsrc_at(Xb, row, jb[t]) : 0.0);
 #pragma unroll
     for (int x = 0; x < TI; ++x)
 #pragma unroll
@@ -450,8 +449,8 @@ __global__ __launch_bounds__(kThreads) void k_rows_mat_mfma(int64_t n, double* _
 // the block's waves in wave order.
 template <typename XT, int NT>
 __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, const double* __restrict__ A,
-                                                          int lda, int s, const double* __restrict__ Gm,
-                                                          int ldg, int r, const double* __restrict__ P,
+                                                          int lda, int s, const GSrc Gm, int r,
+                                                          const double* __restrict__ P,
                                                           XT* __restrict__ X0, int ld,
                                                           double* __restrict__ part, double oscale) {
   extern __shared__ double sm[];
@@ -510,7 +509,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
         for (int e = 0; e < 4; ++e) {
           const int64_t row = row0 + 4 * e + kr;
           if (row < rb1 && j < r) {
-            const double v = Gm[(size_t)row * ldg + j] - acc[t][e];
+            const double v = gsrc_at(Gm, row, j) - acc[t][e];
             X0[(size_t)row * ld + s + j] = XT(v * oscale);
             nrm_res[t0 + t] = fma(v, v, nrm_res[t0 + t]);
           }
@@ -548,8 +547,8 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
 // thread c accumulates column c's norm in row order.
 template <typename XT>
 __global__ __launch_bounds__(kThreads) void k_project(int64_t n, int rpb, const double* __restrict__ A,
-                                                     int lda, int s, const double* __restrict__ Gm,
-                                                     int ldg, int r, const double* __restrict__ P,
+                                                     int lda, int s, const GSrc Gm, int r,
+                                                     const double* __restrict__ P,
                                                      int p_in_lds, XT* __restrict__ X0, int ld,
                                                      int tr, double* __restrict__ part,
                                                      double oscale) {
@@ -593,10 +592,9 @@ __global__ __launch_bounds__(kThreads) void k_project(int64_t n, int rpb, const 
         for (int u = 0; u < 4; ++u)
           if (j0 + u < r) acc[u] = fma(a, pr[u], acc[u]);
       }
-      const double* gr = Gm + (size_t)(rowb + rr) * ldg + j0;
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (j0 + u < r) so[rr * ld + s + j0 + u] = gr[u] - acc[u];
+        if (j0 + u < r) so[rr * ld + s + j0 + u] = gsrc_at(Gm, rowb + rr, j0 + u) - acc[u];
     }
     __syncthreads();
     if (t < ld) {
@@ -645,13 +643,20 @@ __global__ __launch_bounds__(kThreads) void k_gershgorin(int64_t n, const int* _
 
 hipError_t launch_gemm_tn(hipStream_t st, const Geom& g, const double* Xa, int lda, int ca,
                           const double* Xb, int ldb, int cb, double* part) {
-  if (g.n < 1 || g.nblk < 1 || !Xa || !Xb || !part || ca < 1 || cb < 1 || ca > lda || cb > ldb ||
-      (int64_t)g.nblk * g.rpb < g.n)
+  if (!Xb || cb > ldb) return hipErrorInvalidValue;
+  return launch_gemm_tn_g(st, g, Xa, lda, ca, GSrc{Xb, ldb, nullptr, 0}, cb, part);
+}
+
+hipError_t launch_gemm_tn_g(hipStream_t st, const Geom& g, const double* Xa, int lda, int ca,
+                            const GSrc& Xb, int cb, double* part) {
+  if (g.n < 1 || g.nblk < 1 || !Xa || !part || ca < 1 || cb < 1 || ca > lda ||
+      (int64_t)g.nblk * g.rpb < g.n || (!Xb.dense) == (!Xb.mask) ||
+      (Xb.dense && cb > Xb.ld) || (Xb.mask && Xb.nw != (cb + 63) / 64))
     return hipErrorInvalidValue;
   // 2 x 2 tiles of 16 x 16 per wave on the matrix cores
   const int ngi = (ca + 31) / 32, ngj = (cb + 31) / 32;
   hipLaunchKernelGGL((k_gemm_tn_mfma<2, 2>), dim3(g.nblk, ngi * ngj), dim3(kThreads), 0, st, g.n,
-                     g.rpb, Xa, lda, ca, Xb, ldb, cb, ngj, part);
+                     g.rpb, Xa, lda, ca, Xb, cb, ngj, part);
   return hipGetLastError();
 }
 
@@ -703,11 +708,12 @@ hipError_t launch_subspace_eig(hipStream_t st, int q, int k, const double* G, do
 }
 
 hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int lda, int s,
-                          const double* Gm, int ldg, int r, const double* P, void* X0, double* part,
+                          const GSrc& Gm, int r, const double* P, void* X0, double* part,
                           double oscale) {
-  if (g.n < 1 || g.nblk < 1 || (int64_t)g.nblk * g.rpb < g.n || !Gm || !X0 || !part || r < 1 ||
-      s < 0 || s + r > g.ld || g.ld > kThreads || (s > 0 && (!A || !P || lda < s)) || ldg < r ||
-      !(oscale > 0.0))
+  if (g.n < 1 || g.nblk < 1 || (int64_t)g.nblk * g.rpb < g.n || !X0 || !part || r < 1 ||
+      s < 0 || s + r > g.ld || g.ld > kThreads || (s > 0 && (!A || !P || lda < s)) ||
+      (!Gm.dense) == (!Gm.mask) || (Gm.dense && Gm.ld < r) ||
+      (Gm.mask && Gm.nw != (r + 63) / 64) || !(oscale > 0.0))
     return hipErrorInvalidValue;
   {
     // matrix cores when P (and the norm partials) fit the block's LDS
@@ -721,7 +727,7 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
         constexpr int NT = decltype(nt_tag)::value;
         auto fn = k_project_mfma<XTT, NT>;
         hipLaunchKernelGGL(fn, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n, g.rpb, A, lda, s, Gm,
-                           ldg, r, P, static_cast<XTT*>(X0), g.ld, part, oscale);
+                           r, P, static_cast<XTT*>(X0), g.ld, part, oscale);
       };
       auto by_nt = [&](auto xt_tag) {
         if (nt <= 4)
@@ -753,13 +759,13 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
   }
   if (g.xbytes == 8)
     hipLaunchKernelGGL(k_project<double>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A, lda,
-                       s, Gm, ldg, r, P, p_in_lds, static_cast<double*>(X0), g.ld, tr, part, oscale);
+                       s, Gm, r, P, p_in_lds, static_cast<double*>(X0), g.ld, tr, part, oscale);
   else if (g.xbytes == 4)
     hipLaunchKernelGGL(k_project<float>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A, lda,
-                       s, Gm, ldg, r, P, p_in_lds, static_cast<float*>(X0), g.ld, tr, part, oscale);
+                       s, Gm, r, P, p_in_lds, static_cast<float*>(X0), g.ld, tr, part, oscale);
   else
     hipLaunchKernelGGL(k_project<_Float16>, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A,
-                       lda, s, Gm, ldg, r, P, p_in_lds, static_cast<_Float16*>(X0), g.ld, tr, part,
+                       lda, s, Gm, r, P, p_in_lds, static_cast<_Float16*>(X0), g.ld, tr, part,
                        oscale);
   return hipGetLastError();
 }

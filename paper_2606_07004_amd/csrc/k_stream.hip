@@ -945,6 +945,44 @@ static int stream_grid(const Geom& g, const void* fn) {
     default: { constexpr int CC = 4; __VA_ARGS__; } break; \
   }
 
+// Block (b, w): Philox blocks (b, pbase + 64 w + j) for j < 64 into LDS, then
+// thread rr packs row 256 b + rr's 64 sign bits.
+__global__ __launch_bounds__(kThreads) void k_rademacher_mask(uint64_t seed, int64_t n, int pbase,
+                                                             int ncols, uint64_t* __restrict__ masks,
+                                                             int nw) {
+  __shared__ uint64_t words[64][4];
+  const int64_t r0 = (int64_t)blockIdx.x * 256;
+  const int w = blockIdx.y;
+  const int nc = min(64, ncols - 64 * w);
+  if ((int)threadIdx.x < nc) {
+    uint64_t c0 = (uint64_t)blockIdx.x, c1 = (uint64_t)(pbase + 64 * w + (int)threadIdx.x), c2 = 0,
+             c3 = 0;
+    philox4x64_10(c0, c1, c2, c3, seed, 0ull);
+    words[threadIdx.x][0] = c0;
+    words[threadIdx.x][1] = c1;
+    words[threadIdx.x][2] = c2;
+    words[threadIdx.x][3] = c3;
+  }
+  __syncthreads();
+  const int rr = threadIdx.x;
+  const int64_t row = r0 + rr;
+  if (row >= n) return;
+  uint64_t m = 0;
+  for (int j = 0; j < nc; ++j) m |= ((words[j][(rr >> 6) & 3] >> (rr & 63)) & 1ull) << j;
+  masks[(size_t)row * nw + w] = m;
+}
+
+hipError_t launch_rademacher_mask(hipStream_t st, uint64_t seed, int64_t n, int pbase, int ncols,
+                                  uint64_t* masks, int nw) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  if (!masks || pbase < 0 || nw != (ncols + 63) / 64) return hipErrorInvalidValue;
+  static_assert(kThreads == 256, "one thread per row of a 256-row Philox block");
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)nw);
+  hipLaunchKernelGGL(k_rademacher_mask, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols, masks,
+                     nw);
+  return hipGetLastError();
+}
+
 hipError_t launch_rademacher(hipStream_t st, uint64_t seed, int64_t n, int pbase, int ncols,
                              int nvalid, void* X, int xbytes, int ld, int col0) {
   if (n <= 0 || ncols <= 0) return hipSuccess;

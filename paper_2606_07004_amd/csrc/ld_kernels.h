@@ -116,6 +116,26 @@ constexpr int PROBE_RADEMACHER = 0;
 constexpr int PROBE_GAUSSIAN = 1;
 hipError_t launch_probes(hipStream_t st, int dist, uint64_t seed, int64_t n, int pbase, int ncols,
                          int nvalid, void* X, int xbytes, int ld, int col0);
+// Rademacher probe columns pbase .. pbase+ncols-1 as sign bits: bit j of
+// masks[row][w] is 1 where column pbase + 64 w + j holds -1 (the same Philox
+// bits as launch_rademacher); nw = ceil(ncols / 64) words per row.
+hipError_t launch_rademacher_mask(hipStream_t st, uint64_t seed, int64_t n, int pbase, int ncols,
+                                  uint64_t* masks, int nw);
+
+// A block of FP64 probe columns read by the sketch kernels: dense values
+// (dense[row * ld + j]) or Rademacher signs packed 64 per word
+// (mask[row * nw + j / 64], bit j % 64 set for -1).
+struct GSrc {
+  const double* dense;
+  int ld;
+  const uint64_t* mask;
+  int nw;
+};
+__device__ inline double gsrc_at(const GSrc& g, int64_t row, int j) {
+  if (g.dense) return g.dense[(size_t)row * g.ld + j];
+  const uint64_t w = g.mask[(size_t)row * g.nw + (j >> 6)];
+  return ((w >> (j & 63)) & 1ull) ? -1.0 : 1.0;
+}
 
 // W = opscale * (Q X) * diag(xmult); X, W share ld/type.  With nf (<= 2)
 // fused vectors: part[voff+v][col][block] = mult_v[col] * sum x_v w, where
@@ -263,6 +283,9 @@ hipError_t launch_combine(hipStream_t st, int64_t n, int ld, int nt, const void*
 // part[i][j][b] = sum_{rows of b} Xa[row][i] * Xb[row][j], i < ca, j < cb
 hipError_t launch_gemm_tn(hipStream_t st, const Geom& g, const double* Xa, int lda, int ca,
                           const double* Xb, int ldb, int cb, double* part);
+// Same with the right operand given as dense columns or packed signs.
+hipError_t launch_gemm_tn_g(hipStream_t st, const Geom& g, const double* Xa, int lda, int ca,
+                            const GSrc& Xb, int cb, double* part);
 hipError_t launch_chol_inv(hipStream_t st, int s, const double* G, double* work, double* Rinv,
                            int* flag);
 hipError_t launch_trsm_rows(hipStream_t st, int64_t n, double* Y, int ld, int s, const double* Rinv);
@@ -278,8 +301,8 @@ hipError_t launch_subspace_eig(hipStream_t st, int q, int k, const double* G, do
 // X0 is stored at the scale oscale (a power of two); the norm partials are
 // those of the unscaled FP64 vectors.
 hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int lda, int s,
-                          const double* Gm, int ldg, int r, const double* P, void* X0,
-                          double* part, double oscale);
+                          const GSrc& Gm, int r, const double* P, void* X0, double* part,
+                          double oscale);
 
 // Plain device copy of `bytes` (multiple of 16 used), calibration only.
 hipError_t launch_copy16(hipStream_t st, const void* src, void* dst, size_t bytes);

@@ -352,8 +352,13 @@ size_t Run::layout(char* base) {
   }
   slots_ = take(slot_bytes);
   mult_ = static_cast<double*>(take((size_t)nslots_ * ldx_ * 8));
-  S_ = static_cast<double*>(take(n * std::max(lds_, ldr_) * 8));
-  G_ = S_;
+  // Rademacher residual probes as packed signs (64 per word); Gaussian ones
+  // as FP64 columns in the sketch-probe buffer once the sketch is formed
+  const bool gsigns = p_.probe_dist == LD_PROBE_RADEMACHER;
+  nwr_ = (r_ + 63) / 64;
+  S_ = static_cast<double*>(take(n * (gsigns ? lds_ : std::max(lds_, ldr_)) * 8));
+  G_ = gsigns ? nullptr : S_;
+  gmask_ = gsigns ? static_cast<uint64_t*>(take(n * (size_t)nwr_ * 8)) : nullptr;
   Y_ = s_ > 0 ? static_cast<double*>(take(n * lds_ * 8)) : nullptr;
   // streaming kernels: fused product dots (2 rows of ld) and further dots
   // launches (up to 4 rows of ld) in separate regions, kMaxBlocks each
@@ -432,16 +437,25 @@ ld_status Run::sketch_qr(hipStream_t st, double* Y, int cols) {
 ld_status Run::start_block(hipStream_t st, const double* A, int s_cols) {
   // no previous quadrature value yet (all-ones bytes: NaN) for the adaptive test
   LD_HIP(hipMemsetAsync(kprev_, 0xFF, (size_t)ldx_ * 8, st));
-  LD_LAUNCH(LD_PROF_PROBES, (double)n_ * ldr_ * 8,
-            launch_probes(st, p_.probe_dist, p_.seed, n_, s_, ldr_, r_, G_, 8, ldr_, 0));
+  GSrc gs{G_, ldr_, gmask_, nwr_};
+  if (gmask_) {
+    gs.dense = nullptr;
+    LD_LAUNCH(LD_PROF_PROBES, (double)n_ * nwr_ * 8,
+              launch_rademacher_mask(st, p_.seed, n_, s_, r_, gmask_, nwr_));
+  } else {
+    gs.mask = nullptr;
+    LD_LAUNCH(LD_PROF_PROBES, (double)n_ * ldr_ * 8,
+              launch_probes(st, p_.probe_dist, p_.seed, n_, s_, ldr_, r_, G_, 8, ldr_, 0));
+  }
+  const double gbytes = gmask_ ? (double)n_ * nwr_ * 8 : (double)n_ * r_ * 8;
   if (s_cols > 0) {
-    LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * (s_cols + r_) * 8,
-              launch_gemm_tn(st, gS_, A, lds_, s_cols, G_, ldr_, r_, part_));
+    LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * s_cols * 8 + gbytes,
+              launch_gemm_tn_g(st, gS_, A, lds_, s_cols, gs, r_, part_));
     LD_LAUNCH(LD_PROF_REDUCE, (double)gS_.nblk * s_cols * r_ * 8,
               launch_reduce(st, part_, gS_.nblk, s_cols * r_, pmat_));
   }
-  LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * (s_cols + r_) * 8 + (double)n_ * ldB_ * xb_,
-            launch_project(st, gB_, A, lds_, s_cols, G_, ldr_, r_, pmat_, slots_, part_, oscale_));
+  LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * s_cols * 8 + gbytes + (double)n_ * ldB_ * xb_,
+            launch_project(st, gB_, A, lds_, s_cols, gs, r_, pmat_, slots_, part_, oscale_));
   LD_LAUNCH(LD_PROF_SMALL, (double)gB_.nblk * ldB_ * 8,
             launch_start_finish(st, B_, ldB_, part_, gB_.nblk, norm2_, mult_, active_, meff_, gq_,
                                 m_ + 1, 1.0 / oscale_));

@@ -199,7 +199,9 @@ class Run {
   // device buffers
   double* S_ = nullptr;       // [n][lds] sketch probes (aliases G_)
   double* Y_ = nullptr;       // [n][lds] sketch image -> basis A
-  double* G_ = nullptr;       // [n][ldr] residual probes
+  double* G_ = nullptr;       // [n][ldr] residual probes (Gaussian)
+  uint64_t* gmask_ = nullptr; // [n][nwr] residual probe signs (Rademacher)
+  int nwr_ = 0;
   void* slots_ = nullptr;     // Krylov storage
   double* mult_ = nullptr;    // [nslots][ld]
   double* part_ = nullptr;    // per-block partial sums
