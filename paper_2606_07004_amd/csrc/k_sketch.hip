@@ -327,10 +327,12 @@ __device__ inline dmf4 mfma_f64(double a, double b, dmf4 c) {
 // 16 x 16); each wave takes a quarter of the block's rows (the k dimension of
 // the product is the row index, 4 rows per instruction) and the four waves'
 // sums are added in wave order.
-template <int TI, int TJ>
+template <int TI, int TJ, bool MASK>
 __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, const double* __restrict__ Xa,
-                                                          int lda, int ca, const GSrc Xb, int cb,
-                                                          int ngj, double* __restrict__ part) {
+                                                          int lda, int ca, const double* __restrict__ Xb,
+                                                          int ldb, const uint64_t* __restrict__ Mb,
+                                                          int nwb, int cb, int ngj,
+                                                          double* __restrict__ part) {
   __shared__ double red[3][TI * TJ * 4][64];
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int gi = blockIdx.y / ngj, gj = blockIdx.y % ngj;
@@ -360,7 +362,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, c
     for (int y = 0; y < TJ; ++y) acc[x][y] = dmf4{0.0, 0.0, 0.0, 0.0};
   // a Gram product (the same block on both sides, diagonal tile group):
   // the B operand is the A operand already loaded
-  const bool same = Xa == Xb.dense && lda == Xb.ld && gi == gj && ca == cb;
+  const bool same = Xa == Xb && lda == ldb && gi == gj && ca == cb;
+  // sign words: the TJ tiles of 16 columns from jb[0] lie in one 64-column word
+  const int wb = jb[0] >> 6;
 #pragma unroll 4
   for (int64_t base = r0; base < r1; base += 4) {
     const int64_t row = base + kr;
@@ -370,7 +374,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, c
     for (int t = 0; t < TI; ++t) a[t] = (okr && oka[t]) ? Xa[(size_t)row * lda + ia[t]] : 0.0;
 #pragma unroll
     for (int t = 0; t < TJ; ++t)
-      bb[t] = (same && t < TI) ? a[t] : ((okr && okb[t]) ? gsrc_at(Xb, row, jb[t]) : 0.0);
+      bb[t] = (same && t < TI) ? a[t] : ((!MASK && okr && okb[t]) ? Xb[(size_t)row * ldb + jb[t]] : 0.0);
+    if constexpr (MASK) {
+      const uint64_t wd = okr ? Mb[(size_t)row * nwb + wb] : 0ull;
+#pragma unroll
+      for (int t = 0; t < TJ; ++t)
+        bb[t] = (okr && okb[t]) ? (((wd >> (jb[t] & 63)) & 1ull) ? -1.0 : 1.0) : 0.0;
+    }
 #pragma unroll
     for (int x = 0; x < TI; ++x)
 #pragma unroll
@@ -447,9 +457,11 @@ __global__ __launch_bounds__(kThreads) void k_rows_mat_mfma(int64_t n, double* _
 // chunks of 4 column tiles.  Column norms: each lane sums its column over
 // its rows, the four lanes of a column are combined by a fixed shuffle tree,
 // the block's waves in wave order.
-template <typename XT, int NT>
+template <typename XT, int NT, bool MASK>
 __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, const double* __restrict__ A,
-                                                          int lda, int s, const GSrc Gm, int r,
+                                                          int lda, int s, const double* __restrict__ Gd,
+                                                          int ldg, const uint64_t* __restrict__ Gmk,
+                                                          int nwg, int r,
                                                           const double* __restrict__ P,
                                                           XT* __restrict__ X0, int ld,
                                                           double* __restrict__ part, double oscale) {
@@ -501,6 +513,13 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
         for (int t = 0; t < 4; ++t)
           if (t0 + t < ntile) acc[t] = mfma_f64(a, sP[kk * r16 + (t0 + t) * 16 + cl], acc[t]);
       }
+      // sign words: tiles t0 .. t0 + 3 are columns 64 (t0 / 4) .. + 63
+      uint64_t wd[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = row0 + 4 * e + kr;
+        wd[e] = (MASK && row < rb1) ? Gmk[(size_t)row * nwg + (t0 >> 2)] : 0ull;
+      }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         if (t0 + t >= ntile) break;
@@ -509,7 +528,9 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
         for (int e = 0; e < 4; ++e) {
           const int64_t row = row0 + 4 * e + kr;
           if (row < rb1 && j < r) {
-            const double v = gsrc_at(Gm, row, j) - acc[t][e];
+            const double g = MASK ? (((wd[e] >> (j & 63)) & 1ull) ? -1.0 : 1.0)
+                                  : Gd[(size_t)row * ldg + j];
+            const double v = g - acc[t][e];
             X0[(size_t)row * ld + s + j] = XT(v * oscale);
             nrm_res[t0 + t] = fma(v, v, nrm_res[t0 + t]);
           }
@@ -655,8 +676,9 @@ hipError_t launch_gemm_tn_g(hipStream_t st, const Geom& g, const double* Xa, int
     return hipErrorInvalidValue;
   // 2 x 2 tiles of 16 x 16 per wave on the matrix cores
   const int ngi = (ca + 31) / 32, ngj = (cb + 31) / 32;
-  hipLaunchKernelGGL((k_gemm_tn_mfma<2, 2>), dim3(g.nblk, ngi * ngj), dim3(kThreads), 0, st, g.n,
-                     g.rpb, Xa, lda, ca, Xb, cb, ngj, part);
+  auto fn = Xb.mask ? k_gemm_tn_mfma<2, 2, true> : k_gemm_tn_mfma<2, 2, false>;
+  hipLaunchKernelGGL(fn, dim3(g.nblk, ngi * ngj), dim3(kThreads), 0, st, g.n, g.rpb, Xa, lda, ca,
+                     Xb.dense, Xb.ld, Xb.mask, Xb.nw, cb, ngj, part);
   return hipGetLastError();
 }
 
@@ -725,9 +747,10 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
       auto go = [&](auto xt_tag, auto nt_tag) {
         using XTT = decltype(xt_tag);
         constexpr int NT = decltype(nt_tag)::value;
-        auto fn = k_project_mfma<XTT, NT>;
-        hipLaunchKernelGGL(fn, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n, g.rpb, A, lda, s, Gm,
-                           r, P, static_cast<XTT*>(X0), g.ld, part, oscale);
+        auto fn = Gm.mask ? k_project_mfma<XTT, NT, true> : k_project_mfma<XTT, NT, false>;
+        hipLaunchKernelGGL(fn, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n, g.rpb, A, lda, s,
+                           Gm.dense, Gm.ld, Gm.mask, Gm.nw, r, P, static_cast<XTT*>(X0), g.ld,
+                           part, oscale);
       };
       auto by_nt = [&](auto xt_tag) {
         if (nt <= 4)
