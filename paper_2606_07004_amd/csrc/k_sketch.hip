@@ -457,7 +457,18 @@ __global__ __launch_bounds__(kThreads) void k_rows_mat_mfma(int64_t n, double* _
 // chunks of 4 column tiles.  Column norms: each lane sums its column over
 // its rows, the four lanes of a column are combined by a fixed shuffle tree,
 // the block's waves in wave order.
-template <typename XT, int NT, bool MASK>
+// Ordering of LDS accesses between lanes of one wave (a wave's LDS
+// instructions run in order; this keeps the compiler from moving them).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// STAGE: each wave assembles its 16-row output tile in LDS and writes it
+// with 16-byte stores (the rows of X0 are contiguous); otherwise element
+// stores.  Same values either way.
+template <typename XT, int NT, bool MASK, bool STAGE>
 __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, const double* __restrict__ A,
                                                           int lda, int s, const double* __restrict__ Gd,
                                                           int ldg, const uint64_t* __restrict__ Gmk,
@@ -469,6 +480,8 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
   const int r16 = (r + 15) & ~15, s4 = (s + 3) & ~3;
   double* sP = sm;                                  // [s4][r16]
   double* sN = sm + (size_t)s4 * r16;               // [4 waves][kMaxLd] norm partials
+  // [4 waves][16][ld] output tiles (STAGE)
+  XT* sO = reinterpret_cast<XT*>(sN + 4 * kMaxLd) + (size_t)(threadIdx.x >> 6) * 16 * ld;
   for (int e = threadIdx.x; e < s4 * r16; e += kThreads) {
     const int i = e / r16, j = e % r16;
     sP[e] = (i < s && j < r) ? P[(size_t)i * r + j] : 0.0;
@@ -490,7 +503,10 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
         const int64_t row = row0 + q;
         if (row >= rb1) break;
         const double v = A[(size_t)row * lda + l];
-        X0[(size_t)row * ld + l] = XT(v * oscale);
+        if constexpr (STAGE)
+          sO[q * ld + l] = XT(v * oscale);
+        else
+          X0[(size_t)row * ld + l] = XT(v * oscale);
         nrm_a = fma(v, v, nrm_a);
       }
     }
@@ -498,7 +514,10 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
       for (int q = 0; q < 16; ++q) {
         const int64_t row = row0 + q;
         if (row >= rb1) break;
-        X0[(size_t)row * ld + s + r + l] = XT(0.0);
+        if constexpr (STAGE)
+          sO[q * ld + s + r + l] = XT(0.0);
+        else
+          X0[(size_t)row * ld + s + r + l] = XT(0.0);
       }
     }
     const int64_t arow = row0 + cl;
@@ -531,11 +550,25 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
             const double g = MASK ? (((wd[e] >> (j & 63)) & 1ull) ? -1.0 : 1.0)
                                   : Gd[(size_t)row * ldg + j];
             const double v = g - acc[t][e];
-            X0[(size_t)row * ld + s + j] = XT(v * oscale);
+            if constexpr (STAGE)
+              sO[(4 * e + kr) * ld + s + j] = XT(v * oscale);
+            else
+              X0[(size_t)row * ld + s + j] = XT(v * oscale);
             nrm_res[t0 + t] = fma(v, v, nrm_res[t0 + t]);
           }
         }
       }
+    }
+    if constexpr (STAGE) {
+      // the tile's valid rows as 16-byte chunks (a row is a whole number of
+      // chunks: ld * sizeof(XT) is a multiple of 16)
+      wave_lds_sync();
+      const int nrow = (int)min((int64_t)16, rb1 - row0);
+      const int nck = nrow * ld * (int)sizeof(XT) / 16;
+      const float4* src = reinterpret_cast<const float4*>(sO);
+      float4* dst = reinterpret_cast<float4*>(X0 + (size_t)row0 * ld);
+      for (int c = l; c < nck; c += 64) dst[c] = src[c];
+      wave_lds_sync();
     }
   }
   // column sums: residual columns over the 4 lanes of a column, then waves
@@ -741,14 +774,22 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
     // matrix cores when P (and the norm partials) fit the block's LDS
     const size_t r16 = (size_t)((r + 15) & ~15), s4 = (size_t)((s + 3) & ~3);
     const size_t lds_m = (s4 * r16 + 4 * kMaxLd) * sizeof(double);
+    // with the output tiles staged when they fit
+    const size_t lds_st = lds_m + (size_t)4 * 16 * g.ld * g.xbytes;
+    const bool stage = lds_st <= 64 * 1024 && (g.ld * g.xbytes) % 16 == 0 &&
+                       reinterpret_cast<uintptr_t>(X0) % 16 == 0;
     if (s <= kMfmaMaxCols && r <= 256 && lds_m <= 64 * 1024) {
       // residual column tiles held per lane: 4, 8 or 16
       const int nt = (int)(r16 / 16);
       auto go = [&](auto xt_tag, auto nt_tag) {
         using XTT = decltype(xt_tag);
         constexpr int NT = decltype(nt_tag)::value;
-        auto fn = Gm.mask ? k_project_mfma<XTT, NT, true> : k_project_mfma<XTT, NT, false>;
-        hipLaunchKernelGGL(fn, dim3(g.nblk), dim3(kThreads), lds_m, st, g.n, g.rpb, A, lda, s,
+        auto fn = Gm.mask ? (stage ? k_project_mfma<XTT, NT, true, true>
+                                   : k_project_mfma<XTT, NT, true, false>)
+                          : (stage ? k_project_mfma<XTT, NT, false, true>
+                                   : k_project_mfma<XTT, NT, false, false>);
+        hipLaunchKernelGGL(fn, dim3(g.nblk), dim3(kThreads), stage ? lds_st : lds_m, st, g.n, g.rpb,
+                           A, lda, s,
                            Gm.dense, Gm.ld, Gm.mask, Gm.nw, r, P, static_cast<XTT*>(X0), g.ld,
                            part, oscale);
       };
