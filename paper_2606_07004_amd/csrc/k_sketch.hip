@@ -362,7 +362,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, c
     for (int y = 0; y < TJ; ++y) acc[x][y] = dmf4{0.0, 0.0, 0.0, 0.0};
   // a Gram product (the same block on both sides, diagonal tile group):
   // the B operand is the A operand already loaded
-  const bool same = Xa == Xb && lda == ldb && gi == gj && ca == cb;
+  const bool same = TI == TJ && Xa == Xb && lda == ldb && gi == gj && ca == cb;
   // sign words: the TJ tiles of 16 columns from jb[0] lie in one 64-column word
   const int wb = jb[0] >> 6;
 #pragma unroll 4
@@ -707,8 +707,18 @@ hipError_t launch_gemm_tn_g(hipStream_t st, const Geom& g, const double* Xa, int
       (int64_t)g.nblk * g.rpb < g.n || (!Xb.dense) == (!Xb.mask) ||
       (Xb.dense && cb > Xb.ld) || (Xb.mask && Xb.nw != (cb + 63) / 64))
     return hipErrorInvalidValue;
-  // 2 x 2 tiles of 16 x 16 per wave on the matrix cores
-  const int ngi = (ca + 31) / 32, ngj = (cb + 31) / 32;
+  // 2 x 2 tiles of 16 x 16 per wave on the matrix cores; 2 x 4 for a wider
+  // right operand that is not the left one (each row of Xa then read once per
+  // 64 columns of Xb instead of per 32)
+  const int ngi = (ca + 31) / 32;
+  if (cb > 32 && Xa != Xb.dense) {
+    const int ngj = (cb + 63) / 64;
+    auto fn = Xb.mask ? k_gemm_tn_mfma<2, 4, true> : k_gemm_tn_mfma<2, 4, false>;
+    hipLaunchKernelGGL(fn, dim3(g.nblk, ngi * ngj), dim3(kThreads), 0, st, g.n, g.rpb, Xa, lda, ca,
+                       Xb.dense, Xb.ld, Xb.mask, Xb.nw, cb, ngj, part);
+    return hipGetLastError();
+  }
+  const int ngj = (cb + 31) / 32;
   auto fn = Xb.mask ? k_gemm_tn_mfma<2, 2, true> : k_gemm_tn_mfma<2, 2, false>;
   hipLaunchKernelGGL(fn, dim3(g.nblk, ngi * ngj), dim3(kThreads), 0, st, g.n, g.rpb, Xa, lda, ca,
                      Xb.dense, Xb.ld, Xb.mask, Xb.nw, cb, ngj, part);
