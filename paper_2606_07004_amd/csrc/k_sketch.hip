@@ -59,15 +59,17 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn(int64_t n, int rpb, const 
 // operations in the same order either way.
 __device__ inline void chol_inv_body(int s, const double* __restrict__ G, double* __restrict__ R,
                                      double* __restrict__ Rinv, int* __restrict__ flag,
-                                     double& piv, int& bad) {
+                                     double& piv, int& bad, double* gdiag) {
   const int t = threadIdx.x;
   for (int idx = t; idx < s * s; idx += kThreads) R[idx] = G[idx];
+  // the original diagonal (the pivot test) in LDS: no global read per step
+  for (int k = t; k < s; k += kThreads) gdiag[k] = G[k * s + k];
   if (t == 0) bad = 0;
   __syncthreads();
   for (int k = 0; k < s; ++k) {
     if (t == 0) {
       const double a = R[k * s + k];
-      if (!(a > 1e-14 * G[k * s + k]) || !isfinite(a)) bad = 1;
+      if (!(a > 1e-14 * gdiag[k]) || !isfinite(a)) bad = 1;
       piv = sqrt(a);
       R[k * s + k] = piv;
     }
@@ -94,8 +96,21 @@ __device__ inline void chol_inv_body(int s, const double* __restrict__ G, double
     for (int i = s - 1; i > j; --i) Rinv[i * s + j] = 0.0;
     Rinv[j * s + j] = 1.0 / R[j * s + j];
     for (int i = j - 1; i >= 0; --i) {
+      // sum over l = i+1 .. j in ascending order; four terms' operands
+      // loaded before their FMAs
       double acc = 0.0;
-      for (int l = i + 1; l <= j; ++l) acc = fma(R[i * s + l], Rinv[l * s + j], acc);
+      int l = i + 1;
+      for (; l + 4 <= j + 1; l += 4) {
+        const double r0 = R[i * s + l], r1 = R[i * s + l + 1], r2 = R[i * s + l + 2],
+                     r3 = R[i * s + l + 3];
+        const double x0 = Rinv[l * s + j], x1 = Rinv[(l + 1) * s + j], x2 = Rinv[(l + 2) * s + j],
+                     x3 = Rinv[(l + 3) * s + j];
+        acc = fma(r0, x0, acc);
+        acc = fma(r1, x1, acc);
+        acc = fma(r2, x2, acc);
+        acc = fma(r3, x3, acc);
+      }
+      for (; l <= j; ++l) acc = fma(R[i * s + l], Rinv[l * s + j], acc);
       Rinv[i * s + j] = -acc / R[i * s + i];
     }
   }
@@ -108,7 +123,8 @@ __global__ __launch_bounds__(kThreads) void k_chol_inv(int s, const double* __re
                                                       int* __restrict__ flag) {
   __shared__ double piv;
   __shared__ int bad;
-  chol_inv_body(s, G, R, Rinv, flag, piv, bad);
+  __shared__ double gdiag[256];
+  chol_inv_body(s, G, R, Rinv, flag, piv, bad, gdiag);
 }
 
 // s <= kCholLdsMax: the factor and its inverse in LDS, copied out at the end
@@ -123,7 +139,8 @@ __global__ __launch_bounds__(kThreads) void k_chol_inv_lds(int s, const double* 
   __shared__ int bad;
   double* sR = sm;
   double* sI = sm + (size_t)s * s;
-  chol_inv_body(s, G, sR, sI, flag, piv, bad);
+  __shared__ double gdiag[kCholLdsMax];
+  chol_inv_body(s, G, sR, sI, flag, piv, bad, gdiag);
   __syncthreads();
   if (bad) return;
   for (int idx = threadIdx.x; idx < s * s; idx += kThreads) {
