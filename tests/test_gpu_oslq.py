@@ -188,3 +188,41 @@ def test_oslq_sketch_widths(L, ctx, s):
     a = W.lap2d(45, 0.3)
     ref, res, det = _check_oslq(L, ctx, a, s + 20, s, 12, 2, 5)
     _elementwise(ref, det, s, 1e-8)
+
+
+@pytest.mark.parametrize("prec_name,vt_name,npr,s", [("FP64", "FP64", 110, 20),
+                                                     ("MIXED", "FP32", 110, 20),
+                                                     ("HALF", "FP32", 150, 21)])
+def test_oslq_wide_residual_block(L, ctx, prec_name, vt_name, npr, s):
+    # residual blocks wider than 64 columns and ragged against the 16-column
+    # tiles: two or three sign words per row for the Rademacher residual
+    # probes, several tile groups in the projection, output tiles staged in
+    # LDS or stored directly depending on their size
+    a = W.lap2d(50, 0.2)
+    prec = getattr(L, "LD_PREC_" + prec_name)
+    vt = getattr(L, "LD_VT_" + vt_name)
+    ref, res, det = _check_oslq(L, ctx, a, npr, s, 14, 2, 9, prec=prec, vt=vt,
+                                rtol=1e-6 if prec_name == "FP64" else 1e-4)
+    # squared residual norms from the FP64 projection, before any narrowing;
+    # with FP32 values the sketch product itself sees the rounded matrix
+    # (2^-24 per value), which moves the sketch basis and so the norms
+    np.testing.assert_allclose(det["probe_norm2"], ref.probe_norm2,
+                               rtol=1e-10 if vt_name == "FP64" else 1e-6)
+
+
+def test_oslq_wide_residual_block_gaussian(L, ctx):
+    # Gaussian residual probes take the dense-column path of the same kernels
+    a = W.lap2d(50, 0.2)
+    npr, s, m, k, seed = 110, 20, 14, 2, 12
+    _announce(f"oslq {a.name} Gaussian probes={npr} s={s}")
+    ref = oracle.oslq(a, npr, s, m, k, seed, dist=oracle.PROBE_GAUSSIAN)
+    h = ctx.matrix(a)
+    try:
+        p = L.make_params(npr, s, m, k, seed, probe_dist=L.LD_PROBE_GAUSSIAN)
+        res, det = L.ld_estimate_detail(h, p, n=a.n)
+    finally:
+        ctx.release(h)
+    rel = abs(res.logdet - ref.logdet) / abs(ref.logdet)
+    print(f"  gpu {res.logdet!r} oracle {ref.logdet!r} rel {rel:.3e}", flush=True)
+    assert rel <= 1e-6
+    np.testing.assert_allclose(det["probe_norm2"], ref.probe_norm2, rtol=1e-9)
