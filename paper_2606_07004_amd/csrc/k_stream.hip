@@ -983,6 +983,81 @@ hipError_t launch_rademacher_mask(hipStream_t st, uint64_t seed, int64_t n, int 
   return hipGetLastError();
 }
 
+// L lanes per row (a power of two), lane l holding columns 2 l and 2 l + 1;
+// every lane of a row reads the row's (column, value) pairs (the same
+// addresses: one request per row) and the sign word of each neighbour.
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void k_spmm_signs(int64_t n, int lgL,
+                                                        const int* __restrict__ rp,
+                                                        const int* __restrict__ ci,
+                                                        const VT* __restrict__ va,
+                                                        const uint64_t* __restrict__ masks, int nw,
+                                                        int s, double* __restrict__ Y, int ldy,
+                                                        double opscale) {
+  const int L = 1 << lgL, rpb = kThreads >> lgL;
+  const int l = (int)threadIdx.x & (L - 1);
+  const int c0 = 2 * l;
+  if (c0 >= ldy) return;
+  const int wsel = min(c0 >> 6, nw - 1), sh = c0 & 63;  // padding columns: any valid word
+  const bool v0 = c0 < s, v1 = c0 + 1 < s;
+  for (int64_t row = (int64_t)blockIdx.x * rpb + ((int)threadIdx.x >> lgL); row < n;
+       row += (int64_t)gridDim.x * rpb) {
+    double acc0 = 0.0, acc1 = 0.0;
+    const int kb = rp[row], ke = rp[row + 1];
+    // eight entries at a time: their (column, value) loads, then their sign
+    // words, then the FMAs in entry order
+    for (int k0 = kb; k0 < ke; k0 += 8) {
+      int cc[8];
+      double aa[8];
+      uint64_t ww[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + u;
+        cc[u] = k < ke ? ci[k] : -1;
+        aa[u] = k < ke ? value_as<VT, double>(va[k]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ww[u] = cc[u] >= 0 ? masks[(size_t)cc[u] * nw + wsel] : 0ull;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (cc[u] >= 0) {
+          const double x0 = v0 ? (((ww[u] >> sh) & 1ull) ? -1.0 : 1.0) : 0.0;
+          const double x1 = v1 ? (((ww[u] >> (sh + 1)) & 1ull) ? -1.0 : 1.0) : 0.0;
+          acc0 = fma(aa[u], x0, acc0);
+          acc1 = fma(aa[u], x1, acc1);
+        }
+    }
+    double2 o;
+    o.x = acc0 * opscale;
+    o.y = acc1 * opscale;
+    *reinterpret_cast<double2*>(Y + (size_t)row * ldy + c0) = o;
+  }
+}
+
+hipError_t launch_spmm_signs(hipStream_t st, int64_t n, const int* rp, const int* ci,
+                             const void* va, int vt, const uint64_t* masks, int nw, int s,
+                             double* Y, int ldy, double opscale) {
+  if (n < 1 || !rp || !ci || !va || !masks || !Y || s < 1 || ldy < s || ldy > 128 || ldy % 2 ||
+      nw != (s + 63) / 64 || reinterpret_cast<uintptr_t>(Y) % 16)
+    return hipErrorInvalidValue;
+  int lgL = 0;
+  while ((1 << lgL) < ldy / 2) ++lgL;
+  const int rpb = kThreads >> lgL;
+  const int64_t nb = std::min<int64_t>((n + rpb - 1) / rpb, 8 * (int64_t)kMaxBlocks);
+  if (vt == VT_F64)
+    hipLaunchKernelGGL(k_spmm_signs<double>, dim3((unsigned)nb), dim3(kThreads), 0, st, n, lgL, rp,
+                       ci, static_cast<const double*>(va), masks, nw, s, Y, ldy, opscale);
+  else if (vt == VT_F32)
+    hipLaunchKernelGGL(k_spmm_signs<float>, dim3((unsigned)nb), dim3(kThreads), 0, st, n, lgL, rp,
+                       ci, static_cast<const float*>(va), masks, nw, s, Y, ldy, opscale);
+  else if (vt == VT_BF16)
+    hipLaunchKernelGGL(k_spmm_signs<uint16_t>, dim3((unsigned)nb), dim3(kThreads), 0, st, n, lgL,
+                       rp, ci, static_cast<const uint16_t*>(va), masks, nw, s, Y, ldy, opscale);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_rademacher(hipStream_t st, uint64_t seed, int64_t n, int pbase, int ncols,
                              int nvalid, void* X, int xbytes, int ld, int col0) {
   if (n <= 0 || ncols <= 0) return hipSuccess;

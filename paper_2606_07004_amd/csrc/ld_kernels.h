@@ -283,6 +283,14 @@ hipError_t launch_combine(hipStream_t st, int64_t n, int ld, int nt, const void*
 // part[i][j][b] = sum_{rows of b} Xa[row][i] * Xb[row][j], i < ca, j < cb
 hipError_t launch_gemm_tn(hipStream_t st, const Geom& g, const double* Xa, int lda, int ca,
                           const double* Xb, int ldb, int cb, double* part);
+// Y = opscale (Q S) in FP64 for Rademacher S given as sign words
+// (masks[row][w], bit j of word w set where column 64 w + j holds -1; columns
+// s .. ldy-1 of Y are zero): each entry gathers one word instead of a row of
+// S.  Entries accumulate in CSR order with one FMA each, as in launch_spmm on
+// the FP64 +-1 block.  ldy even, s <= ldy <= 128, nw = ceil(s / 64).
+hipError_t launch_spmm_signs(hipStream_t st, int64_t n, const int* rp, const int* ci,
+                             const void* va, int vt, const uint64_t* masks, int nw, int s,
+                             double* Y, int ldy, double opscale);
 // Same with the right operand given as dense columns or packed signs.
 hipError_t launch_gemm_tn_g(hipStream_t st, const Geom& g, const double* Xa, int lda, int ca,
                             const GSrc& Xb, int cb, double* part);

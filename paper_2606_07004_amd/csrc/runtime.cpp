@@ -356,9 +356,15 @@ size_t Run::layout(char* base) {
   // as FP64 columns in the sketch-probe buffer once the sketch is formed
   const bool gsigns = p_.probe_dist == LD_PROBE_RADEMACHER;
   nwr_ = (r_ + 63) / 64;
-  S_ = static_cast<double*>(take(n * (gsigns ? lds_ : std::max(lds_, ldr_)) * 8));
+  // the OSLQ sketch product gathers sign words too (up to 128 columns), so
+  // no FP64 sketch-probe block is needed
+  const bool ssigns = gsigns && p_.method == LD_METHOD_OSLQ && s_ > 0 && lds_ <= 128;
+  nws_ = (s_ + 63) / 64;
+  S_ = static_cast<double*>(
+      take(n * (gsigns ? (ssigns ? 0 : lds_) : std::max(lds_, ldr_)) * 8));
   G_ = gsigns ? nullptr : S_;
   gmask_ = gsigns ? static_cast<uint64_t*>(take(n * (size_t)nwr_ * 8)) : nullptr;
+  smask_ = ssigns ? static_cast<uint64_t*>(take(n * (size_t)nws_ * 8)) : nullptr;
   Y_ = s_ > 0 ? static_cast<double*>(take(n * lds_ * 8)) : nullptr;
   // streaming kernels: fused product dots (2 rows of ld) and further dots
   // launches (up to 4 rows of ld) in separate regions, kMaxBlocks each
@@ -509,11 +515,22 @@ ld_status Run::run_prologue(hipStream_t st) {
   if (p_.method == LD_METHOD_OSLQ) {
     if (s_ > 0) {
       // Y = J S, J = Q / alpha (Alg 3: sketch from J S, not from f(J) S)
-      LD_LAUNCH(LD_PROF_PROBES, (double)n_ * lds_ * 8,
-                launch_probes(st, p_.probe_dist, p_.seed, n_, 0, lds_, s_, S_, 8, lds_, 0));
-      LD_LAUNCH(LD_PROF_SPMM, spmm_bytes(lds_, 8),
-                launch_spmm(st, gS_, a_->rp, a_->ci, vals_sketch, vt_sketch, S_, Y_, nullptr,
-                            opscale_, nullptr, 0, 0, nullptr, nullptr));
+      if (smask_) {
+        const int vb = vt_sketch == VT_BF16 ? 2 : (vt_sketch == VT_F32 ? 4 : 8);
+        LD_LAUNCH(LD_PROF_PROBES, (double)n_ * nws_ * 8,
+                  launch_rademacher_mask(st, p_.seed, n_, 0, s_, smask_, nws_));
+        LD_LAUNCH(LD_PROF_SKETCH,
+                  (double)a_->nnz * (vb + 4) + 4.0 * (n_ + 1) + (double)n_ * nws_ * 8 +
+                      (double)n_ * lds_ * 8,
+                  launch_spmm_signs(st, n_, a_->rp, a_->ci, vals_sketch, vt_sketch, smask_, nws_,
+                                    s_, Y_, lds_, opscale_));
+      } else {
+        LD_LAUNCH(LD_PROF_PROBES, (double)n_ * lds_ * 8,
+                  launch_probes(st, p_.probe_dist, p_.seed, n_, 0, lds_, s_, S_, 8, lds_, 0));
+        LD_LAUNCH(LD_PROF_SPMM, spmm_bytes(lds_, 8),
+                  launch_spmm(st, gS_, a_->rp, a_->ci, vals_sketch, vt_sketch, S_, Y_, nullptr,
+                              opscale_, nullptr, 0, 0, nullptr, nullptr));
+      }
       ld_status rc = sketch_qr(st, Y_, s_);
       if (rc != LD_OK) return rc;
     }

@@ -202,6 +202,8 @@ class Run {
   double* G_ = nullptr;       // [n][ldr] residual probes (Gaussian)
   uint64_t* gmask_ = nullptr; // [n][nwr] residual probe signs (Rademacher)
   int nwr_ = 0;
+  uint64_t* smask_ = nullptr; // [n][nws] OSLQ sketch probe signs (Rademacher, lds <= 128)
+  int nws_ = 0;
   void* slots_ = nullptr;     // Krylov storage
   double* mult_ = nullptr;    // [nslots][ld]
   double* part_ = nullptr;    // per-block partial sums
