@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-nmax", type=float, default=2e5)
-    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--copy-bytes", type=float, default=805306368,
                     help="bytes of the copy-kernel calibration (0 to skip)")
     ap.add_argument("--no-comparators", action="store_true",
