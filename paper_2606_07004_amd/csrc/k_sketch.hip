@@ -432,48 +432,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, c
 // the update is in place.
 constexpr int kMfmaMaxCols = 64;
 
-__global__ __launch_bounds__(kThreads) void k_rows_mat_mfma(int64_t n, double* __restrict__ Y, int ld,
-                                                           int s, const double* __restrict__ M,
-                                                           int sout) {
-  __shared__ double sM[kMfmaMaxCols * kMfmaMaxCols];
-  for (int e = threadIdx.x; e < kMfmaMaxCols * kMfmaMaxCols; e += kThreads) {
-    const int i = e / kMfmaMaxCols, j = e % kMfmaMaxCols;
-    sM[e] = (i < s && j < sout) ? M[(size_t)i * sout + j] : 0.0;
-  }
-  __syncthreads();
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int kr = l >> 4, cl = l & 15;
-  const int64_t row0 = ((int64_t)blockIdx.x * (kThreads / 64) + w) * 16;
-  if (row0 >= n) return;
-  const int s4 = (s + 3) & ~3, ntile = (sout + 15) / 16;
-  dmf4 acc[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = dmf4{0.0, 0.0, 0.0, 0.0};
-  const int64_t arow = row0 + cl;
-  for (int k0 = 0; k0 < s4; k0 += 4) {
-    const int kk = k0 + kr;
-    const double a = (arow < n && kk < s) ? Y[(size_t)arow * ld + kk] : 0.0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (t < ntile) acc[t] = mfma_f64(a, sM[kk * kMfmaMaxCols + t * 16 + cl], acc[t]);
-  }
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-    if (t < ntile)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = row0 + 4 * e + kr;
-        const int j = t * 16 + cl;
-        if (row < n && j < sout) Y[(size_t)row * ld + j] = acc[t][e];
-      }
-}
-
-// Start block [A | G - A P] (s <= 64, r <= 256, P in LDS) and the per-block
-// partial squared column norms (FP64 values before narrowing): one wave per
-// 16-row tile of the block's rows, the product A P on the matrix cores in
-// chunks of 4 column tiles.  Column norms: each lane sums its column over
-// its rows, the four lanes of a column are combined by a fixed shuffle tree,
-// the block's waves in wave order.
 // Ordering of LDS accesses between lanes of one wave (a wave's LDS
 // instructions run in order; this keeps the compiler from moving them).
 __device__ inline void wave_lds_sync() {
@@ -482,6 +440,115 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__global__ __launch_bounds__(kThreads) void k_rows_mat_mfma(int64_t n, double* __restrict__ Y, int ld,
+                                                           int s, const double* __restrict__ M,
+                                                           int sout) {
+  // M's first s4 rows (zero-padded to 64 columns), loaded once per block;
+  // the block's waves then take 16-row tiles in a grid-stride loop
+  __shared__ double sM[kMfmaMaxCols * kMfmaMaxCols];
+  const int s4 = (s + 3) & ~3, ntile = (sout + 15) / 16;
+  for (int e = threadIdx.x; e < s4 * kMfmaMaxCols; e += kThreads) {
+    const int i = e / kMfmaMaxCols, j = e % kMfmaMaxCols;
+    sM[e] = (i < s && j < sout) ? M[(size_t)i * sout + j] : 0.0;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int kr = l >> 4, cl = l & 15;
+  for (int64_t row0 = ((int64_t)blockIdx.x * (kThreads / 64) + w) * 16; row0 < n;
+       row0 += (int64_t)gridDim.x * (kThreads / 64) * 16) {
+    dmf4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = dmf4{0.0, 0.0, 0.0, 0.0};
+    const int64_t arow = row0 + cl;
+    for (int k0 = 0; k0 < s4; k0 += 4) {
+      const int kk = k0 + kr;
+      const double a = (arow < n && kk < s) ? Y[(size_t)arow * ld + kk] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < ntile) acc[t] = mfma_f64(a, sM[kk * kMfmaMaxCols + t * 16 + cl], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < ntile)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = row0 + 4 * e + kr;
+          const int j = t * 16 + cl;
+          if (row < n && j < sout) Y[(size_t)row * ld + j] = acc[t][e];
+        }
+  }
+}
+
+// The same product with each wave's 16-row tile moved through LDS: one
+// coalesced 16-byte read of the tile (row stride ld + 1 in LDS against bank
+// conflicts), the same MFMA sequence on it, the result written back into the
+// tile and stored with 16-byte writes (columns sout .. ld-1 keep their
+// values).  Dynamic LDS: M [s4][64] and four tiles [16][ld + 1].
+__global__ __launch_bounds__(kThreads) void k_rows_mat_mfma_lds(int64_t n, double* __restrict__ Y,
+                                                               int ld, int s,
+                                                               const double* __restrict__ M,
+                                                               int sout) {
+  extern __shared__ double sm[];
+  const int s4 = (s + 3) & ~3, ntile = (sout + 15) / 16, st = ld + 1;
+  double* sM = sm;
+  for (int e = threadIdx.x; e < s4 * kMfmaMaxCols; e += kThreads) {
+    const int i = e / kMfmaMaxCols, j = e % kMfmaMaxCols;
+    sM[e] = (i < s && j < sout) ? M[(size_t)i * sout + j] : 0.0;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int kr = l >> 4, cl = l & 15;
+  double* sT = sm + (size_t)s4 * kMfmaMaxCols + (size_t)w * 16 * st;
+  const int half = ld / 2;  // 16-byte chunks per row
+  for (int64_t row0 = ((int64_t)blockIdx.x * (kThreads / 64) + w) * 16; row0 < n;
+       row0 += (int64_t)gridDim.x * (kThreads / 64) * 16) {
+    const int nrow = (int)min((int64_t)16, n - row0);
+    const double2* src = reinterpret_cast<const double2*>(Y + (size_t)row0 * ld);
+    for (int c = l; c < nrow * half; c += 64) {
+      const double2 v = src[c];
+      const int r = c / half, q = 2 * (c - r * half);
+      sT[r * st + q] = v.x;
+      sT[r * st + q + 1] = v.y;
+    }
+    wave_lds_sync();
+    dmf4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = dmf4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < s4; k0 += 4) {
+      const int kk = k0 + kr;
+      const double a = (cl < nrow && kk < s) ? sT[cl * st + kk] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < ntile) acc[t] = mfma_f64(a, sM[kk * kMfmaMaxCols + t * 16 + cl], acc[t]);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < ntile)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = 4 * e + kr, j = t * 16 + cl;
+          if (r < nrow && j < sout) sT[r * st + j] = acc[t][e];
+        }
+    wave_lds_sync();
+    double2* dst = reinterpret_cast<double2*>(Y + (size_t)row0 * ld);
+    for (int c = l; c < nrow * half; c += 64) {
+      const int r = c / half, q = 2 * (c - r * half);
+      double2 v;
+      v.x = sT[r * st + q];
+      v.y = sT[r * st + q + 1];
+      dst[c] = v;
+    }
+    wave_lds_sync();
+  }
+}
+
+// Start block [A | G - A P] (s <= 64, r <= 256, P in LDS) and the per-block
+// partial squared column norms (FP64 values before narrowing): one wave per
+// 16-row tile of the block's rows, the product A P on the matrix cores in
+// chunks of 4 column tiles.  Column norms: each lane sums its column over
+// its rows, the four lanes of a column are combined by a fixed shuffle tree,
+// the block's waves in wave order.
 // STAGE: each wave assembles its 16-row output tile in LDS and writes it
 // with 16-byte stores (the rows of X0 are contiguous); otherwise element
 // stores.  Same values either way.
@@ -753,14 +820,26 @@ hipError_t launch_chol_inv(hipStream_t st, int s, const double* G, double* work,
   return hipGetLastError();
 }
 
+// Y <- Y M on the matrix cores (s, sout <= 64): through LDS tiles when they
+// fit, else straight from global memory.
+static hipError_t rows_mat_mfma(hipStream_t st, int64_t n, double* Y, int ld, int s,
+                                const double* M, int sout) {
+  const int64_t tiles = (n + 15) / 16;
+  const int64_t nb = std::min<int64_t>((tiles + 3) / 4, 2 * kMaxBlocks);
+  const size_t lds = ((size_t)((s + 3) & ~3) * kMfmaMaxCols + (size_t)4 * 16 * (ld + 1)) *
+                     sizeof(double);
+  if (ld % 2 == 0 && lds <= 64 * 1024 && reinterpret_cast<uintptr_t>(Y) % 16 == 0)
+    hipLaunchKernelGGL(k_rows_mat_mfma_lds, dim3((unsigned)nb), dim3(kThreads), lds, st, n, Y, ld,
+                       s, M, sout);
+  else
+    hipLaunchKernelGGL(k_rows_mat_mfma, dim3((unsigned)nb), dim3(kThreads), 0, st, n, Y, ld, s, M,
+                       sout);
+  return hipGetLastError();
+}
+
 hipError_t launch_trsm_rows(hipStream_t st, int64_t n, double* Y, int ld, int s, const double* Rinv) {
   if (n < 1 || s < 1 || s > 256 || ld < s || !Y || !Rinv) return hipErrorInvalidValue;
-  if (s <= kMfmaMaxCols) {
-    const int tiles = (int)((n + 15) / 16);
-    hipLaunchKernelGGL(k_rows_mat_mfma, dim3((tiles + 3) / 4), dim3(kThreads), 0, st, n, Y, ld, s,
-                       Rinv, s);
-    return hipGetLastError();
-  }
+  if (s <= kMfmaMaxCols) return rows_mat_mfma(st, n, Y, ld, s, Rinv, s);
   const size_t lds = (size_t)(16 * s + 16 * s) * sizeof(double);
   hipLaunchKernelGGL(k_rows_mat<true>, dim3((unsigned)((n + 15) / 16)), dim3(kThreads), lds, st, n, Y,
                      ld, s, Rinv, s);
@@ -772,10 +851,7 @@ hipError_t launch_rows_mat(hipStream_t st, int64_t n, double* Y, int ld, int s, 
   if (n < 1 || s < 1 || s > 256 || sout < 1 || sout > s || ld < s || !Y || !M)
     return hipErrorInvalidValue;
   if (s <= kMfmaMaxCols) {
-    const int tiles = (int)((n + 15) / 16);
-    hipLaunchKernelGGL(k_rows_mat_mfma, dim3((tiles + 3) / 4), dim3(kThreads), 0, st, n, Y, ld, s, M,
-                       sout);
-    return hipGetLastError();
+    return rows_mat_mfma(st, n, Y, ld, s, M, sout);
   }
   const size_t lds = (size_t)(16 * s + 16 * s) * sizeof(double);
   hipLaunchKernelGGL(k_rows_mat<false>, dim3((unsigned)((n + 15) / 16)), dim3(kThreads), lds, st, n, Y,
