@@ -549,10 +549,12 @@ __global__ __launch_bounds__(kThreads) void k_rows_mat_mfma_lds(int64_t n, doubl
 // chunks of 4 column tiles.  Column norms: each lane sums its column over
 // its rows, the four lanes of a column are combined by a fixed shuffle tree,
 // the block's waves in wave order.
-// STAGE: each wave assembles its 16-row output tile in LDS and writes it
+// MODE >= 1: each wave assembles its 16-row output tile in LDS and writes it
 // with 16-byte stores (the rows of X0 are contiguous); otherwise element
-// stores.  Same values either way.
-template <typename XT, int NT, bool MASK, bool STAGE>
+// stores.  MODE 2: the wave's 16-row tile of A is read once with 16-byte
+// loads into LDS (row stride lda + 1) and both uses of A read it there.  Same
+// values in every mode.
+template <typename XT, int NT, bool MASK, int MODE>
 __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, const double* __restrict__ A,
                                                           int lda, int s, const double* __restrict__ Gd,
                                                           int ldg, const uint64_t* __restrict__ Gmk,
@@ -562,10 +564,16 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
                                                           double* __restrict__ part, double oscale) {
   extern __shared__ double sm[];
   const int r16 = (r + 15) & ~15, s4 = (s + 3) & ~3;
-  double* sP = sm;                                  // [s4][r16]
-  double* sN = sm + (size_t)s4 * r16;               // [4 waves][kMaxLd] norm partials
-  // [4 waves][16][ld] output tiles (STAGE)
-  XT* sO = reinterpret_cast<XT*>(sN + 4 * kMaxLd) + (size_t)(threadIdx.x >> 6) * 16 * ld;
+  constexpr bool STAGE = MODE >= 1, SA = MODE == 2;
+  // P [s4][r16]; then one region for the A tiles [4 waves][16][lda + 1] (SA,
+  // used inside the row loop) and the norm partials [4 waves][kMaxLd] (used
+  // after it); then the output tiles [4 waves][16][ld] (STAGE)
+  const int sta = lda + 1;
+  const size_t nu = SA ? max((size_t)4 * kMaxLd, (size_t)4 * 16 * sta) : (size_t)4 * kMaxLd;
+  double* sP = sm;
+  double* sN = sm + (size_t)s4 * r16;
+  double* sA = sN + (size_t)(threadIdx.x >> 6) * 16 * sta;
+  XT* sO = reinterpret_cast<XT*>(sN + nu) + (size_t)(threadIdx.x >> 6) * 16 * ld;
   for (int e = threadIdx.x; e < s4 * r16; e += kThreads) {
     const int i = e / r16, j = e % r16;
     sP[e] = (i < s && j < r) ? P[(size_t)i * r + j] : 0.0;
@@ -581,12 +589,23 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
   for (int t = 0; t < NT; ++t) nrm_res[t] = 0.0;
   double nrm_a = 0.0;   // column l of the sketch part (l < s)
   for (int64_t row0 = rb0 + 16 * w; row0 < rb1; row0 += 16 * (kThreads / 64)) {
+    if constexpr (SA) {
+      const int nrow = (int)min((int64_t)16, rb1 - row0), halfa = lda / 2;
+      const double2* src = reinterpret_cast<const double2*>(A + (size_t)row0 * lda);
+      for (int c = l; c < nrow * halfa; c += 64) {
+        const double2 v = src[c];
+        const int rr = c / halfa, q = 2 * (c - rr * halfa);
+        sA[rr * sta + q] = v.x;
+        sA[rr * sta + q + 1] = v.y;
+      }
+      wave_lds_sync();
+    }
     // sketch columns (lane l: column l) and padding columns (lane l: s + r + l)
     if (l < s) {
       for (int q = 0; q < 16; ++q) {
         const int64_t row = row0 + q;
         if (row >= rb1) break;
-        const double v = A[(size_t)row * lda + l];
+        const double v = SA ? sA[q * sta + l] : A[(size_t)row * lda + l];
         if constexpr (STAGE)
           sO[q * ld + l] = XT(v * oscale);
         else
@@ -611,7 +630,9 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
       for (int t = 0; t < 4; ++t) acc[t] = dmf4{0.0, 0.0, 0.0, 0.0};
       for (int k0 = 0; k0 < s4; k0 += 4) {
         const int kk = k0 + kr;
-        const double a = (arow < rb1 && kk < s) ? A[(size_t)arow * lda + kk] : 0.0;
+        const double a = (arow < rb1 && kk < s)
+                             ? (SA ? sA[cl * sta + kk] : A[(size_t)arow * lda + kk])
+                             : 0.0;
 #pragma unroll
         for (int t = 0; t < 4; ++t)
           if (t0 + t < ntile) acc[t] = mfma_f64(a, sP[kk * r16 + (t0 + t) * 16 + cl], acc[t]);
@@ -663,6 +684,7 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
     v += __shfl_xor(v, 32, 64);
     nrm_res[t] = v;
   }
+  if constexpr (SA) __syncthreads();  // every wave is done with its A tile
   for (int c = threadIdx.x; c < 4 * kMaxLd; c += kThreads) sN[c] = 0.0;
   __syncthreads();
   if (l < s) sN[w * kMaxLd + l] = nrm_a;
@@ -881,18 +903,28 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
     const size_t lds_st = lds_m + (size_t)4 * 16 * g.ld * g.xbytes;
     const bool stage = lds_st <= 64 * 1024 && (g.ld * g.xbytes) % 16 == 0 &&
                        reinterpret_cast<uintptr_t>(X0) % 16 == 0;
+    const size_t lds_sa =
+        ((size_t)s4 * r16 + std::max((size_t)4 * kMaxLd, (size_t)4 * 16 * (lda + 1))) *
+            sizeof(double) +
+        (size_t)4 * 16 * g.ld * g.xbytes;
+    const bool stage_a = stage && s > 0 && lds_sa <= 64 * 1024 && lda % 2 == 0 &&
+                         reinterpret_cast<uintptr_t>(A) % 16 == 0;
+    const int mode = stage_a ? 2 : (stage ? 1 : 0);
     if (s <= kMfmaMaxCols && r <= 256 && lds_m <= 64 * 1024) {
       // residual column tiles held per lane: 4, 8 or 16
       const int nt = (int)(r16 / 16);
       auto go = [&](auto xt_tag, auto nt_tag) {
         using XTT = decltype(xt_tag);
         constexpr int NT = decltype(nt_tag)::value;
-        auto fn = Gm.mask ? (stage ? k_project_mfma<XTT, NT, true, true>
-                                   : k_project_mfma<XTT, NT, true, false>)
-                          : (stage ? k_project_mfma<XTT, NT, false, true>
-                                   : k_project_mfma<XTT, NT, false, false>);
-        hipLaunchKernelGGL(fn, dim3(g.nblk), dim3(kThreads), stage ? lds_st : lds_m, st, g.n, g.rpb,
-                           A, lda, s,
+        auto pick = [&](auto mask_tag) {
+          constexpr bool MK = decltype(mask_tag)::value;
+          return mode == 2 ? k_project_mfma<XTT, NT, MK, 2>
+                           : (mode == 1 ? k_project_mfma<XTT, NT, MK, 1>
+                                        : k_project_mfma<XTT, NT, MK, 0>);
+        };
+        auto fn = Gm.mask ? pick(std::true_type{}) : pick(std::false_type{});
+        const size_t lds = mode == 2 ? lds_sa : (mode == 1 ? lds_st : lds_m);
+        hipLaunchKernelGGL(fn, dim3(g.nblk), dim3(kThreads), lds, st, g.n, g.rpb, A, lda, s,
                            Gm.dense, Gm.ld, Gm.mask, Gm.nw, r, P, static_cast<XTT*>(X0), g.ld,
                            part, oscale);
       };
