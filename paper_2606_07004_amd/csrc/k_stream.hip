@@ -484,13 +484,17 @@ __device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int l
     okc[c] = cv < ncolv;
     colc[c] = cv * VEC;
   }
-  double nacc[C][VEC], gacc[V1 ? C : 1][VEC], sacc[SYM ? C : 1][VEC];
+  // V1: v1^T w (the new vector) and v1^T x_{nv-1} (the newest input vector)
+  double nacc[C][VEC], gacc[V1 ? C : 1][VEC], hacc[V1 ? C : 1][VEC], sacc[SYM ? C : 1][VEC];
 #pragma unroll
   for (int c = 0; c < C; ++c)
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
       nacc[c][e] = 0.0;
-      if constexpr (V1) gacc[c][e] = 0.0;
+      if constexpr (V1) {
+        gacc[c][e] = 0.0;
+        hacc[c][e] = 0.0;
+      }
       if constexpr (SYM) sacc[c][e] = 0.0;
     }
   const int nn = (int)n;  // n < 2^31
@@ -507,6 +511,8 @@ __device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int l
         U wd[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) wd[e] = U(w.v[e]);
+        V16<XT> x1;
+        if constexpr (V1) x1.load(v1 + (size_t)row * ld + colc[c]);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
           if (v < nv) {
@@ -519,6 +525,13 @@ __device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int l
             const U* cfv = cf + v * ld + colc[c];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) wd[e] = fma(-cfv[e], U(x.v[e]), wd[e]);
+            if constexpr (V1) {
+              if (v == nv - 1 && want_norm) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                  hacc[c][e] = fma(double(U(x1.v[e])), double(U(x.v[e])), hacc[c][e]);
+              }
+            }
           }
         V16<XT> o;
 #pragma unroll
@@ -536,8 +549,6 @@ __device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int l
               sacc[c][e] = fma(double(U(w.v[e])), od[e], sacc[c][e]);
           }
           if constexpr (V1) {
-            V16<XT> x1;
-            x1.load(v1 + (size_t)row * ld + colc[c]);
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
               gacc[c][e] = fma(double(U(x1.v[e])), od[e], gacc[c][e]);
@@ -549,8 +560,12 @@ __device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int l
     block_partials<C, VEC>(nacc, red, rm, ld, nullptr, part, 0, bk, nbk);
     if constexpr (V1) {
       block_partials<C, VEC>(gacc, red, rm, ld, v1mult, part, (size_t)ld, bk, nbk);
+      block_partials<C, VEC>(hacc, red, rm, ld, v1mult, part, (size_t)3 * ld, bk, nbk);
     } else {
-      for (int i = threadIdx.x; i < ld; i += kThreads) part[((size_t)ld + i) * nbk + bk] = 0.0;
+      for (int i = threadIdx.x; i < ld; i += kThreads) {
+        part[((size_t)ld + i) * nbk + bk] = 0.0;
+        part[((size_t)3 * ld + i) * nbk + bk] = 0.0;
+      }
     }
     if constexpr (SYM) block_partials<C, VEC>(sacc, red, rm, ld, nullptr, part, (size_t)2 * ld, bk, nbk);
   }
@@ -652,6 +667,7 @@ __global__ __launch_bounds__(kThreads) void k_step_finish(BatchArgs<FinDesc> bt)
   int* __restrict__ flags = q.flags;
   const double nrm2 = row_sum(part + (size_t)p * nblk, nblk, lane);
   const double gdot = g ? row_sum(part + (size_t)(ld + p) * nblk, nblk, lane) : 0.0;
+  const double gin = (g && q.gin_mult) ? row_sum(part + (size_t)(3 * ld + p) * nblk, nblk, lane) : 0.0;
   const double sdot = sym_row >= 0 ? row_sum(part + (size_t)(2 * ld + p) * nblk, nblk, lane) : 0.0;
   if (lane != 0) return;
   // the window inner products of this step are read below before d[sym_row]
@@ -662,6 +678,8 @@ __global__ __launch_bounds__(kThreads) void k_step_finish(BatchArgs<FinDesc> bt)
     if (dsym) *dsym = 0.0;
     return;
   }
+  // v1^T v_t of this step's input vector (needed even if the step breaks down)
+  if (g && q.gin_mult) g[(size_t)p * (m + 1) + t] = gin * q.gin_mult[p];
   double* Hp = H + (size_t)p * (m + 1) * m;
   bool finite = true;
   // the product output, and with it every window inner product and the new
@@ -1466,6 +1484,7 @@ hipError_t launch_step_finish_batch(hipStream_t st, const FinishItem* items, int
       d.mult_next = it.mult_next;
       d.g = it.g;
       d.flags = it.flags;
+      d.gin_mult = it.gin_mult;
       d.tol = it.tol;
       d.B = it.B;
       d.ld = it.ld;
@@ -1490,9 +1509,9 @@ hipError_t launch_step_finish_batch(hipStream_t st, const FinishItem* items, int
 hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, double* d, int j0,
                               int nv, const double* part, int nblk, double tol, double* H,
                               int* meff, int* active, double* mult_next, double* g, int* flags,
-                              int sym_row, double inv_s) {
+                              int sym_row, double inv_s, const double* gin_mult) {
   const FinishItem it{B,     ld,   t,    m,      d,         j0, nv,    part,    nblk,
-                      tol,   H,    meff, active, mult_next, g,  flags, sym_row, inv_s};
+                      tol,   H,    meff, active, mult_next, g,  flags, sym_row, inv_s, gin_mult};
   return launch_step_finish_batch(st, &it, 1);
 }
 

@@ -102,6 +102,7 @@ struct FinDesc {
   double* mult_next;
   double* g;
   int* flags;
+  const double* gin_mult;  // non-null: also g[t] from part[3]
   double tol;
   double inv_s;  // 1 / the power-of-two scale the product output is stored at
   int B, ld, t, m, j0, nv, nblk, sym_row;
@@ -154,8 +155,10 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
 
 // w[row][col] -= sum_v d[voff+v][col] * mult_v[col] * x_v[row][col] (nv <= 4); when
 // want_norm: part[0][col][block] = sum w^2, part[1][col][block] = v1mult[col] *
-// sum v1[row][col] w[row][col] (zero when v1 is null) and, with sym,
-// part[2][col][block] = sum w_in[row][col] w[row][col] (w_in: W before the update).
+// sum v1[row][col] w[row][col] and part[3][col][block] = v1mult[col] * sum
+// v1[row][col] x_{nv-1}[row][col] (the newest input vector; both zero when v1
+// is null) and, with sym, part[2][col][block] = sum w_in[row][col]
+// w[row][col] (w_in: W before the update).
 hipError_t launch_update(hipStream_t st, const Geom& g, void* W, const VecSet& vs, int nv,
                          const double* d, int voff, int want_norm, const void* v1,
                          const double* v1mult, bool sym, double* part, int* nblk_out);
@@ -214,6 +217,9 @@ struct FinishItem {
   int* flags;
   int sym_row;
   double inv_s;
+  // with g: g[t] = (reduced part[3]) * gin_mult[p] as well (the v1 dot of the
+  // step's input vector), also on a breakdown step
+  const double* gin_mult = nullptr;
 };
 hipError_t launch_spmm_batch(hipStream_t st, SpmmItem* items, int count);
 hipError_t launch_update_batch(hipStream_t st, UpdateItem* items, int count);
@@ -233,10 +239,12 @@ hipError_t launch_start_finish(hipStream_t st, int B, int ld, const double* part
 // With sym_row >= 0 it also reduces part[2] and stores, per probe, the inner
 // product of the new vector with the product it came from (sum / ||w||) in
 // d[sym_row][p], where the next step's window inner products are read.
+// With g it stores g[p][t+1] = v1^T v_{t+1} from part[1] and, when gin_mult
+// is given, g[p][t] = v1^T v_t from part[3] times gin_mult (mult_t).
 hipError_t launch_step_finish(hipStream_t st, int B, int ld, int t, int m, double* d, int j0,
                               int nv, const double* part, int nblk, double tol, double* H,
                               int* meff, int* active, double* mult_next, double* g, int* flags,
-                              int sym_row, double inv_s);
+                              int sym_row, double inv_s, const double* gin_mult = nullptr);
 
 // Gauss quadrature of log on each probe's T (diag h_tt, subdiag h_t+1,t).
 // (need: when non-null, only runs with need[p] != 0 are evaluated.)

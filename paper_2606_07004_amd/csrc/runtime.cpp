@@ -633,6 +633,11 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
   // the update pass hands the next step its second-newest inner product when
   // it runs as one launch and the window holds two vectors or more
   const bool sym_out = k_ >= 2 && nv <= 4 && t + 1 < m_;
+  // OSA-IOP estimate runs keep g_t = v1^T v_t.  v1 is read on odd steps only,
+  // which form v1^T v_{t+1} (the new vector) and v1^T v_t (the step's input):
+  // after any step t every g_0 .. g_t is known (g_0 = 1), which is all a run
+  // that stops at that step (breakdown, adaptive test) uses.
+  const bool v1step = kpin_ && (t & 1);
   const int nv_next = (t + 1) - std::max(0, t + 2 - k_) + 1;
   const bool check = adaptive() && (t + 1) % adapt_every_ == 0 && t + 1 < m_;
   if (plan) {
@@ -668,13 +673,14 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
       up.d = dwin_;
       up.voff = 0;
       up.want_norm = 1;
-      up.v1 = kpin_ ? slot_ptr(0) : nullptr;
-      up.v1mult = kpin_ ? mult_ptr(0) : nullptr;
+      up.v1 = v1step ? slot_ptr(0) : nullptr;
+      up.v1mult = v1step ? mult_ptr(0) : nullptr;
       up.sym = sym_out;
       up.part = part_;
       plan->fin = FinishItem{kB_, kld_, t, m_, dwin_, j0, nv, part_, 0, tol_, H_, meff_, active_,
-                             mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_,
-                             sym_out ? nv_next - 2 : -1, 1.0 / vscale_};
+                             mult_ptr(t + 1), v1step ? gq_ : nullptr, flags_,
+                             sym_out ? nv_next - 2 : -1, 1.0 / vscale_,
+                             v1step ? mult_ptr(t) : nullptr};
       sym_ready_ = sym_out;
       return LD_OK;
     }
@@ -706,16 +712,17 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
       vs.mult[v] = mult_ptr(j0 + c0 + v);
     }
     const bool last = c0 + nc >= nv;
-    LD_LAUNCH(LD_PROF_UPDATE, (double)(nc + 2 + ((last && kpin_) ? 1 : 0)) * vec_bytes,
+    LD_LAUNCH(LD_PROF_UPDATE, (double)(nc + 2 + ((last && v1step) ? 1 : 0)) * vec_bytes,
               launch_update(st, kgu_, W, vs, nc, dwin_, c0, last ? 1 : 0,
-                            (last && kpin_) ? slot_ptr(0) : nullptr,
-                            (last && kpin_) ? mult_ptr(0) : nullptr, last && sym_out, part_, &nb));
+                            (last && v1step) ? slot_ptr(0) : nullptr,
+                            (last && v1step) ? mult_ptr(0) : nullptr, last && sym_out, part_, &nb));
   }
   sym_ready_ = sym_out;
   LD_LAUNCH(LD_PROF_SMALL, (double)nb * 2 * kld_ * 8,
             launch_step_finish(st, kB_, kld_, t, m_, dwin_, j0, nv, part_, nb, tol_, H_,
-                               meff_, active_, mult_ptr(t + 1), kpin_ ? gq_ : nullptr, flags_,
-                               sym_out ? nv_next - 2 : -1, 1.0 / vscale_));
+                               meff_, active_, mult_ptr(t + 1), v1step ? gq_ : nullptr, flags_,
+                               sym_out ? nv_next - 2 : -1, 1.0 / vscale_,
+                               v1step ? mult_ptr(t) : nullptr));
   if (check) {
     // adaptive Krylov dimension: runs whose quadrature value settled stop;
     // the count of runs still going comes back to the host for the early exit
