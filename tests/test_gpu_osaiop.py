@@ -105,3 +105,20 @@ def test_osa_iop_sketch_basis_matches(L, ctx):
 def test_osa_iop_mixed(L, ctx):
     a = W.lap3d(18, 1e-2)
     _check(L, ctx, a, 18, 6, 20, 2, 1, prec=L.LD_PREC_MIXED, vt=L.LD_VT_FP32, rtol=1e-4)
+
+
+@pytest.mark.parametrize("nvals,m", [(5, 9), (6, 9), (5, 10), (6, 10)])
+def test_osa_iop_breakdown_step_parity(L, ctx, nvals, m):
+    # v1 is read on alternate steps only: runs that break down after an odd
+    # or an even number of steps must still have every g_t they use (per-run
+    # quadratic forms against the oracle)
+    d = np.repeat(np.geomspace(0.3, 5.0, nvals), 8)
+    a = W.diag_matrix(d)
+    ref, res, det = _check(L, ctx, a, 9, 3, m, 2, 3)
+    assert max(det["probe_steps"]) <= nvals and res.n_breakdowns >= 1
+
+
+@pytest.mark.parametrize("m,k", [(7, 2), (8, 2), (7, 4), (8, 4)])
+def test_osa_iop_step_count_parity(L, ctx, m, k):
+    # an odd or even number of steps (the last step reads v1 or not)
+    _check(L, ctx, W.lap2d(24, 0.2), 12, 4, m, k, 11)
