@@ -1362,6 +1362,7 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
     if (m->ci) (void)hipFree(m->ci);
     if (m->v64) (void)hipFree(m->v64);
     if (m->vlo) (void)hipFree(m->vlo);
+    if (m->gpart) (void)hipFree(m->gpart);
   };
   hipError_t e = hipMalloc(&m->rp, (size_t)(n + 1) * 4);
   if (e == hipSuccess) e = hipMalloc(&m->ci, (size_t)nnz * 4);
@@ -1411,15 +1412,15 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
   if (e == hipSuccess && lo_bytes > 0)
     e = upload(m->vlo, lo_host.data(), lo_bytes);
   // Gershgorin interval (Section 2.1), on the device
-  double* part = nullptr;
   const int nb = (int)((n + kThreads - 1) / kThreads);
-  if (e == hipSuccess) e = hipMalloc(&part, (size_t)nb * 2 * 8);
+  if (e == hipSuccess) e = hipMalloc(&m->gpart, (size_t)nb * 2 * 8);
   int nparts = 0;
-  if (e == hipSuccess) e = launch_gershgorin(ctx->stream, n, m->rp, m->ci, m->v64, part, &nparts);
+  if (e == hipSuccess)
+    e = launch_gershgorin(ctx->stream, n, m->rp, m->ci, m->v64, m->gpart, &nparts);
   std::vector<double> hp((size_t)nb * 2);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hp.data(), m->gpart, hp.size() * 8, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e == hipSuccess) e = hipMemcpy(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost);
-  if (part) (void)hipFree(part);
   if (e != hipSuccess) {
     cleanup();
     return set_error(LD_E_DEVICE, std::string("matrix upload: ") + hipGetErrorString(e));
@@ -1454,6 +1455,7 @@ ld_status ld_destroy(ld_matrix* a) {
   if (a->ci) (void)hipFree(a->ci);
   if (a->v64) (void)hipFree(a->v64);
   if (a->vlo) (void)hipFree(a->vlo);
+  if (a->gpart) (void)hipFree(a->gpart);
   a->ctx->n_matrices.fetch_sub(1);
   delete a;
   return LD_OK;

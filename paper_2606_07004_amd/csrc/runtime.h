@@ -103,6 +103,10 @@ struct ld_matrix {
   int vt_lo = 1;            // storage type of vlo (VT_F32 or VT_BF16)
   int vt = 0;               // requested ld_value_type
   double glo = 0, ghi = 0;  // Gershgorin bounds
+  // Gershgorin block partials, kept with the matrix: freeing device memory
+  // synchronises the device, which would make a matrix created while
+  // requests run wait for them
+  double* gpart = nullptr;
   double lo_hint = 0, hi_hint = 0;
   double lo = 0, hi = 0;    // interval used by the estimators
   size_t bytes = 0;
