@@ -1194,8 +1194,8 @@ hipError_t Stager::init() {
   return e;
 }
 
-hipError_t Stager::upload(void* dst, const void* src, size_t bytes) {
-  const char* s = static_cast<const char*>(src);
+hipError_t Stager::upload_fill(void* dst, size_t bytes,
+                               const std::function<void(char*, size_t, size_t)>& fill) {
   char* d = static_cast<char*>(dst);
   size_t i = 0;
   for (size_t off = 0; off < bytes; off += kChunk, ++i) {
@@ -1206,14 +1206,21 @@ hipError_t Stager::upload(void* dst, const void* src, size_t bytes) {
       const hipError_t e = hipEventSynchronize(ev[i & 1]);
       if (e != hipSuccess) return e;
     }
-    parallel_ranges((int64_t)len, host_threads((int64_t)len / 4), [&](int, int64_t b0, int64_t b1) {
-      std::memcpy(b + b0, s + off + b0, (size_t)(b1 - b0));
-    });
+    fill(b, off, len);
     hipError_t e = hipMemcpyAsync(d + off, b, len, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(ev[i & 1], st);
     if (e != hipSuccess) return e;
   }
   return hipStreamSynchronize(st);
+}
+
+hipError_t Stager::upload(void* dst, const void* src, size_t bytes) {
+  const char* s = static_cast<const char*>(src);
+  return upload_fill(dst, bytes, [&](char* b, size_t off, size_t len) {
+    parallel_ranges((int64_t)len, host_threads((int64_t)len / 4), [&](int, int64_t b0, int64_t b1) {
+      std::memcpy(b + b0, s + off + b0, (size_t)(b1 - b0));
+    });
+  });
 }
 
 }  // namespace ld
@@ -1379,38 +1386,57 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
                      std::string("matrix allocation: ") + hipGetErrorString(e));
   }
   m->bytes = (size_t)(n + 1) * 4 + (size_t)nnz * 12 + lo_bytes;
-  std::vector<char> lo_host(lo_bytes);
-  {
-    const int nt = host_threads(nnz);
+  // the FP32 or BF16 copy of values[k0 .. k1) into h (host threads)
+  auto convert = [&](void* h, int64_t k0, int64_t k1) {
+    const int nt = host_threads(k1 - k0);
     if (m->vt_lo == VT_BF16) {
-      uint16_t* h = reinterpret_cast<uint16_t*>(lo_host.data());
-      parallel_ranges(nnz, nt, [&](int, int64_t k0, int64_t k1) {
-        for (int64_t k = k0; k < k1; ++k) h[k] = double_to_bf16_rne(values[k]);
+      uint16_t* o = static_cast<uint16_t*>(h);
+      parallel_ranges(k1 - k0, nt, [&](int, int64_t a, int64_t b) {
+        for (int64_t k = a; k < b; ++k) o[k] = double_to_bf16_rne(values[k0 + k]);
       });
-    } else if (m->vt_lo == VT_F32) {
-      float* h = reinterpret_cast<float*>(lo_host.data());
-      parallel_ranges(nnz, nt, [&](int, int64_t k0, int64_t k1) {
-        for (int64_t k = k0; k < k1; ++k) h[k] = (float)values[k];
+    } else {
+      float* o = static_cast<float*>(h);
+      parallel_ranges(k1 - k0, nt, [&](int, int64_t a, int64_t b) {
+        for (int64_t k = a; k < b; ++k) o[k] = (float)values[k0 + k];
       });
     }
-  }
-  // large arrays go through the context's pinned staging buffers
-  auto upload = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
-    if (bytes < ((size_t)32 << 20)) return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
-    std::lock_guard<std::mutex> lk(ctx->stage_mu);
+  };
+  // large arrays go through the context's pinned staging buffers (the
+  // narrowed values are converted straight into them)
+  constexpr size_t kStageMin = (size_t)32 << 20;
+  auto stager = [&]() -> hipError_t {
     if (!ctx->stager) {
       std::unique_ptr<Stager> sg(new Stager());
       const hipError_t ei = sg->init();
       if (ei != hipSuccess) return ei;
       ctx->stager = std::move(sg);
     }
-    return ctx->stager->upload(dst, src, bytes);
+    return hipSuccess;
+  };
+  auto upload = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (bytes < kStageMin) return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    std::lock_guard<std::mutex> lk(ctx->stage_mu);
+    const hipError_t ei = stager();
+    return ei != hipSuccess ? ei : ctx->stager->upload(dst, src, bytes);
   };
   e = upload(m->rp, row_ptr, (size_t)(n + 1) * 4);
   if (e == hipSuccess) e = upload(m->ci, col_idx, (size_t)nnz * 4);
   if (e == hipSuccess) e = upload(m->v64, values, (size_t)nnz * 8);
-  if (e == hipSuccess && lo_bytes > 0)
-    e = upload(m->vlo, lo_host.data(), lo_bytes);
+  if (e == hipSuccess && lo_bytes > 0) {
+    const size_t vb = m->vt_lo == VT_BF16 ? 2 : 4;
+    if (lo_bytes < kStageMin) {
+      std::vector<char> lo_host(lo_bytes);
+      convert(lo_host.data(), 0, nnz);
+      e = hipMemcpy(m->vlo, lo_host.data(), lo_bytes, hipMemcpyHostToDevice);
+    } else {
+      std::lock_guard<std::mutex> lk(ctx->stage_mu);
+      e = stager();
+      if (e == hipSuccess)
+        e = ctx->stager->upload_fill(m->vlo, lo_bytes, [&](char* b, size_t off, size_t len) {
+          convert(b, (int64_t)(off / vb), (int64_t)((off + len) / vb));
+        });
+    }
+  }
   // Gershgorin interval (Section 2.1), on the device
   const int nb = (int)((n + kThreads - 1) / kThreads);
   if (e == hipSuccess) e = hipMalloc(&m->gpart, (size_t)nb * 2 * 8);

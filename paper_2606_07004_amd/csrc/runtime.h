@@ -10,6 +10,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -45,6 +46,10 @@ struct Stager {
   ~Stager();
   hipError_t init();
   hipError_t upload(void* dst, const void* src, size_t bytes);
+  // bytes of device data produced on the host chunk by chunk: fill(buf, off,
+  // len) writes bytes off .. off+len-1 into the pinned buffer buf
+  hipError_t upload_fill(void* dst, size_t bytes,
+                         const std::function<void(char*, size_t, size_t)>& fill);
 };
 
 // Event-bracketed launch timing per kernel family (see ld_profile_enable).
