@@ -110,16 +110,26 @@ void Server::loop() {
         cv_work_.wait(lk, [&] { return stop_ || !queue_.empty(); });
         if (stop_ && queue_.empty()) return;
       }
-      for (Slot& s : slots_) {
-        if (s.req || queue_.empty()) continue;
-        for (auto it = queue_.begin(); it != queue_.end(); ++it) {
-          if (used_ + (*it)->bytes <= budget_) {
-            s.req = std::move(*it);
-            queue_.erase(it);
-            used_ += s.req->bytes;
-            break;
-          }
+      // each admitted request takes the free slot with the smallest buffer
+      // that already fits it, else the free slot with the largest buffer (to
+      // grow), so slot buffers are rarely reallocated
+      for (auto it = queue_.begin(); it != queue_.end();) {
+        if (used_ + (*it)->bytes > budget_) {
+          ++it;
+          continue;
         }
+        Slot* fit = nullptr;
+        Slot* big = nullptr;
+        for (Slot& s : slots_) {
+          if (s.req) continue;
+          if (s.mem_bytes >= (*it)->bytes && (!fit || s.mem_bytes < fit->mem_bytes)) fit = &s;
+          if (!big || s.mem_bytes > big->mem_bytes) big = &s;
+        }
+        Slot* s = fit ? fit : big;
+        if (!s) break;  // no free slot
+        s->req = std::move(*it);
+        it = queue_.erase(it);
+        used_ += s->req->bytes;
       }
       int act = 0;
       for (Slot& s : slots_) act += s.req ? 1 : 0;
@@ -149,6 +159,7 @@ void Server::loop() {
           s.mem_bytes = 0;
         }
         if (hipMalloc(&s.mem, s.req->bytes) != hipSuccess) {
+          (void)hipGetLastError();
           s.mem = nullptr;
           finish(s, LD_E_NO_MEMORY, nullptr, "device allocation for a request failed");
           continue;
