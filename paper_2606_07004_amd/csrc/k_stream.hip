@@ -1001,9 +1001,10 @@ hipError_t launch_rademacher_mask(hipStream_t st, uint64_t seed, int64_t n, int 
   return hipGetLastError();
 }
 
-// L lanes per row (a power of two), lane l holding columns 2 l and 2 l + 1;
-// every lane of a row reads the row's (column, value) pairs (the same
-// addresses: one request per row) and the sign word of each neighbour.
+// L lanes per row (a power of two), lane l holding columns 2 l and 2 l + 1.
+// The row's lanes load L entries at a time (lane q: entry q of the round: its
+// column, value and the sign words of that column) and pass them around the
+// row by lane shuffles; every lane accumulates the entries in CSR order.
 template <typename VT>
 __global__ __launch_bounds__(kThreads) void k_spmm_signs(int64_t n, int lgL,
                                                         const int* __restrict__ rp,
@@ -1015,40 +1016,57 @@ __global__ __launch_bounds__(kThreads) void k_spmm_signs(int64_t n, int lgL,
   const int L = 1 << lgL, rpb = kThreads >> lgL;
   const int l = (int)threadIdx.x & (L - 1);
   const int c0 = 2 * l;
-  if (c0 >= ldy) return;
+  const bool outl = c0 < ldy;  // lanes past the row's columns only load and pass entries
   const int wsel = min(c0 >> 6, nw - 1), sh = c0 & 63;  // padding columns: any valid word
   const bool v0 = c0 < s, v1 = c0 + 1 < s;
-  for (int64_t row = (int64_t)blockIdx.x * rpb + ((int)threadIdx.x >> lgL); row < n;
-       row += (int64_t)gridDim.x * rpb) {
+  const int64_t nn = n;
+  // every lane of the block runs the same number of row rounds (shuffles)
+  const int64_t rounds = (nn + (int64_t)gridDim.x * rpb - 1) / ((int64_t)gridDim.x * rpb);
+  for (int64_t rr = 0; rr < rounds; ++rr) {
+    const int64_t row = (rr * gridDim.x + blockIdx.x) * rpb + ((int)threadIdx.x >> lgL);
+    const bool live = row < nn;
+    const int kb = live ? rp[row] : 0, ke = live ? rp[row + 1] : 0;
+    // the row's longest-lived count decides its rounds; rows of one wave run
+    // the wave's maximum (absent entries carry a zero coefficient)
+    int cnt = ke - kb;
+    for (int d = L; d < 64; d <<= 1) cnt = max(cnt, __shfl_xor(cnt, d, 64));
     double acc0 = 0.0, acc1 = 0.0;
-    const int kb = rp[row], ke = rp[row + 1];
-    // eight entries at a time: their (column, value) loads, then their sign
-    // words, then the FMAs in entry order
-    for (int k0 = kb; k0 < ke; k0 += 8) {
-      int cc[8];
-      double aa[8];
-      uint64_t ww[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = k0 + u;
-        cc[u] = k < ke ? ci[k] : -1;
-        aa[u] = k < ke ? value_as<VT, double>(va[k]) : 0.0;
+    for (int base = 0; base < cnt; base += L) {
+      const int k = kb + base + l;
+      const bool have = k < ke;
+      const int col = have ? ci[k] : 0;
+      const double a = have ? value_as<VT, double>(va[k]) : 0.0;
+      uint64_t w0 = 0, w1 = 0;
+      if (have) {
+        w0 = masks[(size_t)col * nw];
+        if (nw > 1) w1 = masks[(size_t)col * nw + 1];
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) ww[u] = cc[u] >= 0 ? masks[(size_t)cc[u] * nw + wsel] : 0ull;
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (cc[u] >= 0) {
-          const double x0 = v0 ? (((ww[u] >> sh) & 1ull) ? -1.0 : 1.0) : 0.0;
-          const double x1 = v1 ? (((ww[u] >> (sh + 1)) & 1ull) ? -1.0 : 1.0) : 0.0;
-          acc0 = fma(aa[u], x0, acc0);
-          acc1 = fma(aa[u], x1, acc1);
+      const int m = min(L, cnt - base);
+      for (int q = 0; q < m; ++q) {
+        const double aq = __shfl(a, q, L);
+        // entry q's sign word for this lane's columns (the owner holds both)
+        uint64_t wq = (uint64_t)(uint32_t)__shfl((int)(uint32_t)w0, q, L) |
+                      ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(w0 >> 32), q, L) << 32);
+        if (nw > 1) {
+          const uint64_t wq1 = (uint64_t)(uint32_t)__shfl((int)(uint32_t)w1, q, L) |
+                               ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(w1 >> 32), q, L) << 32);
+          if (wsel) wq = wq1;
         }
+        const bool hq = __shfl((int)have, q, L) != 0;
+        if (hq) {
+          const double x0 = v0 ? (((wq >> sh) & 1ull) ? -1.0 : 1.0) : 0.0;
+          const double x1 = v1 ? (((wq >> (sh + 1)) & 1ull) ? -1.0 : 1.0) : 0.0;
+          acc0 = fma(aq, x0, acc0);
+          acc1 = fma(aq, x1, acc1);
+        }
+      }
     }
-    double2 o;
-    o.x = acc0 * opscale;
-    o.y = acc1 * opscale;
-    *reinterpret_cast<double2*>(Y + (size_t)row * ldy + c0) = o;
+    if (live && outl) {
+      double2 o;
+      o.x = acc0 * opscale;
+      o.y = acc1 * opscale;
+      *reinterpret_cast<double2*>(Y + (size_t)row * ldy + c0) = o;
+    }
   }
 }
 
