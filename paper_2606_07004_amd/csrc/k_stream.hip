@@ -112,14 +112,38 @@ __global__ __launch_bounds__(kThreads) void k_gaussian(uint64_t seed, int64_t n,
 // With an entry split ES = 2^lgES (the product only) the L lanes of a row
 // form ES groups of Lc = L / ES column lanes; group eg takes every ES-th
 // sparse entry of the row and the groups' sums are added at the row's end.
+// The product also takes an L that is not a power of two (12 lanes for the
+// 12 chunks of 96 FP16 probes instead of 16 with 4 idle): rows never
+// straddle a wave, each wave holds 64 / L rows and its last 64 mod L lanes
+// are idle (on = false).  lb is the wave lane of the row's first lane.
 struct RowMap {
-  int lg, L, rpi, rg, gl, Lc, cl, eg;
+  int lg, L, rpi, rg, gl, Lc, cl, eg, lb;
+  bool on;
   __device__ RowMap(int lgL, int lgES = 0) : lg(lgL), L(1 << lgL), rpi(kThreads >> lgL) {
     rg = (int)threadIdx.x >> lg;
     gl = (int)threadIdx.x & (L - 1);
     Lc = L >> lgES;
     cl = gl & (Lc - 1);
     eg = lgES ? gl >> (lgL - lgES) : 0;
+    lb = ((int)threadIdx.x & 63) & ~(L - 1);
+    on = true;
+  }
+  // any 1 <= L <= 64 (no entry split unless L is a power of two)
+  __device__ static RowMap lanes(int L, int lgES) {
+    if ((L & (L - 1)) == 0) return RowMap(__builtin_ctz((unsigned)L), lgES);
+    RowMap m(0);
+    const int rpw = 64 / L, lane = (int)threadIdx.x & 63, rw = lane / L;
+    m.lg = -1;
+    m.L = L;
+    m.rpi = (kThreads / 64) * rpw;
+    m.on = rw < rpw;
+    m.rg = ((int)threadIdx.x >> 6) * rpw + (m.on ? rw : 0);
+    m.gl = lane - rw * L;
+    m.Lc = L;
+    m.cl = m.gl;
+    m.eg = 0;
+    m.lb = rw * L;
+    return m;
   }
 };
 
@@ -160,7 +184,7 @@ template <int C, int VEC>
 __device__ inline void block_partials(const double (&acc)[C][VEC], double* red, const RowMap& rm,
                                       int ld, const double* mult, double* part, size_t row0, int bk,
                                       int nbk) {
-  if (rm.eg == 0) {
+  if (rm.eg == 0 && rm.on) {
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
@@ -181,7 +205,7 @@ __device__ inline void block_partials(const double (&acc)[C][VEC], double* red, 
 // part[voff+v][col][block] = mult_v[col] * sum_rows x_v[row][col] w[row][col].
 // ---------------------------------------------------------------------------
 template <typename VT, typename XT, int C, int NF, bool SPLIT>
-__device__ inline void spmm_body(int64_t n, int lgL, int lgES_arg, const int* __restrict__ rp,
+__device__ inline void spmm_body(int64_t n, int Lr, int lgES_arg, const int* __restrict__ rp,
                                  const int* __restrict__ ci, const VT* __restrict__ va,
                                  const XT* __restrict__ X, XT* __restrict__ W, int ld, int ncolv,
                                  const double* __restrict__ xmult, double opscale, const void* const* fx,
@@ -205,7 +229,7 @@ __device__ inline void spmm_body(int64_t n, int lgL, int lgES_arg, const int* __
   // entry split only in the SPLIT instantiations (the plain path keeps its
   // registers and code)
   const int lgES = SPLIT ? lgES_arg : 0;
-  const RowMap rm(lgL, lgES);
+  const RowMap rm = RowMap::lanes(Lr, lgES);
   const int ES = 1 << lgES;
   for (int i = threadIdx.x; i < ld; i += kThreads)
     scs[i] = A(opscale * (xmult ? xmult[i] : 1.0));
@@ -217,8 +241,9 @@ __device__ inline void spmm_body(int64_t n, int lgL, int lgES_arg, const int* __
     okc[c] = cv < ncolv;
     colc[c] = cv * VEC;
     if constexpr (LDSACC) {
+      if (rm.on)
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) red[red_slot<C, VEC>(rm, c, e)] = 0.0;
+        for (int e = 0; e < VEC; ++e) red[red_slot<C, VEC>(rm, c, e)] = 0.0;
     }
   }
   __syncthreads();
@@ -234,7 +259,7 @@ __device__ inline void spmm_body(int64_t n, int lgL, int lgES_arg, const int* __
   for (int j = 0; j * nbk < nchunk; ++j) {
     const int ch = chunk_of(j, bk, nbk);
     const int row = ch * rm.rpi + rm.rg;
-    if (ch >= nchunk || row >= nn) continue;
+    if (!rm.on || ch >= nchunk || row >= nn) continue;
     A acc[C][VEC];
     V16<XT> xd[FUSED ? C : 1];
 #pragma unroll
@@ -300,17 +325,17 @@ __device__ inline void spmm_body(int64_t n, int lgL, int lgES_arg, const int* __
         if (ES == 1) {
           int j = 0;
           for (; j + 2 <= cnt; j += 2)
-            step2(__shfl(myc[u], j, rm.L), __shfl(mya[u], j, rm.L), __shfl(myc[u], j + 1, rm.L),
-                  __shfl(mya[u], j + 1, rm.L));
-          if (j < cnt) step1(__shfl(myc[u], j, rm.L), __shfl(mya[u], j, rm.L));
+            step2(__shfl(myc[u], rm.lb + j), __shfl(mya[u], rm.lb + j),
+                  __shfl(myc[u], rm.lb + j + 1), __shfl(mya[u], rm.lb + j + 1));
+          if (j < cnt) step1(__shfl(myc[u], rm.lb + j), __shfl(mya[u], rm.lb + j));
         } else {
           // entry group eg: entries eg, eg + ES, ... of the round (absent
           // ones gather the row itself with a zero coefficient)
           const int ni = (cnt + ES - 1) >> lgES;
           for (int i = 0; i < ni; i += 2) {
             const int e0 = rm.eg + (i << lgES), e1 = e0 + ES;
-            int c0 = __shfl(myc[u], e0, rm.L), c1 = __shfl(myc[u], e1, rm.L);
-            A a0 = __shfl(mya[u], e0, rm.L), a1 = __shfl(mya[u], e1, rm.L);
+            int c0 = __shfl(myc[u], rm.lb + e0), c1 = __shfl(myc[u], rm.lb + e1);
+            A a0 = __shfl(mya[u], rm.lb + e0), a1 = __shfl(mya[u], rm.lb + e1);
             if (e0 >= cnt) {
               c0 = row;
               a0 = A(0);
@@ -386,7 +411,7 @@ __global__ __launch_bounds__(kThreads, (NF == 2 || (sizeof(VT) == 8 && sizeof(XT
   int r = 0;
   while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
   const SpmmDesc& q = bt.d[r];
-  spmm_body<VT, XT, C, NF, SPLIT>(q.n, q.lgL, q.lgES, q.rp, q.ci, static_cast<const VT*>(q.va),
+  spmm_body<VT, XT, C, NF, SPLIT>(q.n, q.L, q.lgES, q.rp, q.ci, static_cast<const VT*>(q.va),
                            static_cast<const XT*>(q.X), static_cast<XT*>(q.W), q.ld, q.ncolv, q.xmult,
                            q.opscale, q.fx, q.fmult, q.voff, q.part, (int)blockIdx.x - bt.off[r],
                            bt.off[r + 1] - bt.off[r]);
@@ -866,6 +891,13 @@ static int pow2_at_least(int x) {
   return p;
 }
 
+// Rows a 256-thread block holds with L lanes per row (rows never straddle a
+// 64-lane wave).
+static int rows_per_block(int L) {
+  if (L < 1 || L > 64) return 1;
+  return (kThreads / 64) * (64 / L);
+}
+
 Geom make_geom(int64_t n, int ld, int xbytes) {
   Geom g;
   g.vec = 16 / xbytes;
@@ -905,7 +937,7 @@ Geom make_geom_lc(int64_t n, int ld, int xbytes, int L, int C) {
   g.C = C;
   g.lgL = 0;
   while (g.lgL < 7 && (1 << g.lgL) < g.L) ++g.lgL;
-  const int rpi = kThreads / (L >= 1 && L <= kThreads ? L : 1);
+  const int rpi = rows_per_block(L);
   const int64_t nchunk = (n + rpi - 1) / rpi;
   int64_t nb = nchunk;
   if (nb > kMaxBlocks) nb = kMaxBlocks;
@@ -915,12 +947,16 @@ Geom make_geom_lc(int64_t n, int ld, int xbytes, int L, int C) {
   return g;
 }
 
-static bool geom_ok(const Geom& g);
+static bool geom_ok(const Geom& g, bool any_lanes = false);
 bool geom_usable(const Geom& g) { return geom_ok(g); }
+bool geom_usable_spmm(const Geom& g) { return geom_ok(g, true); }
 
-static bool geom_ok(const Geom& g) {
+// The update and inner-product kernels take L a power of two; the product
+// any L <= 64 when it does not split entries.
+static bool geom_ok(const Geom& g, bool any_lanes) {
+  const bool lanes = (1 << g.lgL) == g.L || (any_lanes && g.lges == 0);
   return g.n > 0 && g.ld > 0 && g.ld % 4 == 0 && (g.xbytes == 8 || g.xbytes == 4 || g.xbytes == 2) &&
-         g.vec * g.ncolv == g.ld && g.L >= 1 && g.L <= 64 && (1 << g.lgL) == g.L && g.C >= 1 &&
+         g.vec * g.ncolv == g.ld && g.L >= 1 && g.L <= 64 && lanes && g.C >= 1 &&
          g.C <= kMaxC && g.lges >= 0 && g.lges <= g.lgL && g.lges <= 3 &&
          (g.lges == 0 || g.C <= 2) &&
          (g.L >> g.lges) * g.C >= g.ncolv && g.nblk >= 1 && (int64_t)g.nblk * g.rpb >= g.n;
@@ -948,7 +984,7 @@ static int resident_blocks(const void* fn) {
 // Grid of a chunk-sweeping kernel: at most one resident wave of blocks, a
 // multiple of 8 from 8 blocks up (see chunk_of).
 static int stream_grid(const Geom& g, const void* fn) {
-  const int rpi = kThreads / g.L;
+  const int rpi = rows_per_block(g.L);
   const int64_t nchunk = (g.n + rpi - 1) / rpi;
   int64_t nb = std::min<int64_t>(nchunk, resident_blocks(fn));
   if (nb >= 8) nb &= ~int64_t(7);
@@ -1166,7 +1202,7 @@ static hipError_t launch_grouped(Item* items, int count, KeyFn key, LaunchFn lau
 
 static bool spmm_item_ok(const SpmmItem& it) {
   const Geom& g = it.g;
-  if (!geom_ok(g) || g.ld > kMaxLd || !it.rp || !it.ci || !it.va || !it.X || !it.W ||
+  if (!geom_ok(g, true) || g.ld > kMaxLd || !it.rp || !it.ci || !it.va || !it.X || !it.W ||
       it.X == it.W || it.nf < 0 || it.nf > 2 || (it.nf > 0 && (!it.part || it.voff < 0)))
     return false;
   if (!(it.vt == VT_F64 || it.vt == VT_F32 || it.vt == VT_BF16)) return false;
@@ -1201,7 +1237,7 @@ static hipError_t spmm_launch(hipStream_t st, SpmmItem* items, const int* idx, i
       d.fmult[v] = v < it.nf ? it.fused.mult[v] : nullptr;
     }
     d.part = it.part;
-    d.lgL = it.g.lgL;
+    d.L = it.g.L;
     d.lgES = it.g.lges;
     d.ld = it.g.ld;
     d.ncolv = it.g.ncolv;

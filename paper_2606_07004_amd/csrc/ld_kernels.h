@@ -19,7 +19,7 @@ constexpr int kMaxLd = 256;       // probe-block row length (columns) of the Kry
 constexpr int kSoSlqMaxSketch = 48;  // So-SLQ sketch width (Jacobi eigen-solve in LDS)
 
 // Row partition of an [n][ld] probe block.  The streaming kernels sweep
-// chunks of 256/L consecutive rows, block b taking chunks b, b+nblk, ...; the
+// chunks of 4 floor(64/L) consecutive rows (256/L for a power-of-two L), block b taking chunks b, b+nblk, ...; the
 // sketch kernels give block b the rows [b*rpb, min(n, (b+1)*rpb)).  A row is
 // handled by L lanes, each touching C chunks of `vec` consecutive columns
 // (16 bytes).
@@ -32,7 +32,7 @@ struct Geom {
   int xbytes = 8;  // element size: 8 (FP64) or 4 (FP32)
   int vec = 2;
   int ncolv = 0;   // ld / vec
-  int L = 1;       // lanes per row (power of two, <= 64)
+  int L = 1;       // lanes per row (<= 64; a power of two except for the product)
   int lgL = 0;     // log2(L)
   int C = 1;       // 16-byte chunks per lane (<= 4), L * C >= ncolv
   int nblk = 0;
@@ -40,10 +40,14 @@ struct Geom {
   int lges = 0;    // product only: log2 of the entry split (L / 2^lges column lanes)
 };
 Geom make_geom(int64_t n, int ld, int xbytes);
-// The same with an explicit lanes-per-row L (power of two) and chunks per
-// lane C (an autotuned choice); geom_usable tells whether it covers ld.
+// The same with an explicit lanes-per-row L and chunks per lane C (an
+// autotuned choice); geom_usable tells whether it covers ld and suits every
+// streaming kernel (L a power of two), geom_usable_spmm whether it suits the
+// product.
 Geom make_geom_lc(int64_t n, int ld, int xbytes, int L, int C);
 bool geom_usable(const Geom& g);
+// The product's check: L need not be a power of two when lges == 0.
+bool geom_usable_spmm(const Geom& g);
 
 // ---------------------------------------------------------------------------
 // Batched per-step launches: one launch advances the same kernel for up to
@@ -72,7 +76,7 @@ struct SpmmDesc {
   const void* fx[2];
   const double* fmult[2];
   double* part;
-  int lgL, lgES, ld, ncolv, voff;
+  int L, lgES, ld, ncolv, voff;  // L lanes per row, any 1..64 (see Geom)
 };
 
 struct UpdDesc {

@@ -40,6 +40,18 @@ def _usable(ncolv):
             if lanes * ch >= ncolv]
 
 
+def _product_lanes(ncolv):
+    """Product-only geometries: L lanes per row not a power of two (a wave
+    holds floor(64 / L) rows, the rest of its lanes idle), the tight
+    L = ceil(ncolv / C) and one with a spare lane per row."""
+    out = []
+    for ch in (1, 2, 3, 4):
+        for lanes in (-(-ncolv // ch), -(-ncolv // ch) + 1):
+            if lanes <= 64 and lanes & (lanes - 1) and (lanes, ch) not in out:
+                out.append((lanes, ch))
+    return out
+
+
 def _splits(lanes, chunks=1):
     """Entry splits of the product that fit `lanes` column lanes in 64 (one or
     two chunks per lane)."""
@@ -57,6 +69,7 @@ def _sweep(L, ctx, a, npr, prec, vt, rtol_oracle, rtol_default, vec, k):
         ncolv = ((npr + 3) // 4 * 4) // vec
         geoms = _usable(ncolv)
         cases = [(lanes, ch, e) for lanes, ch in geoms for e in _splits(lanes, ch)]
+        cases += [(lanes, ch, 1) for lanes, ch in _product_lanes(ncolv)]
         for i, (lanes, ch, e) in enumerate(cases):
             # the update takes the geometries in the other order, so product
             # and update differ in most cases
@@ -131,13 +144,19 @@ def test_invalid_geometry_rejected(L, ctx):
     try:
         p = L.make_params(24, 6, 10, 2, 1)
         base = L.ld_estimate_ex(h, p).logdet
-        for bad in ((3, 4, 1), (0, 1, 1), (128, 1, 1), (4, 0, 1), (4, 5, 1), (1, 4, 1),
-                    (2, 4, 1), (16, 1, 3), (16, 1, 16), (8, 2, 2), (64, 1, 8)):
+        for bad in ((3, 3, 1), (0, 1, 1), (128, 1, 1), (4, 0, 1), (4, 5, 1), (1, 4, 1),
+                    (2, 4, 1), (16, 1, 3), (16, 1, 16), (8, 2, 2), (64, 1, 8), (11, 1, 1),
+                    (12, 1, 2), (24, 1, 2), (65, 1, 1)):
             _announce(f"ld_tune_set rejects L={bad[0]} C={bad[1]} split={bad[2]} "
                       "for 12 chunks per row")
             with pytest.raises(L.LdError) as ei:
                 L.ld_tune_set(h, p, bad[0], bad[1], 4, 3, bad[2])
             assert ei.value.status == L.LD_E_INVALID_ARG
+        # the update takes only a power-of-two L
+        _announce("ld_tune_set rejects an update with L=12 C=1")
+        with pytest.raises(L.LdError) as ei:
+            L.ld_tune_set(h, p, 12, 1, 12, 1, 1)
+        assert ei.value.status == L.LD_E_INVALID_ARG
         # nothing was stored: still the default geometry
         assert L.ld_estimate_ex(h, p).logdet == base
     finally:
