@@ -220,17 +220,16 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
 
 /* Autotuner of the Krylov-step kernels (the product Q V of a probe block,
  * and the orthogonalisation update with its fused norms).  Both sweep the
- * probe block row by row with L lanes per row (a power of two <= 64), each
- * lane holding C 16-byte chunks of the row (1 <= C <= 4, L * C chunks
- * covering the block).  The product may also split a row's sparse entries
- * over E = 1, 2, 4 or 8 lane groups (L / E column lanes each, their sums
- * added at the row's end), which shortens the per-lane chain of dependent
- * gathers on long rows (tried when rows hold 16 entries or more on average),
- * and, without a split, take an L that is not a power of two (a 64-lane
- * wave then holds floor(64 / L) rows, its remaining lanes idle).
- * ld_autotune times every such (L, C, E) with at most
- * half a row of idle chunks on this matrix, and for the product also
- * L = ceil(chunks / C) where that is not a power of two, for the probe-block shapes and
+ * probe block row by row with L <= 64 lanes per row (a 64-lane wave holds
+ * floor(64 / L) rows, any remaining lanes idle), each lane holding C
+ * 16-byte chunks of the row (1 <= C <= 4, L * C chunks covering the block).
+ * The product may also split a row's sparse entries over E = 1, 2, 4 or 8
+ * lane groups (L a power of two, L / E column lanes each, their sums added
+ * at the row's end), which shortens the per-lane chain of dependent gathers
+ * on long rows (tried when rows hold 16 entries or more on average).
+ * ld_autotune times every such (L, C, E) with L a power of two and at most
+ * half a row of idle chunks on this matrix, and L = ceil(chunks / C) where
+ * that is not a power of two, for the probe-block shapes and
  * precision that `p` implies (the estimate block and, for OSA-IOP and So-SLQ,
  * the sketch-run block), each kernel `reps` times per round over three
  * rounds, keeping the fastest per kernel.  The choice is stored in the
@@ -258,8 +257,8 @@ ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_re
  * spmm_entry_split lane groups, the update likewise (no split).  Any
  * (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8}, E <= L, C <= 2
  * when E > 1, and (L / E) * C chunks covering the block is accepted, where
- * L is a power of two for the update and for a product with E > 1;
- * anything else is LD_E_INVALID_ARG and stores nothing. */
+ * L is a power of two when E > 1; anything else is LD_E_INVALID_ARG and
+ * stores nothing. */
 ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
                       int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks);
 

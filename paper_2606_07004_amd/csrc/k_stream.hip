@@ -112,10 +112,10 @@ __global__ __launch_bounds__(kThreads) void k_gaussian(uint64_t seed, int64_t n,
 // With an entry split ES = 2^lgES (the product only) the L lanes of a row
 // form ES groups of Lc = L / ES column lanes; group eg takes every ES-th
 // sparse entry of the row and the groups' sums are added at the row's end.
-// The product also takes an L that is not a power of two (12 lanes for the
-// 12 chunks of 96 FP16 probes instead of 16 with 4 idle): rows never
-// straddle a wave, each wave holds 64 / L rows and its last 64 mod L lanes
-// are idle (on = false).  lb is the wave lane of the row's first lane.
+// Without an entry split L need not be a power of two (12 lanes for the 12
+// chunks of 96 FP16 probes instead of 16 with 4 idle): rows never straddle a
+// wave, each wave holds 64 / L rows and its last 64 mod L lanes are idle
+// (on = false).  lb is the wave lane of the row's first lane.
 struct RowMap {
   int lg, L, rpi, rg, gl, Lc, cl, eg, lb;
   bool on;
@@ -423,12 +423,12 @@ __global__ __launch_bounds__(kThreads, (NF == 2 || (sizeof(VT) == 8 && sizeof(XT
 constexpr int kDotsPerLaunch = 4;
 
 template <typename XT, int C>
-__global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int lgL, const XT* __restrict__ W,
+__global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int Lr, const XT* __restrict__ W,
                                                   int ld, int ncolv, VecSet vs, int nv, int voff,
                                                   double* __restrict__ part) {
   constexpr int VEC = V16<XT>::N;
   __shared__ double red[kThreads * VEC * C];
-  const RowMap rm(lgL);
+  const RowMap rm = RowMap::lanes(Lr, 0);
   bool okc[C];
   int colc[C];
 #pragma unroll
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int lgL, const XT*
   for (int j = 0; j * (int)gridDim.x < nchunk; ++j) {
     const int ch = chunk_of(j, (int)blockIdx.x, (int)gridDim.x);
     const int row = ch * rm.rpi + rm.rg;
-    if (ch >= nchunk || row >= nn) continue;
+    if (!rm.on || ch >= nchunk || row >= nn) continue;
 #pragma unroll
     for (int c = 0; c < C; ++c)
       if (okc[c]) {
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int lgL, const XT*
 // not have to read v_t for.  The coefficients h_v * mult_v live in LDS.
 // ---------------------------------------------------------------------------
 template <typename XT, int C, int NV, bool V1, bool SYM>
-__device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int ld, int ncolv,
+__device__ inline void update_body(int64_t n, int Lr, XT* __restrict__ W, int ld, int ncolv,
                                    const void* const* vx, const double* const* vmult, int nv,
                                    const double* __restrict__ d, int voff, int want_norm,
                                    const XT* __restrict__ v1, const double* __restrict__ v1mult,
@@ -495,7 +495,7 @@ __device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int l
   using U = typename std::conditional<std::is_same<XT, _Float16>::value, float, double>::type;
   __shared__ double red[kThreads * VEC * C];
   __shared__ U cf[NV * kMaxLd];
-  const RowMap rm(lgL);
+  const RowMap rm = RowMap::lanes(Lr, 0);
   for (int i = threadIdx.x; i < NV * ld; i += kThreads) {
     const int v = i / ld, col = i - v * ld;
     cf[i] = U(v < nv ? d[(size_t)(voff + v) * ld + col] * (vmult[v] ? vmult[v][col] : 1.0) : 0.0);
@@ -527,7 +527,7 @@ __device__ inline void update_body(int64_t n, int lgL, XT* __restrict__ W, int l
   for (int j = 0; j * nbk < nchunk; ++j) {
     const int ch = chunk_of(j, bk, nbk);
     const int row = ch * rm.rpi + rm.rg;
-    if (ch >= nchunk || row >= nn) continue;
+    if (!rm.on || ch >= nchunk || row >= nn) continue;
 #pragma unroll
     for (int c = 0; c < C; ++c)
       if (okc[c]) {
@@ -602,7 +602,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_update(BatchArgs<UpdDesc> bt) {
   int r = 0;
   while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
   const UpdDesc& q = bt.d[r];
-  update_body<XT, C, NV, V1, SYM>(q.n, q.lgL, static_cast<XT*>(q.W), q.ld, q.ncolv, q.vx, q.vmult,
+  update_body<XT, C, NV, V1, SYM>(q.n, q.L, static_cast<XT*>(q.W), q.ld, q.ncolv, q.vx, q.vmult,
                                   q.nv, q.d, q.voff, q.want_norm, static_cast<const XT*>(q.v1),
                                   q.v1mult, q.part, (int)blockIdx.x - bt.off[r],
                                   bt.off[r + 1] - bt.off[r]);
@@ -947,14 +947,12 @@ Geom make_geom_lc(int64_t n, int ld, int xbytes, int L, int C) {
   return g;
 }
 
-static bool geom_ok(const Geom& g, bool any_lanes = false);
+static bool geom_ok(const Geom& g);
 bool geom_usable(const Geom& g) { return geom_ok(g); }
-bool geom_usable_spmm(const Geom& g) { return geom_ok(g, true); }
 
-// The update and inner-product kernels take L a power of two; the product
-// any L <= 64 when it does not split entries.
-static bool geom_ok(const Geom& g, bool any_lanes) {
-  const bool lanes = (1 << g.lgL) == g.L || (any_lanes && g.lges == 0);
+// Any L <= 64 without an entry split; a power of two with one.
+static bool geom_ok(const Geom& g) {
+  const bool lanes = (1 << g.lgL) == g.L || g.lges == 0;
   return g.n > 0 && g.ld > 0 && g.ld % 4 == 0 && (g.xbytes == 8 || g.xbytes == 4 || g.xbytes == 2) &&
          g.vec * g.ncolv == g.ld && g.L >= 1 && g.L <= 64 && lanes && g.C >= 1 &&
          g.C <= kMaxC && g.lges >= 0 && g.lges <= g.lgL && g.lges <= 3 &&
@@ -1202,7 +1200,7 @@ static hipError_t launch_grouped(Item* items, int count, KeyFn key, LaunchFn lau
 
 static bool spmm_item_ok(const SpmmItem& it) {
   const Geom& g = it.g;
-  if (!geom_ok(g, true) || g.ld > kMaxLd || !it.rp || !it.ci || !it.va || !it.X || !it.W ||
+  if (!geom_ok(g) || g.ld > kMaxLd || !it.rp || !it.ci || !it.va || !it.X || !it.W ||
       it.X == it.W || it.nf < 0 || it.nf > 2 || (it.nf > 0 && (!it.part || it.voff < 0)))
     return false;
   if (!(it.vt == VT_F64 || it.vt == VT_F32 || it.vt == VT_BF16)) return false;
@@ -1337,7 +1335,7 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
       auto fn = k_dots<double, CC>;
       const int nb = stream_grid(g, (const void*)fn);
       *nblk_out = nb;
-      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL,
+      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.L,
                          static_cast<const double*>(W), g.ld, g.ncolv, vs, nv, voff, part);
     });
   } else if (g.xbytes == 4) {
@@ -1345,7 +1343,7 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
       auto fn = k_dots<float, CC>;
       const int nb = stream_grid(g, (const void*)fn);
       *nblk_out = nb;
-      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL,
+      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.L,
                          static_cast<const float*>(W), g.ld, g.ncolv, vs, nv, voff, part);
     });
   } else {
@@ -1353,7 +1351,7 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
       auto fn = k_dots<_Float16, CC>;
       const int nb = stream_grid(g, (const void*)fn);
       *nblk_out = nb;
-      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.lgL,
+      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.L,
                          static_cast<const _Float16*>(W), g.ld, g.ncolv, vs, nv, voff, part);
     });
   }
@@ -1393,7 +1391,7 @@ static hipError_t update_launch(hipStream_t st, UpdateItem* items, const int* id
     d.v1 = it.v1;
     d.v1mult = it.v1mult;
     d.part = it.part;
-    d.lgL = it.g.lgL;
+    d.L = it.g.L;
     d.ld = it.g.ld;
     d.ncolv = it.g.ncolv;
     d.nv = it.nv;

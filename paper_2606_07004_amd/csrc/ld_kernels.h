@@ -32,7 +32,7 @@ struct Geom {
   int xbytes = 8;  // element size: 8 (FP64) or 4 (FP32)
   int vec = 2;
   int ncolv = 0;   // ld / vec
-  int L = 1;       // lanes per row (<= 64; a power of two except for the product)
+  int L = 1;       // lanes per row (<= 64; a power of two with an entry split)
   int lgL = 0;     // log2(L)
   int C = 1;       // 16-byte chunks per lane (<= 4), L * C >= ncolv
   int nblk = 0;
@@ -41,13 +41,9 @@ struct Geom {
 };
 Geom make_geom(int64_t n, int ld, int xbytes);
 // The same with an explicit lanes-per-row L and chunks per lane C (an
-// autotuned choice); geom_usable tells whether it covers ld and suits every
-// streaming kernel (L a power of two), geom_usable_spmm whether it suits the
-// product.
+// autotuned choice); geom_usable tells whether it covers ld.
 Geom make_geom_lc(int64_t n, int ld, int xbytes, int L, int C);
 bool geom_usable(const Geom& g);
-// The product's check: L need not be a power of two when lges == 0.
-bool geom_usable_spmm(const Geom& g);
 
 // ---------------------------------------------------------------------------
 // Batched per-step launches: one launch advances the same kernel for up to
@@ -76,7 +72,7 @@ struct SpmmDesc {
   const void* fx[2];
   const double* fmult[2];
   double* part;
-  int L, lgES, ld, ncolv, voff;  // L lanes per row, any 1..64 (see Geom)
+  int L, lgES, ld, ncolv, voff;  // L lanes per row (see Geom)
 };
 
 struct UpdDesc {
@@ -88,7 +84,7 @@ struct UpdDesc {
   const void* v1;
   const double* v1mult;
   double* part;
-  int lgL, ld, ncolv, nv, voff, want_norm;
+  int L, ld, ncolv, nv, voff, want_norm;
 };
 
 struct RedDesc {

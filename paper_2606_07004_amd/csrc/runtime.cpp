@@ -308,7 +308,7 @@ Geom Run::krylov_geom(int ld, int which) const {
     if (it != a_->tune.end()) {
       Geom g = make_geom_lc(n_, ld, xb_, it->second.first & 0xff, it->second.second);
       g.lges = it->second.first >> 8;  // entry split of the product
-      if (which == 0 ? geom_usable_spmm(g) : geom_usable(g)) return g;
+      if (geom_usable(g)) return g;
     }
   }
   if (which == 0 && a_->nnz >= 64 * a_->n) {
@@ -330,7 +330,7 @@ Geom Run::krylov_geom(int ld, int which) const {
     // wave busy than the power of two above it (96 probes: 5 rows of 12
     // lanes per wave instead of 4 of 16 with 4 idle)
     Geom g = make_geom_lc(n_, ld, xb_, d.ncolv, 1);
-    if (geom_usable_spmm(g)) return g;
+    if (geom_usable(g)) return g;
   }
   return d;
 }
@@ -999,10 +999,10 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail, 
 // L * C chunks covering the row with at most half a row idle; the default
 // geometry first.  With split > 0 (the product) also every entry split
 // 2^e <= 8 of each pair with L 2^e <= 64 lanes per row, encoded as
-// (L 2^e) | (e << 8).  With product_lanes the product-only pairs follow:
-// L = ceil(chunks / C) where that is not a power of two.
+// (L 2^e) | (e << 8).  Then the pairs L = ceil(chunks / C) where that is
+// not a power of two (floor(64 / L) rows per wave).
 static std::vector<std::pair<int, int>> tune_candidates(int64_t n, int ld, int xbytes,
-                                                        bool split, bool product_lanes) {
+                                                        bool split) {
   const Geom d = make_geom(n, ld, xbytes);
   std::vector<std::pair<int, int>> out{{d.L, d.C}};
   for (int L = 1; L <= 64; L <<= 1)
@@ -1016,12 +1016,11 @@ static std::vector<std::pair<int, int>> tune_candidates(int64_t n, int ld, int x
         if (geom_usable(g)) out.push_back({(L << e) | (e << 8), C});
       }
     }
-  if (product_lanes)
-    for (int C = 1; C <= kMaxC; ++C) {
-      const int L = (d.ncolv + C - 1) / C;
-      if (L > 64 || (L & (L - 1)) == 0) continue;
-      if (geom_usable_spmm(make_geom_lc(n, ld, xbytes, L, C))) out.push_back({L, C});
-    }
+  for (int C = 1; C <= kMaxC; ++C) {
+    const int L = (d.ncolv + C - 1) / C;
+    if (L > 64 || (L & (L - 1)) == 0) continue;
+    if (geom_usable(make_geom_lc(n, ld, xbytes, L, C))) out.push_back({L, C});
+  }
   return out;
 }
 
@@ -1085,7 +1084,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7475u, n_, 0, ld, ld, X, xb_, ld, 0));
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7476u, n_, 0, ld, ld, V, xb_, ld, 0));
     // entry splits only pay on rows of many entries
-    const auto cand = tune_candidates(n_, ld, xb_, a_->nnz >= 16 * a_->n, true);
+    const auto cand = tune_candidates(n_, ld, xb_, a_->nnz >= 16 * a_->n);
     const int nc = (int)cand.size();
     std::vector<double> tp(nc, 1e300), tu(nc, 1e300);
     VecSet vf{};
@@ -1115,8 +1114,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
         LD_HIP(hipEventSynchronize(ev.b));
         LD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
         tp[c] = std::min(tp[c], (double)ms / reps);
-        // the update has no sparse entries to split and takes a power-of-two L
-        if (g.lges != 0 || !geom_usable(g)) continue;
+        if (g.lges != 0) continue;  // the update has no sparse entries to split
         LD_HIP(update());
         LD_HIP(hipEventRecord(ev.a, st));
         for (int i = 0; i < reps; ++i) LD_HIP(update());
@@ -1158,12 +1156,12 @@ ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int upd
   while (e < 4 && (1 << e) < spmm_split) ++e;
   Geom gp = make_geom_lc(n_, ldB_, xb_, spmm_lanes, spmm_chunks);
   gp.lges = e;
-  if ((1 << e) != spmm_split || !geom_usable_spmm(gp) ||
+  if ((1 << e) != spmm_split || !geom_usable(gp) ||
       !geom_usable(make_geom_lc(n_, ldB_, xb_, update_lanes, update_chunks)))
     return set_error(LD_E_INVALID_ARG,
-                     "lanes must be <= 64 (a power of two for the update and for a split "
-                     "product), chunks in [1, 4] and the entry split 1, 2, 4 or 8 (at most the "
-                     "lanes), the lanes per split group and the chunks covering the probe block");
+                     "lanes must be <= 64 (a power of two with an entry split), chunks in "
+                     "[1, 4] and the entry split 1, 2, 4 or 8 (at most the lanes), the lanes "
+                     "per split group and the chunks covering the probe block");
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
   std::lock_guard<std::mutex> lk(a_->tune_mu);
   a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes | (e << 8), spmm_chunks};

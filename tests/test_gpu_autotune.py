@@ -40,9 +40,9 @@ def _usable(ncolv):
             if lanes * ch >= ncolv]
 
 
-def _product_lanes(ncolv):
-    """Product-only geometries: L lanes per row not a power of two (a wave
-    holds floor(64 / L) rows, the rest of its lanes idle), the tight
+def _np2_lanes(ncolv):
+    """Geometries with L lanes per row not a power of two (a wave holds
+    floor(64 / L) rows, the rest of its lanes idle): the tight
     L = ceil(ncolv / C) and one with a spare lane per row."""
     out = []
     for ch in (1, 2, 3, 4):
@@ -67,9 +67,9 @@ def _sweep(L, ctx, a, npr, prec, vt, rtol_oracle, rtol_default, vec, k):
         base = L.ld_estimate_ex(h, p).logdet
         assert abs(base - ref.logdet) <= rtol_oracle * abs(ref.logdet)
         ncolv = ((npr + 3) // 4 * 4) // vec
-        geoms = _usable(ncolv)
-        cases = [(lanes, ch, e) for lanes, ch in geoms for e in _splits(lanes, ch)]
-        cases += [(lanes, ch, 1) for lanes, ch in _product_lanes(ncolv)]
+        geoms = _usable(ncolv) + _np2_lanes(ncolv)
+        cases = [(lanes, ch, e) for lanes, ch in geoms
+                 for e in (_splits(lanes, ch) if lanes & (lanes - 1) == 0 else [1])]
         for i, (lanes, ch, e) in enumerate(cases):
             # the update takes the geometries in the other order, so product
             # and update differ in most cases
@@ -152,10 +152,9 @@ def test_invalid_geometry_rejected(L, ctx):
             with pytest.raises(L.LdError) as ei:
                 L.ld_tune_set(h, p, bad[0], bad[1], 4, 3, bad[2])
             assert ei.value.status == L.LD_E_INVALID_ARG
-        # the update takes only a power-of-two L
-        _announce("ld_tune_set rejects an update with L=12 C=1")
+        _announce("ld_tune_set rejects an update with L=11 C=1")
         with pytest.raises(L.LdError) as ei:
-            L.ld_tune_set(h, p, 12, 1, 12, 1, 1)
+            L.ld_tune_set(h, p, 12, 1, 11, 1, 1)
         assert ei.value.status == L.LD_E_INVALID_ARG
         # nothing was stored: still the default geometry
         assert L.ld_estimate_ex(h, p).logdet == base
