@@ -404,9 +404,13 @@ __device__ inline void spmm_body(int64_t n, int Lr, int lgES_arg, const int* __r
 }
 
 // One CSR x block product per batch entry: blocks off[r] .. off[r+1]-1 of
-// the grid belong to request r (a single product is a batch of one).
+// the grid belong to request r (a single product is a batch of one).  Three
+// or more chunks per lane take 5 blocks per CU instead of 6 (their gathers
+// then fit the registers without spills to scratch).
 template <typename VT, typename XT, int C, int NF, bool SPLIT>
-__global__ __launch_bounds__(kThreads, (NF == 2 || (sizeof(VT) == 8 && sizeof(XT) < 8)) ? 4 : 6) void k_spmm(
+__global__ __launch_bounds__(kThreads, (NF == 2 || (sizeof(VT) == 8 && sizeof(XT) < 8))
+                                           ? 4
+                                           : (C >= 3 ? 5 : 6)) void k_spmm(
     BatchArgs<SpmmDesc> bt) {
   int r = 0;
   while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
@@ -596,9 +600,17 @@ __device__ inline void update_body(int64_t n, int Lr, XT* __restrict__ W, int ld
   }
 }
 
-// One update per batch entry (see k_spmm for the block ranges).
+// One update per batch entry (see k_spmm for the block ranges).  With V1 and
+// more than 8 elements per lane its four sets of FP64 column sums do not fit
+// 128 registers: 3 waves per SIMD instead of 4, 2 beyond 12 elements and 1
+// beyond 24 (no spills to scratch).
+template <typename XT, int C, int V1E = C * V16<XT>::N>
+constexpr int update_min_blocks(bool v1) {
+  return !v1 ? 4 : (V1E > 24 ? 1 : (V1E > 12 ? 2 : (V1E > 8 ? 3 : 4)));
+}
 template <typename XT, int C, int NV, bool V1, bool SYM>
-__global__ __launch_bounds__(kThreads, 4) void k_update(BatchArgs<UpdDesc> bt) {
+__global__ __launch_bounds__(kThreads, (update_min_blocks<XT, C>(V1))) void k_update(
+    BatchArgs<UpdDesc> bt) {
   int r = 0;
   while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
   const UpdDesc& q = bt.d[r];
