@@ -1123,10 +1123,14 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
         LD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
         tu[c] = std::min(tu[c], (double)ms / reps);
       }
+    // a candidate replaces the best so far only when more than 1% faster
+    // (timing noise would otherwise pick geometries at random, and the
+    // update's geometry also serves the wider OSA-IOP v1 pass, which the
+    // tuner does not time)
     int bp = 0, bu = 0;
     for (int c = 1; c < nc; ++c) {
-      if (tp[c] < tp[bp]) bp = c;
-      if (tu[c] < tu[bu]) bu = c;
+      if (tp[c] < 0.99 * tp[bp]) bp = c;
+      if (tu[c] < 0.99 * tu[bu]) bu = c;
     }
     {
       std::lock_guard<std::mutex> lk(a_->tune_mu);
