@@ -72,6 +72,19 @@ def test_half_oslq_lap3d(L, ctx, npr, s):
     np.testing.assert_allclose(det["probe_norm2"], ref.probe_norm2, rtol=1e-10)
 
 
+@pytest.mark.parametrize("npr,s,k", [(40, 8, 4), (96, 32, 3)])
+def test_half_oslq_any_lanes_wide_window(L, ctx, npr, s, k):
+    # 5 or 12 chunks per row: the FP16 product and update on L = 5 (12 rows
+    # per wave) or L = 12 lanes per row (not powers of two), with windows of
+    # 3 and 4 (two inner products fused into the product)
+    a = W.lap3d(26, 1e-2)
+    m, seed = 30, 8
+    _announce(f"half oslq {a.name} n={a.n} probes={npr} s={s} m={m} k={k}")
+    ref = oracle.oslq(a, npr, s, m, k, seed)
+    p = L.make_params(npr, s, m, k, seed, precision=L.LD_PREC_HALF)
+    _half_vs_oracle(L, ctx, a, ref, p)
+
+
 @pytest.mark.parametrize("vt_name", ["FP64", "FP32", "BF16"])
 def test_half_value_types(L, ctx, vt_name):
     a = W.er_laplacian(20000, 120000, seed=6)
