@@ -19,10 +19,10 @@ constexpr int kMaxLd = 256;       // probe-block row length (columns) of the Kry
 constexpr int kSoSlqMaxSketch = 48;  // So-SLQ sketch width (Jacobi eigen-solve in LDS)
 
 // Row partition of an [n][ld] probe block.  The streaming kernels sweep
-// chunks of 4 floor(64/L) consecutive rows (256/L for a power-of-two L), block b taking chunks b, b+nblk, ...; the
-// sketch kernels give block b the rows [b*rpb, min(n, (b+1)*rpb)).  A row is
-// handled by L lanes, each touching C chunks of `vec` consecutive columns
-// (16 bytes).
+// chunks of 4 floor(64/L) consecutive rows (256/L for a power-of-two L),
+// block b taking chunks b, b+nblk, ...; the sketch kernels give block b the
+// rows [b*rpb, min(n, (b+1)*rpb)).  A row is handled by L lanes, each
+// touching C chunks of `vec` consecutive columns (16 bytes).
 // The partition fixes the order of every reduction, so results are bitwise
 // reproducible for a given (n, ld, element size).  Per-block partial sums are
 // stored transposed: part[i * nblk + block].
