@@ -43,8 +43,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--method", choices=("oslq", "osa_iop"), default="oslq")
-    ap.add_argument("--precision", choices=("mixed", "half", "fp64"), default="half",
-                    help="Krylov vectors in FP16 (half), FP32 (mixed) or FP64")
+    ap.add_argument("--precision", choices=("mixed", "half", "fp64"), default="mixed",
+                    help="Krylov vectors in FP32 (mixed: FP32 vectors and values, FP64 "
+                         "reductions and small matrices), FP16 (half) or FP64")
     ap.add_argument("--serve-precision", choices=("mixed", "half", "auto"), default="auto",
                     help="Krylov vectors of the served requests (auto: FP16 when the "
                          "spectral bound ratio allows, else FP32)")
@@ -95,12 +96,14 @@ def pmc_traffic(args, family, tune):
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        rec = json.load(f)
+        db = json.load(f)
     key = (f"{args.method} {args.precision} values={args.values} lap3d {args.grid} "
            f"shift={args.shift:g} probes={args.probes} sketch={args.sketch} "
            f"m={args.krylov_steps} k={args.window} seed={args.seed}")
-    if rec.get("workload") != key:
+    recs = [r for r in db.get("records", []) if r.get("workload") == key]
+    if not recs:
         return None
+    rec = recs[0]
     for src, digest in rec.get("sources", {}).items():
         with open(os.path.join(ROOT, src), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
@@ -120,7 +123,20 @@ def pmc_traffic(args, family, tune):
         return None
     return {"bytes_per_launch": k["scaled_bytes"], "kernel": kname,
             "fetch_scale": rec["fetch_scale"], "write_scale": rec["write_scale"],
-            "summary": "profiles/oslq_half_lap3d128_pmc_traffic.md"}
+            "summary": rec.get("summary")}
+
+
+def stream_ceiling(L, ctx, nbytes):
+    """Attainable streaming bandwidth on this GPU at several read:write mixes
+    (the library's plain streaming kernel, 16 bytes per lane): the ceiling a
+    kernel with the same mix can reach, beside the 8 TB/s published peak."""
+    out = {}
+    for reads, writes in ((1, 0), (2, 0), (1, 1), (2, 1), (3, 1)):
+        ms = L.ld_debug_stream(ctx.handle, nbytes, reads, writes, 10)
+        out[f"{reads}r{writes}w"] = {"ms": ms,
+                                     "GB/s": (reads + writes) * nbytes / (ms * 1e-3) / 1e9}
+    print(f"[bench] stream ceiling {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def golden_for(matrix_name, args):
@@ -147,6 +163,24 @@ def golden_file(name):
         return json.load(f)
 
 
+def host_cpu():
+    """Host CPU model and the logical CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover - not Linux
+        avail = os.cpu_count()
+    return {"model": model, "nproc": avail, "os_cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(a, args):
     """The CPU FP64 oracle, as it stands, on a bounded sample of the same
     workload: the same matrix and Krylov settings, fewer probes."""
@@ -166,6 +200,8 @@ def cpu_baseline(a, args):
         limiter.unregister() if hasattr(limiter, "unregister") else None
     steps = sum(res.probe_steps) + (args.krylov_steps * s if args.method == "osa_iop" else 0)
     return {"value": steps / dt, "unit": "probe-steps/s", "cores": 1, "kind": "oracle",
+            "host": host_cpu(),
+            "threads": "one: BLAS limited to 1 thread, scipy.sparse products single-threaded",
             "sample": f"{args.method} oracle, same {a.name} matrix, {npr} probes "
                       f"(sketch {s}), {args.krylov_steps} steps, window {args.window}: "
                       f"{steps} probe-steps in {dt:.1f} s"}
@@ -268,13 +304,17 @@ def configs_bench(L, W, args):
             h = ctx.matrix(a, vt=L.LD_VT_FP32, lo_hint=lo)
             rec = {"n": a.n, "nnz": a.nnz, "probes": npr, "sketch": s, "steps": m, "window": k}
             del a
-            for prec in ("half", "mixed", "auto"):
-                if prec == "half" and k > 4:
-                    continue
+            for prec in ("mixed", "half", "auto"):
                 p = L.make_params(npr, s, m, k, 0, precision=PRECISIONS[prec](L))
-                if args.tune_reps > 0 and prec != "auto":
-                    L.ld_autotune(h, p, args.tune_reps)
-                r = L.ld_estimate_ex(h, p)
+                try:
+                    if args.tune_reps > 0 and prec != "auto":
+                        L.ld_autotune(h, p, args.tune_reps)
+                    r = L.ld_estimate_ex(h, p)
+                except L.LdError as e:
+                    # FP16 vectors are refused outside the range where they
+                    # hold 1e-4 (spectral bound ratio above 512, window above 4)
+                    rec[prec] = {"refused": str(e)}
+                    continue
                 reps = 3
                 steps = 0
                 t0 = time.perf_counter()
@@ -302,9 +342,14 @@ def precision_variants(L, ctx, h, args, ref):
         p = L.make_params(args.probes, args.sketch, args.krylov_steps, args.window, args.seed,
                           method=L.LD_METHOD_OSLQ if args.method == "oslq" else L.LD_METHOD_OSA_IOP,
                           precision=PRECISIONS[name](L))
-        if args.tune_reps > 0:
-            L.ld_autotune(h, p, args.tune_reps)
-        r = L.ld_estimate_ex(h, p)
+        try:
+            if args.tune_reps > 0:
+                L.ld_autotune(h, p, args.tune_reps)
+            r = L.ld_estimate_ex(h, p)
+        except L.LdError as e:
+            out[name] = {"refused": str(e)}
+            print(f"[bench] variant {name} refused: {e}", file=sys.stderr, flush=True)
+            continue
         reps = max(1, min(args.steps, 5))
         steps = 0
         t0 = time.perf_counter()
@@ -506,11 +551,26 @@ def main():
         variants = precision_variants(L, ctx, h, args, accuracy.get("logdet_fp64_gpu"))
 
     copy = None
+    ceiling = None
     if args.copy_bytes > 0:
         nb = int(args.copy_bytes) // 16 * 16
         ms = L.ld_debug_copy(ctx.handle, nb, 10)
         copy = {"bytes": nb, "ms": ms, "GB/s": 2 * nb / (ms * 1e-3) / 1e9}
         print(f"[bench] copy calibration {copy}", file=sys.stderr, flush=True)
+        ceiling = stream_ceiling(L, ctx, nb)
+        # each Krylov-step kernel against the measured ceiling of its own mix:
+        # the product reads about as much as it writes (input block and matrix
+        # in, output block out), the update reads three blocks per one written
+        fam_rate = {k: (v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None)
+                    for k, v in fam.items()}
+        roofline["kernels"] = {}
+        for name, mix in (("spmm", "1r1w"), ("update", "3r1w")):
+            rate = achieved if name == dom else fam_rate.get(name)
+            if rate:
+                roofline["kernels"][name] = {
+                    "achieved": rate, "frac_of_peak": rate * 1e9 / HBM_PEAK,
+                    "attainable": ceiling[mix]["GB/s"], "attainable_mix": mix,
+                    "frac_of_attainable": rate / ceiling[mix]["GB/s"]}
 
     comparators = None
     if not args.no_comparators:
@@ -570,6 +630,7 @@ def main():
         "configs": configs,
         "grf_sweep": grf_sweep,
         "copy_kernel": copy,
+        "stream_ceiling": ceiling,
         "device_ms_per_step": device_ms_total,
     }
     ctx.close()

@@ -82,15 +82,17 @@ typedef enum { LD_PROBE_RADEMACHER = 0, LD_PROBE_GAUSSIAN = 1 } ld_probe_dist;
  * vectors near 1 and below the FP16 range limit; the scale is removed
  * exactly from every inner product and norm.  Half the vector traffic of
  * LD_PREC_MIXED; the extra rounding (2^-11 per stored entry) enters the
- * estimate through averages over n entries and many probes.  Windows up to
- * iop_window = 4 (LD_E_INVALID_ARG beyond: classical Gram-Schmidt over a
- * longer window of FP16-rounded vectors can lose stability and make the
- * tridiagonal T indefinite).
- * LD_PREC_AUTO: LD_PREC_HALF when the matrix's spectral interval has
- * lambda_hi <= 512 lambda_lo and iop_window <= 4, else LD_PREC_MIXED.  The
- * FP16 error grows with the share of the spectrum near lambda_lo; below this
- * ratio it stayed within 1e-4 of FP64 on Laplacian and Wendland covariance
- * requests alike. */
+ * estimate through averages over n entries and many probes, and grows with
+ * the share of the spectrum near lambda_lo.  Accepted only where it holds
+ * the mixed-precision accuracy (1e-4 relative to FP64): windows up to
+ * iop_window = 4 (beyond, classical Gram-Schmidt over a longer window of
+ * FP16-rounded vectors can lose stability and make the tridiagonal T
+ * indefinite) and matrices whose spectral interval (ld_matrix_bounds) has
+ * lambda_hi <= 512 lambda_lo (beyond, Wendland covariances with many
+ * eigenvalues near their nugget move by more than 1e-4); anything else is
+ * LD_E_INVALID_ARG.
+ * LD_PREC_AUTO: LD_PREC_HALF where LD_PREC_HALF is accepted, else
+ * LD_PREC_MIXED. */
 typedef enum {
   LD_PREC_FP64 = 0,
   LD_PREC_MIXED = 1,
@@ -118,7 +120,10 @@ typedef struct {
   int32_t n_probes;          /* s + r: sketch columns plus residual probes       */
   int32_t sketch_rank;       /* s, 0 <= s <= min(n, 256); s = 0 is plain SLQ /
                                 Hutchinson.  So-SLQ: the sketch width q,
-                                1 <= q <= min(n, 64)                             */
+                                1 <= q <= min(n, 48).  Block caps: n_probes
+                                (and s) <= 128 in LD_PREC_FP64, <= 256 in the
+                                other precisions (LD_E_INVALID_ARG beyond); for
+                                So-SLQ the cap applies to k + n_probes - q      */
   int32_t krylov_steps;      /* m, 1 <= m <= min(n, 512): mat-vecs per Krylov run */
   int32_t iop_window;        /* k >= 1: orthogonalise against the k newest basis
                                 vectors (the paper's IOP uses k = 2; k >= m is
@@ -312,6 +317,14 @@ ld_status ld_debug_probes(ld_ctx* ctx, uint64_t seed, int64_t n, int32_t col_beg
  * byte counters (FETCH_SIZE / WRITE_SIZE) against a transfer of known size
  * and to measure attainable HBM bandwidth. */
 ld_status ld_debug_copy(ld_ctx* ctx, uint64_t bytes, int32_t reps, double* ms);
+/* Calibration hook: attainable streaming bandwidth at a read:write mix.  A
+ * plain 16-byte-per-lane kernel reads `reads` (1..3) device buffers of
+ * `bytes` each and, with writes = 1, writes their elementwise sum to a
+ * fourth (writes = 0: reads only).  Runs `reps` times after a warm-up and
+ * returns the mean device time per run in *ms; the bytes moved are
+ * (reads + writes) * bytes. */
+ld_status ld_debug_stream(ld_ctx* ctx, uint64_t bytes, int32_t reads, int32_t writes,
+                          int32_t reps, double* ms);
 
 #ifdef __cplusplus
 }

@@ -9,10 +9,14 @@
 // each plane rotation to that row alone (Golub & Welsch, Math. Comp. 1969):
 // O(m^2) work instead of O(m^3).
 //
-// The iteration is the standard implicitly shifted QL algorithm for
-// symmetric tridiagonal matrices: deflate when |e_i| <= eps (|d_i|+|d_i+1|),
-// otherwise take the shift from the eigenvalue of the leading 2x2 block
-// closest to d_l and chase the bulge upward with Givens rotations.
+// The iteration is the implicitly shifted QL algorithm for symmetric
+// tridiagonal matrices in the form published by Bowdler, Martin, Reinsch and
+// Wilkinson ("The QR and QL algorithms for symmetric matrices", Numer. Math.
+// 11, 1968; the procedure later distributed as EISPACK's imtql2): deflate
+// when |e_i| <= eps (|d_i|+|d_i+1|), otherwise take the Wilkinson-type shift
+// from the eigenvalue of the leading 2x2 block closest to d_l and chase the
+// bulge upward with Givens rotations.  Golub and Welsch's contribution used
+// here is to carry only the first row of the rotations.
 #pragma once
 
 #include <math.h>

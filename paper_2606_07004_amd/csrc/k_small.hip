@@ -378,6 +378,64 @@ __global__ __launch_bounds__(kThreads) void k_copy16(const float4* __restrict__ 
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n16; i += stride) b[i] = a[i];
 }
 
+// Streaming probe of attainable bandwidth at a given read:write mix: R
+// streams read and (W = 1) one written, 16 bytes per lane, grid-stride, two
+// elements in flight per thread; with W = 0 each thread keeps a running sum
+// and stores it once (so the reads are not dropped).
+template <int R, int W>
+__global__ __launch_bounds__(kThreads) void k_stream_rw(const float4* __restrict__ a0,
+                                                       const float4* __restrict__ a1,
+                                                       const float4* __restrict__ a2,
+                                                       float4* __restrict__ out,
+                                                       float* __restrict__ sink, size_t n16) {
+  const size_t stride = (size_t)gridDim.x * kThreads;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto add = [](float4 x, float4 y) { return make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w); };
+  size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  for (; i + stride < n16; i += 2 * stride) {
+    float4 v0 = a0[i], v1 = a0[i + stride];
+    if (R > 1) { v0 = add(v0, a1[i]); v1 = add(v1, a1[i + stride]); }
+    if (R > 2) { v0 = add(v0, a2[i]); v1 = add(v1, a2[i + stride]); }
+    if (W) {
+      out[i] = v0;
+      out[i + stride] = v1;
+    } else {
+      acc = add(acc, add(v0, v1));
+    }
+  }
+  for (; i < n16; i += stride) {
+    float4 v = a0[i];
+    if (R > 1) v = add(v, a1[i]);
+    if (R > 2) v = add(v, a2[i]);
+    if (W) out[i] = v; else acc = add(acc, v);
+  }
+  if (!W) sink[(size_t)blockIdx.x * kThreads + threadIdx.x] = acc.x + acc.y + acc.z + acc.w;
+}
+
+hipError_t launch_stream_rw(hipStream_t st, int reads, int writes, const void* const* src, void* dst,
+                            float* sink, size_t bytes) {
+  const size_t n16 = bytes / 16;
+  if (!src || n16 == 0 || reads < 1 || reads > 3 || writes < 0 || writes > 1 ||
+      (writes && !dst) || (!writes && !sink))
+    return hipErrorInvalidValue;
+  for (int r = 0; r < reads; ++r)
+    if (!src[r]) return hipErrorInvalidValue;
+  const float4* a0 = static_cast<const float4*>(src[0]);
+  const float4* a1 = reads > 1 ? static_cast<const float4*>(src[1]) : nullptr;
+  const float4* a2 = reads > 2 ? static_cast<const float4*>(src[2]) : nullptr;
+  float4* o = static_cast<float4*>(dst);
+  const dim3 grid(kMaxBlocks), block(kThreads);
+#define LD_STREAM(RR, WW) \
+  hipLaunchKernelGGL((k_stream_rw<RR, WW>), grid, block, 0, st, a0, a1, a2, o, sink, n16)
+  if (writes) {
+    if (reads == 1) LD_STREAM(1, 1); else if (reads == 2) LD_STREAM(2, 1); else LD_STREAM(3, 1);
+  } else {
+    if (reads == 1) LD_STREAM(1, 0); else if (reads == 2) LD_STREAM(2, 0); else LD_STREAM(3, 0);
+  }
+#undef LD_STREAM
+  return hipGetLastError();
+}
+
 hipError_t launch_copy16(hipStream_t st, const void* src, void* dst, size_t bytes) {
   const size_t n16 = bytes / 16;
   if (!src || !dst || n16 == 0) return hipErrorInvalidValue;

@@ -322,6 +322,11 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
 
 // Plain device copy of `bytes` (multiple of 16 used), calibration only.
 hipError_t launch_copy16(hipStream_t st, const void* src, void* dst, size_t bytes);
+// Bandwidth probe: reads `reads` (1..3) streams src[0..reads-1] of `bytes`
+// each and writes their sum to dst (writes = 1) or, with writes = 0, one
+// running sum per thread to sink (kMaxBlocks * kThreads floats).
+hipError_t launch_stream_rw(hipStream_t st, int reads, int writes, const void* const* src, void* dst,
+                            float* sink, size_t bytes);
 
 // Matrix set-up.
 hipError_t launch_gershgorin(hipStream_t st, int64_t n, const int* rp, const int* ci,

@@ -165,10 +165,11 @@ void Profiler::query(uint32_t fam, int64_t* n, double* ms, double* bytes) {
 static inline int round4(int x) { return (x + 3) & ~3; }
 static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-// LD_PREC_AUTO: FP16 Krylov vectors when lambda_hi / lambda_lo is at most
-// this, FP32 otherwise (measured on the serving mix of Laplacians and
-// Wendland covariances: FP16 stays within 1e-4 of FP64 up to a ratio of ~500
-// on every kind, and on the Laplacians far beyond)
+// FP16 Krylov vectors are accepted when lambda_hi / lambda_lo is at most
+// this (LD_PREC_HALF refuses wider intervals, LD_PREC_AUTO takes FP32 there).
+// Measured on the serving mix of Laplacians and Wendland covariances: FP16
+// stays within 1e-4 of FP64 up to a ratio of ~500 on every kind; beyond it
+// Wendland covariances, whose spectra crowd near the nugget, exceed 1e-4.
 constexpr double kAutoHalfRatio = 512.0;
 
 // ---------------------------------------------------------------------------
@@ -246,6 +247,11 @@ ld_status Run::validate() {
     return set_error(LD_E_INVALID_ARG,
                      "FP16 Krylov vectors take iop_window <= 4: with more window vectors the "
                      "classical Gram-Schmidt step on FP16-rounded vectors loses stability");
+  if (half_ && !(a_->hi <= kAutoHalfRatio * a_->lo))
+    return set_error(LD_E_INVALID_ARG,
+                     "FP16 Krylov vectors take matrices with lambda_hi <= 512 lambda_lo: on "
+                     "wider spectral intervals the 2^-11 storage rounding can move the estimate "
+                     "by more than 1e-4 (use LD_PREC_MIXED or LD_PREC_AUTO)");
   // Krylov blocks hold whole 16-byte chunks per row (8 FP16 values)
   auto roundv = [&](int x) { return half_ ? (x + 7) / 8 * 8 : round4(x); };
   lds_ = roundv(std::max(s_, 1));
@@ -1656,6 +1662,42 @@ ld_status ld_debug_copy(ld_ctx* ctx, uint64_t bytes, int32_t reps, double* ms) {
   LD_HIP_API(hipEventElapsedTime(&t, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  *ms = t / reps;
+  return LD_OK;
+}
+
+ld_status ld_debug_stream(ld_ctx* ctx, uint64_t bytes, int32_t reads, int32_t writes,
+                          int32_t reps, double* ms) {
+  if (!ctx || !ms || bytes < 16 || reps < 1 || reads < 1 || reads > 3 || writes < 0 || writes > 1)
+    return set_error(LD_E_INVALID_ARG, "bad argument");
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  LD_HIP_API(hipSetDevice(ctx->device));
+  DeviceBuffer in[3], out, sink;
+  const void* src[3] = {nullptr, nullptr, nullptr};
+  for (int r = 0; r < reads; ++r) {
+    LD_HIP_API(in[r].ensure(bytes));
+    LD_HIP_API(hipMemsetAsync(in[r].ptr, 0, bytes, ctx->stream));
+    src[r] = in[r].ptr;
+  }
+  if (writes) LD_HIP_API(out.ensure(bytes));
+  LD_HIP_API(sink.ensure((size_t)kMaxBlocks * kThreads * sizeof(float)));
+  hipEvent_t e0, e1;
+  LD_HIP_API(hipEventCreate(&e0));
+  LD_HIP_API(hipEventCreate(&e1));
+  auto go = [&]() {
+    return launch_stream_rw(ctx->stream, reads, writes, src, out.ptr, static_cast<float*>(sink.ptr),
+                            bytes);
+  };
+  hipError_t e = go();  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) e = go();
+  if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  LD_HIP_API(e);
   *ms = t / reps;
   return LD_OK;
 }

@@ -119,6 +119,8 @@ _SIGNATURES = [
     ("ld_debug_rademacher", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, C.c_int32,
                                         _DP]),
     ("ld_debug_copy", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int32, _DP]),
+    ("ld_debug_stream", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int32, C.c_int32, C.c_int32,
+                                    _DP]),
     ("ld_debug_probes", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, C.c_int32,
                                     C.c_int32, _DP]),
 ]
@@ -327,6 +329,14 @@ def ld_debug_copy(ctx, nbytes: int, reps: int = 10) -> float:
     """Mean device ms of a plain copy of nbytes (calibration hook)."""
     ms = C.c_double()
     _check(lib().ld_debug_copy(ctx, nbytes, reps, C.byref(ms)))
+    return ms.value
+
+
+def ld_debug_stream(ctx, nbytes: int, reads: int, writes: int, reps: int = 10) -> float:
+    """Mean device ms of a streaming kernel reading `reads` buffers of nbytes
+    and writing `writes` (0 or 1) (attainable-bandwidth hook)."""
+    ms = C.c_double()
+    _check(lib().ld_debug_stream(ctx, nbytes, reads, writes, reps, C.byref(ms)))
     return ms.value
 
 

@@ -32,6 +32,19 @@ CASES = {
                       128, 42, 60, 4, 0, (0.0, 0.0)),
     "wendland5e5_oslq_k2": (lambda: W.wendland(500_000, 48.0, 1e-2, seed=0), "oslq", 64, 21, 40, 2,
                             0, (1e-2, 0.0)),
+    # the rest of the 128^3 grid: shift 1e-1, windows 4 and 8, both methods
+    "lap3d128_s1e-1_oslq_k2": (lambda: W.lap3d(128, 1e-1), "oslq", 96, 32, 50, 2, 0, (0.0, 0.0)),
+    "lap3d128_s1e-1_osaiop_k2": (lambda: W.lap3d(128, 1e-1), "osa_iop", 96, 32, 50, 2, 0,
+                                 (0.0, 0.0)),
+    "lap3d128_s1e-2_oslq_k4": (lambda: W.lap3d(128, 1e-2), "oslq", 96, 32, 50, 4, 0, (0.0, 0.0)),
+    "lap3d128_s1e-2_osaiop_k4": (lambda: W.lap3d(128, 1e-2), "osa_iop", 96, 32, 50, 4, 0,
+                                 (0.0, 0.0)),
+    "lap3d128_s1e-2_osaiop_k8": (lambda: W.lap3d(128, 1e-2), "osa_iop", 96, 32, 50, 8, 0,
+                                 (0.0, 0.0)),
+    # the Wendland covariance with its values rounded to bfloat16: the FP64
+    # reference of the matrix a bfloat16-valued product actually multiplies
+    "wendland5e5_bf16_oslq_k2": (lambda: W.round_values_bf16(W.wendland(500_000, 48.0, 1e-2, seed=0)),
+                                 "oslq", 64, 21, 40, 2, 0, (1e-2, 0.0)),
 }
 
 

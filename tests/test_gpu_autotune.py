@@ -105,14 +105,14 @@ def test_entry_split_long_rows(L, ctx):
     # Wendland rows (~60 entries): every entry split of the product, FP64 and
     # FP16 vectors, against the oracle; fused inner product from the re-read
     # diagonal block row
-    a = W.wendland(6000, 60.0, 1e-2, seed=9)
     npr, s, m, k, seed = 32, 8, 20, 2, 4
-    ref = oracle.oslq(a, npr, s, m, k, seed, lo_hint=1e-2)
-    # FP16 vectors on a Wendland matrix sit near 1e-4 from FP64 (its many
-    # eigenvalues near the nugget): checked against the unsplit FP16 run
-    for prec, vec, tol in ((L.LD_PREC_FP64, 2, 1e-6), (L.LD_PREC_HALF, 8, 1e-3)):
+    # FP16 vectors take a larger nugget (bound ratio 170; FP16 is refused on
+    # nugget 1e-2, ratio ~1700)
+    for prec, vec, tol, nug in ((L.LD_PREC_FP64, 2, 1e-6, 1e-2), (L.LD_PREC_HALF, 8, 1e-4, 0.1)):
+        a = W.wendland(6000, 60.0, nug, seed=9)
+        ref = oracle.oslq(a, npr, s, m, k, seed, lo_hint=nug)
         h = ctx.matrix(a, vt=L.LD_VT_FP32 if prec == L.LD_PREC_HALF else L.LD_VT_FP64,
-                       lo_hint=1e-2)
+                       lo_hint=nug)
         try:
             p = L.make_params(npr, s, m, k, seed, precision=prec)
             ncolv = npr // vec
@@ -235,3 +235,4 @@ def test_served_equals_alone_when_tuned(L):
         assert served == alone
     finally:
         c.close()
+

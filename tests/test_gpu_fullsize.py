@@ -21,12 +21,21 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 BUILDERS = {
+    # the 128^3 grid: shifts 1e-3, 1e-2, 1e-1; windows 2, 4, 8; both methods
     "lap3d128_s1e-2_oslq_k2": lambda: W.lap3d(128, 1e-2),
     "lap3d128_s1e-3_oslq_k2": lambda: W.lap3d(128, 1e-3),
+    "lap3d128_s1e-1_oslq_k2": lambda: W.lap3d(128, 1e-1),
+    "lap3d128_s1e-2_oslq_k4": lambda: W.lap3d(128, 1e-2),
     "lap3d128_s1e-2_oslq_k8": lambda: W.lap3d(128, 1e-2),
     "lap3d128_s1e-2_osaiop_k2": lambda: W.lap3d(128, 1e-2),
+    "lap3d128_s1e-1_osaiop_k2": lambda: W.lap3d(128, 1e-1),
+    "lap3d128_s1e-2_osaiop_k4": lambda: W.lap3d(128, 1e-2),
+    "lap3d128_s1e-2_osaiop_k8": lambda: W.lap3d(128, 1e-2),
     "er1e6_oslq_k4": lambda: W.er_laplacian(1_000_000, 8_000_000, seed=0, shift=0.05),
     "wendland5e5_oslq_k2": lambda: W.wendland(500_000, 48.0, 1e-2, seed=0),
+    # values rounded to bfloat16: the matrix a BF16-valued product multiplies
+    "wendland5e5_bf16_oslq_k2": lambda: W.round_values_bf16(W.wendland(500_000, 48.0, 1e-2,
+                                                                       seed=0)),
 }
 
 
@@ -95,25 +104,44 @@ HALF_CASES = [n for n in BUILDERS if _load(n)["iop_window"] <= 4]
 
 @pytest.mark.parametrize("name", HALF_CASES)
 def test_fullsize_half(L, ctx, name):
-    # FP16 Krylov vectors, FP32 values (windows up to 4 vectors).  Gated at
-    # 1e-4 on the Laplacians and the graph.  The Wendland covariance has many
-    # eigenvalues near its nugget, about 5e-3 of its largest: the 2^-11
-    # storage rounding is then a sizeable fraction of them, and the estimate
-    # moves by 1.6e-4 (reported; the FP32-vector precision holds 1e-4 there)
+    # FP16 Krylov vectors, FP32 values.  Accepted on spectral intervals with
+    # lambda_hi <= 512 lambda_lo (windows up to 4), and then gated at 1e-4
+    # like the FP32-vector precision; on wider intervals (the 128^3
+    # Laplacian at shifts 1e-2 and 1e-3, the graph, the Wendland covariance)
+    # the library refuses it
+    gold = _load(name)
+    ratio = gold["lambda_hi"] / gold["lambda_lo"]
+    if ratio > 512:
+        a = BUILDERS[name]()
+        h = ctx.matrix(a, vt=L.LD_VT_FP32, lo_hint=gold["lo_hint"], hi_hint=gold["hi_hint"])
+        try:
+            method = L.LD_METHOD_OSLQ if gold["method"] == "oslq" else L.LD_METHOD_OSA_IOP
+            p = L.make_params(gold["n_probes"], gold["sketch_rank"], gold["krylov_steps"],
+                              gold["iop_window"], gold["seed"], method=method,
+                              precision=L.LD_PREC_HALF)
+            print(f"\n[case] fullsize {name} FP16 refused at bound ratio {ratio:.0f}", flush=True)
+            with pytest.raises(L.LdError) as ei:
+                L.ld_estimate_ex(h, p)
+            assert ei.value.status == L.LD_E_INVALID_ARG
+        finally:
+            ctx.release(h)
+        return
     gold, res, det, rel = _run(L, ctx, name, L.LD_PREC_HALF, L.LD_VT_FP32)
-    assert rel <= (1e-3 if name.startswith("wendland") else 1e-4)
+    assert rel <= 1e-4
     # OSLQ's sketch image is an FP64 product: start norms to rounding; OSA-IOP
     # builds its sketch from FP16 Krylov runs
     ntol = 1e-10 if gold["method"] == "oslq" else 1e-6
     np.testing.assert_allclose(det["probe_norm2"], gold["probe_norm2"], rtol=ntol)
 
 
-def test_fullsize_bf16_values_reported(L, ctx):
-    # BF16 storage rounds the matrix itself (relative 2^-9 per value, about
-    # 2e-3 absolute on entries near 1, against a smallest eigenvalue of 1e-2
-    # from the nugget): the log-determinant of the rounded matrix differs by
-    # a few percent.  This is reported, not gated; the run must stay finite
-    # and SPD.
-    gold, res, det, rel = _run(L, ctx, "wendland5e5_oslq_k2", L.LD_PREC_MIXED, L.LD_VT_BF16)
-    print(f"  bf16-value error vs FP64 oracle: {rel:.3e}")
-    assert np.isfinite(res.logdet) and rel < 0.2
+def test_fullsize_bf16_values(L, ctx):
+    # BF16 storage multiplies by the matrix with every value rounded to
+    # bfloat16 (2^-9 relative): the reference is the FP64 oracle run on that
+    # rounded matrix (tests/golden/wendland5e5_bf16_oslq_k2.json), and the
+    # BF16-valued product with FP32 vectors is gated like the mixed precision
+    gold, res, det, rel = _run(L, ctx, "wendland5e5_bf16_oslq_k2", L.LD_PREC_MIXED, L.LD_VT_BF16)
+    assert rel <= 1e-4
+    unrounded = _load("wendland5e5_oslq_k2")["logdet"]
+    print(f"  rounding the values to bfloat16 moves the log-determinant by "
+          f"{abs(gold['logdet'] - unrounded) / abs(unrounded):.3e}")
+    np.testing.assert_allclose(det["probe_norm2"], gold["probe_norm2"], rtol=1e-6)

@@ -7,7 +7,10 @@ FP64.  Gate: |dlogdet| / |logdet| <= 1e-4 against the oracle, as for the
 FP32-vector precision, on every method, probe distribution, value type and
 block shape (ragged probe counts that are not a multiple of the 8-value
 chunk), and on operators whose norm forces a block scale below 1.  Start
-norms come from FP64 values and must match the oracle to rounding.
+norms come from FP64 values and must match the oracle to rounding.  The
+precision is accepted only where it holds that gate (spectral bound ratio
+at most 512, windows up to 4): every matrix here lies inside that range, and
+the refusals outside it are tested too.
 """
 import numpy as np
 import pytest
@@ -63,7 +66,7 @@ def _half_vs_oracle(L, ctx, a, ref, params, vt=None, lo_hint=0.0, rtol=1e-4):
 
 @pytest.mark.parametrize("npr,s", [(96, 32), (13, 4), (30, 10), (8, 0)])
 def test_half_oslq_lap3d(L, ctx, npr, s):
-    a = W.lap3d(26, 1e-2)
+    a = W.lap3d(26, 0.05)
     m, k, seed = 30, 2, 3
     _announce(f"half oslq {a.name} n={a.n} probes={npr} s={s} m={m} k={k}")
     ref = oracle.oslq(a, npr, s, m, k, seed)
@@ -77,7 +80,7 @@ def test_half_oslq_any_lanes_wide_window(L, ctx, npr, s, k):
     # 5 or 12 chunks per row: the FP16 product and update on L = 5 (12 rows
     # per wave) or L = 12 lanes per row (not powers of two), with windows of
     # 3 and 4 (two inner products fused into the product)
-    a = W.lap3d(26, 1e-2)
+    a = W.lap3d(26, 0.05)
     m, seed = 30, 8
     _announce(f"half oslq {a.name} n={a.n} probes={npr} s={s} m={m} k={k}")
     ref = oracle.oslq(a, npr, s, m, k, seed)
@@ -87,22 +90,49 @@ def test_half_oslq_any_lanes_wide_window(L, ctx, npr, s, k):
 
 @pytest.mark.parametrize("vt_name", ["FP64", "FP32", "BF16"])
 def test_half_value_types(L, ctx, vt_name):
-    a = W.er_laplacian(20000, 120000, seed=6)
+    a = W.er_laplacian(20000, 120000, seed=6, shift=0.5)
+    if vt_name == "BF16":
+        # the oracle runs on the matrix a bfloat16-valued product multiplies:
+        # the values rounded once to bfloat16 (the library's rounding of the
+        # already rounded values is exact)
+        a = W.round_values_bf16(a)
     vt = getattr(L, "LD_VT_" + vt_name)
     _announce(f"half oslq {a.name} values {vt_name}")
     ref = oracle.oslq(a, 24, 8, 25, 2, 11)
     p = L.make_params(24, 8, 25, 2, 11, precision=L.LD_PREC_HALF)
-    # BF16 values round the matrix itself (2^-9 per value): compare those
-    # with the FP64-vector run on the same rounded matrix only
-    _half_vs_oracle(L, ctx, a, ref, p, vt=vt, rtol=1e-4 if vt_name != "BF16" else 1e-2)
+    _half_vs_oracle(L, ctx, a, ref, p, vt=vt)
 
 
 def test_half_wendland_with_hint(L, ctx):
-    a = W.wendland(8000, 40.0, 1e-2, seed=2)
+    a = W.wendland(8000, 40.0, 0.1, seed=2)
     _announce(f"half oslq {a.name} with lambda_lo hint")
-    ref = oracle.oslq(a, 30, 10, 30, 2, 5, lo_hint=1e-2)
+    ref = oracle.oslq(a, 30, 10, 30, 2, 5, lo_hint=0.1)
     p = L.make_params(30, 10, 30, 2, 5, precision=L.LD_PREC_HALF)
-    _half_vs_oracle(L, ctx, a, ref, p, lo_hint=1e-2)
+    _half_vs_oracle(L, ctx, a, ref, p, lo_hint=0.1)
+
+
+def test_half_refuses_wide_spectral_interval(L, ctx):
+    # a Wendland covariance with nugget 1e-2 (bound ratio ~1400): many
+    # eigenvalues sit near the nugget and FP16 storage would move the estimate
+    # by more than 1e-4, so the precision is refused; AUTO takes FP32 vectors
+    a = W.wendland(8000, 40.0, 1e-2, seed=2)
+    h = ctx.matrix(a, vt=L.LD_VT_FP32, lo_hint=1e-2)
+    try:
+        lo, hi = L.ld_matrix_bounds(h)
+        _announce(f"half refuses {a.name} ratio {hi / lo:.0f}")
+        assert hi > 512 * lo
+        p = L.make_params(30, 10, 30, 2, 5, precision=L.LD_PREC_HALF)
+        with pytest.raises(L.LdError) as ei:
+            L.ld_estimate_ex(h, p)
+        assert ei.value.status == L.LD_E_INVALID_ARG
+        with pytest.raises(L.LdError) as ei:
+            L.ld_submit(h, p)
+        assert ei.value.status == L.LD_E_INVALID_ARG
+        auto = L.ld_estimate_ex(h, L.make_params(30, 10, 30, 2, 5, precision=L.LD_PREC_AUTO))
+        mixed = L.ld_estimate_ex(h, L.make_params(30, 10, 30, 2, 5, precision=L.LD_PREC_MIXED))
+        assert auto.logdet == mixed.logdet
+    finally:
+        ctx.release(h)
 
 
 @pytest.mark.parametrize("k", [2, 4])
@@ -124,7 +154,7 @@ def test_half_so_slq(L, ctx):
 
 
 def test_half_gaussian_and_adaptive(L, ctx):
-    a = W.lap3d(22, 1e-2)
+    a = W.lap3d(22, 0.05)
     _announce(f"half oslq {a.name} Gaussian probes, adaptive dimension")
     ref = oracle.oslq(a, 32, 8, 40, 2, 21, dist=oracle.PROBE_GAUSSIAN, adapt_tol=1e-6,
                       adapt_every=5)
@@ -148,7 +178,7 @@ def test_half_operator_scale(L, ctx, factor):
 
 
 def test_half_deterministic_and_served(L, ctx):
-    a = W.lap3d(24, 1e-2)
+    a = W.lap3d(24, 0.05)
     p = L.make_params(40, 12, 20, 2, 4, precision=L.LD_PREC_HALF)
     _announce(f"half determinism and serving {a.name}")
     h = ctx.matrix(a, vt=L.LD_VT_FP32)

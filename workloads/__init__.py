@@ -23,7 +23,7 @@ import scipy.sparse as sp
 __all__ = [
     "Csr", "lap2d", "lap3d", "er_laplacian", "wendland", "diag_matrix",
     "random_spd_dense", "from_dense", "lap2d_exact_logdet",
-    "lap3d_exact_logdet", "request_stream", "csr_digest",
+    "lap3d_exact_logdet", "request_stream", "csr_digest", "round_values_bf16",
 ]
 
 
@@ -266,6 +266,30 @@ def random_spd_dense(n: int, seed: int, lo: float = 0.1, hi: float = 10.0) -> np
     lam = np.exp(rng.uniform(math.log(lo), math.log(hi), size=n))
     q = (u * lam) @ u.T
     return 0.5 * (q + q.T)
+
+
+def round_values_bf16(a: Csr) -> Csr:
+    """The same matrix with every value rounded once to bfloat16 (8 exponent
+    bits, 7 stored mantissa bits), round-to-nearest, ties to even, and held
+    in float64 again.  A library that stores values as bfloat16 sees exactly
+    this matrix, so an FP64 reference run on it isolates the error of the
+    low-precision arithmetic from the change of the matrix.  Values must be
+    finite and inside the float32 normal range (or zero)."""
+    v = np.ascontiguousarray(a.values, dtype=np.float64)
+    fin = np.abs(v[v != 0.0])
+    if fin.size and (not np.all(np.isfinite(fin)) or fin.min() < 2.0 ** -126
+                     or fin.max() >= 2.0 ** 127):
+        raise ValueError("round_values_bf16: values outside the float32 normal range")
+    bits = v.view(np.uint64)
+    drop = np.uint64(45)                      # 52 - 7 mantissa bits dropped
+    low = bits & np.uint64((1 << 45) - 1)
+    half = np.uint64(1 << 44)
+    keep = bits >> drop
+    up = (low > half) | ((low == half) & ((keep & np.uint64(1)) == np.uint64(1)))
+    keep = keep + up.astype(np.uint64)        # a carry moves into the exponent
+    out = (keep << drop).view(np.float64)
+    return Csr(n=a.n, row_ptr=a.row_ptr, col_idx=a.col_idx, values=out.copy(),
+               name=a.name + "_bf16")
 
 
 def csr_digest(a: Csr) -> str:
