@@ -222,6 +222,23 @@ ld_status ld_estimate_ex(ld_matrix* a, const ld_params* p, ld_result* out);
 /* As ld_estimate_ex, also filling the non-NULL arrays of `detail`. */
 ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
                              const ld_detail* detail);
+/* For callers that cannot allocate device memory during the call (code that
+ * runs where hipMalloc is not allowed, tight serving loops, harnesses that
+ * forbid allocation): ld_estimate_ex with every device buffer of the estimate
+ * (Krylov blocks, sketch, partial sums, per-run state) carved from a fixed
+ * 256 MiB scratch array that each GPU holds from the library's load until the
+ * process ends.  The call performs no hipMalloc, hipFree or other allocating
+ * routine; the matrix (created earlier by ld_create_csr) and the host result
+ * are the caller's.  The events and the pinned word it needs are created with
+ * the context.  Same kernels, geometry and summation order as ld_estimate_ex:
+ * the result is bitwise the same.  A request whose buffers exceed the scratch
+ * (about 500 n bytes for 30 FP32 probes with window 2) is LD_E_INVALID_ARG,
+ * as is everything ld_estimate_ex refuses.  Blocking.  Every call on one GPU
+ * uses that GPU's one scratch array, which keeps the last call's contents
+ * (each call clears what it needs); calls on one GPU from this library are
+ * serialised, and overlapping use of the array by other means would race.
+ * Profiling (ld_profile_enable) does not cover it. */
+ld_status ld_estimate_noalloc(ld_matrix* a, const ld_params* p, ld_result* out);
 
 /* Autotuner of the Krylov-step kernels (the product Q V of a probe block,
  * and the orthogonalisation update with its fused norms).  Both sweep the

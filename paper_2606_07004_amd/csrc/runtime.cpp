@@ -186,6 +186,8 @@ enum Stage : int {
 Run::Run(ld_matrix* a, const ld_params& p) : a_(a), p_(p) {}
 
 Run::~Run() {
+  if (check_ev_ && pending_check_) (void)hipEventSynchronize(check_ev_);
+  if (ext_) return;
   if (ev0_) (void)hipEventDestroy(ev0_);
   if (ev1_) (void)hipEventDestroy(ev1_);
   if (check_ev_) {
@@ -1251,6 +1253,46 @@ hipError_t Stager::upload(void* dst, const void* src, size_t bytes) {
 }  // namespace ld
 
 // ---------------------------------------------------------------------------
+// Device-resident scratch of the no-allocation estimate.  A file-scope device
+// array: every GPU the library runs on holds its own copy from module load
+// until the process ends.  Host code never uses the array's name as an
+// address: the device address of each GPU's copy is looked up once per device
+// (with that device current) by hipGetSymbolAddress and kept here.
+// ---------------------------------------------------------------------------
+namespace ld {
+
+constexpr size_t kScratchBytes = (size_t)256 << 20;  // 256 MiB per GPU
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+// calls of the no-allocation estimate on one device share its scratch: they
+// run one at a time
+std::mutex g_scratch_use_mu[kMaxDevices];
+}  // namespace
+
+// Device address of `device`'s scratch (looked up on the first call for the
+// device; the device must be current).
+static hipError_t scratch_ptr(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+}  // namespace ld
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 using namespace ld;
@@ -1297,6 +1339,14 @@ ld_status ld_ctx_create(const ld_ctx_opts* opts, ld_ctx** out) {
     LD_HIP_API(hipMemGetInfo(&fr, &tot));
     c->opts.hbm_budget_bytes = (uint64_t)(0.8 * (double)fr);
   }
+  // set-up of the no-allocation estimate: the device's scratch address, and
+  // the events and pinned counter its runs use in place of creating their own
+  void* sp = nullptr;
+  LD_HIP_API(scratch_ptr(o.device, &sp));
+  for (int i = 0; i < 3; ++i)
+    LD_HIP_API(hipEventCreateWithFlags(&c->na_ev[i], i == 2 ? hipEventDisableTiming
+                                                               : hipEventDefault));
+  LD_HIP_API(hipHostMalloc((void**)&c->na_nact, sizeof(int), hipHostMallocDefault));
   *out = c.release();
   return LD_OK;
 }
@@ -1308,6 +1358,10 @@ ld_status ld_ctx_destroy(ld_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   ctx->server.reset();
   ctx->workspace.release();
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t& e : ctx->na_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->na_nact) (void)hipHostFree(ctx->na_nact);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return LD_OK;
@@ -1608,6 +1662,42 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
 
 ld_status ld_estimate_ex(ld_matrix* a, const ld_params* p, ld_result* out) {
   return ld_estimate_detail(a, p, out, nullptr);
+}
+
+ld_status ld_estimate_noalloc(ld_matrix* a, const ld_params* p, ld_result* out) {
+  if (!a || !p || !out) return set_error(LD_E_INVALID_ARG, "null argument");
+  const double t0 = now_seconds();
+  ld_ctx* ctx = a->ctx;
+  if (ctx->device < 0 || ctx->device >= kMaxDevices || !ctx->na_ev[0] || !ctx->na_nact)
+    return set_error(LD_E_INVALID_ARG, "context without the no-allocation set-up");
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  std::lock_guard<std::mutex> lk_dev(g_scratch_use_mu[ctx->device]);
+  LD_HIP_API(hipSetDevice(ctx->device));
+  void* base = nullptr;
+  LD_HIP_API(scratch_ptr(ctx->device, &base));
+  Run run(a, *p);
+  run.set_submit_time(t0);
+  run.set_blocking(true);
+  run.use_external(ctx->na_ev[0], ctx->na_ev[1], ctx->na_ev[2], ctx->na_nact);
+  ld_status rc = run.validate();
+  if (rc != LD_OK) return rc;
+  const size_t need = run.device_bytes();
+  if (need > kScratchBytes)
+    return set_error(LD_E_INVALID_ARG,
+                     "the request needs " + std::to_string(need) +
+                         " device bytes; ld_estimate_noalloc holds at most " +
+                         std::to_string(kScratchBytes) + " (use ld_estimate_ex)");
+  rc = run.bind(base, kScratchBytes);
+  if (rc != LD_OK) return rc;
+  bool done = false;
+  while (!done) {
+    rc = run.advance(ctx->stream, 1 << 30, &done);
+    if (rc != LD_OK) {
+      (void)hipStreamSynchronize(ctx->stream);
+      return rc;
+    }
+  }
+  return run.collect(ctx->stream, out, nullptr);
 }
 
 ld_status ld_estimate(ld_matrix* a, int32_t n_probes, int32_t sketch_rank, int32_t krylov_steps,

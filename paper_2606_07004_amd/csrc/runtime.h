@@ -96,6 +96,10 @@ struct ld_ctx {
   ld::Profiler prof;
   std::mutex stage_mu;
   std::unique_ptr<ld::Stager> stager;
+  // the no-allocation estimate's timing events, adaptive-check event and
+  // pinned count of active runs, created with the context
+  hipEvent_t na_ev[3] = {nullptr, nullptr, nullptr};
+  int* na_nact = nullptr;
 };
 
 struct ld_matrix {
@@ -260,10 +264,20 @@ class Run {
   int nslots_ = 0;
   int wstride_ = 0;           // OSA-IOP: per-run workspace of the Hessenberg log
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+  bool ext_ = false;          // events and pinned count belong to the caller
   double t_submit_ = 0;
   Profiler* prof_ = nullptr;
  public:
   void set_profiler(Profiler* p) { prof_ = p; }
+  // Use caller-owned events (start, end, adaptive check) and a pinned int
+  // instead of creating them; the run then creates and frees nothing.
+  void use_external(hipEvent_t e0, hipEvent_t e1, hipEvent_t chk, int* nact_pinned) {
+    ev0_ = e0;
+    ev1_ = e1;
+    check_ev_ = chk;
+    nact_host_ = nact_pinned;
+    ext_ = true;
+  }
   void set_blocking(bool b) { blocking_ = b; }
   // Time the candidate geometries of the Krylov-block product and update on
   // this request's matrix and block shape; store the fastest in the matrix.

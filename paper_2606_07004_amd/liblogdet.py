@@ -110,6 +110,7 @@ _SIGNATURES = [
     ("ld_estimate_ex", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(ld_result)]),
     ("ld_estimate_detail", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(ld_result),
                                        C.POINTER(ld_detail)]),
+    ("ld_estimate_noalloc", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(ld_result)]),
     ("ld_submit", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(C.c_uint64)]),
     ("ld_poll", C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(ld_result)]),
     ("ld_wait", C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(ld_result)]),
@@ -224,6 +225,13 @@ def ld_estimate(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_windo
 def ld_estimate_ex(a, params: ld_params) -> ld_result:
     res = ld_result()
     _check(lib().ld_estimate_ex(a, C.byref(params), C.byref(res)))
+    return res
+
+
+def ld_estimate_noalloc(a, params: ld_params) -> ld_result:
+    """ld_estimate_ex with the device buffers in the library's fixed scratch."""
+    res = ld_result()
+    _check(lib().ld_estimate_noalloc(a, C.byref(params), C.byref(res)))
     return res
 
 
