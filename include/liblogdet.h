@@ -44,7 +44,7 @@ enum {
   LD_E_BAD_CSR = -2,         /* malformed CSR structure                        */
   LD_E_NOT_SPD = -3,         /* a_ii <= 0, a non-positive Ritz value, or a
                                 Hessenberg log that is not real                */
-  LD_E_NUMERIC = -4,         /* NaN/Inf, or the sketch QR lost rank            */
+  LD_E_NUMERIC = -4,         /* NaN/Inf in a Krylov run or the sketch QR       */
   LD_E_NO_MEMORY = -5,       /* the request can never fit the HBM budget       */
   LD_E_BUSY = -6,            /* object still referenced by in-flight requests  */
   LD_E_DEVICE = -7,          /* HIP runtime error (message in ld_last_error)   */
@@ -141,7 +141,17 @@ typedef struct {
                                 0 -> every run takes krylov_steps (or stops at
                                 h < tol).  Must be 0 for OSA-IOP.                */
   int32_t adapt_every;       /* steps between convergence checks (0 -> 5)        */
-  int32_t reserved;          /* must be 0                                        */
+  int32_t sketch_passes;     /* OSA-IOP and So-SLQ sketch image Y = L S (one
+                                Alg 1 run per sketch column, y = ||s|| V_m
+                                log(H_m) e1 + ...): 0 or 1 keeps each run's
+                                basis V_m (m + 1 probe blocks of s columns);
+                                2 runs the sketch recurrences twice, the first
+                                time for H_m only, the second time adding each
+                                basis vector into Y while it is still in a ring
+                                of min(k, m) + 9 blocks (the same values and
+                                sums, bitwise: about m - 1 more sketch steps
+                                for m + 1 - (min(k, m) + 9) fewer blocks).
+                                OSLQ (whose sketch is one product): 0 or 1    */
 } ld_params;
 
 typedef struct {
@@ -159,6 +169,13 @@ typedef struct {
   int32_t n_breakdowns;      /* runs stopped early by h < tol                    */
   double device_ms;          /* device time of the estimate (HIP events)        */
   double latency_ms;         /* host wall time from call (or submit) to result  */
+  int32_t basis_rank;        /* columns of the sketch basis A kept by its QR:
+                                orth(Y) takes the columns of Y in order and
+                                drops one whose part orthogonal to those kept
+                                before it is at most 1e-6 of its norm (its run
+                                is skipped, K = 0); = sketch_rank (So-SLQ:
+                                subspace_rank) unless the sketch image is
+                                rank-deficient                                  */
 } ld_result;
 
 /* Optional per-run outputs of ld_estimate_detail.  Each pointer may be NULL;
@@ -239,6 +256,13 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
  * serialised, and overlapping use of the array by other means would race.
  * Profiling (ld_profile_enable) does not cover it. */
 ld_status ld_estimate_noalloc(ld_matrix* a, const ld_params* p, ld_result* out);
+
+/* Device bytes an estimate of `a` with parameters `p` takes beyond the
+ * matrix itself (Krylov blocks, sketch, partial sums, per-run state): the
+ * workspace ld_estimate_ex uses and the amount a served request is charged
+ * against the HBM budget.  LD_E_INVALID_ARG for parameters the estimate
+ * would refuse. */
+ld_status ld_request_bytes(ld_matrix* a, const ld_params* p, uint64_t* bytes);
 
 /* Autotuner of the Krylov-step kernels (the product Q V of a probe block,
  * and the orthogonalisation update with its fused norms).  Both sweep the

@@ -12,7 +12,13 @@ Readings of the paper used here (each also listed in the design notes):
 * the residual update of Alg 3 applies the weight once to the finished sum
   (the printed listing multiplies inside the loop), and its f(theta_k) means
   the residual run's own Ritz values;
-* QR convention: the Q-factor with a positive diagonal of R;
+* QR convention: the Q-factor with a positive diagonal of R; a sketch image
+  that is numerically rank-deficient (the paper does not say what orth()
+  returns then) keeps, in column order, the columns whose part orthogonal to
+  the columns kept before them exceeds RANK_RTOL of their norm, and the
+  basis is the Q-factor of those columns; a dropped column leaves a zero
+  column of the basis, whose run is skipped (quadratic form 0, like a
+  residual probe that projects to zero);
 * OSLQ's "Lanczos" is the windowed recurrence of Alg 1 (window k, MGS order)
   and T keeps only the diagonal and first subdiagonal of H;
 * OSA-IOP's sketch line "Y = log(L) S" is read as Y = L_c S, each column from
@@ -38,6 +44,7 @@ from .quadrature import (NotSPDError, adaptive_dimension, gauss_quadrature_log,
 from .spectral import osa_iop_shift, oslq_scaling, spectral_interval
 
 DEFAULT_TOL = 1e-10
+RANK_RTOL = 1e-6    # relative residual at or below which a sketch column is dependent
 
 
 @dataclasses.dataclass
@@ -64,13 +71,34 @@ def _as_scipy(a) -> sp.csr_matrix:
 
 
 def _orth(y: np.ndarray) -> np.ndarray:
-    """Orthonormal basis of range(Y): Q-factor of Y = QR with diag(R) > 0."""
-    if y.shape[1] == 0:
-        return np.zeros_like(y)
-    q, r = np.linalg.qr(y, mode="reduced")
-    d = np.sign(np.diag(r))
-    d[d == 0] = 1.0
-    return q * d[None, :]
+    """Orthonormal basis of range(Y) (the "orthonormal basis via QR" of Alg 2
+    and Alg 3), one column per column of Y.
+
+    Columns are taken in order; column j is kept when the part of y_j
+    orthogonal to the columns kept before it (Gram-Schmidt applied twice)
+    has norm above RANK_RTOL * ||y_j||.  The kept columns' basis is the
+    Q-factor of their QR factorisation with diag(R) > 0; a dropped column
+    gives a zero column.  For a Y of full column rank this is the Q-factor
+    of Y itself."""
+    n, s = y.shape
+    out = np.zeros_like(y)
+    kept = []
+    basis = np.zeros((n, 0))
+    for j in range(s):
+        v = y[:, j]
+        nv = float(np.linalg.norm(v))
+        w = v - basis @ (basis.T @ v)
+        w = w - basis @ (basis.T @ w)
+        nw = float(np.linalg.norm(w))
+        if nv > 0.0 and nw > RANK_RTOL * nv:
+            kept.append(j)
+            basis = np.column_stack([basis, w / nw])
+    if kept:
+        q, r = np.linalg.qr(y[:, kept], mode="reduced")
+        d = np.sign(np.diag(r))
+        d[d == 0] = 1.0
+        out[:, kept] = q * d[None, :]
+    return out
 
 
 def _split(n_probes: int, sketch_rank: int, n: int, m: int, window: int):
@@ -114,6 +142,10 @@ def oslq(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: int,
     tr_sketch = 0.0
     for i in range(s):
         qi = basis[:, i]
+        if not np.any(qi):  # a column dropped by orth(): no run
+            ks.append(0.0); norms.append(0.0); steps.append(0)
+            alphas.append(np.zeros(0)); betas.append(np.zeros(0))
+            continue
         kval, m_eff, al, be = quad(qi)
         tr_sketch += kval
         ks.append(kval); norms.append(float(qi @ qi)); steps.append(m_eff)
@@ -179,6 +211,10 @@ def osa_iop(a, n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: i
     tr_sketch = 0.0
     for i in range(s):
         ai = basis[:, i]
+        if not np.any(ai):  # a column dropped by orth(): no run
+            ks.append(0.0); norms.append(0.0); steps.append(0)
+            alphas.append(np.zeros(0)); betas.append(np.zeros(0))
+            continue
         yi, m_eff, h, _ = _iop_log_action(q, ai, gamma, c, krylov_steps, iop_window, tol)
         val = float(ai @ yi)
         nrm = float(ai @ ai)

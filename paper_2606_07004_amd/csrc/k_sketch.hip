@@ -57,6 +57,18 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn(int64_t n, int rpb, const 
 // Gram diagonal (the sketch image has numerically lost rank).
 // R and Rinv may live in global memory or in LDS (small s): the same
 // operations in the same order either way.
+// Cholesky factor R of the Gram matrix G = Y^T Y and the inverse of R, with
+// columns that are numerically dependent on earlier ones dropped: at step k
+// the pivot (in exact arithmetic the squared norm of the part of column k
+// orthogonal to the columns kept before it) is compared with the column's
+// squared norm G_kk; at or below kRankRtol^2 G_kk (or G_kk = 0) the column
+// is dropped: its row of R is zero (so it updates nothing after it) and its
+// row and column of the inverse are zero, so Y R^{-1} keeps an orthonormal
+// basis of range(Y) in the kept columns, in column order, and zero columns
+// in the dropped ones.  A full-rank Y drops nothing.  flag = 1 only for a
+// non-finite pivot.
+constexpr double kRankRtol = 1e-6;
+
 __device__ inline void chol_inv_body(int s, const double* __restrict__ G, double* __restrict__ R,
                                      double* __restrict__ Rinv, int* __restrict__ flag,
                                      double& piv, int& bad, double* gdiag) {
@@ -69,12 +81,19 @@ __device__ inline void chol_inv_body(int s, const double* __restrict__ G, double
   for (int k = 0; k < s; ++k) {
     if (t == 0) {
       const double a = R[k * s + k];
-      if (!(a > 1e-14 * gdiag[k]) || !isfinite(a)) bad = 1;
-      piv = sqrt(a);
+      if (!isfinite(a) || !isfinite(gdiag[k])) bad = 1;
+      // dropped column: pivot 0 (the test below keeps it out of the inverse)
+      piv = (a > kRankRtol * kRankRtol * gdiag[k] && gdiag[k] > 0.0) ? sqrt(a) : 0.0;
       R[k * s + k] = piv;
     }
     __syncthreads();
     if (bad) break;
+    if (piv == 0.0) {
+      // a dependent column: zero row, nothing to subtract from later columns
+      for (int j = k + 1 + t; j < s; j += kThreads) R[k * s + j] = 0.0;
+      __syncthreads();
+      continue;
+    }
     for (int j = k + 1 + t; j < s; j += kThreads) R[k * s + j] /= piv;
     __syncthreads();
     const int rem = s - k - 1;
@@ -91,11 +110,21 @@ __device__ inline void chol_inv_body(int s, const double* __restrict__ G, double
   for (int idx = t; idx < s * s; idx += kThreads)
     if (idx / s > idx % s) R[idx] = 0.0;
   __syncthreads();
-  // inverse of the upper triangle by back substitution, one column per thread
+  // inverse of the upper triangle by back substitution, one column per
+  // thread, over the kept columns (a dropped column j: zero column; a
+  // dropped row i: zero entry, so it adds nothing to the rows above)
   for (int j = t; j < s; j += kThreads) {
     for (int i = s - 1; i > j; --i) Rinv[i * s + j] = 0.0;
+    if (R[j * s + j] == 0.0) {
+      for (int i = j; i >= 0; --i) Rinv[i * s + j] = 0.0;
+      continue;
+    }
     Rinv[j * s + j] = 1.0 / R[j * s + j];
     for (int i = j - 1; i >= 0; --i) {
+      if (R[i * s + i] == 0.0) {
+        Rinv[i * s + j] = 0.0;
+        continue;
+      }
       // sum over l = i+1 .. j in ascending order; four terms' operands
       // loaded before their FMAs
       double acc = 0.0;

@@ -304,13 +304,14 @@ __global__ __launch_bounds__(kThreads) void k_combine(int64_t n, int ld, int nt,
                                                      const XT* __restrict__ slots,
                                                      size_t slot_elems,
                                                      const double* __restrict__ coef,
-                                                     double* __restrict__ Y, int ldy) {
+                                                     double* __restrict__ Y, int ldy,
+                                                     int accumulate) {
   const int64_t total = n * ld;
   for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * kThreads) {
     const int col = (int)(e % ld);
     const int64_t row = e / ld;
-    double acc = 0.0;
+    double acc = accumulate ? Y[row * ldy + col] : 0.0;
     for (int t = 0; t < nt; ++t)
       acc = fma(coef[(size_t)t * ld + col], double(slots[(size_t)t * slot_elems + e]), acc);
     Y[row * ldy + col] = acc;
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_combine16(int64_t n, int ld, int n
                                                        const XT* __restrict__ slots,
                                                        size_t slot_elems,
                                                        const double* __restrict__ coef,
-                                                       double* __restrict__ Y) {
+                                                       double* __restrict__ Y, int accumulate) {
   constexpr int VEC = 16 / sizeof(XT);
   typedef XT xv __attribute__((ext_vector_type(VEC)));
   extern __shared__ double cs[];  // [nt][ld]
@@ -339,9 +340,20 @@ __global__ __launch_bounds__(kThreads) void k_combine16(int64_t n, int ld, int n
     const int64_t row = q / nch;
     const int col = (int)(q - row * nch) * VEC;
     const size_t off = (size_t)row * ld + col;
+    // the FMA chain continues from the stored partial sum when accumulating
+    // (the same sequence as one pass over every term)
     double acc[VEC];
+    if (accumulate) {
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[e] = 0.0;
+      for (int e = 0; e < VEC; e += 2) {
+        const double2 y = *reinterpret_cast<const double2*>(Y + off + e);
+        acc[e] = y.x;
+        acc[e + 1] = y.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] = 0.0;
+    }
     int t = 0;
     for (; t + 4 <= nt; t += 4) {
       xv x[4];
@@ -379,35 +391,46 @@ __global__ __launch_bounds__(kThreads) void k_copy16(const float4* __restrict__ 
 }
 
 // Streaming probe of attainable bandwidth at a given read:write mix: R
-// streams read and (W = 1) one written, 16 bytes per lane, grid-stride, two
-// elements in flight per thread; with W = 0 each thread keeps a running sum
-// and stores it once (so the reads are not dropped).
+// streams read and (W = 1) one written.  The sweep is the Krylov kernels'
+// (one resident wave of blocks, the grid a multiple of 8, each round's
+// chunks banded per XCD): a chunk is 1024 16-byte elements, each thread
+// taking four of them 256 elements apart, all four loads in flight before
+// the stores.  With W = 0 each thread keeps a running sum and stores it once
+// (so the reads are not dropped).
 template <int R, int W>
 __global__ __launch_bounds__(kThreads) void k_stream_rw(const float4* __restrict__ a0,
                                                        const float4* __restrict__ a1,
                                                        const float4* __restrict__ a2,
                                                        float4* __restrict__ out,
                                                        float* __restrict__ sink, size_t n16) {
-  const size_t stride = (size_t)gridDim.x * kThreads;
+  constexpr int kPer = 4;
+  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+  const size_t nchunk = (n16 + kThreads * kPer - 1) / (kThreads * kPer);
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   auto add = [](float4 x, float4 y) { return make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w); };
-  size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
-  for (; i + stride < n16; i += 2 * stride) {
-    float4 v0 = a0[i], v1 = a0[i + stride];
-    if (R > 1) { v0 = add(v0, a1[i]); v1 = add(v1, a1[i + stride]); }
-    if (R > 2) { v0 = add(v0, a2[i]); v1 = add(v1, a2[i + stride]); }
-    if (W) {
-      out[i] = v0;
-      out[i + stride] = v1;
-    } else {
-      acc = add(acc, add(v0, v1));
+  for (size_t j = 0; j * nb < nchunk; ++j) {
+    const size_t base = j * nb;
+    const size_t ch = (nb & 7) ? base + b : base + (size_t)(b & 7) * (nb >> 3) + (b >> 3);
+    if (ch >= nchunk) continue;
+    const size_t e0 = ch * kThreads * kPer + threadIdx.x;
+    float4 v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const size_t e = e0 + (size_t)u * kThreads;
+      v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < n16) {
+        v[u] = a0[e];
+        if (R > 1) v[u] = add(v[u], a1[e]);
+        if (R > 2) v[u] = add(v[u], a2[e]);
+      }
     }
-  }
-  for (; i < n16; i += stride) {
-    float4 v = a0[i];
-    if (R > 1) v = add(v, a1[i]);
-    if (R > 2) v = add(v, a2[i]);
-    if (W) out[i] = v; else acc = add(acc, v);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const size_t e = e0 + (size_t)u * kThreads;
+      if (e < n16) {
+        if (W) out[e] = v[u]; else acc = add(acc, v[u]);
+      }
+    }
   }
   if (!W) sink[(size_t)blockIdx.x * kThreads + threadIdx.x] = acc.x + acc.y + acc.z + acc.w;
 }
@@ -424,7 +447,23 @@ hipError_t launch_stream_rw(hipStream_t st, int reads, int writes, const void* c
   const float4* a1 = reads > 1 ? static_cast<const float4*>(src[1]) : nullptr;
   const float4* a2 = reads > 2 ? static_cast<const float4*>(src[2]) : nullptr;
   float4* o = static_cast<float4*>(dst);
-  const dim3 grid(kMaxBlocks), block(kThreads);
+  // one resident wave of blocks, a multiple of 8 (the sink holds kMaxBlocks)
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  const void* fn = writes ? (reads == 1 ? (const void*)k_stream_rw<1, 1>
+                                        : reads == 2 ? (const void*)k_stream_rw<2, 1>
+                                                     : (const void*)k_stream_rw<3, 1>)
+                          : (reads == 1 ? (const void*)k_stream_rw<1, 0>
+                                        : reads == 2 ? (const void*)k_stream_rw<2, 0>
+                                                     : (const void*)k_stream_rw<3, 0>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  int nb = std::min(kMaxBlocks, per_cu * cus);
+  if (nb >= 8) nb &= ~7;
+  const dim3 grid(std::max(1, nb)), block(kThreads);
 #define LD_STREAM(RR, WW) \
   hipLaunchKernelGGL((k_stream_rw<RR, WW>), grid, block, 0, st, a0, a1, a2, o, sink, n16)
   if (writes) {
@@ -494,7 +533,9 @@ hipError_t launch_osa_coef(hipStream_t st, int B, int ld, int m, const double* e
 }
 
 hipError_t launch_combine(hipStream_t st, int64_t n, int ld, int nt, const void* slots, int xbytes,
-                          size_t slot_elems, const double* coef, double* Y, int ldy) {
+                          size_t slot_elems, const double* coef, double* Y, int ldy,
+                          bool accumulate) {
+  const int acc = accumulate ? 1 : 0;
   if (n < 1 || ld < 1 || nt < 1 || !slots || !coef || !Y || ldy != ld ||
       slot_elems < (size_t)n * ld)
     return hipErrorInvalidValue;
@@ -508,13 +549,13 @@ hipError_t launch_combine(hipStream_t st, int64_t n, int ld, int nt, const void*
     const int64_t nb = std::min<int64_t>((chunks + kThreads - 1) / kThreads, kMaxBlocks);
     if (xbytes == 8)
       hipLaunchKernelGGL(k_combine16<double>, dim3((unsigned)nb), dim3(kThreads), lds, st, n, ld,
-                         nt, static_cast<const double*>(slots), slot_elems, coef, Y);
+                         nt, static_cast<const double*>(slots), slot_elems, coef, Y, acc);
     else if (xbytes == 4)
       hipLaunchKernelGGL(k_combine16<float>, dim3((unsigned)nb), dim3(kThreads), lds, st, n, ld,
-                         nt, static_cast<const float*>(slots), slot_elems, coef, Y);
+                         nt, static_cast<const float*>(slots), slot_elems, coef, Y, acc);
     else if (xbytes == 2)
       hipLaunchKernelGGL(k_combine16<_Float16>, dim3((unsigned)nb), dim3(kThreads), lds, st, n, ld,
-                         nt, static_cast<const _Float16*>(slots), slot_elems, coef, Y);
+                         nt, static_cast<const _Float16*>(slots), slot_elems, coef, Y, acc);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
@@ -524,13 +565,13 @@ hipError_t launch_combine(hipStream_t st, int64_t n, int ld, int nt, const void*
   if (nb > 4 * kMaxBlocks) nb = 4 * kMaxBlocks;
   if (xbytes == 8)
     hipLaunchKernelGGL(k_combine<double>, dim3((unsigned)nb), dim3(kThreads), 0, st, n, ld, nt,
-                       static_cast<const double*>(slots), slot_elems, coef, Y, ldy);
+                       static_cast<const double*>(slots), slot_elems, coef, Y, ldy, acc);
   else if (xbytes == 4)
     hipLaunchKernelGGL(k_combine<float>, dim3((unsigned)nb), dim3(kThreads), 0, st, n, ld, nt,
-                       static_cast<const float*>(slots), slot_elems, coef, Y, ldy);
+                       static_cast<const float*>(slots), slot_elems, coef, Y, ldy, acc);
   else if (xbytes == 2)
     hipLaunchKernelGGL(k_combine<_Float16>, dim3((unsigned)nb), dim3(kThreads), 0, st, n, ld, nt,
-                       static_cast<const _Float16*>(slots), slot_elems, coef, Y, ldy);
+                       static_cast<const _Float16*>(slots), slot_elems, coef, Y, ldy, acc);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -283,9 +283,11 @@ hipError_t launch_hess_log(hipStream_t st, int B, int m, const double* H, const 
 hipError_t launch_osa_coef(hipStream_t st, int B, int ld, int m, const double* ell,
                            const double* mult, const double* norm2, const int* meff, double shift,
                            double* coef);
-// Y[row][col] = sum_{t < nt} coef[t][col] X_t[row][col], X_t = slots + t * slot_elems.
+// Y[row][col] = sum_{t < nt} coef[t][col] X_t[row][col], X_t = slots + t * slot_elems;
+// with accumulate the sum continues from Y (the same FMA chain as one pass).
 hipError_t launch_combine(hipStream_t st, int64_t n, int ld, int nt, const void* slots, int xbytes,
-                          size_t slot_elems, const double* coef, double* Y, int ldy);
+                          size_t slot_elems, const double* coef, double* Y, int ldy,
+                          bool accumulate = false);
 
 // Dense pieces of the Hutch++ sketch (FP64).
 // part[i][j][b] = sum_{rows of b} Xa[row][i] * Xb[row][j], i < ca, j < cb

@@ -213,7 +213,11 @@ ld_status Run::validate() {
     return set_error(LD_E_INVALID_ARG, "unknown precision");
   if (p_.probe_dist != LD_PROBE_RADEMACHER && p_.probe_dist != LD_PROBE_GAUSSIAN)
     return set_error(LD_E_INVALID_ARG, "unknown probe distribution");
-  if (p_.reserved != 0) return set_error(LD_E_INVALID_ARG, "reserved field must be 0");
+  if (p_.sketch_passes < 0 || p_.sketch_passes > 2 ||
+      (p_.sketch_passes == 2 && p_.method == LD_METHOD_OSLQ))
+    return set_error(LD_E_INVALID_ARG, "sketch_passes must be 0, 1 or 2 (2: OSA-IOP and "
+                                       "So-SLQ, whose sketch image comes from Krylov runs)");
+  two_pass_ = p_.sketch_passes == 2;
   if (!(p_.adapt_tol >= 0.0) || !std::isfinite(p_.adapt_tol) || p_.adapt_every < 0)
     return set_error(LD_E_INVALID_ARG, "adapt_tol must be finite and >= 0, adapt_every >= 0");
   if (p_.adapt_tol > 0.0 && p_.method == LD_METHOD_OSA_IOP)
@@ -361,11 +365,13 @@ size_t Run::layout(char* base) {
     nslots_ = std::min(k_, m_) + 1;
     slot_bytes = (size_t)nslots_ * n * ldB_ * xb_;
   } else {
-    // phase 0 keeps the sketch runs' whole basis; phase 1 is a ring (OSA-IOP
-    // also keeps v1)
+    // phase 0 keeps the sketch runs' whole basis (two passes: a ring of the
+    // window plus one combine batch); phase 1 is a ring (OSA-IOP also keeps
+    // v1)
     const int ring = std::min(k_, m_) + (p_.method == LD_METHOD_OSA_IOP ? 2 : 1);
-    nslots_ = std::max(m_ + 1, ring);
-    slot_bytes = std::max((size_t)(m_ + 1) * n * ld1_ * xb_, (size_t)ring * n * ldB_ * xb_);
+    const int ring0 = two_pass_ ? std::min(k_, m_) + 1 + kCombBatch : m_ + 1;
+    nslots_ = std::max(ring0, ring);
+    slot_bytes = std::max((size_t)ring0 * n * ld1_ * xb_, (size_t)ring * n * ldB_ * xb_);
   }
   slots_ = take(slot_bytes);
   mult_ = static_cast<double*>(take((size_t)nslots_ * ldx_ * 8));
@@ -408,6 +414,7 @@ size_t Run::layout(char* base) {
   if (p_.method == LD_METHOD_SO_SLQ) umat_ = static_cast<double*>(take((size_t)s_ * kb_ * 8));
   ell_ = static_cast<double*>(take((size_t)ld1_ * m_ * 8));
   coefs_ = static_cast<double*>(take((size_t)(m_ + 1) * ld1_ * 8));
+  multall_ = two_pass_ ? static_cast<double*>(take((size_t)(m_ + 1) * ld1_ * 8)) : nullptr;
   meff_ = static_cast<int*>(take((size_t)ldx_ * 4));
   active_ = static_cast<int*>(take((size_t)ldx_ * 4));
   flags_ = static_cast<int*>(take((size_t)ldx_ * 4));
@@ -440,8 +447,10 @@ double Run::spmm_bytes(int ld, int xbytes) const {
 
 // CholQR2: Y <- Y R1^{-1}, then again, so that Y = A R with A orthonormal and
 // R = R2 R1 upper triangular with a positive diagonal (the QR convention of
-// the oracle).  dflag_[0] is set when the Gram matrix is not numerically
-// positive definite.
+// the oracle).  A column whose part orthogonal to the columns kept before it
+// is at most 1e-6 of its norm is dropped (a zero column of A, whose run then
+// contributes nothing): A spans range(Y) in column order also when the sketch
+// image is rank-deficient.  dflag_[pass] is set on a non-finite pivot.
 ld_status Run::sketch_qr(hipStream_t st, double* Y, int cols) {
   for (int pass = 0; pass < 2; ++pass) {
     LD_LAUNCH(LD_PROF_SKETCH, (double)n_ * cols * 8,
@@ -503,8 +512,8 @@ ld_status Run::begin_krylov(int phase) {
     kg_ = g1p_;
     kgu_ = g1u_;
     kpin_ = false;
-    kfull_ = true;
-    kns_ = m_ + 1;
+    kfull_ = !two_pass_;
+    kns_ = two_pass_ ? std::min(k_, m_) + 1 + kCombBatch : m_ + 1;
   } else {
     kB_ = B_;
     kld_ = ldB_;
@@ -515,9 +524,48 @@ ld_status Run::begin_krylov(int phase) {
     kns_ = std::min(k_, m_) + 2;
   }
   kslots_ = slots_;
-  kmult_ = mult_;
+  // the sketch-image runs of a two-pass sketch keep every vector's
+  // multiplier (the combination coefficients need all of them)
+  kmfull_ = kfull_ || (phase == 0 && two_pass_);
+  kmult_ = (phase == 0 && two_pass_) ? multall_ : mult_;
   slot_elems_ = (size_t)n_ * kld_;
   pending_check_ = false;
+  // the second pass of a two-pass sketch needs the basis vectors v_1 .. v_m
+  // only: its last step (which forms v_m+1) is skipped
+  kend_ = (phase == 0 && two_pass_ && opass_ == 1) ? m_ - 1 : m_;
+  return LD_OK;
+}
+
+// Start block of the sketch-image runs: the sketch columns S themselves in
+// Krylov precision, their norms and per-run start state.
+ld_status Run::sketch_runs_start(hipStream_t st) {
+  LD_LAUNCH(LD_PROF_PROBES, (double)n_ * ld1_ * xb_,
+            launch_probes(st, p_.probe_dist, p_.seed, n_, 0, ld1_, s_, slots_, xb_, ld1_, 0));
+  VecSet vs{};
+  vs.x[0] = slots_;
+  int nb = 0;
+  LD_LAUNCH(LD_PROF_DOTS, (double)n_ * ld1_ * xb_,
+            launch_dots(st, g1_, slots_, vs, 1, 0, part_, &nb));
+  LD_LAUNCH(LD_PROF_SMALL, (double)nb * ld1_ * 8,
+            launch_start_finish(st, s_, ld1_, part_, nb, norm2_, two_pass_ ? multall_ : mult_,
+                                active_, meff_, nullptr, 0, 1.0));
+  return LD_OK;
+}
+
+// Two-pass sketch image: Y (+)= sum_{j = comb_next_ .. upto} coef_j X_j,
+// X_j the ring slot of basis vector j (at most two launches when the range
+// wraps the ring); the FMA chain per entry runs over j in order, as in the
+// one-pass combine over the kept basis.
+ld_status Run::sketch_combine_upto(hipStream_t st, int upto) {
+  while (comb_next_ <= upto) {
+    const int slot = comb_next_ % kns_;
+    const int cnt = std::min(upto - comb_next_ + 1, kns_ - slot);
+    const void* base = static_cast<const char*>(slots_) + (size_t)slot * slot_elems_ * xb_;
+    LD_LAUNCH(LD_PROF_SKETCH, (double)cnt * n_ * ld1_ * xb_ + (double)n_ * lds_ * 16,
+              launch_combine(st, n_, ld1_, cnt, base, xb_, slot_elems_,
+                             coefs_ + (size_t)comb_next_ * ld1_, Y_, lds_, comb_next_ > 0));
+    comb_next_ += cnt;
+  }
   return LD_OK;
 }
 
@@ -556,19 +604,13 @@ ld_status Run::run_prologue(hipStream_t st) {
     begin_krylov(0);
     return LD_OK;
   }
-  // OSA-IOP: the sketch-image runs start from S itself (phase 0, basis kept)
+  // OSA-IOP: the sketch-image runs start from S itself (phase 0, basis kept
+  // or, in two passes, a ring)
   if (s_ > 0) {
-    LD_LAUNCH(LD_PROF_PROBES, (double)n_ * ld1_ * xb_,
-              launch_probes(st, p_.probe_dist, p_.seed, n_, 0, ld1_, s_, slots_, xb_, ld1_, 0));
-    VecSet vs{};
-    vs.x[0] = slots_;
-    int nb = 0;
-    LD_LAUNCH(LD_PROF_DOTS, (double)n_ * ld1_ * xb_,
-              launch_dots(st, g1_, slots_, vs, 1, 0, part_, &nb));
-    LD_LAUNCH(LD_PROF_SMALL, (double)nb * ld1_ * 8,
-              launch_start_finish(st, s_, ld1_, part_, nb, norm2_, mult_, active_, meff_, nullptr,
-                                  0, 1.0));
+    ld_status rc = sketch_runs_start(st);
+    if (rc != LD_OK) return rc;
     LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldx_ * (m_ + 1) * m_ * 8, st));
+    opass_ = 0;
     begin_krylov(0);
     return LD_OK;
   }
@@ -585,15 +627,33 @@ ld_status Run::run_prologue(hipStream_t st) {
 // runs (Alg 2).
 ld_status Run::osa_sketch_combine(hipStream_t st) {
   const double shift = std::log(scale_) - c_;
-  // keep the sketch-image runs' Krylov dimensions for the step count
-  LD_HIP(hipMemcpyAsync(meff0_, meff_, (size_t)std::max(s_, 1) * 4, hipMemcpyDeviceToDevice, st));
-  LD_LAUNCH(LD_PROF_SMALL, 0,
-            launch_hess_log(st, s_, m_, H_, meff_, quad_a(), quad_b(), work_, wstride_, 0, ell_,
-                            nullptr, 0.0, nullptr, flags_, symtol(), need_));
-  LD_LAUNCH(LD_PROF_SMALL, 0,
-            launch_osa_coef(st, s_, ld1_, m_, ell_, mult_, norm2_, meff_, shift, coefs_));
-  LD_LAUNCH(LD_PROF_SKETCH, (double)m_ * n_ * ld1_ * xb_ + (double)n_ * lds_ * 8,
-            launch_combine(st, n_, ld1_, m_, slots_, xb_, (size_t)n_ * ld1_, coefs_, Y_, lds_));
+  if (!two_pass_ || opass_ == 0) {
+    // keep the sketch-image runs' Krylov dimensions for the step count
+    LD_HIP(hipMemcpyAsync(meff0_, meff_, (size_t)std::max(s_, 1) * 4, hipMemcpyDeviceToDevice,
+                          st));
+    LD_LAUNCH(LD_PROF_SMALL, 0,
+              launch_hess_log(st, s_, m_, H_, meff_, quad_a(), quad_b(), work_, wstride_, 0, ell_,
+                              nullptr, 0.0, nullptr, flags_, symtol(), need_));
+    // the coefficient of v_t in each run's y (its multipliers folded in)
+    LD_LAUNCH(LD_PROF_SMALL, 0,
+              launch_osa_coef(st, s_, ld1_, m_, ell_, two_pass_ ? multall_ : mult_, norm2_, meff_,
+                              shift, coefs_));
+  }
+  if (two_pass_ && opass_ == 0) {
+    // second pass: the same runs again from S (the same kernels in the same
+    // order give the same vectors), adding v_1 .. v_m into Y as they pass
+    // through the ring; H is not needed again (the rewrite is identical)
+    ld_status rc = sketch_runs_start(st);
+    if (rc != LD_OK) return rc;
+    opass_ = 1;
+    comb_next_ = 0;
+    begin_krylov(0);
+    if (kend_ == 0) return sketch_combine_upto(st, m_ - 1);  // m = 1: v_1 only
+    return LD_OK;
+  }
+  if (!two_pass_)
+    LD_LAUNCH(LD_PROF_SKETCH, (double)m_ * n_ * ld1_ * xb_ + (double)n_ * lds_ * 8,
+              launch_combine(st, n_, ld1_, m_, slots_, xb_, (size_t)n_ * ld1_, coefs_, Y_, lds_));
   if (p_.method == LD_METHOD_SO_SLQ) {
     // So-SLQ keeps the kb dominant left singular vectors of Y: Y V_k
     // Lambda_k^{-1/2} from the eigenpairs of Y^T Y (rank-deficient sketches
@@ -625,7 +685,9 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
   auto slot_ptr = [&](int j) -> void* {
     return static_cast<char*>(kslots_) + (size_t)slot_of(j) * slot_elems_ * eb;
   };
-  auto mult_ptr = [&](int j) -> double* { return kmult_ + (size_t)slot_of(j) * kld_; };
+  auto mult_ptr = [&](int j) -> double* {
+    return kmult_ + (size_t)(kmfull_ ? j : slot_of(j)) * kld_;
+  };
   const void* vals = (mixed_ && a_->vlo) ? a_->vlo : a_->v64;
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
   const double vec_bytes = (double)n_ * kld_ * xb_;
@@ -657,10 +719,15 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
   const bool v1step = kpin_ && (t & 1);
   const int nv_next = (t + 1) - std::max(0, t + 2 - k_) + 1;
   const bool check = adaptive() && (t + 1) % adapt_every_ == 0 && t + 1 < m_;
+  // second pass of a two-pass sketch: after this step forms v_t+2 (index
+  // t + 1), the vectors that fill a batch, or the last one needed, go into Y
+  const bool pass_b = two_pass_ && kphase_ == 0 && opass_ == 1;
+  const int produced = std::min(t + 1, m_ - 1);
+  const bool comb = pass_b && (produced - comb_next_ + 1 >= kCombBatch || produced == m_ - 1);
   if (plan) {
     // a step of four launches (product, reduction, one update, bookkeeping)
     // can join a batch of other requests' steps; the caller launches it
-    plan->valid = nold == 0 && nv <= 4 && !check && !prof_;
+    plan->valid = nold == 0 && nv <= 4 && !check && !prof_ && !pass_b;
     if (plan->valid) {
       SpmmItem& sp = plan->spmm;
       sp = SpmmItem{};
@@ -740,6 +807,10 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
                                meff_, active_, mult_ptr(t + 1), v1step ? gq_ : nullptr, flags_,
                                sym_out ? nv_next - 2 : -1, 1.0 / vscale_,
                                v1step ? mult_ptr(t) : nullptr));
+  if (comb) {
+    ld_status rc = sketch_combine_upto(st, produced);
+    if (rc != LD_OK) return rc;
+  }
   if (check) {
     // adaptive Krylov dimension: runs whose quadrature value settled stop;
     // the count of runs still going comes back to the host for the early exit
@@ -841,11 +912,16 @@ ld_status Run::advance(hipStream_t st, int budget, bool* done, StepPlan* plan, b
             LD_HIP(q);
           }
         }
+        if (t_ >= kend_) {
+          // a phase without steps (the second sketch pass at m = 1)
+          stage_ = (p_.method != LD_METHOD_OSLQ && kphase_ == 0) ? ST_COMBINE : ST_EPILOGUE;
+          break;
+        }
         ld_status rc = run_krylov_step(st, t_, plan);
         if (rc != LD_OK) return rc;
         ++t_;
         --budget;
-        if (t_ >= m_)
+        if (t_ >= kend_)
           stage_ = (p_.method != LD_METHOD_OSLQ && kphase_ == 0) ? ST_COMBINE : ST_EPILOGUE;
         if (plan && plan->valid) {
           // the caller launches this step (with other requests' steps) first
@@ -921,7 +997,7 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail, 
   float ms = 0.f;
   LD_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
   if (dflag[0] || dflag[1])
-    return set_error(LD_E_NUMERIC, "sketch image lost rank (Cholesky of its Gram matrix failed)");
+    return set_error(LD_E_NUMERIC, "NaN/Inf in the Gram matrix of the sketch image");
   if (dflag[2])
     return set_error(LD_E_NUMERIC, "So-SLQ: the sketch has rank below subspace_rank, or the Jacobi "
                                    "eigen-decomposition of its Gram matrix did not converge");
@@ -939,8 +1015,11 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail, 
   // Gauss quadrature methods start from unit basis vectors; OSA-IOP's K is
   // per unit norm of its start vector)
   double tr_sketch = 0.0;
-  for (int i = 0; i < kb_; ++i)
+  int basis_rank = 0;  // basis columns kept by the QR (dropped ones are zero, K = 0)
+  for (int i = 0; i < kb_; ++i) {
     tr_sketch += (p_.method != LD_METHOD_OSA_IOP) ? K[i] : nrm[i] * K[i];
+    basis_rank += nrm[i] > 0.0 ? 1 : 0;
+  }
   double acc = 0.0;
   for (int j = kb_; j < B_; ++j) acc += nrm[j] * K[j];
   const double tr_resid = acc / r_;
@@ -969,6 +1048,7 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail, 
   res.matvecs = sketch_mv + (int64_t)B_ * m_;
   res.min_steps = minst;
   res.n_breakdowns = nbreak;
+  res.basis_rank = basis_rank;
   res.device_ms = ms;
   res.latency_ms = (now_seconds() - t_submit_) * 1e3;
   if (detail) {
@@ -1658,6 +1738,15 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
     }
   }
   return run.collect(ctx->stream, out, detail);
+}
+
+ld_status ld_request_bytes(ld_matrix* a, const ld_params* p, uint64_t* bytes) {
+  if (!a || !p || !bytes) return set_error(LD_E_INVALID_ARG, "null argument");
+  Run run(a, *p);
+  ld_status rc = run.validate();
+  if (rc != LD_OK) return rc;
+  *bytes = (uint64_t)run.device_bytes();
+  return LD_OK;
 }
 
 ld_status ld_estimate_ex(ld_matrix* a, const ld_params* p, ld_result* out) {

@@ -174,6 +174,8 @@ class Run {
   ld_status osa_sketch_prologue(hipStream_t st);
   ld_status osa_sketch_combine(hipStream_t st);
   ld_status start_block(hipStream_t st, const double* A, int s_cols);
+  ld_status sketch_runs_start(hipStream_t st);     // start block of the sketch-image runs
+  ld_status sketch_combine_upto(hipStream_t st, int upto);  // two-pass: X_comb_next_..X_upto into Y
   ld_status begin_krylov(int phase);
   size_t layout(char* base);
   // product (which = 0) or update (which = 1) geometry of a Krylov block of
@@ -202,6 +204,16 @@ class Run {
   int stage_ = 0;             // 0 prologue, 1 krylov, 2 epilogue..., see .cpp
   int t_ = 0;
   int kphase_ = 0;            // OSA-IOP: 0 sketch-image runs, 1 estimate runs
+  int kend_ = 0;              // steps of the current Krylov phase
+  // two-pass sketch image (sketch_passes = 2): the sketch-image runs on a
+  // ring of blocks, first for H only (opass_ 0), then again adding their
+  // basis vectors into Y in batches of kCombBatch while still in the ring
+  static constexpr int kCombBatch = 8;
+  bool two_pass_ = false;
+  int opass_ = 0;
+  int comb_next_ = 0;         // next basis vector index to add to Y
+  double* multall_ = nullptr; // two-pass: [m+1][ld1] multipliers of every sketch-run vector
+  bool kmfull_ = false;       // multipliers indexed by vector, not by ring slot
   // Krylov phase parameters (current)
   int kB_ = 0, kld_ = 0, kns_ = 0;
   bool kpin_ = false, kfull_ = false;

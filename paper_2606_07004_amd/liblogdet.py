@@ -55,7 +55,8 @@ class ld_params(C.Structure):
                 ("sketch_rank", C.c_int32), ("krylov_steps", C.c_int32),
                 ("iop_window", C.c_int32), ("seed", C.c_uint64), ("tol", C.c_double),
                 ("probe_dist", C.c_int32), ("subspace_rank", C.c_int32),
-                ("adapt_tol", C.c_double), ("adapt_every", C.c_int32), ("reserved", C.c_int32)]
+                ("adapt_tol", C.c_double), ("adapt_every", C.c_int32),
+                ("sketch_passes", C.c_int32)]
 
 
 class ld_result(C.Structure):
@@ -63,7 +64,8 @@ class ld_result(C.Structure):
                 ("shift_c", C.c_double), ("lambda_lo", C.c_double), ("lambda_hi", C.c_double),
                 ("scale", C.c_double), ("probe_steps", C.c_int64), ("matvecs", C.c_int64),
                 ("min_steps", C.c_int32), ("n_breakdowns", C.c_int32),
-                ("device_ms", C.c_double), ("latency_ms", C.c_double)]
+                ("device_ms", C.c_double), ("latency_ms", C.c_double),
+                ("basis_rank", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -108,6 +110,7 @@ _SIGNATURES = [
     ("ld_estimate", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                 C.c_uint64, C.POINTER(ld_result)]),
     ("ld_estimate_ex", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(ld_result)]),
+    ("ld_request_bytes", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(C.c_uint64)]),
     ("ld_estimate_detail", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(ld_result),
                                        C.POINTER(ld_detail)]),
     ("ld_estimate_noalloc", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(ld_result)]),
@@ -201,9 +204,9 @@ def make_params(n_probes: int, sketch_rank: int, krylov_steps: int, iop_window: 
                 method: int = LD_METHOD_OSLQ, precision: int = LD_PREC_FP64,
                 tol: float = 0.0, probe_dist: int = LD_PROBE_RADEMACHER,
                 subspace_rank: int = 0, adapt_tol: float = 0.0,
-                adapt_every: int = 0) -> ld_params:
+                adapt_every: int = 0, sketch_passes: int = 0) -> ld_params:
     return ld_params(method, precision, n_probes, sketch_rank, krylov_steps, iop_window,
-                     seed, tol, probe_dist, subspace_rank, adapt_tol, adapt_every, 0)
+                     seed, tol, probe_dist, subspace_rank, adapt_tol, adapt_every, sketch_passes)
 
 
 def runs_and_basis(params: ld_params):
@@ -226,6 +229,13 @@ def ld_estimate_ex(a, params: ld_params) -> ld_result:
     res = ld_result()
     _check(lib().ld_estimate_ex(a, C.byref(params), C.byref(res)))
     return res
+
+
+def ld_request_bytes(a, params: ld_params) -> int:
+    """Device bytes an estimate with `params` takes beyond the matrix."""
+    out = C.c_uint64()
+    _check(lib().ld_request_bytes(a, C.byref(params), C.byref(out)))
+    return out.value
 
 
 def ld_estimate_noalloc(a, params: ld_params) -> ld_result:

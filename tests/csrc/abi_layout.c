@@ -14,12 +14,12 @@ int main(void) {
   F(ld_params, method); F(ld_params, precision); F(ld_params, n_probes); F(ld_params, sketch_rank);
   F(ld_params, krylov_steps); F(ld_params, iop_window); F(ld_params, seed); F(ld_params, tol);
   F(ld_params, probe_dist); F(ld_params, subspace_rank); F(ld_params, adapt_tol);
-  F(ld_params, adapt_every); F(ld_params, reserved);
+  F(ld_params, adapt_every); F(ld_params, sketch_passes);
   Z(ld_params);
   F(ld_result, logdet); F(ld_result, tr_sketch); F(ld_result, tr_resid); F(ld_result, shift_c);
   F(ld_result, lambda_lo); F(ld_result, lambda_hi); F(ld_result, scale); F(ld_result, probe_steps);
   F(ld_result, matvecs); F(ld_result, min_steps); F(ld_result, n_breakdowns);
-  F(ld_result, device_ms); F(ld_result, latency_ms);
+  F(ld_result, device_ms); F(ld_result, latency_ms); F(ld_result, basis_rank);
   Z(ld_result);
   F(ld_detail, probe_K); F(ld_detail, probe_norm2); F(ld_detail, probe_steps);
   F(ld_detail, tri_alpha); F(ld_detail, tri_beta); F(ld_detail, sketch_basis);

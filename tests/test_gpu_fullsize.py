@@ -145,3 +145,36 @@ def test_fullsize_bf16_values(L, ctx):
     print(f"  rounding the values to bfloat16 moves the log-determinant by "
           f"{abs(gold['logdet'] - unrounded) / abs(unrounded):.3e}")
     np.testing.assert_allclose(det["probe_norm2"], gold["probe_norm2"], rtol=1e-6)
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "MIXED"])
+def test_fullsize_osa_iop_two_pass_sketch(L, ctx, prec_name):
+    # the 128^3 Laplacian, OSA-IOP, window 2, with the memory-lean two-pass
+    # sketch image: bitwise the kept-basis estimate, within the gate of the
+    # stored oracle result, in a fraction of the device memory
+    name = "lap3d128_s1e-2_osaiop_k2"
+    gold = _load(name)
+    a = BUILDERS[name]()
+    assert W.csr_digest(a) == gold["digest"]
+    prec = getattr(L, "LD_PREC_" + prec_name)
+    vt = L.LD_VT_FP64 if prec_name == "FP64" else L.LD_VT_FP32
+    print(f"\n[case] fullsize {name} two-pass sketch {prec_name}", flush=True)
+    h = ctx.matrix(a, vt=vt)
+    try:
+        p1 = L.make_params(gold["n_probes"], gold["sketch_rank"], gold["krylov_steps"],
+                           gold["iop_window"], gold["seed"], method=L.LD_METHOD_OSA_IOP,
+                           precision=prec)
+        p2 = L.make_params(gold["n_probes"], gold["sketch_rank"], gold["krylov_steps"],
+                           gold["iop_window"], gold["seed"], method=L.LD_METHOD_OSA_IOP,
+                           precision=prec, sketch_passes=2)
+        b1, b2 = L.ld_request_bytes(h, p1), L.ld_request_bytes(h, p2)
+        r2 = L.ld_estimate_ex(h, p2)
+        r1 = L.ld_estimate_ex(h, p1)
+    finally:
+        ctx.release(h)
+    rel = abs(r2.logdet - gold["logdet"]) / abs(gold["logdet"])
+    print(f"  two-pass {r2.logdet!r} ({b2 / 1e9:.2f} GB, {r2.device_ms:.1f} ms) one-pass "
+          f"{r1.logdet!r} ({b1 / 1e9:.2f} GB, {r1.device_ms:.1f} ms) rel {rel:.2e}", flush=True)
+    assert r2.logdet == r1.logdet
+    assert rel <= (1e-6 if prec_name == "FP64" else 1e-4)
+    assert b2 < 0.4 * b1

@@ -122,3 +122,96 @@ def test_osa_iop_breakdown_step_parity(L, ctx, nvals, m):
 def test_osa_iop_step_count_parity(L, ctx, m, k):
     # an odd or even number of steps (the last step reads v1 or not)
     _check(L, ctx, W.lap2d(24, 0.2), 12, 4, m, k, 11)
+
+
+def test_osa_iop_window_8_small(L, ctx):
+    # window 8 (the largest of the 128^3 grid) at a size the oracle runs in
+    # seconds, FP64 per run and mixed precision
+    a = W.lap3d(18, 1e-2)
+    _check(L, ctx, a, 30, 10, 24, 8, 5, ktol=1e-8)
+    _check(L, ctx, a, 30, 10, 24, 8, 5, prec=L.LD_PREC_MIXED, vt=L.LD_VT_FP32, rtol=1e-4)
+
+
+# ---------------------------------------------------------------------------
+# Two-pass sketch image (sketch_passes = 2): the sketch-image runs go twice
+# through a ring of min(k, m) + 9 blocks, the first time for H, the second
+# adding each basis vector into Y before its block is reused.  The same
+# kernels in the same order give the same vectors, and the batched FMA chain
+# of the combination continues from the stored partial sums, so the estimate
+# is bitwise the one-pass estimate over the kept basis.
+# ---------------------------------------------------------------------------
+def _two_pass_pair(L, ctx, a, p1, vt, lo_hint=0.0):
+    import ctypes
+    p2 = type(p1).from_buffer_copy(p1)
+    p2.sketch_passes = 2
+    h = ctx.matrix(a, vt=vt, lo_hint=lo_hint)
+    try:
+        r1, d1 = L.ld_estimate_detail(h, p1, n=a.n, tri=True)
+        r2, d2 = L.ld_estimate_detail(h, p2, n=a.n, tri=True)
+        b1, b2 = L.ld_request_bytes(h, p1), L.ld_request_bytes(h, p2)
+    finally:
+        ctx.release(h)
+    print(f"  one pass {r1.logdet!r} ({b1} B)  two passes {r2.logdet!r} ({b2} B)", flush=True)
+    assert r2.logdet == r1.logdet
+    assert r2.tr_sketch == r1.tr_sketch and r2.tr_resid == r1.tr_resid
+    assert r2.probe_steps == r1.probe_steps
+    for key in ("probe_K", "probe_norm2", "probe_steps", "tri_alpha", "tri_beta"):
+        np.testing.assert_array_equal(d2[key], d1[key])
+    return r1, b1, b2
+
+
+@pytest.mark.parametrize("prec_name,m,k", [("FP64", 1, 2), ("FP64", 7, 2), ("FP64", 8, 2),
+                                           ("FP64", 11, 2), ("FP64", 25, 4), ("FP64", 20, 8),
+                                           ("MIXED", 25, 2), ("HALF", 30, 3)])
+def test_two_pass_sketch_is_bitwise_one_pass(L, ctx, prec_name, m, k):
+    # m = 1: no second-pass step, v_1 alone; m = 7, 8: below and at one
+    # combine batch; m = 11: the ring of window 2 (11 blocks) wraps; m = 25,
+    # window 4: the ring wraps twice; window 8
+    a = W.lap2d(60, 0.05)
+    prec = getattr(L, "LD_PREC_" + prec_name)
+    vt = L.LD_VT_FP64 if prec_name == "FP64" else L.LD_VT_FP32
+    seed = 3
+    print(f"\n[case] two-pass osa-iop {a.name} m={m} k={k} {prec_name}", flush=True)
+    p1 = L.make_params(30, 10, m, k, seed, method=L.LD_METHOD_OSA_IOP, precision=prec)
+    r1, b1, b2 = _two_pass_pair(L, ctx, a, p1, vt)
+    ref = oracle.osa_iop(a, 30, 10, m, k, seed)
+    tol = 1e-6 if prec_name == "FP64" else 1e-4
+    assert abs(r1.logdet - ref.logdet) <= tol * abs(ref.logdet)
+    # the sketch phase shrinks from m + 1 blocks of s columns to min(k, m) + 9;
+    # the estimate phase's ring (n_probes columns) can still dominate, and the
+    # two-pass run adds (m + 1) s multipliers
+    assert b2 <= b1 + 8192
+
+
+def test_two_pass_sketch_breakdown_and_so_slq(L, ctx):
+    # sketch-image runs that break down after 4 steps (4 distinct
+    # eigenvalues): later multipliers are zero and so are their coefficients
+    a = W.diag_matrix(np.repeat(np.array([0.3, 0.9, 1.7, 4.0]), 400))
+    print(f"\n[case] two-pass osa-iop breakdown {a.name}", flush=True)
+    _two_pass_pair(L, ctx, a, L.make_params(24, 8, 15, 2, 4, method=L.LD_METHOD_OSA_IOP),
+                   L.LD_VT_FP64)
+    # So-SLQ builds its sketch of log J from the same runs
+    b = W.lap3d(14, 0.05)
+    print(f"\n[case] two-pass so-slq {b.name}", flush=True)
+    _two_pass_pair(L, ctx, b, L.make_params(40, 20, 16, 2, 6, method=L.LD_METHOD_SO_SLQ,
+                                            subspace_rank=8), L.LD_VT_FP64)
+
+
+def test_two_pass_sketch_served_and_refused_for_oslq(L, ctx):
+    a = W.lap2d(50, 0.1)
+    h = ctx.matrix(a)
+    try:
+        ps = [L.make_params(20, 6, 14, 2, 9 + i, method=L.LD_METHOD_OSA_IOP,
+                            sketch_passes=2 if i % 2 else 0) for i in range(4)]
+        print("\n[case] two-pass osa-iop served with one-pass requests", flush=True)
+        alone = [L.ld_estimate_ex(h, p).logdet for p in ps]
+        tickets = [L.ld_submit(h, p) for p in ps]
+        served = [L.ld_wait(ctx.handle, t).logdet for t in tickets]
+        assert served == alone
+        for bad in (L.make_params(20, 6, 14, 2, 1, sketch_passes=2),
+                    L.make_params(20, 6, 14, 2, 1, method=L.LD_METHOD_OSA_IOP, sketch_passes=3)):
+            with pytest.raises(L.LdError) as ei:
+                L.ld_estimate_ex(h, bad)
+            assert ei.value.status == L.LD_E_INVALID_ARG
+    finally:
+        ctx.release(h)

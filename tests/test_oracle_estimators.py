@@ -256,3 +256,105 @@ def test_gaussian_probes_full_sketch_is_exact(method):
     fn = getattr(O, method)
     res = fn(a, 9, 8, 8, 8, 1, dist=O.PROBE_GAUSSIAN)
     assert res.logdet == pytest.approx(O.dense_logdet(a), rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# orth() of the sketch image (Alg 2, Alg 3: "orthonormal basis via QR"),
+# including the reading for a rank-deficient image.
+# ---------------------------------------------------------------------------
+from oracle.estimators import RANK_RTOL, _orth  # noqa: E402
+
+
+def _check_basis(q, y, kept):
+    """q: the kept columns orthonormal, spanning range(y), upper-triangular
+    positive-diagonal factor q^T y on the kept columns, zero elsewhere."""
+    n, s = y.shape
+    dropped = [j for j in range(s) if j not in kept]
+    assert np.all(q[:, dropped] == 0.0)
+    qk = q[:, kept]
+    np.testing.assert_allclose(qk.T @ qk, np.eye(len(kept)), atol=1e-12)
+    r = qk.T @ y[:, kept]
+    np.testing.assert_allclose(np.tril(r, -1), 0.0, atol=1e-10)
+    assert np.all(np.diag(r) > 0)
+    # every column of y (kept or not) lies in span(qk)
+    np.testing.assert_allclose(qk @ (qk.T @ y), y, atol=1e-9 * max(1.0, np.abs(y).max()))
+
+
+def test_orth_full_rank_is_positive_diagonal_qr():
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal((40, 7))
+    _check_basis(_orth(y), y, list(range(7)))
+
+
+def test_orth_drops_dependent_columns_in_order():
+    rng = np.random.default_rng(4)
+    a, b, c = rng.standard_normal((3, 50))
+    y = np.column_stack([a, b, a + 2.0 * b, np.zeros(50), c, -3.0 * c + b])
+    q = _orth(y)
+    _check_basis(q, y, [0, 1, 4])
+
+
+def test_orth_threshold_is_relative_to_the_column():
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal(60)
+    e = rng.standard_normal(60)
+    e -= a * (a @ e) / (a @ a)
+    e /= np.linalg.norm(e)
+    scale = 1e5  # the test is relative to ||y_j||, not to ||Y||
+    for eps, kept in ((1e-3, [0, 1]), (3.0 * RANK_RTOL, [0, 1]), (1e-9, [0])):
+        col = scale * (a / np.linalg.norm(a) + eps * e)
+        y = np.column_stack([a, col])
+        q = _orth(y)
+        assert [j for j in range(2) if np.any(q[:, j])] == kept, eps
+        _check_basis(q, y, kept)
+
+
+def test_osa_iop_exact_with_rank_deficient_sketch_image():
+    # rank(L_c) = 3 < s = 5: Y = L_c S has rank 3, two sketch columns are
+    # dropped, and Hutch++ is still exact (A spans range(L_c), every residual
+    # form vanishes); the two dropped runs report K = 0, norm 0, no steps
+    d = np.concatenate([np.full(27, 0.2), [0.6, 1.7, 3.1]])
+    a = W.diag_matrix(d)
+    s = 5
+    seed = next(sd for sd in range(200)
+                if np.linalg.matrix_rank(rademacher(sd, 30, 0, s)[27:, :]) == 3)
+    res = O.osa_iop(a, n_probes=8, sketch_rank=s, krylov_steps=10, iop_window=2, seed=seed)
+    assert res.logdet == pytest.approx(float(np.sum(np.log(d))), rel=1e-10)
+    assert abs(res.tr_resid) < 1e-10
+    kept = [i for i in range(s) if res.probe_norm2[i] > 0]
+    assert len(kept) == 3
+    for i in range(s):
+        if i not in kept:
+            assert res.probe_K[i] == 0.0 and res.probe_steps[i] == 0
+
+
+def test_oslq_singular_sketch_matches_dense_split():
+    # a singular 6 x 6 sign sketch (rank 5): the basis has 5 columns; with
+    # m = n and the full window every quadratic form is exact, so the estimate
+    # equals the Hutch++ split evaluated densely with an orthonormal basis of
+    # range(J S) from the SVD (tr(A^T L A) and the residual depend on span(A)
+    # only) and L = logm(J) - c I
+    import scipy.linalg
+    n = 6
+    seed = next(sd for sd in range(200)
+                if np.linalg.matrix_rank(rademacher(sd, n, 0, n)) == n - 1)
+    a = W.from_dense(W.random_spd_dense(n, seed=11, lo=0.3, hi=4.0))
+    npr = n + 3
+    res = O.oslq(a, npr, n, n, n, seed)
+    qd = a.to_dense()
+    lo, hi = O.spectral_interval(a)
+    alpha, c = O.oslq_scaling(lo, hi)
+    jm = qd / alpha
+    lm = np.real(scipy.linalg.logm(jm))
+    y = jm @ rademacher(seed, n, 0, n)
+    u, sv, _ = np.linalg.svd(y)
+    basis = u[:, :int(np.sum(sv > 1e-10 * sv[0]))]
+    assert basis.shape[1] == n - 1
+    tr_sketch = float(np.trace(basis.T @ lm @ basis))
+    g = rademacher(seed, n, n, npr)
+    uu = g - basis @ (basis.T @ g)
+    tr_resid = float(np.sum(uu * (lm @ uu))) / (npr - n)
+    assert res.tr_sketch == pytest.approx(tr_sketch, rel=1e-9, abs=1e-10)
+    assert res.tr_resid == pytest.approx(tr_resid, rel=1e-9, abs=1e-10)
+    assert res.logdet == pytest.approx(n * c + tr_sketch + tr_resid, rel=1e-10)
+    assert sum(1 for i in range(n) if res.probe_norm2[i] > 0) == n - 1
