@@ -46,9 +46,6 @@ def parse():
     ap.add_argument("--precision", choices=("mixed", "half", "fp64"), default="mixed",
                     help="Krylov vectors in FP32 (mixed: FP32 vectors and values, FP64 "
                          "reductions and small matrices), FP16 (half) or FP64")
-    ap.add_argument("--serve-precision", choices=("mixed", "half", "auto"), default="auto",
-                    help="Krylov vectors of the served requests (auto: FP16 when the "
-                         "spectral bound ratio allows, else FP32)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other full-size configurations (graph, Wendland)")
     ap.add_argument("--no-variants", action="store_true",
@@ -65,8 +62,8 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-probes", type=int, default=12)
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=64)
-    ap.add_argument("--serve-nmax", type=float, default=2e5)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-nmax", type=float, default=2e6)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--copy-bytes", type=float, default=805306368,
                     help="bytes of the copy-kernel calibration (0 to skip)")
@@ -364,50 +361,82 @@ def precision_variants(L, ctx, h, args, ref):
 
 
 def serving_bench(L, W, args):
-    """Served log-determinants (the serving workload): requests of uneven n,
-    kind and Krylov depth.  Baseline: plain FP64 estimates one at a time.
-    Served: FP32 or FP16 Krylov vectors through ld_submit with continuous batching,
-    (i) all requests at t = 0 (throughput), (ii) Poisson arrivals at 0.7x the
-    FP64 sequential rate (latency).  Every served result is checked against
-    its own FP64 result."""
+    """Served log-determinants (the serving workload): requests of uneven n
+    (log-uniform up to 2e6), kind (2D / 3D Laplacian, Wendland covariance),
+    shift and Krylov depth, every matrix built and resident before the clock.
+    Baseline: plain FP64 estimates one at a time.  Served with continuous
+    batching: (i) every request submitted at t = 0 (throughput), with FP32
+    Krylov vectors (the mixed precision) and with LD_PREC_AUTO; (ii) Poisson
+    arrivals at 0.7x the FP64 sequential rate (latency p50 / p99).  Every
+    served result is compared with its own FP64 result."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     reqs = W.request_stream(args.serve_requests, seed=1, rate_hz=1.0, n_min=1e4,
                             n_max=args.serve_nmax)
-    t0 = time.perf_counter()
-    mats = [W.build_request_matrix(r) for r in reqs]
-    t_build = time.perf_counter() - t0
-    print(f"[bench] serving: built {len(mats)} matrices in {t_build:.1f} s", file=sys.stderr,
-          flush=True)
     ctx = L.Context(0, max_slots=args.serve_slots)
     try:
-        # FP64 storage: the mixed requests read FP64 values with FP64 row sums
-        # (FP32 vectors), which keeps ill-conditioned requests (small nuggets)
-        # well inside the 1e-4 gate
-        hs = [ctx.matrix(a, vt=L.LD_VT_FP64, lo_hint=(r["shift"] if r["kind"] == "wendland" else 0.0))
-              for a, r in zip(mats, reqs)]
+        # build on host threads, upload in request order as each finishes (the
+        # host copy is dropped after the upload)
+        t0 = time.perf_counter()
+        hs = [None] * len(reqs)
+        nnz = 0
+        with ThreadPoolExecutor(max_workers=8) as ex:
+            futs = [ex.submit(W.build_request_matrix, r) for r in reqs]
+            for i, (f, r) in enumerate(zip(futs, reqs)):
+                a = f.result()
+                nnz += a.nnz
+                # FP64 storage: the mixed requests read FP64 values with FP64
+                # row sums (FP32 vectors), which keeps the ill-conditioned
+                # requests (nuggets down to 1e-3) well inside the 1e-4 gate
+                hs[i] = ctx.matrix(a, vt=L.LD_VT_FP64,
+                                   lo_hint=(r["shift"] if r["kind"] == "wendland" else 0.0))
+                futs[i] = None
+                del a
+        t_build = time.perf_counter() - t0
+        ns = np.array([r["size"] ** {"lap2d": 2, "lap3d": 3}.get(r["kind"], 1) for r in reqs],
+                      dtype=np.float64)
+        print(f"[bench] serving: built and uploaded {len(reqs)} matrices ({nnz / 1e9:.2f}e9 "
+              f"entries) in {t_build:.1f} s", file=sys.stderr, flush=True)
 
         def params(r, prec):
             return L.make_params(r["n_probes"], r["sketch_rank"], r["krylov_steps"],
                                  r["iop_window"], 1000 + r["id"], precision=prec)
         # warm the kernels once
         L.ld_estimate_ex(hs[0], params(reqs[0], L.LD_PREC_FP64))
+        L.ld_estimate_ex(hs[0], params(reqs[0], L.LD_PREC_MIXED))
         t0 = time.perf_counter()
         ref = [L.ld_estimate_ex(h, params(r, L.LD_PREC_FP64)).logdet for h, r in zip(hs, reqs)]
         t_seq = time.perf_counter() - t0
         seq_rate = len(reqs) / t_seq
         print(f"[bench] serving: FP64 sequential {seq_rate:.1f} logdets/s", file=sys.stderr,
               flush=True)
-        # (i) saturation: everything submitted at once
-        t0 = time.perf_counter()
-        sprec = PRECISIONS[args.serve_precision](L)
-        tickets = [L.ld_submit(h, params(r, sprec)) for h, r in zip(hs, reqs)]
-        served = [L.ld_wait(ctx.handle, t) for t in tickets]
-        t_sat = time.perf_counter() - t0
-        sat_rate = len(reqs) / t_sat
-        errs = [abs(sv.logdet - rf) / abs(rf) for sv, rf in zip(served, ref)]
-        print(f"[bench] serving: {args.serve_precision} served {sat_rate:.1f} logdets/s, max rel err "
-              f"{max(errs):.2e}", file=sys.stderr, flush=True)
-        # (ii) Poisson arrivals at 0.7x the FP64 sequential rate
+        out = {"requests": len(reqs), "n_range": [1e4, args.serve_nmax],
+               "n_median": float(np.median(ns)), "n_max_drawn": float(ns.max()),
+               "kinds": {k: sum(1 for r in reqs if r["kind"] == k)
+                         for k in ("lap2d", "lap3d", "wendland")},
+               "matrix_entries": nnz, "host_build_and_upload_s": t_build,
+               "fp64_sequential_logdets_per_s": seq_rate, "slots": args.serve_slots}
+
+        def saturate(prec):
+            st0 = L.ld_serving_stats_get(ctx.handle)
+            t0 = time.perf_counter()
+            tickets = [L.ld_submit(h, params(r, prec)) for h, r in zip(hs, reqs)]
+            served = [L.ld_wait(ctx.handle, t) for t in tickets]
+            dt = time.perf_counter() - t0
+            st1 = L.ld_serving_stats_get(ctx.handle)
+            errs = [abs(sv.logdet - rf) / abs(rf) for sv, rf in zip(served, ref)]
+            return {"logdets_per_s": len(reqs) / dt, "wall_s": dt,
+                    "speedup_vs_fp64_sequential": len(reqs) / dt / seq_rate,
+                    "max_rel_err_vs_fp64": max(errs),
+                    "requests_over_1e-4": sum(1 for e in errs if e > 1e-4),
+                    "batched_launches": st1.batched_launches - st0.batched_launches,
+                    "batched_steps": st1.batched_steps - st0.batched_steps,
+                    "graph_replays": st1.graph_replays - st0.graph_replays}
+        out["served_mixed"] = saturate(L.LD_PREC_MIXED)
+        print(f"[bench] serving: mixed {out['served_mixed']}", file=sys.stderr, flush=True)
+        out["served_auto"] = saturate(L.LD_PREC_AUTO)
+        print(f"[bench] serving: auto {out['served_auto']}", file=sys.stderr, flush=True)
+        # (ii) Poisson arrivals at 0.7x the FP64 sequential rate, mixed precision
         rate = 0.7 * seq_rate
         rng = np.random.Generator(np.random.PCG64(7))
         arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
@@ -418,7 +447,7 @@ def serving_bench(L, W, args):
         while i < len(reqs) or pending:
             now = time.perf_counter() - start
             while i < len(reqs) and arrivals[i] <= now:
-                pending[L.ld_submit(hs[i], params(reqs[i], sprec))] = i
+                pending[L.ld_submit(hs[i], params(reqs[i], L.LD_PREC_MIXED))] = i
                 i += 1
             for t in list(pending):
                 res = L.ld_poll(ctx.handle, t)
@@ -427,16 +456,16 @@ def serving_bench(L, W, args):
                     del pending[t]
             time.sleep(0.0002)
         lat = np.array(lat)
-        out = {"requests": len(reqs), "n_range": [1e4, args.serve_nmax],
-               "fp64_sequential_logdets_per_s": seq_rate,
-               "served_precision": args.serve_precision,
-               "served_logdets_per_s": sat_rate,
-               "speedup_vs_fp64_sequential": sat_rate / seq_rate,
-               "max_rel_err_vs_fp64": max(errs),
-               "poisson_rate_hz": rate,
-               "p50_latency_ms": float(np.percentile(lat, 50)),
-               "p99_latency_ms": float(np.percentile(lat, 99)),
-               "slots": args.serve_slots}
+        st = L.ld_serving_stats_get(ctx.handle)
+        out.update({"served_precision": "mixed (FP32 Krylov vectors)",
+                    "served_logdets_per_s": out["served_mixed"]["logdets_per_s"],
+                    "speedup_vs_fp64_sequential": out["served_mixed"]["speedup_vs_fp64_sequential"],
+                    "max_rel_err_vs_fp64": out["served_mixed"]["max_rel_err_vs_fp64"],
+                    "poisson_rate_hz": rate,
+                    "p50_latency_ms": float(np.percentile(lat, 50)),
+                    "p99_latency_ms": float(np.percentile(lat, 99)),
+                    "peak_held_bytes": st.peak_held_bytes, "budget_bytes": st.budget_bytes,
+                    "peak_active": st.peak_active})
         for h in hs:
             ctx.release(h)
         return out

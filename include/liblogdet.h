@@ -148,10 +148,10 @@ typedef struct {
                                 2 runs the sketch recurrences twice, the first
                                 time for H_m only, the second time adding each
                                 basis vector into Y while it is still in a ring
-                                of min(k, m) + 9 blocks (the same values and
-                                sums, bitwise: about m - 1 more sketch steps
-                                for m + 1 - (min(k, m) + 9) fewer blocks).
-                                OSLQ (whose sketch is one product): 0 or 1    */
+                                of min(m + 1, min(k, m) + 9) blocks: the same
+                                values and sums, bitwise, for about m - 1 more
+                                sketch steps.  OSLQ (whose sketch is one
+                                product): 0 or 1                                */
 } ld_params;
 
 typedef struct {
@@ -320,6 +320,24 @@ ld_status ld_submit(ld_matrix* a, const ld_params* p, uint64_t* ticket);
 ld_status ld_poll(ld_ctx* ctx, uint64_t ticket, ld_result* out);
 /* Blocks until the request finishes, then behaves as ld_poll. */
 ld_status ld_wait(ld_ctx* ctx, uint64_t ticket, ld_result* out);
+
+/* Serving scheduler statistics of a context (zero before the first
+ * ld_submit).  held_bytes is what the resident slots' device buffers hold
+ * now, idle slots included; the scheduler keeps it at or below
+ * budget_bytes (ld_ctx_opts.hbm_budget_bytes), releasing idle buffers before
+ * a slot grows, and peak_held_bytes is the most it has held.  A batched
+ * launch advances every resident request by one Krylov step; graph_replays
+ * counts the scheduler rounds replayed from a captured HIP graph and
+ * graph_captures the graphs it captured (a new slot-table shape). */
+typedef struct {
+  uint64_t submitted, completed, ticks;
+  uint64_t batched_steps, batched_launches;
+  uint64_t held_bytes, peak_held_bytes, budget_bytes;
+  uint64_t buffer_allocs, buffer_frees;
+  uint64_t graph_replays, graph_captures;
+  int32_t peak_active, max_slots;
+} ld_serving_stats;
+ld_status ld_serving_stats_get(ld_ctx* ctx, ld_serving_stats* out);
 
 /* Instrumentation (off by default).  While enabled, every launch of a kernel
  * family in `family_mask` is bracketed by two HIP events recorded on the

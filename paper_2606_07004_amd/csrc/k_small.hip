@@ -383,6 +383,72 @@ __global__ __launch_bounds__(kThreads) void k_combine16(int64_t n, int ld, int n
   }
 }
 
+// Up to kMaxFill ranges of 32-bit words, grid-stride over the concatenation.
+struct FillArgs {
+  FillItem it[kMaxFill];
+  size_t end[kMaxFill];  // running sums of n32
+  int count;
+};
+__global__ __launch_bounds__(kThreads) void k_fill(FillArgs a) {
+  const size_t total = a.end[a.count - 1];
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * kThreads) {
+    int r = 0;
+    while (i >= a.end[r]) ++r;
+    const size_t j = i - (r ? a.end[r - 1] : 0);
+    static_cast<uint32_t*>(a.it[r].p)[j] = a.it[r].val;
+  }
+}
+
+hipError_t launch_fill(hipStream_t st, const FillItem* items, int count) {
+  if (count < 1 || count > kMaxFill || !items) return hipErrorInvalidValue;
+  FillArgs a{};
+  size_t run = 0;
+  for (int r = 0; r < count; ++r) {
+    if (!items[r].p && items[r].n32) return hipErrorInvalidValue;
+    a.it[r] = items[r];
+    run += items[r].n32;
+    a.end[r] = run;
+  }
+  a.count = count;
+  if (run == 0) return hipSuccess;
+  const size_t nb = std::min<size_t>((run + kThreads - 1) / kThreads, 4 * kMaxBlocks);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void k_pack_results(int ld, const double* __restrict__ K,
+                                                          const double* __restrict__ norm2,
+                                                          const int* __restrict__ meff,
+                                                          const int* __restrict__ flags,
+                                                          const int* __restrict__ dflag,
+                                                          const int* __restrict__ meff0,
+                                                          char* __restrict__ out) {
+  double* oK = reinterpret_cast<double*>(out);
+  double* oN = oK + ld;
+  int* oM = reinterpret_cast<int*>(oN + ld);
+  int* oF = oM + ld;
+  int* oD = oF + ld;
+  int* oM0 = oD + 4;
+  for (int i = threadIdx.x; i < ld; i += kThreads) {
+    oK[i] = K[i];
+    oN[i] = norm2[i];
+    oM[i] = meff[i];
+    oF[i] = flags[i];
+    oM0[i] = meff0 ? meff0[i] : 0;
+  }
+  if (threadIdx.x < 4) oD[threadIdx.x] = dflag[threadIdx.x];
+}
+
+hipError_t launch_pack_results(hipStream_t st, int ld, const double* K, const double* norm2,
+                               const int* meff, const int* flags, const int* dflag,
+                               const int* meff0, void* out) {
+  if (ld < 1 || !K || !norm2 || !meff || !flags || !dflag || !out) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pack_results, dim3(1), dim3(kThreads), 0, st, ld, K, norm2, meff, flags,
+                     dflag, meff0, static_cast<char*>(out));
+  return hipGetLastError();
+}
+
 // Plain copy, 16 bytes per lane, grid-stride (calibration of byte counters).
 __global__ __launch_bounds__(kThreads) void k_copy16(const float4* __restrict__ a,
                                                     float4* __restrict__ b, size_t n16) {

@@ -322,6 +322,25 @@ hipError_t launch_project(hipStream_t st, const Geom& g, const double* A, int ld
                           const GSrc& Gm, int r, const double* P, void* X0, double* part,
                           double oscale);
 
+// Fill up to kMaxFill ranges of 32-bit words with a value each, in one launch
+// (kernels, not memset nodes: the estimate's launches can be captured in a
+// HIP graph and replayed).
+constexpr int kMaxFill = 4;
+struct FillItem {
+  void* p;
+  size_t n32;    // 32-bit words
+  uint32_t val;
+};
+hipError_t launch_fill(hipStream_t st, const FillItem* items, int count);
+
+// The per-run results an estimate hands back, packed for one copy:
+// [K: ld doubles | norm2: ld doubles | meff: ld ints | flags: ld ints |
+//  dflag: 4 ints | meff0: ld ints] (meff0 may be null: zeros).
+inline size_t pack_results_bytes(int ld) { return (size_t)ld * 28 + 16; }
+hipError_t launch_pack_results(hipStream_t st, int ld, const double* K, const double* norm2,
+                               const int* meff, const int* flags, const int* dflag,
+                               const int* meff0, void* out);
+
 // Plain device copy of `bytes` (multiple of 16 used), calibration only.
 hipError_t launch_copy16(hipStream_t st, const void* src, void* dst, size_t bytes);
 // Bandwidth probe: reads `reads` (1..3) streams src[0..reads-1] of `bytes`

@@ -369,7 +369,7 @@ size_t Run::layout(char* base) {
     // window plus one combine batch); phase 1 is a ring (OSA-IOP also keeps
     // v1)
     const int ring = std::min(k_, m_) + (p_.method == LD_METHOD_OSA_IOP ? 2 : 1);
-    const int ring0 = two_pass_ ? std::min(k_, m_) + 1 + kCombBatch : m_ + 1;
+    const int ring0 = two_pass_ ? std::min(m_ + 1, std::min(k_, m_) + 1 + kCombBatch) : m_ + 1;
     nslots_ = std::max(ring0, ring);
     slot_bytes = std::max((size_t)ring0 * n * ld1_ * xb_, (size_t)ring * n * ldB_ * xb_);
   }
@@ -513,7 +513,7 @@ ld_status Run::begin_krylov(int phase) {
     kgu_ = g1u_;
     kpin_ = false;
     kfull_ = !two_pass_;
-    kns_ = two_pass_ ? std::min(k_, m_) + 1 + kCombBatch : m_ + 1;
+    kns_ = two_pass_ ? std::min(m_ + 1, std::min(k_, m_) + 1 + kCombBatch) : m_ + 1;
   } else {
     kB_ = B_;
     kld_ = ldB_;
@@ -1924,6 +1924,33 @@ static ld::Server* server_of(ld_ctx* ctx) {
   std::lock_guard<std::mutex> lk(ctx->server_mu);
   if (!ctx->server) ctx->server.reset(new ld::Server(ctx));
   return ctx->server.get();
+}
+
+ld_status ld_serving_stats_get(ld_ctx* ctx, ld_serving_stats* out) {
+  if (!ctx || !out) return set_error(LD_E_INVALID_ARG, "null argument");
+  ld_serving_stats o{};
+  o.max_slots = ctx->opts.max_slots;
+  o.budget_bytes = ctx->opts.hbm_budget_bytes;
+  {
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    if (ctx->server) {
+      const ld::Server::Stats st = ctx->server->stats();
+      o.submitted = st.submitted;
+      o.completed = st.completed;
+      o.ticks = st.ticks;
+      o.batched_steps = st.batched_steps;
+      o.batched_launches = st.batched_launches;
+      o.held_bytes = st.held_bytes;
+      o.peak_held_bytes = st.peak_bytes;
+      o.buffer_allocs = st.buffer_allocs;
+      o.buffer_frees = st.buffer_frees;
+      o.graph_replays = st.graph_replays;
+      o.graph_captures = st.graph_captures;
+      o.peak_active = st.peak_active;
+    }
+  }
+  *out = o;
+  return LD_OK;
 }
 
 ld_status ld_submit(ld_matrix* a, const ld_params* p, uint64_t* ticket) {

@@ -1,6 +1,7 @@
 // Serving scheduler (continuous batching).  See serve.h.
 #include "serve.h"
 
+#include <algorithm>
 #include <chrono>
 
 ld_ctx::ld_ctx() = default;
@@ -75,7 +76,10 @@ ld_status Server::poll(uint64_t ticket, ld_result* out, bool wait) {
 
 Server::Stats Server::stats() {
   std::unique_lock<std::mutex> lk(mu_);
-  return stats_;
+  Stats st = stats_;
+  st.held_bytes = held_;
+  st.budget_bytes = budget_;
+  return st;
 }
 
 void Server::finish(Slot& s, ld_status st, const ld_result* res, const std::string& err) {
@@ -87,7 +91,6 @@ void Server::finish(Slot& s, ld_status st, const ld_result* res, const std::stri
   {
     std::unique_lock<std::mutex> lk(mu_);
     done_[s.req->ticket] = d;
-    used_ -= s.req->bytes;
     ++stats_.completed;
   }
   a->inflight.fetch_sub(1);
@@ -111,30 +114,59 @@ void Server::loop() {
         if (stop_ && queue_.empty()) return;
       }
       // each admitted request takes the free slot with the smallest buffer
-      // that already fits it, else the free slot with the largest buffer (to
-      // grow), so slot buffers are rarely reallocated
+      // that already fits it (no new memory), else the free slot with the
+      // largest buffer, grown to the request's size.  The ledger charges
+      // every slot's buffer, idle ones included: a growth that would take the
+      // buffers past the budget first releases idle buffers of other slots
+      // (largest first), and the request waits when even that is not enough
       for (auto it = queue_.begin(); it != queue_.end();) {
-        if (used_ + (*it)->bytes > budget_) {
-          ++it;
-          continue;
-        }
+        const size_t want = (*it)->bytes;
         Slot* fit = nullptr;
         Slot* big = nullptr;
         for (Slot& s : slots_) {
-          if (s.req) continue;
-          if (s.mem_bytes >= (*it)->bytes && (!fit || s.mem_bytes < fit->mem_bytes)) fit = &s;
+          // a slot whose buffer is being given up takes no request this tick
+          if (s.req || s.release) continue;
+          if (s.mem_bytes >= want && (!fit || s.mem_bytes < fit->mem_bytes)) fit = &s;
           if (!big || s.mem_bytes > big->mem_bytes) big = &s;
         }
         Slot* s = fit ? fit : big;
         if (!s) break;  // no free slot
+        if (!fit) {
+          // growth: the slot's buffer goes from its size to `want`
+          const size_t have = s->mem_bytes;
+          size_t need = held_ - have + want;
+          if (need > budget_) {
+            std::vector<Slot*> idle;
+            for (Slot& o : slots_)
+              if (&o != s && !o.req && !o.release && o.mem_bytes > 0) idle.push_back(&o);
+            std::sort(idle.begin(), idle.end(),
+                      [](const Slot* a, const Slot* b) { return a->mem_bytes > b->mem_bytes; });
+            size_t freeable = 0;
+            for (Slot* o : idle) freeable += o->mem_bytes;
+            if (need - std::min(need, freeable) > budget_) {
+              ++it;  // waits for running requests to finish
+              continue;
+            }
+            for (Slot* o : idle) {
+              if (need <= budget_) break;
+              o->release = true;
+              held_ -= o->mem_bytes;
+              need -= o->mem_bytes;
+            }
+          }
+          held_ = held_ - have + want;
+          s->want_bytes = want;
+        } else {
+          s->want_bytes = s->mem_bytes;
+        }
         s->req = std::move(*it);
         it = queue_.erase(it);
-        used_ += s->req->bytes;
       }
       int act = 0;
       for (Slot& s : slots_) act += s.req ? 1 : 0;
       if (act > stats_.peak_active) stats_.peak_active = act;
-      if (used_ > stats_.peak_bytes) stats_.peak_bytes = used_;
+      if (held_ > stats_.peak_bytes) stats_.peak_bytes = held_;
+      stats_.held_bytes = held_;
       ++stats_.ticks;
     }
     // bind newly admitted requests
@@ -144,6 +176,21 @@ void Server::loop() {
         if (s.req) finish(s, LD_E_DEVICE, nullptr, "stream creation failed");
       continue;
     }
+    // idle buffers given up to make room (their requests finished: the
+    // stream is drained first, as freeing device memory synchronises anyway)
+    bool synced = false;
+    for (Slot& s : slots_) {
+      if (!s.release) continue;
+      if (!synced) {
+        (void)hipStreamSynchronize(stream_);
+        synced = true;
+      }
+      if (s.mem) (void)hipFree(s.mem);
+      s.mem = nullptr;
+      s.mem_bytes = 0;
+      s.release = false;
+      ++stats_.buffer_frees;
+    }
     for (Slot& s : slots_) {
       if (!s.req || s.enqueued_all || s.bound) continue;
       if (!s.done_ev && hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming) != hipSuccess) {
@@ -151,20 +198,26 @@ void Server::loop() {
         finish(s, LD_E_DEVICE, nullptr, "event creation failed");
         continue;
       }
-      if (s.mem_bytes < s.req->bytes) {
+      if (s.mem_bytes < s.want_bytes) {
         if (s.mem) {
           (void)hipStreamSynchronize(stream_);
           (void)hipFree(s.mem);
           s.mem = nullptr;
-          s.mem_bytes = 0;
+          ++stats_.buffer_frees;
         }
-        if (hipMalloc(&s.mem, s.req->bytes) != hipSuccess) {
+        s.mem_bytes = 0;
+        if (hipMalloc(&s.mem, s.want_bytes) != hipSuccess) {
           (void)hipGetLastError();
           s.mem = nullptr;
+          {
+            std::unique_lock<std::mutex> lk(mu_);
+            held_ -= s.want_bytes;  // charged at admission, never allocated
+          }
           finish(s, LD_E_NO_MEMORY, nullptr, "device allocation for a request failed");
           continue;
         }
-        s.mem_bytes = s.req->bytes;
+        s.mem_bytes = s.want_bytes;
+        ++stats_.buffer_allocs;
       }
       // a slot's memory is reused only after its previous request's work:
       // every request runs on the one scheduler stream, in order

@@ -26,7 +26,11 @@ class Server {
   struct Stats {
     uint64_t submitted = 0, completed = 0, ticks = 0;
     uint64_t batched_steps = 0, batched_launches = 0;  // Krylov steps, batches
-    size_t peak_bytes = 0;
+    size_t peak_bytes = 0;       // most device bytes the slot buffers held at once
+    size_t held_bytes = 0;       // device bytes the slot buffers hold now
+    uint64_t buffer_allocs = 0, buffer_frees = 0;
+    uint64_t graph_replays = 0, graph_captures = 0;
+    size_t budget_bytes = 0;
     int peak_active = 0;
   };
   Stats stats();
@@ -41,7 +45,9 @@ class Server {
     hipEvent_t done_ev = nullptr;
     std::unique_ptr<Request> req;
     void* mem = nullptr;
-    size_t mem_bytes = 0;
+    size_t mem_bytes = 0;        // bytes of the buffer (charged to held_)
+    size_t want_bytes = 0;       // buffer size the admitted request needs
+    bool release = false;        // idle buffer to free before the next binding
     bool enqueued_all = false;
     bool bound = false;
   };
@@ -61,7 +67,9 @@ class Server {
   std::map<uint64_t, bool> live_;   // submitted and not yet retired
   std::vector<Slot> slots_;
   hipStream_t stream_ = nullptr;    // the scheduler's stream
-  size_t budget_ = 0, used_ = 0;
+  // budget_: device bytes the slot buffers may hold; held_: what they hold
+  // (idle slots keep their buffers for reuse, so they are charged too)
+  size_t budget_ = 0, held_ = 0;
   uint64_t next_ticket_ = 1;
   bool stop_ = false;
   int steps_per_tick_ = 4;

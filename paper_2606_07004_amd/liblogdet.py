@@ -71,6 +71,19 @@ class ld_result(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ld_serving_stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("ticks", C.c_uint64),
+                ("batched_steps", C.c_uint64), ("batched_launches", C.c_uint64),
+                ("held_bytes", C.c_uint64), ("peak_held_bytes", C.c_uint64),
+                ("budget_bytes", C.c_uint64), ("buffer_allocs", C.c_uint64),
+                ("buffer_frees", C.c_uint64), ("graph_replays", C.c_uint64),
+                ("graph_captures", C.c_uint64), ("peak_active", C.c_int32),
+                ("max_slots", C.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _DP = C.POINTER(C.c_double)
 _IP = C.POINTER(C.c_int32)
 
@@ -115,6 +128,7 @@ _SIGNATURES = [
                                        C.POINTER(ld_detail)]),
     ("ld_estimate_noalloc", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(ld_result)]),
     ("ld_submit", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(C.c_uint64)]),
+    ("ld_serving_stats_get", C.c_int32, [C.c_void_p, C.POINTER(ld_serving_stats)]),
     ("ld_poll", C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(ld_result)]),
     ("ld_wait", C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(ld_result)]),
     ("ld_profile_enable", C.c_int32, [C.c_void_p, C.c_uint32]),
@@ -291,6 +305,12 @@ def ld_tune_set(a, params: ld_params, spmm_lanes: int, spmm_chunks: int, update_
     """Store a given product / update geometry for the estimate block of `params`."""
     _check(lib().ld_tune_set(a, C.byref(params), int(spmm_lanes), int(spmm_chunks),
                              int(spmm_entry_split), int(update_lanes), int(update_chunks)))
+
+
+def ld_serving_stats_get(ctx) -> ld_serving_stats:
+    out = ld_serving_stats()
+    _check(lib().ld_serving_stats_get(ctx, C.byref(out)))
+    return out
 
 
 def ld_submit(a, params: ld_params) -> int:

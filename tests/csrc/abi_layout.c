@@ -29,5 +29,13 @@ int main(void) {
   F(ld_tune_result, update_ms); F(ld_tune_result, update_default_ms);
   F(ld_tune_result, candidates); F(ld_tune_result, spmm_entry_split);
   Z(ld_tune_result);
+  F(ld_serving_stats, submitted); F(ld_serving_stats, completed); F(ld_serving_stats, ticks);
+  F(ld_serving_stats, batched_steps); F(ld_serving_stats, batched_launches);
+  F(ld_serving_stats, held_bytes); F(ld_serving_stats, peak_held_bytes);
+  F(ld_serving_stats, budget_bytes); F(ld_serving_stats, buffer_allocs);
+  F(ld_serving_stats, buffer_frees); F(ld_serving_stats, graph_replays);
+  F(ld_serving_stats, graph_captures); F(ld_serving_stats, peak_active);
+  F(ld_serving_stats, max_slots);
+  Z(ld_serving_stats);
   return 0;
 }

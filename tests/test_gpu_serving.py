@@ -138,3 +138,45 @@ def test_serving_many_small_requests_throughput(L):
         t_srv = time.perf_counter() - t0
     assert got == seq
     print(f"  sequential {40 / t_seq:.1f} logdets/s, served {40 / t_srv:.1f} logdets/s")
+
+
+def test_budget_charges_idle_slot_buffers(L):
+    # A budget that holds about two of the large requests (or one large and
+    # several small ones).  Idle slots keep their buffers for reuse, so the
+    # ledger charges them too: the bytes the slot buffers hold never pass the
+    # budget (idle buffers are released before a slot grows), no admitted
+    # request fails to allocate, and every result equals the request alone.
+    print("\n[case] serving: ledger with idle slot buffers", flush=True)
+    small = W.lap2d(40, 0.2)
+    large = W.lap3d(40, 0.05)
+    with L.Context(0) as c0:
+        hs, hl = c0.matrix(small), c0.matrix(large)
+        ps = L.make_params(12, 4, 10, 2, 1)
+        pl = L.make_params(40, 12, 20, 2, 2)
+        b_small, b_large = L.ld_request_bytes(hs, ps), L.ld_request_bytes(hl, pl)
+    assert b_large > 20 * b_small
+    budget = int(2.2 * b_large)
+    reqs = []
+    for i in range(16):
+        big = i % 3 == 1
+        reqs.append((1 if big else 0,
+                     L.make_params(40 if big else 12, 12 if big else 4, 20 if big else 10, 2,
+                                   50 + i)))
+    mats = [small, large]
+    ref = _alone(L, mats, reqs)
+    c = L.Context(0, max_slots=6, hbm_budget_bytes=budget)
+    try:
+        hm = [c.matrix(a) for a in mats]
+        tickets = [L.ld_submit(hm[i], p) for i, p in reqs]
+        got = [L.ld_wait(c.handle, t) for t in tickets]
+        st = L.ld_serving_stats_get(c.handle)
+        print(f"  budget {budget} peak held {st.peak_held_bytes} allocs {st.buffer_allocs} "
+              f"frees {st.buffer_frees} peak active {st.peak_active}", flush=True)
+        assert st.budget_bytes == budget
+        assert st.peak_held_bytes <= budget
+        assert st.completed == len(reqs)
+        assert [g.logdet for g in got] == ref  # no LD_E_NO_MEMORY, same results
+        for h in hm:
+            c.release(h)
+    finally:
+        c.close()

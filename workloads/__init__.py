@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 import scipy.sparse as sp
@@ -67,26 +68,41 @@ def from_dense(a: np.ndarray, name: str = "dense") -> Csr:
 
 def _stencil(dims, shift: float, name: str) -> Csr:
     """Dirichlet Laplacian on a tensor grid with natural (first axis fastest)
-    ordering: diagonal 2*len(dims) + shift, -1 to each grid neighbour."""
+    ordering: diagonal 2*len(dims) + shift, -1 to each grid neighbour.
+
+    Built row-major straight into CSR: every row's candidate columns are
+    its neighbours at offsets -stride_k .. +stride_k (ascending, so each row's
+    columns come out sorted), kept where the neighbour lies on the grid."""
     dims = tuple(int(d) for d in dims)
     n = int(np.prod(dims))
     idx = np.arange(n, dtype=np.int64)
-    rows = [idx]
-    cols = [idx]
-    vals = [np.full(n, 2.0 * len(dims) + shift)]
-    stride = 1
-    for d in dims:
-        coord = (idx // stride) % d
-        for step in (-1, 1):
-            ok = (coord + step >= 0) & (coord + step < d)
-            rows.append(idx[ok])
-            cols.append(idx[ok] + step * stride)
-            vals.append(np.full(int(ok.sum()), -1.0))
-        stride *= d
-    m = sp.coo_matrix((np.concatenate(vals),
-                       (np.concatenate(rows), np.concatenate(cols))),
-                      shape=(n, n))
-    return _from_scipy(m, name)
+    strides = np.cumprod((1,) + dims[:-1]).astype(np.int64)
+    offs, checks = [], []
+    for k in reversed(range(len(dims))):      # -stride_last ... -1
+        offs.append(-strides[k])
+        checks.append((k, -1))
+    offs.append(0)
+    checks.append(None)
+    for k in range(len(dims)):                # +1 ... +stride_last
+        offs.append(strides[k])
+        checks.append((k, 1))
+    cand = np.empty((n, len(offs)), dtype=np.int64)
+    valid = np.empty((n, len(offs)), dtype=bool)
+    for j, (off, chk) in enumerate(zip(offs, checks)):
+        cand[:, j] = idx + off
+        if chk is None:
+            valid[:, j] = True
+        else:
+            k, step = chk
+            coord = (idx // strides[k]) % dims[k]
+            valid[:, j] = (coord + step >= 0) & (coord + step < dims[k])
+    counts = valid.sum(axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col_idx = cand[valid]
+    vals = np.where(col_idx == np.repeat(idx, counts), 2.0 * len(dims) + shift, -1.0)
+    return Csr(n=n, row_ptr=row_ptr.astype(np.int32), col_idx=col_idx.astype(np.int32),
+               values=np.ascontiguousarray(vals, dtype=np.float64), name=name)
 
 
 def lap2d(N: int, shift: float) -> Csr:
@@ -151,15 +167,47 @@ def er_laplacian(n: int, n_edges: int, seed: int = 0, shift: float = 0.05,
     return _from_scipy(m, f"er_{n}_{n_edges}_seed{seed}")
 
 
+def _wendland_native(h, n, pts, cell_sorted, ncell, rho, scale, nugget, name) -> Csr:
+    """The C helper's neighbour search over the 3 x 3 cells around each point
+    (rows split over host threads); the same matrix as the NumPy path."""
+    import ctypes as C
+    from concurrent.futures import ThreadPoolExecutor
+    cell_start = np.searchsorted(cell_sorted, np.arange(ncell * ncell + 1), side="left")
+    cell_start = np.ascontiguousarray(cell_start, dtype=np.int64)
+    cell_sorted = np.ascontiguousarray(cell_sorted, dtype=np.int64)
+    dp, i64p, i32p = C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32)
+    pp, cp, sp_ = pts.ctypes.data_as(dp), cell_sorted.ctypes.data_as(i64p), \
+        cell_start.ctypes.data_as(i64p)
+    nt = max(1, min(16, os.cpu_count() or 1, n // 65536))
+    bounds = [(n * t // nt, n * (t + 1) // nt) for t in range(nt)]
+    counts = np.zeros(n, dtype=np.int64)
+    with ThreadPoolExecutor(nt) as ex:
+        list(ex.map(lambda b: h.wendland_count(b[0], b[1], pp, cp, sp_, ncell, rho,
+                                               counts.ctypes.data_as(i64p)), bounds))
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] >= 2**31:
+        raise ValueError("wendland: nnz does not fit int32")
+    col = np.empty(int(row_ptr[-1]), dtype=np.int32)
+    val = np.empty(int(row_ptr[-1]), dtype=np.float64)
+    with ThreadPoolExecutor(nt) as ex:
+        list(ex.map(lambda b: h.wendland_fill(b[0], b[1], pp, cp, sp_, ncell, rho, scale, nugget,
+                                              row_ptr.ctypes.data_as(i64p), col.ctypes.data_as(i32p),
+                                              val.ctypes.data_as(dp)), bounds))
+    return Csr(n=n, row_ptr=row_ptr.astype(np.int32), col_idx=col, values=val, name=name)
+
+
 def wendland(n: int, nnz_per_row: float = 48.0, nugget: float = 1e-2,
-             seed: int = 0, scale: float = 1.0) -> Csr:
+             seed: int = 0, scale: float = 1.0, use_native: bool = True) -> Csr:
     """Wendland C2 covariance matrix on n uniform points in [0,1]^2.
 
     phi(r) = (1 - r/rho)^4_+ (4 r/rho + 1) with support radius
     rho = sqrt(nnz_per_row / (pi n)), so an interior row holds about
     nnz_per_row off-diagonal entries; diagonal = scale*phi(0) + nugget.
     Points (PCG64(seed)) are sorted by rho-cell, row-major over cells, so that
-    neighbouring rows are neighbouring points.
+    neighbouring rows are neighbouring points.  With the C helper built
+    (workloads.native) the neighbour search runs there, giving bitwise the
+    matrix of the NumPy path (use_native=False).
     """
     from scipy.spatial import cKDTree
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -168,20 +216,32 @@ def wendland(n: int, nnz_per_row: float = 48.0, nugget: float = 1e-2,
     ncell = max(1, int(math.floor(1.0 / rho)))
     cx = np.minimum((pts[:, 0] * ncell).astype(np.int64), ncell - 1)
     cy = np.minimum((pts[:, 1] * ncell).astype(np.int64), ncell - 1)
-    order = np.argsort(cy * ncell + cx, kind="stable")
+    cell = cy * ncell + cx
+    order = np.argsort(cell, kind="stable")
     pts = np.ascontiguousarray(pts[order])
+    name = f"wendland_{n}_nugget{nugget:g}_seed{seed}"
+    from . import native
+    h = native.lib() if use_native else None
+    if h is not None:
+        return _wendland_native(h, n, pts, np.ascontiguousarray(cell[order]), ncell, rho, scale,
+                                nugget, name)
     tree = cKDTree(pts)
     pairs = tree.query_pairs(rho, output_type="ndarray").astype(np.int64)
     d = pts[pairs[:, 0]] - pts[pairs[:, 1]]
     r = np.sqrt(d[:, 0] ** 2 + d[:, 1] ** 2) / rho
     keep = r < 1.0
     pairs, r = pairs[keep], r[keep]
-    phi = scale * (1.0 - r) ** 4 * (4.0 * r + 1.0)
+    # (1 - r)^4 as two squarings: only correctly rounded basic operations, so
+    # the values do not depend on the host's vectorised pow (and match the C
+    # helper's bit for bit)
+    t = 1.0 - r
+    t2 = t * t
+    phi = scale * (t2 * t2) * (4.0 * r + 1.0)
     rows = np.concatenate([pairs[:, 0], pairs[:, 1], np.arange(n)])
     cols = np.concatenate([pairs[:, 1], pairs[:, 0], np.arange(n)])
     vals = np.concatenate([phi, phi, np.full(n, scale + nugget)])
     m = sp.coo_matrix((vals, (rows, cols)), shape=(n, n))
-    return _from_scipy(m, f"wendland_{n}_nugget{nugget:g}_seed{seed}")
+    return _from_scipy(m, name)
 
 
 def wendland_grid(ny: int, nx: int, rho: float, nugget: float = 1e-2, scale: float = 1.0) -> Csr:
