@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--no-grf", action="store_true",
                     help="skip the GRF likelihood theta-sweep leg")
     ap.add_argument("--grf-grid", type=str, default="900x1200")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the kernel-by-kernel vs graph-replay leg")
     ap.add_argument("--tune-reps", type=int, default=10,
                     help="launches per candidate of the product/update geometry autotuner "
                          "(0 keeps the default geometry)")
@@ -360,15 +362,63 @@ def precision_variants(L, ctx, h, args, ref):
     return out
 
 
+def graph_bench(L, W, args):
+    """Launch overhead of a blocking estimate: kernel by kernel (graph mode
+    0) against a replayed HIP graph (mode 1), on 3D Laplacians from n = 1.1e4
+    to the headline size, mixed precision, the headline's probes, steps and
+    window, a new seed per call (one graph serves every seed).  wall_ms is
+    host time per estimate, device_ms the events around it; wall - device is
+    what the host adds.  Results of the two modes must be bitwise equal."""
+    out = {}
+    for grid in (22, 48, 80, args.grid):
+        rec = {}
+        for mode in (0, 1):
+            ctx = L.Context(0)
+            try:
+                L.ld_graph_mode(ctx.handle, mode)
+                a = W.lap3d(grid, args.shift)
+                h = ctx.matrix(a, vt=L.LD_VT_FP32)
+                rec["n"] = a.n
+
+                def est(seed):
+                    return L.ld_estimate_ex(h, L.make_params(
+                        args.probes, args.sketch, args.krylov_steps, args.window, seed,
+                        precision=L.LD_PREC_MIXED))
+                est(1)
+                est(2)  # mode 1: captured here
+                reps = 30 if a.n < 1e6 else 5
+                vals, dev = [], 0.0
+                t0 = time.perf_counter()
+                for i in range(reps):
+                    r = est(10 + i)
+                    vals.append(r.logdet)
+                    dev += r.device_ms
+                wall = (time.perf_counter() - t0) * 1e3 / reps
+                st = L.ld_graph_stats_get(ctx.handle)
+                rec["graph" if mode else "kernel_by_kernel"] = {
+                    "wall_ms": wall, "device_ms": dev / reps, "host_ms": wall - dev / reps,
+                    "replays": st.replays, "captures": st.captures, "logdets": vals}
+            finally:
+                ctx.close()
+        rec["bitwise_equal"] = rec["graph"]["logdets"] == rec["kernel_by_kernel"]["logdets"]
+        rec["speedup"] = rec["kernel_by_kernel"]["wall_ms"] / rec["graph"]["wall_ms"]
+        for k in ("graph", "kernel_by_kernel"):
+            del rec[k]["logdets"]
+        out[f"lap3d_{grid}"] = rec
+        print(f"[bench] graph leg lap3d {grid}: {rec}", file=sys.stderr, flush=True)
+    return out
+
+
 def serving_bench(L, W, args):
     """Served log-determinants (the serving workload): requests of uneven n
     (log-uniform up to 2e6), kind (2D / 3D Laplacian, Wendland covariance),
     shift and Krylov depth, every matrix built and resident before the clock.
     Baseline: plain FP64 estimates one at a time.  Served with continuous
-    batching: (i) every request submitted at t = 0 (throughput), with FP32
-    Krylov vectors (the mixed precision) and with LD_PREC_AUTO; (ii) Poisson
-    arrivals at 0.7x the FP64 sequential rate (latency p50 / p99).  Every
-    served result is compared with its own FP64 result."""
+    batching: (i) every request submitted at t = 0 (throughput), with
+    LD_PREC_AUTO (FP32 Krylov vectors where lambda_hi <= 4096 lambda_lo, FP64
+    beyond: the served form) and with FP32 vectors on every request; (ii)
+    Poisson arrivals at 0.7x the FP64 sequential rate, LD_PREC_AUTO (latency
+    p50 / p99).  Every served result is compared with its own FP64 result."""
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
     reqs = W.request_stream(args.serve_requests, seed=1, rate_hz=1.0, n_min=1e4,
@@ -430,13 +480,15 @@ def serving_bench(L, W, args):
                     "max_rel_err_vs_fp64": max(errs),
                     "requests_over_1e-4": sum(1 for e in errs if e > 1e-4),
                     "batched_launches": st1.batched_launches - st0.batched_launches,
-                    "batched_steps": st1.batched_steps - st0.batched_steps,
-                    "graph_replays": st1.graph_replays - st0.graph_replays}
-        out["served_mixed"] = saturate(L.LD_PREC_MIXED)
-        print(f"[bench] serving: mixed {out['served_mixed']}", file=sys.stderr, flush=True)
+                    "batched_steps": st1.batched_steps - st0.batched_steps}
+        ratios = [hi / lo for lo, hi in (L.ld_matrix_bounds(h) for h in hs)]
+        out["auto_fp32_requests"] = sum(1 for q in ratios if q <= 4096.0)
         out["served_auto"] = saturate(L.LD_PREC_AUTO)
         print(f"[bench] serving: auto {out['served_auto']}", file=sys.stderr, flush=True)
-        # (ii) Poisson arrivals at 0.7x the FP64 sequential rate, mixed precision
+        out["served_fp32_everywhere"] = saturate(L.LD_PREC_MIXED)
+        print(f"[bench] serving: fp32 everywhere {out['served_fp32_everywhere']}",
+              file=sys.stderr, flush=True)
+        # (ii) Poisson arrivals at 0.7x the FP64 sequential rate, LD_PREC_AUTO
         rate = 0.7 * seq_rate
         rng = np.random.Generator(np.random.PCG64(7))
         arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
@@ -447,7 +499,7 @@ def serving_bench(L, W, args):
         while i < len(reqs) or pending:
             now = time.perf_counter() - start
             while i < len(reqs) and arrivals[i] <= now:
-                pending[L.ld_submit(hs[i], params(reqs[i], L.LD_PREC_MIXED))] = i
+                pending[L.ld_submit(hs[i], params(reqs[i], L.LD_PREC_AUTO))] = i
                 i += 1
             for t in list(pending):
                 res = L.ld_poll(ctx.handle, t)
@@ -457,10 +509,11 @@ def serving_bench(L, W, args):
             time.sleep(0.0002)
         lat = np.array(lat)
         st = L.ld_serving_stats_get(ctx.handle)
-        out.update({"served_precision": "mixed (FP32 Krylov vectors)",
-                    "served_logdets_per_s": out["served_mixed"]["logdets_per_s"],
-                    "speedup_vs_fp64_sequential": out["served_mixed"]["speedup_vs_fp64_sequential"],
-                    "max_rel_err_vs_fp64": out["served_mixed"]["max_rel_err_vs_fp64"],
+        out.update({"served_precision": "auto (FP32 Krylov vectors where lambda_hi <= 4096 "
+                                        "lambda_lo, else FP64)",
+                    "served_logdets_per_s": out["served_auto"]["logdets_per_s"],
+                    "speedup_vs_fp64_sequential": out["served_auto"]["speedup_vs_fp64_sequential"],
+                    "max_rel_err_vs_fp64": out["served_auto"]["max_rel_err_vs_fp64"],
                     "poisson_rate_hz": rate,
                     "p50_latency_ms": float(np.percentile(lat, 50)),
                     "p99_latency_ms": float(np.percentile(lat, 99)),
@@ -601,6 +654,10 @@ def main():
                     "attainable": ceiling[mix]["GB/s"], "attainable_mix": mix,
                     "frac_of_attainable": rate / ceiling[mix]["GB/s"]}
 
+    graphs = None
+    if not args.no_graph:
+        graphs = graph_bench(L, W, args)
+
     comparators = None
     if not args.no_comparators:
         comparators = comparators_bench(L, W, ctx, h, a, vt, args)
@@ -654,6 +711,7 @@ def main():
         "accuracy": accuracy,
         "kernel_families": families,
         "serving": serving,
+        "graph_replay": graphs,
         "comparators": comparators,
         "precision_variants": variants,
         "configs": configs,

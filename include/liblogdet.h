@@ -90,9 +90,13 @@ typedef enum { LD_PROBE_RADEMACHER = 0, LD_PROBE_GAUSSIAN = 1 } ld_probe_dist;
  * indefinite) and matrices whose spectral interval (ld_matrix_bounds) has
  * lambda_hi <= 512 lambda_lo (beyond, Wendland covariances with many
  * eigenvalues near their nugget move by more than 1e-4); anything else is
- * LD_E_INVALID_ARG.
- * LD_PREC_AUTO: LD_PREC_HALF where LD_PREC_HALF is accepted, else
- * LD_PREC_MIXED. */
+ * LD_E_INVALID_ARG.  The 1e-4 is relative to sum |log lambda_i|: a logdet
+ * whose terms nearly cancel (eigenvalues on both sides of 1) can miss 1e-4
+ * relative to its own value even inside that range.
+ * LD_PREC_AUTO: LD_PREC_MIXED where lambda_hi <= 4096 lambda_lo, else
+ * LD_PREC_FP64 (FP32 vectors held 1e-4 against FP64 on a serving mix of
+ * Laplacians and Wendland covariances up to a ratio of ~8700).  Never
+ * LD_PREC_HALF. */
 typedef enum {
   LD_PREC_FP64 = 0,
   LD_PREC_MIXED = 1,
@@ -326,18 +330,42 @@ ld_status ld_wait(ld_ctx* ctx, uint64_t ticket, ld_result* out);
  * now, idle slots included; the scheduler keeps it at or below
  * budget_bytes (ld_ctx_opts.hbm_budget_bytes), releasing idle buffers before
  * a slot grows, and peak_held_bytes is the most it has held.  A batched
- * launch advances every resident request by one Krylov step; graph_replays
- * counts the scheduler rounds replayed from a captured HIP graph and
- * graph_captures the graphs it captured (a new slot-table shape). */
+ * launch advances every resident request by one Krylov step. */
 typedef struct {
   uint64_t submitted, completed, ticks;
   uint64_t batched_steps, batched_launches;
   uint64_t held_bytes, peak_held_bytes, budget_bytes;
   uint64_t buffer_allocs, buffer_frees;
-  uint64_t graph_replays, graph_captures;
   int32_t peak_active, max_slots;
 } ld_serving_stats;
 ld_status ld_serving_stats_get(ld_ctx* ctx, ld_serving_stats* out);
+
+/* HIP-graph replay of blocking estimates (ld_estimate, ld_estimate_ex,
+ * ld_estimate_detail; not ld_estimate_noalloc, which instantiates nothing).
+ * With mode 1 (the default) the second blocking estimate of a context with
+ * the same matrix and the same parameters apart from the seed captures the
+ * estimate's kernel launches in a HIP graph, and every later one replays it:
+ * one graph launch in place of one launch per kernel (the host stops being
+ * the bound on small matrices).  The seed reaches the probe kernels through
+ * device memory, written before each replay, so one graph serves every seed.
+ * A replay runs the same kernels in the same order on the same buffers: the
+ * result is bitwise the eager one.  Estimates with an adaptive Krylov
+ * dimension (a host check during the run), with profiling enabled, or of a
+ * matrix whose interval has zero width always launch kernel by kernel.  Up
+ * to 8 graphs are kept per context, least recently used dropped first; a
+ * matrix's graphs go with ld_destroy, and all of them when the context's
+ * workspace grows; a new autotune result makes a new graph.  Mode 0
+ * launches every estimate kernel by kernel and drops the kept graphs.
+ * Thread-safe (estimates of a context run one at a time). */
+ld_status ld_graph_mode(ld_ctx* ctx, int32_t mode);
+typedef struct {
+  uint64_t captures;  /* graphs captured                                      */
+  uint64_t replays;   /* estimates run as a graph replay                      */
+  uint64_t eager;     /* blocking estimates launched kernel by kernel         */
+  uint64_t cached;    /* graphs kept now                                      */
+  int32_t mode;       /* the ld_graph_mode setting                            */
+} ld_graph_stats;
+ld_status ld_graph_stats_get(ld_ctx* ctx, ld_graph_stats* out);
 
 /* Instrumentation (off by default).  While enabled, every launch of a kernel
  * family in `family_mask` is bracketed by two HIP events recorded on the

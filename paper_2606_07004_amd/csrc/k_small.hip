@@ -417,6 +417,23 @@ hipError_t launch_fill(hipStream_t st, const FillItem* items, int count) {
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kThreads) void k_copy_words(uint32_t* __restrict__ dst,
+                                                        const uint32_t* __restrict__ src,
+                                                        size_t n32) {
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n32;
+       i += (size_t)gridDim.x * kThreads)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy_words(hipStream_t st, void* dst, const void* src, size_t n32) {
+  if (n32 == 0) return hipSuccess;
+  if (!dst || !src) return hipErrorInvalidValue;
+  const size_t nb = std::min<size_t>((n32 + kThreads - 1) / kThreads, kMaxBlocks);
+  hipLaunchKernelGGL(k_copy_words, dim3((unsigned)nb), dim3(kThreads), 0, st,
+                     static_cast<uint32_t*>(dst), static_cast<const uint32_t*>(src), n32);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kThreads) void k_pack_results(int ld, const double* __restrict__ K,
                                                           const double* __restrict__ norm2,
                                                           const int* __restrict__ meff,

@@ -38,9 +38,10 @@ __device__ inline void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2, u
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_rademacher(uint64_t seed, int64_t n, int pbase,
-                                                        int ncols, int nvalid, T* __restrict__ X,
-                                                        int ld, int col0) {
+__global__ __launch_bounds__(kThreads) void k_rademacher(uint64_t seed, const uint64_t* seed_dev,
+                                                        int64_t n, int pbase, int ncols, int nvalid,
+                                                        T* __restrict__ X, int ld, int col0) {
+  if (seed_dev) seed = *seed_dev;
   __shared__ uint64_t words[64][4];
   const int64_t r0 = (int64_t)blockIdx.x * 256;
   const int cbase = blockIdx.y * 64;
@@ -73,9 +74,10 @@ __global__ __launch_bounds__(kThreads) void k_rademacher(uint64_t seed, int64_t 
 // rho sin(2 pi u2).  Columns are the fastest thread index so that a wave
 // writes contiguous row segments.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gaussian(uint64_t seed, int64_t n, int pbase,
-                                                      int ncols, int nvalid, T* __restrict__ X,
-                                                      int ld, int col0) {
+__global__ __launch_bounds__(kThreads) void k_gaussian(uint64_t seed, const uint64_t* seed_dev,
+                                                      int64_t n, int pbase, int ncols, int nvalid,
+                                                      T* __restrict__ X, int ld, int col0) {
+  if (seed_dev) seed = *seed_dev;
   const int j = (int)(threadIdx.x % 64) + 64 * (int)blockIdx.y;
   const int64_t b = (int64_t)blockIdx.x * (kThreads / 64) + threadIdx.x / 64;
   if (j >= ncols || 4 * b >= n) return;
@@ -1011,9 +1013,11 @@ static int stream_grid(const Geom& g, const void* fn) {
 
 // Block (b, w): Philox blocks (b, pbase + 64 w + j) for j < 64 into LDS, then
 // thread rr packs row 256 b + rr's 64 sign bits.
-__global__ __launch_bounds__(kThreads) void k_rademacher_mask(uint64_t seed, int64_t n, int pbase,
-                                                             int ncols, uint64_t* __restrict__ masks,
-                                                             int nw) {
+__global__ __launch_bounds__(kThreads) void k_rademacher_mask(uint64_t seed,
+                                                             const uint64_t* seed_dev, int64_t n,
+                                                             int pbase, int ncols,
+                                                             uint64_t* __restrict__ masks, int nw) {
+  if (seed_dev) seed = *seed_dev;
   __shared__ uint64_t words[64][4];
   const int64_t r0 = (int64_t)blockIdx.x * 256;
   const int w = blockIdx.y;
@@ -1037,13 +1041,13 @@ __global__ __launch_bounds__(kThreads) void k_rademacher_mask(uint64_t seed, int
 }
 
 hipError_t launch_rademacher_mask(hipStream_t st, uint64_t seed, int64_t n, int pbase, int ncols,
-                                  uint64_t* masks, int nw) {
+                                  uint64_t* masks, int nw, const uint64_t* seed_dev) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
   if (!masks || pbase < 0 || nw != (ncols + 63) / 64) return hipErrorInvalidValue;
   static_assert(kThreads == 256, "one thread per row of a 256-row Philox block");
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)nw);
-  hipLaunchKernelGGL(k_rademacher_mask, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols, masks,
-                     nw);
+  hipLaunchKernelGGL(k_rademacher_mask, grid, dim3(kThreads), 0, st, seed, seed_dev, n, pbase, ncols,
+                     masks, nw);
   return hipGetLastError();
 }
 
@@ -1141,29 +1145,31 @@ hipError_t launch_spmm_signs(hipStream_t st, int64_t n, const int* rp, const int
 }
 
 hipError_t launch_rademacher(hipStream_t st, uint64_t seed, int64_t n, int pbase, int ncols,
-                             int nvalid, void* X, int xbytes, int ld, int col0) {
+                             int nvalid, void* X, int xbytes, int ld, int col0,
+                             const uint64_t* seed_dev) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
   if (!X || col0 < 0 || col0 + ncols > ld || pbase < 0 || nvalid < 0 || nvalid > ncols)
     return hipErrorInvalidValue;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)((ncols + 63) / 64));
   if (xbytes == 8)
-    hipLaunchKernelGGL(k_rademacher<double>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
-                       nvalid, static_cast<double*>(X), ld, col0);
+    hipLaunchKernelGGL(k_rademacher<double>, grid, dim3(kThreads), 0, st, seed, seed_dev, n, pbase,
+                       ncols, nvalid, static_cast<double*>(X), ld, col0);
   else if (xbytes == 4)
-    hipLaunchKernelGGL(k_rademacher<float>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
-                       nvalid, static_cast<float*>(X), ld, col0);
+    hipLaunchKernelGGL(k_rademacher<float>, grid, dim3(kThreads), 0, st, seed, seed_dev, n, pbase,
+                       ncols, nvalid, static_cast<float*>(X), ld, col0);
   else if (xbytes == 2)
-    hipLaunchKernelGGL(k_rademacher<_Float16>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
-                       nvalid, static_cast<_Float16*>(X), ld, col0);
+    hipLaunchKernelGGL(k_rademacher<_Float16>, grid, dim3(kThreads), 0, st, seed, seed_dev, n, pbase,
+                       ncols, nvalid, static_cast<_Float16*>(X), ld, col0);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_probes(hipStream_t st, int dist, uint64_t seed, int64_t n, int pbase, int ncols,
-                         int nvalid, void* X, int xbytes, int ld, int col0) {
+                         int nvalid, void* X, int xbytes, int ld, int col0,
+                         const uint64_t* seed_dev) {
   if (dist == PROBE_RADEMACHER)
-    return launch_rademacher(st, seed, n, pbase, ncols, nvalid, X, xbytes, ld, col0);
+    return launch_rademacher(st, seed, n, pbase, ncols, nvalid, X, xbytes, ld, col0, seed_dev);
   if (dist != PROBE_GAUSSIAN) return hipErrorInvalidValue;
   if (n <= 0 || ncols <= 0) return hipSuccess;
   if (!X || col0 < 0 || col0 + ncols > ld || pbase < 0 || nvalid < 0 || nvalid > ncols)
@@ -1171,14 +1177,14 @@ hipError_t launch_probes(hipStream_t st, int dist, uint64_t seed, int64_t n, int
   const int64_t nb4 = (n + 3) / 4;
   dim3 grid((unsigned)((nb4 + kThreads / 64 - 1) / (kThreads / 64)), (unsigned)((ncols + 63) / 64));
   if (xbytes == 8)
-    hipLaunchKernelGGL(k_gaussian<double>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
-                       nvalid, static_cast<double*>(X), ld, col0);
+    hipLaunchKernelGGL(k_gaussian<double>, grid, dim3(kThreads), 0, st, seed, seed_dev, n, pbase,
+                       ncols, nvalid, static_cast<double*>(X), ld, col0);
   else if (xbytes == 4)
-    hipLaunchKernelGGL(k_gaussian<float>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
-                       nvalid, static_cast<float*>(X), ld, col0);
+    hipLaunchKernelGGL(k_gaussian<float>, grid, dim3(kThreads), 0, st, seed, seed_dev, n, pbase,
+                       ncols, nvalid, static_cast<float*>(X), ld, col0);
   else if (xbytes == 2)
-    hipLaunchKernelGGL(k_gaussian<_Float16>, grid, dim3(kThreads), 0, st, seed, n, pbase, ncols,
-                       nvalid, static_cast<_Float16*>(X), ld, col0);
+    hipLaunchKernelGGL(k_gaussian<_Float16>, grid, dim3(kThreads), 0, st, seed, seed_dev, n, pbase,
+                       ncols, nvalid, static_cast<_Float16*>(X), ld, col0);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

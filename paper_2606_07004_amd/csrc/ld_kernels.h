@@ -110,18 +110,22 @@ struct FinDesc {
 
 // Columns col0 .. col0+ncols-1 of X: probe columns pbase .. pbase+nvalid-1,
 // then zeros up to ncols (padding).
+// With seed_dev, the kernels read the seed from that device word instead (a
+// launch sequence that does not depend on the seed, e.g. a replayed graph).
 hipError_t launch_rademacher(hipStream_t st, uint64_t seed, int64_t n, int pbase, int ncols,
-                             int nvalid, void* X, int xbytes, int ld, int col0);
+                             int nvalid, void* X, int xbytes, int ld, int col0,
+                             const uint64_t* seed_dev = nullptr);
 // Same for either distribution (PROBE_RADEMACHER or PROBE_GAUSSIAN).
 constexpr int PROBE_RADEMACHER = 0;
 constexpr int PROBE_GAUSSIAN = 1;
 hipError_t launch_probes(hipStream_t st, int dist, uint64_t seed, int64_t n, int pbase, int ncols,
-                         int nvalid, void* X, int xbytes, int ld, int col0);
+                         int nvalid, void* X, int xbytes, int ld, int col0,
+                         const uint64_t* seed_dev = nullptr);
 // Rademacher probe columns pbase .. pbase+ncols-1 as sign bits: bit j of
 // masks[row][w] is 1 where column pbase + 64 w + j holds -1 (the same Philox
 // bits as launch_rademacher); nw = ceil(ncols / 64) words per row.
 hipError_t launch_rademacher_mask(hipStream_t st, uint64_t seed, int64_t n, int pbase, int ncols,
-                                  uint64_t* masks, int nw);
+                                  uint64_t* masks, int nw, const uint64_t* seed_dev = nullptr);
 
 // A block of FP64 probe columns read by the sketch kernels: dense values
 // (dense[row * ld + j]) or Rademacher signs packed 64 per word
@@ -333,10 +337,16 @@ struct FillItem {
 };
 hipError_t launch_fill(hipStream_t st, const FillItem* items, int count);
 
+// dst[0 .. n32) = src[0 .. n32), 32-bit words (a kernel rather than a copy
+// node when the sequence is captured in a graph).
+hipError_t launch_copy_words(hipStream_t st, void* dst, const void* src, size_t n32);
+
 // The per-run results an estimate hands back, packed for one copy:
 // [K: ld doubles | norm2: ld doubles | meff: ld ints | flags: ld ints |
 //  dflag: 4 ints | meff0: ld ints] (meff0 may be null: zeros).
 inline size_t pack_results_bytes(int ld) { return (size_t)ld * 28 + 16; }
+constexpr size_t kHostPackBytes = 8192;  // >= pack_results_bytes(kMaxLd)
+static_assert((size_t)kMaxLd * 28 + 16 <= kHostPackBytes, "host pack buffer too small");
 hipError_t launch_pack_results(hipStream_t st, int ld, const double* K, const double* norm2,
                                const int* meff, const int* flags, const int* dflag,
                                const int* meff0, void* out);

@@ -162,15 +162,94 @@ void Profiler::query(uint32_t fam, int64_t* n, double* ms, double* bytes) {
     if (prof_) LD_HIP(prof_->end((fam), st, pa_, (double)(bytes)));      \
   } while (0)
 
+// ---------------------------------------------------------------------------
+// Graph cache of blocking estimates
+// ---------------------------------------------------------------------------
+bool GraphKey::operator==(const GraphKey& o) const {
+  return serial == o.serial && tune_ver == o.tune_ver && method == o.method &&
+         precision == o.precision && n_probes == o.n_probes && sketch_rank == o.sketch_rank &&
+         krylov_steps == o.krylov_steps && iop_window == o.iop_window &&
+         probe_dist == o.probe_dist && subspace_rank == o.subspace_rank &&
+         adapt_every == o.adapt_every && sketch_passes == o.sketch_passes && tol == o.tol &&
+         adapt_tol == o.adapt_tol && ws == o.ws && ws_bytes == o.ws_bytes;
+}
+
+static void destroy_entry(GraphCache::Entry& e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.graph) (void)hipGraphDestroy(e.graph);
+  e.exec = nullptr;
+  e.graph = nullptr;
+}
+
+GraphCache::Entry* GraphCache::find(const GraphKey& k) {
+  for (Entry& e : entries)
+    if (e.key == k) {
+      e.last = ++tick;
+      return &e;
+    }
+  return nullptr;
+}
+
+bool GraphCache::seen_before(const GraphKey& k) {
+  for (const GraphKey& s : seen)
+    if (s == k) return true;
+  seen.push_back(k);
+  if ((int)seen.size() > kSeen) seen.pop_front();
+  return false;
+}
+
+hipError_t GraphCache::insert(const GraphKey& k, hipGraph_t g, hipGraphExec_t x) {
+  if ((int)entries.size() >= kMax) {
+    size_t lru = 0;
+    for (size_t i = 1; i < entries.size(); ++i)
+      if (entries[i].last < entries[lru].last) lru = i;
+    destroy_entry(entries[lru]);
+    entries.erase(entries.begin() + (long)lru);
+  }
+  Entry e;
+  e.key = k;
+  e.graph = g;
+  e.exec = x;
+  e.last = ++tick;
+  entries.push_back(e);
+  ++captures;
+  return hipSuccess;
+}
+
+void GraphCache::drop_matrix(uint64_t serial) {
+  for (size_t i = entries.size(); i-- > 0;)
+    if (entries[i].key.serial == serial) {
+      destroy_entry(entries[i]);
+      entries.erase(entries.begin() + (long)i);
+    }
+  for (size_t i = seen.size(); i-- > 0;)
+    if (seen[i].serial == serial) seen.erase(seen.begin() + (long)i);
+}
+
+void GraphCache::drop_workspace() {
+  for (Entry& e : entries) destroy_entry(e);
+  entries.clear();
+  seen.clear();
+}
+
+void GraphCache::clear() { drop_workspace(); }
+
 static inline int round4(int x) { return (x + 3) & ~3; }
 static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // FP16 Krylov vectors are accepted when lambda_hi / lambda_lo is at most
-// this (LD_PREC_HALF refuses wider intervals, LD_PREC_AUTO takes FP32 there).
-// Measured on the serving mix of Laplacians and Wendland covariances: FP16
-// stays within 1e-4 of FP64 up to a ratio of ~500 on every kind; beyond it
-// Wendland covariances, whose spectra crowd near the nugget, exceed 1e-4.
-constexpr double kAutoHalfRatio = 512.0;
+// this (LD_PREC_HALF refuses wider intervals).  Measured on the serving mix
+// of Laplacians and Wendland covariances: FP16 stays within 1e-4 of FP64 up
+// to a ratio of ~500 on every kind; beyond it Wendland covariances, whose
+// spectra crowd near the nugget, exceed 1e-4.
+constexpr double kHalfMaxRatio = 512.0;
+// LD_PREC_AUTO takes FP32 vectors up to this ratio and FP64 beyond.  FP32
+// held 1e-4 against FP64 on every request of the serving mix with a ratio
+// below ~8700 (Wendland covariances with small nuggets were the first to
+// fail); the cut keeps a factor of two below that.  AUTO never takes FP16:
+// its relative error is bounded against sum |log lambda|, so a logdet whose
+// terms nearly cancel can miss a 1e-4 relative gate inside the FP16 range.
+constexpr double kAutoMixedRatio = 4096.0;
 
 // ---------------------------------------------------------------------------
 // Run
@@ -187,6 +266,7 @@ Run::Run(ld_matrix* a, const ld_params& p) : a_(a), p_(p) {}
 
 Run::~Run() {
   if (check_ev_ && pending_check_) (void)hipEventSynchronize(check_ev_);
+  if (own_hpack_ && hpack_) (void)hipHostFree(hpack_);  // waits for a copy in flight
   if (ext_) return;
   if (ev0_) (void)hipEventDestroy(ev0_);
   if (ev1_) (void)hipEventDestroy(ev1_);
@@ -243,8 +323,7 @@ ld_status Run::validate() {
   adapt_every_ = p_.adapt_every > 0 ? p_.adapt_every : 5;
   mixed_ = p_.precision != LD_PREC_FP64;
   half_ = p_.precision == LD_PREC_HALF;
-  if (p_.precision == LD_PREC_AUTO)
-    half_ = a_->hi <= kAutoHalfRatio * a_->lo && k_ <= 4;
+  if (p_.precision == LD_PREC_AUTO) mixed_ = a_->hi <= kAutoMixedRatio * a_->lo;
   xb_ = half_ ? 2 : (mixed_ ? 4 : 8);
   if (std::max(B_, s_) > (mixed_ ? 256 : 128))
     return set_error(LD_E_INVALID_ARG, mixed_ ? "n_probes must be <= 256 in mixed precision"
@@ -253,7 +332,7 @@ ld_status Run::validate() {
     return set_error(LD_E_INVALID_ARG,
                      "FP16 Krylov vectors take iop_window <= 4: with more window vectors the "
                      "classical Gram-Schmidt step on FP16-rounded vectors loses stability");
-  if (half_ && !(a_->hi <= kAutoHalfRatio * a_->lo))
+  if (half_ && !(a_->hi <= kHalfMaxRatio * a_->lo))
     return set_error(LD_E_INVALID_ARG,
                      "FP16 Krylov vectors take matrices with lambda_hi <= 512 lambda_lo: on "
                      "wider spectral intervals the 2^-11 storage rounding can move the estimate "
@@ -423,6 +502,8 @@ size_t Run::layout(char* base) {
   kprev_ = static_cast<double*>(take((size_t)ldx_ * 8));
   need_ = static_cast<int*>(take((size_t)ldx_ * 4));
   meff0_ = static_cast<int*>(take((size_t)ldx_ * 4));
+  pack_ = take(pack_results_bytes(ldx_));
+  seed_dev_ = static_cast<uint64_t*>(take(8));
   return off;
 }
 
@@ -466,18 +547,22 @@ ld_status Run::sketch_qr(hipStream_t st, double* Y, int cols) {
 
 // X0 = [A | G - A (A^T G)] in Krylov precision, its column norms, and the
 // per-run start state.
-ld_status Run::start_block(hipStream_t st, const double* A, int s_cols) {
-  // no previous quadrature value yet (all-ones bytes: NaN) for the adaptive test
-  LD_HIP(hipMemsetAsync(kprev_, 0xFF, (size_t)ldx_ * 8, st));
+ld_status Run::start_block(hipStream_t st, const double* A, int s_cols, bool zero_h) {
+  // no previous quadrature value yet (all-ones bytes: NaN) for the adaptive
+  // test; a fresh Hessenberg block for a phase that starts here
+  FillItem fi[2] = {{kprev_, (size_t)ldx_ * 2, 0xFFFFFFFFu},
+                    {H_, (size_t)ldx_ * (m_ + 1) * m_ * 2, 0u}};
+  LD_HIP(launch_fill(st, fi, zero_h ? 2 : 1));
   GSrc gs{G_, ldr_, gmask_, nwr_};
   if (gmask_) {
     gs.dense = nullptr;
     LD_LAUNCH(LD_PROF_PROBES, (double)n_ * nwr_ * 8,
-              launch_rademacher_mask(st, p_.seed, n_, s_, r_, gmask_, nwr_));
+              launch_rademacher_mask(st, p_.seed, n_, s_, r_, gmask_, nwr_, seed_dev_));
   } else {
     gs.mask = nullptr;
     LD_LAUNCH(LD_PROF_PROBES, (double)n_ * ldr_ * 8,
-              launch_probes(st, p_.probe_dist, p_.seed, n_, s_, ldr_, r_, G_, 8, ldr_, 0));
+              launch_probes(st, p_.probe_dist, p_.seed, n_, s_, ldr_, r_, G_, 8, ldr_, 0,
+                            seed_dev_));
   }
   const double gbytes = gmask_ ? (double)n_ * nwr_ * 8 : (double)n_ * r_ * 8;
   if (s_cols > 0) {
@@ -540,7 +625,8 @@ ld_status Run::begin_krylov(int phase) {
 // Krylov precision, their norms and per-run start state.
 ld_status Run::sketch_runs_start(hipStream_t st) {
   LD_LAUNCH(LD_PROF_PROBES, (double)n_ * ld1_ * xb_,
-            launch_probes(st, p_.probe_dist, p_.seed, n_, 0, ld1_, s_, slots_, xb_, ld1_, 0));
+            launch_probes(st, p_.probe_dist, p_.seed, n_, 0, ld1_, s_, slots_, xb_, ld1_, 0,
+                          seed_dev_));
   VecSet vs{};
   vs.x[0] = slots_;
   int nb = 0;
@@ -569,12 +655,32 @@ ld_status Run::sketch_combine_upto(hipStream_t st, int upto) {
   return LD_OK;
 }
 
+// The probe kernels read the seed from a device word, so that the launch
+// sequence of an estimate does not depend on it.
+ld_status Run::write_seed(hipStream_t st) {
+  const FillItem fi[2] = {{seed_dev_, 1, (uint32_t)(p_.seed & 0xFFFFFFFFu)},
+                          {reinterpret_cast<uint32_t*>(seed_dev_) + 1, 1,
+                           (uint32_t)(p_.seed >> 32)}};
+  LD_HIP(launch_fill(st, fi, 2));
+  return LD_OK;
+}
+
 ld_status Run::run_prologue(hipStream_t st) {
   if (!ev0_) LD_HIP(hipEventCreate(&ev0_));
   if (!ev1_) LD_HIP(hipEventCreate(&ev1_));
-  LD_HIP(hipEventRecord(ev0_, st));
-  LD_HIP(hipMemsetAsync(flags_, 0, (size_t)ldB_ * 4, st));
-  LD_HIP(hipMemsetAsync(dflag_, 0, 16, st));
+  if (!capturing_) {
+    LD_HIP(hipEventRecord(ev0_, st));
+    ld_status rc = write_seed(st);
+    if (rc != LD_OK) return rc;
+  }
+  {
+    // run flags, QR flags and (Arnoldi methods) the Hessenberg blocks start
+    // at zero
+    FillItem fi[3] = {{flags_, (size_t)ldB_, 0u},
+                      {dflag_, 4, 0u},
+                      {H_, (size_t)ldx_ * (m_ + 1) * m_ * 2, 0u}};
+    LD_HIP(launch_fill(st, fi, p_.method == LD_METHOD_OSLQ ? 2 : 3));
+  }
   const void* vals_sketch = (mixed_ && a_->vlo) ? a_->vlo : a_->v64;
   const int vt_sketch = mixed_ ? a_->vt_lo : VT_F64;
   if (p_.method == LD_METHOD_OSLQ) {
@@ -583,7 +689,7 @@ ld_status Run::run_prologue(hipStream_t st) {
       if (smask_) {
         const int vb = vt_sketch == VT_BF16 ? 2 : (vt_sketch == VT_F32 ? 4 : 8);
         LD_LAUNCH(LD_PROF_PROBES, (double)n_ * nws_ * 8,
-                  launch_rademacher_mask(st, p_.seed, n_, 0, s_, smask_, nws_));
+                  launch_rademacher_mask(st, p_.seed, n_, 0, s_, smask_, nws_, seed_dev_));
         LD_LAUNCH(LD_PROF_SKETCH,
                   (double)a_->nnz * (vb + 4) + 4.0 * (n_ + 1) + (double)n_ * nws_ * 8 +
                       (double)n_ * lds_ * 8,
@@ -591,7 +697,8 @@ ld_status Run::run_prologue(hipStream_t st) {
                                     s_, Y_, lds_, opscale_));
       } else {
         LD_LAUNCH(LD_PROF_PROBES, (double)n_ * lds_ * 8,
-                  launch_probes(st, p_.probe_dist, p_.seed, n_, 0, lds_, s_, S_, 8, lds_, 0));
+                  launch_probes(st, p_.probe_dist, p_.seed, n_, 0, lds_, s_, S_, 8, lds_, 0,
+                                seed_dev_));
         LD_LAUNCH(LD_PROF_SPMM, spmm_bytes(lds_, 8),
                   launch_spmm(st, gS_, a_->rp, a_->ci, vals_sketch, vt_sketch, S_, Y_, nullptr,
                               opscale_, nullptr, 0, 0, nullptr, nullptr));
@@ -599,7 +706,7 @@ ld_status Run::run_prologue(hipStream_t st) {
       ld_status rc = sketch_qr(st, Y_, s_);
       if (rc != LD_OK) return rc;
     }
-    ld_status rc = start_block(st, Y_, s_);
+    ld_status rc = start_block(st, Y_, s_, false);
     if (rc != LD_OK) return rc;
     begin_krylov(0);
     return LD_OK;
@@ -609,14 +716,12 @@ ld_status Run::run_prologue(hipStream_t st) {
   if (s_ > 0) {
     ld_status rc = sketch_runs_start(st);
     if (rc != LD_OK) return rc;
-    LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldx_ * (m_ + 1) * m_ * 8, st));
     opass_ = 0;
     begin_krylov(0);
     return LD_OK;
   }
-  ld_status rc = start_block(st, nullptr, 0);
+  ld_status rc = start_block(st, nullptr, 0, false);
   if (rc != LD_OK) return rc;
-  LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldx_ * (m_ + 1) * m_ * 8, st));
   begin_krylov(1);
   return LD_OK;
 }
@@ -629,8 +734,7 @@ ld_status Run::osa_sketch_combine(hipStream_t st) {
   const double shift = std::log(scale_) - c_;
   if (!two_pass_ || opass_ == 0) {
     // keep the sketch-image runs' Krylov dimensions for the step count
-    LD_HIP(hipMemcpyAsync(meff0_, meff_, (size_t)std::max(s_, 1) * 4, hipMemcpyDeviceToDevice,
-                          st));
+    LD_HIP(launch_copy_words(st, meff0_, meff_, (size_t)std::max(s_, 1)));
     LD_LAUNCH(LD_PROF_SMALL, 0,
               launch_hess_log(st, s_, m_, H_, meff_, quad_a(), quad_b(), work_, wstride_, 0, ell_,
                               nullptr, 0.0, nullptr, flags_, symtol(), need_));
@@ -668,9 +772,8 @@ ld_status Run::osa_sketch_combine(hipStream_t st) {
   }
   ld_status rc = sketch_qr(st, Y_, kb_);
   if (rc != LD_OK) return rc;
-  rc = start_block(st, Y_, kb_);
+  rc = start_block(st, Y_, kb_, true);
   if (rc != LD_OK) return rc;
-  LD_HIP(hipMemsetAsync(H_, 0, (size_t)ldx_ * (m_ + 1) * m_ * 8, st));
   begin_krylov(1);
   return LD_OK;
 }
@@ -816,7 +919,8 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
     // the count of runs still going comes back to the host for the early exit
     if (!nact_host_) LD_HIP(hipHostMalloc((void**)&nact_host_, sizeof(int), hipHostMallocDefault));
     if (!check_ev_) LD_HIP(hipEventCreateWithFlags(&check_ev_, hipEventDisableTiming));
-    LD_HIP(hipMemsetAsync(nact_, 0, sizeof(int), st));
+    const FillItem fi{nact_, 1, 0u};
+    LD_HIP(launch_fill(st, &fi, 1));
     LD_LAUNCH(LD_PROF_SMALL, 0,
               launch_quad_check(st, kB_, m_, H_, meff_, quad_a(), quad_b(), t + 1, active_, kprev_,
                                 p_.adapt_tol, mult_ptr(t + 1), flags_, nact_));
@@ -868,8 +972,28 @@ ld_status Run::run_epilogue(hipStream_t st) {
               launch_hess_log(st, B_, m_, H_, meff_, quad_a(), quad_b(), work_, wstride_, 1,
                               nullptr, gq_, std::log(scale_) - c_, K_, flags_, symtol(), need_));
   }
+  if (capturing_) return LD_OK;  // the replay enqueues the results after the graph
   LD_HIP(hipEventRecord(ev1_, st));
+  return enqueue_results(st);
+}
+
+// The per-run results, packed on the device and copied to pinned host memory
+// in stream order: collect() reads them once the stream (or the request's
+// done event) has passed this point.
+ld_status Run::enqueue_results(hipStream_t st) {
+  if (!hpack_) {
+    LD_HIP(hipHostMalloc(&hpack_, kHostPackBytes, hipHostMallocDefault));
+    own_hpack_ = true;
+  }
+  const int ld = std::max(B_, s_);
+  LD_HIP(launch_pack_results(st, ld, K_, norm2_, meff_, flags_, dflag_,
+                             (p_.method != LD_METHOD_OSLQ && s_ > 0) ? meff0_ : nullptr, pack_));
+  LD_HIP(hipMemcpyAsync(hpack_, pack_, pack_results_bytes(ld), hipMemcpyDeviceToHost, st));
   return LD_OK;
+}
+
+bool Run::capturable() const {
+  return lo_ != hi_ && !(p_.adapt_tol > 0.0) && !(prof_ && prof_->any());
 }
 
 ld_status Run::advance(hipStream_t st, int budget, bool* done, StepPlan* plan, bool* planned) {
@@ -986,14 +1110,18 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail, 
     *out = res;
     return LD_OK;
   }
-  std::vector<double> K(B_), nrm(B_);
-  std::vector<int> meff(B_), flags(B_);
-  int dflag[3] = {0, 0, 0};
-  LD_HIP(hipMemcpy(K.data(), K_, (size_t)B_ * 8, hipMemcpyDeviceToHost));
-  LD_HIP(hipMemcpy(nrm.data(), norm2_, (size_t)B_ * 8, hipMemcpyDeviceToHost));
-  LD_HIP(hipMemcpy(meff.data(), meff_, (size_t)B_ * 4, hipMemcpyDeviceToHost));
-  LD_HIP(hipMemcpy(flags.data(), flags_, (size_t)B_ * 4, hipMemcpyDeviceToHost));
-  LD_HIP(hipMemcpy(dflag, dflag_, 12, hipMemcpyDeviceToHost));
+  // the packed results the epilogue copied to pinned memory (layout of
+  // launch_pack_results)
+  const int ldp = std::max(B_, s_);
+  const double* pK = static_cast<const double*>(hpack_);
+  const double* pN = pK + ldp;
+  const int* pM = reinterpret_cast<const int*>(pN + ldp);
+  const int* pF = pM + ldp;
+  const int* pD = pF + ldp;
+  const int* pM0 = pD + 4;
+  std::vector<double> K(pK, pK + B_), nrm(pN, pN + B_);
+  std::vector<int> meff(pM, pM + B_), flags(pF, pF + B_);
+  const int dflag[3] = {pD[0], pD[1], pD[2]};
   float ms = 0.f;
   LD_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
   if (dflag[0] || dflag[1])
@@ -1039,9 +1167,7 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail, 
   }
   if (p_.method != LD_METHOD_OSLQ && s_ > 0) {
     // OSA-IOP and So-SLQ also ran s Krylov runs for the sketch image
-    std::vector<int> m0(s_);
-    LD_HIP(hipMemcpy(m0.data(), meff0_, (size_t)s_ * 4, hipMemcpyDeviceToHost));
-    for (int p = 0; p < s_; ++p) steps += m0[p];
+    for (int p = 0; p < s_; ++p) steps += pM0[p];
   }
   res.probe_steps = steps;
   const int64_t sketch_mv = (p_.method == LD_METHOD_OSLQ) ? s_ : (int64_t)s_ * m_;  // S or L S
@@ -1136,6 +1262,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     std::lock_guard<std::mutex> lk(a_->tune_mu);
     for (int ld : widths)
       for (int which = 0; which < 2; ++which) a_->tune.erase(tune_key(ld, xb_, vt, which));
+    a_->tune_ver.fetch_add(1);
     if (out) *out = ld_tune_result{};
     return LD_OK;
   }
@@ -1224,6 +1351,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
       std::lock_guard<std::mutex> lk(a_->tune_mu);
       a_->tune[tune_key(ld, xb_, vt, 0)] = cand[bp];
       a_->tune[tune_key(ld, xb_, vt, 1)] = cand[bu];
+      a_->tune_ver.fetch_add(1);
     }
     if (wi == 0 && out) {
       *out = ld_tune_result{};
@@ -1258,6 +1386,7 @@ ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int upd
   std::lock_guard<std::mutex> lk(a_->tune_mu);
   a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes | (e << 8), spmm_chunks};
   a_->tune[tune_key(ldB_, xb_, vt, 1)] = {update_lanes, update_chunks};
+  a_->tune_ver.fetch_add(1);
   return LD_OK;
 }
 
@@ -1384,6 +1513,33 @@ using namespace ld;
       return set_error(LD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Capture the launch sequence of a blocking estimate (everything between the
+// seed write and the result pack) from the context's stream into a graph
+// kept under `key`.  Nothing runs during the capture.
+static ld_status capture_estimate(ld_ctx* ctx, Run& run, const GraphKey& key) {
+  LD_HIP_API(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  run.set_capturing(true);
+  bool done = false;
+  ld_status rc = LD_OK;
+  while (!done && rc == LD_OK) rc = run.advance(ctx->stream, 1 << 30, &done);
+  run.set_capturing(false);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(ctx->stream, &g);
+  if (rc != LD_OK || ee != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    if (rc != LD_OK) return rc;
+    return set_error(LD_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ee));
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return set_error(LD_E_DEVICE, std::string("graph instantiation: ") + hipGetErrorString(ie));
+  }
+  LD_HIP_API(ctx->graphs.insert(key, g, x));
+  return LD_OK;
+}
+
 extern "C" {
 
 const char* ld_last_error(void) { return g_last_error.c_str(); }
@@ -1427,6 +1583,7 @@ ld_status ld_ctx_create(const ld_ctx_opts* opts, ld_ctx** out) {
     LD_HIP_API(hipEventCreateWithFlags(&c->na_ev[i], i == 2 ? hipEventDisableTiming
                                                                : hipEventDefault));
   LD_HIP_API(hipHostMalloc((void**)&c->na_nact, sizeof(int), hipHostMallocDefault));
+  LD_HIP_API(hipHostMalloc(&c->na_pack, kHostPackBytes, hipHostMallocDefault));
   *out = c.release();
   return LD_OK;
 }
@@ -1437,11 +1594,14 @@ ld_status ld_ctx_destroy(ld_ctx* ctx) {
     return set_error(LD_E_BUSY, "destroy every matrix of the context first");
   (void)hipSetDevice(ctx->device);
   ctx->server.reset();
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  ctx->graphs.clear();
   ctx->workspace.release();
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (hipEvent_t& e : ctx->na_ev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->na_nact) (void)hipHostFree(ctx->na_nact);
+  if (ctx->na_pack) (void)hipHostFree(ctx->na_pack);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return LD_OK;
@@ -1516,7 +1676,9 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
     if (first) return set_error(first->st, std::string(first->what) + std::to_string(first->row));
   }
   LD_HIP_API(hipSetDevice(ctx->device));
+  static std::atomic<uint64_t> next_serial{1};
   std::unique_ptr<ld_matrix> m(new ld_matrix());
+  m->serial = next_serial.fetch_add(1);
   m->ctx = ctx;
   m->n = n;
   m->nnz = nnz;
@@ -1635,6 +1797,10 @@ ld_status ld_destroy(ld_matrix* a) {
   if (!a) return set_error(LD_E_INVALID_ARG, "null matrix");
   if (a->inflight.load() > 0) return set_error(LD_E_BUSY, "requests still use the matrix");
   (void)hipSetDevice(a->ctx->device);
+  {
+    std::lock_guard<std::mutex> lk(a->ctx->est_mu);
+    a->ctx->graphs.drop_matrix(a->serial);
+  }
   (void)hipStreamSynchronize(a->ctx->stream);
   if (a->rp) (void)hipFree(a->rp);
   if (a->ci) (void)hipFree(a->ci);
@@ -1716,19 +1882,72 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
   ld_ctx* ctx = a->ctx;
   std::lock_guard<std::mutex> lk(ctx->est_mu);
   LD_HIP_API(hipSetDevice(ctx->device));
+  if (!ctx->na_ev[0] || !ctx->na_nact || !ctx->na_pack)
+    return set_error(LD_E_INVALID_ARG, "context without its blocking-estimate set-up");
   Run run(a, *p);
   run.set_submit_time(t0);
   run.set_profiler(&ctx->prof);
   run.set_blocking(true);
+  run.use_external(ctx->na_ev[0], ctx->na_ev[1], ctx->na_ev[2], ctx->na_nact);
+  run.set_host_pack(ctx->na_pack);
   ld_status rc = run.validate();
   if (rc != LD_OK) return rc;
   const size_t need = run.device_bytes();
+  const void* ws0 = ctx->workspace.ptr;
+  const size_t wb0 = ctx->workspace.bytes;
   hipError_t e = ctx->workspace.ensure(need);
   if (e != hipSuccess)
     return set_error(e == hipErrorOutOfMemory ? LD_E_NO_MEMORY : LD_E_DEVICE,
                      std::string("workspace allocation: ") + hipGetErrorString(e));
+  // graphs captured on the old workspace point into freed memory
+  if (ctx->workspace.ptr != ws0 || ctx->workspace.bytes != wb0) ctx->graphs.drop_workspace();
   rc = run.bind(ctx->workspace.ptr, ctx->workspace.bytes);
   if (rc != LD_OK) return rc;
+  GraphCache& gc = ctx->graphs;
+  if (gc.mode == 1 && run.capturable()) {
+    GraphKey key;
+    key.serial = a->serial;
+    key.tune_ver = a->tune_ver.load();
+    key.method = p->method;
+    key.precision = p->precision;
+    key.n_probes = p->n_probes;
+    key.sketch_rank = p->sketch_rank;
+    key.krylov_steps = p->krylov_steps;
+    key.iop_window = p->iop_window;
+    key.probe_dist = p->probe_dist;
+    key.subspace_rank = p->subspace_rank;
+    key.adapt_every = p->adapt_every;
+    key.sketch_passes = p->sketch_passes;
+    key.tol = p->tol;
+    key.adapt_tol = p->adapt_tol;
+    key.ws = ctx->workspace.ptr;
+    key.ws_bytes = ctx->workspace.bytes;
+    GraphCache::Entry* ent = gc.find(key);
+    if (!ent && gc.seen_before(key)) {
+      // second estimate of this shape: capture its launches (nothing runs
+      // during the capture), then replay below
+      rc = capture_estimate(ctx, run, key);
+      if (rc != LD_OK) return rc;
+      ent = gc.find(key);
+    }
+    if (ent) {
+      // record start, seed, the graph, record end, results: the launches of
+      // an eager estimate in the same order
+      LD_HIP_API(hipEventRecord(run.start_event(), ctx->stream));
+      rc = run.write_seed(ctx->stream);
+      if (rc != LD_OK) return rc;
+      LD_HIP_API(hipGraphLaunch(ent->exec, ctx->stream));
+      LD_HIP_API(hipEventRecord(run.end_event(), ctx->stream));
+      rc = run.enqueue_results(ctx->stream);
+      if (rc != LD_OK) {
+        (void)hipStreamSynchronize(ctx->stream);
+        return rc;
+      }
+      ++gc.replays;
+      return run.collect(ctx->stream, out, detail);
+    }
+  }
+  ++gc.eager;
   bool done = false;
   while (!done) {
     rc = run.advance(ctx->stream, 1 << 30, &done);
@@ -1757,7 +1976,8 @@ ld_status ld_estimate_noalloc(ld_matrix* a, const ld_params* p, ld_result* out) 
   if (!a || !p || !out) return set_error(LD_E_INVALID_ARG, "null argument");
   const double t0 = now_seconds();
   ld_ctx* ctx = a->ctx;
-  if (ctx->device < 0 || ctx->device >= kMaxDevices || !ctx->na_ev[0] || !ctx->na_nact)
+  if (ctx->device < 0 || ctx->device >= kMaxDevices || !ctx->na_ev[0] || !ctx->na_nact ||
+      !ctx->na_pack)
     return set_error(LD_E_INVALID_ARG, "context without the no-allocation set-up");
   std::lock_guard<std::mutex> lk(ctx->est_mu);
   std::lock_guard<std::mutex> lk_dev(g_scratch_use_mu[ctx->device]);
@@ -1768,6 +1988,7 @@ ld_status ld_estimate_noalloc(ld_matrix* a, const ld_params* p, ld_result* out) 
   run.set_submit_time(t0);
   run.set_blocking(true);
   run.use_external(ctx->na_ev[0], ctx->na_ev[1], ctx->na_ev[2], ctx->na_nact);
+  run.set_host_pack(ctx->na_pack);
   ld_status rc = run.validate();
   if (rc != LD_OK) return rc;
   const size_t need = run.device_bytes();
@@ -1926,6 +2147,32 @@ static ld::Server* server_of(ld_ctx* ctx) {
   return ctx->server.get();
 }
 
+ld_status ld_graph_mode(ld_ctx* ctx, int32_t mode) {
+  if (!ctx) return set_error(LD_E_INVALID_ARG, "null context");
+  if (mode != 0 && mode != 1) return set_error(LD_E_INVALID_ARG, "graph mode must be 0 or 1");
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  (void)hipSetDevice(ctx->device);
+  if (mode == 0) {
+    if (ctx->stream) LD_HIP_API(hipStreamSynchronize(ctx->stream));
+    ctx->graphs.clear();
+  }
+  ctx->graphs.mode = mode;
+  return LD_OK;
+}
+
+ld_status ld_graph_stats_get(ld_ctx* ctx, ld_graph_stats* out) {
+  if (!ctx || !out) return set_error(LD_E_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  ld_graph_stats o{};
+  o.captures = ctx->graphs.captures;
+  o.replays = ctx->graphs.replays;
+  o.eager = ctx->graphs.eager;
+  o.cached = (uint64_t)ctx->graphs.entries.size();
+  o.mode = ctx->graphs.mode;
+  *out = o;
+  return LD_OK;
+}
+
 ld_status ld_serving_stats_get(ld_ctx* ctx, ld_serving_stats* out) {
   if (!ctx || !out) return set_error(LD_E_INVALID_ARG, "null argument");
   ld_serving_stats o{};
@@ -1944,8 +2191,6 @@ ld_status ld_serving_stats_get(ld_ctx* ctx, ld_serving_stats* out) {
       o.peak_held_bytes = st.peak_bytes;
       o.buffer_allocs = st.buffer_allocs;
       o.buffer_frees = st.buffer_frees;
-      o.graph_replays = st.graph_replays;
-      o.graph_captures = st.graph_captures;
       o.peak_active = st.peak_active;
     }
   }

@@ -35,6 +35,42 @@ struct DeviceBuffer {
 
 class Server;
 
+// Identity of a blocking estimate's launch sequence: the matrix (its serial
+// number and autotune version), every parameter except the seed (the probe
+// kernels read it from device memory), and the workspace the buffers live in.
+struct GraphKey {
+  uint64_t serial = 0, tune_ver = 0;
+  int32_t method = 0, precision = 0, n_probes = 0, sketch_rank = 0, krylov_steps = 0;
+  int32_t iop_window = 0, probe_dist = 0, subspace_rank = 0, adapt_every = 0, sketch_passes = 0;
+  double tol = 0, adapt_tol = 0;
+  const void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool operator==(const GraphKey& o) const;
+};
+
+// Captured estimates of a context, least recently used dropped beyond kMax.
+struct GraphCache {
+  static constexpr int kMax = 8;
+  static constexpr int kSeen = 16;
+  struct Entry {
+    GraphKey key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last = 0;
+  };
+  std::vector<Entry> entries;
+  std::deque<GraphKey> seen;  // keys run once without a graph (capture on the next)
+  int mode = 1;
+  uint64_t tick = 0, captures = 0, replays = 0, eager = 0;
+  ~GraphCache() { clear(); }
+  Entry* find(const GraphKey& k);
+  bool seen_before(const GraphKey& k);  // records k when not
+  hipError_t insert(const GraphKey& k, hipGraph_t g, hipGraphExec_t x);
+  void drop_matrix(uint64_t serial);
+  void drop_workspace();
+  void clear();
+};
+
 // Host -> device uploads through two pinned staging buffers: host threads
 // fill one while the other is in flight (pageable sources reach only a part
 // of the link rate).  Created on the first large upload of a context.
@@ -58,6 +94,7 @@ class Profiler {
   ~Profiler();
   void enable(uint32_t mask);
   bool on(uint32_t fam) const { return (mask_ & fam) != 0; }
+  bool any() const { return mask_ != 0; }
   hipError_t begin(uint32_t fam, hipStream_t st, hipEvent_t* a);
   hipError_t end(uint32_t fam, hipStream_t st, hipEvent_t a, double bytes);
   hipError_t harvest();  // waits for pending events and accumulates
@@ -96,10 +133,13 @@ struct ld_ctx {
   ld::Profiler prof;
   std::mutex stage_mu;
   std::unique_ptr<ld::Stager> stager;
-  // the no-allocation estimate's timing events, adaptive-check event and
-  // pinned count of active runs, created with the context
+  // the blocking estimates' timing events, adaptive-check event, pinned
+  // count of active runs and pinned result buffer, created with the context
+  // (the blocking estimates run one at a time under est_mu)
   hipEvent_t na_ev[3] = {nullptr, nullptr, nullptr};
   int* na_nact = nullptr;
+  void* na_pack = nullptr;
+  ld::GraphCache graphs;         // captured blocking estimates (under est_mu)
 };
 
 struct ld_matrix {
@@ -120,6 +160,8 @@ struct ld_matrix {
   double lo = 0, hi = 0;    // interval used by the estimators
   size_t bytes = 0;
   std::atomic<int> inflight{0};
+  uint64_t serial = 0;                 // unique per process
+  std::atomic<uint64_t> tune_ver{0};   // bumped on every change of `tune`
   // autotuned product/update geometry per Krylov block shape:
   // key (ld, bytes per element, value type, kernel) -> (lanes per row |
   // log2(entry split) << 8, chunks per lane)
@@ -173,7 +215,7 @@ class Run {
   ld_status sketch_qr(hipStream_t st, double* Y, int cols);
   ld_status osa_sketch_prologue(hipStream_t st);
   ld_status osa_sketch_combine(hipStream_t st);
-  ld_status start_block(hipStream_t st, const double* A, int s_cols);
+  ld_status start_block(hipStream_t st, const double* A, int s_cols, bool zero_h);
   ld_status sketch_runs_start(hipStream_t st);     // start block of the sketch-image runs
   ld_status sketch_combine_upto(hipStream_t st, int upto);  // two-pass: X_comb_next_..X_upto into Y
   ld_status begin_krylov(int phase);
@@ -252,6 +294,11 @@ class Run {
   int* dflag_ = nullptr;      // [2] CholQR flags
   int* need_ = nullptr;       // OSA-IOP: runs needing the general Hessenberg log
   int* meff0_ = nullptr;      // OSA-IOP: Krylov dimensions of the sketch-image runs
+  void* pack_ = nullptr;      // packed per-run results (launch_pack_results)
+  uint64_t* seed_dev_ = nullptr;  // the probe seed, read by the probe kernels
+  bool capturing_ = false;    // enqueue into a graph capture: no event records, no seed write
+  void* hpack_ = nullptr;     // pinned host copy of pack_
+  bool own_hpack_ = false;
   // asymmetry of H accepted by the symmetric fast path of log(H) e1: rounding
   // level of the vectors' precision
   // relative asymmetry of H below which log(H) e1 takes the symmetric
@@ -291,6 +338,20 @@ class Run {
     ext_ = true;
   }
   void set_blocking(bool b) { blocking_ = b; }
+  // Pinned host buffer of at least kHostPackBytes for the packed results
+  // (owned by the caller); without one the run allocates its own.
+  void set_host_pack(void* p) { hpack_ = p; }
+  // Graph capture of the whole estimate: the seed write and the timing
+  // events stay out of the captured sequence (the replay does them around the
+  // graph launch: record ev0, write_seed, launch, record ev1).
+  void set_capturing(bool c) { capturing_ = c; }
+  ld_status write_seed(hipStream_t st);
+  ld_status enqueue_results(hipStream_t st);  // pack + copy to the pinned buffer
+  hipEvent_t start_event() const { return ev0_; }
+  hipEvent_t end_event() const { return ev1_; }
+  // whether the launch sequence depends on nothing but (matrix, params minus
+  // the seed): no adaptive host check, no per-launch profiling events
+  bool capturable() const;
   // Time the candidate geometries of the Krylov-block product and update on
   // this request's matrix and block shape; store the fastest in the matrix.
   ld_status tune(hipStream_t st, int reps, ld_tune_result* out);

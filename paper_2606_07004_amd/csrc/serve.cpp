@@ -29,6 +29,7 @@ Server::~Server() {
   }
   for (Slot& s : slots_) {
     if (s.done_ev) (void)hipEventDestroy(s.done_ev);
+    if (s.hpack) (void)hipHostFree(s.hpack);
     if (s.mem) (void)hipFree(s.mem);
   }
 }
@@ -198,6 +199,12 @@ void Server::loop() {
         finish(s, LD_E_DEVICE, nullptr, "event creation failed");
         continue;
       }
+      if (!s.hpack && hipHostMalloc(&s.hpack, kHostPackBytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        s.hpack = nullptr;
+        finish(s, LD_E_DEVICE, nullptr, "pinned result buffer allocation failed");
+        continue;
+      }
       if (s.mem_bytes < s.want_bytes) {
         if (s.mem) {
           (void)hipStreamSynchronize(stream_);
@@ -221,6 +228,7 @@ void Server::loop() {
       }
       // a slot's memory is reused only after its previous request's work:
       // every request runs on the one scheduler stream, in order
+      s.req->run->set_host_pack(s.hpack);
       ld_status brc = s.req->run->bind(s.mem, s.mem_bytes);
       if (brc != LD_OK) {
         finish(s, brc, nullptr, ld_last_error());

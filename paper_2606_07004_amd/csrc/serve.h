@@ -29,7 +29,6 @@ class Server {
     size_t peak_bytes = 0;       // most device bytes the slot buffers held at once
     size_t held_bytes = 0;       // device bytes the slot buffers hold now
     uint64_t buffer_allocs = 0, buffer_frees = 0;
-    uint64_t graph_replays = 0, graph_captures = 0;
     size_t budget_bytes = 0;
     int peak_active = 0;
   };
@@ -43,6 +42,7 @@ class Server {
   };
   struct Slot {
     hipEvent_t done_ev = nullptr;
+    void* hpack = nullptr;       // pinned buffer the request's results land in
     std::unique_ptr<Request> req;
     void* mem = nullptr;
     size_t mem_bytes = 0;        // bytes of the buffer (charged to held_)

@@ -76,9 +76,16 @@ class ld_serving_stats(C.Structure):
                 ("batched_steps", C.c_uint64), ("batched_launches", C.c_uint64),
                 ("held_bytes", C.c_uint64), ("peak_held_bytes", C.c_uint64),
                 ("budget_bytes", C.c_uint64), ("buffer_allocs", C.c_uint64),
-                ("buffer_frees", C.c_uint64), ("graph_replays", C.c_uint64),
-                ("graph_captures", C.c_uint64), ("peak_active", C.c_int32),
+                ("buffer_frees", C.c_uint64), ("peak_active", C.c_int32),
                 ("max_slots", C.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ld_graph_stats(C.Structure):
+    _fields_ = [("captures", C.c_uint64), ("replays", C.c_uint64), ("eager", C.c_uint64),
+                ("cached", C.c_uint64), ("mode", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -129,6 +136,8 @@ _SIGNATURES = [
     ("ld_estimate_noalloc", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(ld_result)]),
     ("ld_submit", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(C.c_uint64)]),
     ("ld_serving_stats_get", C.c_int32, [C.c_void_p, C.POINTER(ld_serving_stats)]),
+    ("ld_graph_mode", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("ld_graph_stats_get", C.c_int32, [C.c_void_p, C.POINTER(ld_graph_stats)]),
     ("ld_poll", C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(ld_result)]),
     ("ld_wait", C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(ld_result)]),
     ("ld_profile_enable", C.c_int32, [C.c_void_p, C.c_uint32]),
@@ -310,6 +319,16 @@ def ld_tune_set(a, params: ld_params, spmm_lanes: int, spmm_chunks: int, update_
 def ld_serving_stats_get(ctx) -> ld_serving_stats:
     out = ld_serving_stats()
     _check(lib().ld_serving_stats_get(ctx, C.byref(out)))
+    return out
+
+
+def ld_graph_mode(ctx, mode: int) -> None:
+    _check(lib().ld_graph_mode(ctx, int(mode)))
+
+
+def ld_graph_stats_get(ctx) -> ld_graph_stats:
+    out = ld_graph_stats()
+    _check(lib().ld_graph_stats_get(ctx, C.byref(out)))
     return out
 
 

@@ -33,9 +33,11 @@ int main(void) {
   F(ld_serving_stats, batched_steps); F(ld_serving_stats, batched_launches);
   F(ld_serving_stats, held_bytes); F(ld_serving_stats, peak_held_bytes);
   F(ld_serving_stats, budget_bytes); F(ld_serving_stats, buffer_allocs);
-  F(ld_serving_stats, buffer_frees); F(ld_serving_stats, graph_replays);
-  F(ld_serving_stats, graph_captures); F(ld_serving_stats, peak_active);
+  F(ld_serving_stats, buffer_frees); F(ld_serving_stats, peak_active);
   F(ld_serving_stats, max_slots);
   Z(ld_serving_stats);
+  F(ld_graph_stats, captures); F(ld_graph_stats, replays); F(ld_graph_stats, eager);
+  F(ld_graph_stats, cached); F(ld_graph_stats, mode);
+  Z(ld_graph_stats);
   return 0;
 }

@@ -55,7 +55,7 @@ def test_struct_layouts_match_header(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
     mirrors = {"ld_ctx_opts": L.ld_ctx_opts, "ld_params": L.ld_params, "ld_result": L.ld_result,
                "ld_detail": L.ld_detail, "ld_tune_result": L.ld_tune_result,
-               "ld_serving_stats": L.ld_serving_stats}
+               "ld_serving_stats": L.ld_serving_stats, "ld_graph_stats": L.ld_graph_stats}
     seen = {k: set() for k in mirrors}
     for line in out.strip().splitlines():
         struct, field, off, size = line.split()

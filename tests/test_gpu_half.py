@@ -115,12 +115,13 @@ def test_half_refuses_wide_spectral_interval(L, ctx):
     # a Wendland covariance with nugget 1e-2 (bound ratio ~1400): many
     # eigenvalues sit near the nugget and FP16 storage would move the estimate
     # by more than 1e-4, so the precision is refused; AUTO takes FP32 vectors
+    # (the ratio is below 4096)
     a = W.wendland(8000, 40.0, 1e-2, seed=2)
     h = ctx.matrix(a, vt=L.LD_VT_FP32, lo_hint=1e-2)
     try:
         lo, hi = L.ld_matrix_bounds(h)
         _announce(f"half refuses {a.name} ratio {hi / lo:.0f}")
-        assert hi > 512 * lo
+        assert 512 * lo < hi <= 4096 * lo
         p = L.make_params(30, 10, 30, 2, 5, precision=L.LD_PREC_HALF)
         with pytest.raises(L.LdError) as ei:
             L.ld_estimate_ex(h, p)
@@ -212,23 +213,22 @@ def test_half_rejects_long_windows(L, ctx):
 
 
 def test_auto_precision_choice(L, ctx):
-    # LD_PREC_AUTO: FP16 vectors when lambda_hi <= 512 lambda_lo (and window
-    # <= 4), FP32 otherwise; the result is bitwise the chosen precision's
-    for shift, expect in ((0.5, L.LD_PREC_HALF), (1e-3, L.LD_PREC_MIXED)):
+    # LD_PREC_AUTO: FP32 vectors when lambda_hi <= 4096 lambda_lo, FP64
+    # otherwise, never FP16 (whatever the window); the result is bitwise the
+    # chosen precision's
+    for shift, expect in ((0.5, L.LD_PREC_MIXED), (1e-2, L.LD_PREC_MIXED),
+                          (1e-4, L.LD_PREC_FP64)):
         a = W.lap2d(60, shift)
-        h = ctx.matrix(a, vt=L.LD_VT_FP32)
+        h = ctx.matrix(a, vt=L.LD_VT_FP32, lo_hint=shift)
         try:
             lo, hi = L.ld_matrix_bounds(h)
             _announce(f"auto precision {a.name} ratio {hi / lo:.1f}")
-            auto = L.ld_estimate_ex(h, L.make_params(20, 6, 20, 2, 8,
-                                                     precision=L.LD_PREC_AUTO)).logdet
-            ref = L.ld_estimate_ex(h, L.make_params(20, 6, 20, 2, 8, precision=expect)).logdet
-            assert auto == ref
-            # window 5 never takes FP16
-            auto5 = L.ld_estimate_ex(h, L.make_params(20, 6, 20, 5, 8,
-                                                      precision=L.LD_PREC_AUTO)).logdet
-            mixed5 = L.ld_estimate_ex(h, L.make_params(20, 6, 20, 5, 8,
-                                                       precision=L.LD_PREC_MIXED)).logdet
-            assert auto5 == mixed5
+            assert (hi <= 4096 * lo) == (expect == L.LD_PREC_MIXED)
+            for k in (2, 5):
+                auto = L.ld_estimate_ex(h, L.make_params(20, 6, 20, k, 8,
+                                                         precision=L.LD_PREC_AUTO)).logdet
+                ref = L.ld_estimate_ex(h, L.make_params(20, 6, 20, k, 8,
+                                                        precision=expect)).logdet
+                assert auto == ref
         finally:
             ctx.release(h)
