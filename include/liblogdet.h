@@ -394,6 +394,17 @@ ld_status ld_profile_query(ld_ctx* ctx, uint32_t family, int64_t* launches, doub
  * col_begin)], row-major. */
 ld_status ld_debug_rademacher(ld_ctx* ctx, uint64_t seed, int64_t n,
                               int32_t col_begin, int32_t col_end, double* out);
+/* Test hook: the quadrature value K_p = e1^T log(T_p) e1 of `runs`
+ * symmetric tridiagonal matrices, computed as the estimates compute it (the
+ * trapezoidal rule on the Stieltjes integral of log for [a, b], the
+ * Golub-Welsch rule for a T_p with an eigenvalue outside [a/1000, 1000 b]).
+ * T_p has dimension dims[p] <= m, diagonal alpha[p*m + t] and off-diagonal
+ * beta[p*m + t] (t < dims[p] - 1), host arrays.  need[p] = 1 where the
+ * Golub-Welsch rule gave K_p.  LD_E_NUMERIC on a non-positive Ritz value or
+ * a non-finite K. */
+ld_status ld_debug_quad_log(ld_ctx* ctx, int32_t runs, int32_t m, const double* alpha,
+                           const double* beta, const int32_t* dims, double a, double b,
+                           double* K, int32_t* need);
 /* Test hook: as ld_debug_rademacher for either distribution (ld_probe_dist). */
 ld_status ld_debug_probes(ld_ctx* ctx, uint64_t seed, int64_t n, int32_t col_begin,
                           int32_t col_end, int32_t dist, double* out);

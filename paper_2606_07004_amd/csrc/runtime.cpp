@@ -2121,6 +2121,56 @@ ld_status ld_debug_rademacher(ld_ctx* ctx, uint64_t seed, int64_t n, int32_t col
   return LD_OK;
 }
 
+ld_status ld_debug_quad_log(ld_ctx* ctx, int32_t runs, int32_t m, const double* alpha,
+                           const double* beta, const int32_t* dims, double a, double b,
+                           double* K, int32_t* need) {
+  if (!ctx || !alpha || !beta || !dims || !K || !need || runs < 1 || m < 1 || m > 512 ||
+      !(a > 0.0) || !(b >= a))
+    return set_error(LD_E_INVALID_ARG, "bad argument");
+  for (int p = 0; p < runs; ++p)
+    if (dims[p] < 0 || dims[p] > m) return set_error(LD_E_INVALID_ARG, "dims[p] must be in [0, m]");
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  LD_HIP_API(hipSetDevice(ctx->device));
+  // the Hessenberg layout of the estimates: run p's (m+1) x m block, diagonal
+  // h_tt and both off-diagonals h_t+1,t = h_t,t+1 = beta_t
+  const size_t hb = (size_t)(m + 1) * m;
+  std::vector<double> H((size_t)runs * hb, 0.0);
+  for (int p = 0; p < runs; ++p)
+    for (int t = 0; t < m; ++t) {
+      double* Hp = H.data() + (size_t)p * hb;
+      Hp[(size_t)t * m + t] = alpha[(size_t)p * m + t];
+      Hp[(size_t)(t + 1) * m + t] = beta[(size_t)p * m + t];
+      if (t + 1 < m) Hp[(size_t)t * m + t + 1] = beta[(size_t)p * m + t];
+    }
+  DeviceBuffer dH, dm, dK, dn, df;
+  LD_HIP_API(dH.ensure(H.size() * 8));
+  LD_HIP_API(dm.ensure((size_t)runs * 4));
+  LD_HIP_API(dK.ensure((size_t)runs * 8));
+  LD_HIP_API(dn.ensure((size_t)runs * 4));
+  LD_HIP_API(df.ensure((size_t)runs * 4));
+  LD_HIP_API(hipMemcpy(dH.ptr, H.data(), H.size() * 8, hipMemcpyHostToDevice));
+  LD_HIP_API(hipMemcpy(dm.ptr, dims, (size_t)runs * 4, hipMemcpyHostToDevice));
+  const FillItem fi{df.ptr, (size_t)runs, 0u};
+  LD_HIP_API(launch_fill(ctx->stream, &fi, 1));
+  double* hK = static_cast<double*>(dK.ptr);
+  int* hn = static_cast<int*>(dn.ptr);
+  int* hf = static_cast<int*>(df.ptr);
+  const double* hH = static_cast<const double*>(dH.ptr);
+  const int* hm = static_cast<const int*>(dm.ptr);
+  LD_HIP_API(launch_quad_log(ctx->stream, runs, m, hH, hm, a, b, hK, hn, hf));
+  LD_HIP_API(launch_gauss_log(ctx->stream, runs, m, hH, hm, hK, hf, hn));
+  LD_HIP_API(hipStreamSynchronize(ctx->stream));
+  std::vector<int> flags(runs);
+  LD_HIP_API(hipMemcpy(K, dK.ptr, (size_t)runs * 8, hipMemcpyDeviceToHost));
+  LD_HIP_API(hipMemcpy(need, dn.ptr, (size_t)runs * 4, hipMemcpyDeviceToHost));
+  LD_HIP_API(hipMemcpy(flags.data(), df.ptr, (size_t)runs * 4, hipMemcpyDeviceToHost));
+  for (int p = 0; p < runs; ++p)
+    if (flags[p] & 11)
+      return set_error(LD_E_NUMERIC, "run " + std::to_string(p) + ": flags " +
+                                         std::to_string(flags[p]));
+  return LD_OK;
+}
+
 ld_status ld_debug_probes(ld_ctx* ctx, uint64_t seed, int64_t n, int32_t col_begin,
                           int32_t col_end, int32_t dist, double* out) {
   if (!ctx || !out || n < 1 || col_begin < 0 || col_end <= col_begin || n > INT32_MAX ||

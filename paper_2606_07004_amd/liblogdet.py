@@ -146,6 +146,8 @@ _SIGNATURES = [
     ("ld_debug_rademacher", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, C.c_int32,
                                         _DP]),
     ("ld_debug_copy", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int32, _DP]),
+    ("ld_debug_quad_log", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _DP, _DP, _IP,
+                                      C.c_double, C.c_double, _DP, _IP]),
     ("ld_debug_stream", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int32, C.c_int32, C.c_int32,
                                     _DP]),
     ("ld_debug_probes", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, C.c_int32,
@@ -380,6 +382,22 @@ def ld_debug_probes(ctx, seed: int, n: int, col_begin: int, col_end: int,
     _check(lib().ld_debug_probes(ctx, seed, n, col_begin, col_end, dist,
                                  out.ctypes.data_as(_DP)))
     return out
+
+
+def ld_debug_quad_log(ctx, alpha, beta, dims, a: float, b: float):
+    """(K, need) of the tridiagonals (alpha[runs, m], beta[runs, m], dims[runs])
+    by the estimates' quadrature kernels."""
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    be = np.ascontiguousarray(beta, dtype=np.float64)
+    dm = np.ascontiguousarray(dims, dtype=np.int32)
+    runs, m = al.shape
+    assert be.shape == (runs, m) and dm.shape == (runs,)
+    K = np.zeros(runs)
+    need = np.zeros(runs, dtype=np.int32)
+    _check(lib().ld_debug_quad_log(ctx, runs, m, al.ctypes.data_as(_DP), be.ctypes.data_as(_DP),
+                                   dm.ctypes.data_as(_IP), float(a), float(b),
+                                   K.ctypes.data_as(_DP), need.ctypes.data_as(_IP)))
+    return K, need
 
 
 def ld_debug_copy(ctx, nbytes: int, reps: int = 10) -> float:

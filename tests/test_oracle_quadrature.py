@@ -149,3 +149,27 @@ def test_adaptive_estimate_close_to_converged_one():
         assert max(r.probe_steps) < 60
         steps.append(sum(r.probe_steps))
     assert steps[0] <= steps[1] <= steps[2]
+
+
+def test_gauss_quadrature_log_against_extended_precision():
+    # the same sum, e1^T log(T) e1 = sum_i u_{1i}^2 log(theta_i), from a
+    # 40-digit eigendecomposition: the FP64 rule must agree to 1e-13
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(11)
+    for trial in range(8):
+        m = int(rng.integers(2, 20))
+        d = rng.uniform(0.01, 50.0, m)
+        e = rng.uniform(-2.0, 2.0, m - 1)
+        t = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+        lam = np.linalg.eigvalsh(t)
+        if lam.min() <= 0:
+            d = d + (0.05 - lam.min())
+        M = mpmath.matrix(m, m)
+        for i in range(m):
+            M[i, i] = mpmath.mpf(float(d[i]))
+            if i + 1 < m:
+                M[i + 1, i] = M[i, i + 1] = mpmath.mpf(float(e[i]))
+        E, U = mpmath.eigsy(M)
+        exact = float(mpmath.fsum(U[0, i] ** 2 * mpmath.log(E[i]) for i in range(m)))
+        assert abs(gauss_quadrature_log(d, e) - exact) <= 1e-13 * max(1.0, abs(exact))
