@@ -551,6 +551,13 @@ def main():
     p = L.make_params(args.probes, args.sketch, args.krylov_steps, args.window, args.seed,
                       method=method, precision=prec)
 
+    try:
+        L.ld_request_bytes(h, p)  # parameter and precision checks, nothing runs
+    except L.LdError as e:
+        ctx.close()
+        print(json.dumps({"error": f"{args.precision} precision refused on {a.name}: {e}"}))
+        sys.exit(2)
+
     tune = None
     if args.tune_reps > 0:
         t_tune = time.perf_counter()
