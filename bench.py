@@ -80,6 +80,25 @@ def parse():
     return ap.parse_args()
 
 
+def pmc_record(key):
+    """The committed PMC record of a workload key, or None when there is none
+    or the kernel source changed since its counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        db = json.load(f)
+    recs = [r for r in db.get("records", []) if r.get("workload") == key]
+    if not recs:
+        return None
+    for src, digest in recs[0].get("sources", {}).items():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return recs[0]
+
+
 def pmc_traffic(args, family, tune):
     """HBM bytes per launch of `family`'s kernel from the committed PMC summary.
 
@@ -288,7 +307,10 @@ def configs_bench(L, W, args):
     64 probes = 21 + 43, 40 steps, window 2, lower hint 1e-2), FP32 values.
     Per precision: probe-steps/s over a few blocking estimates after a tuning
     pass, and the distance from the stored FP64 oracle result of the same
-    seeded inputs."""
+    seeded inputs.  For FP32 vectors also the product kernel: its time per
+    launch and rate on algorithmic bytes (HIP events, one estimate), and on
+    the bytes its L2 misses fetch (FETCH_SIZE / WRITE_SIZE from the committed
+    PMC record of this configuration, when the kernel source still matches)."""
     out = {}
     cases = {
         "er1e6_oslq_k4": (lambda: W.er_laplacian(1_000_000, 8_000_000, seed=0, shift=0.05),
@@ -303,7 +325,7 @@ def configs_bench(L, W, args):
             h = ctx.matrix(a, vt=L.LD_VT_FP32, lo_hint=lo)
             rec = {"n": a.n, "nnz": a.nnz, "probes": npr, "sketch": s, "steps": m, "window": k}
             del a
-            for prec in ("mixed", "half", "auto"):
+            for prec in ("mixed", "fp64", "half", "auto"):
                 p = L.make_params(npr, s, m, k, 0, precision=PRECISIONS[prec](L))
                 try:
                     if args.tune_reps > 0 and prec != "auto":
@@ -324,6 +346,25 @@ def configs_bench(L, W, args):
                              "logdet": r.logdet,
                              "rel_err_vs_oracle": (abs(r.logdet - gold["logdet"]) / abs(gold["logdet"])
                                                    if gold else None)}
+                if prec == "mixed":
+                    L.ld_profile_enable(ctx.handle, L.LD_PROF_SPMM)
+                    L.ld_estimate_ex(h, p)
+                    n_l, ms, by = L.ld_profile_query(ctx.handle, L.LD_PROF_SPMM)
+                    L.ld_profile_enable(ctx.handle, 0)
+                    ml = ms / max(1, n_l)
+                    prod = {"launches": n_l, "ms_per_launch": ml,
+                            "algorithmic_GB": by / max(1, n_l) / 1e9,
+                            "algorithmic_GB/s": by / (ms * 1e-3) / 1e9 if ms > 0 else None,
+                            "fabric_GB": None, "fabric_GB/s": None}
+                    pr = pmc_record(f"config {name} mixed")
+                    if pr:
+                        ks = [v for kname, v in pr["kernels"].items() if "k_spmm<" in kname]
+                        if ks:
+                            fb = max(ks, key=lambda v: v["dispatches"])["scaled_bytes"]
+                            prod["fabric_GB"] = fb / 1e9
+                            prod["fabric_GB/s"] = fb / (ml * 1e-3) / 1e9
+                            prod["pmc_summary"] = pr.get("summary")
+                    rec[prec]["product"] = prod
             ctx.release(h)
             out[name] = rec
             print(f"[bench] config {name} {rec}", file=sys.stderr, flush=True)
