@@ -366,8 +366,55 @@ def configs_bench(L, W, args):
                             prod["pmc_summary"] = pr.get("summary")
                     rec[prec]["product"] = prod
             ctx.release(h)
+            if name.startswith("wendland"):
+                # the same covariance stored with FP64 and BF16 values (FP32
+                # Krylov vectors): BF16 rounding changes the matrix, so its
+                # distance from the FP64 oracle of the FP64-valued matrix is
+                # reported, not gated
+                a = build()
+                p = L.make_params(npr, s, m, k, 0, precision=L.LD_PREC_MIXED)
+                rec["values"] = {"fp32": rec["mixed"]["rel_err_vs_oracle"]}
+                for vname, vt in (("fp64", L.LD_VT_FP64), ("bf16", L.LD_VT_BF16)):
+                    hv = ctx.matrix(a, vt=vt, lo_hint=lo)
+                    L.ld_estimate_ex(hv, p)
+                    t0 = time.perf_counter()
+                    r = L.ld_estimate_ex(hv, p)
+                    dt = time.perf_counter() - t0
+                    rec["values"][vname] = abs(r.logdet - gold["logdet"]) / abs(gold["logdet"]) if gold else None
+                    rec["values"][vname + "_ms"] = dt * 1e3
+                    ctx.release(hv)
+                del a
             out[name] = rec
             print(f"[bench] config {name} {rec}", file=sys.stderr, flush=True)
+    return out
+
+
+def window_variants(L, ctx, h, args):
+    """The headline matrix with windows 4 and 8 (OSLQ and OSA-IOP): FP32-vector
+    probe-steps/s and the distance from the FP64 estimate of the same
+    parameters (the headline itself is window 2)."""
+    out = {}
+    for method, mcode in (("oslq", L.LD_METHOD_OSLQ), ("osa_iop", L.LD_METHOD_OSA_IOP)):
+        for k in (4, 8):
+            p = L.make_params(args.probes, args.sketch, args.krylov_steps, k, args.seed,
+                              method=mcode, precision=L.LD_PREC_MIXED)
+            p64 = L.make_params(args.probes, args.sketch, args.krylov_steps, k, args.seed,
+                                method=mcode, precision=L.LD_PREC_FP64)
+            r64 = L.ld_estimate_ex(h, p64)
+            L.ld_estimate_ex(h, p)
+            reps = 2
+            steps = 0
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r = L.ld_estimate_ex(h, p)
+                steps += r.probe_steps
+            dt = time.perf_counter() - t0
+            out[f"{method}_k{k}"] = {"probe_steps_per_s": steps / dt,
+                                      "ms_per_estimate": dt * 1e3 / reps, "logdet": r.logdet,
+                                      "rel_err_vs_fp64_gpu": abs(r.logdet - r64.logdet) / abs(r64.logdet),
+                                      "fp64_ms": r64.device_ms}
+            print(f"[bench] window {method} k={k} {out[f'{method}_k{k}']}", file=sys.stderr,
+                  flush=True)
     return out
 
 
@@ -471,11 +518,13 @@ def serving_bench(L, W, args):
         t0 = time.perf_counter()
         hs = [None] * len(reqs)
         nnz = 0
+        shapes = [None] * len(reqs)
         with ThreadPoolExecutor(max_workers=8) as ex:
             futs = [ex.submit(W.build_request_matrix, r) for r in reqs]
             for i, (f, r) in enumerate(zip(futs, reqs)):
                 a = f.result()
                 nnz += a.nnz
+                shapes[i] = (a.n, a.nnz)
                 # FP64 storage: the mixed requests read FP64 values with FP64
                 # row sums (FP32 vectors), which keeps the ill-conditioned
                 # requests (nuggets down to 1e-3) well inside the 1e-4 gate
@@ -508,6 +557,21 @@ def serving_bench(L, W, args):
                "matrix_entries": nnz, "host_build_and_upload_s": t_build,
                "fp64_sequential_logdets_per_s": seq_rate, "slots": args.serve_slots}
 
+        bounds = [L.ld_matrix_bounds(h) for h in hs]
+
+        def alg_bytes(i, res, prec):
+            # the request's algorithmic bytes (the per-probe-step model: the
+            # matrix once per block of probes, the window vectors read once,
+            # the new vector written once), FP64 values (the storage here)
+            n, z = shapes[i]
+            r = reqs[i]
+            lo, hi = bounds[i]
+            fp32 = prec == L.LD_PREC_MIXED or (prec == L.LD_PREC_AUTO and hi <= 4096 * lo)
+            sx = 4 if fp32 else 8
+            b = r["n_probes"]
+            step = (z * (8 + 4) + 4 * (n + 1)) / b + (r["iop_window"] + 1) * n * sx
+            return res.probe_steps * step
+
         def saturate(prec):
             st0 = L.ld_serving_stats_get(ctx.handle)
             t0 = time.perf_counter()
@@ -516,7 +580,10 @@ def serving_bench(L, W, args):
             dt = time.perf_counter() - t0
             st1 = L.ld_serving_stats_get(ctx.handle)
             errs = [abs(sv.logdet - rf) / abs(rf) for sv, rf in zip(served, ref)]
+            tot = sum(alg_bytes(i, sv, prec) for i, sv in enumerate(served))
             return {"logdets_per_s": len(reqs) / dt, "wall_s": dt,
+                    "algorithmic_bytes": tot, "algorithmic_GB/s": tot / dt / 1e9,
+                    "probe_steps": sum(sv.probe_steps for sv in served),
                     "speedup_vs_fp64_sequential": len(reqs) / dt / seq_rate,
                     "max_rel_err_vs_fp64": max(errs),
                     "requests_over_1e-4": sum(1 for e in errs if e > 1e-4),
@@ -677,8 +744,11 @@ def main():
         configs = configs_bench(L, W, args)
 
     variants = None
+    windows = None
     if not args.no_variants:
         variants = precision_variants(L, ctx, h, args, accuracy.get("logdet_fp64_gpu"))
+        if args.grid == 128 and args.method == "oslq":
+            windows = window_variants(L, ctx, h, args)
 
     copy = None
     ceiling = None
@@ -762,6 +832,7 @@ def main():
         "graph_replay": graphs,
         "comparators": comparators,
         "precision_variants": variants,
+        "window_variants": windows,
         "configs": configs,
         "grf_sweep": grf_sweep,
         "copy_kernel": copy,

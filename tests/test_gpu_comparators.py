@@ -121,6 +121,10 @@ def test_so_slq_captures_rank_k(L, ctx):
     a = W.diag_matrix(d)
     ref, res, det = _check_so_slq(L, ctx, a, 18, 12, 4, 10, 10, 3, 1, tol=1e-8)
     assert res.logdet == pytest.approx(float(np.sum(np.log(d))), rel=1e-9)
+    # 12 sketch runs and 10 estimate runs (more sketch columns than runs):
+    # every sketch run from a generic start breaks down at dimension 5 (five
+    # distinct eigenvalues), so the reported steps are the runs' plus 12 x 5
+    assert res.probe_steps == sum(ref.probe_steps) + 12 * 5
 
 
 def test_so_slq_mixed(L, ctx):
