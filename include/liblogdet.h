@@ -416,9 +416,10 @@ ld_status ld_debug_probes(ld_ctx* ctx, uint64_t seed, int64_t n, int32_t col_beg
  * and to measure attainable HBM bandwidth. */
 ld_status ld_debug_copy(ld_ctx* ctx, uint64_t bytes, int32_t reps, double* ms);
 /* Calibration hook: attainable streaming bandwidth at a read:write mix.  A
- * plain 16-byte-per-lane kernel reads `reads` (1..3) device buffers of
- * `bytes` each and, with writes = 1, writes their elementwise sum to a
- * fourth (writes = 0: reads only).  Runs `reps` times after a warm-up and
+ * plain stream kernel (four 16-byte items per lane in flight, streaming
+ * loads and stores, up to 32768 short blocks: the fastest shape measured)
+ * reads `reads` (1..3) device buffers of `bytes` each and, with writes = 1,
+ * writes their elementwise sum to a fourth (writes = 0: reads only).  Runs `reps` times after a warm-up and
  * returns the mean device time per run in *ms; the bytes moved are
  * (reads + writes) * bytes. */
 ld_status ld_debug_stream(ld_ctx* ctx, uint64_t bytes, int32_t reads, int32_t writes,

@@ -486,36 +486,43 @@ __global__ __launch_bounds__(kThreads) void k_stream_rw(const float4* __restrict
                                                        const float4* __restrict__ a2,
                                                        float4* __restrict__ out,
                                                        float* __restrict__ sink, size_t n16) {
+  // the fastest plain stream measured on this part: four 16-byte items per
+  // lane in flight, streaming (non-temporal) loads and stores, many short
+  // blocks, consecutive groups of items on consecutive blocks
   constexpr int kPer = 4;
-  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
-  const size_t nchunk = (n16 + kThreads * kPer - 1) / (kThreads * kPer);
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  auto add = [](float4 x, float4 y) { return make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w); };
-  for (size_t j = 0; j * nb < nchunk; ++j) {
-    const size_t base = j * nb;
-    const size_t ch = (nb & 7) ? base + b : base + (size_t)(b & 7) * (nb >> 3) + (b >> 3);
-    if (ch >= nchunk) continue;
-    const size_t e0 = ch * kThreads * kPer + threadIdx.x;
-    float4 v[kPer];
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4* b0 = reinterpret_cast<const f4*>(a0);
+  const f4* b1 = reinterpret_cast<const f4*>(a1);
+  const f4* b2 = reinterpret_cast<const f4*>(a2);
+  f4* o = reinterpret_cast<f4*>(out);
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+  const size_t stride = (size_t)gridDim.x * kThreads * kPer;
+  for (size_t e0 = (size_t)blockIdx.x * kThreads * kPer + threadIdx.x; e0 < n16; e0 += stride) {
+    f4 v[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const size_t e = e0 + (size_t)u * kThreads;
-      v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      v[u] = f4{0.f, 0.f, 0.f, 0.f};
       if (e < n16) {
-        v[u] = a0[e];
-        if (R > 1) v[u] = add(v[u], a1[e]);
-        if (R > 2) v[u] = add(v[u], a2[e]);
+        v[u] = __builtin_nontemporal_load(b0 + e);
+        if (R > 1) v[u] += __builtin_nontemporal_load(b1 + e);
+        if (R > 2) v[u] += __builtin_nontemporal_load(b2 + e);
       }
     }
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const size_t e = e0 + (size_t)u * kThreads;
       if (e < n16) {
-        if (W) out[e] = v[u]; else acc = add(acc, v[u]);
+        if (W) __builtin_nontemporal_store(v[u], o + e); else acc += v[u];
       }
     }
   }
-  if (!W) sink[(size_t)blockIdx.x * kThreads + threadIdx.x] = acc.x + acc.y + acc.z + acc.w;
+  // read-only streams: the sum is stored only if it is not a number (the
+  // inputs are finite), which keeps the loads without a write per thread
+  if (!W) {
+    const float t = acc.x + acc.y + acc.z + acc.w;
+    if (t != t) sink[((size_t)blockIdx.x * kThreads + threadIdx.x) % ((size_t)kMaxBlocks * kThreads)] = t;
+  }
 }
 
 hipError_t launch_stream_rw(hipStream_t st, int reads, int writes, const void* const* src, void* dst,
@@ -530,23 +537,9 @@ hipError_t launch_stream_rw(hipStream_t st, int reads, int writes, const void* c
   const float4* a1 = reads > 1 ? static_cast<const float4*>(src[1]) : nullptr;
   const float4* a2 = reads > 2 ? static_cast<const float4*>(src[2]) : nullptr;
   float4* o = static_cast<float4*>(dst);
-  // one resident wave of blocks, a multiple of 8 (the sink holds kMaxBlocks)
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    cus = 256;
-  const void* fn = writes ? (reads == 1 ? (const void*)k_stream_rw<1, 1>
-                                        : reads == 2 ? (const void*)k_stream_rw<2, 1>
-                                                     : (const void*)k_stream_rw<3, 1>)
-                          : (reads == 1 ? (const void*)k_stream_rw<1, 0>
-                                        : reads == 2 ? (const void*)k_stream_rw<2, 0>
-                                                     : (const void*)k_stream_rw<3, 0>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  int nb = std::min(kMaxBlocks, per_cu * cus);
-  if (nb >= 8) nb &= ~7;
-  const dim3 grid(std::max(1, nb)), block(kThreads);
+  // up to 32768 blocks of 4 x 256 items each per round
+  const size_t groups = (n16 + (size_t)kThreads * 4 - 1) / ((size_t)kThreads * 4);
+  const dim3 grid((unsigned)std::min<size_t>(groups, 32768)), block(kThreads);
 #define LD_STREAM(RR, WW) \
   hipLaunchKernelGGL((k_stream_rw<RR, WW>), grid, block, 0, st, a0, a1, a2, o, sink, n16)
   if (writes) {

@@ -453,19 +453,20 @@ __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int Lr, const XT* 
   const int nn = (int)n;  // n < 2^31
   const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
   for (int j = 0; j * (int)gridDim.x < nchunk; ++j) {
-    const int ch = chunk_of(j, (int)blockIdx.x, (int)gridDim.x);
+    // a pure stream: consecutive chunks on consecutive blocks (see the update)
+    const int ch = j * (int)gridDim.x + (int)blockIdx.x;
     const int row = ch * rm.rpi + rm.rg;
     if (!rm.on || ch >= nchunk || row >= nn) continue;
 #pragma unroll
     for (int c = 0; c < C; ++c)
       if (okc[c]) {
         V16<XT> w;
-        w.load(W + (size_t)row * ld + colc[c]);
+        w.load_nt(W + (size_t)row * ld + colc[c]);
 #pragma unroll
         for (int v = 0; v < kDotsPerLaunch; ++v)
           if (v < nv) {
             V16<XT> x;
-            x.load(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
+            x.load_nt(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
               acc[v][c][e] = fma(double(x.v[e]), double(w.v[e]), acc[v][c][e]);
@@ -531,7 +532,10 @@ __device__ inline void update_body(int64_t n, int Lr, XT* __restrict__ W, int ld
   const int nn = (int)n;  // n < 2^31
   const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
   for (int j = 0; j * nbk < nchunk; ++j) {
-    const int ch = chunk_of(j, bk, nbk);
+    // a pure stream: consecutive chunks go to consecutive blocks (so the
+    // XCDs interleave), which streams faster than the XCD bands the product
+    // uses for its neighbour gathers
+    const int ch = j * nbk + bk;
     const int row = ch * rm.rpi + rm.rg;
     if (!rm.on || ch >= nchunk || row >= nn) continue;
 #pragma unroll
@@ -543,16 +547,14 @@ __device__ inline void update_body(int64_t n, int Lr, XT* __restrict__ W, int ld
 #pragma unroll
         for (int e = 0; e < VEC; ++e) wd[e] = U(w.v[e]);
         V16<XT> x1;
-        if constexpr (V1) x1.load(v1 + (size_t)row * ld + colc[c]);
+        if constexpr (V1) x1.load_nt(v1 + (size_t)row * ld + colc[c]);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
           if (v < nv) {
             V16<XT> x;
-            // the oldest window vector leaves the window with this step
-            if (v == 0 && nv >= 2)
-              x.load_nt(static_cast<const XT*>(vx[v]) + (size_t)row * ld + colc[c]);
-            else
-              x.load(static_cast<const XT*>(vx[v]) + (size_t)row * ld + colc[c]);
+            // every block is read once per launch and a block is far larger
+            // than the caches: streaming loads throughout
+            x.load_nt(static_cast<const XT*>(vx[v]) + (size_t)row * ld + colc[c]);
             const U* cfv = cf + v * ld + colc[c];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) wd[e] = fma(-cfv[e], U(x.v[e]), wd[e]);

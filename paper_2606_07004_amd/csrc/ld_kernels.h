@@ -354,8 +354,9 @@ hipError_t launch_pack_results(hipStream_t st, int ld, const double* K, const do
 // Plain device copy of `bytes` (multiple of 16 used), calibration only.
 hipError_t launch_copy16(hipStream_t st, const void* src, void* dst, size_t bytes);
 // Bandwidth probe: reads `reads` (1..3) streams src[0..reads-1] of `bytes`
-// each and writes their sum to dst (writes = 1) or, with writes = 0, one
-// running sum per thread to sink (kMaxBlocks * kThreads floats).
+// each and writes their sum to dst (writes = 1); with writes = 0 the sums
+// stay in registers and reach sink (kMaxBlocks * kThreads floats) only if
+// one is not a number.
 hipError_t launch_stream_rw(hipStream_t st, int reads, int writes, const void* const* src, void* dst,
                             float* sink, size_t bytes);
 
