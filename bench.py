@@ -327,9 +327,10 @@ def configs_bench(L, W, args):
             del a
             for prec in ("mixed", "fp64", "half", "auto"):
                 p = L.make_params(npr, s, m, k, 0, precision=PRECISIONS[prec](L))
+                interleaved = 0
                 try:
                     if args.tune_reps > 0 and prec != "auto":
-                        L.ld_autotune(h, p, args.tune_reps)
+                        interleaved = L.ld_autotune(h, p, args.tune_reps).spmm_interleave
                     r = L.ld_estimate_ex(h, p)
                 except L.LdError as e:
                     # FP16 vectors are refused outside the range where they
@@ -357,7 +358,10 @@ def configs_bench(L, W, args):
                             "algorithmic_GB/s": by / (ms * 1e-3) / 1e9 if ms > 0 else None,
                             "fabric_GB": None, "fabric_GB/s": None}
                     pr = pmc_record(f"config {name} mixed")
-                    if pr:
+                    # the counters describe the product's chunk mapping they
+                    # were taken with (the default, banded, without tuning)
+                    prod["interleaved"] = interleaved
+                    if pr and pr.get("product_interleave", 0) == interleaved:
                         ks = [v for kname, v in pr["kernels"].items() if "k_spmm<" in kname]
                         if ks:
                             fb = max(ks, key=lambda v: v["dispatches"])["scaled_bytes"]
@@ -821,6 +825,8 @@ def main():
                                  "fp64": "FP64 throughout"}[args.precision],
                    "values": {0: "fp64", 1: "fp32", 2: "bf16"}[vt], "parallelism": "single GPU",
                    "geometry": ({"product": [tune["spmm_lanes"], tune["spmm_chunks"]],
+                                 "product_entry_split": tune["spmm_entry_split"],
+                                 "product_interleaved": tune["spmm_interleave"],
                                  "update": [tune["update_lanes"], tune["update_chunks"]]}
                                 if tune else "default")},
         "autotune": tune,

@@ -299,18 +299,23 @@ typedef struct {
   double update_ms, update_default_ms;
   int32_t candidates;        /* geometries timed for the product               */
   int32_t spmm_entry_split;  /* sparse-entry groups per row of the product     */
+  int32_t spmm_interleave;   /* 1: the product's row chunks interleave over the
+                              * XCDs; 0: a contiguous band of chunks per XCD,
+                              * which keeps a row's neighbours in one L2    */
 } ld_tune_result;
 ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_result* out);
 /* Stores a given geometry for the estimate block of `p` on this matrix (a
  * choice found earlier, or one to test): the product with spmm_lanes lanes
- * per row, spmm_chunks chunks per lane and its entries split over
- * spmm_entry_split lane groups, the update likewise (no split).  Any
- * (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8}, E <= L, C <= 2
- * when E > 1, and (L / E) * C chunks covering the block is accepted, where
- * L is a power of two when E > 1; anything else is LD_E_INVALID_ARG and
- * stores nothing. */
+ * per row, spmm_chunks chunks per lane, its entries split over
+ * spmm_entry_split lane groups and its row chunks interleaved over the XCDs
+ * (spmm_interleave 1) or banded per XCD (0), the update likewise (no split,
+ * interleaved).  Any (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8},
+ * E <= L, C <= 2 when E > 1, and (L / E) * C chunks covering the block is
+ * accepted, where L is a power of two when E > 1; anything else is
+ * LD_E_INVALID_ARG and stores nothing. */
 ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
-                      int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks);
+                      int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks,
+                      int32_t spmm_interleave);
 
 /* Serving with continuous batching: queue a request and return at once with
  * a ticket.  Requests are admitted as resident slots and HBM budget free up;

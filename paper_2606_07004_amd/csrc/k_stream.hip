@@ -212,7 +212,7 @@ __device__ inline void spmm_body(int64_t n, int Lr, int lgES_arg, const int* __r
                                  const XT* __restrict__ X, XT* __restrict__ W, int ld, int ncolv,
                                  const double* __restrict__ xmult, double opscale, const void* const* fx,
                                  const double* const* fmult, int voff, double* __restrict__ part,
-                                 int bk, int nbk) {
+                                 int bk, int nbk, int il) {
   // FP32 sums for FP32 (or BF16) values on FP32 vectors; FP64 sums whenever
   // the values or the vectors are FP64
   using A = typename std::conditional<std::is_same<VT, double>::value, double,
@@ -259,7 +259,9 @@ __device__ inline void spmm_body(int64_t n, int Lr, int lgES_arg, const int* __r
   const int nn = (int)n;  // n < 2^31
   const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
   for (int j = 0; j * nbk < nchunk; ++j) {
-    const int ch = chunk_of(j, bk, nbk);
+    // per-XCD bands keep a row's neighbours in one L2; interleaving streams
+    // better on wide rows (a tuning choice)
+    const int ch = il ? j * nbk + bk : chunk_of(j, bk, nbk);
     const int row = ch * rm.rpi + rm.rg;
     if (!rm.on || ch >= nchunk || row >= nn) continue;
     A acc[C][VEC];
@@ -420,7 +422,7 @@ __global__ __launch_bounds__(kThreads, (NF == 2 || (sizeof(VT) == 8 && sizeof(XT
   spmm_body<VT, XT, C, NF, SPLIT>(q.n, q.L, q.lgES, q.rp, q.ci, static_cast<const VT*>(q.va),
                            static_cast<const XT*>(q.X), static_cast<XT*>(q.W), q.ld, q.ncolv, q.xmult,
                            q.opscale, q.fx, q.fmult, q.voff, q.part, (int)blockIdx.x - bt.off[r],
-                           bt.off[r + 1] - bt.off[r]);
+                           bt.off[r + 1] - bt.off[r], q.il);
 }
 
 // ---------------------------------------------------------------------------
@@ -1260,6 +1262,7 @@ static hipError_t spmm_launch(hipStream_t st, SpmmItem* items, const int* idx, i
     d.ld = it.g.ld;
     d.ncolv = it.g.ncolv;
     d.voff = it.voff;
+    d.il = it.g.xil;
     bt.off[q] = off;
     off += nb;
   }

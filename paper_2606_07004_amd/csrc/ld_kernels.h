@@ -38,6 +38,8 @@ struct Geom {
   int nblk = 0;
   int rpb = 0;     // rows per block
   int lges = 0;    // product only: log2 of the entry split (L / 2^lges column lanes)
+  int xil = 0;     // product only: 1 = consecutive row chunks on consecutive blocks
+                   // (XCDs interleaved), 0 = a contiguous band of chunks per XCD
 };
 Geom make_geom(int64_t n, int ld, int xbytes);
 // The same with an explicit lanes-per-row L and chunks per lane C (an
@@ -73,6 +75,7 @@ struct SpmmDesc {
   const double* fmult[2];
   double* part;
   int L, lgES, ld, ncolv, voff;  // L lanes per row (see Geom)
+  int il;                        // Geom::xil
 };
 
 struct UpdDesc {

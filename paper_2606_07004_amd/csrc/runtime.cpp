@@ -398,7 +398,8 @@ Geom Run::krylov_geom(int ld, int which) const {
     auto it = a_->tune.find(tune_key(ld, xb_, vt, which));
     if (it != a_->tune.end()) {
       Geom g = make_geom_lc(n_, ld, xb_, it->second.first & 0xff, it->second.second);
-      g.lges = it->second.first >> 8;  // entry split of the product
+      g.lges = (it->second.first >> 8) & 0xf;  // entry split of the product
+      g.xil = (it->second.first >> 12) & 1;    // chunk mapping of the product
       if (geom_usable(g)) return g;
     }
   }
@@ -1214,9 +1215,11 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail, 
 // geometry first.  With split > 0 (the product) also every entry split
 // 2^e <= 8 of each pair with L 2^e <= 64 lanes per row, encoded as
 // (L 2^e) | (e << 8).  Then the pairs L = ceil(chunks / C) where that is
-// not a power of two (floor(64 / L) rows per wave).
+// not a power of two (floor(64 / L) rows per wave).  With interleave, every
+// candidate again with the product's chunks interleaved over the XCDs
+// (bit 12), timed for the product only.
 static std::vector<std::pair<int, int>> tune_candidates(int64_t n, int ld, int xbytes,
-                                                        bool split) {
+                                                        bool split, bool interleave) {
   const Geom d = make_geom(n, ld, xbytes);
   std::vector<std::pair<int, int>> out{{d.L, d.C}};
   for (int L = 1; L <= 64; L <<= 1)
@@ -1235,12 +1238,17 @@ static std::vector<std::pair<int, int>> tune_candidates(int64_t n, int ld, int x
     if (L > 64 || (L & (L - 1)) == 0) continue;
     if (geom_usable(make_geom_lc(n, ld, xbytes, L, C))) out.push_back({L, C});
   }
+  if (interleave) {
+    const size_t base = out.size();
+    for (size_t i = 0; i < base; ++i) out.push_back({out[i].first | (1 << 12), out[i].second});
+  }
   return out;
 }
 
 static Geom candidate_geom(int64_t n, int ld, int xbytes, const std::pair<int, int>& c) {
   Geom g = make_geom_lc(n, ld, xbytes, c.first & 0xff, c.second);
-  g.lges = c.first >> 8;
+  g.lges = (c.first >> 8) & 0xf;
+  g.xil = (c.first >> 12) & 1;
   return g;
 }
 
@@ -1299,7 +1307,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7475u, n_, 0, ld, ld, X, xb_, ld, 0));
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7476u, n_, 0, ld, ld, V, xb_, ld, 0));
     // entry splits only pay on rows of many entries
-    const auto cand = tune_candidates(n_, ld, xb_, a_->nnz >= 16 * a_->n);
+    const auto cand = tune_candidates(n_, ld, xb_, a_->nnz >= 16 * a_->n, true);
     const int nc = (int)cand.size();
     std::vector<double> tp(nc, 1e300), tu(nc, 1e300);
     VecSet vf{};
@@ -1329,7 +1337,8 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
         LD_HIP(hipEventSynchronize(ev.b));
         LD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
         tp[c] = std::min(tp[c], (double)ms / reps);
-        if (g.lges != 0) continue;  // the update has no sparse entries to split
+        // the update has no sparse entries to split and keeps its own mapping
+        if (g.lges != 0 || g.xil != 0) continue;
         LD_HIP(update());
         LD_HIP(hipEventRecord(ev.a, st));
         for (int i = 0; i < reps; ++i) LD_HIP(update());
@@ -1357,7 +1366,8 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
       *out = ld_tune_result{};
       out->spmm_lanes = cand[bp].first & 0xff;
       out->spmm_chunks = cand[bp].second;
-      out->spmm_entry_split = 1 << (cand[bp].first >> 8);
+      out->spmm_entry_split = 1 << ((cand[bp].first >> 8) & 0xf);
+      out->spmm_interleave = (cand[bp].first >> 12) & 1;
       out->update_lanes = cand[bu].first;
       out->update_chunks = cand[bu].second;
       out->spmm_ms = tp[bp];
@@ -1371,20 +1381,22 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
 }
 
 ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int update_lanes,
-                         int update_chunks) {
+                         int update_chunks, int spmm_interleave) {
   int e = 0;
   while (e < 4 && (1 << e) < spmm_split) ++e;
   Geom gp = make_geom_lc(n_, ldB_, xb_, spmm_lanes, spmm_chunks);
   gp.lges = e;
-  if ((1 << e) != spmm_split || !geom_usable(gp) ||
+  if ((1 << e) != spmm_split || !geom_usable(gp) || (spmm_interleave != 0 && spmm_interleave != 1) ||
       !geom_usable(make_geom_lc(n_, ldB_, xb_, update_lanes, update_chunks)))
     return set_error(LD_E_INVALID_ARG,
                      "lanes must be <= 64 (a power of two with an entry split), chunks in "
                      "[1, 4] and the entry split 1, 2, 4 or 8 (at most the lanes), the lanes "
-                     "per split group and the chunks covering the probe block");
+                     "per split group and the chunks covering the probe block, interleave 0 "
+                     "or 1");
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
   std::lock_guard<std::mutex> lk(a_->tune_mu);
-  a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes | (e << 8), spmm_chunks};
+  a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes | (e << 8) | (spmm_interleave << 12),
+                                         spmm_chunks};
   a_->tune[tune_key(ldB_, xb_, vt, 1)] = {update_lanes, update_chunks};
   a_->tune_ver.fetch_add(1);
   return LD_OK;
@@ -1832,12 +1844,14 @@ ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_re
 }
 
 ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
-                      int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks) {
+                      int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks,
+                      int32_t spmm_interleave) {
   if (!a || !p) return set_error(LD_E_INVALID_ARG, "null argument");
   Run run(a, *p);
   ld_status rc = run.validate();
   if (rc != LD_OK) return rc;
-  return run.tune_set(spmm_lanes, spmm_chunks, spmm_entry_split, update_lanes, update_chunks);
+  return run.tune_set(spmm_lanes, spmm_chunks, spmm_entry_split, update_lanes, update_chunks,
+                      spmm_interleave);
 }
 
 ld_status ld_quad_form(ld_matrix* a, const double* x, double* out) {

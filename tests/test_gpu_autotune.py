@@ -74,9 +74,12 @@ def _sweep(L, ctx, a, npr, prec, vt, rtol_oracle, rtol_default, vec, k):
             # the update takes the geometries in the other order, so product
             # and update differ in most cases
             ul, uc = geoms[(len(geoms) - 1 - i) % len(geoms)]
+            # every other case interleaves the product's chunks over the XCDs
+            il = i % 2
             _announce(f"forced geometry n={a.n} probes={npr} prec={prec} "
-                      f"product L={lanes * e} C={ch} split={e} update L={ul} C={uc}")
-            L.ld_tune_set(h, p, lanes * e, ch, ul, uc, e)
+                      f"product L={lanes * e} C={ch} split={e} interleave={il} "
+                      f"update L={ul} C={uc}")
+            L.ld_tune_set(h, p, lanes * e, ch, ul, uc, e, il)
             res, det = L.ld_estimate_detail(h, p, n=a.n, tri=True)
             rel = abs(res.logdet - ref.logdet) / abs(ref.logdet)
             assert rel <= rtol_oracle, (lanes, ch, ul, uc, rel)
@@ -152,6 +155,10 @@ def test_invalid_geometry_rejected(L, ctx):
             with pytest.raises(L.LdError) as ei:
                 L.ld_tune_set(h, p, bad[0], bad[1], 4, 3, bad[2])
             assert ei.value.status == L.LD_E_INVALID_ARG
+        _announce("ld_tune_set rejects an interleave flag other than 0 or 1")
+        with pytest.raises(L.LdError) as ei:
+            L.ld_tune_set(h, p, 16, 1, 16, 1, 1, 2)
+        assert ei.value.status == L.LD_E_INVALID_ARG
         _announce("ld_tune_set rejects an update with L=11 C=1")
         with pytest.raises(L.LdError) as ei:
             L.ld_tune_set(h, p, 12, 1, 11, 1, 1)
