@@ -359,7 +359,9 @@ ld_status ld_serving_stats_get(ld_ctx* ctx, ld_serving_stats* out);
  * matrix whose interval has zero width always launch kernel by kernel.  Up
  * to 8 graphs are kept per context, least recently used dropped first; a
  * matrix's graphs go with ld_destroy, and all of them when the context's
- * workspace grows; a new autotune result makes a new graph.  Mode 0
+ * workspace grows; a new autotune result makes a new graph.  Should the
+ * runtime refuse a capture, the context switches itself to mode 0 and the
+ * estimate runs kernel by kernel (capture_failed below).  Mode 0
  * launches every estimate kernel by kernel and drops the kept graphs.
  * Thread-safe (estimates of a context run one at a time). */
 ld_status ld_graph_mode(ld_ctx* ctx, int32_t mode);
@@ -369,6 +371,9 @@ typedef struct {
   uint64_t eager;     /* blocking estimates launched kernel by kernel         */
   uint64_t cached;    /* graphs kept now                                      */
   int32_t mode;       /* the ld_graph_mode setting                            */
+  int32_t capture_failed; /* 1: a capture or instantiation failed; the context
+                           * then switched to mode 0 and ran that estimate
+                           * kernel by kernel                                 */
 } ld_graph_stats;
 ld_status ld_graph_stats_get(ld_ctx* ctx, ld_graph_stats* out);
 

@@ -1898,15 +1898,21 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
   LD_HIP_API(hipSetDevice(ctx->device));
   if (!ctx->na_ev[0] || !ctx->na_nact || !ctx->na_pack)
     return set_error(LD_E_INVALID_ARG, "context without its blocking-estimate set-up");
-  Run run(a, *p);
-  run.set_submit_time(t0);
-  run.set_profiler(&ctx->prof);
-  run.set_blocking(true);
-  run.use_external(ctx->na_ev[0], ctx->na_ev[1], ctx->na_ev[2], ctx->na_nact);
-  run.set_host_pack(ctx->na_pack);
-  ld_status rc = run.validate();
+  // a run with the context's events and pinned buffers (a second one only
+  // when a graph capture fails and the estimate runs kernel by kernel)
+  auto make_run = [&](std::unique_ptr<Run>& r) -> ld_status {
+    r.reset(new Run(a, *p));
+    r->set_submit_time(t0);
+    r->set_profiler(&ctx->prof);
+    r->set_blocking(true);
+    r->use_external(ctx->na_ev[0], ctx->na_ev[1], ctx->na_ev[2], ctx->na_nact);
+    r->set_host_pack(ctx->na_pack);
+    return r->validate();
+  };
+  std::unique_ptr<Run> runp;
+  ld_status rc = make_run(runp);
   if (rc != LD_OK) return rc;
-  const size_t need = run.device_bytes();
+  const size_t need = runp->device_bytes();
   const void* ws0 = ctx->workspace.ptr;
   const size_t wb0 = ctx->workspace.bytes;
   hipError_t e = ctx->workspace.ensure(need);
@@ -1915,10 +1921,11 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
                      std::string("workspace allocation: ") + hipGetErrorString(e));
   // graphs captured on the old workspace point into freed memory
   if (ctx->workspace.ptr != ws0 || ctx->workspace.bytes != wb0) ctx->graphs.drop_workspace();
-  rc = run.bind(ctx->workspace.ptr, ctx->workspace.bytes);
+  rc = runp->bind(ctx->workspace.ptr, ctx->workspace.bytes);
   if (rc != LD_OK) return rc;
   GraphCache& gc = ctx->graphs;
-  if (gc.mode == 1 && run.capturable()) {
+  if (gc.mode == 1 && runp->capturable()) {
+    Run& run = *runp;
     GraphKey key;
     key.serial = a->serial;
     key.tune_ver = a->tune_ver.load();
@@ -1941,8 +1948,18 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
       // second estimate of this shape: capture its launches (nothing runs
       // during the capture), then replay below
       rc = capture_estimate(ctx, run, key);
-      if (rc != LD_OK) return rc;
-      ent = gc.find(key);
+      if (rc != LD_OK) {
+        // the runtime would not capture or instantiate it: this context
+        // launches kernel by kernel from now on, starting with a fresh run
+        gc.mode = 0;
+        gc.failed = true;
+        gc.clear();
+        rc = make_run(runp);
+        if (rc == LD_OK) rc = runp->bind(ctx->workspace.ptr, ctx->workspace.bytes);
+        if (rc != LD_OK) return rc;
+      } else {
+        ent = gc.find(key);
+      }
     }
     if (ent) {
       // record start, seed, the graph, record end, results: the launches of
@@ -1962,6 +1979,7 @@ ld_status ld_estimate_detail(ld_matrix* a, const ld_params* p, ld_result* out,
     }
   }
   ++gc.eager;
+  Run& run = *runp;
   bool done = false;
   while (!done) {
     rc = run.advance(ctx->stream, 1 << 30, &done);
@@ -2233,6 +2251,7 @@ ld_status ld_graph_stats_get(ld_ctx* ctx, ld_graph_stats* out) {
   o.eager = ctx->graphs.eager;
   o.cached = (uint64_t)ctx->graphs.entries.size();
   o.mode = ctx->graphs.mode;
+  o.capture_failed = ctx->graphs.failed ? 1 : 0;
   *out = o;
   return LD_OK;
 }

@@ -61,6 +61,7 @@ struct GraphCache {
   std::vector<Entry> entries;
   std::deque<GraphKey> seen;  // keys run once without a graph (capture on the next)
   int mode = 1;
+  bool failed = false;  // a capture failed: graphs switched off for the context
   uint64_t tick = 0, captures = 0, replays = 0, eager = 0;
   ~GraphCache() { clear(); }
   Entry* find(const GraphKey& k);

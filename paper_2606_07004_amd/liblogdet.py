@@ -85,7 +85,8 @@ class ld_serving_stats(C.Structure):
 
 class ld_graph_stats(C.Structure):
     _fields_ = [("captures", C.c_uint64), ("replays", C.c_uint64), ("eager", C.c_uint64),
-                ("cached", C.c_uint64), ("mode", C.c_int32)]
+                ("cached", C.c_uint64), ("mode", C.c_int32),
+                ("capture_failed", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

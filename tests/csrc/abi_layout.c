@@ -38,7 +38,7 @@ int main(void) {
   F(ld_serving_stats, max_slots);
   Z(ld_serving_stats);
   F(ld_graph_stats, captures); F(ld_graph_stats, replays); F(ld_graph_stats, eager);
-  F(ld_graph_stats, cached); F(ld_graph_stats, mode);
+  F(ld_graph_stats, cached); F(ld_graph_stats, mode); F(ld_graph_stats, capture_failed);
   Z(ld_graph_stats);
   return 0;
 }

@@ -189,7 +189,7 @@ def test_mode_switch(L):
         assert L.ld_graph_stats_get(ctx.handle).cached == 1
         L.ld_graph_mode(ctx.handle, 0)
         st = L.ld_graph_stats_get(ctx.handle)
-        assert st.cached == 0 and st.mode == 0
+        assert st.cached == 0 and st.mode == 0 and st.capture_failed == 0
         vals.append(L.ld_estimate_ex(h, p).logdet)
         assert len(set(vals)) == 1
         with pytest.raises(L.LdError):
