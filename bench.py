@@ -422,6 +422,42 @@ def window_variants(L, ctx, h, args):
     return out
 
 
+def shift_variants(L, W, args):
+    """The headline Laplacian with the other shifts of its configuration
+    (1e-3 and 1e-1; the headline is 1e-2): FP32 vectors and LD_PREC_AUTO
+    (FP64 at 1e-3, where lambda_hi / lambda_lo is 12006), each against the
+    FP64 estimate and the closed-form log-determinant."""
+    out = {}
+    with L.Context(0) as ctx:
+        for shift in (1e-3, 1e-1):
+            a = W.lap3d(args.grid, shift)
+            h = ctx.matrix(a, vt=L.LD_VT_FP32)
+            exact = W.lap3d_exact_logdet(args.grid, shift)
+            rec = {"closed_form": exact}
+            r64 = L.ld_estimate_ex(h, L.make_params(args.probes, args.sketch, args.krylov_steps,
+                                                    args.window, args.seed,
+                                                    precision=L.LD_PREC_FP64))
+            rec["fp64_ms"] = r64.device_ms
+            for name, prec in (("mixed", L.LD_PREC_MIXED), ("auto", L.LD_PREC_AUTO)):
+                p = L.make_params(args.probes, args.sketch, args.krylov_steps, args.window,
+                                  args.seed, precision=prec)
+                L.ld_estimate_ex(h, p)
+                reps = 2
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    r = L.ld_estimate_ex(h, p)
+                dt = (time.perf_counter() - t0) / reps
+                rec[name] = {"ms_per_estimate": dt * 1e3, "probe_steps_per_s": r.probe_steps / dt,
+                             "rel_err_vs_fp64_gpu": abs(r.logdet - r64.logdet) / abs(r64.logdet),
+                             "rel_err_vs_closed_form": abs(r.logdet - exact) / abs(exact)}
+            lo, hi = L.ld_matrix_bounds(h)
+            rec["bound_ratio"] = hi / lo
+            ctx.release(h)
+            out[f"shift_{shift:g}"] = rec
+            print(f"[bench] shift {shift:g} {rec}", file=sys.stderr, flush=True)
+    return out
+
+
 def precision_variants(L, ctx, h, args, ref):
     """The headline workload with the Krylov vectors in the other precisions
     (FP32 and FP64 beside FP16): probe-steps/s over a few blocking estimates
@@ -749,10 +785,12 @@ def main():
 
     variants = None
     windows = None
+    shifts = None
     if not args.no_variants:
         variants = precision_variants(L, ctx, h, args, accuracy.get("logdet_fp64_gpu"))
         if args.grid == 128 and args.method == "oslq":
             windows = window_variants(L, ctx, h, args)
+            shifts = shift_variants(L, W, args)
 
     copy = None
     ceiling = None
@@ -839,6 +877,7 @@ def main():
         "comparators": comparators,
         "precision_variants": variants,
         "window_variants": windows,
+        "shift_variants": shifts,
         "configs": configs,
         "grf_sweep": grf_sweep,
         "copy_kernel": copy,
