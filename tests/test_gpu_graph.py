@@ -196,3 +196,46 @@ def test_mode_switch(L):
             L.ld_graph_mode(ctx.handle, 2)
     finally:
         ctx.close()
+
+
+def test_concurrent_callers_share_the_cache(L):
+    # blocking estimates of one context from several host threads: they run
+    # one at a time, capture and replay through one cache, and every result
+    # is bitwise the kernel-by-kernel one
+    import threading
+    ctx = L.Context(0)
+    ref_ctx = L.Context(0)
+    L.ld_graph_mode(ref_ctx.handle, 0)
+    try:
+        mats = [W.lap2d(48, 0.1), W.lap3d(14, 0.2), W.lap2d(40, 0.05)]
+        hs = [ctx.matrix(a, vt=L.LD_VT_FP32) for a in mats]
+        hr = [ref_ctx.matrix(a, vt=L.LD_VT_FP32) for a in mats]
+        jobs = [(i % 3, 500 + i) for i in range(24)]
+        p = lambda seed: L.make_params(16, 4, 12, 2, seed, precision=L.LD_PREC_MIXED)
+        _announce("graph: 4 threads x 6 estimates on one context")
+        want = {j: L.ld_estimate_ex(hr[j[0]], p(j[1])).logdet for j in jobs}
+        # one call per matrix first, the largest first, so that the workspace
+        # does not grow (and drop the graphs) once the threads run
+        for i in (1, 0, 2):
+            L.ld_estimate_ex(hs[i], p(1))
+        got = {}
+        errs = []
+
+        def worker(part):
+            try:
+                for j in part:
+                    got[j] = L.ld_estimate_ex(hs[j[0]], p(j[1])).logdet
+            except Exception as e:  # reported below
+                errs.append(e)
+        ths = [threading.Thread(target=worker, args=(jobs[t::4],)) for t in range(4)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        assert not errs, errs
+        assert got == want
+        st = L.ld_graph_stats_get(ctx.handle)
+        assert st.captures == 3 and st.replays == 24
+    finally:
+        ctx.close()
+        ref_ctx.close()
