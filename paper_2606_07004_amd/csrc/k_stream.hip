@@ -1383,7 +1383,8 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
 
 static bool update_item_ok(const UpdateItem& it) {
   const Geom& g = it.g;
-  if (!geom_ok(g) || g.lges != 0 || g.ld > kMaxLd || !it.W || !it.d || it.nv < 0 || it.nv > 4 ||
+  if (!geom_ok(g) || g.lges != 0 || g.ld > kMaxLd || !it.W || !it.d || it.nv < 0 ||
+      it.nv > kMaxNv || (it.nv > 4 && g.xbytes == 2) ||
       (it.want_norm && !it.part) || (it.v1 && !it.v1mult) || (it.sym && !it.want_norm))
     return false;
   for (int v = 0; v < it.nv; ++v)
@@ -1391,7 +1392,9 @@ static bool update_item_ok(const UpdateItem& it) {
   return true;
 }
 
-static int update_nv_class(int nv) { return nv <= 1 ? 1 : (nv == 2 ? 2 : 4); }
+// update instantiations by window vectors per launch: 1, 2, up to 4, up to
+// 8 (FP32 and FP64 vectors; FP16 vectors take windows up to 4)
+static int update_nv_class(int nv) { return nv <= 1 ? 1 : (nv == 2 ? 2 : (nv <= 4 ? 4 : 8)); }
 
 template <typename XT, int C, int NV, bool V1, bool SYM>
 static hipError_t update_launch(hipStream_t st, UpdateItem* items, const int* idx, int cnt) {
@@ -1406,7 +1409,7 @@ static hipError_t update_launch(hipStream_t st, UpdateItem* items, const int* id
     UpdDesc& d = bt.d[q];
     d.n = it.g.n;
     d.W = it.W;
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < kMaxNv; ++v) {
       d.vx[v] = v < it.nv ? it.vs.x[v] : nullptr;
       d.vmult[v] = v < it.nv ? it.vs.mult[v] : nullptr;
     }
@@ -1453,7 +1456,10 @@ static hipError_t update_launch_typed(hipStream_t st, const UpdateItem& it, Upda
   switch (update_nv_class(it.nv)) {
     case 1: return update_launch_flags<XT, 1>(st, it.g.C, v1, it.sym, items, idx, cnt);
     case 2: return update_launch_flags<XT, 2>(st, it.g.C, v1, it.sym, items, idx, cnt);
-    default: return update_launch_flags<XT, 4>(st, it.g.C, v1, it.sym, items, idx, cnt);
+    case 4: return update_launch_flags<XT, 4>(st, it.g.C, v1, it.sym, items, idx, cnt);
+    default:
+      if constexpr (sizeof(XT) == 2) return hipErrorInvalidValue;
+      else return update_launch_flags<XT, 8>(st, it.g.C, v1, it.sym, items, idx, cnt);
   }
 }
 

@@ -81,8 +81,8 @@ struct SpmmDesc {
 struct UpdDesc {
   int64_t n;
   void* W;
-  const void* vx[4];
-  const double* vmult[4];
+  const void* vx[kMaxNv];
+  const double* vmult[kMaxNv];
   const double* d;
   const void* v1;
   const double* v1mult;
@@ -160,7 +160,8 @@ hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* 
 hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSet& vs, int nv,
                        int voff, double* part, int* nblk_out);
 
-// w[row][col] -= sum_v d[voff+v][col] * mult_v[col] * x_v[row][col] (nv <= 4); when
+// w[row][col] -= sum_v d[voff+v][col] * mult_v[col] * x_v[row][col] (nv <= kMaxNv,
+// at most 4 with FP16 vectors); when
 // want_norm: part[0][col][block] = sum w^2, part[1][col][block] = v1mult[col] *
 // sum v1[row][col] w[row][col] and part[3][col][block] = v1mult[col] * sum
 // v1[row][col] x_{nv-1}[row][col] (the newest input vector; both zero when v1

@@ -815,7 +815,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
   }
   // the update pass hands the next step its second-newest inner product when
   // it runs as one launch and the window holds two vectors or more
-  const bool sym_out = k_ >= 2 && nv <= 4 && t + 1 < m_;
+  const bool sym_out = k_ >= 2 && nv <= (half_ ? 4 : kMaxNv) && t + 1 < m_;
   // OSA-IOP estimate runs keep g_t = v1^T v_t.  v1 is read on odd steps only,
   // which form v1^T v_{t+1} (the new vector) and v1^T v_t (the step's input):
   // after any step t every g_0 .. g_t is known (g_0 = 1), which is all a run
@@ -892,9 +892,11 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
     LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nc * kld_ * 8,
               launch_reduce(st, pp, nb, nc * kld_, dwin_ + (size_t)c0 * kld_));
   }
-  for (int c0 = 0; c0 < nv; c0 += 4) {
+  // the update in one launch for windows up to 8 vectors (4 with FP16 vectors)
+  const int upd_max = half_ ? 4 : kMaxNv;
+  for (int c0 = 0; c0 < nv; c0 += upd_max) {
     VecSet vs{};
-    const int nc = std::min(4, nv - c0);
+    const int nc = std::min(upd_max, nv - c0);
     for (int v = 0; v < nc; ++v) {
       vs.x[v] = slot_ptr(j0 + c0 + v);
       vs.mult[v] = mult_ptr(j0 + c0 + v);
