@@ -801,12 +801,13 @@ def main():
         print(f"[bench] copy calibration {copy}", file=sys.stderr, flush=True)
         ceiling = stream_ceiling(L, ctx, nb)
         # each Krylov-step kernel against the measured ceiling of its own mix:
-        # the product reads about as much as it writes (input block and matrix
-        # in, output block out), the update reads three blocks per one written
+        # the product reads two blocks per one written (the gathered input and
+        # the window vector it subtracts; the matrix is small beside them), and
+        # so does the update at window 2 (the product and the newest vector)
         fam_rate = {k: (v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None)
                     for k, v in fam.items()}
         roofline["kernels"] = {}
-        for name, mix in (("spmm", "1r1w"), ("update", "3r1w")):
+        for name, mix in (("spmm", "2r1w"), ("update", "2r1w")):
             rate = achieved if name == dom else fam_rate.get(name)
             if rate:
                 roofline["kernels"][name] = {

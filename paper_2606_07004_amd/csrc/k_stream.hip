@@ -205,6 +205,10 @@ __device__ inline void block_partials(const double (&acc)[C][VEC], double* red, 
 // read once by the row's lanes; each lane gathers C contiguous 16-byte
 // segments of the neighbour's probe vector.  For v < NF:
 // part[voff+v][col][block] = mult_v[col] * sum_rows x_v[row][col] w[row][col].
+// With sx, a window vector whose coefficient sd is already known (the
+// second newest, by the operator's symmetry) is subtracted from W first, in
+// the update's arithmetic, so the update does not read it again; the inner
+// products above then see the reduced W, as modified Gram-Schmidt would.
 // ---------------------------------------------------------------------------
 template <typename VT, typename XT, int C, int NF, bool SPLIT>
 __device__ inline void spmm_body(int64_t n, int Lr, int lgES_arg, const int* __restrict__ rp,
@@ -212,13 +216,16 @@ __device__ inline void spmm_body(int64_t n, int Lr, int lgES_arg, const int* __r
                                  const XT* __restrict__ X, XT* __restrict__ W, int ld, int ncolv,
                                  const double* __restrict__ xmult, double opscale, const void* const* fx,
                                  const double* const* fmult, int voff, double* __restrict__ part,
-                                 int bk, int nbk, int il) {
+                                 int bk, int nbk, int il, const XT* __restrict__ sx,
+                                 const double* __restrict__ smult, const double* __restrict__ sd) {
   // FP32 sums for FP32 (or BF16) values on FP32 vectors; FP64 sums whenever
   // the values or the vectors are FP64
   using A = typename std::conditional<std::is_same<VT, double>::value, double,
                                       typename Acc<XT>::type>::type;
   constexpr int VEC = V16<XT>::N;
   constexpr bool FUSED = NF > 0;
+  // the early subtraction's arithmetic: the update's (FP64, FP32 for FP16 vectors)
+  using U = typename std::conditional<std::is_same<XT, _Float16>::value, float, double>::type;
   // one fused product: its per-thread FP64 sums live in the thread's own LDS
   // slots (fewer registers, more waves in flight for the gather); two: in
   // registers, with the LDS array used for the final column sums
@@ -228,13 +235,16 @@ __device__ inline void spmm_body(int64_t n, int Lr, int lgES_arg, const int* __r
   constexpr int KE = C >= 3 ? 2 : 4;
   __shared__ double red[FUSED ? kThreads * VEC * C : 1];
   __shared__ A scs[kMaxLd];  // opscale * xmult[col], in the accumulation type
+  __shared__ U scf[kMaxLd];  // sd[col] * smult[col] (early subtraction)
   // entry split only in the SPLIT instantiations (the plain path keeps its
   // registers and code)
   const int lgES = SPLIT ? lgES_arg : 0;
   const RowMap rm = RowMap::lanes(Lr, lgES);
   const int ES = 1 << lgES;
-  for (int i = threadIdx.x; i < ld; i += kThreads)
+  for (int i = threadIdx.x; i < ld; i += kThreads) {
     scs[i] = A(opscale * (xmult ? xmult[i] : 1.0));
+    if (sx) scf[i] = U(sd[i] * (smult ? smult[i] : 1.0));
+  }
   bool okc[C];
   int colc[C];
 #pragma unroll
@@ -372,8 +382,17 @@ __device__ inline void spmm_body(int64_t n, int Lr, int lgES_arg, const int* __r
       if (okc[c] && rm.eg == 0) {
         V16<XT> out;
         const A* sce = scs + colc[c];
+        if (sx) {
+          V16<XT> xs;
+          xs.load_nt(sx + (size_t)row * ld + colc[c]);  // read once per step
+          const U* cfe = scf + colc[c];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) out.v[e] = XT(acc[c][e] * sce[e]);
+          for (int e = 0; e < VEC; ++e)
+            out.v[e] = XT(fma(-cfe[e], U(xs.v[e]), U(acc[c][e] * sce[e])));
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) out.v[e] = XT(acc[c][e] * sce[e]);
+        }
         out.store_nt(W + (size_t)row * ld + colc[c]);
         if constexpr (LDSACC) {
           // the newest window vector is X itself
@@ -422,7 +441,8 @@ __global__ __launch_bounds__(kThreads, (NF == 2 || (sizeof(VT) == 8 && sizeof(XT
   spmm_body<VT, XT, C, NF, SPLIT>(q.n, q.L, q.lgES, q.rp, q.ci, static_cast<const VT*>(q.va),
                            static_cast<const XT*>(q.X), static_cast<XT*>(q.W), q.ld, q.ncolv, q.xmult,
                            q.opscale, q.fx, q.fmult, q.voff, q.part, (int)blockIdx.x - bt.off[r],
-                           bt.off[r + 1] - bt.off[r], q.il);
+                           bt.off[r + 1] - bt.off[r], q.il, static_cast<const XT*>(q.sx), q.smult,
+                           q.sd);
 }
 
 // ---------------------------------------------------------------------------
@@ -490,14 +510,17 @@ __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int Lr, const XT* 
 // before the update) to part[2][col][block].  For a symmetric operator J and
 // W = J v_t, w_in^T w / ||w|| = (J v_t)^T v_t+1 = v_t^T (J v_t+1): the window
 // inner product of v_t with the next product, which the next step then does
-// not have to read v_t for.  The coefficients h_v * mult_v live in LDS.
+// not have to read v_t for.  The coefficients h_v * mult_v live in LDS; with
+// dhole > 0 the vectors skip coefficient row voff + dhole - 1 (a vector the
+// product already subtracted).
 // ---------------------------------------------------------------------------
 template <typename XT, int C, int NV, bool V1, bool SYM>
 __device__ inline void update_body(int64_t n, int Lr, XT* __restrict__ W, int ld, int ncolv,
                                    const void* const* vx, const double* const* vmult, int nv,
-                                   const double* __restrict__ d, int voff, int want_norm,
-                                   const XT* __restrict__ v1, const double* __restrict__ v1mult,
-                                   double* __restrict__ part, int bk, int nbk) {
+                                   const double* __restrict__ d, int voff, int dhole,
+                                   int want_norm, const XT* __restrict__ v1,
+                                   const double* __restrict__ v1mult, double* __restrict__ part,
+                                   int bk, int nbk) {
   constexpr int VEC = V16<XT>::N;
   // the vector arithmetic: FP64 for FP64 and FP32 storage; FP32 for FP16
   // storage (its 11-bit results leave FP32 rounding far below their own)
@@ -507,7 +530,8 @@ __device__ inline void update_body(int64_t n, int Lr, XT* __restrict__ W, int ld
   const RowMap rm = RowMap::lanes(Lr, 0);
   for (int i = threadIdx.x; i < NV * ld; i += kThreads) {
     const int v = i / ld, col = i - v * ld;
-    cf[i] = U(v < nv ? d[(size_t)(voff + v) * ld + col] * (vmult[v] ? vmult[v][col] : 1.0) : 0.0);
+    const int dr = voff + v + ((dhole > 0 && v >= dhole - 1) ? 1 : 0);
+    cf[i] = U(v < nv ? d[(size_t)dr * ld + col] * (vmult[v] ? vmult[v][col] : 1.0) : 0.0);
   }
   __syncthreads();
   bool okc[C];
@@ -621,7 +645,7 @@ __global__ __launch_bounds__(kThreads, (update_min_blocks<XT, C>(V1))) void k_up
   while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
   const UpdDesc& q = bt.d[r];
   update_body<XT, C, NV, V1, SYM>(q.n, q.L, static_cast<XT*>(q.W), q.ld, q.ncolv, q.vx, q.vmult,
-                                  q.nv, q.d, q.voff, q.want_norm, static_cast<const XT*>(q.v1),
+                                  q.nv, q.d, q.voff, q.dhole, q.want_norm, static_cast<const XT*>(q.v1),
                                   q.v1mult, q.part, (int)blockIdx.x - bt.off[r],
                                   bt.off[r + 1] - bt.off[r]);
 }
@@ -1230,6 +1254,7 @@ static bool spmm_item_ok(const SpmmItem& it) {
   for (int v = 0; v < it.nf; ++v)
     if (!it.fused.x[v] || it.fused.x[v] == it.W) return false;
   if (it.nf > 0 && it.fused.x[it.nf - 1] != it.X) return false;  // newest vector = the input
+  if (it.sx && (!it.sd || it.sx == it.W || it.sx == it.X)) return false;
   return true;
 }
 
@@ -1263,6 +1288,9 @@ static hipError_t spmm_launch(hipStream_t st, SpmmItem* items, const int* idx, i
     d.ncolv = it.g.ncolv;
     d.voff = it.voff;
     d.il = it.g.xil;
+    d.sx = it.sx;
+    d.smult = it.smult;
+    d.sd = it.sd;
     bt.off[q] = off;
     off += nb;
   }
@@ -1322,7 +1350,8 @@ hipError_t launch_spmm_batch(hipStream_t st, SpmmItem* items, int count) {
 
 hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* ci, const void* va,
                        int vt, const void* X, void* W, const double* xmult, double opscale,
-                       const VecSet* fused, int nf, int voff, double* part, int* nblk_out) {
+                       const VecSet* fused, int nf, int voff, double* part, int* nblk_out,
+                       const void* sx, const double* smult, const double* sd) {
   SpmmItem it{};
   it.g = g;
   it.rp = rp;
@@ -1340,6 +1369,9 @@ hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* 
   it.nf = nf;
   it.voff = voff;
   it.part = part;
+  it.sx = sx;
+  it.smult = smult;
+  it.sd = sd;
   const hipError_t e = launch_spmm_batch(st, &it, 1);
   if (nblk_out) *nblk_out = it.nblk;
   return e;
@@ -1385,7 +1417,8 @@ static bool update_item_ok(const UpdateItem& it) {
   const Geom& g = it.g;
   if (!geom_ok(g) || g.lges != 0 || g.ld > kMaxLd || !it.W || !it.d || it.nv < 0 ||
       it.nv > kMaxNv || (it.nv > 4 && g.xbytes == 2) ||
-      (it.want_norm && !it.part) || (it.v1 && !it.v1mult) || (it.sym && !it.want_norm))
+      (it.want_norm && !it.part) || (it.v1 && !it.v1mult) || (it.sym && !it.want_norm) ||
+      it.dhole < 0 || it.dhole > it.nv)
     return false;
   for (int v = 0; v < it.nv; ++v)
     if (!it.vs.x[v] || it.vs.x[v] == it.W) return false;
@@ -1422,6 +1455,7 @@ static hipError_t update_launch(hipStream_t st, UpdateItem* items, const int* id
     d.ncolv = it.g.ncolv;
     d.nv = it.nv;
     d.voff = it.voff;
+    d.dhole = it.dhole;
     d.want_norm = it.want_norm;
     bt.off[q] = off;
     off += nb;
@@ -1482,7 +1516,8 @@ hipError_t launch_update_batch(hipStream_t st, UpdateItem* items, int count) {
 
 hipError_t launch_update(hipStream_t st, const Geom& g, void* W, const VecSet& vs, int nv,
                          const double* d, int voff, int want_norm, const void* v1,
-                         const double* v1mult, bool sym, double* part, int* nblk_out) {
+                         const double* v1mult, bool sym, double* part, int* nblk_out,
+                         int dhole) {
   UpdateItem it{};
   it.g = g;
   it.W = W;
@@ -1495,6 +1530,7 @@ hipError_t launch_update(hipStream_t st, const Geom& g, void* W, const VecSet& v
   it.v1mult = v1mult;
   it.sym = sym;
   it.part = part;
+  it.dhole = dhole;
   const hipError_t e = launch_update_batch(st, &it, 1);
   if (nblk_out) *nblk_out = it.nblk;
   return e;

@@ -76,6 +76,11 @@ struct SpmmDesc {
   double* part;
   int L, lgES, ld, ncolv, voff;  // L lanes per row (see Geom)
   int il;                        // Geom::xil
+  // optional early subtraction W -= sd[col] * smult[col] * sx[row][col]
+  // (a window vector whose coefficient is known before the product)
+  const void* sx;
+  const double* smult;
+  const double* sd;
 };
 
 struct UpdDesc {
@@ -88,6 +93,7 @@ struct UpdDesc {
   const double* v1mult;
   double* part;
   int L, ld, ncolv, nv, voff, want_norm;
+  int dhole;  // 0, or 1 + a coefficient row the vectors skip
 };
 
 struct RedDesc {
@@ -150,18 +156,23 @@ __device__ inline double gsrc_at(const GSrc& g, int64_t row, int j) {
 // fused->x[nf-1] must be X itself.  The streaming launchers pick their own
 // grid (at most one resident wave of blocks) and report it in *nblk_out, the
 // block count of the partial sums they wrote (at most kMaxBlocks).
+// With sx: before the epilogue's inner products and the store, W[row][col]
+// -= sd[col] * smult[col] * sx[row][col] in the update's arithmetic (sx is a
+// window vector, sd its coefficient row, smult its multipliers).
 hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* ci,
                        const void* va, int vt, const void* X, void* W,
                        const double* xmult, double opscale, const VecSet* fused, int nf,
-                       int voff, double* part, int* nblk_out);
+                       int voff, double* part, int* nblk_out, const void* sx = nullptr,
+                       const double* smult = nullptr, const double* sd = nullptr);
 
 // part[voff+v][col][block] = mult_v[col] * sum_{rows of block} x_v[row][col] w[row][col],
 // v < nv <= 4
 hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSet& vs, int nv,
                        int voff, double* part, int* nblk_out);
 
-// w[row][col] -= sum_v d[voff+v][col] * mult_v[col] * x_v[row][col] (nv <= kMaxNv,
-// at most 4 with FP16 vectors); when
+// w[row][col] -= sum_v d[voff+r(v)][col] * mult_v[col] * x_v[row][col] (nv <= kMaxNv,
+// at most 4 with FP16 vectors; r(v) = v, or v + 1 from v = dhole - 1 on when
+// dhole > 0: the vectors skip that coefficient row); when
 // want_norm: part[0][col][block] = sum w^2, part[1][col][block] = v1mult[col] *
 // sum v1[row][col] w[row][col] and part[3][col][block] = v1mult[col] * sum
 // v1[row][col] x_{nv-1}[row][col] (the newest input vector; both zero when v1
@@ -169,7 +180,8 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
 // w[row][col] (w_in: W before the update).
 hipError_t launch_update(hipStream_t st, const Geom& g, void* W, const VecSet& vs, int nv,
                          const double* d, int voff, int want_norm, const void* v1,
-                         const double* v1mult, bool sym, double* part, int* nblk_out);
+                         const double* v1mult, bool sym, double* part, int* nblk_out,
+                         int dhole = 0);
 
 // Host-side items of the batched launchers (same meaning as the arguments of
 // launch_spmm / launch_update / launch_reduce / launch_step_finish); nblk is
@@ -189,6 +201,9 @@ struct SpmmItem {
   int voff;
   double* part;
   int nblk;
+  const void* sx;  // optional early subtraction (see launch_spmm)
+  const double* smult;
+  const double* sd;
 };
 struct UpdateItem {
   Geom g;
@@ -203,6 +218,7 @@ struct UpdateItem {
   bool sym;
   double* part;
   int nblk;
+  int dhole;  // see launch_update
 };
 struct ReduceItem {
   const double* part;

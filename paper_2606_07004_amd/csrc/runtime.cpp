@@ -805,9 +805,23 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
   // (sym_in); otherwise the product's epilogue reads v_t-1 for it.  Older
   // ones take separate passes.  Each launch writes its partial sums to its own
   // region of part_ with its own grid size and is reduced into its rows.
+  // With sym_in the product also subtracts h_t-1,t v_t-1 from J v_t before
+  // its epilogue (the coefficient is known), so the newest coefficient and
+  // the older ones are taken from the reduced vector, and the update no
+  // longer reads v_t-1: one vector pass less per step.
   const bool sym_in = sym_ready_ && nv >= 2;
   const int nf = sym_in ? 1 : std::min(2, nv);
   const int nold = nv - nf - (sym_in ? 1 : 0);  // rows [0, nold) need a dots pass
+  // the update's vectors: the window without v_t-1 when the product took it
+  // out (coefficient row nv - 2 skipped)
+  const int upd_max = half_ ? 4 : kMaxNv;
+  const bool presub = sym_in && nv - 1 <= upd_max;
+  const int nu = presub ? nv - 1 : nv;
+  const int dhole = presub ? nv - 1 : 0;
+  auto upd_vec = [&](int v) { return j0 + v + ((presub && v >= nv - 2) ? 1 : 0); };
+  const void* sx = presub ? slot_ptr(t - 1) : nullptr;
+  const double* smult = presub ? mult_ptr(t - 1) : nullptr;
+  const double* sd = presub ? dwin_ + (size_t)(nv - 2) * kld_ : nullptr;
   VecSet vf{};
   for (int v = 0; v < nf; ++v) {
     vf.x[v] = slot_ptr(j0 + nv - nf + v);
@@ -848,18 +862,22 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
       sp.nf = nf;
       sp.voff = 0;
       sp.part = part_;
+      sp.sx = sx;
+      sp.smult = smult;
+      sp.sd = sd;
       plan->red = ReduceItem{part_, 0, nf * kld_, dwin_ + (size_t)(nv - nf) * kld_};
       UpdateItem& up = plan->upd;
       up = UpdateItem{};
       up.g = kgu_;
       up.W = W;
-      for (int v = 0; v < nv; ++v) {
-        up.vs.x[v] = slot_ptr(j0 + v);
-        up.vs.mult[v] = mult_ptr(j0 + v);
+      for (int v = 0; v < nu; ++v) {
+        up.vs.x[v] = slot_ptr(upd_vec(v));
+        up.vs.mult[v] = mult_ptr(upd_vec(v));
       }
-      up.nv = nv;
+      up.nv = nu;
       up.d = dwin_;
       up.voff = 0;
+      up.dhole = dhole;
       up.want_norm = 1;
       up.v1 = v1step ? slot_ptr(0) : nullptr;
       up.v1mult = v1step ? mult_ptr(0) : nullptr;
@@ -874,9 +892,9 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
     }
   }
   int nb = 0;
-  LD_LAUNCH(LD_PROF_SPMM, spmm_bytes(kld_, xb_) + (nf - 1) * vec_bytes,
+  LD_LAUNCH(LD_PROF_SPMM, spmm_bytes(kld_, xb_) + (nf - 1 + (presub ? 1 : 0)) * vec_bytes,
             launch_spmm(st, kg_, a_->rp, a_->ci, vals, vt, slot_ptr(t), W, mult_ptr(t),
-                        opscale_ * vscale_, &vf, nf, 0, part_, &nb));
+                        opscale_ * vscale_, &vf, nf, 0, part_, &nb, sx, smult, sd));
   LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nf * kld_ * 8,
             launch_reduce(st, part_, nb, nf * kld_, dwin_ + (size_t)(nv - nf) * kld_));
   for (int c0 = 0; c0 < nold; c0 += 4) {
@@ -893,19 +911,19 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
               launch_reduce(st, pp, nb, nc * kld_, dwin_ + (size_t)c0 * kld_));
   }
   // the update in one launch for windows up to 8 vectors (4 with FP16 vectors)
-  const int upd_max = half_ ? 4 : kMaxNv;
-  for (int c0 = 0; c0 < nv; c0 += upd_max) {
+  for (int c0 = 0; c0 < nu; c0 += upd_max) {
     VecSet vs{};
-    const int nc = std::min(upd_max, nv - c0);
+    const int nc = std::min(upd_max, nu - c0);
     for (int v = 0; v < nc; ++v) {
-      vs.x[v] = slot_ptr(j0 + c0 + v);
-      vs.mult[v] = mult_ptr(j0 + c0 + v);
+      vs.x[v] = slot_ptr(upd_vec(c0 + v));
+      vs.mult[v] = mult_ptr(upd_vec(c0 + v));
     }
-    const bool last = c0 + nc >= nv;
+    const bool last = c0 + nc >= nu;
     LD_LAUNCH(LD_PROF_UPDATE, (double)(nc + 2 + ((last && v1step) ? 1 : 0)) * vec_bytes,
               launch_update(st, kgu_, W, vs, nc, dwin_, c0, last ? 1 : 0,
                             (last && v1step) ? slot_ptr(0) : nullptr,
-                            (last && v1step) ? mult_ptr(0) : nullptr, last && sym_out, part_, &nb));
+                            (last && v1step) ? mult_ptr(0) : nullptr, last && sym_out, part_, &nb,
+                            dhole));
   }
   sym_ready_ = sym_out;
   LD_LAUNCH(LD_PROF_SMALL, (double)nb * 2 * kld_ * 8,
