@@ -77,7 +77,28 @@ def parse():
     ap.add_argument("--tune-reps", type=int, default=10,
                     help="launches per candidate of the product/update geometry autotuner "
                          "(0 keeps the default geometry)")
+    ap.add_argument("--geometry", type=str, default=None,
+                    help="pin the headline geometry instead of autotuning it: "
+                         "'L,C,E,I/L,C' = product lanes per row, chunks per lane, entry "
+                         "split, interleave / update lanes per row, chunks per lane")
     return ap.parse_args()
+
+
+def parse_geometry(spec):
+    prod, upd = spec.split("/")
+    pl, pc, pe, pi = (int(x) for x in prod.split(","))
+    ul, uc = (int(x) for x in upd.split(","))
+    return {"spmm_lanes": pl, "spmm_chunks": pc, "spmm_entry_split": pe, "spmm_interleave": pi,
+            "update_lanes": ul, "update_chunks": uc, "pinned": True}
+
+
+def geometry_key(tune):
+    """The geometry a PMC record was taken with: 'default', or the product's
+    'L,C,E,I' (lanes, chunks, entry split, interleave)."""
+    if not tune:
+        return "default"
+    return (f"{tune['spmm_lanes']},{tune['spmm_chunks']},{tune['spmm_entry_split']},"
+            f"{tune['spmm_interleave']}")
 
 
 def pmc_record(key):
@@ -136,10 +157,18 @@ def pmc_traffic(args, family, tune):
         chunks = rec.get("default_chunks", {}).get(family)
         split = False
     kname = pattern.replace("{C}", str(chunks)).replace("{S}", "true" if split else "false")
-    k = rec.get("kernels", {}).get(kname)
+    # the product's traffic depends on its whole geometry (lanes, chunks,
+    # split, chunk mapping): only counters taken with this run's geometry
+    # count; the update streams every block once whatever its lanes
+    geo = geometry_key(tune)
+    tables = rec.get("geometries", {})
+    if family == "spmm":
+        k = tables.get(geo, {}).get(kname)
+    else:
+        k = next((t[kname] for t in tables.values() if kname in t), None)
     if k is None:
         return None
-    return {"bytes_per_launch": k["scaled_bytes"], "kernel": kname,
+    return {"bytes_per_launch": k["scaled_bytes"], "kernel": kname, "geometry": geo,
             "fetch_scale": rec["fetch_scale"], "write_scale": rec["write_scale"],
             "summary": rec.get("summary")}
 
@@ -707,7 +736,12 @@ def main():
         sys.exit(2)
 
     tune = None
-    if args.tune_reps > 0:
+    if args.geometry:
+        tune = parse_geometry(args.geometry)
+        L.ld_tune_set(h, p, tune["spmm_lanes"], tune["spmm_chunks"], tune["update_lanes"],
+                      tune["update_chunks"], spmm_entry_split=tune["spmm_entry_split"],
+                      spmm_interleave=tune["spmm_interleave"])
+    elif args.tune_reps > 0:
         t_tune = time.perf_counter()
         tune = L.ld_autotune(h, p, args.tune_reps).as_dict()
         tune["wall_s"] = time.perf_counter() - t_tune

@@ -1300,7 +1300,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
   // X (the product's input and newest window vector), V (an older window
   // vector), W (product / update in place), column multipliers, zero
   // coefficients and the partial sums
-  const size_t small = align_up((size_t)ldmax * 8) + align_up((size_t)4 * ldmax * 8);
+  const size_t small = align_up((size_t)ldmax * 8) + align_up((size_t)kMaxNv * ldmax * 8);
   const size_t partb = align_up((size_t)kMaxBlocks * 4 * ldmax * 8);
   DeviceBuffer buf;
   LD_HIP(buf.ensure(3 * vec + small + partb));
@@ -1313,12 +1313,15 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
   double* part = reinterpret_cast<double*>(base + 3 * vec + small);
   const std::vector<double> ones((size_t)ldmax, 1.0);
   LD_HIP(hipMemcpyAsync(mult, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, st));
-  LD_HIP(hipMemsetAsync(dcoef, 0, (size_t)4 * ldmax * 8, st));
+  LD_HIP(hipMemsetAsync(dcoef, 0, (size_t)kMaxNv * ldmax * 8, st));
   const void* vals = (mixed_ && a_->vlo) ? a_->vlo : a_->v64;
-  // the window of a steady-state step: min(k, 4) vectors in one update pass,
-  // the second-newest inner product formed there when k >= 2
-  const int nv = std::max(1, std::min(k_, 4));
+  // the launches of a steady-state step: with k >= 2 the product subtracts
+  // the second-newest vector (V here) and the update takes the rest of the
+  // window (up to 8 vectors, 4 with FP16 vectors) and forms the next
+  // second-newest inner product
+  const int kw = std::max(1, std::min(k_, half_ ? 4 : kMaxNv));
   const bool sym = k_ >= 2;
+  const int nv = sym ? kw - 1 : kw;
   EventPair ev;
   LD_HIP(hipEventCreate(&ev.a));
   LD_HIP(hipEventCreate(&ev.b));
@@ -1345,10 +1348,12 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
         float ms = 0.f;
         auto product = [&]() {
           return launch_spmm(st, g, a_->rp, a_->ci, vals, vt, X, W, mult, opscale_ * vscale_, &vf, 1, 0,
-                             part, &nb);
+                             part, &nb, sym ? V : nullptr, sym ? mult : nullptr,
+                             sym ? dcoef : nullptr);
         };
         auto update = [&]() {
-          return launch_update(st, g, W, vu, nv, dcoef, 0, 1, nullptr, nullptr, sym, part, &nb);
+          return launch_update(st, g, W, vu, nv, dcoef, 0, 1, nullptr, nullptr, sym, part, &nb,
+                               sym ? nv : 0);
         };
         LD_HIP(product());  // warm-up
         LD_HIP(hipEventRecord(ev.a, st));
