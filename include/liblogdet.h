@@ -282,9 +282,12 @@ ld_status ld_request_bytes(ld_matrix* a, const ld_params* p, uint64_t* bytes);
  * that is not a power of two, for the probe-block shapes and
  * precision that `p` implies (the estimate block and, for OSA-IOP and So-SLQ,
  * the sketch-run block), each kernel `reps` times per round over three
- * rounds, keeping the fastest per kernel.  The choice is stored in the
- * matrix and used by every later estimate and served request whose shapes
- * match; results then differ from the untuned ones only by the summation
+ * rounds, keeping the fastest per kernel.  Both are timed as a steady-state
+ * step of `p` runs them: with iop_window >= 2 the product also subtracts the
+ * second-newest window vector and the update takes the rest of the window.
+ * The choice is stored in the matrix and used by every later estimate and
+ * served request whose shapes match (the update's per class of window: 1, 2,
+ * up to 4 or up to 8 vectors after that subtraction); results then differ from the untuned ones only by the summation
  * order of the partial sums (FP64 rounding), and stay bitwise reproducible
  * for a fixed choice.  Blocking; call it before submitting requests on this
  * matrix (a request takes its geometry when it is admitted).  reps = 0 drops
@@ -309,7 +312,7 @@ ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_re
  * per row, spmm_chunks chunks per lane, its entries split over
  * spmm_entry_split lane groups and its row chunks interleaved over the XCDs
  * (spmm_interleave 1) or banded per XCD (0), the update likewise (no split,
- * interleaved).  Any (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8},
+ * interleaved; stored for the window class of `p`).  Any (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8},
  * E <= L, C <= 2 when E > 1, and (L / E) * C chunks covering the block is
  * accepted, where L is a power of two when E > 1; anything else is
  * LD_E_INVALID_ARG and stores nothing. */

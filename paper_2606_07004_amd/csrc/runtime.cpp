@@ -379,16 +379,30 @@ ld_status Run::validate() {
   gS_ = make_geom(n_, lds_, 8);
   g1_ = make_geom(n_, ld1_, xb_);
   gBp_ = krylov_geom(ldB_, 0);
-  gBu_ = krylov_geom(ldB_, 1);
+  gBu_ = krylov_geom(ldB_, upd_which());
   g1p_ = krylov_geom(ld1_, 0);
-  g1u_ = krylov_geom(ld1_, 1);
+  g1u_ = krylov_geom(ld1_, upd_which());
   return LD_OK;
 }
 
 // Key of a tuned geometry: block width, element bytes, matrix value type of
-// the product, kernel (0 product, 1 update).
+// the product, kernel (0 product; 1 | class << 4 the update of a window class).
 static uint64_t tune_key(int ld, int xbytes, int vt, int which) {
   return (uint64_t)ld | ((uint64_t)xbytes << 16) | ((uint64_t)vt << 24) | ((uint64_t)which << 32);
+}
+
+// The update's register footprint grows with the vectors it subtracts, so its
+// tuned geometry is kept per class of the steady-state window: the window
+// (up to 8 vectors per launch, 4 with FP16 vectors) less the second-newest
+// vector, which the product subtracts when the window holds two or more.
+int Run::upd_steady_nv() const {
+  const int kw = std::max(1, std::min(k_, half_ ? 4 : kMaxNv));
+  return k_ >= 2 ? kw - 1 : kw;
+}
+int Run::upd_which() const {
+  const int nv = upd_steady_nv();
+  const int cls = nv <= 1 ? 1 : (nv == 2 ? 2 : (nv <= 4 ? 4 : 8));
+  return 1 | (cls << 4);
 }
 
 Geom Run::krylov_geom(int ld, int which) const {
@@ -1288,8 +1302,10 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
   if (p_.method != LD_METHOD_OSLQ && s_ > 0 && ld1_ != ldB_) widths.push_back(ld1_);
   if (reps == 0) {
     std::lock_guard<std::mutex> lk(a_->tune_mu);
-    for (int ld : widths)
-      for (int which = 0; which < 2; ++which) a_->tune.erase(tune_key(ld, xb_, vt, which));
+    for (int ld : widths) {
+      a_->tune.erase(tune_key(ld, xb_, vt, 0));
+      a_->tune.erase(tune_key(ld, xb_, vt, upd_which()));
+    }
     a_->tune_ver.fetch_add(1);
     if (out) *out = ld_tune_result{};
     return LD_OK;
@@ -1317,11 +1333,9 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
   const void* vals = (mixed_ && a_->vlo) ? a_->vlo : a_->v64;
   // the launches of a steady-state step: with k >= 2 the product subtracts
   // the second-newest vector (V here) and the update takes the rest of the
-  // window (up to 8 vectors, 4 with FP16 vectors) and forms the next
-  // second-newest inner product
-  const int kw = std::max(1, std::min(k_, half_ ? 4 : kMaxNv));
+  // window and forms the next second-newest inner product
   const bool sym = k_ >= 2;
-  const int nv = sym ? kw - 1 : kw;
+  const int nv = upd_steady_nv();
   EventPair ev;
   LD_HIP(hipEventCreate(&ev.a));
   LD_HIP(hipEventCreate(&ev.b));
@@ -1384,7 +1398,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     {
       std::lock_guard<std::mutex> lk(a_->tune_mu);
       a_->tune[tune_key(ld, xb_, vt, 0)] = cand[bp];
-      a_->tune[tune_key(ld, xb_, vt, 1)] = cand[bu];
+      a_->tune[tune_key(ld, xb_, vt, upd_which())] = cand[bu];
       a_->tune_ver.fetch_add(1);
     }
     if (wi == 0 && out) {
@@ -1422,7 +1436,7 @@ ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int upd
   std::lock_guard<std::mutex> lk(a_->tune_mu);
   a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes | (e << 8) | (spmm_interleave << 12),
                                          spmm_chunks};
-  a_->tune[tune_key(ldB_, xb_, vt, 1)] = {update_lanes, update_chunks};
+  a_->tune[tune_key(ldB_, xb_, vt, upd_which())] = {update_lanes, update_chunks};
   a_->tune_ver.fetch_add(1);
   return LD_OK;
 }

@@ -224,6 +224,8 @@ class Run {
   // product (which = 0) or update (which = 1) geometry of a Krylov block of
   // width ld: the matrix's tuned choice when it holds one, else the default
   Geom krylov_geom(int ld, int which) const;
+  int upd_steady_nv() const;  // update vectors of a steady-state step
+  int upd_which() const;      // tuning key of the update (window class)
   double spmm_bytes(int ld, int xbytes) const;
 
   ld_matrix* a_;
