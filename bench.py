@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--tune-reps", type=int, default=10,
                     help="launches per candidate of the product/update geometry autotuner "
                          "(0 keeps the default geometry)")
+    ap.add_argument("--config-geometry", action="append", default=[],
+                    help="NAME=L,C,E,I/L,C: pin the FP32-vector geometry of a full-size "
+                         "configuration leg instead of autotuning it (repeatable)")
     ap.add_argument("--geometry", type=str, default=None,
                     help="pin the headline geometry instead of autotuning it: "
                          "'L,C,E,I/L,C' = product lanes per row, chunks per lane, entry "
@@ -347,6 +350,7 @@ def configs_bench(L, W, args):
         "wendland5e5_oslq_k2": (lambda: W.wendland(500_000, 48.0, 1e-2, seed=0), 64, 21, 40, 2,
                                 1e-2),
     }
+    pinned = dict(g.split("=", 1) for g in args.config_geometry)
     with L.Context(0) as ctx:
         for name, (build, npr, s, m, k, lo) in cases.items():
             a = build()
@@ -356,10 +360,16 @@ def configs_bench(L, W, args):
             del a
             for prec in ("mixed", "fp64", "half", "auto"):
                 p = L.make_params(npr, s, m, k, 0, precision=PRECISIONS[prec](L))
-                interleaved = 0
+                tune = None
                 try:
-                    if args.tune_reps > 0 and prec != "auto":
-                        interleaved = L.ld_autotune(h, p, args.tune_reps).spmm_interleave
+                    if prec == "mixed" and name in pinned:
+                        tune = parse_geometry(pinned[name])
+                        L.ld_tune_set(h, p, tune["spmm_lanes"], tune["spmm_chunks"],
+                                      tune["update_lanes"], tune["update_chunks"],
+                                      spmm_entry_split=tune["spmm_entry_split"],
+                                      spmm_interleave=tune["spmm_interleave"])
+                    elif args.tune_reps > 0 and prec != "auto":
+                        tune = L.ld_autotune(h, p, args.tune_reps).as_dict()
                     r = L.ld_estimate_ex(h, p)
                 except L.LdError as e:
                     # FP16 vectors are refused outside the range where they
@@ -387,16 +397,21 @@ def configs_bench(L, W, args):
                             "algorithmic_GB/s": by / (ms * 1e-3) / 1e9 if ms > 0 else None,
                             "fabric_GB": None, "fabric_GB/s": None}
                     pr = pmc_record(f"config {name} mixed")
-                    # the counters describe the product's chunk mapping they
-                    # were taken with (the default, banded, without tuning)
-                    prod["interleaved"] = interleaved
-                    if pr and pr.get("product_interleave", 0) == interleaved:
-                        ks = [v for kname, v in pr["kernels"].items() if "k_spmm<" in kname]
-                        if ks:
-                            fb = max(ks, key=lambda v: v["dispatches"])["scaled_bytes"]
-                            prod["fabric_GB"] = fb / 1e9
-                            prod["fabric_GB/s"] = fb / (ml * 1e-3) / 1e9
-                            prod["pmc_summary"] = pr.get("summary")
+                    # the counters describe the product geometry they were
+                    # taken with: reported only for the same geometry
+                    geo = geometry_key(tune)
+                    prod["geometry"] = geo
+                    prod["update_geometry"] = (f"{tune['update_lanes']},{tune['update_chunks']}"
+                                               if tune else "default")
+                    prod["interleaved"] = tune["spmm_interleave"] if tune else 0
+                    kname = f"ld::k_spmm<float, float, {tune['spmm_chunks'] if tune else 0}, "
+                    ks = [v for kn, v in (pr or {}).get("geometries", {}).get(geo, {}).items()
+                          if kn.startswith(kname)]
+                    if ks:
+                        fb = max(ks, key=lambda v: v["dispatches"])["scaled_bytes"]
+                        prod["fabric_GB"] = fb / 1e9
+                        prod["fabric_GB/s"] = fb / (ml * 1e-3) / 1e9
+                        prod["pmc_summary"] = pr.get("summary")
                     rec[prec]["product"] = prod
             ctx.release(h)
             if name.startswith("wendland"):
