@@ -78,30 +78,44 @@ def parse():
                     help="launches per candidate of the product/update geometry autotuner "
                          "(0 keeps the default geometry)")
     ap.add_argument("--config-geometry", action="append", default=[],
-                    help="NAME=L,C,E,I/L,C: pin the FP32-vector geometry of a full-size "
+                    help="NAME=L,C,E,I[,S]/L,C: pin the FP32-vector geometry of a full-size "
                          "configuration leg instead of autotuning it (repeatable)")
     ap.add_argument("--geometry", type=str, default=None,
                     help="pin the headline geometry instead of autotuning it: "
-                         "'L,C,E,I/L,C' = product lanes per row, chunks per lane, entry "
-                         "split, interleave / update lanes per row, chunks per lane")
+                         "'L,C,E,I[,S]/L,C' = product lanes per row, chunks per lane, entry "
+                         "split, interleave[, row-tile stride] / update lanes per row, "
+                         "chunks per lane")
     return ap.parse_args()
 
 
 def parse_geometry(spec):
     prod, upd = spec.split("/")
-    pl, pc, pe, pi = (int(x) for x in prod.split(","))
+    pv = [int(x) for x in prod.split(",")]
+    pl, pc, pe, pi = pv[:4]
+    ps = pv[4] if len(pv) > 4 else 0
     ul, uc = (int(x) for x in upd.split(","))
     return {"spmm_lanes": pl, "spmm_chunks": pc, "spmm_entry_split": pe, "spmm_interleave": pi,
-            "update_lanes": ul, "update_chunks": uc, "pinned": True}
+            "spmm_row_stride": ps, "update_lanes": ul, "update_chunks": uc, "pinned": True}
+
+
+def set_geometry(L, h, p, tune):
+    L.ld_tune_set(h, p, tune["spmm_lanes"], tune["spmm_chunks"], tune["update_lanes"],
+                  tune["update_chunks"], spmm_entry_split=tune["spmm_entry_split"],
+                  spmm_interleave=tune["spmm_interleave"],
+                  spmm_row_stride=tune.get("spmm_row_stride", 0))
 
 
 def geometry_key(tune):
     """The geometry a PMC record was taken with: 'default', or the product's
-    'L,C,E,I' (lanes, chunks, entry split, interleave)."""
+    'L,C,E,I' (lanes, chunks, entry split, interleave), with ',S' when its
+    rows are taken in tiles of stride S."""
     if not tune:
         return "default"
-    return (f"{tune['spmm_lanes']},{tune['spmm_chunks']},{tune['spmm_entry_split']},"
-            f"{tune['spmm_interleave']}")
+    key = (f"{tune['spmm_lanes']},{tune['spmm_chunks']},{tune['spmm_entry_split']},"
+           f"{tune['spmm_interleave']}")
+    if tune.get("spmm_row_stride", 0):
+        key += f",{tune['spmm_row_stride']}"
+    return key
 
 
 def pmc_record(key):
@@ -364,10 +378,7 @@ def configs_bench(L, W, args):
                 try:
                     if prec == "mixed" and name in pinned:
                         tune = parse_geometry(pinned[name])
-                        L.ld_tune_set(h, p, tune["spmm_lanes"], tune["spmm_chunks"],
-                                      tune["update_lanes"], tune["update_chunks"],
-                                      spmm_entry_split=tune["spmm_entry_split"],
-                                      spmm_interleave=tune["spmm_interleave"])
+                        set_geometry(L, h, p, tune)
                     elif args.tune_reps > 0 and prec != "auto":
                         tune = L.ld_autotune(h, p, args.tune_reps).as_dict()
                     r = L.ld_estimate_ex(h, p)
@@ -753,9 +764,7 @@ def main():
     tune = None
     if args.geometry:
         tune = parse_geometry(args.geometry)
-        L.ld_tune_set(h, p, tune["spmm_lanes"], tune["spmm_chunks"], tune["update_lanes"],
-                      tune["update_chunks"], spmm_entry_split=tune["spmm_entry_split"],
-                      spmm_interleave=tune["spmm_interleave"])
+        set_geometry(L, h, p, tune)
     elif args.tune_reps > 0:
         t_tune = time.perf_counter()
         tune = L.ld_autotune(h, p, args.tune_reps).as_dict()
@@ -915,6 +924,7 @@ def main():
                    "geometry": ({"product": [tune["spmm_lanes"], tune["spmm_chunks"]],
                                  "product_entry_split": tune["spmm_entry_split"],
                                  "product_interleaved": tune["spmm_interleave"],
+                                 "product_row_stride": tune.get("spmm_row_stride", 0),
                                  "update": [tune["update_lanes"], tune["update_chunks"]]}
                                 if tune else "default")},
         "autotune": tune,

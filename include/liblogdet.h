@@ -277,6 +277,10 @@ ld_status ld_request_bytes(ld_matrix* a, const ld_params* p, uint64_t* bytes);
  * lane groups (L a power of two, L / E column lanes each, their sums added
  * at the row's end), which shortens the per-lane chain of dependent gathers
  * on long rows (tried when rows hold 16 entries or more on average).
+ * The product's rows may also be taken in tiles (ld_tune_set's
+ * spmm_row_stride), which ld_autotune tries on every power-of-two L with the
+ * strides of the matrix's most frequent column offsets (at most two, each in
+ * a quarter of the sampled rows or more).
  * ld_autotune times every such (L, C, E) with L a power of two and at most
  * half a row of idle chunks on this matrix, and L = ceil(chunks / C) where
  * that is not a power of two, for the probe-block shapes and
@@ -305,20 +309,28 @@ typedef struct {
   int32_t spmm_interleave;   /* 1: the product's row chunks interleave over the
                               * XCDs; 0: a contiguous band of chunks per XCD,
                               * which keeps a row's neighbours in one L2    */
+  int32_t spmm_row_stride;   /* 0, or S: the product's block takes its rows as
+                              * 4 runs S rows apart (row tiles)             */
 } ld_tune_result;
 ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_result* out);
 /* Stores a given geometry for the estimate block of `p` on this matrix (a
  * choice found earlier, or one to test): the product with spmm_lanes lanes
  * per row, spmm_chunks chunks per lane, its entries split over
  * spmm_entry_split lane groups and its row chunks interleaved over the XCDs
- * (spmm_interleave 1) or banded per XCD (0), the update likewise (no split,
- * interleaved; stored for the window class of `p`).  Any (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8},
+ * (spmm_interleave 1) or banded per XCD (0), and its rows taken in tiles
+ * (spmm_row_stride S > 0: each 256-thread block's four waves take runs of
+ * 64 / L consecutive rows S rows apart, so on a grid operator whose line
+ * stride is S the +-S neighbours of one wave's rows are the rows the other
+ * waves of the block gather at the same time; S a multiple of 64 / L, L a
+ * power of two, S <= 32767; rows past the last whole tile of 4 S rows keep
+ * the plain order), the update likewise (no split, interleaved; stored for
+ * the window class of `p`).  Any (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8},
  * E <= L, C <= 2 when E > 1, and (L / E) * C chunks covering the block is
  * accepted, where L is a power of two when E > 1; anything else is
  * LD_E_INVALID_ARG and stores nothing. */
 ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
                       int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks,
-                      int32_t spmm_interleave);
+                      int32_t spmm_interleave, int32_t spmm_row_stride);
 
 /* Serving with continuous batching: queue a request and return at once with
  * a ticket.  Requests are admitted as resident slots and HBM budget free up;

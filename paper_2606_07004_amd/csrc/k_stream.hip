@@ -216,7 +216,7 @@ __device__ inline void spmm_body(int64_t n, int Lr, int lgES_arg, const int* __r
                                  const XT* __restrict__ X, XT* __restrict__ W, int ld, int ncolv,
                                  const double* __restrict__ xmult, double opscale, const void* const* fx,
                                  const double* const* fmult, int voff, double* __restrict__ part,
-                                 int bk, int nbk, int il, const XT* __restrict__ sx,
+                                 int bk, int nbk, int il, int ts, const XT* __restrict__ sx,
                                  const double* __restrict__ smult, const double* __restrict__ sd) {
   // FP32 sums for FP32 (or BF16) values on FP32 vectors; FP64 sums whenever
   // the values or the vectors are FP64
@@ -268,11 +268,22 @@ __device__ inline void spmm_body(int64_t n, int Lr, int lgES_arg, const int* __r
       for (int e = 0; e < VEC; ++e) dacc[v][c][e] = 0.0;
   const int nn = (int)n;  // n < 2^31
   const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
+  // row tiles (ts > 0): a tile is 4 rows of ts rows, the block's wave w
+  // taking rows w ts + q rpw .. + rpw - 1 of tile t for chunk t segs + q;
+  // chunks past the last whole tile keep consecutive rows
+  const int rpw = rm.rpi >> 2;  // rows per wave (L a power of two)
+  const int segs = ts > 0 ? ts / rpw : 1;
+  const int tchunks = ts > 0 ? (nn / (4 * ts)) * segs : 0;
+  const int wv = (int)threadIdx.x >> 6, rw = rm.rg - wv * rpw;
   for (int j = 0; j * nbk < nchunk; ++j) {
     // per-XCD bands keep a row's neighbours in one L2; interleaving streams
     // better on wide rows (a tuning choice)
     const int ch = il ? j * nbk + bk : chunk_of(j, bk, nbk);
-    const int row = ch * rm.rpi + rm.rg;
+    int row = ch * rm.rpi + rm.rg;
+    if (ch < tchunks) {
+      const int t = ch / segs, q = ch - t * segs;
+      row = (t * 4 + wv) * ts + q * rpw + rw;
+    }
     if (!rm.on || ch >= nchunk || row >= nn) continue;
     A acc[C][VEC];
     V16<XT> xd[FUSED ? C : 1];
@@ -441,7 +452,7 @@ __global__ __launch_bounds__(kThreads, (NF == 2 || (sizeof(VT) == 8 && sizeof(XT
   spmm_body<VT, XT, C, NF, SPLIT>(q.n, q.L, q.lgES, q.rp, q.ci, static_cast<const VT*>(q.va),
                            static_cast<const XT*>(q.X), static_cast<XT*>(q.W), q.ld, q.ncolv, q.xmult,
                            q.opscale, q.fx, q.fmult, q.voff, q.part, (int)blockIdx.x - bt.off[r],
-                           bt.off[r + 1] - bt.off[r], q.il, static_cast<const XT*>(q.sx), q.smult,
+                           bt.off[r + 1] - bt.off[r], q.il, q.ts, static_cast<const XT*>(q.sx), q.smult,
                            q.sd);
 }
 
@@ -999,7 +1010,9 @@ static bool geom_ok(const Geom& g) {
          g.vec * g.ncolv == g.ld && g.L >= 1 && g.L <= 64 && lanes && g.C >= 1 &&
          g.C <= kMaxC && g.lges >= 0 && g.lges <= g.lgL && g.lges <= 3 &&
          (g.lges == 0 || g.C <= 2) &&
-         (g.L >> g.lges) * g.C >= g.ncolv && g.nblk >= 1 && (int64_t)g.nblk * g.rpb >= g.n;
+         (g.L >> g.lges) * g.C >= g.ncolv && g.nblk >= 1 && (int64_t)g.nblk * g.rpb >= g.n &&
+         g.ts >= 0 && g.ts <= kMaxRowStride &&
+         (g.ts == 0 || ((1 << g.lgL) == g.L && g.ts % (64 / g.L) == 0));
 }
 
 // Resident 256-thread blocks of a kernel on the whole device (cached).
@@ -1288,6 +1301,7 @@ static hipError_t spmm_launch(hipStream_t st, SpmmItem* items, const int* idx, i
     d.ncolv = it.g.ncolv;
     d.voff = it.voff;
     d.il = it.g.xil;
+    d.ts = it.g.ts;
     d.sx = it.sx;
     d.smult = it.smult;
     d.sd = it.sd;
@@ -1381,7 +1395,8 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
                        int voff, double* part, int* nblk_out) {
   int dummy = 0;
   if (!nblk_out) nblk_out = &dummy;
-  if (!geom_ok(g) || g.lges != 0 || !W || !part || nv < 1 || nv > kDotsPerLaunch || voff < 0)
+  if (!geom_ok(g) || g.lges != 0 || g.ts != 0 || !W || !part || nv < 1 || nv > kDotsPerLaunch ||
+      voff < 0)
     return hipErrorInvalidValue;
   for (int v = 0; v < nv; ++v)
     if (!vs.x[v]) return hipErrorInvalidValue;
@@ -1415,7 +1430,7 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
 
 static bool update_item_ok(const UpdateItem& it) {
   const Geom& g = it.g;
-  if (!geom_ok(g) || g.lges != 0 || g.ld > kMaxLd || !it.W || !it.d || it.nv < 0 ||
+  if (!geom_ok(g) || g.lges != 0 || g.ts != 0 || g.ld > kMaxLd || !it.W || !it.d || it.nv < 0 ||
       it.nv > kMaxNv || (it.nv > 4 && g.xbytes == 2) ||
       (it.want_norm && !it.part) || (it.v1 && !it.v1mult) || (it.sym && !it.want_norm) ||
       it.dhole < 0 || it.dhole > it.nv)

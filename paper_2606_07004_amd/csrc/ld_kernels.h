@@ -16,6 +16,7 @@ enum ValueType : int { VT_F64 = 0, VT_F32 = 1, VT_BF16 = 2 };
 constexpr int kMaxBlocks = 2048;  // 256 CUs x 8 resident 256-thread blocks
 constexpr int kMaxC = 4;          // 16-byte chunks per lane
 constexpr int kMaxLd = 256;       // probe-block row length (columns) of the Krylov kernels
+constexpr int kMaxRowStride = 32767;  // Geom::ts
 constexpr int kSoSlqMaxSketch = 48;  // So-SLQ sketch width (Jacobi eigen-solve in LDS)
 
 // Row partition of an [n][ld] probe block.  The streaming kernels sweep
@@ -40,6 +41,10 @@ struct Geom {
   int lges = 0;    // product only: log2 of the entry split (L / 2^lges column lanes)
   int xil = 0;     // product only: 1 = consecutive row chunks on consecutive blocks
                    // (XCDs interleaved), 0 = a contiguous band of chunks per XCD
+  int ts = 0;      // product only, L a power of two: 0, or S = a multiple of the rows
+                   // per wave (64 / L): the block's 4 waves take rows S apart (one
+                   // tile of 4 rows of S rows), so a stencil's +-S neighbours of
+                   // one wave's rows are the rows its sibling waves gather
 };
 Geom make_geom(int64_t n, int ld, int xbytes);
 // The same with an explicit lanes-per-row L and chunks per lane C (an
@@ -76,6 +81,7 @@ struct SpmmDesc {
   double* part;
   int L, lgES, ld, ncolv, voff;  // L lanes per row (see Geom)
   int il;                        // Geom::xil
+  int ts;                        // Geom::ts
   // optional early subtraction W -= sd[col] * smult[col] * sx[row][col]
   // (a window vector whose coefficient is known before the product)
   const void* sx;

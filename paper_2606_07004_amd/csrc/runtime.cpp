@@ -414,6 +414,7 @@ Geom Run::krylov_geom(int ld, int which) const {
       Geom g = make_geom_lc(n_, ld, xb_, it->second.first & 0xff, it->second.second);
       g.lges = (it->second.first >> 8) & 0xf;  // entry split of the product
       g.xil = (it->second.first >> 12) & 1;    // chunk mapping of the product
+      g.ts = (it->second.first >> 16) & 0x7fff;  // row tiles of the product
       if (geom_usable(g)) return g;
     }
   }
@@ -1251,9 +1252,12 @@ ld_status Run::collect(hipStream_t st, ld_result* out, const ld_detail* detail, 
 // (L 2^e) | (e << 8).  Then the pairs L = ceil(chunks / C) where that is
 // not a power of two (floor(64 / L) rows per wave).  With interleave, every
 // candidate again with the product's chunks interleaved over the XCDs
-// (bit 12), timed for the product only.
+// (bit 12), and every power-of-two one with its rows in tiles of each given
+// stride that is a multiple of its rows per wave (bits 16..30), both timed
+// for the product only.
 static std::vector<std::pair<int, int>> tune_candidates(int64_t n, int ld, int xbytes,
-                                                        bool split, bool interleave) {
+                                                        bool split, bool interleave,
+                                                        const std::vector<int>& strides) {
   const Geom d = make_geom(n, ld, xbytes);
   std::vector<std::pair<int, int>> out{{d.L, d.C}};
   for (int L = 1; L <= 64; L <<= 1)
@@ -1276,6 +1280,17 @@ static std::vector<std::pair<int, int>> tune_candidates(int64_t n, int ld, int x
     const size_t base = out.size();
     for (size_t i = 0; i < base; ++i) out.push_back({out[i].first | (1 << 12), out[i].second});
   }
+  const size_t base = out.size();
+  for (size_t i = 0; i < base; ++i) {
+    const int L = out[i].first & 0xff;
+    if (L & (L - 1)) continue;
+    for (int S : strides) {
+      Geom g = make_geom_lc(n, ld, xbytes, L, out[i].second);
+      g.lges = (out[i].first >> 8) & 0xf;
+      g.ts = S;
+      if (S % (64 / L) == 0 && geom_usable(g)) out.push_back({out[i].first | (S << 16), out[i].second});
+    }
+  }
   return out;
 }
 
@@ -1283,7 +1298,46 @@ static Geom candidate_geom(int64_t n, int ld, int xbytes, const std::pair<int, i
   Geom g = make_geom_lc(n, ld, xbytes, c.first & 0xff, c.second);
   g.lges = (c.first >> 8) & 0xf;
   g.xil = (c.first >> 12) & 1;
+  g.ts = (c.first >> 16) & 0x7fff;
   return g;
+}
+
+// Row strides worth a row-tile trial for the product: the positive column
+// offsets (col - row) that occur in at least a quarter of the rows of two
+// sampled windows (the start and the middle of the matrix), most frequent
+// first, at most two.  A stencil on a grid gives its line and plane strides.
+std::vector<int> Run::stride_candidates(hipStream_t st) const {
+  constexpr int64_t kWin = 4096;
+  std::map<int64_t, int64_t> count;
+  int64_t rows = 0;
+  for (int64_t r0 : {int64_t(0), n_ / 2}) {
+    const int64_t r1 = std::min(n_, r0 + kWin);
+    if (r1 <= r0 || (r0 > 0 && r0 < kWin)) continue;
+    std::vector<int> rp((size_t)(r1 - r0 + 1));
+    if (hipMemcpyAsync(rp.data(), a_->rp + r0, rp.size() * sizeof(int), hipMemcpyDeviceToHost,
+                       st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+      return {};
+    std::vector<int> ci((size_t)(rp.back() - rp.front()));
+    if (!ci.empty() &&
+        (hipMemcpyAsync(ci.data(), a_->ci + rp.front(), ci.size() * sizeof(int),
+                        hipMemcpyDeviceToHost, st) != hipSuccess ||
+         hipStreamSynchronize(st) != hipSuccess))
+      return {};
+    for (int64_t i = r0; i < r1; ++i) {
+      for (int k = rp[i - r0] - rp.front(); k < rp[i - r0 + 1] - rp.front(); ++k) {
+        const int64_t d = (int64_t)ci[k] - i;
+        if (d >= 2 && d <= kMaxRowStride) ++count[d];
+      }
+      ++rows;
+    }
+  }
+  std::vector<std::pair<int64_t, int>> byc;
+  for (const auto& kv : count)
+    if (4 * kv.second >= rows) byc.push_back({-kv.second, (int)kv.first});
+  std::sort(byc.begin(), byc.end());
+  std::vector<int> out;
+  for (size_t i = 0; i < byc.size() && i < 2; ++i) out.push_back(byc[i].second);
+  return out;
 }
 
 namespace {
@@ -1344,7 +1398,8 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7475u, n_, 0, ld, ld, X, xb_, ld, 0));
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7476u, n_, 0, ld, ld, V, xb_, ld, 0));
     // entry splits only pay on rows of many entries
-    const auto cand = tune_candidates(n_, ld, xb_, a_->nnz >= 16 * a_->n, true);
+    const auto cand = tune_candidates(n_, ld, xb_, a_->nnz >= 16 * a_->n, true,
+                                      stride_candidates(st));
     const int nc = (int)cand.size();
     std::vector<double> tp(nc, 1e300), tu(nc, 1e300);
     VecSet vf{};
@@ -1377,7 +1432,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
         LD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
         tp[c] = std::min(tp[c], (double)ms / reps);
         // the update has no sparse entries to split and keeps its own mapping
-        if (g.lges != 0 || g.xil != 0) continue;
+        if (g.lges != 0 || g.xil != 0 || g.ts != 0) continue;
         LD_HIP(update());
         LD_HIP(hipEventRecord(ev.a, st));
         for (int i = 0; i < reps; ++i) LD_HIP(update());
@@ -1407,6 +1462,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
       out->spmm_chunks = cand[bp].second;
       out->spmm_entry_split = 1 << ((cand[bp].first >> 8) & 0xf);
       out->spmm_interleave = (cand[bp].first >> 12) & 1;
+      out->spmm_row_stride = (cand[bp].first >> 16) & 0x7fff;
       out->update_lanes = cand[bu].first;
       out->update_chunks = cand[bu].second;
       out->spmm_ms = tp[bp];
@@ -1420,21 +1476,24 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
 }
 
 ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int update_lanes,
-                         int update_chunks, int spmm_interleave) {
+                         int update_chunks, int spmm_interleave, int spmm_row_stride) {
   int e = 0;
   while (e < 4 && (1 << e) < spmm_split) ++e;
   Geom gp = make_geom_lc(n_, ldB_, xb_, spmm_lanes, spmm_chunks);
   gp.lges = e;
+  gp.ts = spmm_row_stride;
   if ((1 << e) != spmm_split || !geom_usable(gp) || (spmm_interleave != 0 && spmm_interleave != 1) ||
       !geom_usable(make_geom_lc(n_, ldB_, xb_, update_lanes, update_chunks)))
     return set_error(LD_E_INVALID_ARG,
                      "lanes must be <= 64 (a power of two with an entry split), chunks in "
                      "[1, 4] and the entry split 1, 2, 4 or 8 (at most the lanes), the lanes "
                      "per split group and the chunks covering the probe block, interleave 0 "
-                     "or 1");
+                     "or 1, the row stride 0 or a multiple of the rows per wave (64 / lanes, "
+                     "lanes a power of two) up to 32767");
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
   std::lock_guard<std::mutex> lk(a_->tune_mu);
-  a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes | (e << 8) | (spmm_interleave << 12),
+  a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes | (e << 8) | (spmm_interleave << 12) |
+                                             (spmm_row_stride << 16),
                                          spmm_chunks};
   a_->tune[tune_key(ldB_, xb_, vt, upd_which())] = {update_lanes, update_chunks};
   a_->tune_ver.fetch_add(1);
@@ -1884,13 +1943,13 @@ ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_re
 
 ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
                       int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks,
-                      int32_t spmm_interleave) {
+                      int32_t spmm_interleave, int32_t spmm_row_stride) {
   if (!a || !p) return set_error(LD_E_INVALID_ARG, "null argument");
   Run run(a, *p);
   ld_status rc = run.validate();
   if (rc != LD_OK) return rc;
   return run.tune_set(spmm_lanes, spmm_chunks, spmm_entry_split, update_lanes, update_chunks,
-                      spmm_interleave);
+                      spmm_interleave, spmm_row_stride);
 }
 
 ld_status ld_quad_form(ld_matrix* a, const double* x, double* out) {

@@ -359,7 +359,8 @@ class Run {
   // this request's matrix and block shape; store the fastest in the matrix.
   ld_status tune(hipStream_t st, int reps, ld_tune_result* out);
   ld_status tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int update_lanes,
-                     int update_chunks, int spmm_interleave = 0);
+                     int update_chunks, int spmm_interleave = 0, int spmm_row_stride = 0);
+  std::vector<int> stride_candidates(hipStream_t st) const;
   double submit_time() const { return t_submit_; }
   void set_submit_time(double t) { t_submit_ = t; }
   int64_t n() const { return n_; }

@@ -141,6 +141,67 @@ def test_entry_split_long_rows(L, ctx):
             ctx.release(h)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_row_tiles(L, ctx, prec):
+    # the product taking its rows in tiles of 4 runs S rows apart: any valid
+    # S gives the estimate up to the order of the FP64 partial sums; strides
+    # with whole tiles only (n = 8000 = 20 tiles of 400) and with a ragged
+    # remainder of rows in the plain order
+    a = W.lap3d(20, 0.05)
+    mixed = prec == "mixed"
+    npr = 96 if mixed else 24
+    P = L.LD_PREC_MIXED if mixed else L.LD_PREC_FP64
+    vt = L.LD_VT_FP32 if mixed else L.LD_VT_FP64
+    s, m, seed = 6, 14, 12
+    tol, tight = (1e-4, 1e-5) if mixed else (1e-6, 1e-11)
+    for k in (2, 5):
+        ref = oracle.oslq(a, npr, s, m, k, seed)
+        h = ctx.matrix(a, vt=vt)
+        try:
+            p = L.make_params(npr, s, m, k, seed, precision=P)
+            base = L.ld_estimate_ex(h, p).logdet
+            # (lanes, chunks, split, strides): rows per wave 64 / lanes
+            geoms = ((8, 3, 1, (8, 24, 400, 2000)), (32, 2, 2, (2, 20, 22, 400))) if mixed else \
+                    ((16, 1, 1, (4, 12, 20, 400)), (32, 1, 2, (2, 20, 22, 400)))
+            for lanes, ch, e, strides in geoms:
+                for S in strides:
+                    for il in (0, 1):
+                        _announce(f"row tiles n={a.n} prec={prec} k={k} L={lanes} C={ch} "
+                                  f"split={e} interleave={il} stride={S}")
+                        L.ld_tune_set(h, p, lanes, ch, 8, 3 if mixed else 2, e, il, S)
+                        res, det = L.ld_estimate_detail(h, p, n=a.n, tri=True)
+                        rel = abs(res.logdet - ref.logdet) / abs(ref.logdet)
+                        assert rel <= tol, (lanes, S, il, rel)
+                        assert abs(res.logdet - base) <= tight * abs(base), (lanes, S, il)
+                        np.testing.assert_array_equal(det["probe_steps"],
+                                                      np.array(ref.probe_steps))
+                        assert L.ld_estimate_ex(h, p).logdet == res.logdet
+            # a served request on the tiled geometry equals the same request alone
+            L.ld_tune_set(h, p, geoms[0][0], geoms[0][1], 8, 3 if mixed else 2, 1, 1, 400)
+            alone = L.ld_estimate_ex(h, p).logdet
+            t = L.ld_submit(h, p)
+            assert L.ld_wait(ctx.handle, t).logdet == alone
+        finally:
+            ctx.release(h)
+
+
+def test_row_stride_rejected(L, ctx):
+    a = W.lap2d(40, 0.1)
+    h = ctx.matrix(a)
+    try:
+        p = L.make_params(24, 6, 10, 2, 1)  # FP64: 12 chunks per row
+        base = L.ld_estimate_ex(h, p).logdet
+        for lanes, ch, e, S in ((16, 1, 1, 6), (16, 1, 1, -4), (16, 1, 1, 32768),
+                                (12, 1, 1, 16), (8, 2, 1, 4), (32, 1, 2, 3)):
+            _announce(f"ld_tune_set rejects row stride {S} with L={lanes} C={ch} split={e}")
+            with pytest.raises(L.LdError) as ei:
+                L.ld_tune_set(h, p, lanes, ch, 16, 1, e, 0, S)
+            assert ei.value.status == L.LD_E_INVALID_ARG
+        assert L.ld_estimate_ex(h, p).logdet == base
+    finally:
+        ctx.release(h)
+
+
 def test_invalid_geometry_rejected(L, ctx):
     a = W.lap2d(40, 0.1)
     h = ctx.matrix(a)
@@ -188,6 +249,8 @@ def test_autotune_parity_and_reset(L, ctx, prec):
         ncolv = npr // (4 if mixed else 2)
         assert tr.candidates >= 1
         assert tr.spmm_entry_split in (1, 2, 4, 8)
+        # row tiles are tried at the grid's line and plane strides (24, 576)
+        assert tr.spmm_row_stride in (0, 24, 576)
         for lanes, ch in ((tr.spmm_lanes // tr.spmm_entry_split, tr.spmm_chunks),
                           (tr.update_lanes, tr.update_chunks)):
             assert (lanes, ch) in _usable(ncolv)
