@@ -481,7 +481,8 @@ def shift_variants(L, W, args):
     """The headline Laplacian with the other shifts of its configuration
     (1e-3 and 1e-1; the headline is 1e-2): FP32 vectors and LD_PREC_AUTO
     (FP64 at 1e-3, where lambda_hi / lambda_lo is 12006), each against the
-    FP64 estimate and the closed-form log-determinant."""
+    FP64 estimate and the closed-form log-determinant, each precision after
+    its own autotuning pass on the new matrix (as the headline)."""
     out = {}
     with L.Context(0) as ctx:
         for shift in (1e-3, 1e-1):
@@ -489,13 +490,17 @@ def shift_variants(L, W, args):
             h = ctx.matrix(a, vt=L.LD_VT_FP32)
             exact = W.lap3d_exact_logdet(args.grid, shift)
             rec = {"closed_form": exact}
-            r64 = L.ld_estimate_ex(h, L.make_params(args.probes, args.sketch, args.krylov_steps,
-                                                    args.window, args.seed,
-                                                    precision=L.LD_PREC_FP64))
+            p64 = L.make_params(args.probes, args.sketch, args.krylov_steps, args.window,
+                                args.seed, precision=L.LD_PREC_FP64)
+            if args.tune_reps > 0:
+                L.ld_autotune(h, p64, args.tune_reps)
+            r64 = L.ld_estimate_ex(h, p64)
             rec["fp64_ms"] = r64.device_ms
             for name, prec in (("mixed", L.LD_PREC_MIXED), ("auto", L.LD_PREC_AUTO)):
                 p = L.make_params(args.probes, args.sketch, args.krylov_steps, args.window,
                                   args.seed, precision=prec)
+                if args.tune_reps > 0 and prec == L.LD_PREC_MIXED:
+                    L.ld_autotune(h, p, args.tune_reps)
                 L.ld_estimate_ex(h, p)
                 reps = 2
                 t0 = time.perf_counter()
