@@ -1317,13 +1317,20 @@ std::vector<int> Run::stride_candidates(hipStream_t st) const {
     if (hipMemcpyAsync(rp.data(), a_->rp + r0, rp.size() * sizeof(int), hipMemcpyDeviceToHost,
                        st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
       return {};
+    // at most kMaxEntries sampled entries per window (long rows)
+    constexpr int kMaxEntries = 1 << 20;
+    size_t nr = rp.size() - 1;
+    while (nr > 1 && rp[nr] - rp.front() > kMaxEntries) nr /= 2;
+    rp.resize(nr + 1);
+    if (rp.back() - rp.front() > kMaxEntries) continue;
+    const int64_t r1s = r0 + (int64_t)nr;
     std::vector<int> ci((size_t)(rp.back() - rp.front()));
     if (!ci.empty() &&
         (hipMemcpyAsync(ci.data(), a_->ci + rp.front(), ci.size() * sizeof(int),
                         hipMemcpyDeviceToHost, st) != hipSuccess ||
          hipStreamSynchronize(st) != hipSuccess))
       return {};
-    for (int64_t i = r0; i < r1; ++i) {
+    for (int64_t i = r0; i < r1s; ++i) {
       for (int k = rp[i - r0] - rp.front(); k < rp[i - r0 + 1] - rp.front(); ++k) {
         const int64_t d = (int64_t)ci[k] - i;
         if (d >= 2 && d <= kMaxRowStride) ++count[d];
