@@ -78,43 +78,50 @@ def parse():
                     help="launches per candidate of the product/update geometry autotuner "
                          "(0 keeps the default geometry)")
     ap.add_argument("--config-geometry", action="append", default=[],
-                    help="NAME=L,C,E,I[,S]/L,C: pin the FP32-vector geometry of a full-size "
+                    help="NAME=L,C,E,I[,S]/L,C[/P]: pin the FP32-vector geometry of a full-size "
                          "configuration leg instead of autotuning it (repeatable)")
     ap.add_argument("--geometry", type=str, default=None,
                     help="pin the headline geometry instead of autotuning it: "
-                         "'L,C,E,I[,S]/L,C' = product lanes per row, chunks per lane, entry "
-                         "split, interleave[, row-tile stride] / update lanes per row, "
-                         "chunks per lane")
+                         "'L,C,E,I[,S]/L,C[/P]' = product lanes per row, chunks per lane, "
+                         "entry split, interleave[, row-tile stride] / update lanes per row, "
+                         "chunks per lane [/ step schedule: 1 the product subtracts the "
+                         "second-newest window vector (default), 0 the update]")
     return ap.parse_args()
 
 
 def parse_geometry(spec):
-    prod, upd = spec.split("/")
-    pv = [int(x) for x in prod.split(",")]
+    parts = spec.split("/")
+    pv = [int(x) for x in parts[0].split(",")]
     pl, pc, pe, pi = pv[:4]
     ps = pv[4] if len(pv) > 4 else 0
-    ul, uc = (int(x) for x in upd.split(","))
+    ul, uc = (int(x) for x in parts[1].split(","))
+    sched = int(parts[2]) if len(parts) > 2 else 1
     return {"spmm_lanes": pl, "spmm_chunks": pc, "spmm_entry_split": pe, "spmm_interleave": pi,
-            "spmm_row_stride": ps, "update_lanes": ul, "update_chunks": uc, "pinned": True}
+            "spmm_row_stride": ps, "update_lanes": ul, "update_chunks": uc,
+            "step_presub": sched, "pinned": True}
 
 
 def set_geometry(L, h, p, tune):
     L.ld_tune_set(h, p, tune["spmm_lanes"], tune["spmm_chunks"], tune["update_lanes"],
                   tune["update_chunks"], spmm_entry_split=tune["spmm_entry_split"],
                   spmm_interleave=tune["spmm_interleave"],
-                  spmm_row_stride=tune.get("spmm_row_stride", 0))
+                  spmm_row_stride=tune.get("spmm_row_stride", 0),
+                  step_presub=tune.get("step_presub", 1))
 
 
 def geometry_key(tune):
     """The geometry a PMC record was taken with: 'default', or the product's
     'L,C,E,I' (lanes, chunks, entry split, interleave), with ',S' when its
-    rows are taken in tiles of stride S."""
+    rows are taken in tiles of stride S and '+plain' when the update, not
+    the product, subtracts the second-newest window vector."""
     if not tune:
         return "default"
     key = (f"{tune['spmm_lanes']},{tune['spmm_chunks']},{tune['spmm_entry_split']},"
            f"{tune['spmm_interleave']}")
     if tune.get("spmm_row_stride", 0):
         key += f",{tune['spmm_row_stride']}"
+    if not tune.get("step_presub", 1):
+        key += "+plain"
     return key
 
 
@@ -414,6 +421,7 @@ def configs_bench(L, W, args):
                     prod["geometry"] = geo
                     prod["update_geometry"] = (f"{tune['update_lanes']},{tune['update_chunks']}"
                                                if tune else "default")
+                    prod["step_presub"] = tune.get("step_presub", 1) if tune else 1
                     prod["interleaved"] = tune["spmm_interleave"] if tune else 0
                     kname = f"ld::k_spmm<float, float, {tune['spmm_chunks'] if tune else 0}, "
                     ks = [v for kn, v in (pr or {}).get("geometries", {}).get(geo, {}).items()
@@ -930,6 +938,7 @@ def main():
                                  "product_entry_split": tune["spmm_entry_split"],
                                  "product_interleaved": tune["spmm_interleave"],
                                  "product_row_stride": tune.get("spmm_row_stride", 0),
+                                 "step_presub": tune.get("step_presub", 1),
                                  "update": [tune["update_lanes"], tune["update_chunks"]]}
                                 if tune else "default")},
         "autotune": tune,

@@ -277,6 +277,10 @@ ld_status ld_request_bytes(ld_matrix* a, const ld_params* p, uint64_t* bytes);
  * lane groups (L a power of two, L / E column lanes each, their sums added
  * at the row's end), which shortens the per-lane chain of dependent gathers
  * on long rows (tried when rows hold 16 entries or more on average).
+ * For windows of two or more ld_autotune also times the two step schedules
+ * (ld_tune_result.step_presub) on its choices and keeps the schedule in
+ * which the product subtracts the second-newest vector unless the other is
+ * more than 1% faster per step.
  * The product's rows may also be taken in tiles (ld_tune_set's
  * spmm_row_stride), which ld_autotune tries on every power-of-two L with the
  * strides of the matrix's most frequent column offsets (at most two, each in
@@ -311,6 +315,12 @@ typedef struct {
                               * which keeps a row's neighbours in one L2    */
   int32_t spmm_row_stride;   /* 0, or S: the product's block takes its rows as
                               * 4 runs S rows apart (row tiles)             */
+  int32_t step_presub;       /* 1: the product subtracts the second-newest
+                              * window vector (its coefficient is known by
+                              * symmetry) and the update the rest; 0: the
+                              * update subtracts the whole window           */
+  double step_presub_ms;     /* product + update per step, schedule 1       */
+  double step_plain_ms;      /* the same, schedule 0 (0 for windows of 1)   */
 } ld_tune_result;
 ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_result* out);
 /* Stores a given geometry for the estimate block of `p` on this matrix (a
@@ -324,13 +334,15 @@ ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_re
  * waves of the block gather at the same time; S a multiple of 64 / L, L a
  * power of two, S <= 32767; rows past the last whole tile of 4 S rows keep
  * the plain order), the update likewise (no split, interleaved; stored for
- * the window class of `p`).  Any (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8},
+ * the window class of `p`), with the step schedule step_presub (1: the
+ * product subtracts the second-newest window vector, the default; 0: the
+ * update subtracts the whole window; see ld_tune_result).  Any (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8},
  * E <= L, C <= 2 when E > 1, and (L / E) * C chunks covering the block is
  * accepted, where L is a power of two when E > 1; anything else is
  * LD_E_INVALID_ARG and stores nothing. */
 ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
                       int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks,
-                      int32_t spmm_interleave, int32_t spmm_row_stride);
+                      int32_t spmm_interleave, int32_t spmm_row_stride, int32_t step_presub);
 
 /* Serving with continuous batching: queue a request and return at once with
  * a ticket.  Requests are admitted as resident slots and HBM budget free up;

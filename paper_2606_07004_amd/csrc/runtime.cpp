@@ -378,31 +378,41 @@ ld_status Run::validate() {
   gB_ = make_geom(n_, ldB_, xb_);
   gS_ = make_geom(n_, lds_, 8);
   g1_ = make_geom(n_, ld1_, xb_);
+  psB_ = presub_choice(ldB_);
+  ps1_ = presub_choice(ld1_);
   gBp_ = krylov_geom(ldB_, 0);
-  gBu_ = krylov_geom(ldB_, upd_which());
+  gBu_ = krylov_geom(ldB_, upd_which(psB_));
   g1p_ = krylov_geom(ld1_, 0);
-  g1u_ = krylov_geom(ld1_, upd_which());
+  g1u_ = krylov_geom(ld1_, upd_which(ps1_));
   return LD_OK;
 }
 
 // Key of a tuned geometry: block width, element bytes, matrix value type of
-// the product, kernel (0 product; 1 | class << 4 the update of a window class).
+// the product, kernel (0 product; 1 | class << 4 the update of a window class;
+// 2 the step schedule: {1, 0} when the update, not the product, subtracts
+// the second-newest window vector).
 static uint64_t tune_key(int ld, int xbytes, int vt, int which) {
   return (uint64_t)ld | ((uint64_t)xbytes << 16) | ((uint64_t)vt << 24) | ((uint64_t)which << 32);
 }
 
 // The update's register footprint grows with the vectors it subtracts, so its
 // tuned geometry is kept per class of the steady-state window: the window
-// (up to 8 vectors per launch, 4 with FP16 vectors) less the second-newest
-// vector, which the product subtracts when the window holds two or more.
-int Run::upd_steady_nv() const {
+// (up to 8 vectors per launch, 4 with FP16 vectors), less the second-newest
+// vector when the product subtracts it (windows of two or more).
+int Run::upd_steady_nv(bool presub) const {
   const int kw = std::max(1, std::min(k_, half_ ? 4 : kMaxNv));
-  return k_ >= 2 ? kw - 1 : kw;
+  return (k_ >= 2 && presub) ? kw - 1 : kw;
 }
-int Run::upd_which() const {
-  const int nv = upd_steady_nv();
+int Run::upd_which(bool presub) const {
+  const int nv = upd_steady_nv(presub);
   const int cls = nv <= 1 ? 1 : (nv == 2 ? 2 : (nv <= 4 ? 4 : 8));
   return 1 | (cls << 4);
+}
+bool Run::presub_choice(int ld) const {
+  const int vt = mixed_ ? a_->vt_lo : VT_F64;
+  std::lock_guard<std::mutex> lk(a_->tune_mu);
+  auto it = a_->tune.find(tune_key(ld, xb_, vt, 2));
+  return it == a_->tune.end() || it->second.first == 0;
 }
 
 Geom Run::krylov_geom(int ld, int which) const {
@@ -604,6 +614,7 @@ ld_status Run::begin_krylov(int phase) {
     kld_ = ldB_;
     kg_ = gBp_;
     kgu_ = gBu_;
+    kps_ = psB_;
     kpin_ = false;
     kfull_ = false;
     kns_ = std::min(k_, m_) + 1;
@@ -612,6 +623,7 @@ ld_status Run::begin_krylov(int phase) {
     kld_ = ld1_;
     kg_ = g1p_;
     kgu_ = g1u_;
+    kps_ = ps1_;
     kpin_ = false;
     kfull_ = !two_pass_;
     kns_ = two_pass_ ? std::min(m_ + 1, std::min(k_, m_) + 1 + kCombBatch) : m_ + 1;
@@ -620,6 +632,7 @@ ld_status Run::begin_krylov(int phase) {
     kld_ = ldB_;
     kg_ = gBp_;
     kgu_ = gBu_;
+    kps_ = psB_;
     kpin_ = true;
     kfull_ = false;
     kns_ = std::min(k_, m_) + 2;
@@ -830,7 +843,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
   // the update's vectors: the window without v_t-1 when the product took it
   // out (coefficient row nv - 2 skipped)
   const int upd_max = half_ ? 4 : kMaxNv;
-  const bool presub = sym_in && nv - 1 <= upd_max;
+  const bool presub = kps_ && sym_in && nv - 1 <= upd_max;
   const int nu = presub ? nv - 1 : nv;
   const int dhole = presub ? nv - 1 : 0;
   auto upd_vec = [&](int v) { return j0 + v + ((presub && v >= nv - 2) ? 1 : 0); };
@@ -1365,7 +1378,9 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     std::lock_guard<std::mutex> lk(a_->tune_mu);
     for (int ld : widths) {
       a_->tune.erase(tune_key(ld, xb_, vt, 0));
-      a_->tune.erase(tune_key(ld, xb_, vt, upd_which()));
+      a_->tune.erase(tune_key(ld, xb_, vt, upd_which(true)));
+      a_->tune.erase(tune_key(ld, xb_, vt, upd_which(false)));
+      a_->tune.erase(tune_key(ld, xb_, vt, 2));
     }
     a_->tune_ver.fetch_add(1);
     if (out) *out = ld_tune_result{};
@@ -1396,7 +1411,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
   // the second-newest vector (V here) and the update takes the rest of the
   // window and forms the next second-newest inner product
   const bool sym = k_ >= 2;
-  const int nv = upd_steady_nv();
+  const int nv = upd_steady_nv(true);
   EventPair ev;
   LD_HIP(hipEventCreate(&ev.a));
   LD_HIP(hipEventCreate(&ev.b));
@@ -1457,10 +1472,80 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
       if (tp[c] < 0.99 * tp[bp]) bp = c;
       if (tu[c] < 0.99 * tu[bu]) bu = c;
     }
+    // the step schedule: the product subtracting the second-newest vector
+    // (as swept above) or the update taking the whole window (the product
+    // then streams one vector less and the update one more), both timed
+    // again in the same rounds; the latter is kept only when its product
+    // and update are more than 1% faster per step
+    bool presub = true;
+    int bun = 0;
+    double ps_ms = tp[bp] + tu[bu], plain_ms = 0.0;
+    if (sym) {
+      const int nvn = upd_steady_nv(false);
+      VecSet vun{};
+      for (int v = 0; v < nvn; ++v) {
+        vun.x[v] = v + 1 == nvn ? X : V;
+        vun.mult[v] = mult;
+      }
+      const Geom gp = candidate_geom(n_, ld, xb_, cand[bp]);
+      const Geom gu = candidate_geom(n_, ld, xb_, cand[bu]);
+      std::vector<int> ucand;
+      for (int c = 0; c < nc; ++c) {
+        const Geom g = candidate_geom(n_, ld, xb_, cand[c]);
+        if (g.lges == 0 && g.xil == 0 && g.ts == 0) ucand.push_back(c);
+      }
+      double t_psp = 1e300, t_psu = 1e300, t_pp = 1e300;
+      std::vector<double> t_pu(nc, 1e300);
+      auto timed = [&](auto&& fn, double& best) -> hipError_t {
+        hipError_t e = fn();  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(ev.a, st);
+        for (int i = 0; i < reps && e == hipSuccess; ++i) e = fn();
+        if (e == hipSuccess) e = hipEventRecord(ev.b, st);
+        if (e == hipSuccess) e = hipEventSynchronize(ev.b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.a, ev.b);
+        if (e == hipSuccess) best = std::min(best, (double)ms / reps);
+        return e;
+      };
+      int nb = 0;
+      for (int round = 0; round < 3; ++round) {
+        LD_HIP(timed([&]() {
+          return launch_spmm(st, gp, a_->rp, a_->ci, vals, vt, X, W, mult, opscale_ * vscale_,
+                             &vf, 1, 0, part, &nb, V, mult, dcoef);
+        }, t_psp));
+        LD_HIP(timed([&]() {
+          return launch_spmm(st, gp, a_->rp, a_->ci, vals, vt, X, W, mult, opscale_ * vscale_,
+                             &vf, 1, 0, part, &nb);
+        }, t_pp));
+        LD_HIP(timed([&]() {
+          return launch_update(st, gu, W, vu, nv, dcoef, 0, 1, nullptr, nullptr, true, part,
+                               &nb, nv);
+        }, t_psu));
+        for (int c : ucand) {
+          const Geom g = candidate_geom(n_, ld, xb_, cand[c]);
+          LD_HIP(timed([&]() {
+            return launch_update(st, g, W, vun, nvn, dcoef, 0, 1, nullptr, nullptr, true, part,
+                                 &nb);
+          }, t_pu[c]));
+        }
+      }
+      bun = ucand.front();
+      for (int c : ucand)
+        if (t_pu[c] < 0.99 * t_pu[bun]) bun = c;
+      ps_ms = t_psp + t_psu;
+      plain_ms = t_pp + t_pu[bun];
+      presub = !(plain_ms < 0.99 * ps_ms);
+    }
     {
       std::lock_guard<std::mutex> lk(a_->tune_mu);
       a_->tune[tune_key(ld, xb_, vt, 0)] = cand[bp];
-      a_->tune[tune_key(ld, xb_, vt, upd_which())] = cand[bu];
+      if (presub) {
+        a_->tune[tune_key(ld, xb_, vt, upd_which(true))] = cand[bu];
+        a_->tune.erase(tune_key(ld, xb_, vt, 2));
+      } else {
+        a_->tune[tune_key(ld, xb_, vt, upd_which(false))] = cand[bun];
+        a_->tune[tune_key(ld, xb_, vt, 2)] = {1, 0};
+      }
       a_->tune_ver.fetch_add(1);
     }
     if (wi == 0 && out) {
@@ -1470,39 +1555,48 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
       out->spmm_entry_split = 1 << ((cand[bp].first >> 8) & 0xf);
       out->spmm_interleave = (cand[bp].first >> 12) & 1;
       out->spmm_row_stride = (cand[bp].first >> 16) & 0x7fff;
-      out->update_lanes = cand[bu].first;
-      out->update_chunks = cand[bu].second;
+      out->update_lanes = cand[presub ? bu : bun].first;
+      out->update_chunks = cand[presub ? bu : bun].second;
       out->spmm_ms = tp[bp];
       out->spmm_default_ms = tp[0];
       out->update_ms = tu[bu];
       out->update_default_ms = tu[0];
       out->candidates = nc;
+      out->step_presub = presub ? 1 : 0;
+      out->step_presub_ms = ps_ms;
+      out->step_plain_ms = plain_ms;
     }
   }
   return LD_OK;
 }
 
 ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int update_lanes,
-                         int update_chunks, int spmm_interleave, int spmm_row_stride) {
+                         int update_chunks, int spmm_interleave, int spmm_row_stride,
+                         int step_presub) {
   int e = 0;
   while (e < 4 && (1 << e) < spmm_split) ++e;
   Geom gp = make_geom_lc(n_, ldB_, xb_, spmm_lanes, spmm_chunks);
   gp.lges = e;
   gp.ts = spmm_row_stride;
   if ((1 << e) != spmm_split || !geom_usable(gp) || (spmm_interleave != 0 && spmm_interleave != 1) ||
-      !geom_usable(make_geom_lc(n_, ldB_, xb_, update_lanes, update_chunks)))
+      !geom_usable(make_geom_lc(n_, ldB_, xb_, update_lanes, update_chunks)) ||
+      (step_presub != 0 && step_presub != 1))
     return set_error(LD_E_INVALID_ARG,
                      "lanes must be <= 64 (a power of two with an entry split), chunks in "
                      "[1, 4] and the entry split 1, 2, 4 or 8 (at most the lanes), the lanes "
                      "per split group and the chunks covering the probe block, interleave 0 "
                      "or 1, the row stride 0 or a multiple of the rows per wave (64 / lanes, "
-                     "lanes a power of two) up to 32767");
+                     "lanes a power of two) up to 32767, the step schedule 0 or 1");
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
   std::lock_guard<std::mutex> lk(a_->tune_mu);
   a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes | (e << 8) | (spmm_interleave << 12) |
                                              (spmm_row_stride << 16),
                                          spmm_chunks};
-  a_->tune[tune_key(ldB_, xb_, vt, upd_which())] = {update_lanes, update_chunks};
+  a_->tune[tune_key(ldB_, xb_, vt, upd_which(step_presub != 0))] = {update_lanes, update_chunks};
+  if (step_presub)
+    a_->tune.erase(tune_key(ldB_, xb_, vt, 2));
+  else
+    a_->tune[tune_key(ldB_, xb_, vt, 2)] = {1, 0};
   a_->tune_ver.fetch_add(1);
   return LD_OK;
 }
@@ -1950,13 +2044,14 @@ ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_re
 
 ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
                       int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks,
-                      int32_t spmm_interleave, int32_t spmm_row_stride) {
+                      int32_t spmm_interleave, int32_t spmm_row_stride,
+                      int32_t step_presub) {
   if (!a || !p) return set_error(LD_E_INVALID_ARG, "null argument");
   Run run(a, *p);
   ld_status rc = run.validate();
   if (rc != LD_OK) return rc;
   return run.tune_set(spmm_lanes, spmm_chunks, spmm_entry_split, update_lanes, update_chunks,
-                      spmm_interleave, spmm_row_stride);
+                      spmm_interleave, spmm_row_stride, step_presub);
 }
 
 ld_status ld_quad_form(ld_matrix* a, const double* x, double* out) {

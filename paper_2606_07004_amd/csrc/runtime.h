@@ -224,8 +224,9 @@ class Run {
   // product (which = 0) or update (which = 1) geometry of a Krylov block of
   // width ld: the matrix's tuned choice when it holds one, else the default
   Geom krylov_geom(int ld, int which) const;
-  int upd_steady_nv() const;  // update vectors of a steady-state step
-  int upd_which() const;      // tuning key of the update (window class)
+  int upd_steady_nv(bool presub) const;  // update vectors of a steady-state step
+  int upd_which(bool presub) const;      // tuning key of the update (window class)
+  bool presub_choice(int ld) const;      // the stored step schedule of block width ld
   double spmm_bytes(int ld, int xbytes) const;
 
   ld_matrix* a_;
@@ -245,6 +246,7 @@ class Run {
   int lds_ = 0, ldr_ = 0, ldB_ = 0, ld1_ = 0, ldx_ = 0;
   Geom gB_, gS_, g1_;
   Geom gBp_, gBu_, g1p_, g1u_;  // Krylov product / update geometries
+  bool psB_ = true, ps1_ = true;  // the product subtracts the second-newest vector
   // state machine
   int stage_ = 0;             // 0 prologue, 1 krylov, 2 epilogue..., see .cpp
   int t_ = 0;
@@ -264,6 +266,7 @@ class Run {
   bool kpin_ = false, kfull_ = false;
   bool sym_ready_ = false;    // the next step's second-newest window product is in dwin_
   Geom kg_, kgu_;             // product / dots-and-update geometry of the phase
+  bool kps_ = true;           // the phase's product subtracts the second-newest vector
   void* kslots_ = nullptr;
   double* kmult_ = nullptr;
   // device buffers
@@ -359,7 +362,8 @@ class Run {
   // this request's matrix and block shape; store the fastest in the matrix.
   ld_status tune(hipStream_t st, int reps, ld_tune_result* out);
   ld_status tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int update_lanes,
-                     int update_chunks, int spmm_interleave = 0, int spmm_row_stride = 0);
+                     int update_chunks, int spmm_interleave = 0, int spmm_row_stride = 0,
+                     int step_presub = 1);
   std::vector<int> stride_candidates(hipStream_t st) const;
   double submit_time() const { return t_submit_; }
   void set_submit_time(double t) { t_submit_ = t; }

@@ -185,6 +185,45 @@ def test_row_tiles(L, ctx, prec):
             ctx.release(h)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_step_schedules(L, ctx, prec):
+    # the two step schedules (the product subtracting the second-newest
+    # window vector, or the update subtracting the whole window) give the
+    # estimate up to rounding, for windows 2, 3, 5 and a window larger than
+    # one launch of the update takes; served equals alone under either
+    a = W.lap2d(45, 0.05)
+    mixed = prec == "mixed"
+    npr = 40 if mixed else 24
+    P = L.LD_PREC_MIXED if mixed else L.LD_PREC_FP64
+    vt = L.LD_VT_FP32 if mixed else L.LD_VT_FP64
+    s, m, seed = 6, 16, 21
+    tol, tight = (1e-4, 1e-5) if mixed else (1e-6, 1e-11)
+    h = ctx.matrix(a, vt=vt)
+    try:
+        for k in (2, 3, 5, 10):
+            ref = oracle.oslq(a, npr, s, m, k, seed)
+            p = L.make_params(npr, s, m, k, seed, precision=P)
+            vals = {}
+            for ps in (1, 0):
+                _announce(f"step schedule presub={ps} n={a.n} prec={prec} k={k}")
+                L.ld_tune_set(h, p, 16, 1, 16, 1, 1, ps % 2, 0, ps)
+                res, det = L.ld_estimate_detail(h, p, n=a.n, tri=True)
+                rel = abs(res.logdet - ref.logdet) / abs(ref.logdet)
+                assert rel <= tol, (k, ps, rel)
+                np.testing.assert_array_equal(det["probe_steps"], np.array(ref.probe_steps))
+                assert L.ld_estimate_ex(h, p).logdet == res.logdet
+                t = L.ld_submit(h, p)
+                assert L.ld_wait(ctx.handle, t).logdet == res.logdet
+                vals[ps] = res.logdet
+            assert abs(vals[0] - vals[1]) <= tight * abs(vals[1]), k
+        with pytest.raises(L.LdError) as ei:
+            L.ld_tune_set(h, L.make_params(npr, s, m, 2, seed, precision=P), 16, 1, 16, 1, 1, 0,
+                          0, 2)
+        assert ei.value.status == L.LD_E_INVALID_ARG
+    finally:
+        ctx.release(h)
+
+
 def test_row_stride_rejected(L, ctx):
     a = W.lap2d(40, 0.1)
     h = ctx.matrix(a)
@@ -251,6 +290,7 @@ def test_autotune_parity_and_reset(L, ctx, prec):
         assert tr.spmm_entry_split in (1, 2, 4, 8)
         # row tiles are tried at the grid's line and plane strides (24, 576)
         assert tr.spmm_row_stride in (0, 24, 576)
+        assert tr.step_presub in (0, 1) and tr.step_presub_ms > 0 and tr.step_plain_ms > 0
         for lanes, ch in ((tr.spmm_lanes // tr.spmm_entry_split, tr.spmm_chunks),
                           (tr.update_lanes, tr.update_chunks)):
             assert (lanes, ch) in _usable(ncolv)
