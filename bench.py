@@ -281,7 +281,9 @@ def cpu_baseline(a, args):
 def comparators_bench(L, W, ctx, h, a, vt, args):
     """The paper's comparison (SLQ, So-SLQ, OSLQ, OSA-IOP, Section 4) redone on
     the benchmark matrix: one estimate each after a warm-up, the same total
-    probe count, mixed precision; error against the closed form."""
+    probe count, mixed precision; error against the closed form.  So-SLQ and
+    OSA-IOP also run Krylov blocks of the sketch width, which the headline's
+    autotuning pass does not cover: they get a pass of their own."""
     exact = W.lap3d_exact_logdet(args.grid, args.shift) if args.grid in (64, 128) else None
     npr, m, win = args.probes, args.krylov_steps, args.window
     cases = {
@@ -298,6 +300,8 @@ def comparators_bench(L, W, ctx, h, a, vt, args):
     out = {}
     for name, p in cases.items():
         p.precision = PRECISIONS[args.precision](L)
+        if args.tune_reps > 0 and name in ("so_slq_q30_k10", "osa_iop"):
+            L.ld_autotune(h, p, args.tune_reps)
         L.ld_estimate_ex(h, p)
         t0 = time.perf_counter()
         r = L.ld_estimate_ex(h, p)
@@ -845,6 +849,17 @@ def main():
     if tr is not None:
         roofline["traffic"] = tr["bytes_per_launch"]
         roofline["traffic_detail"] = tr
+    # the Krylov step as a whole (product, window dots, update): where the
+    # second-newest vector is subtracted moves bytes between the product and
+    # the update, not the step's total
+    step_fams = ("spmm", "dots", "update")
+    st_b = sum(fam[k]["bytes"] for k in step_fams)
+    st_ms = sum(fam[k]["ms"] for k in step_fams)
+    if st_ms > 0:
+        roofline["krylov_step"] = {"families": list(step_fams), "bytes_per_estimate": st_b,
+                                   "ms_per_estimate": st_ms,
+                                   "achieved": st_b / (st_ms * 1e-3) / 1e9,
+                                   "frac": st_b / (st_ms * 1e-3) / HBM_PEAK}
     device_ms_total = sum(v["ms"] for v in fam.values())  # one estimate
     families = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                     "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
