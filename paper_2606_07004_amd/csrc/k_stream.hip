@@ -457,11 +457,11 @@ __global__ __launch_bounds__(kThreads, (NF == 2 || (sizeof(VT) == 8 && sizeof(XT
 }
 
 // ---------------------------------------------------------------------------
-// Window inner products not fused into the product: up to 4 vectors.
+// Window inner products not fused into the product: up to NV vectors per
+// launch, 4 in any geometry, 8 with one 16-byte chunk per lane (the FP64
+// sums of 8 vectors then fit the registers).
 // ---------------------------------------------------------------------------
-constexpr int kDotsPerLaunch = 4;
-
-template <typename XT, int C>
+template <typename XT, int C, int NV>
 __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int Lr, const XT* __restrict__ W,
                                                   int ld, int ncolv, VecSet vs, int nv, int voff,
                                                   double* __restrict__ part) {
@@ -476,9 +476,9 @@ __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int Lr, const XT* 
     okc[c] = cv < ncolv;
     colc[c] = cv * VEC;
   }
-  double acc[kDotsPerLaunch][C][VEC];
+  double acc[NV][C][VEC];
 #pragma unroll
-  for (int v = 0; v < kDotsPerLaunch; ++v)
+  for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
@@ -496,7 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int Lr, const XT* 
         V16<XT> w;
         w.load_nt(W + (size_t)row * ld + colc[c]);
 #pragma unroll
-        for (int v = 0; v < kDotsPerLaunch; ++v)
+        for (int v = 0; v < NV; ++v)
           if (v < nv) {
             V16<XT> x;
             x.load_nt(static_cast<const XT*>(vs.x[v]) + (size_t)row * ld + colc[c]);
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(kThreads) void k_dots(int64_t n, int Lr, const XT* 
       }
   }
 #pragma unroll
-  for (int v = 0; v < kDotsPerLaunch; ++v)
+  for (int v = 0; v < NV; ++v)
     if (v < nv)
       block_partials<C, VEC>(acc[v], red, rm, ld, vs.mult[v], part, (size_t)(voff + v) * ld,
                              (int)blockIdx.x, (int)gridDim.x);
@@ -1395,14 +1395,33 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
                        int voff, double* part, int* nblk_out) {
   int dummy = 0;
   if (!nblk_out) nblk_out = &dummy;
-  if (!geom_ok(g) || g.lges != 0 || g.ts != 0 || !W || !part || nv < 1 || nv > kDotsPerLaunch ||
+  if (!geom_ok(g) || g.lges != 0 || g.ts != 0 || !W || !part || nv < 1 || nv > kDotsWide ||
       voff < 0)
     return hipErrorInvalidValue;
   for (int v = 0; v < nv; ++v)
     if (!vs.x[v]) return hipErrorInvalidValue;
+  if (nv > kDotsPerLaunch) {
+    // the wide launch: one chunk per lane (FP32 or FP64 vectors)
+    if (g.xbytes == 4 && g.C == 1) {
+      auto fn = k_dots<float, 1, kDotsWide>;
+      const int nb = stream_grid(g, (const void*)fn);
+      *nblk_out = nb;
+      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.L,
+                         static_cast<const float*>(W), g.ld, g.ncolv, vs, nv, voff, part);
+    } else if (g.xbytes == 8 && g.C == 1) {
+      auto fn = k_dots<double, 1, kDotsWide>;
+      const int nb = stream_grid(g, (const void*)fn);
+      *nblk_out = nb;
+      hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.L,
+                         static_cast<const double*>(W), g.ld, g.ncolv, vs, nv, voff, part);
+    } else {
+      return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   if (g.xbytes == 8) {
     LD_DISPATCH_C(g.C, {
-      auto fn = k_dots<double, CC>;
+      auto fn = k_dots<double, CC, kDotsPerLaunch>;
       const int nb = stream_grid(g, (const void*)fn);
       *nblk_out = nb;
       hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.L,
@@ -1410,7 +1429,7 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
     });
   } else if (g.xbytes == 4) {
     LD_DISPATCH_C(g.C, {
-      auto fn = k_dots<float, CC>;
+      auto fn = k_dots<float, CC, kDotsPerLaunch>;
       const int nb = stream_grid(g, (const void*)fn);
       *nblk_out = nb;
       hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.L,
@@ -1418,7 +1437,7 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
     });
   } else {
     LD_DISPATCH_C(g.C, {
-      auto fn = k_dots<_Float16, CC>;
+      auto fn = k_dots<_Float16, CC, kDotsPerLaunch>;
       const int nb = stream_grid(g, (const void*)fn);
       *nblk_out = nb;
       hipLaunchKernelGGL(fn, dim3(nb), dim3(kThreads), 0, st, g.n, g.L,

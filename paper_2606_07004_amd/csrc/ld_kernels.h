@@ -172,7 +172,10 @@ hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* 
                        const double* smult = nullptr, const double* sd = nullptr);
 
 // part[voff+v][col][block] = mult_v[col] * sum_{rows of block} x_v[row][col] w[row][col],
-// v < nv <= 4
+// v < nv <= kDotsPerLaunch, or nv <= kDotsWide with one chunk per lane (FP32
+// or FP64 vectors)
+constexpr int kDotsPerLaunch = 4;
+constexpr int kDotsWide = 8;
 hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSet& vs, int nv,
                        int voff, double* part, int* nblk_out);
 

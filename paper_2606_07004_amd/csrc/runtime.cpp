@@ -495,8 +495,9 @@ size_t Run::layout(char* base) {
   smask_ = ssigns ? static_cast<uint64_t*>(take(n * (size_t)nws_ * 8)) : nullptr;
   Y_ = s_ > 0 ? static_cast<double*>(take(n * lds_ * 8)) : nullptr;
   // streaming kernels: fused product dots (2 rows of ld) and further dots
-  // launches (up to 4 rows of ld) in separate regions, kMaxBlocks each
-  size_t pe = (size_t)kMaxBlocks * (2 + 4) * ldx_;
+  // launches (up to 4 rows of ld, 8 for windows that have more than 4 older
+  // vectors) in separate regions, kMaxBlocks each
+  size_t pe = (size_t)kMaxBlocks * (2 + dots_rows()) * ldx_;
   if (s_ > 0) pe = std::max(pe, (size_t)gS_.nblk * s_ * std::max(s_, r_));
   part_elems_ = pe;
   part_ = static_cast<double*>(take(pe * 8));
@@ -925,16 +926,28 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
                         opscale_ * vscale_, &vf, nf, 0, part_, &nb, sx, smult, sd));
   LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nf * kld_ * 8,
             launch_reduce(st, part_, nb, nf * kld_, dwin_ + (size_t)(nv - nf) * kld_));
-  for (int c0 = 0; c0 < nold; c0 += 4) {
+  // more than 4 older vectors: one wide launch (up to 8) with one 16-byte
+  // chunk per lane, when a row has at most 64 chunks
+  Geom gd = kgu_;
+  int dmax = kDotsPerLaunch;
+  if (nold > kDotsPerLaunch && dots_rows() > kDotsPerLaunch) {
+    const int ncolv = kld_ / (16 / xb_);
+    const Geom g = make_geom_lc(n_, kld_, xb_, ncolv, 1);
+    if (ncolv <= 64 && geom_usable(g)) {
+      gd = g;
+      dmax = kDotsWide;
+    }
+  }
+  for (int c0 = 0; c0 < nold; c0 += dmax) {
     VecSet vs{};
-    const int nc = std::min(4, nold - c0);
+    const int nc = std::min(dmax, nold - c0);
     for (int v = 0; v < nc; ++v) {
       vs.x[v] = slot_ptr(j0 + c0 + v);
       vs.mult[v] = mult_ptr(j0 + c0 + v);
     }
     double* pp = part_ + (size_t)2 * kld_ * kMaxBlocks;
     LD_LAUNCH(LD_PROF_DOTS, (double)(nc + 1) * vec_bytes,
-              launch_dots(st, kgu_, W, vs, nc, 0, pp, &nb));
+              launch_dots(st, gd, W, vs, nc, 0, pp, &nb));
     LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nc * kld_ * 8,
               launch_reduce(st, pp, nb, nc * kld_, dwin_ + (size_t)c0 * kld_));
   }

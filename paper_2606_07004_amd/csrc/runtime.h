@@ -227,6 +227,10 @@ class Run {
   int upd_steady_nv(bool presub) const;  // update vectors of a steady-state step
   int upd_which(bool presub) const;      // tuning key of the update (window class)
   bool presub_choice(int ld) const;      // the stored step schedule of block width ld
+  // rows of partial sums a window-dots launch may write: kDotsWide when a
+  // window can hold more than kDotsPerLaunch vectors older than the two
+  // newest (FP32 and FP64 vectors), else kDotsPerLaunch
+  int dots_rows() const { return (k_ - 2 > kDotsPerLaunch && !half_) ? kDotsWide : kDotsPerLaunch; }
   double spmm_bytes(int ld, int xbytes) const;
 
   ld_matrix* a_;

@@ -96,6 +96,21 @@ def test_oslq_lap3d_windows(L, ctx, k):
     _elementwise(ref, det, 8, 1e-8)
 
 
+@pytest.mark.parametrize("prec_name,npr,k", [("FP64", 24, 10), ("MIXED", 96, 8),
+                                              ("FP64", 128, 8), ("MIXED", 256, 7)])
+def test_oslq_wide_window_dots(L, ctx, prec_name, npr, k):
+    # windows with more than four vectors older than the two newest: their
+    # inner products in one launch of up to eight, one 16-byte chunk per lane
+    # (up to 64 lanes per row: 128 FP64 or 256 FP32 probes)
+    a = W.lap2d(36, 0.05)
+    prec = getattr(L, "LD_PREC_" + prec_name)
+    vt = L.LD_VT_FP64 if prec_name == "FP64" else L.LD_VT_FP32
+    tol = 1e-6 if prec_name == "FP64" else 1e-4
+    ref, res, det = _check_oslq(L, ctx, a, npr, 8, 18, k, 4, prec=prec, vt=vt, rtol=tol)
+    if prec_name == "FP64":
+        _elementwise(ref, det, 8, 1e-8)
+
+
 def test_oslq_ragged_sizes(L, ctx):
     # n not a multiple of any tile, 7 probes (padded block of 8), odd window
     a = W.lap2d(37, 0.3)
