@@ -268,9 +268,10 @@ __device__ inline void spmm_body(int64_t n, int Lr, int lgES_arg, const int* __r
       for (int e = 0; e < VEC; ++e) dacc[v][c][e] = 0.0;
   const int nn = (int)n;  // n < 2^31
   const int nchunk = (nn + rm.rpi - 1) / rm.rpi;
-  // row tiles (ts > 0): a tile is 4 rows of ts rows, the block's wave w
-  // taking rows w ts + q rpw .. + rpw - 1 of tile t for chunk t segs + q;
-  // chunks past the last whole tile keep consecutive rows
+  // row tiles (ts > 0): tile t is the 4 ts consecutive rows from 4 t ts;
+  // for chunk t segs + q the block's wave w takes its rpw rows from
+  // 4 t ts + w ts + q rpw, so the four waves work ts rows apart; chunks past
+  // the last whole tile keep consecutive rows
   const int rpw = rm.rpi >> 2;  // rows per wave (L a power of two)
   const int segs = ts > 0 ? ts / rpw : 1;
   const int tchunks = ts > 0 ? (nn / (4 * ts)) * segs : 0;
