@@ -581,8 +581,10 @@ __global__ __launch_bounds__(kThreads) void k_rows_mat_mfma_lds(int64_t n, doubl
 // MODE >= 1: each wave assembles its 16-row output tile in LDS and writes it
 // with 16-byte stores (the rows of X0 are contiguous); otherwise element
 // stores.  MODE 2: the wave's 16-row tile of A is read once with 16-byte
-// loads into LDS (row stride lda + 1) and both uses of A read it there.  Same
-// values in every mode.
+// loads into LDS (row stride lda + 1) and both uses of A read it there; when
+// a tile is at most four 16-byte loads per lane (lda <= 32) the next tile's
+// rows, and the sign words of its first 64 residual columns, are loaded into
+// registers while the current tile is computed.  Same values in every mode.
 template <typename XT, int NT, bool MASK, int MODE>
 __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, const double* __restrict__ A,
                                                           int lda, int s, const double* __restrict__ Gd,
@@ -617,15 +619,50 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
 #pragma unroll
   for (int t = 0; t < NT; ++t) nrm_res[t] = 0.0;
   double nrm_a = 0.0;   // column l of the sketch part (l < s)
+  const int halfa = lda / 2;
+  const bool pfa = SA && 16 * halfa <= 4 * 64;
+  double2 na[4];        // the next tile's rows of A (pfa)
+  uint64_t nw[4], cw[4];  // its / this tile's sign words of residual columns 0..63
+  auto fetch = [&](int64_t r0) {
+    const int nrow = (int)min((int64_t)16, rb1 - r0);
+    const double2* src = reinterpret_cast<const double2*>(A + (size_t)r0 * lda);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = l + 64 * i;
+      if (c < nrow * halfa) na[i] = src[c];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = r0 + 4 * e + kr;
+      nw[e] = (MASK && row < rb1) ? Gmk[(size_t)row * nwg] : 0ull;
+    }
+  };
+  if (pfa && rb0 + 16 * w < rb1) fetch(rb0 + 16 * w);
   for (int64_t row0 = rb0 + 16 * w; row0 < rb1; row0 += 16 * (kThreads / 64)) {
     if constexpr (SA) {
-      const int nrow = (int)min((int64_t)16, rb1 - row0), halfa = lda / 2;
-      const double2* src = reinterpret_cast<const double2*>(A + (size_t)row0 * lda);
-      for (int c = l; c < nrow * halfa; c += 64) {
-        const double2 v = src[c];
-        const int rr = c / halfa, q = 2 * (c - rr * halfa);
-        sA[rr * sta + q] = v.x;
-        sA[rr * sta + q + 1] = v.y;
+      const int nrow = (int)min((int64_t)16, rb1 - row0);
+      if (pfa) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = l + 64 * i;
+          if (c < nrow * halfa) {
+            const int rr = c / halfa, q = 2 * (c - rr * halfa);
+            sA[rr * sta + q] = na[i].x;
+            sA[rr * sta + q + 1] = na[i].y;
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cw[e] = nw[e];
+        const int64_t next = row0 + 16 * (kThreads / 64);
+        if (next < rb1) fetch(next);
+      } else {
+        const double2* src = reinterpret_cast<const double2*>(A + (size_t)row0 * lda);
+        for (int c = l; c < nrow * halfa; c += 64) {
+          const double2 v = src[c];
+          const int rr = c / halfa, q = 2 * (c - rr * halfa);
+          sA[rr * sta + q] = v.x;
+          sA[rr * sta + q + 1] = v.y;
+        }
       }
       wave_lds_sync();
     }
@@ -671,7 +708,8 @@ __global__ __launch_bounds__(kThreads) void k_project_mfma(int64_t n, int rpb, c
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t row = row0 + 4 * e + kr;
-        wd[e] = (MASK && row < rb1) ? Gmk[(size_t)row * nwg + (t0 >> 2)] : 0ull;
+        wd[e] = (pfa && t0 == 0) ? cw[e]
+                                 : ((MASK && row < rb1) ? Gmk[(size_t)row * nwg + (t0 >> 2)] : 0ull);
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
