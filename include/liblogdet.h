@@ -277,6 +277,10 @@ ld_status ld_request_bytes(ld_matrix* a, const ld_params* p, uint64_t* bytes);
  * lane groups (L a power of two, L / E column lanes each, their sums added
  * at the row's end), which shortens the per-lane chain of dependent gathers
  * on long rows (tried when rows hold 16 entries or more on average).
+ * For OSA-IOP it also times, for the estimate block, the update of the
+ * steps that also read v1 (every other step), which keeps a geometry of its
+ * own (untuned: the update's, or fewer chunks per lane when the update's
+ * holds more than 8 elements per lane).
  * For windows of two or more ld_autotune also times the two step schedules
  * (ld_tune_result.step_presub) on its choices and keeps the schedule in
  * which the product subtracts the second-newest vector unless the other is

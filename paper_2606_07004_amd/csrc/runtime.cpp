@@ -382,6 +382,7 @@ ld_status Run::validate() {
   ps1_ = presub_choice(ld1_);
   gBp_ = krylov_geom(ldB_, 0);
   gBu_ = krylov_geom(ldB_, upd_which(psB_));
+  gBuv_ = v1_geom(ldB_, gBu_, psB_);
   g1p_ = krylov_geom(ld1_, 0);
   g1u_ = krylov_geom(ld1_, upd_which(ps1_));
   return LD_OK;
@@ -389,8 +390,9 @@ ld_status Run::validate() {
 
 // Key of a tuned geometry: block width, element bytes, matrix value type of
 // the product, kernel (0 product; 1 | class << 4 the update of a window class;
-// 2 the step schedule: {1, 0} when the update, not the product, subtracts
-// the second-newest window vector).
+// 3 | class << 4 the same update when it also reads v1 (OSA-IOP); 2 the step
+// schedule: {1, 0} when the update, not the product, subtracts the
+// second-newest window vector).
 static uint64_t tune_key(int ld, int xbytes, int vt, int which) {
   return (uint64_t)ld | ((uint64_t)xbytes << 16) | ((uint64_t)vt << 24) | ((uint64_t)which << 32);
 }
@@ -408,6 +410,31 @@ int Run::upd_which(bool presub) const {
   const int cls = nv <= 1 ? 1 : (nv == 2 ? 2 : (nv <= 4 ? 4 : 8));
   return 1 | (cls << 4);
 }
+// The OSA-IOP update that also reads v1 holds two more sets of FP64 column
+// sums per lane, so a geometry with many chunks per lane costs it occupancy:
+// it takes its own tuned geometry (key 3 | class << 4), else the plain
+// update's when that has at most 8 elements per lane, else the power-of-two
+// lanes with the fewest chunks up to 8 elements per lane.
+Geom Run::v1_geom(int ld, const Geom& gu, bool presub) const {
+  const int vt = mixed_ ? a_->vt_lo : VT_F64;
+  {
+    std::lock_guard<std::mutex> lk(a_->tune_mu);
+    auto it = a_->tune.find(tune_key(ld, xb_, vt, upd_which(presub) + 2));
+    if (it != a_->tune.end()) {
+      const Geom g = make_geom_lc(n_, ld, xb_, it->second.first, it->second.second);
+      if (geom_usable(g)) return g;
+    }
+  }
+  const int vec = 16 / xb_;
+  if (gu.C * vec <= 8) return gu;
+  const int ncolv = ld / vec;
+  const int cmax = std::max(1, 8 / vec);
+  int L = 1;
+  while (L * cmax < ncolv && L < 64) L <<= 1;
+  const Geom g = make_geom_lc(n_, ld, xb_, L, std::min(cmax, (ncolv + L - 1) / L));
+  return geom_usable(g) ? g : gu;
+}
+
 bool Run::presub_choice(int ld) const {
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
   std::lock_guard<std::mutex> lk(a_->tune_mu);
@@ -615,6 +642,7 @@ ld_status Run::begin_krylov(int phase) {
     kld_ = ldB_;
     kg_ = gBp_;
     kgu_ = gBu_;
+    kguv_ = gBuv_;
     kps_ = psB_;
     kpin_ = false;
     kfull_ = false;
@@ -624,6 +652,7 @@ ld_status Run::begin_krylov(int phase) {
     kld_ = ld1_;
     kg_ = g1p_;
     kgu_ = g1u_;
+    kguv_ = g1u_;
     kps_ = ps1_;
     kpin_ = false;
     kfull_ = !two_pass_;
@@ -633,6 +662,7 @@ ld_status Run::begin_krylov(int phase) {
     kld_ = ldB_;
     kg_ = gBp_;
     kgu_ = gBu_;
+    kguv_ = gBuv_;
     kps_ = psB_;
     kpin_ = true;
     kfull_ = false;
@@ -897,7 +927,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
       plan->red = ReduceItem{part_, 0, nf * kld_, dwin_ + (size_t)(nv - nf) * kld_};
       UpdateItem& up = plan->upd;
       up = UpdateItem{};
-      up.g = kgu_;
+      up.g = v1step ? kguv_ : kgu_;
       up.W = W;
       for (int v = 0; v < nu; ++v) {
         up.vs.x[v] = slot_ptr(upd_vec(v));
@@ -961,7 +991,8 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
     }
     const bool last = c0 + nc >= nu;
     LD_LAUNCH(LD_PROF_UPDATE, (double)(nc + 2 + ((last && v1step) ? 1 : 0)) * vec_bytes,
-              launch_update(st, kgu_, W, vs, nc, dwin_, c0, last ? 1 : 0,
+              launch_update(st, (last && v1step) ? kguv_ : kgu_, W, vs, nc, dwin_, c0,
+                            last ? 1 : 0,
                             (last && v1step) ? slot_ptr(0) : nullptr,
                             (last && v1step) ? mult_ptr(0) : nullptr, last && sym_out, part_, &nb,
                             dhole));
@@ -1391,8 +1422,10 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     std::lock_guard<std::mutex> lk(a_->tune_mu);
     for (int ld : widths) {
       a_->tune.erase(tune_key(ld, xb_, vt, 0));
-      a_->tune.erase(tune_key(ld, xb_, vt, upd_which(true)));
-      a_->tune.erase(tune_key(ld, xb_, vt, upd_which(false)));
+      for (bool ps : {true, false}) {
+        a_->tune.erase(tune_key(ld, xb_, vt, upd_which(ps)));
+        a_->tune.erase(tune_key(ld, xb_, vt, upd_which(ps) + 2));
+      }
       a_->tune.erase(tune_key(ld, xb_, vt, 2));
     }
     a_->tune_ver.fetch_add(1);
@@ -1549,9 +1582,43 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
       plain_ms = t_pp + t_pu[bun];
       presub = !(plain_ms < 0.99 * ps_ms);
     }
+    // OSA-IOP estimate runs: the update that also reads v1 (every other
+    // step), in the chosen schedule, over the update candidates
+    int bv = -1;
+    if (p_.method == LD_METHOD_OSA_IOP && wi == 0) {
+      const int nvs = upd_steady_nv(presub);
+      VecSet vv{};
+      for (int v = 0; v < nvs; ++v) {
+        vv.x[v] = v + 1 == nvs ? X : V;
+        vv.mult[v] = mult;
+      }
+      std::vector<double> tv(nc, 1e300);
+      for (int round = 0; round < 3; ++round)
+        for (int c = 0; c < nc; ++c) {
+          const Geom g = candidate_geom(n_, ld, xb_, cand[c]);
+          if (g.lges != 0 || g.xil != 0 || g.ts != 0) continue;
+          int nb = 0;
+          auto upd = [&]() {
+            return launch_update(st, g, W, vv, nvs, dcoef, 0, 1, V, mult, sym, part, &nb,
+                                 (sym && presub) ? nvs : 0);
+          };
+          LD_HIP(upd());
+          LD_HIP(hipEventRecord(ev.a, st));
+          for (int i = 0; i < reps; ++i) LD_HIP(upd());
+          LD_HIP(hipEventRecord(ev.b, st));
+          LD_HIP(hipEventSynchronize(ev.b));
+          float ms = 0.f;
+          LD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+          tv[c] = std::min(tv[c], (double)ms / reps);
+        }
+      bv = 0;
+      for (int c = 1; c < nc; ++c)
+        if (tv[c] < 0.99 * tv[bv]) bv = c;
+    }
     {
       std::lock_guard<std::mutex> lk(a_->tune_mu);
       a_->tune[tune_key(ld, xb_, vt, 0)] = cand[bp];
+      if (bv >= 0) a_->tune[tune_key(ld, xb_, vt, upd_which(presub) + 2)] = cand[bv];
       if (presub) {
         a_->tune[tune_key(ld, xb_, vt, upd_which(true))] = cand[bu];
         a_->tune.erase(tune_key(ld, xb_, vt, 2));

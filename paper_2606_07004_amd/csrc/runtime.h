@@ -227,6 +227,7 @@ class Run {
   int upd_steady_nv(bool presub) const;  // update vectors of a steady-state step
   int upd_which(bool presub) const;      // tuning key of the update (window class)
   bool presub_choice(int ld) const;      // the stored step schedule of block width ld
+  Geom v1_geom(int ld, const Geom& gu, bool presub) const;  // update geometry with v1
   // rows of partial sums a window-dots launch may write: kDotsWide when a
   // window can hold more than kDotsPerLaunch vectors older than the two
   // newest (FP32 and FP64 vectors), else kDotsPerLaunch
@@ -251,6 +252,7 @@ class Run {
   Geom gB_, gS_, g1_;
   Geom gBp_, gBu_, g1p_, g1u_;  // Krylov product / update geometries
   bool psB_ = true, ps1_ = true;  // the product subtracts the second-newest vector
+  Geom gBuv_;                     // the estimate block's update with v1 (OSA-IOP)
   // state machine
   int stage_ = 0;             // 0 prologue, 1 krylov, 2 epilogue..., see .cpp
   int t_ = 0;
@@ -271,6 +273,7 @@ class Run {
   bool sym_ready_ = false;    // the next step's second-newest window product is in dwin_
   Geom kg_, kgu_;             // product / dots-and-update geometry of the phase
   bool kps_ = true;           // the phase's product subtracts the second-newest vector
+  Geom kguv_;                 // the phase's update when it also reads v1
   void* kslots_ = nullptr;
   double* kmult_ = nullptr;
   // device buffers
