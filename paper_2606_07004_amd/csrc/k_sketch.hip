@@ -411,26 +411,44 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, c
   const bool same = TI == TJ && Xa == Xb && lda == ldb && gi == gj && ca == cb;
   // sign words: the TJ tiles of 16 columns from jb[0] lie in one 64-column word
   const int wb = jb[0] >> 6;
-#pragma unroll 4
-  for (int64_t base = r0; base < r1; base += 4) {
-    const int64_t row = base + kr;
-    const bool okr = row < r1;
-    double a[TI], bb[TJ];
+  // four groups of 4 rows per round: their loads are issued together, then
+  // the products run in row order (the same accumulation order as one group
+  // at a time)
+  constexpr int U = 4;
+  for (int64_t base = r0; base < r1; base += 4 * U) {
+    double a[U][TI], bd[U][TJ];
+    uint64_t wd[U];
 #pragma unroll
-    for (int t = 0; t < TI; ++t) a[t] = (okr && oka[t]) ? Xa[(size_t)row * lda + ia[t]] : 0.0;
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = base + 4 * u + kr;
+      const bool okr = row < r1;
 #pragma unroll
-    for (int t = 0; t < TJ; ++t)
-      bb[t] = (same && t < TI) ? a[t] : ((!MASK && okr && okb[t]) ? Xb[(size_t)row * ldb + jb[t]] : 0.0);
-    if constexpr (MASK) {
-      const uint64_t wd = okr ? Mb[(size_t)row * nwb + wb] : 0ull;
+      for (int t = 0; t < TI; ++t)
+        a[u][t] = (okr && oka[t]) ? Xa[(size_t)row * lda + ia[t]] : 0.0;
+      if constexpr (MASK) {
+        wd[u] = okr ? Mb[(size_t)row * nwb + wb] : 0ull;
+      } else {
 #pragma unroll
-      for (int t = 0; t < TJ; ++t)
-        bb[t] = (okr && okb[t]) ? (((wd >> (jb[t] & 63)) & 1ull) ? -1.0 : 1.0) : 0.0;
+        for (int t = 0; t < TJ; ++t)
+          bd[u][t] = (!same && okr && okb[t]) ? Xb[(size_t)row * ldb + jb[t]] : 0.0;
+      }
     }
 #pragma unroll
-    for (int x = 0; x < TI; ++x)
+    for (int u = 0; u < U; ++u) {
+      const bool okr = base + 4 * u + kr < r1;
+      double bb[TJ];
 #pragma unroll
-      for (int y = 0; y < TJ; ++y) acc[x][y] = mfma_f64(a[x], bb[y], acc[x][y]);
+      for (int t = 0; t < TJ; ++t) {
+        if constexpr (MASK)
+          bb[t] = (okr && okb[t]) ? (((wd[u] >> (jb[t] & 63)) & 1ull) ? -1.0 : 1.0) : 0.0;
+        else
+          bb[t] = (same && t < TI) ? a[u][t] : bd[u][t];
+      }
+#pragma unroll
+      for (int x = 0; x < TI; ++x)
+#pragma unroll
+        for (int y = 0; y < TJ; ++y) acc[x][y] = mfma_f64(a[u][x], bb[y], acc[x][y]);
+    }
   }
   if (w > 0) {
 #pragma unroll
