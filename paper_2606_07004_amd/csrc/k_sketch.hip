@@ -547,15 +547,45 @@ __global__ __launch_bounds__(kThreads) void k_rows_mat_mfma_lds(int64_t n, doubl
   const int kr = l >> 4, cl = l & 15;
   double* sT = sm + (size_t)s4 * kMfmaMaxCols + (size_t)w * 16 * st;
   const int half = ld / 2;  // 16-byte chunks per row
-  for (int64_t row0 = ((int64_t)blockIdx.x * (kThreads / 64) + w) * 16; row0 < n;
-       row0 += (int64_t)gridDim.x * (kThreads / 64) * 16) {
+  // a tile of at most four 16-byte loads per lane (ld <= 32): the wave's next
+  // tile is loaded into registers while this one is computed (a tile's rows
+  // belong to one wave, so reading them early is safe with the in-place
+  // update)
+  const bool pf = 16 * half <= 4 * 64;
+  const int64_t step = (int64_t)gridDim.x * (kThreads / 64) * 16;
+  double2 nx[4];
+  auto fetch = [&](int64_t r0) {
+    const int nr = (int)min((int64_t)16, n - r0);
+    const double2* src = reinterpret_cast<const double2*>(Y + (size_t)r0 * ld);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = l + 64 * i;
+      if (c < nr * half) nx[i] = src[c];
+    }
+  };
+  const int64_t first = ((int64_t)blockIdx.x * (kThreads / 64) + w) * 16;
+  if (pf && first < n) fetch(first);
+  for (int64_t row0 = first; row0 < n; row0 += step) {
     const int nrow = (int)min((int64_t)16, n - row0);
-    const double2* src = reinterpret_cast<const double2*>(Y + (size_t)row0 * ld);
-    for (int c = l; c < nrow * half; c += 64) {
-      const double2 v = src[c];
-      const int r = c / half, q = 2 * (c - r * half);
-      sT[r * st + q] = v.x;
-      sT[r * st + q + 1] = v.y;
+    if (pf) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = l + 64 * i;
+        if (c < nrow * half) {
+          const int r = c / half, q = 2 * (c - r * half);
+          sT[r * st + q] = nx[i].x;
+          sT[r * st + q + 1] = nx[i].y;
+        }
+      }
+      if (row0 + step < n) fetch(row0 + step);
+    } else {
+      const double2* src = reinterpret_cast<const double2*>(Y + (size_t)row0 * ld);
+      for (int c = l; c < nrow * half; c += 64) {
+        const double2 v = src[c];
+        const int r = c / half, q = 2 * (c - r * half);
+        sT[r * st + q] = v.x;
+        sT[r * st + q + 1] = v.y;
+      }
     }
     wave_lds_sync();
     dmf4 acc[4];
