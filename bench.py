@@ -615,8 +615,8 @@ def serving_bench(L, W, args):
     shift and Krylov depth, every matrix built and resident before the clock.
     Baseline: plain FP64 estimates one at a time.  Served with continuous
     batching: (i) every request submitted at t = 0 (throughput), with
-    LD_PREC_AUTO (FP32 Krylov vectors where lambda_hi <= 4096 lambda_lo, FP64
-    beyond: the served form) and with FP32 vectors on every request; (ii)
+    LD_PREC_AUTO (FP32 Krylov vectors and FP32 values where lambda_hi <= 4096
+    lambda_lo, FP64 beyond: the served form) and with FP32 on every request; (ii)
     Poisson arrivals at 0.7x the FP64 sequential rate, LD_PREC_AUTO (latency
     p50 / p99).  Every served result is compared with its own FP64 result."""
     import numpy as np
@@ -637,10 +637,11 @@ def serving_bench(L, W, args):
                 a = f.result()
                 nnz += a.nnz
                 shapes[i] = (a.n, a.nnz)
-                # FP64 storage: the mixed requests read FP64 values with FP64
-                # row sums (FP32 vectors), which keeps the ill-conditioned
-                # requests (nuggets down to 1e-3) well inside the 1e-4 gate
-                hs[i] = ctx.matrix(a, vt=L.LD_VT_FP64,
+                # FP64 values plus an FP32 copy: requests with FP32 Krylov
+                # vectors read the FP32 values (mixed precision), FP64 ones the
+                # FP64 values (LD_PREC_AUTO sends the ill-conditioned requests,
+                # nuggets down to 1e-3, to FP64)
+                hs[i] = ctx.matrix(a, vt=L.LD_VT_FP32,
                                    lo_hint=(r["shift"] if r["kind"] == "wendland" else 0.0))
                 futs[i] = None
                 del a
@@ -674,14 +675,15 @@ def serving_bench(L, W, args):
         def alg_bytes(i, res, prec):
             # the request's algorithmic bytes (the per-probe-step model: the
             # matrix once per block of probes, the window vectors read once,
-            # the new vector written once), FP64 values (the storage here)
+            # the new vector written once); FP32 values with FP32 vectors,
+            # FP64 values with FP64 vectors
             n, z = shapes[i]
             r = reqs[i]
             lo, hi = bounds[i]
             fp32 = prec == L.LD_PREC_MIXED or (prec == L.LD_PREC_AUTO and hi <= 4096 * lo)
             sx = 4 if fp32 else 8
             b = r["n_probes"]
-            step = (z * (8 + 4) + 4 * (n + 1)) / b + (r["iop_window"] + 1) * n * sx
+            step = (z * (sx + 4) + 4 * (n + 1)) / b + (r["iop_window"] + 1) * n * sx
             return res.probe_steps * step
 
         def saturate(prec):
@@ -729,8 +731,8 @@ def serving_bench(L, W, args):
             time.sleep(0.0002)
         lat = np.array(lat)
         st = L.ld_serving_stats_get(ctx.handle)
-        out.update({"served_precision": "auto (FP32 Krylov vectors where lambda_hi <= 4096 "
-                                        "lambda_lo, else FP64)",
+        out.update({"served_precision": "auto (FP32 Krylov vectors and values where lambda_hi "
+                                        "<= 4096 lambda_lo, else FP64)",
                     "served_logdets_per_s": out["served_auto"]["logdets_per_s"],
                     "speedup_vs_fp64_sequential": out["served_auto"]["speedup_vs_fp64_sequential"],
                     "max_rel_err_vs_fp64": out["served_auto"]["max_rel_err_vs_fp64"],

@@ -34,19 +34,19 @@ def _requests(L):
     return mats, reqs
 
 
-def _alone(L, mats, reqs):
+def _alone(L, mats, reqs, vt=0):
     out = []
     with L.Context(0) as c:
-        hs = [c.matrix(a) for a in mats]
+        hs = [c.matrix(a, vt=vt) for a in mats]
         for i, p in reqs:
             out.append(L.ld_estimate_ex(hs[i], p).logdet)
     return out
 
 
-def _served(L, mats, reqs, budget=0, slots=0):
+def _served(L, mats, reqs, budget=0, slots=0, vt=0):
     c = L.Context(0, max_slots=slots, hbm_budget_bytes=budget)
     try:
-        hs = [c.matrix(a) for a in mats]
+        hs = [c.matrix(a, vt=vt) for a in mats]
         tickets = [L.ld_submit(hs[i], p) for i, p in reqs]
         res = [L.ld_wait(c.handle, t) for t in tickets]
         for h in hs:
@@ -74,6 +74,32 @@ def test_served_under_tiny_budget(L):
     got = _served(L, mats, reqs, budget=60 << 20, slots=4)
     for r, g in zip(ref, got):
         assert g.logdet == r
+
+
+def test_served_fp32_values(L):
+    """Matrices with an FP32 copy of their values (the served form): FP32-
+    vector requests read the FP32 values, FP64 ones the FP64 values."""
+    print("\n[case] serving: FP32 value copies, mixed / auto / FP64 requests", flush=True)
+    mats, base = _requests(L)
+    precs = (L.LD_PREC_MIXED, L.LD_PREC_AUTO, L.LD_PREC_FP64)
+    reqs = []
+    for j, (i, p) in enumerate(base):
+        q = L.make_params(p.n_probes, p.sketch_rank, p.krylov_steps, p.iop_window, p.seed,
+                          method=p.method, precision=precs[j % 3])
+        reqs.append((i, q))
+    ref = _alone(L, mats, reqs, vt=L.LD_VT_FP32)
+    got = _served(L, mats, reqs, vt=L.LD_VT_FP32)
+    for r, g in zip(ref, got):
+        assert g.logdet == r
+    # the same requests in FP64 on FP64-only storage
+    f64 = [(i, L.make_params(p.n_probes, p.sketch_rank, p.krylov_steps, p.iop_window, p.seed,
+                             method=p.method, precision=L.LD_PREC_FP64)) for i, p in reqs]
+    exact = _alone(L, mats, f64)
+    for (i, p), g, e in zip(reqs, got, exact):
+        if p.precision == L.LD_PREC_FP64:
+            assert g.logdet == e
+        else:
+            assert abs(g.logdet - e) <= 1e-4 * abs(e), (i, p.precision, g.logdet, e)
 
 
 def test_poll_semantics_and_errors(L):
