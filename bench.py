@@ -78,12 +78,13 @@ def parse():
                     help="launches per candidate of the product/update geometry autotuner "
                          "(0 keeps the default geometry)")
     ap.add_argument("--config-geometry", action="append", default=[],
-                    help="NAME=L,C,E,I[,S]/L,C[/P]: pin the FP32-vector geometry of a full-size "
-                         "configuration leg instead of autotuning it (repeatable)")
+                    help="NAME=L,C,E,I[,S][+rg]/L,C[/P]: pin the FP32-vector geometry of a "
+                         "full-size configuration leg instead of autotuning it (repeatable)")
     ap.add_argument("--geometry", type=str, default=None,
                     help="pin the headline geometry instead of autotuning it: "
-                         "'L,C,E,I[,S]/L,C[/P]' = product lanes per row, chunks per lane, "
-                         "entry split, interleave[, row-tile stride] / update lanes per row, "
+                         "'L,C,E,I[,S][+rg]/L,C[/P]' = product lanes per row, chunks per lane, "
+                         "entry split, interleave[, row-tile stride][, row groups] / update "
+                         "lanes per row, "
                          "chunks per lane [/ step schedule: 1 the product subtracts the "
                          "second-newest window vector (default), 0 the update]")
     return ap.parse_args()
@@ -91,14 +92,16 @@ def parse():
 
 def parse_geometry(spec):
     parts = spec.split("/")
-    pv = [int(x) for x in parts[0].split(",")]
+    prod = parts[0]
+    rg = prod.endswith("+rg")
+    pv = [int(x) for x in prod[:-3 if rg else None].split(",")]
     pl, pc, pe, pi = pv[:4]
     ps = pv[4] if len(pv) > 4 else 0
     ul, uc = (int(x) for x in parts[1].split(","))
     sched = int(parts[2]) if len(parts) > 2 else 1
     return {"spmm_lanes": pl, "spmm_chunks": pc, "spmm_entry_split": pe, "spmm_interleave": pi,
-            "spmm_row_stride": ps, "update_lanes": ul, "update_chunks": uc,
-            "step_presub": sched, "pinned": True}
+            "spmm_row_stride": ps, "spmm_row_groups": int(rg), "update_lanes": ul,
+            "update_chunks": uc, "step_presub": sched, "pinned": True}
 
 
 def set_geometry(L, h, p, tune):
@@ -106,20 +109,24 @@ def set_geometry(L, h, p, tune):
                   tune["update_chunks"], spmm_entry_split=tune["spmm_entry_split"],
                   spmm_interleave=tune["spmm_interleave"],
                   spmm_row_stride=tune.get("spmm_row_stride", 0),
-                  step_presub=tune.get("step_presub", 1))
+                  step_presub=tune.get("step_presub", 1),
+                  spmm_row_groups=tune.get("spmm_row_groups", 0))
 
 
 def geometry_key(tune):
     """The geometry a PMC record was taken with: 'default', or the product's
     'L,C,E,I' (lanes, chunks, entry split, interleave), with ',S' when its
-    rows are taken in tiles of stride S and '+plain' when the update, not
-    the product, subtracts the second-newest window vector."""
+    rows are taken in tiles of stride S, '+rg' when it reads the matrix's row
+    groups and '+plain' when the update, not the product, subtracts the
+    second-newest window vector."""
     if not tune:
         return "default"
     key = (f"{tune['spmm_lanes']},{tune['spmm_chunks']},{tune['spmm_entry_split']},"
            f"{tune['spmm_interleave']}")
     if tune.get("spmm_row_stride", 0):
         key += f",{tune['spmm_row_stride']}"
+    if tune.get("spmm_row_groups", 0):
+        key += "+rg"
     if not tune.get("step_presub", 1):
         key += "+plain"
     return key
@@ -427,7 +434,9 @@ def configs_bench(L, W, args):
                                                if tune else "default")
                     prod["step_presub"] = tune.get("step_presub", 1) if tune else 1
                     prod["interleaved"] = tune["spmm_interleave"] if tune else 0
-                    kname = f"ld::k_spmm<float, float, {tune['spmm_chunks'] if tune else 0}, "
+                    prod["row_groups"] = tune.get("spmm_row_groups", 0) if tune else 0
+                    kname = (f"ld::k_spmm_rg<{tune['spmm_chunks']}, " if prod["row_groups"] else
+                             f"ld::k_spmm<float, float, {tune['spmm_chunks'] if tune else 0}, ")
                     ks = [v for kn, v in (pr or {}).get("geometries", {}).get(geo, {}).items()
                           if kn.startswith(kname)]
                     if ks:

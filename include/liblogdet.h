@@ -289,6 +289,16 @@ ld_status ld_request_bytes(ld_matrix* a, const ld_params* p, uint64_t* bytes);
  * spmm_row_stride), which ld_autotune tries on every power-of-two L with the
  * strides of the matrix's most frequent column offsets (at most two, each in
  * a quarter of the sampled rows or more).
+ * Matrices created with LD_VT_FP32 whose groups of 4 consecutive rows share
+ * most of their columns (at least 2 entries per column of the group's
+ * union, as on covariance matrices of sorted points) also keep those groups:
+ * the union of the 4 rows' columns with one FP32 value per row and column
+ * (zero where a row has no entry), about (4 + 16) bytes per union column.
+ * The product of FP32 Krylov vectors can then gather each union column's
+ * probe row once for the 4 rows (spmm_row_groups; the untuned default on
+ * such matrices, with one chunk per lane), which ld_autotune tries in every
+ * plain geometry of at most 2 chunks per lane; a row's sum sees its nonzero
+ * terms in CSR order, so the product's output is the CSR product's.
  * ld_autotune times every such (L, C, E) with L a power of two and at most
  * half a row of idle chunks on this matrix, and L = ceil(chunks / C) where
  * that is not a power of two, for the probe-block shapes and
@@ -325,6 +335,7 @@ typedef struct {
                               * update subtracts the whole window           */
   double step_presub_ms;     /* product + update per step, schedule 1       */
   double step_plain_ms;      /* the same, schedule 0 (0 for windows of 1)   */
+  int32_t spmm_row_groups;   /* 1: the product reads the matrix's row groups */
 } ld_tune_result;
 ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_result* out);
 /* Stores a given geometry for the estimate block of `p` on this matrix (a
@@ -340,13 +351,17 @@ ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_re
  * the plain order), the update likewise (no split, interleaved; stored for
  * the window class of `p`), with the step schedule step_presub (1: the
  * product subtracts the second-newest window vector, the default; 0: the
- * update subtracts the whole window; see ld_tune_result).  Any (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8},
+ * update subtracts the whole window; see ld_tune_result), and the product
+ * over the matrix's row groups (spmm_row_groups 1: FP32 Krylov vectors on a
+ * matrix that keeps them, C <= 2, no entry split, no row tiles) or its CSR
+ * rows (0).  Any (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8},
  * E <= L, C <= 2 when E > 1, and (L / E) * C chunks covering the block is
  * accepted, where L is a power of two when E > 1; anything else is
  * LD_E_INVALID_ARG and stores nothing. */
 ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
                       int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks,
-                      int32_t spmm_interleave, int32_t spmm_row_stride, int32_t step_presub);
+                      int32_t spmm_interleave, int32_t spmm_row_stride, int32_t step_presub,
+                      int32_t spmm_row_groups);
 
 /* Serving with continuous batching: queue a request and return at once with
  * a ticket.  Requests are admitted as resident slots and HBM budget free up;

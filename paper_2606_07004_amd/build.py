@@ -17,7 +17,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "liblogdet.so")
 OBJ_DIR = os.path.join(OUT_DIR, "obj")
 
-SOURCES = ["k_stream.hip", "k_sketch.hip", "k_small.hip", "runtime.cpp", "serve.cpp"]
+SOURCES = ["k_stream.hip", "k_rowgroup.hip", "k_sketch.hip", "k_small.hip", "runtime.cpp", "serve.cpp"]
 
 # Packed FP32 instructions are disabled for all device code (the compiler
 # would otherwise form them from scalar float arithmetic).

@@ -1,0 +1,302 @@
+// Row-group sparse product W = opscale * (Q X) * diag(xmult) for FP32 values
+// and FP32 probe blocks (Alg 1's operator application, as in the CSR product
+// of k_stream.hip, over the matrix's row groups).
+//
+// A group is kRowGroup consecutive rows with the sorted union of their
+// columns and, per union column, one value per row (zero where the row has
+// no entry).  The group's L lanes gather each union column's probe row once
+// and multiply it into every row of the group: on covariance-like matrices,
+// whose neighbouring rows share most of their columns, the gathers (and the
+// bytes the L1 returns to the lanes, which bound that product) drop by the
+// ratio of entries to union columns.  A row's sum sees its own nonzero terms
+// in CSR order (a zero value adds an exact zero), so W is the CSR product's
+// W; the epilogue (scaling, early subtraction, store, fused inner products)
+// is the CSR product's, per row.
+#include "ld_kernels.h"
+
+namespace ld {
+
+struct RgDesc {
+  int64_t n;
+  const int* gp;
+  const int* col;
+  const float* val;
+  const float* X;
+  float* W;
+  const double* xmult;
+  double opscale;
+  const float* fx[2];
+  const double* fmult[2];
+  double* part;
+  int L, ld, ncolv, voff, il;
+  const float* sx;
+  const double* smult;
+  const double* sd;
+};
+
+template <int C, int NF>
+__device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
+  constexpr int VEC = V16<float>::N;
+  constexpr int G = kRowGroup;
+  static_assert(G == 4, "one float4 of values per union column");
+  constexpr bool FUSED = NF > 0;
+  // one fused product: per-thread FP64 sums in the thread's LDS slots; two:
+  // in registers (as in the CSR product)
+  constexpr bool LDSACC = NF == 1;
+  constexpr int ND = (FUSED && !LDSACC) ? NF : 1;
+  // union entries whose (column, values) a lane loads per round (four with
+  // one chunk per lane: fewer rounds of dependent entry loads per group)
+  constexpr int KE = C == 1 ? 4 : 2;
+  __shared__ double red[FUSED ? kThreads * VEC * C : 1];
+  __shared__ float scs[kMaxLd];   // opscale * xmult[col]
+  __shared__ double scf[kMaxLd];  // sd[col] * smult[col] (early subtraction)
+  const RowMap rm = RowMap::lanes(q.L, 0);
+  const int ld = q.ld;
+  for (int i = threadIdx.x; i < ld; i += kThreads) {
+    scs[i] = float(q.opscale * (q.xmult ? q.xmult[i] : 1.0));
+    if (q.sx) scf[i] = q.sd[i] * (q.smult ? q.smult[i] : 1.0);
+  }
+  bool okc[C];
+  int colc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int cv = rm.cl + rm.Lc * c;
+    okc[c] = cv < q.ncolv;
+    colc[c] = cv * VEC;
+    if constexpr (LDSACC) {
+      if (rm.on)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) red[red_slot<C, VEC>(rm, c, e)] = 0.0;
+    }
+  }
+  __syncthreads();
+  double dacc[ND][C][VEC];
+#pragma unroll
+  for (int v = 0; v < ND; ++v)
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) dacc[v][c][e] = 0.0;
+  const int nn = (int)q.n;  // n < 2^31
+  const int ng = (nn + G - 1) / G;
+  const int nchunk = (ng + rm.rpi - 1) / rm.rpi;
+  const float4* vals = reinterpret_cast<const float4*>(q.val);
+  for (int j = 0; j * nbk < nchunk; ++j) {
+    const int ch = q.il ? j * nbk + bk : chunk_of(j, bk, nbk);
+    const int grp = ch * rm.rpi + rm.rg;
+    if (!rm.on || ch >= nchunk || grp >= ng) continue;
+    const int r0 = grp * G;
+    float acc[G][C][VEC];
+#pragma unroll
+    for (int r = 0; r < G; ++r)
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[r][c][e] = 0.0f;
+    // one union column into the group's rows
+    auto add = [&](const V16<float> (&x)[C], float4 a) {
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        if (okc[c]) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            acc[0][c][e] = fmaf(a.x, x[c].v[e], acc[0][c][e]);
+            acc[1][c][e] = fmaf(a.y, x[c].v[e], acc[1][c][e]);
+            acc[2][c][e] = fmaf(a.z, x[c].v[e], acc[2][c][e]);
+            acc[3][c][e] = fmaf(a.w, x[c].v[e], acc[3][c][e]);
+          }
+        }
+    };
+    auto bcast = [&](float4 v, int src) {
+      float4 o;
+      o.x = __shfl(v.x, src);
+      o.y = __shfl(v.y, src);
+      o.z = __shfl(v.z, src);
+      o.w = __shfl(v.w, src);
+      return o;
+    };
+    const int ub = q.gp[grp], ue = q.gp[grp + 1];
+    // the group's L lanes load KE * L consecutive union entries per round,
+    // lane l holding entries l, l + L, ..., and pass them around the group
+    // by lane shuffles; two entries' gathers in flight, in union order
+    for (int base = ub; base < ue; base += rm.L * KE) {
+      int myc[KE];
+      float4 myv[KE];
+#pragma unroll
+      for (int u = 0; u < KE; ++u) {
+        const int kk = base + rm.gl + rm.L * u;
+        myc[u] = r0;
+        myv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (kk < ue) {
+          myc[u] = q.col[kk];
+          myv[u] = vals[kk];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < KE; ++u) {
+        const int cnt = min(rm.L, ue - base - rm.L * u);
+        if (cnt <= 0) break;
+        int e = 0;
+        for (; e + 2 <= cnt; e += 2) {
+          const int c0 = __shfl(myc[u], rm.lb + e), c1 = __shfl(myc[u], rm.lb + e + 1);
+          const float4 a0 = bcast(myv[u], rm.lb + e), a1 = bcast(myv[u], rm.lb + e + 1);
+          V16<float> x0[C], x1[C];
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+            if (okc[c]) {
+              x0[c].load(q.X + (size_t)c0 * ld + colc[c]);
+              x1[c].load(q.X + (size_t)c1 * ld + colc[c]);
+            }
+          add(x0, a0);
+          add(x1, a1);
+        }
+        if (e < cnt) {
+          const int c0 = __shfl(myc[u], rm.lb + e);
+          const float4 a0 = bcast(myv[u], rm.lb + e);
+          V16<float> x0[C];
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+            if (okc[c]) x0[c].load(q.X + (size_t)c0 * ld + colc[c]);
+          add(x0, a0);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const int row = r0 + r;
+      if (row >= nn) break;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        if (okc[c]) {
+          V16<float> out;
+          const float* sce = scs + colc[c];
+          if (q.sx) {
+            V16<float> xs;
+            xs.load_nt(q.sx + (size_t)row * ld + colc[c]);  // read once per step
+            const double* cfe = scf + colc[c];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+              out.v[e] = float(fma(-cfe[e], double(xs.v[e]), double(acc[r][c][e] * sce[e])));
+          } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) out.v[e] = acc[r][c][e] * sce[e];
+          }
+          out.store_nt(q.W + (size_t)row * ld + colc[c]);
+          if constexpr (FUSED) {
+            // the newest window vector is X itself: the row's value is read
+            // again (the group's gathers do not keep it)
+            V16<float> xd;
+            xd.load(q.X + (size_t)row * ld + colc[c]);
+            if constexpr (LDSACC) {
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) {
+                double& slot = red[red_slot<C, VEC>(rm, c, e)];
+                slot = fma(double(xd.v[e]), double(out.v[e]), slot);
+              }
+            } else {
+#pragma unroll
+              for (int v = 0; v < NF; ++v) {
+                V16<float> x;
+                if (v == NF - 1)
+                  x = xd;
+                else
+                  x.load(q.fx[v] + (size_t)row * ld + colc[c]);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                  dacc[v][c][e] = fma(double(x.v[e]), double(out.v[e]), dacc[v][c][e]);
+              }
+            }
+          }
+        }
+    }
+  }
+  if constexpr (LDSACC) {
+    __syncthreads();
+    red_partials<C, VEC>(red, rm, ld, q.fmult[0], q.part, (size_t)q.voff * ld, bk, nbk);
+  } else if constexpr (FUSED) {
+#pragma unroll
+    for (int v = 0; v < NF; ++v)
+      block_partials<C, VEC>(dacc[v], red, rm, ld, q.fmult[v], q.part, (size_t)(q.voff + v) * ld,
+                             bk, nbk);
+  }
+}
+
+// blocks per CU at which every instance fits its registers without spills
+template <int C, int NF>
+constexpr int rg_min_blocks() {
+  return C == 1 ? (NF == 2 ? 4 : 5) : (NF == 2 ? 3 : 4);
+}
+
+template <int C, int NF>
+__global__ __launch_bounds__(kThreads, (rg_min_blocks<C, NF>())) void k_spmm_rg(
+    BatchArgs<RgDesc> bt) {
+  int r = 0;
+  while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
+  rg_body<C, NF>(bt.d[r], (int)blockIdx.x - bt.off[r], bt.off[r + 1] - bt.off[r]);
+}
+
+template <int C, int NF>
+static hipError_t rg_launch(hipStream_t st, SpmmItem* items, const int* idx, int cnt) {
+  auto fn = k_spmm_rg<C, NF>;
+  BatchArgs<RgDesc> bt{};
+  bt.count = cnt;
+  int off = 0;
+  for (int q = 0; q < cnt; ++q) {
+    SpmmItem& it = items[idx[q]];
+    const int nb = stream_grid(it.g, (const void*)fn);
+    it.nblk = nb;
+    RgDesc& d = bt.d[q];
+    d.n = it.g.n;
+    d.gp = it.rg.gp;
+    d.col = it.rg.col;
+    d.val = it.rg.val;
+    d.X = static_cast<const float*>(it.X);
+    d.W = static_cast<float*>(it.W);
+    d.xmult = it.xmult;
+    d.opscale = it.opscale;
+    for (int v = 0; v < 2; ++v) {
+      d.fx[v] = v < it.nf ? static_cast<const float*>(it.fused.x[v]) : nullptr;
+      d.fmult[v] = v < it.nf ? it.fused.mult[v] : nullptr;
+    }
+    d.part = it.part;
+    d.L = it.g.L;
+    d.ld = it.g.ld;
+    d.ncolv = it.g.ncolv;
+    d.voff = it.voff;
+    d.il = it.g.xil;
+    d.sx = static_cast<const float*>(it.sx);
+    d.smult = it.smult;
+    d.sd = it.sd;
+    bt.off[q] = off;
+    off += nb;
+  }
+  bt.off[cnt] = off;
+  hipLaunchKernelGGL(fn, dim3(off), dim3(kThreads), 0, st, bt);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm_rg_group(hipStream_t st, SpmmItem* items, const int* idx, int cnt) {
+  if (!items || !idx || cnt < 1 || cnt > kMaxBatch) return hipErrorInvalidValue;
+  const SpmmItem& it = items[idx[0]];
+  for (int q = 0; q < cnt; ++q) {
+    const SpmmItem& x = items[idx[q]];
+    if (!x.g.rg || x.g.xbytes != 4 || x.vt != VT_F32 || x.g.C != it.g.C || x.nf != it.nf ||
+        x.g.lges != 0 || x.g.ts != 0 || !x.rg.gp || !x.rg.col || !x.rg.val ||
+        reinterpret_cast<uintptr_t>(x.rg.val) % 16 != 0)
+      return hipErrorInvalidValue;
+  }
+  const int C = it.g.C, nf = it.nf;
+  if (C == 1) {
+    if (nf == 0) return rg_launch<1, 0>(st, items, idx, cnt);
+    if (nf == 1) return rg_launch<1, 1>(st, items, idx, cnt);
+    return rg_launch<1, 2>(st, items, idx, cnt);
+  }
+  if (C == 2) {
+    if (nf == 0) return rg_launch<2, 0>(st, items, idx, cnt);
+    if (nf == 1) return rg_launch<2, 1>(st, items, idx, cnt);
+    return rg_launch<2, 2>(st, items, idx, cnt);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ld

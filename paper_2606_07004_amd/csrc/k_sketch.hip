@@ -479,14 +479,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm_tn_mfma(int64_t n, int rpb, c
 // the update is in place.
 constexpr int kMfmaMaxCols = 64;
 
-// Ordering of LDS accesses between lanes of one wave (a wave's LDS
-// instructions run in order; this keeps the compiler from moving them).
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __global__ __launch_bounds__(kThreads) void k_rows_mat_mfma(int64_t n, double* __restrict__ Y, int ld,
                                                            int s, const double* __restrict__ M,
                                                            int sout) {

@@ -101,102 +101,6 @@ __global__ __launch_bounds__(kThreads) void k_gaussian(uint64_t seed, const uint
 }
 
 // ---------------------------------------------------------------------------
-// Row mapping shared by the streaming kernels.  Rows are swept in chunks of
-// RPI = 256 / L consecutive rows; block b takes chunks b, b + nblk, ... so the
-// whole grid advances through the matrix in order (the rows in flight, and
-// the probe-vector rows their sparse entries gather, stay within a window
-// that the memory-side cache holds).  Inside a chunk L lanes share a row
-// and each lane owns C 16-byte chunks of the row's probe vector (chunk c of
-// lane l is chunk l + L*c), so L*C chunks cover ld columns with few idle
-// lanes (96 FP32 probes: L = 8, C = 3).  Per-block partial sums are stored
-// transposed, part[i][block], so the reduction reads contiguous memory.
-// ---------------------------------------------------------------------------
-// With an entry split ES = 2^lgES (the product only) the L lanes of a row
-// form ES groups of Lc = L / ES column lanes; group eg takes every ES-th
-// sparse entry of the row and the groups' sums are added at the row's end.
-// Without an entry split L need not be a power of two (12 lanes for the 12
-// chunks of 96 FP16 probes instead of 16 with 4 idle): rows never straddle a
-// wave, each wave holds 64 / L rows and its last 64 mod L lanes are idle
-// (on = false).  lb is the wave lane of the row's first lane.
-struct RowMap {
-  int lg, L, rpi, rg, gl, Lc, cl, eg, lb;
-  bool on;
-  __device__ RowMap(int lgL, int lgES = 0) : lg(lgL), L(1 << lgL), rpi(kThreads >> lgL) {
-    rg = (int)threadIdx.x >> lg;
-    gl = (int)threadIdx.x & (L - 1);
-    Lc = L >> lgES;
-    cl = gl & (Lc - 1);
-    eg = lgES ? gl >> (lgL - lgES) : 0;
-    lb = ((int)threadIdx.x & 63) & ~(L - 1);
-    on = true;
-  }
-  // any 1 <= L <= 64 (no entry split unless L is a power of two)
-  __device__ static RowMap lanes(int L, int lgES) {
-    if ((L & (L - 1)) == 0) return RowMap(__builtin_ctz((unsigned)L), lgES);
-    RowMap m(0);
-    const int rpw = 64 / L, lane = (int)threadIdx.x & 63, rw = lane / L;
-    m.lg = -1;
-    m.L = L;
-    m.rpi = (kThreads / 64) * rpw;
-    m.on = rw < rpw;
-    m.rg = ((int)threadIdx.x >> 6) * rpw + (m.on ? rw : 0);
-    m.gl = lane - rw * L;
-    m.Lc = L;
-    m.cl = m.gl;
-    m.eg = 0;
-    m.lb = rw * L;
-    return m;
-  }
-};
-
-// Chunk taken by this block in round j.  The grid is at most one resident
-// wave of blocks and, from 8 blocks up, a multiple of 8; blocks are placed
-// round-robin on the 8 XCDs (block b on XCD b % 8), so in every round XCD x
-// gets one contiguous band of the round's chunks: rows a few chunks apart
-// (the +-N neighbours of a stencil) then share that XCD's L2.
-__device__ inline int chunk_of(int j, int b, int nb) {
-  const int base = j * nb;
-  return (nb & 7) ? base + b : base + (b & 7) * (nb >> 3) + (b >> 3);
-}
-
-// Column sums of the per-thread slots red[rg][c][gl][e] over the row groups
-// of the block, stored as the block's partial sums (times mult[col]).
-template <int C, int VEC>
-__device__ inline void red_partials(const double* red, const RowMap& rm, int ld, const double* mult,
-                                    double* part, size_t row0, int bk, int nbk) {
-  const int WC = rm.Lc * C * VEC;
-  for (int i = threadIdx.x; i < WC; i += kThreads) {
-    double sum = 0.0;
-    for (int q = 0; q < rm.rpi; ++q) sum += red[q * WC + i];
-    if (i < ld) part[(row0 + i) * nbk + bk] = sum * (mult ? mult[i] : 1.0);
-  }
-  __syncthreads();
-}
-
-// Slot of thread (rg, cl) for chunk c, element e in a [rpi][C*Lc*VEC] array
-// (the slot index within a row group is the column).
-template <int C, int VEC>
-__device__ inline int red_slot(const RowMap& rm, int c, int e) {
-  return rm.rg * (rm.Lc * C * VEC) + (c * rm.Lc + rm.cl) * VEC + e;
-}
-
-// Sum the per-lane accumulators of one vector over the row groups of the
-// block and store the block's partial sums (times mult[col]).
-template <int C, int VEC>
-__device__ inline void block_partials(const double (&acc)[C][VEC], double* red, const RowMap& rm,
-                                      int ld, const double* mult, double* part, size_t row0, int bk,
-                                      int nbk) {
-  if (rm.eg == 0 && rm.on) {
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) red[red_slot<C, VEC>(rm, c, e)] = acc[c][e];
-  }
-  __syncthreads();
-  red_partials<C, VEC>(red, rm, ld, mult, part, row0, bk, nbk);
-}
-
-// ---------------------------------------------------------------------------
 // CSR x probe block, with up to two window inner products fused into the
 // epilogue (NF of them).  The newest window vector is the product's own
 // input: its value on the row comes from the gathered diagonal entry (every
@@ -1013,7 +917,8 @@ static bool geom_ok(const Geom& g) {
          (g.lges == 0 || g.C <= 2) &&
          (g.L >> g.lges) * g.C >= g.ncolv && g.nblk >= 1 && (int64_t)g.nblk * g.rpb >= g.n &&
          g.ts >= 0 && g.ts <= kMaxRowStride &&
-         (g.ts == 0 || ((1 << g.lgL) == g.L && g.ts % (64 / g.L) == 0));
+         (g.ts == 0 || ((1 << g.lgL) == g.L && g.ts % (64 / g.L) == 0)) &&
+         (g.rg == 0 || (g.rg == 1 && g.lges == 0 && g.ts == 0 && g.C <= 2 && g.xbytes == 4));
 }
 
 // Resident 256-thread blocks of a kernel on the whole device (cached).
@@ -1037,9 +942,12 @@ static int resident_blocks(const void* fn) {
 
 // Grid of a chunk-sweeping kernel: at most one resident wave of blocks, a
 // multiple of 8 from 8 blocks up (see chunk_of).
-static int stream_grid(const Geom& g, const void* fn) {
+int stream_grid(const Geom& g, const void* fn) {
   const int rpi = rows_per_block(g.L);
-  const int64_t nchunk = (g.n + rpi - 1) / rpi;
+  // a row-group product sweeps groups of kRowGroup rows the way the others
+  // sweep rows
+  const int64_t units = g.rg ? (g.n + kRowGroup - 1) / kRowGroup : g.n;
+  const int64_t nchunk = (units + rpi - 1) / rpi;
   int64_t nb = std::min<int64_t>(nchunk, resident_blocks(fn));
   if (nb >= 8) nb &= ~int64_t(7);
   return (int)std::max<int64_t>(1, nb);
@@ -1269,6 +1177,7 @@ static bool spmm_item_ok(const SpmmItem& it) {
     if (!it.fused.x[v] || it.fused.x[v] == it.W) return false;
   if (it.nf > 0 && it.fused.x[it.nf - 1] != it.X) return false;  // newest vector = the input
   if (it.sx && (!it.sd || it.sx == it.W || it.sx == it.X)) return false;
+  if (g.rg && (!it.rg.gp || !it.rg.col || !it.rg.val || it.vt != VT_F32)) return false;
   return true;
 }
 
@@ -1341,10 +1250,12 @@ hipError_t launch_spmm_batch(hipStream_t st, SpmmItem* items, int count) {
     if (!spmm_item_ok(items[a])) return hipErrorInvalidValue;
   auto key = [](const SpmmItem& it) -> uint64_t {
     return (uint64_t)it.g.xbytes | ((uint64_t)it.vt << 8) | ((uint64_t)it.g.C << 16) |
-           ((uint64_t)it.nf << 24) | ((uint64_t)(it.g.lges > 0) << 32);
+           ((uint64_t)it.nf << 24) | ((uint64_t)(it.g.lges > 0) << 32) |
+           ((uint64_t)it.g.rg << 33);
   };
   return launch_grouped(items, count, key, [&](const int* idx, int cnt) -> hipError_t {
     const SpmmItem& it = items[idx[0]];
+    if (it.g.rg) return launch_spmm_rg_group(st, items, idx, cnt);
     if (it.g.xbytes == 8) {
       if (it.vt == VT_F64) return spmm_launch_typed<double, double>(st, it.g.C, it.nf, items, idx, cnt);
       if (it.vt == VT_F32) return spmm_launch_typed<float, double>(st, it.g.C, it.nf, items, idx, cnt);
@@ -1366,8 +1277,10 @@ hipError_t launch_spmm_batch(hipStream_t st, SpmmItem* items, int count) {
 hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* ci, const void* va,
                        int vt, const void* X, void* W, const double* xmult, double opscale,
                        const VecSet* fused, int nf, int voff, double* part, int* nblk_out,
-                       const void* sx, const double* smult, const double* sd) {
+                       const void* sx, const double* smult, const double* sd,
+                       const RowGroups* rg) {
   SpmmItem it{};
+  if (rg) it.rg = *rg;
   it.g = g;
   it.rp = rp;
   it.ci = ci;
@@ -1396,7 +1309,7 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
                        int voff, double* part, int* nblk_out) {
   int dummy = 0;
   if (!nblk_out) nblk_out = &dummy;
-  if (!geom_ok(g) || g.lges != 0 || g.ts != 0 || !W || !part || nv < 1 || nv > kDotsWide ||
+  if (!geom_ok(g) || g.lges != 0 || g.ts != 0 || g.rg != 0 || !W || !part || nv < 1 || nv > kDotsWide ||
       voff < 0)
     return hipErrorInvalidValue;
   for (int v = 0; v < nv; ++v)
@@ -1450,7 +1363,7 @@ hipError_t launch_dots(hipStream_t st, const Geom& g, const void* W, const VecSe
 
 static bool update_item_ok(const UpdateItem& it) {
   const Geom& g = it.g;
-  if (!geom_ok(g) || g.lges != 0 || g.ts != 0 || g.ld > kMaxLd || !it.W || !it.d || it.nv < 0 ||
+  if (!geom_ok(g) || g.lges != 0 || g.ts != 0 || g.rg != 0 || g.ld > kMaxLd || !it.W || !it.d || it.nv < 0 ||
       it.nv > kMaxNv || (it.nv > 4 && g.xbytes == 2) ||
       (it.want_norm && !it.part) || (it.v1 && !it.v1mult) || (it.sym && !it.want_norm) ||
       it.dhole < 0 || it.dhole > it.nv)

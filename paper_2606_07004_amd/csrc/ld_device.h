@@ -113,6 +113,14 @@ template <> struct V16<_Float16> {
   }
 };
 
+// Ordering of LDS accesses between lanes of one wave (a wave's LDS
+// instructions run in order; this keeps the compiler from moving them).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Vectors handed to the multi-vector streaming kernels.  x[v] is a block of
 // the same [n][ld] layout as the output; mult[v][col] (may be null -> 1) is
 // the per-column factor that turns the stored block into the basis vector.
@@ -120,5 +128,101 @@ struct VecSet {
   const void* x[kMaxNv];
   const double* mult[kMaxNv];
 };
+
+// ---------------------------------------------------------------------------
+// Row mapping shared by the streaming kernels.  Rows are swept in chunks of
+// RPI = 256 / L consecutive rows; block b takes chunks b, b + nblk, ... so the
+// whole grid advances through the matrix in order (the rows in flight, and
+// the probe-vector rows their sparse entries gather, stay within a window
+// that the memory-side cache holds).  Inside a chunk L lanes share a row
+// and each lane owns C 16-byte chunks of the row's probe vector (chunk c of
+// lane l is chunk l + L*c), so L*C chunks cover ld columns with few idle
+// lanes (96 FP32 probes: L = 8, C = 3).  Per-block partial sums are stored
+// transposed, part[i][block], so the reduction reads contiguous memory.
+// ---------------------------------------------------------------------------
+// With an entry split ES = 2^lgES (the product only) the L lanes of a row
+// form ES groups of Lc = L / ES column lanes; group eg takes every ES-th
+// sparse entry of the row and the groups' sums are added at the row's end.
+// Without an entry split L need not be a power of two (12 lanes for the 12
+// chunks of 96 FP16 probes instead of 16 with 4 idle): rows never straddle a
+// wave, each wave holds 64 / L rows and its last 64 mod L lanes are idle
+// (on = false).  lb is the wave lane of the row's first lane.
+struct RowMap {
+  int lg, L, rpi, rg, gl, Lc, cl, eg, lb;
+  bool on;
+  __device__ RowMap(int lgL, int lgES = 0) : lg(lgL), L(1 << lgL), rpi(kThreads >> lgL) {
+    rg = (int)threadIdx.x >> lg;
+    gl = (int)threadIdx.x & (L - 1);
+    Lc = L >> lgES;
+    cl = gl & (Lc - 1);
+    eg = lgES ? gl >> (lgL - lgES) : 0;
+    lb = ((int)threadIdx.x & 63) & ~(L - 1);
+    on = true;
+  }
+  // any 1 <= L <= 64 (no entry split unless L is a power of two)
+  __device__ static RowMap lanes(int L, int lgES) {
+    if ((L & (L - 1)) == 0) return RowMap(__builtin_ctz((unsigned)L), lgES);
+    RowMap m(0);
+    const int rpw = 64 / L, lane = (int)threadIdx.x & 63, rw = lane / L;
+    m.lg = -1;
+    m.L = L;
+    m.rpi = (kThreads / 64) * rpw;
+    m.on = rw < rpw;
+    m.rg = ((int)threadIdx.x >> 6) * rpw + (m.on ? rw : 0);
+    m.gl = lane - rw * L;
+    m.Lc = L;
+    m.cl = m.gl;
+    m.eg = 0;
+    m.lb = rw * L;
+    return m;
+  }
+};
+
+// Chunk taken by this block in round j.  The grid is at most one resident
+// wave of blocks and, from 8 blocks up, a multiple of 8; blocks are placed
+// round-robin on the 8 XCDs (block b on XCD b % 8), so in every round XCD x
+// gets one contiguous band of the round's chunks: rows a few chunks apart
+// (the +-N neighbours of a stencil) then share that XCD's L2.
+__device__ inline int chunk_of(int j, int b, int nb) {
+  const int base = j * nb;
+  return (nb & 7) ? base + b : base + (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// Column sums of the per-thread slots red[rg][c][gl][e] over the row groups
+// of the block, stored as the block's partial sums (times mult[col]).
+template <int C, int VEC>
+__device__ inline void red_partials(const double* red, const RowMap& rm, int ld, const double* mult,
+                                    double* part, size_t row0, int bk, int nbk) {
+  const int WC = rm.Lc * C * VEC;
+  for (int i = threadIdx.x; i < WC; i += kThreads) {
+    double sum = 0.0;
+    for (int q = 0; q < rm.rpi; ++q) sum += red[q * WC + i];
+    if (i < ld) part[(row0 + i) * nbk + bk] = sum * (mult ? mult[i] : 1.0);
+  }
+  __syncthreads();
+}
+
+// Slot of thread (rg, cl) for chunk c, element e in a [rpi][C*Lc*VEC] array
+// (the slot index within a row group is the column).
+template <int C, int VEC>
+__device__ inline int red_slot(const RowMap& rm, int c, int e) {
+  return rm.rg * (rm.Lc * C * VEC) + (c * rm.Lc + rm.cl) * VEC + e;
+}
+
+// Sum the per-lane accumulators of one vector over the row groups of the
+// block and store the block's partial sums (times mult[col]).
+template <int C, int VEC>
+__device__ inline void block_partials(const double (&acc)[C][VEC], double* red, const RowMap& rm,
+                                      int ld, const double* mult, double* part, size_t row0, int bk,
+                                      int nbk) {
+  if (rm.eg == 0 && rm.on) {
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) red[red_slot<C, VEC>(rm, c, e)] = acc[c][e];
+  }
+  __syncthreads();
+  red_partials<C, VEC>(red, rm, ld, mult, part, row0, bk, nbk);
+}
 
 }  // namespace ld

@@ -45,12 +45,28 @@ struct Geom {
                    // per wave (64 / L): the block's 4 waves take rows S apart (one
                    // tile of 4 rows of S rows), so a stencil's +-S neighbours of
                    // one wave's rows are the rows its sibling waves gather
+  int rg = 0;      // product only: 1 = the matrix's row groups (RowGroups below)
+                   // instead of its CSR rows; FP32 values and vectors, C <= 2,
+                   // no entry split, no row tiles
 };
 Geom make_geom(int64_t n, int ld, int xbytes);
 // The same with an explicit lanes-per-row L and chunks per lane C (an
 // autotuned choice); geom_usable tells whether it covers ld.
 Geom make_geom_lc(int64_t n, int ld, int xbytes, int L, int C);
 bool geom_usable(const Geom& g);
+
+// Row groups of a CSR matrix: rows kRowGroup g .. kRowGroup g + kRowGroup - 1
+// form group g; its entries are the sorted union of the rows' columns,
+// col[gp[g] .. gp[g+1]), and for each union column u the kRowGroup values
+// val[kRowGroup u + r] of row r (zero where the row has no entry there).
+// One gather of a neighbour's probe row then serves every row of the group
+// that references it; the rows' sums see their nonzero terms in CSR order.
+constexpr int kRowGroup = 4;
+struct RowGroups {
+  const int* gp = nullptr;
+  const int* col = nullptr;
+  const float* val = nullptr;
+};
 
 // ---------------------------------------------------------------------------
 // Batched per-step launches: one launch advances the same kernel for up to
@@ -165,11 +181,14 @@ __device__ inline double gsrc_at(const GSrc& g, int64_t row, int j) {
 // With sx: before the epilogue's inner products and the store, W[row][col]
 // -= sd[col] * smult[col] * sx[row][col] in the update's arithmetic (sx is a
 // window vector, sd its coefficient row, smult its multipliers).
+// With g.rg the product reads the row groups `rg` (FP32 values, vt =
+// VT_F32) instead of rp / ci / va.
 hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* ci,
                        const void* va, int vt, const void* X, void* W,
                        const double* xmult, double opscale, const VecSet* fused, int nf,
                        int voff, double* part, int* nblk_out, const void* sx = nullptr,
-                       const double* smult = nullptr, const double* sd = nullptr);
+                       const double* smult = nullptr, const double* sd = nullptr,
+                       const RowGroups* rg = nullptr);
 
 // part[voff+v][col][block] = mult_v[col] * sum_{rows of block} x_v[row][col] w[row][col],
 // v < nv <= kDotsPerLaunch, or nv <= kDotsWide with one chunk per lane (FP32
@@ -213,6 +232,7 @@ struct SpmmItem {
   const void* sx;  // optional early subtraction (see launch_spmm)
   const double* smult;
   const double* sd;
+  RowGroups rg;  // with g.rg
 };
 struct UpdateItem {
   Geom g;
@@ -255,6 +275,12 @@ struct FinishItem {
   const double* gin_mult = nullptr;
 };
 hipError_t launch_spmm_batch(hipStream_t st, SpmmItem* items, int count);
+// The row-group items of a batch (g.rg, checked by launch_spmm_batch), at
+// most kMaxBatch of them with the same C and nf: one launch.
+hipError_t launch_spmm_rg_group(hipStream_t st, SpmmItem* items, const int* idx, int cnt);
+// Grid of a streaming kernel `fn` over g's rows (row groups with g.rg): at
+// most one resident wave of blocks, a multiple of 8 from 8 blocks up.
+int stream_grid(const Geom& g, const void* fn);
 hipError_t launch_update_batch(hipStream_t st, UpdateItem* items, int count);
 hipError_t launch_reduce_batch(hipStream_t st, const ReduceItem* items, int count);
 hipError_t launch_step_finish_batch(hipStream_t st, const FinishItem* items, int count);

@@ -435,6 +435,17 @@ Geom Run::v1_geom(int ld, const Geom& gu, bool presub) const {
   return geom_usable(g) ? g : gu;
 }
 
+// The matrix's row groups serve the product of FP32 Krylov vectors over its
+// FP32 values.
+bool Run::rg_ok() const { return a_->rg_gp && mixed_ && a_->vt_lo == VT_F32 && xb_ == 4; }
+RowGroups Run::row_groups() const {
+  RowGroups r;
+  r.gp = a_->rg_gp;
+  r.col = a_->rg_col;
+  r.val = a_->rg_val;
+  return r;
+}
+
 bool Run::presub_choice(int ld) const {
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
   std::lock_guard<std::mutex> lk(a_->tune_mu);
@@ -452,8 +463,16 @@ Geom Run::krylov_geom(int ld, int which) const {
       g.lges = (it->second.first >> 8) & 0xf;  // entry split of the product
       g.xil = (it->second.first >> 12) & 1;    // chunk mapping of the product
       g.ts = (it->second.first >> 16) & 0x7fff;  // row tiles of the product
-      if (geom_usable(g)) return g;
+      g.rg = (it->second.first >> 13) & 1;       // row groups of the product
+      if (geom_usable(g) && (g.rg == 0 || rg_ok())) return g;
     }
+  }
+  if (which == 0 && rg_ok()) {
+    // row groups: one chunk per lane, a row's chunks over that many lanes
+    const int ncolv = ld / (16 / xb_);
+    Geom g = make_geom_lc(n_, ld, xb_, ncolv, 1);
+    g.rg = 1;
+    if (ncolv <= 64 && geom_usable(g)) return g;
   }
   if (which == 0 && a_->nnz >= 64 * a_->n) {
     // long rows: one chunk per lane and the row's entries over two lane
@@ -924,6 +943,7 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
       sp.sx = sx;
       sp.smult = smult;
       sp.sd = sd;
+      if (kg_.rg) sp.rg = row_groups();
       plan->red = ReduceItem{part_, 0, nf * kld_, dwin_ + (size_t)(nv - nf) * kld_};
       UpdateItem& up = plan->upd;
       up = UpdateItem{};
@@ -951,9 +971,11 @@ ld_status Run::run_krylov_step(hipStream_t st, int t, StepPlan* plan) {
     }
   }
   int nb = 0;
+  const RowGroups rgs = row_groups();
   LD_LAUNCH(LD_PROF_SPMM, spmm_bytes(kld_, xb_) + (nf - 1 + (presub ? 1 : 0)) * vec_bytes,
             launch_spmm(st, kg_, a_->rp, a_->ci, vals, vt, slot_ptr(t), W, mult_ptr(t),
-                        opscale_ * vscale_, &vf, nf, 0, part_, &nb, sx, smult, sd));
+                        opscale_ * vscale_, &vf, nf, 0, part_, &nb, sx, smult, sd,
+                        kg_.rg ? &rgs : nullptr));
   LD_LAUNCH(LD_PROF_REDUCE, (double)nb * nf * kld_ * 8,
             launch_reduce(st, part_, nb, nf * kld_, dwin_ + (size_t)(nv - nf) * kld_));
   // more than 4 older vectors: one wide launch (up to 8) with one 16-byte
@@ -1356,6 +1378,7 @@ static Geom candidate_geom(int64_t n, int ld, int xbytes, const std::pair<int, i
   g.lges = (c.first >> 8) & 0xf;
   g.xil = (c.first >> 12) & 1;
   g.ts = (c.first >> 16) & 0x7fff;
+  g.rg = (c.first >> 13) & 1;
   return g;
 }
 
@@ -1466,8 +1489,21 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7475u, n_, 0, ld, ld, X, xb_, ld, 0));
     LD_HIP(launch_probes(st, PROBE_RADEMACHER, 0x7476u, n_, 0, ld, ld, V, xb_, ld, 0));
     // entry splits only pay on rows of many entries
-    const auto cand = tune_candidates(n_, ld, xb_, a_->nnz >= 16 * a_->n, true,
-                                      stride_candidates(st));
+    auto cand = tune_candidates(n_, ld, xb_, a_->nnz >= 16 * a_->n, true,
+                                stride_candidates(st));
+    if (rg_ok()) {
+      // the row-group product in every plain geometry of at most two chunks
+      // per lane (both chunk mappings), and its default first among them
+      const size_t base = cand.size();
+      const int ncolv = ld / (16 / xb_);
+      if (ncolv <= 64) cand.push_back({ncolv | (1 << 13), 1});
+      for (size_t i = 0; i < base; ++i) {
+        const Geom g = candidate_geom(n_, ld, xb_, cand[i]);
+        if (g.lges == 0 && g.ts == 0 && g.C <= 2 && !(g.L == ncolv && g.C == 1 && g.xil == 0))
+          cand.push_back({cand[i].first | (1 << 13), cand[i].second});
+      }
+    }
+    const RowGroups rgs = row_groups();
     const int nc = (int)cand.size();
     std::vector<double> tp(nc, 1e300), tu(nc, 1e300);
     VecSet vf{};
@@ -1486,7 +1522,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
         auto product = [&]() {
           return launch_spmm(st, g, a_->rp, a_->ci, vals, vt, X, W, mult, opscale_ * vscale_, &vf, 1, 0,
                              part, &nb, sym ? V : nullptr, sym ? mult : nullptr,
-                             sym ? dcoef : nullptr);
+                             sym ? dcoef : nullptr, g.rg ? &rgs : nullptr);
         };
         auto update = [&]() {
           return launch_update(st, g, W, vu, nv, dcoef, 0, 1, nullptr, nullptr, sym, part, &nb,
@@ -1500,7 +1536,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
         LD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
         tp[c] = std::min(tp[c], (double)ms / reps);
         // the update has no sparse entries to split and keeps its own mapping
-        if (g.lges != 0 || g.xil != 0 || g.ts != 0) continue;
+        if (g.lges != 0 || g.xil != 0 || g.ts != 0 || g.rg != 0) continue;
         LD_HIP(update());
         LD_HIP(hipEventRecord(ev.a, st));
         for (int i = 0; i < reps; ++i) LD_HIP(update());
@@ -1538,7 +1574,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
       std::vector<int> ucand;
       for (int c = 0; c < nc; ++c) {
         const Geom g = candidate_geom(n_, ld, xb_, cand[c]);
-        if (g.lges == 0 && g.xil == 0 && g.ts == 0) ucand.push_back(c);
+        if (g.lges == 0 && g.xil == 0 && g.ts == 0 && g.rg == 0) ucand.push_back(c);
       }
       double t_psp = 1e300, t_psu = 1e300, t_pp = 1e300;
       std::vector<double> t_pu(nc, 1e300);
@@ -1557,11 +1593,12 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
       for (int round = 0; round < 3; ++round) {
         LD_HIP(timed([&]() {
           return launch_spmm(st, gp, a_->rp, a_->ci, vals, vt, X, W, mult, opscale_ * vscale_,
-                             &vf, 1, 0, part, &nb, V, mult, dcoef);
+                             &vf, 1, 0, part, &nb, V, mult, dcoef, gp.rg ? &rgs : nullptr);
         }, t_psp));
         LD_HIP(timed([&]() {
           return launch_spmm(st, gp, a_->rp, a_->ci, vals, vt, X, W, mult, opscale_ * vscale_,
-                             &vf, 1, 0, part, &nb);
+                             &vf, 1, 0, part, &nb, nullptr, nullptr, nullptr,
+                             gp.rg ? &rgs : nullptr);
         }, t_pp));
         LD_HIP(timed([&]() {
           return launch_update(st, gu, W, vu, nv, dcoef, 0, 1, nullptr, nullptr, true, part,
@@ -1596,7 +1633,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
       for (int round = 0; round < 3; ++round)
         for (int c = 0; c < nc; ++c) {
           const Geom g = candidate_geom(n_, ld, xb_, cand[c]);
-          if (g.lges != 0 || g.xil != 0 || g.ts != 0) continue;
+          if (g.lges != 0 || g.xil != 0 || g.ts != 0 || g.rg != 0) continue;
           int nb = 0;
           auto upd = [&]() {
             return launch_update(st, g, W, vv, nvs, dcoef, 0, 1, V, mult, sym, part, &nb,
@@ -1635,6 +1672,7 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
       out->spmm_entry_split = 1 << ((cand[bp].first >> 8) & 0xf);
       out->spmm_interleave = (cand[bp].first >> 12) & 1;
       out->spmm_row_stride = (cand[bp].first >> 16) & 0x7fff;
+      out->spmm_row_groups = (cand[bp].first >> 13) & 1;
       out->update_lanes = cand[presub ? bu : bun].first;
       out->update_chunks = cand[presub ? bu : bun].second;
       out->spmm_ms = tp[bp];
@@ -1652,25 +1690,29 @@ ld_status Run::tune(hipStream_t st, int reps, ld_tune_result* out) {
 
 ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int update_lanes,
                          int update_chunks, int spmm_interleave, int spmm_row_stride,
-                         int step_presub) {
+                         int step_presub, int spmm_row_groups) {
   int e = 0;
   while (e < 4 && (1 << e) < spmm_split) ++e;
   Geom gp = make_geom_lc(n_, ldB_, xb_, spmm_lanes, spmm_chunks);
   gp.lges = e;
   gp.ts = spmm_row_stride;
+  gp.rg = spmm_row_groups == 1 ? 1 : 0;
   if ((1 << e) != spmm_split || !geom_usable(gp) || (spmm_interleave != 0 && spmm_interleave != 1) ||
       !geom_usable(make_geom_lc(n_, ldB_, xb_, update_lanes, update_chunks)) ||
-      (step_presub != 0 && step_presub != 1))
+      (step_presub != 0 && step_presub != 1) || (spmm_row_groups != 0 && spmm_row_groups != 1) ||
+      (gp.rg && !rg_ok()))
     return set_error(LD_E_INVALID_ARG,
                      "lanes must be <= 64 (a power of two with an entry split), chunks in "
                      "[1, 4] and the entry split 1, 2, 4 or 8 (at most the lanes), the lanes "
                      "per split group and the chunks covering the probe block, interleave 0 "
                      "or 1, the row stride 0 or a multiple of the rows per wave (64 / lanes, "
-                     "lanes a power of two) up to 32767, the step schedule 0 or 1");
+                     "lanes a power of two) up to 32767, the step schedule 0 or 1, row "
+                     "groups 0 or 1 (1: FP32 Krylov vectors on a matrix that keeps row "
+                     "groups, at most 2 chunks, no entry split, no row stride)");
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
   std::lock_guard<std::mutex> lk(a_->tune_mu);
   a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes | (e << 8) | (spmm_interleave << 12) |
-                                             (spmm_row_stride << 16),
+                                             (gp.rg << 13) | (spmm_row_stride << 16),
                                          spmm_chunks};
   a_->tune[tune_key(ldB_, xb_, vt, upd_which(step_presub != 0))] = {update_lanes, update_chunks};
   if (step_presub)
@@ -1913,6 +1955,45 @@ static uint16_t double_to_bf16_rne(double d) {
   return (uint16_t)(upper | (std::signbit(d) ? 0x8000u : 0u));
 }
 
+// Row groups of kRowGroup consecutive rows (the sorted union of their
+// columns, kRowGroup FP32 values per union column, zero where a row has no
+// entry), kept where they gather much less than the rows: at least
+// kRowGroupMinRatio entries per union column (covariance-like matrices; a
+// 3D Laplacian has 1.3, a random graph 1.0), estimated first on a sample of
+// groups.
+static constexpr double kRowGroupMinRatio = 2.0;
+
+// Union columns of group g (rows sorted, as the structure checks ensure);
+// with cols: also the union and its values (vals[kRowGroup u + r]).
+static int64_t group_union(const int32_t* rp, const int32_t* ci, const double* values, int64_t n,
+                           int64_t g, int32_t* cols, float* vals) {
+  const int64_t r0 = g * kRowGroup;
+  const int nr = (int)std::min<int64_t>(kRowGroup, n - r0);
+  int32_t k[kRowGroup], e[kRowGroup];
+  for (int r = 0; r < nr; ++r) {
+    k[r] = rp[r0 + r];
+    e[r] = rp[r0 + r + 1];
+  }
+  int64_t cnt = 0;
+  for (;;) {
+    int32_t c = INT32_MAX;  // columns are below n <= INT32_MAX
+    for (int r = 0; r < nr; ++r)
+      if (k[r] < e[r]) c = std::min(c, ci[k[r]]);
+    if (c == INT32_MAX) break;
+    if (cols) {
+      cols[cnt] = c;
+      for (int r = 0; r < kRowGroup; ++r) vals[cnt * kRowGroup + r] = 0.0f;
+    }
+    for (int r = 0; r < nr; ++r)
+      if (k[r] < e[r] && ci[k[r]] == c) {
+        if (cols) vals[cnt * kRowGroup + r] = (float)values[k[r]];
+        ++k[r];
+      }
+    ++cnt;
+  }
+  return cnt;
+}
+
 ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_ptr,
                         const int32_t* col_idx, const double* values, int32_t vt,
                         double lambda_lo_hint, double lambda_hi_hint, ld_matrix** out) {
@@ -1982,6 +2063,9 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
     if (m->v64) (void)hipFree(m->v64);
     if (m->vlo) (void)hipFree(m->vlo);
     if (m->gpart) (void)hipFree(m->gpart);
+    if (m->rg_gp) (void)hipFree(m->rg_gp);
+    if (m->rg_col) (void)hipFree(m->rg_col);
+    if (m->rg_val) (void)hipFree(m->rg_val);
   };
   hipError_t e = hipMalloc(&m->rp, (size_t)(n + 1) * 4);
   if (e == hipSuccess) e = hipMalloc(&m->ci, (size_t)nnz * 4);
@@ -2049,6 +2133,47 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
         });
     }
   }
+  // row groups, for the FP32 values of mixed-precision products
+  if (e == hipSuccess && m->vt_lo == VT_F32) {
+    const int64_t ng = (n + kRowGroup - 1) / kRowGroup;
+    const int64_t ns = std::min<int64_t>(ng, 4096);
+    int64_t se = 0, su = 0;
+    for (int64_t i = 0; i < ns; ++i) {
+      const int64_t g = i * ng / ns;
+      se += row_ptr[std::min(n, (g + 1) * kRowGroup)] - row_ptr[g * kRowGroup];
+      su += group_union(row_ptr, col_idx, values, n, g, nullptr, nullptr);
+    }
+    if ((double)se >= kRowGroupMinRatio * (double)su) {
+      std::vector<int32_t> gp((size_t)ng + 1, 0);
+      const int nt = host_threads(nnz);
+      parallel_ranges(ng, nt, [&](int, int64_t g0, int64_t g1) {
+        for (int64_t g = g0; g < g1; ++g)
+          gp[g + 1] = (int32_t)group_union(row_ptr, col_idx, values, n, g, nullptr, nullptr);
+      });
+      // a union column comes from at least one entry: nu <= nnz < 2^31
+      for (int64_t g = 0; g < ng; ++g) gp[g + 1] += gp[g];
+      const int64_t nu = gp[ng];
+      if ((double)nnz >= kRowGroupMinRatio * (double)nu) {
+        std::vector<int32_t> cols((size_t)nu);
+        std::vector<float> vals((size_t)nu * kRowGroup);
+        parallel_ranges(ng, nt, [&](int, int64_t g0, int64_t g1) {
+          for (int64_t g = g0; g < g1; ++g)
+            group_union(row_ptr, col_idx, values, n, g, cols.data() + gp[g],
+                        vals.data() + (size_t)gp[g] * kRowGroup);
+        });
+        e = hipMalloc(&m->rg_gp, ((size_t)ng + 1) * 4);
+        if (e == hipSuccess) e = hipMalloc(&m->rg_col, (size_t)nu * 4);
+        if (e == hipSuccess) e = hipMalloc(&m->rg_val, (size_t)nu * kRowGroup * 4);
+        if (e == hipSuccess) e = upload(m->rg_gp, gp.data(), ((size_t)ng + 1) * 4);
+        if (e == hipSuccess) e = upload(m->rg_col, cols.data(), (size_t)nu * 4);
+        if (e == hipSuccess) e = upload(m->rg_val, vals.data(), (size_t)nu * kRowGroup * 4);
+        if (e == hipSuccess) {
+          m->rg_nu = nu;
+          m->bytes += ((size_t)ng + 1) * 4 + (size_t)nu * (4 + 4 * kRowGroup);
+        }
+      }
+    }
+  }
   // Gershgorin interval (Section 2.1), on the device
   const int nb = (int)((n + kThreads - 1) / kThreads);
   if (e == hipSuccess) e = hipMalloc(&m->gpart, (size_t)nb * 2 * 8);
@@ -2098,6 +2223,9 @@ ld_status ld_destroy(ld_matrix* a) {
   if (a->v64) (void)hipFree(a->v64);
   if (a->vlo) (void)hipFree(a->vlo);
   if (a->gpart) (void)hipFree(a->gpart);
+  if (a->rg_gp) (void)hipFree(a->rg_gp);
+  if (a->rg_col) (void)hipFree(a->rg_col);
+  if (a->rg_val) (void)hipFree(a->rg_val);
   a->ctx->n_matrices.fetch_sub(1);
   delete a;
   return LD_OK;
@@ -2125,13 +2253,13 @@ ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_re
 ld_status ld_tune_set(ld_matrix* a, const ld_params* p, int32_t spmm_lanes, int32_t spmm_chunks,
                       int32_t spmm_entry_split, int32_t update_lanes, int32_t update_chunks,
                       int32_t spmm_interleave, int32_t spmm_row_stride,
-                      int32_t step_presub) {
+                      int32_t step_presub, int32_t spmm_row_groups) {
   if (!a || !p) return set_error(LD_E_INVALID_ARG, "null argument");
   Run run(a, *p);
   ld_status rc = run.validate();
   if (rc != LD_OK) return rc;
   return run.tune_set(spmm_lanes, spmm_chunks, spmm_entry_split, update_lanes, update_chunks,
-                      spmm_interleave, spmm_row_stride, step_presub);
+                      spmm_interleave, spmm_row_stride, step_presub, spmm_row_groups);
 }
 
 ld_status ld_quad_form(ld_matrix* a, const double* x, double* out) {

@@ -157,6 +157,12 @@ struct ld_matrix {
   // synchronises the device, which would make a matrix created while
   // requests run wait for them
   double* gpart = nullptr;
+  // row groups (FP32 storage, where they gather much less than the rows):
+  // group pointers, union columns and kRowGroup FP32 values per union column
+  int* rg_gp = nullptr;
+  int* rg_col = nullptr;
+  float* rg_val = nullptr;
+  int64_t rg_nu = 0;
   double lo_hint = 0, hi_hint = 0;
   double lo = 0, hi = 0;    // interval used by the estimators
   size_t bytes = 0;
@@ -224,6 +230,8 @@ class Run {
   // product (which = 0) or update (which = 1) geometry of a Krylov block of
   // width ld: the matrix's tuned choice when it holds one, else the default
   Geom krylov_geom(int ld, int which) const;
+  bool rg_ok() const;             // the product may read the matrix's row groups
+  RowGroups row_groups() const;
   int upd_steady_nv(bool presub) const;  // update vectors of a steady-state step
   int upd_which(bool presub) const;      // tuning key of the update (window class)
   bool presub_choice(int ld) const;      // the stored step schedule of block width ld
@@ -370,7 +378,7 @@ class Run {
   ld_status tune(hipStream_t st, int reps, ld_tune_result* out);
   ld_status tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int update_lanes,
                      int update_chunks, int spmm_interleave = 0, int spmm_row_stride = 0,
-                     int step_presub = 1);
+                     int step_presub = 1, int spmm_row_groups = 0);
   std::vector<int> stride_candidates(hipStream_t st) const;
   double submit_time() const { return t_submit_; }
   void set_submit_time(double t) { t_submit_ = t; }

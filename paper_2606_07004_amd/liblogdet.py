@@ -109,7 +109,7 @@ class ld_tune_result(C.Structure):
                 ("candidates", C.c_int32), ("spmm_entry_split", C.c_int32),
                 ("spmm_interleave", C.c_int32), ("spmm_row_stride", C.c_int32),
                 ("step_presub", C.c_int32), ("step_presub_ms", C.c_double),
-                ("step_plain_ms", C.c_double)]
+                ("step_plain_ms", C.c_double), ("spmm_row_groups", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -131,7 +131,7 @@ _SIGNATURES = [
                                 C.POINTER(ld_tune_result)]),
     ("ld_tune_set", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.c_int32, C.c_int32,
                                 C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
-                                C.c_int32]),
+                                C.c_int32, C.c_int32]),
     ("ld_estimate", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                 C.c_uint64, C.POINTER(ld_result)]),
     ("ld_estimate_ex", C.c_int32, [C.c_void_p, C.POINTER(ld_params), C.POINTER(ld_result)]),
@@ -318,11 +318,12 @@ def ld_autotune(a, params: ld_params, reps: int = 20) -> ld_tune_result:
 
 def ld_tune_set(a, params: ld_params, spmm_lanes: int, spmm_chunks: int, update_lanes: int,
                 update_chunks: int, spmm_entry_split: int = 1, spmm_interleave: int = 0,
-                spmm_row_stride: int = 0, step_presub: int = 1) -> None:
+                spmm_row_stride: int = 0, step_presub: int = 1, spmm_row_groups: int = 0) -> None:
     """Store a given product / update geometry for the estimate block of `params`."""
     _check(lib().ld_tune_set(a, C.byref(params), int(spmm_lanes), int(spmm_chunks),
                              int(spmm_entry_split), int(update_lanes), int(update_chunks),
-                             int(spmm_interleave), int(spmm_row_stride), int(step_presub)))
+                             int(spmm_interleave), int(spmm_row_stride), int(step_presub),
+                             int(spmm_row_groups)))
 
 
 def ld_serving_stats_get(ctx) -> ld_serving_stats:

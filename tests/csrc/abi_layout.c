@@ -30,7 +30,7 @@ int main(void) {
   F(ld_tune_result, candidates); F(ld_tune_result, spmm_entry_split);
   F(ld_tune_result, spmm_interleave); F(ld_tune_result, spmm_row_stride);
   F(ld_tune_result, step_presub); F(ld_tune_result, step_presub_ms);
-  F(ld_tune_result, step_plain_ms);
+  F(ld_tune_result, step_plain_ms); F(ld_tune_result, spmm_row_groups);
   Z(ld_tune_result);
   F(ld_serving_stats, submitted); F(ld_serving_stats, completed); F(ld_serving_stats, ticks);
   F(ld_serving_stats, batched_steps); F(ld_serving_stats, batched_launches);
