@@ -296,9 +296,11 @@ ld_status ld_request_bytes(ld_matrix* a, const ld_params* p, uint64_t* bytes);
  * (zero where a row has no entry), about (4 + 16) bytes per union column.
  * The product of FP32 Krylov vectors can then gather each union column's
  * probe row once for the 4 rows (spmm_row_groups; the untuned default on
- * such matrices, with one chunk per lane), which ld_autotune tries in every
- * plain geometry of at most 2 chunks per lane; a row's sum sees its nonzero
- * terms in CSR order, so the product's output is the CSR product's.
+ * such matrices for blocks of 16 columns or more, with one chunk per lane),
+ * which ld_autotune tries in every plain geometry of at most 2 chunks per
+ * lane; a row's sum sees its nonzero terms in CSR order, so the product's
+ * output is the CSR product's.  The groups are built on the device when
+ * the matrix is created.
  * ld_autotune times every such (L, C, E) with L a power of two and at most
  * half a row of idle chunks on this matrix, and L = ceil(chunks / C) where
  * that is not a power of two, for the probe-block shapes and

@@ -12,6 +12,8 @@
 // in CSR order (a zero value adds an exact zero), so W is the CSR product's
 // W; the epilogue (scaling, early subtraction, store, fused inner products)
 // is the CSR product's, per row.
+#include <climits>
+
 #include "ld_kernels.h"
 
 namespace ld {
@@ -297,6 +299,78 @@ hipError_t launch_spmm_rg_group(hipStream_t st, SpmmItem* items, const int* idx,
     return rg_launch<2, 2>(st, items, idx, cnt);
   }
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Row groups from the CSR arrays on the device: one thread per group merges
+// its rows' sorted column lists.  Pass 1 counts each group's union columns
+// (cnt[g]); pass 2, given gp (the exclusive prefix sums), writes the union
+// columns and their kRowGroup values (the FP64 values rounded to FP32, zero
+// where a row has no entry).
+// ---------------------------------------------------------------------------
+template <bool FILL>
+__global__ __launch_bounds__(kThreads) void k_rowgroup_build(int64_t n, const int* __restrict__ rp,
+                                                             const int* __restrict__ ci,
+                                                             const double* __restrict__ v64,
+                                                             int* __restrict__ cnt,
+                                                             const int* __restrict__ gp,
+                                                             int* __restrict__ col,
+                                                             float* __restrict__ val) {
+  const int64_t ng = (n + kRowGroup - 1) / kRowGroup;
+  const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (g >= ng) return;
+  const int64_t r0 = g * kRowGroup;
+  const int nr = (int)min((int64_t)kRowGroup, n - r0);
+  int k[kRowGroup], e[kRowGroup];
+#pragma unroll
+  for (int r = 0; r < kRowGroup; ++r) {
+    k[r] = r < nr ? rp[r0 + r] : 0;
+    e[r] = r < nr ? rp[r0 + r + 1] : 0;
+  }
+  int u = FILL ? gp[g] : 0;
+  int m = 0;
+  for (;;) {
+    int c = INT_MAX;  // columns are below n <= INT_MAX
+#pragma unroll
+    for (int r = 0; r < kRowGroup; ++r)
+      if (k[r] < e[r]) c = min(c, ci[k[r]]);
+    if (c == INT_MAX) break;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    float* vr = reinterpret_cast<float*>(&v);
+#pragma unroll
+    for (int r = 0; r < kRowGroup; ++r)
+      if (k[r] < e[r] && ci[k[r]] == c) {
+        if (FILL) vr[r] = (float)v64[k[r]];
+        ++k[r];
+      }
+    if (FILL) {
+      col[u] = c;
+      reinterpret_cast<float4*>(val)[u] = v;
+      ++u;
+    }
+    ++m;
+  }
+  if (!FILL) cnt[g] = m;
+}
+
+hipError_t launch_rowgroup_count(hipStream_t st, int64_t n, const int* rp, const int* ci,
+                                 int* cnt) {
+  if (n < 1 || !rp || !ci || !cnt) return hipErrorInvalidValue;
+  const int64_t ng = (n + kRowGroup - 1) / kRowGroup;
+  hipLaunchKernelGGL(k_rowgroup_build<false>, dim3((unsigned)((ng + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, st, n, rp, ci, nullptr, cnt, nullptr, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowgroup_fill(hipStream_t st, int64_t n, const int* rp, const int* ci,
+                                const double* v64, const int* gp, int* col, float* val) {
+  if (n < 1 || !rp || !ci || !v64 || !gp || !col || !val ||
+      reinterpret_cast<uintptr_t>(val) % 16 != 0)
+    return hipErrorInvalidValue;
+  const int64_t ng = (n + kRowGroup - 1) / kRowGroup;
+  hipLaunchKernelGGL(k_rowgroup_build<true>, dim3((unsigned)((ng + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, st, n, rp, ci, v64, nullptr, gp, col, val);
+  return hipGetLastError();
 }
 
 }  // namespace ld

@@ -68,6 +68,14 @@ struct RowGroups {
   const float* val = nullptr;
 };
 
+// Row groups of an n-row CSR matrix (rows sorted) on the device: cnt[g] =
+// group g's union columns; then, with gp the exclusive prefix sums of cnt
+// (gp[g] = first union column of group g), the union columns col and their
+// values val (v64 rounded to FP32, kRowGroup per column).
+hipError_t launch_rowgroup_count(hipStream_t st, int64_t n, const int* rp, const int* ci, int* cnt);
+hipError_t launch_rowgroup_fill(hipStream_t st, int64_t n, const int* rp, const int* ci,
+                                const double* v64, const int* gp, int* col, float* val);
+
 // ---------------------------------------------------------------------------
 // Batched per-step launches: one launch advances the same kernel for up to
 // kMaxBatch requests (the scheduler's continuous batching); a single request

@@ -467,8 +467,10 @@ Geom Run::krylov_geom(int ld, int which) const {
       if (geom_usable(g) && (g.rg == 0 || rg_ok())) return g;
     }
   }
-  if (which == 0 && rg_ok()) {
+  if (which == 0 && rg_ok() && ld >= 16) {
     // row groups: one chunk per lane, a row's chunks over that many lanes
+    // (blocks of 16 columns or more: on narrower ones the groups' extra
+    // multiply-adds and shuffles weigh more than the gathers they save)
     const int ncolv = ld / (16 / xb_);
     Geom g = make_geom_lc(n_, ld, xb_, ncolv, 1);
     g.rg = 1;
@@ -1960,13 +1962,11 @@ static uint16_t double_to_bf16_rne(double d) {
 // entry), kept where they gather much less than the rows: at least
 // kRowGroupMinRatio entries per union column (covariance-like matrices; a
 // 3D Laplacian has 1.3, a random graph 1.0), estimated first on a sample of
-// groups.
+// groups on the host, then counted and built on the device.
 static constexpr double kRowGroupMinRatio = 2.0;
 
-// Union columns of group g (rows sorted, as the structure checks ensure);
-// with cols: also the union and its values (vals[kRowGroup u + r]).
-static int64_t group_union(const int32_t* rp, const int32_t* ci, const double* values, int64_t n,
-                           int64_t g, int32_t* cols, float* vals) {
+// Union columns of group g (rows sorted, as the structure checks ensure).
+static int64_t group_union_size(const int32_t* rp, const int32_t* ci, int64_t n, int64_t g) {
   const int64_t r0 = g * kRowGroup;
   const int nr = (int)std::min<int64_t>(kRowGroup, n - r0);
   int32_t k[kRowGroup], e[kRowGroup];
@@ -1980,15 +1980,8 @@ static int64_t group_union(const int32_t* rp, const int32_t* ci, const double* v
     for (int r = 0; r < nr; ++r)
       if (k[r] < e[r]) c = std::min(c, ci[k[r]]);
     if (c == INT32_MAX) break;
-    if (cols) {
-      cols[cnt] = c;
-      for (int r = 0; r < kRowGroup; ++r) vals[cnt * kRowGroup + r] = 0.0f;
-    }
     for (int r = 0; r < nr; ++r)
-      if (k[r] < e[r] && ci[k[r]] == c) {
-        if (cols) vals[cnt * kRowGroup + r] = (float)values[k[r]];
-        ++k[r];
-      }
+      if (k[r] < e[r] && ci[k[r]] == c) ++k[r];
     ++cnt;
   }
   return cnt;
@@ -2066,6 +2059,7 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
     if (m->rg_gp) (void)hipFree(m->rg_gp);
     if (m->rg_col) (void)hipFree(m->rg_col);
     if (m->rg_val) (void)hipFree(m->rg_val);
+    if (m->rg_unused) (void)hipFree(m->rg_unused);
   };
   hipError_t e = hipMalloc(&m->rp, (size_t)(n + 1) * 4);
   if (e == hipSuccess) e = hipMalloc(&m->ci, (size_t)nnz * 4);
@@ -2136,41 +2130,47 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
   // row groups, for the FP32 values of mixed-precision products
   if (e == hipSuccess && m->vt_lo == VT_F32) {
     const int64_t ng = (n + kRowGroup - 1) / kRowGroup;
-    const int64_t ns = std::min<int64_t>(ng, 4096);
+    const int64_t ns = std::min<int64_t>(ng, 256);
     int64_t se = 0, su = 0;
     for (int64_t i = 0; i < ns; ++i) {
       const int64_t g = i * ng / ns;
       se += row_ptr[std::min(n, (g + 1) * kRowGroup)] - row_ptr[g * kRowGroup];
-      su += group_union(row_ptr, col_idx, values, n, g, nullptr, nullptr);
+      su += group_union_size(row_ptr, col_idx, n, g);
     }
     if ((double)se >= kRowGroupMinRatio * (double)su) {
+      // counts into gp[1 ..], prefix sums on the host (a union column comes
+      // from at least one entry: nu <= nnz < 2^31), then the fill
       std::vector<int32_t> gp((size_t)ng + 1, 0);
-      const int nt = host_threads(nnz);
-      parallel_ranges(ng, nt, [&](int, int64_t g0, int64_t g1) {
-        for (int64_t g = g0; g < g1; ++g)
-          gp[g + 1] = (int32_t)group_union(row_ptr, col_idx, values, n, g, nullptr, nullptr);
-      });
-      // a union column comes from at least one entry: nu <= nnz < 2^31
-      for (int64_t g = 0; g < ng; ++g) gp[g + 1] += gp[g];
-      const int64_t nu = gp[ng];
-      if ((double)nnz >= kRowGroupMinRatio * (double)nu) {
-        std::vector<int32_t> cols((size_t)nu);
-        std::vector<float> vals((size_t)nu * kRowGroup);
-        parallel_ranges(ng, nt, [&](int, int64_t g0, int64_t g1) {
-          for (int64_t g = g0; g < g1; ++g)
-            group_union(row_ptr, col_idx, values, n, g, cols.data() + gp[g],
-                        vals.data() + (size_t)gp[g] * kRowGroup);
-        });
-        e = hipMalloc(&m->rg_gp, ((size_t)ng + 1) * 4);
+      e = hipMalloc(&m->rg_gp, ((size_t)ng + 1) * 4);
+      if (e == hipSuccess) e = launch_rowgroup_count(ctx->stream, n, m->rp, m->ci, m->rg_gp + 1);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(gp.data() + 1, m->rg_gp + 1, (size_t)ng * 4, hipMemcpyDeviceToHost,
+                           ctx->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+      int64_t nu = 0;
+      for (int64_t g = 0; g < ng && e == hipSuccess; ++g) {
+        nu += gp[g + 1];
+        gp[g + 1] = (int32_t)nu;
+      }
+      if (e == hipSuccess && (double)nnz >= kRowGroupMinRatio * (double)nu) {
+        e = hipMemcpyAsync(m->rg_gp, gp.data(), ((size_t)ng + 1) * 4, hipMemcpyHostToDevice,
+                           ctx->stream);
         if (e == hipSuccess) e = hipMalloc(&m->rg_col, (size_t)nu * 4);
         if (e == hipSuccess) e = hipMalloc(&m->rg_val, (size_t)nu * kRowGroup * 4);
-        if (e == hipSuccess) e = upload(m->rg_gp, gp.data(), ((size_t)ng + 1) * 4);
-        if (e == hipSuccess) e = upload(m->rg_col, cols.data(), (size_t)nu * 4);
-        if (e == hipSuccess) e = upload(m->rg_val, vals.data(), (size_t)nu * kRowGroup * 4);
+        if (e == hipSuccess)
+          e = launch_rowgroup_fill(ctx->stream, n, m->rp, m->ci, m->v64, m->rg_gp, m->rg_col,
+                                   m->rg_val);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e == hipSuccess) {
           m->rg_nu = nu;
           m->bytes += ((size_t)ng + 1) * 4 + (size_t)nu * (4 + 4 * kRowGroup);
         }
+      } else if (e == hipSuccess) {
+        // the full count missed the ratio the sample promised: no groups (the
+        // count buffer stays with the matrix, since a free would synchronise
+        // the device)
+        m->rg_unused = m->rg_gp;
+        m->rg_gp = nullptr;
       }
     }
   }
@@ -2226,6 +2226,7 @@ ld_status ld_destroy(ld_matrix* a) {
   if (a->rg_gp) (void)hipFree(a->rg_gp);
   if (a->rg_col) (void)hipFree(a->rg_col);
   if (a->rg_val) (void)hipFree(a->rg_val);
+  if (a->rg_unused) (void)hipFree(a->rg_unused);
   a->ctx->n_matrices.fetch_sub(1);
   delete a;
   return LD_OK;

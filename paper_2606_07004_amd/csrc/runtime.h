@@ -163,6 +163,7 @@ struct ld_matrix {
   int* rg_col = nullptr;
   float* rg_val = nullptr;
   int64_t rg_nu = 0;
+  int* rg_unused = nullptr;  // a count buffer whose groups were not kept
   double lo_hint = 0, hi_hint = 0;
   double lo = 0, hi = 0;    // interval used by the estimators
   size_t bytes = 0;

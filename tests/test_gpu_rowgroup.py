@@ -87,9 +87,13 @@ def test_rowgroup_oslq_wide_windows(L, ctx, cov):
 
 
 def test_rowgroup_osa_iop(L, ctx, cov):
-    # the sketch runs (10 columns: 3 chunks) take the untuned row-group
-    # default, 3 lanes per group (not a power of two)
     _pair(L, ctx, cov, L.LD_METHOD_OSA_IOP, 30, 10, 12, 2, 7, [(8, 1, 0, 1)])
+
+
+def test_rowgroup_lanes_not_power_of_two(L, ctx, cov):
+    # 22 probes (6 chunks): 6 lanes per group (10 groups per wave, 4 lanes
+    # idle) and 3 lanes of two chunks
+    _pair(L, ctx, cov, L.LD_METHOD_OSLQ, 22, 6, 12, 2, 9, [(6, 1, 0, 1), (3, 2, 1, 1)])
 
 
 def test_rowgroup_default_and_tuner(L, ctx, cov):
