@@ -215,9 +215,9 @@ const char* ld_last_error(void);
  * diagonal entry present and > 0 (else LD_E_NOT_SPD).  values are FP64 and
  * stored as `vt`; an FP64 copy is kept as well for LD_PREC_FP64 runs.
  * With LD_VT_FP32 the matrix may also keep row groups (see ld_autotune):
- * about (4 + 16) bytes per union column, at most 20 bytes per entry, built
- * on the device here when groups of 4 rows hold at least 2 entries per
- * union column.
+ * (4 + 16) bytes per union column, built on the device here when groups of
+ * 4 rows hold at least 2 entries per union column (so at most 10 bytes per
+ * entry).
  * lambda_lo_hint / lambda_hi_hint > 0 replace the Gershgorin bounds
  * (Section 2.1); a Gershgorin lower bound <= 0 without a hint is replaced by
  * 1e-6 * lambda_hi.  n and nnz must fit int32. */
