@@ -1,6 +1,7 @@
-// Row-group sparse product W = opscale * (Q X) * diag(xmult) for FP32 values
-// and FP32 probe blocks (Alg 1's operator application, as in the CSR product
-// of k_stream.hip, over the matrix's row groups).
+// Row-group sparse product W = opscale * (Q X) * diag(xmult), FP32 values on
+// FP32 probe blocks or FP64 values on FP64 blocks (Alg 1's operator
+// application, as in the CSR product of k_stream.hip, over the matrix's row
+// groups).
 //
 // A group is kRowGroup consecutive rows with the sorted union of their
 // columns and, per union column, one value per row (zero where the row has
@@ -13,6 +14,7 @@
 // W; the epilogue (scaling, early subtraction, store, fused inner products)
 // is the CSR product's, per row.
 #include <climits>
+#include <type_traits>
 
 #include "ld_kernels.h"
 
@@ -22,40 +24,66 @@ struct RgDesc {
   int64_t n;
   const int* gp;
   const int* col;
-  const float* val;
-  const float* X;
-  float* W;
+  const void* val;  // kRowGroup values per union column, in the element type
+  const void* X;
+  void* W;
   const double* xmult;
   double opscale;
-  const float* fx[2];
+  const void* fx[2];
   const double* fmult[2];
   double* part;
   int L, ld, ncolv, voff, il;
-  const float* sx;
+  const void* sx;
   const double* smult;
   const double* sd;
 };
 
-template <int C, int NF>
+// The kRowGroup values of one union column.
+template <typename T>
+struct Vals4 {
+  T v[4];
+  __device__ inline void load(const T* p, int u) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 t = reinterpret_cast<const float4*>(p)[u];
+      v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else {
+      const double2 a = reinterpret_cast<const double2*>(p)[2 * u];
+      const double2 b = reinterpret_cast<const double2*>(p)[2 * u + 1];
+      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+  }
+  // lane src's values (wave lane index)
+  __device__ inline Vals4 from(int src) const {
+    Vals4 o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o.v[r] = __shfl(v[r], src);
+    return o;
+  }
+};
+
+// T: the element type of the values and the probe blocks (float or double);
+// the sums are in T, as in the CSR product with values and vectors of T.
+template <typename T, int C, int NF>
 __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
-  constexpr int VEC = V16<float>::N;
+  constexpr int VEC = V16<T>::N;
   constexpr int G = kRowGroup;
-  static_assert(G == 4, "one float4 of values per union column");
+  static_assert(G == 4, "four values per union column");
   constexpr bool FUSED = NF > 0;
   // one fused product: per-thread FP64 sums in the thread's LDS slots; two:
   // in registers (as in the CSR product)
   constexpr bool LDSACC = NF == 1;
   constexpr int ND = (FUSED && !LDSACC) ? NF : 1;
   // union entries whose (column, values) a lane loads per round (four with
-  // one chunk per lane: fewer rounds of dependent entry loads per group)
-  constexpr int KE = C == 1 ? 4 : 2;
+  // FP32 values and one chunk per lane: fewer rounds of dependent entry
+  // loads per group)
+  constexpr int KE = (sizeof(T) == 4 && C == 1) ? 4 : 2;
   __shared__ double red[FUSED ? kThreads * VEC * C : 1];
-  __shared__ float scs[kMaxLd];   // opscale * xmult[col]
+  __shared__ T scs[kMaxLd];       // opscale * xmult[col]
   __shared__ double scf[kMaxLd];  // sd[col] * smult[col] (early subtraction)
   const RowMap rm = RowMap::lanes(q.L, 0);
   const int ld = q.ld;
   for (int i = threadIdx.x; i < ld; i += kThreads) {
-    scs[i] = float(q.opscale * (q.xmult ? q.xmult[i] : 1.0));
+    scs[i] = T(q.opscale * (q.xmult ? q.xmult[i] : 1.0));
     if (q.sx) scf[i] = q.sd[i] * (q.smult ? q.smult[i] : 1.0);
   }
   bool okc[C];
@@ -82,40 +110,32 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
   const int nn = (int)q.n;  // n < 2^31
   const int ng = (nn + G - 1) / G;
   const int nchunk = (ng + rm.rpi - 1) / rm.rpi;
-  const float4* vals = reinterpret_cast<const float4*>(q.val);
+  const T* vals = static_cast<const T*>(q.val);
+  const T* X = static_cast<const T*>(q.X);
+  T* W = static_cast<T*>(q.W);
+  const T* sx = static_cast<const T*>(q.sx);
   for (int j = 0; j * nbk < nchunk; ++j) {
     const int ch = q.il ? j * nbk + bk : chunk_of(j, bk, nbk);
     const int grp = ch * rm.rpi + rm.rg;
     if (!rm.on || ch >= nchunk || grp >= ng) continue;
     const int r0 = grp * G;
-    float acc[G][C][VEC];
+    T acc[G][C][VEC];
 #pragma unroll
     for (int r = 0; r < G; ++r)
 #pragma unroll
       for (int c = 0; c < C; ++c)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[r][c][e] = 0.0f;
+        for (int e = 0; e < VEC; ++e) acc[r][c][e] = T(0);
     // one union column into the group's rows
-    auto add = [&](const V16<float> (&x)[C], float4 a) {
+    auto add = [&](const V16<T> (&x)[C], const Vals4<T>& a) {
 #pragma unroll
       for (int c = 0; c < C; ++c)
         if (okc[c]) {
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) {
-            acc[0][c][e] = fmaf(a.x, x[c].v[e], acc[0][c][e]);
-            acc[1][c][e] = fmaf(a.y, x[c].v[e], acc[1][c][e]);
-            acc[2][c][e] = fmaf(a.z, x[c].v[e], acc[2][c][e]);
-            acc[3][c][e] = fmaf(a.w, x[c].v[e], acc[3][c][e]);
-          }
+          for (int e = 0; e < VEC; ++e)
+#pragma unroll
+            for (int r = 0; r < G; ++r) acc[r][c][e] = fma(a.v[r], x[c].v[e], acc[r][c][e]);
         }
-    };
-    auto bcast = [&](float4 v, int src) {
-      float4 o;
-      o.x = __shfl(v.x, src);
-      o.y = __shfl(v.y, src);
-      o.z = __shfl(v.z, src);
-      o.w = __shfl(v.w, src);
-      return o;
     };
     const int ub = q.gp[grp], ue = q.gp[grp + 1];
     // the group's L lanes load KE * L consecutive union entries per round,
@@ -123,15 +143,16 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
     // by lane shuffles; two entries' gathers in flight, in union order
     for (int base = ub; base < ue; base += rm.L * KE) {
       int myc[KE];
-      float4 myv[KE];
+      Vals4<T> myv[KE];
 #pragma unroll
       for (int u = 0; u < KE; ++u) {
         const int kk = base + rm.gl + rm.L * u;
         myc[u] = r0;
-        myv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int r = 0; r < G; ++r) myv[u].v[r] = T(0);
         if (kk < ue) {
           myc[u] = q.col[kk];
-          myv[u] = vals[kk];
+          myv[u].load(vals, kk);
         }
       }
 #pragma unroll
@@ -141,24 +162,24 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
         int e = 0;
         for (; e + 2 <= cnt; e += 2) {
           const int c0 = __shfl(myc[u], rm.lb + e), c1 = __shfl(myc[u], rm.lb + e + 1);
-          const float4 a0 = bcast(myv[u], rm.lb + e), a1 = bcast(myv[u], rm.lb + e + 1);
-          V16<float> x0[C], x1[C];
+          const Vals4<T> a0 = myv[u].from(rm.lb + e), a1 = myv[u].from(rm.lb + e + 1);
+          V16<T> x0[C], x1[C];
 #pragma unroll
           for (int c = 0; c < C; ++c)
             if (okc[c]) {
-              x0[c].load(q.X + (size_t)c0 * ld + colc[c]);
-              x1[c].load(q.X + (size_t)c1 * ld + colc[c]);
+              x0[c].load(X + (size_t)c0 * ld + colc[c]);
+              x1[c].load(X + (size_t)c1 * ld + colc[c]);
             }
           add(x0, a0);
           add(x1, a1);
         }
         if (e < cnt) {
           const int c0 = __shfl(myc[u], rm.lb + e);
-          const float4 a0 = bcast(myv[u], rm.lb + e);
-          V16<float> x0[C];
+          const Vals4<T> a0 = myv[u].from(rm.lb + e);
+          V16<T> x0[C];
 #pragma unroll
           for (int c = 0; c < C; ++c)
-            if (okc[c]) x0[c].load(q.X + (size_t)c0 * ld + colc[c]);
+            if (okc[c]) x0[c].load(X + (size_t)c0 * ld + colc[c]);
           add(x0, a0);
         }
       }
@@ -170,25 +191,25 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
 #pragma unroll
       for (int c = 0; c < C; ++c)
         if (okc[c]) {
-          V16<float> out;
-          const float* sce = scs + colc[c];
-          if (q.sx) {
-            V16<float> xs;
-            xs.load_nt(q.sx + (size_t)row * ld + colc[c]);  // read once per step
+          V16<T> out;
+          const T* sce = scs + colc[c];
+          if (sx) {
+            V16<T> xs;
+            xs.load_nt(sx + (size_t)row * ld + colc[c]);  // read once per step
             const double* cfe = scf + colc[c];
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
-              out.v[e] = float(fma(-cfe[e], double(xs.v[e]), double(acc[r][c][e] * sce[e])));
+              out.v[e] = T(fma(-cfe[e], double(xs.v[e]), double(acc[r][c][e] * sce[e])));
           } else {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) out.v[e] = acc[r][c][e] * sce[e];
           }
-          out.store_nt(q.W + (size_t)row * ld + colc[c]);
+          out.store_nt(W + (size_t)row * ld + colc[c]);
           if constexpr (FUSED) {
             // the newest window vector is X itself: the row's value is read
             // again (the group's gathers do not keep it)
-            V16<float> xd;
-            xd.load(q.X + (size_t)row * ld + colc[c]);
+            V16<T> xd;
+            xd.load(X + (size_t)row * ld + colc[c]);
             if constexpr (LDSACC) {
 #pragma unroll
               for (int e = 0; e < VEC; ++e) {
@@ -198,11 +219,11 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
             } else {
 #pragma unroll
               for (int v = 0; v < NF; ++v) {
-                V16<float> x;
+                V16<T> x;
                 if (v == NF - 1)
                   x = xd;
                 else
-                  x.load(q.fx[v] + (size_t)row * ld + colc[c]);
+                  x.load(static_cast<const T*>(q.fx[v]) + (size_t)row * ld + colc[c]);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
                   dacc[v][c][e] = fma(double(x.v[e]), double(out.v[e]), dacc[v][c][e]);
@@ -224,22 +245,22 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
 }
 
 // blocks per CU at which every instance fits its registers without spills
-template <int C, int NF>
+template <typename T, int C, int NF>
 constexpr int rg_min_blocks() {
-  return C == 1 ? (NF == 2 ? 4 : 5) : (NF == 2 ? 3 : 4);
+  return (C == 1 && sizeof(T) == 4) ? (NF == 2 ? 4 : 5) : (NF == 2 ? 3 : 4);
 }
 
-template <int C, int NF>
-__global__ __launch_bounds__(kThreads, (rg_min_blocks<C, NF>())) void k_spmm_rg(
+template <typename T, int C, int NF>
+__global__ __launch_bounds__(kThreads, (rg_min_blocks<T, C, NF>())) void k_spmm_rg(
     BatchArgs<RgDesc> bt) {
   int r = 0;
   while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
-  rg_body<C, NF>(bt.d[r], (int)blockIdx.x - bt.off[r], bt.off[r + 1] - bt.off[r]);
+  rg_body<T, C, NF>(bt.d[r], (int)blockIdx.x - bt.off[r], bt.off[r + 1] - bt.off[r]);
 }
 
-template <int C, int NF>
+template <typename T, int C, int NF>
 static hipError_t rg_launch(hipStream_t st, SpmmItem* items, const int* idx, int cnt) {
-  auto fn = k_spmm_rg<C, NF>;
+  auto fn = k_spmm_rg<T, C, NF>;
   BatchArgs<RgDesc> bt{};
   bt.count = cnt;
   int off = 0;
@@ -251,13 +272,14 @@ static hipError_t rg_launch(hipStream_t st, SpmmItem* items, const int* idx, int
     d.n = it.g.n;
     d.gp = it.rg.gp;
     d.col = it.rg.col;
-    d.val = it.rg.val;
-    d.X = static_cast<const float*>(it.X);
-    d.W = static_cast<float*>(it.W);
+    d.val = sizeof(T) == 4 ? static_cast<const void*>(it.rg.val)
+                           : static_cast<const void*>(it.rg.val64);
+    d.X = it.X;
+    d.W = it.W;
     d.xmult = it.xmult;
     d.opscale = it.opscale;
     for (int v = 0; v < 2; ++v) {
-      d.fx[v] = v < it.nf ? static_cast<const float*>(it.fused.x[v]) : nullptr;
+      d.fx[v] = v < it.nf ? it.fused.x[v] : nullptr;
       d.fmult[v] = v < it.nf ? it.fused.mult[v] : nullptr;
     }
     d.part = it.part;
@@ -266,7 +288,7 @@ static hipError_t rg_launch(hipStream_t st, SpmmItem* items, const int* idx, int
     d.ncolv = it.g.ncolv;
     d.voff = it.voff;
     d.il = it.g.xil;
-    d.sx = static_cast<const float*>(it.sx);
+    d.sx = it.sx;
     d.smult = it.smult;
     d.sd = it.sd;
     bt.off[q] = off;
@@ -282,21 +304,31 @@ hipError_t launch_spmm_rg_group(hipStream_t st, SpmmItem* items, const int* idx,
   const SpmmItem& it = items[idx[0]];
   for (int q = 0; q < cnt; ++q) {
     const SpmmItem& x = items[idx[q]];
-    if (!x.g.rg || x.g.xbytes != 4 || x.vt != VT_F32 || x.g.C != it.g.C || x.nf != it.nf ||
-        x.g.lges != 0 || x.g.ts != 0 || !x.rg.gp || !x.rg.col || !x.rg.val ||
-        reinterpret_cast<uintptr_t>(x.rg.val) % 16 != 0)
+    // FP32 values on FP32 blocks, or FP64 values on FP64 blocks
+    const bool f32 = x.g.xbytes == 4 && x.vt == VT_F32;
+    const bool f64 = x.g.xbytes == 8 && x.vt == VT_F64;
+    const void* val = f32 ? static_cast<const void*>(x.rg.val) : static_cast<const void*>(x.rg.val64);
+    if (!x.g.rg || !(f32 || f64) || x.g.xbytes != it.g.xbytes || x.g.C != it.g.C ||
+        x.nf != it.nf || x.g.lges != 0 || x.g.ts != 0 || !x.rg.gp || !x.rg.col || !val ||
+        reinterpret_cast<uintptr_t>(val) % 16 != 0)
       return hipErrorInvalidValue;
   }
   const int C = it.g.C, nf = it.nf;
-  if (C == 1) {
-    if (nf == 0) return rg_launch<1, 0>(st, items, idx, cnt);
-    if (nf == 1) return rg_launch<1, 1>(st, items, idx, cnt);
-    return rg_launch<1, 2>(st, items, idx, cnt);
-  }
-  if (C == 2) {
-    if (nf == 0) return rg_launch<2, 0>(st, items, idx, cnt);
-    if (nf == 1) return rg_launch<2, 1>(st, items, idx, cnt);
-    return rg_launch<2, 2>(st, items, idx, cnt);
+  auto by_nf = [&](auto t, auto c) -> hipError_t {
+    using T = decltype(t);
+    constexpr int CC = decltype(c)::value;
+    if (nf == 0) return rg_launch<T, CC, 0>(st, items, idx, cnt);
+    if (nf == 1) return rg_launch<T, CC, 1>(st, items, idx, cnt);
+    return rg_launch<T, CC, 2>(st, items, idx, cnt);
+  };
+  using C1 = std::integral_constant<int, 1>;
+  using C2 = std::integral_constant<int, 2>;
+  if (it.g.xbytes == 4) {
+    if (C == 1) return by_nf(float{}, C1{});
+    if (C == 2) return by_nf(float{}, C2{});
+  } else {
+    if (C == 1) return by_nf(double{}, C1{});
+    if (C == 2) return by_nf(double{}, C2{});
   }
   return hipErrorInvalidValue;
 }
@@ -305,8 +337,8 @@ hipError_t launch_spmm_rg_group(hipStream_t st, SpmmItem* items, const int* idx,
 // Row groups from the CSR arrays on the device: one thread per group merges
 // its rows' sorted column lists.  Pass 1 counts each group's union columns
 // (cnt[g]); pass 2, given gp (the exclusive prefix sums), writes the union
-// columns and their kRowGroup values (the FP64 values rounded to FP32, zero
-// where a row has no entry).
+// columns and their kRowGroup values (the FP64 values rounded to FP32 and,
+// with val64, as they are; zero where a row has no entry).
 // ---------------------------------------------------------------------------
 template <bool FILL>
 __global__ __launch_bounds__(kThreads) void k_rowgroup_build(int64_t n, const int* __restrict__ rp,
@@ -315,7 +347,8 @@ __global__ __launch_bounds__(kThreads) void k_rowgroup_build(int64_t n, const in
                                                              int* __restrict__ cnt,
                                                              const int* __restrict__ gp,
                                                              int* __restrict__ col,
-                                                             float* __restrict__ val) {
+                                                             float* __restrict__ val,
+                                                             double* __restrict__ val64) {
   const int64_t ng = (n + kRowGroup - 1) / kRowGroup;
   const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (g >= ng) return;
@@ -335,17 +368,21 @@ __global__ __launch_bounds__(kThreads) void k_rowgroup_build(int64_t n, const in
     for (int r = 0; r < kRowGroup; ++r)
       if (k[r] < e[r]) c = min(c, ci[k[r]]);
     if (c == INT_MAX) break;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    float* vr = reinterpret_cast<float*>(&v);
+    double vr[kRowGroup] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < kRowGroup; ++r)
       if (k[r] < e[r] && ci[k[r]] == c) {
-        if (FILL) vr[r] = (float)v64[k[r]];
+        if (FILL) vr[r] = v64[k[r]];
         ++k[r];
       }
     if (FILL) {
       col[u] = c;
-      reinterpret_cast<float4*>(val)[u] = v;
+      reinterpret_cast<float4*>(val)[u] =
+          make_float4((float)vr[0], (float)vr[1], (float)vr[2], (float)vr[3]);
+      if (val64) {
+        reinterpret_cast<double2*>(val64)[2 * u] = make_double2(vr[0], vr[1]);
+        reinterpret_cast<double2*>(val64)[2 * u + 1] = make_double2(vr[2], vr[3]);
+      }
       ++u;
     }
     ++m;
@@ -358,18 +395,20 @@ hipError_t launch_rowgroup_count(hipStream_t st, int64_t n, const int* rp, const
   if (n < 1 || !rp || !ci || !cnt) return hipErrorInvalidValue;
   const int64_t ng = (n + kRowGroup - 1) / kRowGroup;
   hipLaunchKernelGGL(k_rowgroup_build<false>, dim3((unsigned)((ng + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, st, n, rp, ci, nullptr, cnt, nullptr, nullptr, nullptr);
+                     dim3(kThreads), 0, st, n, rp, ci, nullptr, cnt, nullptr, nullptr, nullptr,
+                     nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_rowgroup_fill(hipStream_t st, int64_t n, const int* rp, const int* ci,
-                                const double* v64, const int* gp, int* col, float* val) {
+                                const double* v64, const int* gp, int* col, float* val,
+                                double* val64) {
   if (n < 1 || !rp || !ci || !v64 || !gp || !col || !val ||
-      reinterpret_cast<uintptr_t>(val) % 16 != 0)
+      reinterpret_cast<uintptr_t>(val) % 16 != 0 || reinterpret_cast<uintptr_t>(val64) % 16 != 0)
     return hipErrorInvalidValue;
   const int64_t ng = (n + kRowGroup - 1) / kRowGroup;
   hipLaunchKernelGGL(k_rowgroup_build<true>, dim3((unsigned)((ng + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, st, n, rp, ci, v64, nullptr, gp, col, val);
+                     dim3(kThreads), 0, st, n, rp, ci, v64, nullptr, gp, col, val, val64);
   return hipGetLastError();
 }
 

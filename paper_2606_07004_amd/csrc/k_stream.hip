@@ -918,7 +918,7 @@ static bool geom_ok(const Geom& g) {
          (g.L >> g.lges) * g.C >= g.ncolv && g.nblk >= 1 && (int64_t)g.nblk * g.rpb >= g.n &&
          g.ts >= 0 && g.ts <= kMaxRowStride &&
          (g.ts == 0 || ((1 << g.lgL) == g.L && g.ts % (64 / g.L) == 0)) &&
-         (g.rg == 0 || (g.rg == 1 && g.lges == 0 && g.ts == 0 && g.C <= 2 && g.xbytes == 4));
+         (g.rg == 0 || (g.rg == 1 && g.lges == 0 && g.ts == 0 && g.C <= 2 && g.xbytes >= 4));
 }
 
 // Resident 256-thread blocks of a kernel on the whole device (cached).
@@ -1177,7 +1177,9 @@ static bool spmm_item_ok(const SpmmItem& it) {
     if (!it.fused.x[v] || it.fused.x[v] == it.W) return false;
   if (it.nf > 0 && it.fused.x[it.nf - 1] != it.X) return false;  // newest vector = the input
   if (it.sx && (!it.sd || it.sx == it.W || it.sx == it.X)) return false;
-  if (g.rg && (!it.rg.gp || !it.rg.col || !it.rg.val || it.vt != VT_F32)) return false;
+  if (g.rg && (!it.rg.gp || !it.rg.col ||
+               !(g.xbytes == 4 ? (it.rg.val && it.vt == VT_F32) : (it.rg.val64 && it.vt == VT_F64))))
+    return false;
   return true;
 }
 

@@ -436,13 +436,17 @@ Geom Run::v1_geom(int ld, const Geom& gu, bool presub) const {
 }
 
 // The matrix's row groups serve the product of FP32 Krylov vectors over its
-// FP32 values.
-bool Run::rg_ok() const { return a_->rg_gp && mixed_ && a_->vt_lo == VT_F32 && xb_ == 4; }
+// FP32 values and that of FP64 vectors over its FP64 values.
+bool Run::rg_ok() const {
+  if (!a_->rg_gp) return false;
+  return mixed_ ? (a_->vt_lo == VT_F32 && xb_ == 4) : (xb_ == 8 && a_->rg_val64);
+}
 RowGroups Run::row_groups() const {
   RowGroups r;
   r.gp = a_->rg_gp;
   r.col = a_->rg_col;
   r.val = a_->rg_val;
+  r.val64 = a_->rg_val64;
   return r;
 }
 
@@ -468,13 +472,15 @@ Geom Run::krylov_geom(int ld, int which) const {
     }
   }
   if (which == 0 && rg_ok() && ld >= 16) {
-    // row groups: one chunk per lane, a row's chunks over that many lanes
-    // (blocks of 16 columns or more: on narrower ones the groups' extra
-    // multiply-adds and shuffles weigh more than the gathers they save)
+    // row groups (blocks of 16 columns or more: on narrower ones the groups'
+    // extra multiply-adds and shuffles weigh more than the gathers they
+    // save): one chunk per lane with FP32 vectors, two with FP64 ones (the
+    // 64-probe covariance: 16 x 2 0.55 ms, 32 x 1 0.67 ms per product)
     const int ncolv = ld / (16 / xb_);
-    Geom g = make_geom_lc(n_, ld, xb_, ncolv, 1);
+    const int C = (xb_ == 8 && ncolv >= 4) ? 2 : 1;
+    Geom g = make_geom_lc(n_, ld, xb_, (ncolv + C - 1) / C, C);
     g.rg = 1;
-    if (ncolv <= 64 && geom_usable(g)) return g;
+    if ((ncolv + C - 1) / C <= 64 && geom_usable(g)) return g;
   }
   if (which == 0 && a_->nnz >= 64 * a_->n) {
     // long rows: one chunk per lane and the row's entries over two lane
@@ -1709,8 +1715,8 @@ ld_status Run::tune_set(int spmm_lanes, int spmm_chunks, int spmm_split, int upd
                      "per split group and the chunks covering the probe block, interleave 0 "
                      "or 1, the row stride 0 or a multiple of the rows per wave (64 / lanes, "
                      "lanes a power of two) up to 32767, the step schedule 0 or 1, row "
-                     "groups 0 or 1 (1: FP32 Krylov vectors on a matrix that keeps row "
-                     "groups, at most 2 chunks, no entry split, no row stride)");
+                     "groups 0 or 1 (1: FP32 or FP64 Krylov vectors on a matrix that keeps "
+                     "row groups, at most 2 chunks, no entry split, no row stride)");
   const int vt = mixed_ ? a_->vt_lo : VT_F64;
   std::lock_guard<std::mutex> lk(a_->tune_mu);
   a_->tune[tune_key(ldB_, xb_, vt, 0)] = {spmm_lanes | (e << 8) | (spmm_interleave << 12) |
@@ -2059,6 +2065,7 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
     if (m->rg_gp) (void)hipFree(m->rg_gp);
     if (m->rg_col) (void)hipFree(m->rg_col);
     if (m->rg_val) (void)hipFree(m->rg_val);
+    if (m->rg_val64) (void)hipFree(m->rg_val64);
     if (m->rg_unused) (void)hipFree(m->rg_unused);
   };
   hipError_t e = hipMalloc(&m->rp, (size_t)(n + 1) * 4);
@@ -2157,13 +2164,14 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
                            ctx->stream);
         if (e == hipSuccess) e = hipMalloc(&m->rg_col, (size_t)nu * 4);
         if (e == hipSuccess) e = hipMalloc(&m->rg_val, (size_t)nu * kRowGroup * 4);
+        if (e == hipSuccess) e = hipMalloc(&m->rg_val64, (size_t)nu * kRowGroup * 8);
         if (e == hipSuccess)
           e = launch_rowgroup_fill(ctx->stream, n, m->rp, m->ci, m->v64, m->rg_gp, m->rg_col,
-                                   m->rg_val);
+                                   m->rg_val, m->rg_val64);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e == hipSuccess) {
           m->rg_nu = nu;
-          m->bytes += ((size_t)ng + 1) * 4 + (size_t)nu * (4 + 4 * kRowGroup);
+          m->bytes += ((size_t)ng + 1) * 4 + (size_t)nu * (4 + 12 * kRowGroup);
         }
       } else if (e == hipSuccess) {
         // the full count missed the ratio the sample promised: no groups (the
@@ -2226,6 +2234,7 @@ ld_status ld_destroy(ld_matrix* a) {
   if (a->rg_gp) (void)hipFree(a->rg_gp);
   if (a->rg_col) (void)hipFree(a->rg_col);
   if (a->rg_val) (void)hipFree(a->rg_val);
+  if (a->rg_val64) (void)hipFree(a->rg_val64);
   if (a->rg_unused) (void)hipFree(a->rg_unused);
   a->ctx->n_matrices.fetch_sub(1);
   delete a;

@@ -158,10 +158,12 @@ struct ld_matrix {
   // requests run wait for them
   double* gpart = nullptr;
   // row groups (FP32 storage, where they gather much less than the rows):
-  // group pointers, union columns and kRowGroup FP32 values per union column
+  // group pointers, union columns and kRowGroup FP32 and FP64 values per
+  // union column
   int* rg_gp = nullptr;
   int* rg_col = nullptr;
   float* rg_val = nullptr;
+  double* rg_val64 = nullptr;
   int64_t rg_nu = 0;
   int* rg_unused = nullptr;  // a count buffer whose groups were not kept
   double lo_hint = 0, hi_hint = 0;

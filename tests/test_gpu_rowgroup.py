@@ -1,4 +1,5 @@
-"""GPU tests of the row-group product (FP32 values, FP32 Krylov vectors).
+"""GPU tests of the row-group product (FP32 values on FP32 Krylov vectors,
+FP64 values on FP64 ones).
 
 A matrix created with FP32 values whose groups of 4 consecutive rows share
 most of their columns keeps, per group, the union of the rows' columns with
@@ -45,28 +46,33 @@ def cov():
     return W.wendland(6002, 48.0, NUG, seed=21)
 
 
-def _pair(L, ctx, a, method, npr, s, m, k, seed, geoms):
+def _pair(L, ctx, a, method, npr, s, m, k, seed, geoms, fp64=False):
     fn = oracle.oslq if method == L.LD_METHOD_OSLQ else oracle.osa_iop
     ref = fn(a, npr, s, m, k, seed, lo_hint=NUG)
     h = ctx.matrix(a, vt=L.LD_VT_FP32, lo_hint=NUG)
+    # FP64 estimates: the oracle's 1e-6, and the two products' W agree to the
+    # last bit (only the order of the fused FP64 inner products differs)
+    tol, ptol = (1e-6, 1e-10) if fp64 else (1e-4, 1e-7)
     try:
-        p = L.make_params(npr, s, m, k, seed, method=method, precision=L.LD_PREC_MIXED)
-        ncolv = (npr + 3) // 4  # 16-byte chunks of an FP32 row
+        p = L.make_params(npr, s, m, k, seed, method=method,
+                          precision=L.LD_PREC_FP64 if fp64 else L.LD_PREC_MIXED)
+        # 16-byte chunks of a row
+        ncolv = (npr + 3) // 4 * (2 if fp64 else 1)
         for lanes, ch, il, sched in geoms:
             got = {}
             for rg in (0, 1):
-                _announce(f"row groups {rg}: method {method} n={a.n} probes {npr} window {k} "
-                          f"L={lanes} C={ch} interleave {il} schedule {sched}")
+                _announce(f"row groups {rg}: method {method} fp64 {fp64} n={a.n} probes {npr} "
+                          f"window {k} L={lanes} C={ch} interleave {il} schedule {sched}")
                 L.ld_tune_set(h, p, lanes, ch, ncolv, 1, 1, il, 0, sched, rg)
                 res = L.ld_estimate_ex(h, p)
                 rel = abs(res.logdet - ref.logdet) / abs(ref.logdet)
                 print(f"  logdet {res.logdet!r} rel {rel:.3e}", flush=True)
-                assert rel <= 1e-4, (rg, rel)
+                assert rel <= tol, (rg, rel)
                 assert L.ld_estimate_ex(h, p).logdet == res.logdet  # reproducible
                 got[rg] = res
             a0, a1 = got[0], got[1]
-            assert abs(a1.logdet - a0.logdet) <= 1e-7 * abs(a0.logdet)
-            assert abs(a1.tr_resid - a0.tr_resid) <= 1e-7 * abs(a0.tr_resid) + 1e-9
+            assert abs(a1.logdet - a0.logdet) <= ptol * abs(a0.logdet)
+            assert abs(a1.tr_resid - a0.tr_resid) <= ptol * abs(a0.tr_resid) + 1e-9
             assert a1.probe_steps == a0.probe_steps
     finally:
         ctx.release(h)
@@ -96,6 +102,14 @@ def test_rowgroup_lanes_not_power_of_two(L, ctx, cov):
     _pair(L, ctx, cov, L.LD_METHOD_OSLQ, 22, 6, 12, 2, 9, [(6, 1, 0, 1), (3, 2, 1, 1)])
 
 
+def test_rowgroup_fp64(L, ctx, cov):
+    # FP64 values on FP64 Krylov vectors: 30 probes (16 chunks of two FP64
+    # values), one and two chunks per lane, both schedules; OSA-IOP
+    _pair(L, ctx, cov, L.LD_METHOD_OSLQ, 30, 10, 14, 2, 11,
+          [(16, 1, 0, 1), (8, 2, 1, 1), (16, 1, 1, 0)], fp64=True)
+    _pair(L, ctx, cov, L.LD_METHOD_OSA_IOP, 30, 10, 10, 2, 12, [(16, 1, 0, 1)], fp64=True)
+
+
 def test_rowgroup_default_and_tuner(L, ctx, cov):
     npr, s, m, k, seed = 30, 10, 12, 2, 8
     h = ctx.matrix(cov, vt=L.LD_VT_FP32, lo_hint=NUG)
@@ -113,10 +127,6 @@ def test_rowgroup_default_and_tuner(L, ctx, cov):
         assert abs(res - base) <= 1e-7 * abs(base)
         L.ld_autotune(h, p, 0)
         assert L.ld_estimate_ex(h, p).logdet == base
-        _announce("row groups refused with FP64 vectors")
-        p64 = L.make_params(npr, s, m, k, seed, precision=L.LD_PREC_FP64)
-        with pytest.raises(L.LdError):
-            L.ld_tune_set(h, p64, 16, 1, 16, 1, 1, 0, 0, 1, 1)
         _announce("row groups refused with three chunks per lane")
         with pytest.raises(L.LdError):
             L.ld_tune_set(h, p, 4, 3, 8, 1, 1, 0, 0, 1, 1)
