@@ -435,7 +435,7 @@ def configs_bench(L, W, args):
                     prod["step_presub"] = tune.get("step_presub", 1) if tune else 1
                     prod["interleaved"] = tune["spmm_interleave"] if tune else 0
                     prod["row_groups"] = tune.get("spmm_row_groups", 0) if tune else 0
-                    kname = (f"ld::k_spmm_rg<float, {tune['spmm_chunks']}, " if prod["row_groups"] else
+                    kname = (f"ld::k_spmm_rg<float, float, {tune['spmm_chunks']}, " if prod["row_groups"] else
                              f"ld::k_spmm<float, float, {tune['spmm_chunks'] if tune else 0}, ")
                     ks = [v for kn, v in (pr or {}).get("geometries", {}).get(geo, {}).items()
                           if kn.startswith(kname)]

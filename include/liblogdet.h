@@ -214,10 +214,11 @@ const char* ld_last_error(void);
  * nnz; col_idx[nnz] in [0, n), sorted and unique within each row; every
  * diagonal entry present and > 0 (else LD_E_NOT_SPD).  values are FP64 and
  * stored as `vt`; an FP64 copy is kept as well for LD_PREC_FP64 runs.
- * With LD_VT_FP32 the matrix may also keep row groups (see ld_autotune):
- * (4 + 16 + 32) bytes per union column (its column, 4 FP32 and 4 FP64
- * values), built on the device here when groups of 4 rows hold at least 2
- * entries per union column (so at most 26 bytes per entry).
+ * With LD_VT_FP32 or LD_VT_FP64 the matrix may also keep row groups (see
+ * ld_autotune): per union column its index and 4 FP64 values (plus 4 FP32
+ * ones with LD_VT_FP32), 36 or 52 bytes, built on the device here when
+ * groups of 4 rows hold at least 2 entries per union column (so at most
+ * 18 or 26 bytes per entry).
  * lambda_lo_hint / lambda_hi_hint > 0 replace the Gershgorin bounds
  * (Section 2.1); a Gershgorin lower bound <= 0 without a hint is replaced by
  * 1e-6 * lambda_hi.  n and nnz must fit int32. */
@@ -293,19 +294,20 @@ ld_status ld_request_bytes(ld_matrix* a, const ld_params* p, uint64_t* bytes);
  * spmm_row_stride), which ld_autotune tries on every power-of-two L with the
  * strides of the matrix's most frequent column offsets (at most two, each in
  * a quarter of the sampled rows or more).
- * Matrices created with LD_VT_FP32 whose groups of 4 consecutive rows share
- * most of their columns (at least 2 entries per column of the group's
- * union, as on covariance matrices of sorted points) also keep those groups:
- * the union of the 4 rows' columns with one FP32 value per row and column
- * (zero where a row has no entry), about (4 + 16) bytes per union column.
- * The product of FP32 Krylov vectors (over the FP32 values) or FP64 ones
- * (over the FP64 values) can then gather each union column's probe row once
- * for the 4 rows (spmm_row_groups; the untuned default on such matrices for
- * blocks of 16 columns or more, with one chunk per lane for FP32 vectors
- * and two for FP64), which ld_autotune tries in every plain geometry of at
- * most 2 chunks per lane; a row's sum sees its nonzero terms in CSR order,
- * so the product's output is the CSR product's.  The groups are built on
- * the device when the matrix is created.
+ * Matrices created with LD_VT_FP32 or LD_VT_FP64 whose groups of 4
+ * consecutive rows share most of their columns (at least 2 entries per
+ * column of the group's union, as on covariance matrices of sorted points)
+ * also keep those groups: the union of the 4 rows' columns with one value
+ * per row and column (zero where a row has no entry), in FP64 and, with
+ * LD_VT_FP32, FP32.  The product then gathers each union column's probe
+ * row once for the 4 rows (spmm_row_groups), over the values the estimate
+ * reads (FP32 or FP64 storage values on FP32 Krylov vectors, FP64 values on
+ * FP64 vectors; not with FP16 vectors or BF16 values); it is the untuned
+ * default on such matrices for blocks of 16 columns or more, with one chunk
+ * per lane for FP32 vectors and two for FP64, and ld_autotune tries it in
+ * every plain geometry of at most 2 chunks per lane.  A row's sum sees its
+ * nonzero terms in CSR order, so the product's output is the CSR product's.
+ * The groups are built on the device when the matrix is created.
  * ld_autotune times every such (L, C, E) with L a power of two and at most
  * half a row of idle chunks on this matrix, and L = ceil(chunks / C) where
  * that is not a power of two, for the probe-block shapes and
@@ -360,7 +362,8 @@ ld_status ld_autotune(ld_matrix* a, const ld_params* p, int32_t reps, ld_tune_re
  * product subtracts the second-newest window vector, the default; 0: the
  * update subtracts the whole window; see ld_tune_result), and the product
  * over the matrix's row groups (spmm_row_groups 1: FP32 or FP64 Krylov
- * vectors on a matrix that keeps them, C <= 2, no entry split, no row tiles) or its CSR
+ * vectors on a matrix that keeps them, not BF16 values, C <= 2, no entry
+ * split, no row tiles) or its CSR
  * rows (0).  Any (L, C, E) with L <= 64, 1 <= C <= 4, E in {1, 2, 4, 8},
  * E <= L, C <= 2 when E > 1, and (L / E) * C chunks covering the block is
  * accepted, where L is a power of two when E > 1; anything else is

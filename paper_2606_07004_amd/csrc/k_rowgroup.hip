@@ -1,5 +1,5 @@
 // Row-group sparse product W = opscale * (Q X) * diag(xmult), FP32 values on
-// FP32 probe blocks or FP64 values on FP64 blocks (Alg 1's operator
+// FP32 probe blocks or FP64 values on FP64 or FP32 blocks (Alg 1's operator
 // application, as in the CSR product of k_stream.hip, over the matrix's row
 // groups).
 //
@@ -61,10 +61,12 @@ struct Vals4 {
   }
 };
 
-// T: the element type of the values and the probe blocks (float or double);
-// the sums are in T, as in the CSR product with values and vectors of T.
-template <typename T, int C, int NF>
+// VT: the values' type, T: the probe blocks' (FP32 values on FP32 blocks,
+// FP64 on FP64, FP64 on FP32); the sums are in FP64 when either is, else in
+// FP32, as in the CSR product of the same types.
+template <typename VT, typename T, int C, int NF>
 __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
+  using A = typename std::conditional<sizeof(VT) == 8 || sizeof(T) == 8, double, float>::type;
   constexpr int VEC = V16<T>::N;
   constexpr int G = kRowGroup;
   static_assert(G == 4, "four values per union column");
@@ -76,14 +78,14 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
   // union entries whose (column, values) a lane loads per round (four with
   // FP32 values and one chunk per lane: fewer rounds of dependent entry
   // loads per group)
-  constexpr int KE = (sizeof(T) == 4 && C == 1) ? 4 : 2;
+  constexpr int KE = (sizeof(VT) == 4 && C == 1) ? 4 : 2;
   __shared__ double red[FUSED ? kThreads * VEC * C : 1];
-  __shared__ T scs[kMaxLd];       // opscale * xmult[col]
+  __shared__ A scs[kMaxLd];       // opscale * xmult[col]
   __shared__ double scf[kMaxLd];  // sd[col] * smult[col] (early subtraction)
   const RowMap rm = RowMap::lanes(q.L, 0);
   const int ld = q.ld;
   for (int i = threadIdx.x; i < ld; i += kThreads) {
-    scs[i] = T(q.opscale * (q.xmult ? q.xmult[i] : 1.0));
+    scs[i] = A(q.opscale * (q.xmult ? q.xmult[i] : 1.0));
     if (q.sx) scf[i] = q.sd[i] * (q.smult ? q.smult[i] : 1.0);
   }
   bool okc[C];
@@ -110,7 +112,7 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
   const int nn = (int)q.n;  // n < 2^31
   const int ng = (nn + G - 1) / G;
   const int nchunk = (ng + rm.rpi - 1) / rm.rpi;
-  const T* vals = static_cast<const T*>(q.val);
+  const VT* vals = static_cast<const VT*>(q.val);
   const T* X = static_cast<const T*>(q.X);
   T* W = static_cast<T*>(q.W);
   const T* sx = static_cast<const T*>(q.sx);
@@ -119,22 +121,23 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
     const int grp = ch * rm.rpi + rm.rg;
     if (!rm.on || ch >= nchunk || grp >= ng) continue;
     const int r0 = grp * G;
-    T acc[G][C][VEC];
+    A acc[G][C][VEC];
 #pragma unroll
     for (int r = 0; r < G; ++r)
 #pragma unroll
       for (int c = 0; c < C; ++c)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[r][c][e] = T(0);
+        for (int e = 0; e < VEC; ++e) acc[r][c][e] = A(0);
     // one union column into the group's rows
-    auto add = [&](const V16<T> (&x)[C], const Vals4<T>& a) {
+    auto add = [&](const V16<T> (&x)[C], const Vals4<VT>& a) {
 #pragma unroll
       for (int c = 0; c < C; ++c)
         if (okc[c]) {
 #pragma unroll
           for (int e = 0; e < VEC; ++e)
 #pragma unroll
-            for (int r = 0; r < G; ++r) acc[r][c][e] = fma(a.v[r], x[c].v[e], acc[r][c][e]);
+            for (int r = 0; r < G; ++r)
+              acc[r][c][e] = fma(A(a.v[r]), A(x[c].v[e]), acc[r][c][e]);
         }
     };
     const int ub = q.gp[grp], ue = q.gp[grp + 1];
@@ -143,13 +146,13 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
     // by lane shuffles; two entries' gathers in flight, in union order
     for (int base = ub; base < ue; base += rm.L * KE) {
       int myc[KE];
-      Vals4<T> myv[KE];
+      Vals4<VT> myv[KE];
 #pragma unroll
       for (int u = 0; u < KE; ++u) {
         const int kk = base + rm.gl + rm.L * u;
         myc[u] = r0;
 #pragma unroll
-        for (int r = 0; r < G; ++r) myv[u].v[r] = T(0);
+        for (int r = 0; r < G; ++r) myv[u].v[r] = VT(0);
         if (kk < ue) {
           myc[u] = q.col[kk];
           myv[u].load(vals, kk);
@@ -162,7 +165,7 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
         int e = 0;
         for (; e + 2 <= cnt; e += 2) {
           const int c0 = __shfl(myc[u], rm.lb + e), c1 = __shfl(myc[u], rm.lb + e + 1);
-          const Vals4<T> a0 = myv[u].from(rm.lb + e), a1 = myv[u].from(rm.lb + e + 1);
+          const Vals4<VT> a0 = myv[u].from(rm.lb + e), a1 = myv[u].from(rm.lb + e + 1);
           V16<T> x0[C], x1[C];
 #pragma unroll
           for (int c = 0; c < C; ++c)
@@ -175,7 +178,7 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
         }
         if (e < cnt) {
           const int c0 = __shfl(myc[u], rm.lb + e);
-          const Vals4<T> a0 = myv[u].from(rm.lb + e);
+          const Vals4<VT> a0 = myv[u].from(rm.lb + e);
           V16<T> x0[C];
 #pragma unroll
           for (int c = 0; c < C; ++c)
@@ -192,7 +195,7 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
       for (int c = 0; c < C; ++c)
         if (okc[c]) {
           V16<T> out;
-          const T* sce = scs + colc[c];
+          const A* sce = scs + colc[c];
           if (sx) {
             V16<T> xs;
             xs.load_nt(sx + (size_t)row * ld + colc[c]);  // read once per step
@@ -202,7 +205,7 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
               out.v[e] = T(fma(-cfe[e], double(xs.v[e]), double(acc[r][c][e] * sce[e])));
           } else {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) out.v[e] = acc[r][c][e] * sce[e];
+            for (int e = 0; e < VEC; ++e) out.v[e] = T(acc[r][c][e] * sce[e]);
           }
           out.store_nt(W + (size_t)row * ld + colc[c]);
           if constexpr (FUSED) {
@@ -245,22 +248,24 @@ __device__ inline void rg_body(const RgDesc& q, int bk, int nbk) {
 }
 
 // blocks per CU at which every instance fits its registers without spills
-template <typename T, int C, int NF>
+template <typename VT, typename T, int C, int NF>
 constexpr int rg_min_blocks() {
-  return (C == 1 && sizeof(T) == 4) ? (NF == 2 ? 4 : 5) : (NF == 2 ? 3 : 4);
+  // FP64 values on FP32 blocks keep FP64 sums of 4 elements per chunk
+  if (sizeof(VT) == 8 && sizeof(T) == 4 && C == 2) return NF == 2 ? 2 : 3;
+  return (C == 1 && sizeof(VT) == 4 && sizeof(T) == 4) ? (NF == 2 ? 4 : 5) : (NF == 2 ? 3 : 4);
 }
 
-template <typename T, int C, int NF>
-__global__ __launch_bounds__(kThreads, (rg_min_blocks<T, C, NF>())) void k_spmm_rg(
+template <typename VT, typename T, int C, int NF>
+__global__ __launch_bounds__(kThreads, (rg_min_blocks<VT, T, C, NF>())) void k_spmm_rg(
     BatchArgs<RgDesc> bt) {
   int r = 0;
   while (r + 1 < bt.count && (int)blockIdx.x >= bt.off[r + 1]) ++r;
-  rg_body<T, C, NF>(bt.d[r], (int)blockIdx.x - bt.off[r], bt.off[r + 1] - bt.off[r]);
+  rg_body<VT, T, C, NF>(bt.d[r], (int)blockIdx.x - bt.off[r], bt.off[r + 1] - bt.off[r]);
 }
 
-template <typename T, int C, int NF>
+template <typename VT, typename T, int C, int NF>
 static hipError_t rg_launch(hipStream_t st, SpmmItem* items, const int* idx, int cnt) {
-  auto fn = k_spmm_rg<T, C, NF>;
+  auto fn = k_spmm_rg<VT, T, C, NF>;
   BatchArgs<RgDesc> bt{};
   bt.count = cnt;
   int off = 0;
@@ -272,8 +277,8 @@ static hipError_t rg_launch(hipStream_t st, SpmmItem* items, const int* idx, int
     d.n = it.g.n;
     d.gp = it.rg.gp;
     d.col = it.rg.col;
-    d.val = sizeof(T) == 4 ? static_cast<const void*>(it.rg.val)
-                           : static_cast<const void*>(it.rg.val64);
+    d.val = sizeof(VT) == 4 ? static_cast<const void*>(it.rg.val)
+                            : static_cast<const void*>(it.rg.val64);
     d.X = it.X;
     d.W = it.W;
     d.xmult = it.xmult;
@@ -304,41 +309,41 @@ hipError_t launch_spmm_rg_group(hipStream_t st, SpmmItem* items, const int* idx,
   const SpmmItem& it = items[idx[0]];
   for (int q = 0; q < cnt; ++q) {
     const SpmmItem& x = items[idx[q]];
-    // FP32 values on FP32 blocks, or FP64 values on FP64 blocks
-    const bool f32 = x.g.xbytes == 4 && x.vt == VT_F32;
-    const bool f64 = x.g.xbytes == 8 && x.vt == VT_F64;
-    const void* val = f32 ? static_cast<const void*>(x.rg.val) : static_cast<const void*>(x.rg.val64);
-    if (!x.g.rg || !(f32 || f64) || x.g.xbytes != it.g.xbytes || x.g.C != it.g.C ||
+    // FP32 values on FP32 blocks, FP64 values on FP64 or FP32 blocks
+    const bool ok = (x.g.xbytes == 4 && (x.vt == VT_F32 || x.vt == VT_F64)) ||
+                    (x.g.xbytes == 8 && x.vt == VT_F64);
+    const void* val = x.vt == VT_F32 ? static_cast<const void*>(x.rg.val)
+                                     : static_cast<const void*>(x.rg.val64);
+    if (!x.g.rg || !ok || x.g.xbytes != it.g.xbytes || x.vt != it.vt || x.g.C != it.g.C ||
         x.nf != it.nf || x.g.lges != 0 || x.g.ts != 0 || !x.rg.gp || !x.rg.col || !val ||
         reinterpret_cast<uintptr_t>(val) % 16 != 0)
       return hipErrorInvalidValue;
   }
   const int C = it.g.C, nf = it.nf;
-  auto by_nf = [&](auto t, auto c) -> hipError_t {
+  auto by_nf = [&](auto v, auto t, auto c) -> hipError_t {
+    using VT = decltype(v);
     using T = decltype(t);
     constexpr int CC = decltype(c)::value;
-    if (nf == 0) return rg_launch<T, CC, 0>(st, items, idx, cnt);
-    if (nf == 1) return rg_launch<T, CC, 1>(st, items, idx, cnt);
-    return rg_launch<T, CC, 2>(st, items, idx, cnt);
+    if (nf == 0) return rg_launch<VT, T, CC, 0>(st, items, idx, cnt);
+    if (nf == 1) return rg_launch<VT, T, CC, 1>(st, items, idx, cnt);
+    return rg_launch<VT, T, CC, 2>(st, items, idx, cnt);
   };
-  using C1 = std::integral_constant<int, 1>;
-  using C2 = std::integral_constant<int, 2>;
-  if (it.g.xbytes == 4) {
-    if (C == 1) return by_nf(float{}, C1{});
-    if (C == 2) return by_nf(float{}, C2{});
-  } else {
-    if (C == 1) return by_nf(double{}, C1{});
-    if (C == 2) return by_nf(double{}, C2{});
-  }
-  return hipErrorInvalidValue;
+  auto by_c = [&](auto v, auto t) -> hipError_t {
+    if (C == 1) return by_nf(v, t, std::integral_constant<int, 1>{});
+    if (C == 2) return by_nf(v, t, std::integral_constant<int, 2>{});
+    return hipErrorInvalidValue;
+  };
+  if (it.g.xbytes == 8) return by_c(double{}, double{});
+  if (it.vt == VT_F64) return by_c(double{}, float{});
+  return by_c(float{}, float{});
 }
 
 // ---------------------------------------------------------------------------
 // Row groups from the CSR arrays on the device: one thread per group merges
 // its rows' sorted column lists.  Pass 1 counts each group's union columns
 // (cnt[g]); pass 2, given gp (the exclusive prefix sums), writes the union
-// columns and their kRowGroup values (the FP64 values rounded to FP32 and,
-// with val64, as they are; zero where a row has no entry).
+// columns and their kRowGroup values (with val, the FP64 values rounded to
+// FP32; with val64, as they are; zero where a row has no entry).
 // ---------------------------------------------------------------------------
 template <bool FILL>
 __global__ __launch_bounds__(kThreads) void k_rowgroup_build(int64_t n, const int* __restrict__ rp,
@@ -377,8 +382,9 @@ __global__ __launch_bounds__(kThreads) void k_rowgroup_build(int64_t n, const in
       }
     if (FILL) {
       col[u] = c;
-      reinterpret_cast<float4*>(val)[u] =
-          make_float4((float)vr[0], (float)vr[1], (float)vr[2], (float)vr[3]);
+      if (val)
+        reinterpret_cast<float4*>(val)[u] =
+            make_float4((float)vr[0], (float)vr[1], (float)vr[2], (float)vr[3]);
       if (val64) {
         reinterpret_cast<double2*>(val64)[2 * u] = make_double2(vr[0], vr[1]);
         reinterpret_cast<double2*>(val64)[2 * u + 1] = make_double2(vr[2], vr[3]);
@@ -403,7 +409,7 @@ hipError_t launch_rowgroup_count(hipStream_t st, int64_t n, const int* rp, const
 hipError_t launch_rowgroup_fill(hipStream_t st, int64_t n, const int* rp, const int* ci,
                                 const double* v64, const int* gp, int* col, float* val,
                                 double* val64) {
-  if (n < 1 || !rp || !ci || !v64 || !gp || !col || !val ||
+  if (n < 1 || !rp || !ci || !v64 || !gp || !col || (!val && !val64) ||
       reinterpret_cast<uintptr_t>(val) % 16 != 0 || reinterpret_cast<uintptr_t>(val64) % 16 != 0)
     return hipErrorInvalidValue;
   const int64_t ng = (n + kRowGroup - 1) / kRowGroup;

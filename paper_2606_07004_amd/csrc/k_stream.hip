@@ -1178,7 +1178,8 @@ static bool spmm_item_ok(const SpmmItem& it) {
   if (it.nf > 0 && it.fused.x[it.nf - 1] != it.X) return false;  // newest vector = the input
   if (it.sx && (!it.sd || it.sx == it.W || it.sx == it.X)) return false;
   if (g.rg && (!it.rg.gp || !it.rg.col ||
-               !(g.xbytes == 4 ? (it.rg.val && it.vt == VT_F32) : (it.rg.val64 && it.vt == VT_F64))))
+               !(it.vt == VT_F32 ? (it.rg.val && g.xbytes == 4)
+                                 : (it.vt == VT_F64 && it.rg.val64))))
     return false;
   return true;
 }

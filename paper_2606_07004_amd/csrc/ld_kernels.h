@@ -46,8 +46,9 @@ struct Geom {
                    // tile of 4 rows of S rows), so a stencil's +-S neighbours of
                    // one wave's rows are the rows its sibling waves gather
   int rg = 0;      // product only: 1 = the matrix's row groups (RowGroups below)
-                   // instead of its CSR rows; FP32 values and vectors or FP64
-                   // values and vectors, C <= 2, no entry split, no row tiles
+                   // instead of its CSR rows; FP32 values on FP32 vectors or
+                   // FP64 values on FP64 or FP32 vectors, C <= 2, no entry
+                   // split, no row tiles
 };
 Geom make_geom(int64_t n, int ld, int xbytes);
 // The same with an explicit lanes-per-row L and chunks per lane C (an
@@ -72,8 +73,8 @@ struct RowGroups {
 // Row groups of an n-row CSR matrix (rows sorted) on the device: cnt[g] =
 // group g's union columns; then, with gp the exclusive prefix sums of cnt
 // (gp[g] = first union column of group g), the union columns col and their
-// values val (v64 rounded to FP32, kRowGroup per column) and, when val64 is
-// not null, val64 (v64 itself).
+// values, kRowGroup per column: val (v64 rounded to FP32) and val64 (v64
+// itself), each when not null.
 hipError_t launch_rowgroup_count(hipStream_t st, int64_t n, const int* rp, const int* ci, int* cnt);
 hipError_t launch_rowgroup_fill(hipStream_t st, int64_t n, const int* rp, const int* ci,
                                 const double* v64, const int* gp, int* col, float* val,
@@ -194,7 +195,7 @@ __device__ inline double gsrc_at(const GSrc& g, int64_t row, int j) {
 // window vector, sd its coefficient row, smult its multipliers).
 // With g.rg the product reads the row groups `rg` instead of rp / ci / va
 // (their FP32 values with vt = VT_F32 on FP32 blocks, their FP64 values with
-// vt = VT_F64 on FP64 blocks).
+// vt = VT_F64 on FP64 or FP32 blocks).
 hipError_t launch_spmm(hipStream_t st, const Geom& g, const int* rp, const int* ci,
                        const void* va, int vt, const void* X, void* W,
                        const double* xmult, double opscale, const VecSet* fused, int nf,

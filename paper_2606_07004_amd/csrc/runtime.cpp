@@ -435,11 +435,14 @@ Geom Run::v1_geom(int ld, const Geom& gu, bool presub) const {
   return geom_usable(g) ? g : gu;
 }
 
-// The matrix's row groups serve the product of FP32 Krylov vectors over its
-// FP32 values and that of FP64 vectors over its FP64 values.
+// The matrix's row groups serve the products over the values that the
+// estimate reads: FP32 (or FP64, on FP64 storage) values with FP32 Krylov
+// vectors, FP64 values with FP64 vectors.
 bool Run::rg_ok() const {
   if (!a_->rg_gp) return false;
-  return mixed_ ? (a_->vt_lo == VT_F32 && xb_ == 4) : (xb_ == 8 && a_->rg_val64);
+  if (!mixed_) return xb_ == 8 && a_->rg_val64;
+  // mixed: the values in their storage type, FP32 or FP64, on FP32 vectors
+  return xb_ == 4 && (a_->vt_lo == VT_F32 ? a_->rg_val != nullptr : a_->rg_val64 != nullptr);
 }
 RowGroups Run::row_groups() const {
   RowGroups r;
@@ -1964,7 +1967,7 @@ static uint16_t double_to_bf16_rne(double d) {
 }
 
 // Row groups of kRowGroup consecutive rows (the sorted union of their
-// columns, kRowGroup FP32 values per union column, zero where a row has no
+// columns, kRowGroup values per union column, zero where a row has no
 // entry), kept where they gather much less than the rows: at least
 // kRowGroupMinRatio entries per union column (covariance-like matrices; a
 // 3D Laplacian has 1.3, a random graph 1.0), estimated first on a sample of
@@ -2134,8 +2137,8 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
         });
     }
   }
-  // row groups, for the FP32 values of mixed-precision products
-  if (e == hipSuccess && m->vt_lo == VT_F32) {
+  // row groups (FP32 or FP64 storage; BF16 values keep the CSR product)
+  if (e == hipSuccess && (m->vt_lo == VT_F32 || m->vt_lo == VT_F64)) {
     const int64_t ng = (n + kRowGroup - 1) / kRowGroup;
     const int64_t ns = std::min<int64_t>(ng, 256);
     int64_t se = 0, su = 0;
@@ -2163,7 +2166,10 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
         e = hipMemcpyAsync(m->rg_gp, gp.data(), ((size_t)ng + 1) * 4, hipMemcpyHostToDevice,
                            ctx->stream);
         if (e == hipSuccess) e = hipMalloc(&m->rg_col, (size_t)nu * 4);
-        if (e == hipSuccess) e = hipMalloc(&m->rg_val, (size_t)nu * kRowGroup * 4);
+        // FP32 values only with FP32 storage (mixed runs read them); FP64
+        // values always (FP64 runs, and mixed runs on FP64 storage)
+        const bool f32 = m->vt_lo == VT_F32;
+        if (e == hipSuccess && f32) e = hipMalloc(&m->rg_val, (size_t)nu * kRowGroup * 4);
         if (e == hipSuccess) e = hipMalloc(&m->rg_val64, (size_t)nu * kRowGroup * 8);
         if (e == hipSuccess)
           e = launch_rowgroup_fill(ctx->stream, n, m->rp, m->ci, m->v64, m->rg_gp, m->rg_col,
@@ -2171,7 +2177,7 @@ ld_status ld_create_csr(ld_ctx* ctx, int64_t n, int64_t nnz, const int32_t* row_
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e == hipSuccess) {
           m->rg_nu = nu;
-          m->bytes += ((size_t)ng + 1) * 4 + (size_t)nu * (4 + 12 * kRowGroup);
+          m->bytes += ((size_t)ng + 1) * 4 + (size_t)nu * (4 + (f32 ? 12 : 8) * kRowGroup);
         }
       } else if (e == hipSuccess) {
         // the full count missed the ratio the sample promised: no groups (the

@@ -157,9 +157,9 @@ struct ld_matrix {
   // synchronises the device, which would make a matrix created while
   // requests run wait for them
   double* gpart = nullptr;
-  // row groups (FP32 storage, where they gather much less than the rows):
-  // group pointers, union columns and kRowGroup FP32 and FP64 values per
-  // union column
+  // row groups (FP32 or FP64 storage, where they gather much less than the
+  // rows): group pointers, union columns and kRowGroup values per union
+  // column, FP64 and (FP32 storage) FP32
   int* rg_gp = nullptr;
   int* rg_col = nullptr;
   float* rg_val = nullptr;

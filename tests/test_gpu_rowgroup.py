@@ -1,8 +1,8 @@
 """GPU tests of the row-group product (FP32 values on FP32 Krylov vectors,
-FP64 values on FP64 ones).
+FP64 values on FP64 or FP32 ones).
 
-A matrix created with FP32 values whose groups of 4 consecutive rows share
-most of their columns keeps, per group, the union of the rows' columns with
+A matrix created with FP32 or FP64 values whose groups of 4 consecutive rows
+share most of their columns keeps, per group, the union of the rows' columns with
 one value per row (zero where a row has no entry); the product can read the
 groups instead of the CSR rows and gather each union column's probe row once
 for the group.  A row's sum sees its nonzero terms in CSR order, so the
@@ -46,10 +46,10 @@ def cov():
     return W.wendland(6002, 48.0, NUG, seed=21)
 
 
-def _pair(L, ctx, a, method, npr, s, m, k, seed, geoms, fp64=False):
+def _pair(L, ctx, a, method, npr, s, m, k, seed, geoms, fp64=False, vt=None):
     fn = oracle.oslq if method == L.LD_METHOD_OSLQ else oracle.osa_iop
     ref = fn(a, npr, s, m, k, seed, lo_hint=NUG)
-    h = ctx.matrix(a, vt=L.LD_VT_FP32, lo_hint=NUG)
+    h = ctx.matrix(a, vt=L.LD_VT_FP32 if vt is None else vt, lo_hint=NUG)
     # FP64 estimates: the oracle's 1e-6, and the two products' W agree to the
     # last bit (only the order of the fused FP64 inner products differs)
     tol, ptol = (1e-6, 1e-10) if fp64 else (1e-4, 1e-7)
@@ -110,6 +110,12 @@ def test_rowgroup_fp64(L, ctx, cov):
     _pair(L, ctx, cov, L.LD_METHOD_OSA_IOP, 30, 10, 10, 2, 12, [(16, 1, 0, 1)], fp64=True)
 
 
+def test_rowgroup_fp64_storage_mixed(L, ctx, cov):
+    # FP64 storage: mixed runs read the FP64 values (FP64 sums) on FP32 vectors
+    _pair(L, ctx, cov, L.LD_METHOD_OSLQ, 30, 10, 14, 2, 13, [(8, 1, 0, 1), (4, 2, 1, 1)],
+          vt=L.LD_VT_FP64)
+
+
 def test_rowgroup_default_and_tuner(L, ctx, cov):
     npr, s, m, k, seed = 30, 10, 12, 2, 8
     h = ctx.matrix(cov, vt=L.LD_VT_FP32, lo_hint=NUG)
@@ -133,7 +139,7 @@ def test_rowgroup_default_and_tuner(L, ctx, cov):
     finally:
         ctx.release(h)
     _announce("row groups refused where the matrix keeps none")
-    for a, vt in ((W.lap3d(20, 1e-2), L.LD_VT_FP32), (cov, L.LD_VT_FP64)):
+    for a, vt in ((W.lap3d(20, 1e-2), L.LD_VT_FP32), (cov, L.LD_VT_BF16)):
         h = ctx.matrix(a, vt=vt, lo_hint=NUG if a is cov else 0.0)
         try:
             p = L.make_params(npr, s, m, k, seed, precision=L.LD_PREC_MIXED)
