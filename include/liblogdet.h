@@ -303,9 +303,10 @@ ld_status ld_request_bytes(ld_matrix* a, const ld_params* p, uint64_t* bytes);
  * row once for the 4 rows (spmm_row_groups), over the values the estimate
  * reads (FP32 or FP64 storage values on FP32 Krylov vectors, FP64 values on
  * FP64 vectors; not with FP16 vectors or BF16 values); it is the untuned
- * default on such matrices for blocks of 16 columns or more, with one chunk
- * per lane for FP32 vectors and two for FP64, and ld_autotune tries it in
- * every plain geometry of at most 2 chunks per lane.  A row's sum sees its
+ * default on such matrices for blocks of 16 columns or more where values
+ * and vectors have the same type, with one chunk per lane for FP32 and two
+ * for FP64, and ld_autotune tries it in every plain geometry of at most 2
+ * chunks per lane.  A row's sum sees its
  * nonzero terms in CSR order, so the product's output is the CSR product's.
  * The groups are built on the device when the matrix is created.
  * ld_autotune times every such (L, C, E) with L a power of two and at most

@@ -474,11 +474,15 @@ Geom Run::krylov_geom(int ld, int which) const {
       if (geom_usable(g) && (g.rg == 0 || rg_ok())) return g;
     }
   }
-  if (which == 0 && rg_ok() && ld >= 16) {
+  if (which == 0 && rg_ok() && ld >= 16 && !(mixed_ && a_->vt_lo == VT_F64)) {
     // row groups (blocks of 16 columns or more: on narrower ones the groups'
     // extra multiply-adds and shuffles weigh more than the gathers they
     // save): one chunk per lane with FP32 vectors, two with FP64 ones (the
-    // 64-probe covariance: 16 x 2 0.55 ms, 32 x 1 0.67 ms per product)
+    // 64-probe covariance: 16 x 2 0.55 ms, 32 x 1 0.67 ms per product).
+    // FP64 values on FP32 vectors keep the CSR product by default (their
+    // FP64 sums of 4 rows cost occupancy: on that covariance 22.3 against
+    // 21.3 ms per estimate); the autotuner and ld_tune_set can still take
+    // the groups there
     const int ncolv = ld / (16 / xb_);
     const int C = (xb_ == 8 && ncolv >= 4) ? 2 : 1;
     Geom g = make_geom_lc(n_, ld, xb_, (ncolv + C - 1) / C, C);
