@@ -491,6 +491,15 @@ ld_status ld_debug_copy(ld_ctx* ctx, uint64_t bytes, int32_t reps, double* ms);
  * (reads + writes) * bytes. */
 ld_status ld_debug_stream(ld_ctx* ctx, uint64_t bytes, int32_t reads, int32_t writes,
                           int32_t reps, double* ms);
+/* Debug: the matrix's row groups (the product's alternative storage, see
+ * ld_autotune).  *n_union = the number of union columns (0: the matrix
+ * keeps none).  When gp, col and val are all non-NULL, also copies into
+ * them (caller-owned host memory, sized from a first call with NULL
+ * arrays) the group pointers gp[ceil(n / 4) + 1], the union columns
+ * col[n_union] and their FP64 values val[4 n_union] (val[4 u + r]: row r
+ * of the group, zero where that row has no entry).  Blocking. */
+ld_status ld_debug_row_groups(ld_matrix* a, int64_t* n_union, int32_t* gp, int32_t* col,
+                              double* val);
 
 #ifdef __cplusplus
 }

@@ -2526,6 +2526,21 @@ ld_status ld_debug_copy(ld_ctx* ctx, uint64_t bytes, int32_t reps, double* ms) {
   return LD_OK;
 }
 
+ld_status ld_debug_row_groups(ld_matrix* a, int64_t* n_union, int32_t* gp, int32_t* col,
+                              double* val) {
+  if (!a || !n_union) return set_error(LD_E_INVALID_ARG, "null argument");
+  *n_union = a->rg_gp ? a->rg_nu : 0;
+  if (!gp || !col || !val || !a->rg_gp) return LD_OK;
+  ld_ctx* ctx = a->ctx;
+  std::lock_guard<std::mutex> lk(ctx->est_mu);
+  LD_HIP_API(hipSetDevice(ctx->device));
+  const int64_t ng = (a->n + kRowGroup - 1) / kRowGroup;
+  LD_HIP_API(hipMemcpy(gp, a->rg_gp, ((size_t)ng + 1) * 4, hipMemcpyDeviceToHost));
+  LD_HIP_API(hipMemcpy(col, a->rg_col, (size_t)a->rg_nu * 4, hipMemcpyDeviceToHost));
+  LD_HIP_API(hipMemcpy(val, a->rg_val64, (size_t)a->rg_nu * kRowGroup * 8, hipMemcpyDeviceToHost));
+  return LD_OK;
+}
+
 ld_status ld_debug_stream(ld_ctx* ctx, uint64_t bytes, int32_t reads, int32_t writes,
                           int32_t reps, double* ms) {
   if (!ctx || !ms || bytes < 16 || reps < 1 || reads < 1 || reads > 3 || writes < 0 || writes > 1)

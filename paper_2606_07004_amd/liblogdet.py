@@ -157,6 +157,7 @@ _SIGNATURES = [
                                     _DP]),
     ("ld_debug_probes", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, C.c_int32,
                                     C.c_int32, _DP]),
+    ("ld_debug_row_groups", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), _IP, _IP, _DP]),
 ]
 
 
@@ -421,6 +422,21 @@ def ld_debug_stream(ctx, nbytes: int, reads: int, writes: int, reps: int = 10) -
     ms = C.c_double()
     _check(lib().ld_debug_stream(ctx, nbytes, reads, writes, reps, C.byref(ms)))
     return ms.value
+
+
+def ld_debug_row_groups(a, n: int):
+    """The row groups matrix `a` (n rows) keeps: None, or (gp, col, val) with
+    val of shape [union columns][4] (FP64)."""
+    nu = C.c_int64()
+    _check(lib().ld_debug_row_groups(a, C.byref(nu), None, None, None))
+    if nu.value == 0:
+        return None
+    gp = np.zeros((n + 3) // 4 + 1, dtype=np.int32)
+    col = np.zeros(nu.value, dtype=np.int32)
+    val = np.zeros((nu.value, 4), dtype=np.float64)
+    _check(lib().ld_debug_row_groups(a, C.byref(nu), gp.ctypes.data_as(_IP),
+                                     col.ctypes.data_as(_IP), val.ctypes.data_as(_DP)))
+    return gp, col, val
 
 
 class Context:

@@ -11,6 +11,7 @@ the rows in another order (FP64).  Every case pins the CSR product and then
 the row-group product in the same geometry and compares the two estimates
 (tightly) and each with the CPU FP64 oracle (the mixed-precision 1e-4).
 """
+import numpy as np
 import pytest
 
 import oracle
@@ -114,6 +115,48 @@ def test_rowgroup_fp64_storage_mixed(L, ctx, cov):
     # FP64 storage: mixed runs read the FP64 values (FP64 sums) on FP32 vectors
     _pair(L, ctx, cov, L.LD_METHOD_OSLQ, 30, 10, 14, 2, 13, [(8, 1, 0, 1), (4, 2, 1, 1)],
           vt=L.LD_VT_FP64)
+
+
+def _groups_by_definition(a):
+    """Row groups written out from their definition: per group of 4 rows the
+    sorted union of the rows' columns and, per union column, each row's value
+    (0 where the row has no entry there)."""
+    rp, ci, va = a.row_ptr, a.col_idx, a.values
+    gp, cols, vals = [0], [], []
+    for g in range((a.n + 3) // 4):
+        rows = range(4 * g, min(a.n, 4 * g + 4))
+        u = np.unique(np.concatenate([ci[rp[r]:rp[r + 1]] for r in rows]))
+        v = np.zeros((len(u), 4))
+        for j, r in enumerate(rows):
+            v[np.searchsorted(u, ci[rp[r]:rp[r + 1]]), j] = va[rp[r]:rp[r + 1]]
+        gp.append(gp[-1] + len(u))
+        cols.append(u)
+        vals.append(v)
+    return np.array(gp), np.concatenate(cols), np.concatenate(vals)
+
+
+def test_rowgroup_build_exact(L, ctx, cov):
+    # the device-built groups against their definition, element by element
+    gp, col, val = _groups_by_definition(cov)
+    assert cov.nnz >= 2 * len(col)  # kept: at least 2 entries per union column
+    for vt in (L.LD_VT_FP32, L.LD_VT_FP64):
+        _announce(f"row groups built on the device, storage {vt}, n={cov.n}")
+        h = ctx.matrix(cov, vt=vt, lo_hint=NUG)
+        try:
+            got = L.ld_debug_row_groups(h, cov.n)
+            assert got is not None
+            assert np.array_equal(got[0], gp)
+            assert np.array_equal(got[1], col)
+            assert np.array_equal(got[2], val)
+        finally:
+            ctx.release(h)
+    _announce("no row groups on a Laplacian (1.3 entries per union column) or BF16 values")
+    for a, vt in ((W.lap3d(20, 1e-2), L.LD_VT_FP32), (cov, L.LD_VT_BF16)):
+        h = ctx.matrix(a, vt=vt, lo_hint=NUG if a is cov else 0.0)
+        try:
+            assert L.ld_debug_row_groups(h, a.n) is None
+        finally:
+            ctx.release(h)
 
 
 def test_rowgroup_default_and_tuner(L, ctx, cov):
